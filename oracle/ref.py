@@ -1,0 +1,202 @@
+"""ctypes wrapper of the FP64 C oracle (test infrastructure only).
+
+Each function mirrors one routine of ``jd_oracle.c``; see that file for which
+passage of the paper each follows.  Inputs are numpy arrays and
+``Problem`` instances from the seeded workload generators.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+
+
+class _Problem(C.Structure):
+    _fields_ = [("d", C.c_int32), ("N", C.c_int32), ("T", C.c_double), ("lambda_", C.c_double),
+                ("cubic", C.c_double), ("nu", C.c_double),
+                ("x0", C.c_void_p), ("A", C.c_void_p), ("B", C.c_void_p), ("s", C.c_void_p),
+                ("jump_mean", C.c_void_p), ("jump_std", C.c_void_p), ("xT", C.c_void_p),
+                ("xd", C.c_void_p)]
+
+
+class _Opt(C.Structure):
+    _fields_ = [("n_max", C.c_int32), ("tol", C.c_double), ("zeta0", C.c_double),
+                ("rho", C.c_double), ("c_armijo", C.c_double), ("max_backtracks", C.c_int32)]
+
+
+def lib():
+    """Load the oracle shared library, building it first if absent.  The
+    environment variable JD_ORACLE_LIB names another build of the same source
+    (the mutation tests use it to run the pins against planted mistakes)."""
+    global _lib
+    if _lib is None:
+        alt = os.environ.get("JD_ORACLE_LIB")
+        if alt:
+            _lib = _bind(C.CDLL(alt))
+        else:
+            if not os.path.exists(_build.LIB):
+                _build.build()
+            _lib = _bind(C.CDLL(_build.LIB))
+    return _lib
+
+
+def _bind(L):
+    P = C.c_void_p
+    L.or_philox4x32_10.argtypes = [P, P, P]
+    L.or_uniform.argtypes = [C.c_uint32]
+    L.or_uniform.restype = C.c_double
+    L.or_uniform_batch.argtypes = [P, C.c_int64, P]
+    L.or_poisson_thresholds.argtypes = [C.c_double, P]
+    L.or_poisson_count.argtypes = [C.c_uint32, P]
+    L.or_poisson_count.restype = C.c_int
+    L.or_draws_grid.argtypes = [C.c_uint64, C.c_uint32, C.c_int, C.c_double, C.c_int64,
+                                C.c_int64, C.c_int32, C.c_int32, P, P, P]
+    L.or_paths.argtypes = [P, C.c_uint64, C.c_uint32, C.c_int64, C.c_int64, P, P, P, P, C.c_int]
+    L.or_paths.restype = C.c_int
+    L.or_cost_grad.argtypes = [P, C.c_int64, C.c_uint64, C.c_uint32, P, P, P, C.c_int]
+    L.or_cost_grad.restype = C.c_int
+    L.or_tangent.argtypes = [P, C.c_int64, C.c_uint64, C.c_uint32, P, P, P, C.c_int]
+    L.or_tangent.restype = C.c_int
+    L.or_optimize.argtypes = [P, C.c_int64, C.c_uint64, C.c_uint32, P, P, P, P, P, P, P, C.c_int]
+    L.or_optimize.restype = C.c_int
+    return L
+
+
+def default_threads() -> int:
+    n = os.environ.get("OMP_NUM_THREADS")
+    if n and n.isdigit() and int(n) > 0:
+        return int(n)
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def _ptr(a: np.ndarray) -> int:
+    return a.ctypes.data
+
+
+class _ProblemRef:
+    """Holds the ctypes struct and keeps the numpy arrays it points to alive."""
+
+    def __init__(self, p):
+        self.keep = [np.ascontiguousarray(x, np.float64) for x in
+                     (p.x0, p.A, p.B, p.s, p.jump_mean, p.jump_std, p.xT, p.xd)]
+        x0, A, B, s, jm, js, xT, xd = self.keep
+        assert xd.shape == (p.N, p.d)
+        self.st = _Problem(p.d, p.N, p.T, p.lam, p.cubic, p.nu, _ptr(x0), _ptr(A), _ptr(B),
+                           _ptr(s), _ptr(jm), _ptr(js), _ptr(xT), _ptr(xd))
+
+    @property
+    def ref(self):
+        return C.byref(self.st)
+
+
+def _u(p, u):
+    if u is None:
+        return np.zeros((p.N, p.d))
+    u = np.ascontiguousarray(u, np.float64)
+    assert u.shape == (p.N, p.d)
+    return u
+
+
+def philox(ctr: np.ndarray, key) -> np.ndarray:
+    """Philox4x32-10 blocks for counters ctr (n x 4 uint32) under key (2 uint32)."""
+    L = lib()
+    ctr = np.ascontiguousarray(ctr, np.uint32).reshape(-1, 4)
+    k = np.ascontiguousarray(key, np.uint32).reshape(2)
+    out = np.empty_like(ctr)
+    o = np.empty(4, np.uint32)
+    for i in range(ctr.shape[0]):
+        c = np.ascontiguousarray(ctr[i])
+        L.or_philox4x32_10(_ptr(c), _ptr(k), _ptr(o))
+        out[i] = o
+    return out
+
+
+def uniform(w: np.ndarray) -> np.ndarray:
+    w = np.ascontiguousarray(w, np.uint32)
+    out = np.empty(w.shape, np.float64)
+    lib().or_uniform_batch(_ptr(w), w.size, _ptr(out))
+    return out
+
+
+def poisson_thresholds(mu: float) -> np.ndarray:
+    t = np.zeros(32, np.uint64)
+    lib().or_poisson_thresholds(float(mu), _ptr(t))
+    return t
+
+
+def poisson_count(P: int, thr: np.ndarray) -> int:
+    thr = np.ascontiguousarray(thr, np.uint64)
+    return lib().or_poisson_count(int(P), _ptr(thr))
+
+
+def draws(seed: int, it: int, d: int, mu: float, m0: int, mc: int, k0: int, kc: int):
+    """Brownian normals zw, jump normals zj (mc x kc x d) and counts (mc x kc)."""
+    zw = np.empty((mc, kc, d))
+    zj = np.empty((mc, kc, d))
+    n = np.empty((mc, kc), np.int32)
+    lib().or_draws_grid(seed, it, d, float(mu), m0, mc, k0, kc, _ptr(zw), _ptr(zj), _ptr(n))
+    return zw, zj, n
+
+
+def paths(p, seed: int, it: int, m0: int, count: int, u=None, nthreads: int | None = None):
+    """Per-path X (count x (N+1) x d), lam (same; row 0 zero) and C (count)."""
+    pr = _ProblemRef(p)
+    u = _u(p, u)
+    X = np.empty((count, p.N + 1, p.d))
+    lam = np.empty((count, p.N + 1, p.d))
+    Cm = np.empty(count)
+    rc = lib().or_paths(pr.ref, seed, it, m0, count, _ptr(u), _ptr(X), _ptr(lam), _ptr(Cm),
+                        nthreads or default_threads())
+    if rc:
+        raise ValueError(f"or_paths rejected the problem (rc={rc})")
+    return X, lam, Cm
+
+
+def cost_grad(p, M: int, seed: int, it: int, u=None, grad: bool = True,
+              nthreads: int | None = None):
+    """(J, g) with g of shape (N, d) (None when grad=False)."""
+    pr = _ProblemRef(p)
+    u = _u(p, u)
+    J = np.zeros(1)
+    g = np.empty((p.N, p.d)) if grad else None
+    rc = lib().or_cost_grad(pr.ref, M, seed, it, _ptr(u), _ptr(J), _ptr(g) if grad else None,
+                            nthreads or default_threads())
+    if rc:
+        raise ValueError(f"or_cost_grad failed (rc={rc})")
+    return float(J[0]), g
+
+
+def tangent(p, M: int, seed: int, it: int, u, delta, nthreads: int | None = None) -> float:
+    pr = _ProblemRef(p)
+    u = _u(p, u)
+    dl = _u(p, delta)
+    out = np.zeros(1)
+    rc = lib().or_tangent(pr.ref, M, seed, it, _ptr(u), _ptr(dl), _ptr(out),
+                          nthreads or default_threads())
+    if rc:
+        raise ValueError(f"or_tangent failed (rc={rc})")
+    return float(out[0])
+
+
+def optimize(p, M: int, seed: int, it0: int, u0=None, n_max: int = 20, tol: float = 0.0,
+             zeta0: float = 1.0, rho: float = 0.5, c_armijo: float = 1e-4,
+             max_backtracks: int = 30, nthreads: int | None = None):
+    """Returns (u_final, log dict, iterations done)."""
+    pr = _ProblemRef(p)
+    u = _u(p, u0).copy()
+    opt = _Opt(n_max, tol, zeta0, rho, c_armijo, max_backtracks)
+    logs = {k: np.zeros(max(n_max, 1)) for k in ("J", "gnorm", "zeta", "E")}
+    bt = np.zeros(max(n_max, 1), np.int32)
+    n = lib().or_optimize(pr.ref, M, seed, it0, C.byref(opt), _ptr(u), _ptr(logs["J"]),
+                          _ptr(logs["gnorm"]), _ptr(logs["zeta"]), _ptr(bt), _ptr(logs["E"]),
+                          nthreads or default_threads())
+    if n < 0:
+        raise RuntimeError(f"or_optimize failed (rc={n})")
+    logs = {k: v[:n] for k, v in logs.items()}
+    logs["backtracks"] = bt[:n]
+    return u, logs, n

@@ -1,0 +1,220 @@
+"""Pins of the oracle's forward sweep, cost, adjoint, gradient and optimizer.
+
+Each check reaches the oracle's result by a route other than the oracle's own
+formula: closed-form moments of the linear case (statistical, 5 standard
+errors), matrix-power and dense-matrix solutions of the deterministic case,
+exact sample identities that hold for any draws, the tangent-linear model
+(forward-mode derivative, derived separately from the adjoint), central finite
+differences under common random numbers, and the dense linear-quadratic
+optimum.  Test problems use a non-symmetric A and a non-identity B so that a
+transposed operand shows up."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from oracle import closed_form as cf
+from oracle import ref
+from paper_2505_04328_amd import workloads as wl
+
+
+def _det(p):
+    """Noise-free, jump-free copy of p."""
+    return dataclasses.replace(p, s=np.zeros(p.d), lam=0.0)
+
+
+@pytest.mark.parametrize("d", [1, 3, 8])
+def test_deterministic_path_matches_matrix_powers(oracle_lib, d):
+    p = _det(wl.general_problem(d, 40, seed=d))
+    u = wl.random_control(p, 4)
+    X, lam, C = ref.paths(p, seed=1, it=0, m0=0, count=3, u=u)
+    Xcf = cf.deterministic_path(p, u)
+    for i in range(3):
+        np.testing.assert_allclose(X[i], Xcf, rtol=1e-12, atol=1e-13)
+    # every path identical: no noise, no jumps
+    assert np.array_equal(X[0], X[2]) and np.array_equal(C[0], C[1])
+
+
+@pytest.mark.parametrize("d", [1, 3])
+def test_deterministic_cost_and_gradient_exact(oracle_lib, d):
+    """s = 0, lam = 0: the sample J equals E[J] and g equals the dense-matrix
+    gradient of the quadratic E[J] (transposition done by the matrix algebra,
+    not by an adjoint recursion)."""
+    p = _det(wl.general_problem(d, 30, seed=10 + d))
+    u = wl.random_control(p, 5)
+    J, g = ref.cost_grad(p, M=5, seed=2, it=0, u=u)
+    assert J == pytest.approx(cf.expected_cost(p, u), rel=1e-12)
+    np.testing.assert_allclose(g, cf.expected_grad_dense(p, u), rtol=1e-10, atol=1e-12)
+    np.testing.assert_allclose(cf.expected_grad(p, u), cf.expected_grad_dense(p, u),
+                               rtol=1e-10, atol=1e-12)
+
+
+def test_zero_rate_equals_jumps_disabled(oracle_lib):
+    p = wl.general_problem(3, 50, seed=3)
+    p0 = dataclasses.replace(p, lam=0.0)
+    p1 = dataclasses.replace(p, lam=0.0, jump_mean=np.zeros(3), jump_std=np.zeros(3))
+    a = ref.paths(p0, 1, 0, 0, 50)
+    b = ref.paths(p1, 1, 0, 0, 50)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    # and lam > 0 does change the paths
+    c = ref.paths(p, 1, 0, 0, 50)
+    assert not np.array_equal(a[0], c[0])
+
+
+@pytest.fixture(scope="module")
+def mc_linear(oracle_lib):
+    """Linear problem with jumps (non-zero jump mean), M paths with per-path data."""
+    p = wl.general_problem(3, 40, seed=21, lam=4.0, jump_mean=0.15, jump_std=0.3)
+    u = wl.random_control(p, 6)
+    M = 40000
+    X, lam, C = ref.paths(p, seed=7, it=3, m0=0, count=M, u=u)
+    return p, u, M, X, lam, C
+
+
+def test_forward_moments_closed_form(mc_linear):
+    p, u, M, X, _, _ = mc_linear
+    m, P = cf.moments(p, u)
+    xm = X.mean(0)
+    sd = X.std(0)
+    sd[0] = 1.0
+    z = np.abs(xm - m) / (sd / np.sqrt(M))
+    assert z.max() < 5.0
+    # covariance: elementwise, SE of a sample covariance ~ sqrt((P_ii P_jj + P_ij^2)/M)
+    for k in (1, p.N // 2, p.N):
+        c = np.cov(X[:, k, :].T, bias=True)
+        se = np.sqrt((np.outer(np.diag(P[k]), np.diag(P[k])) + P[k] ** 2) / M)
+        assert np.max(np.abs(c - P[k]) / se) < 5.5
+
+
+def test_expected_cost_closed_form(mc_linear, oracle_lib):
+    p, u, M, _, _, C = mc_linear
+    J, _ = ref.cost_grad(p, M, seed=7, it=3, u=u)
+    # J is the path mean of C plus the control cost
+    assert J == pytest.approx(C.mean() + 0.5 * p.nu * p.dt * np.sum(u * u), rel=1e-12)
+    se = C.std() / np.sqrt(M)
+    assert abs(J - cf.expected_cost(p, u)) < 5 * se
+
+
+def test_gradient_closed_form(mc_linear, oracle_lib):
+    p, u, M, _, lam, _ = mc_linear
+    _, g = ref.cost_grad(p, M, seed=7, it=3, u=u)
+    contrib = lam[:, 1:, :] @ p.B  # per path B^T lam_{k+1}, rows k = 0..N-1
+    np.testing.assert_allclose(g, p.nu * u + contrib.mean(0), rtol=1e-11, atol=1e-13)
+    se = contrib.std(0) / np.sqrt(M)
+    assert np.max(np.abs(g - cf.expected_grad(p, u)) / se) < 5.0
+
+
+def test_sample_identities_linear(mc_linear):
+    """For cubic = 0 the adjoint is affine with path-independent coefficients, so
+    the Monte Carlo gradient equals the mean recursion run on the sample-mean path,
+    and the sample cost splits into mean and biased sample covariance.  Both hold
+    for any draws, to rounding."""
+    p, u, M, X, lam, C = mc_linear
+    xb = X.mean(0)
+    Phi = np.eye(p.d) + p.dt * p.A
+    lb = np.zeros((p.N + 1, p.d))
+    lb[p.N] = xb[p.N] - p.xT
+    for k in range(p.N - 1, 0, -1):
+        lb[k] = Phi.T @ lb[k + 1] + p.dt * (xb[k] - p.xd[k])
+    np.testing.assert_allclose(lam.mean(0)[1:], lb[1:], rtol=1e-10, atol=1e-12)
+    var = ((X - xb) ** 2).mean(0).sum(1)
+    run = 0.5 * p.dt * (np.sum((xb[:p.N] - p.xd) ** 2) + var[:p.N].sum())
+    term = 0.5 * (np.sum((xb[p.N] - p.xT) ** 2) + var[p.N])
+    assert C.mean() == pytest.approx(run + term, rel=1e-11)
+
+
+@pytest.mark.parametrize("d,cubic", [(1, 0.0), (3, 0.0), (3, 0.1), (8, 0.1)])
+def test_tangent_linear_duality(oracle_lib, d, cubic):
+    """dJ[delta] from the forward-mode model equals dt * sum_k g_k . delta_k."""
+    p = wl.general_problem(d, 60, seed=30 + d, cubic=cubic)
+    u = wl.random_control(p, 8)
+    M = 700
+    _, g = ref.cost_grad(p, M, seed=5, it=2, u=u)
+    for delta in wl.fd_directions(p, 3, seed=9):
+        tl = ref.tangent(p, M, 5, 2, u, delta)
+        adj = p.dt * np.sum(g * delta)
+        assert tl == pytest.approx(adj, rel=1e-12, abs=1e-14)
+
+
+@pytest.mark.parametrize("d,cubic,tol", [(1, 0.0, 1e-8), (3, 0.0, 1e-8), (3, 0.1, 1e-6),
+                                         (8, 0.1, 1e-6)])
+def test_central_differences_common_random_numbers(oracle_lib, d, cubic, tol):
+    """The sample J is smooth in u (jumps do not depend on u), so central FD with
+    the same counters matches <g, delta>_L2: exactly for the linear case (J is
+    quadratic), to O(h^2) for the cubic one."""
+    p = wl.general_problem(d, 50, seed=40 + d, cubic=cubic)
+    u = wl.random_control(p, 11)
+    M, h = 500, 1e-4
+    _, g = ref.cost_grad(p, M, seed=3, it=1, u=u)
+    gn = np.sqrt(p.dt * np.sum(g * g))
+    for delta in wl.fd_directions(p, 4, seed=2):
+        jp, _ = ref.cost_grad(p, M, 3, 1, u + h * delta, grad=False)
+        jm, _ = ref.cost_grad(p, M, 3, 1, u - h * delta, grad=False)
+        fd = (jp - jm) / (2 * h)
+        assert abs(fd - p.dt * np.sum(g * delta)) / gn < tol
+
+
+def test_thread_count_does_not_change_results(oracle_lib):
+    p = wl.general_problem(2, 30, seed=50, cubic=0.05)
+    u = wl.random_control(p, 1)
+    a = ref.cost_grad(p, 10000, 1, 0, u, nthreads=1)
+    b = ref.cost_grad(p, 10000, 1, 0, u, nthreads=7)
+    assert a[0] == b[0] and np.array_equal(a[1], b[1])
+
+
+def test_iteration_counter_gives_fresh_samples(oracle_lib):
+    p = wl.general_problem(1, 20, seed=51)
+    a = ref.cost_grad(p, 1000, 1, 0)
+    b = ref.cost_grad(p, 1000, 1, 1)
+    assert a[0] != b[0]
+
+
+def test_optimizer_armijo_and_descent(oracle_lib):
+    """C1-shaped problem: E[J] (closed form) at the iterates decreases at every
+    iteration and moves toward the dense LQ optimum."""
+    p = wl.config("c1").problem
+    ustar = cf.lq_optimum(p)
+    e0, e_star = cf.expected_cost(p), cf.expected_cost(p, ustar)
+    u = np.zeros((p.N, p.d))
+    prev = e0
+    for n in range(10):
+        u, log, done = ref.optimize(p, 4000, seed=1, it0=n, u0=u, n_max=1)
+        assert done == 1 and log["zeta"][0] > 0 and log["E"][0] > 0
+        e = cf.expected_cost(p, u)
+        assert e < prev
+        prev = e
+    assert (prev - e_star) < 0.5 * (e0 - e_star)
+
+
+@pytest.mark.parametrize("zeta0,c", [(1.0, 1e-4), (64.0, 0.5)])
+def test_optimizer_armijo_replay(oracle_lib, zeta0, c):
+    """One iteration replayed from the outside: the step is u - zeta g, the
+    accepted trial satisfies the Armijo inequality on the same counters and the
+    trial before it (if any) does not."""
+    p = wl.general_problem(2, 25, seed=60, cubic=0.1)
+    M = 2000
+    u0 = np.zeros((p.N, p.d))
+    u1, log, n = ref.optimize(p, M, seed=4, it0=5, u0=u0, n_max=1, zeta0=zeta0, c_armijo=c)
+    J0, g0 = ref.cost_grad(p, M, 4, 5, u0)
+    assert log["J"][0] == J0
+    zeta = log["zeta"][0]
+    assert zeta == zeta0 * 0.5 ** log["backtracks"][0]
+    np.testing.assert_array_equal(u1, u0 - zeta * g0)
+    J1, _ = ref.cost_grad(p, M, 4, 5, u1, grad=False)
+    gg = p.dt * np.sum(g0 * g0)
+    assert J1 <= J0 - c * zeta * gg
+    if zeta0 > 1:
+        assert log["backtracks"][0] > 0
+    if log["backtracks"][0] > 0:
+        Jb, _ = ref.cost_grad(p, M, 4, 5, u0 - (zeta / 0.5) * g0, grad=False)
+        assert Jb > J0 - c * (zeta / 0.5) * gg
+
+
+def test_optimizer_resume_is_bitwise(oracle_lib):
+    p = wl.general_problem(1, 30, seed=61)
+    a, la, _ = ref.optimize(p, 1500, seed=2, it0=0, n_max=6)
+    b1, lb1, _ = ref.optimize(p, 1500, seed=2, it0=0, n_max=3)
+    b2, lb2, _ = ref.optimize(p, 1500, seed=2, it0=3, u0=b1, n_max=3)
+    assert np.array_equal(a, b2)
+    assert np.array_equal(la["J"], np.concatenate([lb1["J"], lb2["J"]]))
