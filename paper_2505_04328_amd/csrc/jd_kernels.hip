@@ -1,0 +1,643 @@
+// Kernels of the hot path on gfx950 and their typed launchers.
+//
+//  k_table            per-step table: B u_k and x_d(t_k) in the path precision
+//  k_forward          forward Euler-Maruyama sweep, one path per lane, draws in
+//                     registers, FP64 path cost, trajectory or checkpoint store
+//  k_adjoint_stored   backward adjoint sweep over the stored trajectory
+//  k_adjoint_recompute backward adjoint sweep regenerating each checkpoint
+//                     segment with the same counters (bit-identical states)
+//  k_finalize_grad    fixed-order FP64 sum of the per-block partials -> g
+//  k_finalize_cost    fixed-order FP64 sum of the path costs -> J, ||g||^2
+//  k_trial, k_armijo  line-search step and sufficient-decrease test
+//  k_draws, k_philox  the draws / raw Philox words, for parity checks
+//
+// The paper's method: forward model (Section 3, eq. model_approximation;
+// Section 5, model equation), adjoint (Section 4, eq. AdjointModel; Section 5,
+// adjoint equation), gradient (Section 4, eq. definition_Gradient), line search
+// (Section 5, eq. Stochastic_Armijo, Algorithm 5.4).
+#include "jd_device.hpp"
+#include "jd_launch.hpp"
+
+namespace jd {
+
+template <typename Real, int D>
+struct SweepArgs {
+    Coef<Real, D> c;
+    PoissonThresholds thr;
+    const Real* tab;  // N rows of 2D: B u_k (D), then x_d(t_k) (D)
+    void* traj;       // trajectory or checkpoints
+    double* part;     // per-block partial sums
+    int64_t M, ldm;
+    int N, d, K;
+    uint32_t key0, key1, iter;
+    double dt64;
+    // per-path diagnostics
+    int64_t dm0, dcount;
+    Real* dX;
+    Real* dlam;
+    double* dcost;
+};
+
+// Trajectory rows: row `row` (= (k-1)*d + c for X_k, or (j-1)*d + c for
+// checkpoint j), column m.
+template <typename Real, int D>
+__device__ __forceinline__ void load_state(const Real* __restrict__ base, int slot, int d,
+                                           int64_t ldm, int64_t m, bool act, Real* X) {
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+        X[c] = (Real)0;
+        if (c < d && act)
+            X[c] = __builtin_nontemporal_load(base + ((size_t)slot * d + c) * ldm + m);
+    }
+}
+
+template <typename Real, int D>
+__device__ __forceinline__ void store_state(Real* __restrict__ base, int slot, int d, int64_t ldm,
+                                            int64_t m, const Real* X) {
+#pragma unroll
+    for (int c = 0; c < D; ++c)
+        if (c < d)
+            __builtin_nontemporal_store(X[c], base + ((size_t)slot * d + c) * ldm + m);
+}
+
+template <typename Real, int D>
+__device__ __forceinline__ void dump_state(const SweepArgs<Real, D>& a, Real* dst, int k, int64_t m,
+                                           const Real* v) {
+    const int64_t p = m - a.dm0;
+    if (dst != nullptr && p >= 0 && p < a.dcount) {
+#pragma unroll
+        for (int c = 0; c < D; ++c)
+            if (c < a.d)
+                dst[((size_t)(k - 1) * a.d + c) * a.dcount + p] = v[c];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// B u_k and x_d rows.  B is passed by value (d*d <= 64 doubles).
+struct BMat {
+    double b[64];
+};
+
+template <typename Real, int D>
+__global__ void __launch_bounds__(kThreads)
+k_table(const double* __restrict__ u, const double* __restrict__ xd, Real* __restrict__ tab, int N,
+        int d, BMat B) {
+    const int idx = blockIdx.x * kThreads + threadIdx.x;
+    if (idx >= N * D)
+        return;
+    const int k = idx / D, i = idx - k * D;
+    double bu = 0.0, x = 0.0;
+    if (i < d) {
+        for (int j = 0; j < d; ++j)
+            bu += B.b[i * d + j] * u[(size_t)k * d + j];
+        x = xd[(size_t)k * d + i];
+    }
+    tab[(size_t)k * 2 * D + i] = (Real)bu;
+    tab[(size_t)k * 2 * D + D + i] = (Real)x;
+}
+
+// ---------------------------------------------------------------------------
+template <typename Real, int D, int MODE>
+__global__ void __launch_bounds__(kThreads) k_forward(SweepArgs<Real, D> a, double* __restrict__ cpart) {
+    __shared__ double sh[kThreads];
+    const int64_t m = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    const bool act = m < a.M;
+    const int N = a.N;
+    Real X[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+        X[i] = a.c.x0[i];
+    double acc = 0.0;
+    Real* traj = (Real*)a.traj;
+    for (int k = 0; k < N; ++k) {
+        const Real* row = a.tab + (size_t)k * 2 * D;
+        acc += (double)sq_dist<Real, D>(X, row + D);
+        Real zw[D], zj[D];
+        int n;
+        draws<Real, D>((uint32_t)m, (uint32_t)k, a.iter, a.key0, a.key1, a.thr, zw, zj, n);
+        euler_step<Real, D>(a.c, row, X, zw, zj, n);
+        if (MODE == FWD_STORE) {
+            if (act)
+                store_state<Real, D>(traj, k, a.d, a.ldm, m, X);
+        } else if (MODE == FWD_CKPT) {
+            if (act && ((k + 1) % a.K == 0 || k + 1 == N))
+                store_state<Real, D>(traj, (k + a.K) / a.K - 1, a.d, a.ldm, m, X);
+        }
+    }
+    double C = 0.5 * a.dt64 * acc + 0.5 * (double)sq_dist<Real, D>(X, a.c.xT);
+    if (!act)
+        C = 0.0;
+    if (a.dcost != nullptr) {
+        const int64_t p = m - a.dm0;
+        if (act && p >= 0 && p < a.dcount)
+            a.dcost[p] = C;
+    }
+    const double s = block_sum(C, sh);
+    if (threadIdx.x == 0)
+        cpart[blockIdx.x] = s;
+}
+
+// ---------------------------------------------------------------------------
+template <typename Real, int D>
+__device__ __forceinline__ void push_masked(StepReducer<D>& red, int k, const Real* lam, bool act,
+                                            double* part, int nblk) {
+    Real v[D];
+#pragma unroll
+    for (int c = 0; c < D; ++c)
+        v[c] = act ? lam[c] : (Real)0;
+    red.push(k, v, part, nblk);
+}
+
+template <typename Real, int D>
+__global__ void __launch_bounds__(kThreads) k_adjoint_stored(SweepArgs<Real, D> a) {
+    __shared__ double tile[StepReducer<D>::kRows][kThreads];
+    StepReducer<D> red;
+    red.init(tile);
+    const int64_t m = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    const bool act = m < a.M;
+    const int N = a.N, nblk = (int)gridDim.x;
+    const Real* traj = (const Real*)a.traj;
+    Real X[D], lam[D], Xn[D];
+    load_state<Real, D>(traj, N - 1, a.d, a.ldm, m, act, X);
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+        lam[i] = X[i] - a.c.xT[i];
+    dump_state(a, a.dX, N, m, X);
+    dump_state(a, a.dlam, N, m, lam);
+    if (N >= 2)
+        load_state<Real, D>(traj, N - 2, a.d, a.ldm, m, act, Xn);
+    for (int k = N - 1; k >= 0; --k) {
+        push_masked<Real, D>(red, k, lam, act, a.part, nblk);
+        if (k >= 1) {
+#pragma unroll
+            for (int i = 0; i < D; ++i)
+                X[i] = Xn[i];
+            if (k >= 2)
+                load_state<Real, D>(traj, k - 2, a.d, a.ldm, m, act, Xn);
+            adjoint_step<Real, D>(a.c, a.tab + (size_t)k * 2 * D + D, X, lam);
+            dump_state(a, a.dX, k, m, X);
+            dump_state(a, a.dlam, k, m, lam);
+        }
+    }
+    red.flush(a.part, nblk);
+}
+
+// ---------------------------------------------------------------------------
+// Segment j covers steps [jK, min((j+1)K, N)).  Its states are rebuilt from
+// checkpoint j (x0 for j = 0) in sub-segments of R steps: a first pass keeps
+// the sub-segment starts (at most SMAX of them) in registers, then each
+// sub-segment, last first, is regenerated into an R-entry register buffer and
+// swept backwards.
+template <typename Real, int D, int R, int SMAX>
+__global__ void __launch_bounds__(kThreads) k_adjoint_recompute(SweepArgs<Real, D> a) {
+    __shared__ double tile[StepReducer<D>::kRows][kThreads];
+    StepReducer<D> red;
+    red.init(tile);
+    const int64_t m = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    const bool act = m < a.M;
+    const int N = a.N, K = a.K, nblk = (int)gridDim.x;
+    const int nseg = (N + K - 1) / K;
+    const Real* ck = (const Real*)a.traj;
+    Real lam[D];
+    {
+        Real XN[D];
+        load_state<Real, D>(ck, nseg - 1, a.d, a.ldm, m, act, XN);
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+            lam[i] = XN[i] - a.c.xT[i];
+        dump_state(a, a.dX, N, m, XN);
+        dump_state(a, a.dlam, N, m, lam);
+    }
+    for (int j = nseg - 1; j >= 0; --j) {
+        const int s0 = j * K;
+        const int s1 = min(s0 + K, N);
+        const int ns = (s1 - s0 + R - 1) / R;
+        Real sub[SMAX][D];
+        Real X[D];
+        if (j == 0) {
+#pragma unroll
+            for (int i = 0; i < D; ++i)
+                X[i] = a.c.x0[i];
+        } else {
+            load_state<Real, D>(ck, j - 1, a.d, a.ldm, m, act, X);
+        }
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+            sub[0][i] = X[i];
+        for (int s = 1; s < ns; ++s) {
+            for (int k = s0 + (s - 1) * R; k < s0 + s * R; ++k) {
+                Real zw[D], zj[D];
+                int n;
+                draws<Real, D>((uint32_t)m, (uint32_t)k, a.iter, a.key0, a.key1, a.thr, zw, zj, n);
+                euler_step<Real, D>(a.c, a.tab + (size_t)k * 2 * D, X, zw, zj, n);
+            }
+#pragma unroll
+            for (int t = 1; t < SMAX; ++t)
+                if (t == s) {
+#pragma unroll
+                    for (int i = 0; i < D; ++i)
+                        sub[t][i] = X[i];
+                }
+        }
+        for (int s = ns - 1; s >= 0; --s) {
+            const int a0 = s0 + s * R;
+            const int a1 = min(a0 + R, s1);
+            Real buf[R][D];
+#pragma unroll
+            for (int t = 0; t < SMAX; ++t)
+                if (t == s) {
+#pragma unroll
+                    for (int i = 0; i < D; ++i)
+                        buf[0][i] = sub[t][i];
+                }
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                if (a0 + r < a1) {
+                    const int k = a0 + r - 1;
+#pragma unroll
+                    for (int i = 0; i < D; ++i)
+                        buf[r][i] = buf[r - 1][i];
+                    Real zw[D], zj[D];
+                    int n;
+                    draws<Real, D>((uint32_t)m, (uint32_t)k, a.iter, a.key0, a.key1, a.thr, zw, zj, n);
+                    euler_step<Real, D>(a.c, a.tab + (size_t)k * 2 * D, buf[r], zw, zj, n);
+                }
+            }
+#pragma unroll
+            for (int r = R - 1; r >= 0; --r) {
+                if (a0 + r < a1) {
+                    const int k = a0 + r;
+                    push_masked<Real, D>(red, k, lam, act, a.part, nblk);
+                    if (k >= 1) {
+                        adjoint_step<Real, D>(a.c, a.tab + (size_t)k * 2 * D + D, buf[r], lam);
+                        dump_state(a, a.dX, k, m, buf[r]);
+                        dump_state(a, a.dlam, k, m, lam);
+                    }
+                }
+            }
+        }
+    }
+    red.flush(a.part, nblk);
+}
+
+// ---------------------------------------------------------------------------
+// One block per step k: sums the d rows (k, c) of block partials in a fixed
+// order, then g_k = nu u_k + B^T (sum / M).
+__global__ void __launch_bounds__(kThreads)
+k_finalize_grad(const double* __restrict__ part, int nblk, int D, int d, int64_t M, double nu,
+                const double* __restrict__ u, BMat B, double* __restrict__ g) {
+    __shared__ double sh[kThreads];
+    __shared__ double G[8];
+    const int k = blockIdx.x;
+    for (int c = 0; c < d; ++c) {
+        const double* row = part + (size_t)(k * D + c) * nblk;
+        double s = 0.0;
+        for (int b = threadIdx.x; b < nblk; b += kThreads)
+            s += row[b];
+        s = block_sum(s, sh);
+        if (threadIdx.x == 0)
+            G[c] = s / (double)M;
+    }
+    __syncthreads();
+    const int i = threadIdx.x;
+    if (i < d) {
+        double v = 0.0;
+        for (int j = 0; j < d; ++j)
+            v += B.b[j * d + i] * G[j];
+        g[(size_t)k * d + i] = nu * u[(size_t)k * d + i] + v;
+    }
+}
+
+// One block: J = (1/M) sum C + nu dt/2 sum |u|^2, and if g is given also
+// dt sum |g|^2; flags non-finite results.
+__global__ void __launch_bounds__(kThreads)
+k_finalize_cost(const double* __restrict__ cpart, int nblk, int64_t M, double nu, double dt,
+                const double* __restrict__ u, const double* __restrict__ g, int nd,
+                double* __restrict__ J_out, WsHeader* hdr, int slot) {
+    __shared__ double sh[kThreads];
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += kThreads)
+        s += cpart[b];
+    const double csum = block_sum(s, sh);
+    double uu = 0.0;
+    for (int q = threadIdx.x; q < nd; q += kThreads)
+        uu += u[q] * u[q];
+    uu = block_sum(uu, sh);
+    double gg = 0.0;
+    int bad = 0;
+    if (g != nullptr) {
+        for (int q = threadIdx.x; q < nd; q += kThreads) {
+            gg += g[q] * g[q];
+            bad |= !isfinite(g[q]);
+        }
+        gg = block_sum(gg, sh);
+        bad = (int)block_sum((double)bad, sh);
+    }
+    if (threadIdx.x == 0) {
+        const double J = csum / (double)M + 0.5 * nu * dt * uu;
+        if (slot == 0) {
+            hdr->J = J;
+            if (g != nullptr)
+                hdr->gnorm2 = dt * gg;
+        } else {
+            hdr->J_trial = J;
+        }
+        if (J_out != nullptr)
+            *J_out = J;
+        if (!isfinite(J) || bad)
+            hdr->nonfinite = 1;
+    }
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_trial(const double* __restrict__ u, const double* __restrict__ g, double zeta,
+        double* __restrict__ ut, int nd) {
+    const int q = blockIdx.x * kThreads + threadIdx.x;
+    if (q < nd)
+        ut[q] = u[q] - zeta * g[q];
+}
+
+// Sufficient decrease J(u - zeta g) <= J(u) - c zeta ||g||^2_L2 on the same
+// draws; on acceptance records ||u' - u||^2_L2 and moves u to u'.
+__global__ void __launch_bounds__(kThreads)
+k_armijo(WsHeader* hdr, double* __restrict__ u, const double* __restrict__ ut, int nd,
+         double c_armijo, double zeta, double dt) {
+    __shared__ double sh[kThreads];
+    __shared__ int acc;
+    if (threadIdx.x == 0) {
+        const double J = hdr->J, Jt = hdr->J_trial;
+        acc = (Jt <= J - c_armijo * zeta * hdr->gnorm2) ? 1 : 0;
+        hdr->accept = acc;
+    }
+    __syncthreads();
+    if (!acc)
+        return;
+    double e = 0.0;
+    for (int q = threadIdx.x; q < nd; q += kThreads) {
+        const double r = ut[q] - u[q];
+        e += r * r;
+    }
+    e = block_sum(e, sh);
+    for (int q = threadIdx.x; q < nd; q += kThreads)
+        u[q] = ut[q];
+    if (threadIdx.x == 0)
+        hdr->E2 = dt * e;
+}
+
+__global__ void k_clear_flag(WsHeader* hdr) {
+    if (threadIdx.x == 0 && blockIdx.x == 0)
+        hdr->nonfinite = 0;
+}
+
+// ---------------------------------------------------------------------------
+template <typename Real, int D>
+__global__ void __launch_bounds__(kThreads)
+k_draws(SweepArgs<Real, D> a, int64_t m0, int64_t mc, int k0, int kc, Real* __restrict__ zw,
+        Real* __restrict__ zj, int32_t* __restrict__ counts) {
+    const int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (idx >= mc * kc)
+        return;
+    const int64_t p = idx / kc;
+    const int q = (int)(idx - p * kc);
+    Real w[D], j[D];
+    int n;
+    draws<Real, D>((uint32_t)(m0 + p), (uint32_t)(k0 + q), a.iter, a.key0, a.key1, a.thr, w, j, n);
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        if (i < a.d) {
+            if (zw)
+                zw[idx * a.d + i] = w[i];
+            if (zj)
+                zj[idx * a.d + i] = j[i];
+        }
+    }
+    if (counts)
+        counts[idx] = n;
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_philox(uint32_t key0, uint32_t key1, const uint32_t* __restrict__ ctr, int64_t n,
+         uint32_t* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= n)
+        return;
+    uint32_t w[4];
+    philox4x32_10(ctr[4 * i], ctr[4 * i + 1], ctr[4 * i + 2], ctr[4 * i + 3], key0, key1, w);
+    for (int q = 0; q < 4; ++q)
+        out[4 * i + q] = w[q];
+}
+
+// ===========================================================================
+// Launchers.
+
+size_t real_size(int prec) { return prec == JD_FP64 ? sizeof(double) : sizeof(float); }
+
+// Register-buffer shape of the recomputing adjoint: R steps of D values plus
+// SMAX sub-segment starts; a checkpoint interval K is supported up to R * SMAX.
+template <typename Real, int D>
+struct RecomputeShape;
+template <> struct RecomputeShape<float, 1> { static constexpr int R = 32, S = 4; };
+template <> struct RecomputeShape<float, 2> { static constexpr int R = 16, S = 4; };
+template <> struct RecomputeShape<float, 4> { static constexpr int R = 8, S = 8; };
+template <> struct RecomputeShape<float, 8> { static constexpr int R = 8, S = 8; };
+template <> struct RecomputeShape<double, 1> { static constexpr int R = 16, S = 4; };
+template <> struct RecomputeShape<double, 2> { static constexpr int R = 8, S = 4; };
+template <> struct RecomputeShape<double, 4> { static constexpr int R = 4, S = 8; };
+template <> struct RecomputeShape<double, 8> { static constexpr int R = 4, S = 4; };
+
+template <typename Real, int D>
+static int max_K() { return RecomputeShape<Real, D>::R * RecomputeShape<Real, D>::S; }
+
+bool recompute_supported(int prec, int D, int K) {
+    int mk = 0;
+    if (prec == JD_FP64) {
+        mk = D == 1 ? max_K<double, 1>() : D == 2 ? max_K<double, 2>() : D == 4 ? max_K<double, 4>()
+                                                                                  : max_K<double, 8>();
+    } else {
+        mk = D == 1 ? max_K<float, 1>() : D == 2 ? max_K<float, 2>() : D == 4 ? max_K<float, 4>()
+                                                                                : max_K<float, 8>();
+    }
+    return K >= 1 && K <= mk;
+}
+
+template <typename Real, int D>
+static SweepArgs<Real, D> make_args(const HostProblem& p, const HostRun& r) {
+    SweepArgs<Real, D> a;
+    for (int i = 0; i < D * D; ++i)
+        a.c.A[i] = (Real)p.A[i];
+    const double sq = sqrt(p.dt);
+    for (int i = 0; i < D; ++i) {
+        a.c.sq[i] = (Real)(sq * p.s[i]);
+        a.c.jm[i] = (Real)p.jm[i];
+        a.c.js[i] = (Real)p.js[i];
+        a.c.x0[i] = (Real)p.x0[i];
+        a.c.xT[i] = (Real)p.xT[i];
+    }
+    a.c.dt = (Real)p.dt;
+    a.c.c3 = (Real)p.cubic;
+    for (int j = 0; j < 32; ++j)
+        a.thr.t[j] = p.thr[j];
+    a.tab = nullptr;
+    a.traj = nullptr;
+    a.part = nullptr;
+    a.M = r.M;
+    a.ldm = r.ldm;
+    a.N = p.N;
+    a.d = p.d;
+    a.K = r.K;
+    a.key0 = (uint32_t)(r.seed & 0xFFFFFFFFu);
+    a.key1 = (uint32_t)(r.seed >> 32);
+    a.iter = r.iter;
+    a.dt64 = p.dt;
+    a.dm0 = 0;
+    a.dcount = 0;
+    a.dX = nullptr;
+    a.dlam = nullptr;
+    a.dcost = nullptr;
+    if (r.dump != nullptr) {
+        a.dm0 = r.dump->m0;
+        a.dcount = r.dump->count;
+        a.dX = (Real*)r.dump->X;
+        a.dlam = (Real*)r.dump->lam;
+        a.dcost = r.dump->cost;
+    }
+    return a;
+}
+
+static BMat make_B(const HostProblem& p) {
+    BMat B;
+    for (int i = 0; i < 64; ++i)
+        B.b[i] = i < p.d * p.d ? p.B[i] : 0.0;
+    return B;
+}
+
+static inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
+
+// Dispatch on (precision, padded dimension).
+#define JD_DISPATCH(prec, D, FN)                                 \
+    do {                                                         \
+        if ((prec) == JD_FP64) {                                 \
+            switch (D) {                                         \
+            case 1: FN(double, 1); break;                        \
+            case 2: FN(double, 2); break;                        \
+            case 4: FN(double, 4); break;                        \
+            default: FN(double, 8); break;                       \
+            }                                                    \
+        } else {                                                 \
+            switch (D) {                                         \
+            case 1: FN(float, 1); break;                         \
+            case 2: FN(float, 2); break;                         \
+            case 4: FN(float, 4); break;                         \
+            default: FN(float, 8); break;                        \
+            }                                                    \
+        }                                                        \
+    } while (0)
+
+hipError_t launch_setup(const HostProblem& p, const HostRun& r, const double* u, void* tab,
+                        hipStream_t st) {
+    const BMat B = make_B(p);
+    const unsigned nb = blocks_for((int64_t)p.N * p.D);
+#define JD_SETUP(T, DD) \
+    hipLaunchKernelGGL((k_table<T, DD>), dim3(nb), dim3(kThreads), 0, st, u, p.xd, (T*)tab, p.N, p.d, B)
+    JD_DISPATCH(r.prec, p.D, JD_SETUP);
+#undef JD_SETUP
+    return hipGetLastError();
+}
+
+hipError_t launch_forward(const HostProblem& p, const HostRun& r, const void* tab, void* traj,
+                          int fwd_mode, double* cpart, hipStream_t st) {
+    const unsigned nb = (unsigned)r.nblk;
+#define JD_FWD(T, DD)                                                                               \
+    do {                                                                                            \
+        SweepArgs<T, DD> a = make_args<T, DD>(p, r);                                                \
+        a.tab = (const T*)tab;                                                                      \
+        a.traj = traj;                                                                              \
+        if (fwd_mode == FWD_STORE)                                                                  \
+            hipLaunchKernelGGL((k_forward<T, DD, FWD_STORE>), dim3(nb), dim3(kThreads), 0, st, a, cpart); \
+        else if (fwd_mode == FWD_CKPT)                                                              \
+            hipLaunchKernelGGL((k_forward<T, DD, FWD_CKPT>), dim3(nb), dim3(kThreads), 0, st, a, cpart);  \
+        else                                                                                        \
+            hipLaunchKernelGGL((k_forward<T, DD, FWD_COST>), dim3(nb), dim3(kThreads), 0, st, a, cpart);  \
+    } while (0)
+    JD_DISPATCH(r.prec, p.D, JD_FWD);
+#undef JD_FWD
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint(const HostProblem& p, const HostRun& r, const void* tab, const void* traj,
+                          double* apart, hipStream_t st) {
+    const unsigned nb = (unsigned)r.nblk;
+#define JD_ADJ(T, DD)                                                                             \
+    do {                                                                                          \
+        SweepArgs<T, DD> a = make_args<T, DD>(p, r);                                              \
+        a.tab = (const T*)tab;                                                                    \
+        a.traj = const_cast<void*>(traj);                                                         \
+        a.part = apart;                                                                           \
+        if (r.mode == JD_RECOMPUTE)                                                               \
+            hipLaunchKernelGGL((k_adjoint_recompute<T, DD, RecomputeShape<T, DD>::R,              \
+                                                    RecomputeShape<T, DD>::S>),                   \
+                               dim3(nb), dim3(kThreads), 0, st, a);                               \
+        else                                                                                      \
+            hipLaunchKernelGGL((k_adjoint_stored<T, DD>), dim3(nb), dim3(kThreads), 0, st, a);    \
+    } while (0)
+    JD_DISPATCH(r.prec, p.D, JD_ADJ);
+#undef JD_ADJ
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize_grad(const HostProblem& p, const HostRun& r, const double* apart,
+                                const double* u, double* g, hipStream_t st) {
+    hipLaunchKernelGGL(k_finalize_grad, dim3(p.N), dim3(kThreads), 0, st, apart, r.nblk, p.D, p.d,
+                       r.M, p.nu, u, make_B(p), g);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize_cost(const HostProblem& p, const HostRun& r, const double* cpart,
+                                const double* u, const double* g, double* J_out, WsHeader* hdr,
+                                int slot, hipStream_t st) {
+    hipLaunchKernelGGL(k_finalize_cost, dim3(1), dim3(kThreads), 0, st, cpart, r.nblk, r.M, p.nu,
+                       p.dt, u, g, p.N * p.d, J_out, hdr, slot);
+    return hipGetLastError();
+}
+
+hipError_t launch_trial(const double* u, const double* g, double zeta, double* ut, int nd,
+                        hipStream_t st) {
+    hipLaunchKernelGGL(k_trial, dim3(blocks_for(nd)), dim3(kThreads), 0, st, u, g, zeta, ut, nd);
+    return hipGetLastError();
+}
+
+hipError_t launch_armijo(WsHeader* hdr, double* u, const double* ut, int nd, double c_armijo,
+                         double zeta, double dt, hipStream_t st) {
+    hipLaunchKernelGGL(k_armijo, dim3(1), dim3(kThreads), 0, st, hdr, u, ut, nd, c_armijo, zeta, dt);
+    return hipGetLastError();
+}
+
+hipError_t launch_clear_flag(WsHeader* hdr, hipStream_t st) {
+    hipLaunchKernelGGL(k_clear_flag, dim3(1), dim3(64), 0, st, hdr);
+    return hipGetLastError();
+}
+
+hipError_t launch_draws(const HostProblem& p, const HostRun& r, int64_t m0, int64_t mc, int k0,
+                        int kc, void* zw, void* zj, int32_t* counts, hipStream_t st) {
+    const unsigned nb = blocks_for(mc * kc);
+#define JD_DRAWS(T, DD)                                                                           \
+    do {                                                                                          \
+        SweepArgs<T, DD> a = make_args<T, DD>(p, r);                                              \
+        hipLaunchKernelGGL((k_draws<T, DD>), dim3(nb), dim3(kThreads), 0, st, a, m0, mc, k0, kc,  \
+                           (T*)zw, (T*)zj, counts);                                               \
+    } while (0)
+    JD_DISPATCH(r.prec, p.D, JD_DRAWS);
+#undef JD_DRAWS
+    return hipGetLastError();
+}
+
+hipError_t launch_philox(uint64_t seed, const uint32_t* ctr, int64_t n, uint32_t* out,
+                         hipStream_t st) {
+    if (n == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_philox, dim3(blocks_for(n)), dim3(kThreads), 0, st,
+                       (uint32_t)(seed & 0xFFFFFFFFu), (uint32_t)(seed >> 32), ctr, n, out);
+    return hipGetLastError();
+}
+
+}  // namespace jd

@@ -1,0 +1,79 @@
+// Internal interface between the C-ABI layer (jd_api.cpp) and the kernels
+// (jd_kernels.hip).  Host-side, validated, FP64 problem data in the padded
+// layout the kernels use.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/jd.h"
+
+namespace jd {
+
+constexpr int kBlock = 256;  // threads per block of the sweep kernels
+
+struct HostProblem {
+    int d;   // caller's dimension
+    int D;   // padded dimension: 1, 2, 4 or 8
+    int N;
+    double T, dt, lambda, cubic, nu;
+    double A[64];  // D x D row-major, zero-padded
+    double B[64];  // d x d row-major (caller layout)
+    double x0[8], s[8], jm[8], js[8], xT[8];  // zero-padded to D
+    const double* xd;  // device, N x d
+    uint64_t thr[32];  // Poisson thresholds for lambda*dt
+};
+
+struct HostRun {
+    int64_t M;
+    int64_t ldm;  // leading dimension of trajectory rows (M rounded up to 64)
+    uint64_t seed;
+    uint32_t iter;
+    int prec;  // JD_FP32 / JD_FP64
+    int mode;  // JD_STORE / JD_RECOMPUTE
+    int K;
+    int nblk;  // blocks of the sweeps = ceil(M / kBlock)
+    const jd_dump* dump;
+};
+
+// Device header at the start of every workspace.
+struct WsHeader {
+    double J;        // last cost reduction
+    double gnorm2;   // dt * sum |g_k|^2 of the last gradient reduction
+    double J_trial;  // last cost-only reduction of a line-search trial
+    double E2;       // dt * sum |u' - u|^2 of the last accepted trial
+    int32_t accept;  // last Armijo test
+    int32_t nonfinite;
+    int32_t pad[54];
+};
+static_assert(sizeof(WsHeader) == 256, "header is one 256-byte line");
+
+enum FwdMode { FWD_COST = 0, FWD_STORE = 1, FWD_CKPT = 2 };
+
+size_t real_size(int prec);
+bool recompute_supported(int prec, int D, int K);
+
+hipError_t launch_setup(const HostProblem& p, const HostRun& r, const double* u, void* tab,
+                        hipStream_t st);
+hipError_t launch_forward(const HostProblem& p, const HostRun& r, const void* tab, void* traj,
+                          int fwd_mode, double* cpart, hipStream_t st);
+hipError_t launch_adjoint(const HostProblem& p, const HostRun& r, const void* tab, const void* traj,
+                          double* apart, hipStream_t st);
+hipError_t launch_finalize_grad(const HostProblem& p, const HostRun& r, const double* apart,
+                                const double* u, double* g, hipStream_t st);
+// slot 0: J -> hdr->J (and J_out), with gnorm2 from g if g != nullptr; slot 1: -> hdr->J_trial
+hipError_t launch_finalize_cost(const HostProblem& p, const HostRun& r, const double* cpart,
+                                const double* u, const double* g, double* J_out, WsHeader* hdr,
+                                int slot, hipStream_t st);
+hipError_t launch_trial(const double* u, const double* g, double zeta, double* ut, int nd,
+                        hipStream_t st);
+hipError_t launch_armijo(WsHeader* hdr, double* u, const double* ut, int nd, double c_armijo,
+                         double zeta, double dt, hipStream_t st);
+hipError_t launch_draws(const HostProblem& p, const HostRun& r, int64_t m0, int64_t mc, int k0,
+                        int kc, void* zw, void* zj, int32_t* counts, hipStream_t st);
+hipError_t launch_philox(uint64_t seed, const uint32_t* ctr, int64_t n, uint32_t* out,
+                         hipStream_t st);
+hipError_t launch_clear_flag(WsHeader* hdr, hipStream_t st);
+
+}  // namespace jd

@@ -1,0 +1,191 @@
+"""The C-ABI library loads, exports every symbol include/jd.h declares, and
+rejects invalid arguments before anything is enqueued.  Host-only: no call here
+reaches the GPU (every call returns from validation or is host arithmetic)."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from oracle import ref
+from paper_2505_04328_amd import binding as B
+from paper_2505_04328_amd import workloads as wl
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "jd.h")
+
+
+def _gpu_visible() -> bool:
+    try:
+        import torch
+        return torch.cuda.device_count() > 0
+    except Exception:
+        return False
+
+
+# Validation tests hand fake device addresses to the entry points; they are
+# meant for the host only and never run where a GPU is visible.
+host_only = pytest.mark.skipif(_gpu_visible(), reason="host-only validation test")
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(B.LIB_PATH):
+        from paper_2505_04328_amd import build
+        build.build()
+    return B.lib()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\**\s+\**(jd_[a-z_0-9]+)\s*\(", text,
+                                 flags=re.M)))
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = declared_functions()
+    assert len(names) >= 12, names
+    out = subprocess.run(["nm", "-D", "--defined-only", B.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = {ln.split()[-1] for ln in out.splitlines() if " T " in ln}
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    assert set(B.EXPORTED) == set(names)
+
+
+def test_version_and_strerror(L):
+    assert L.jd_version() == 100
+    for code in (0, -1, -2, -3, -4, -5, -6, -99):
+        assert isinstance(L.jd_strerror(code), bytes)
+
+
+@pytest.mark.parametrize("mu", [0.0, 0.002, 0.005, 0.012, 0.02, 0.1, 1.0, 2.0])
+def test_poisson_thresholds_match_oracle_bitwise(L, mu):
+    """Two independent FP64 implementations of the same threshold sequence agree
+    exactly (both are then pinned against scipy's CDF by the oracle tests)."""
+    np.testing.assert_array_equal(B.poisson_thresholds(mu), ref.poisson_thresholds(mu))
+
+
+class _Dummy:
+    """A problem whose x_d pointer is a fake non-null address: only validation runs."""
+
+    def __init__(self, p):
+        self.p = p
+        self._keep = [np.ascontiguousarray(a, np.float64) for a in
+                      (p.x0, p.A, p.B, p.s, p.jump_mean, p.jump_std, p.xT)]
+        x0, A, Bm, s, jm, js, xT = self._keep
+        self.st = B.jd_problem(p.d, p.N, p.T, p.lam, p.cubic, p.nu, x0.ctypes.data,
+                               A.ctypes.data, Bm.ctypes.data, s.ctypes.data, jm.ctypes.data,
+                               js.ctypes.data, xT.ctypes.data, 0x1000)
+
+
+def _sizes(L, prob, run):
+    return L.jd_workspace_bytes(C.byref(prob.st), C.byref(run)), L.jd_traj_bytes(C.byref(prob.st), C.byref(run))
+
+
+def test_workspace_and_traj_sizes(L):
+    p = wl.config("c2").problem
+    pr = _Dummy(p)
+    M = 1 << 20
+    ws, tb = _sizes(L, pr, B.make_run(M, precision="fp32"))
+    assert tb == p.N * 1 * M * 4
+    assert ws >= p.N * (M // 256) * 8  # per-block FP64 partials of the adjoint
+    _, tb64 = _sizes(L, pr, B.make_run(M, precision="fp64"))
+    assert tb64 == 2 * tb
+    _, tck = _sizes(L, pr, B.make_run(M, precision="fp32", mode="recompute", K=32))
+    assert tck == (p.N // 32 + (p.N % 32 > 0)) * M * 4
+    # rows padded to 64 paths
+    _, t7 = _sizes(L, pr, B.make_run(7, precision="fp32"))
+    assert t7 == p.N * 64 * 4
+
+
+@host_only
+def test_invalid_arguments_rejected_before_launch(L):
+    p = wl.general_problem(3, 20, seed=1)
+    pr = _Dummy(p)
+    run = B.make_run(1000)
+    P = C.byref(pr.st)
+    fake = C.c_void_p(0x2000)
+    ws = 1 << 30
+    # null pointers
+    assert L.jd_forward(None, C.byref(run), fake, fake, fake, fake, ws, None) == B.JD_EINVAL
+    assert L.jd_forward(P, None, fake, fake, fake, fake, ws, None) == B.JD_EINVAL
+    assert L.jd_forward(P, C.byref(run), None, fake, fake, fake, ws, None) == B.JD_EINVAL
+    assert L.jd_cost_grad(P, C.byref(run), fake, fake, fake, None, fake, ws, None) == B.JD_EINVAL
+    assert L.jd_adjoint(P, C.byref(run), fake, None, fake, fake, ws, None) == B.JD_EINVAL
+    # workspace too small
+    assert L.jd_forward(P, C.byref(run), fake, fake, fake, fake, 100, None) == B.JD_EWORKSPACE
+    assert L.jd_forward(P, C.byref(run), fake, fake, fake, None, ws, None) == B.JD_EINVAL
+
+    def bad(**kw):
+        q = _Dummy(wl.general_problem(3, 20, seed=1))
+        for k, v in kw.items():
+            setattr(q.st, k, v)
+        return L.jd_forward(C.byref(q.st), C.byref(run), fake, fake, fake, fake, ws, None)
+
+    assert bad(d=0) == B.JD_EINVAL
+    assert bad(d=9) == B.JD_EINVAL
+    assert bad(N=0) == B.JD_EINVAL
+    assert bad(T=0.0) == B.JD_EINVAL
+    assert bad(T=float("nan")) == B.JD_EINVAL
+    assert bad(lambda_=-1.0) == B.JD_EINVAL
+    assert bad(lambda_=41.0 * 20) == B.JD_EINVAL  # lambda*dt > 2
+    assert bad(nu=-1.0) == B.JD_EINVAL
+    assert bad(xd=None) == B.JD_EINVAL
+    assert bad(A=None) == B.JD_EINVAL
+
+    def badrun(**kw):
+        r = B.make_run(1000)
+        for k, v in kw.items():
+            setattr(r, k, v)
+        return L.jd_forward(P, C.byref(r), fake, fake, fake, fake, ws, None)
+
+    assert badrun(M=0) == B.JD_EINVAL
+    assert badrun(M=(1 << 31) + 1) == B.JD_EINVAL
+    assert badrun(precision=2) == B.JD_EINVAL
+    assert badrun(mode=3) == B.JD_EINVAL
+    assert badrun(mode=B.JD_RECOMPUTE, K=0) == B.JD_EINVAL
+    assert badrun(mode=B.JD_RECOMPUTE, K=21) == B.JD_EINVAL
+    # a checkpoint interval beyond the register buffers is refused, not mis-run
+    q = _Dummy(wl.general_problem(8, 400, seed=2))
+    r = B.make_run(1000, precision="fp32", mode="recompute", K=65)
+    assert L.jd_forward(C.byref(q.st), C.byref(r), fake, fake, fake, fake, ws, None) == B.JD_EUNSUPPORTED
+    # dump range outside [0, M)
+    dp = B.jd_dump(990, 20, None, None, None)
+    r = B.make_run(1000, dump=dp)
+    assert L.jd_forward(P, C.byref(r), fake, fake, fake, fake, ws, None) == B.JD_EINVAL
+    # non-finite coefficient
+    q = _Dummy(wl.general_problem(3, 20, seed=1))
+    q._keep[1][0, 0] = np.inf
+    assert L.jd_forward(C.byref(q.st), C.byref(run), fake, fake, fake, fake, ws, None) == B.JD_EINVAL
+
+
+@host_only
+def test_optimizer_options_validated(L):
+    pr = _Dummy(wl.general_problem(2, 10, seed=3))
+    run = B.make_run(500)
+    fake = C.c_void_p(0x2000)
+    P = C.byref(pr.st)
+    for kw in (dict(n_max=-1), dict(max_backtracks=0), dict(zeta0=0.0), dict(rho=1.0),
+               dict(rho=0.0), dict(c_armijo=0.0), dict(tol=-1.0)):
+        o = B.jd_opt(5, 30, 0.0, 1.0, 0.5, 1e-4)
+        for k, v in kw.items():
+            setattr(o, k, v)
+        assert L.jd_optimize(P, C.byref(run), C.byref(o), fake, None, None, fake, fake, 1 << 30,
+                             None) == B.JD_EINVAL
+    assert L.jd_optimize(P, C.byref(run), None, fake, None, None, fake, fake, 1 << 30,
+                         None) == B.JD_EINVAL
+
+
+@host_only
+def test_draws_and_philox_argument_checks(L):
+    pr = _Dummy(wl.general_problem(2, 10, seed=3))
+    run = B.make_run(500)
+    assert L.jd_draws(C.byref(pr.st), C.byref(run), -1, 1, 0, 1, None, None, None, None) == B.JD_EINVAL
+    assert L.jd_draws(C.byref(pr.st), C.byref(run), 0, 0, 0, 1, None, None, None, None) == B.JD_OK
+    assert L.jd_philox(1, None, 5, None, None) == B.JD_EINVAL
+    assert L.jd_philox(1, None, 0, None, None) == B.JD_OK
+    assert L.jd_poisson_thresholds(-1.0, None) == B.JD_EINVAL
