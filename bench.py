@@ -1,0 +1,247 @@
+#!/usr/bin/env python3
+"""Benchmark of the hot path: forward + adjoint path-steps per second.
+
+One step = one jd_cost_grad call (forward Euler-Maruyama sweep with in-register
+Philox draws, backward adjoint sweep, FP64 Monte Carlo reductions of J and g)
+over the whole workload, with every input already resident in HBM.
+
+Workload (the configuration the metric is quoted on): the 1-D controlled OU
+jump-diffusion with M = 2^20 paths, N = 1000 steps, lambda = 5, jump sizes
+N(-0.1, 0.3^2), FP32 path arithmetic with FP64 reductions, stored trajectory.
+Also measured: the checkpoint-every-32-steps recompute variant and the pure
+FP64 GPU form, p50/p99 per call, per-kernel times (HIP events on the stream the
+library launches on), errors against the FP64 oracle on a bounded sample, and
+the oracle's own throughput on the host cores.
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# VALU peak: MI355X FP32 vector 157.3 TFLOP/s counts a fused multiply-add as
+# two flops, i.e. 78.6e12 full-rate 32-bit lane operations per second
+# (256 CUs x 4 SIMDs x 32 lanes/clk x 2.4 GHz).  One "slot" is one such
+# operation; transcendentals (log2, sqrt, sin, cos) and 32x32->64-bit integer
+# products are quarter rate (4 slots), FP64 adds and converts half rate (2).
+VALU_PEAK_SLOTS = 256 * 4 * 32 * 2.4e9
+# Algorithmic slots per path-step of the forward sweep (d = 1, FP32): the work
+# the method needs with wave-uniform counter words 1-3 and key (rounds 1-2 of
+# Philox are then half uniform and run on the scalar unit):
+#   Philox4x32-10 block: 18 lane-varying 32x32->64 products (72) + 19 xor3 (19)  = 91
+#   Box-Muller pair: 2 uniforms (8), log2 (4), scale (1), sqrt (4), cos+sin (8),
+#                    two products (2)                                            = 27
+#   Poisson word (3) and the first threshold compare (1)                        =  4
+#   Euler step: A X + B u, X^3 (2), cubic, dt and noise terms                   =  6
+#   running cost: difference, square, FP64 convert and accumulate              =  6
+# (the jump term is evaluated only in lanes that jump, ~lambda*dt of them)
+FWD_SLOTS_PER_PATH_STEP = 134
+HBM_PEAK = 8.0e12  # B/s
+METRIC = "forward+adjoint path-steps/s (FP32 vs FP64 GPU) at 1e-6 rel grad err; p50/p99"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-paths", type=int, default=1 << 17)
+    ap.add_argument("--only", choices=["all", "fp32_store", "kernels"], default="all",
+                    help="kernels: time jd_forward / jd_adjoint only (for profiler runs)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (HBM counter calibration)")
+    return ap.parse_args()
+
+
+def percentile(xs, q):
+    return float(np.percentile(np.asarray(xs), q))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        sys.exit("bench.py: this build runs on one GPU only (the paths shard across GPUs "
+                 "by contiguous path ranges, but no multi-GPU path is built); use --gpus 1")
+    import torch
+    from paper_2505_04328_amd import binding as B
+    from paper_2505_04328_amd import workloads as wl
+
+    dev = torch.device("cuda:0")
+    w = wl.config("c2")
+    p = w.problem
+    M, N = w.M, p.N
+    u = torch.zeros((N, p.d), dtype=torch.float64, device=dev)
+    st = torch.cuda.current_stream(dev)
+
+    def ev():
+        return torch.cuda.Event(enable_timing=True)
+
+    def time_calls(fn, reps):
+        """Per-call times (ms) with events on the library's stream."""
+        out = []
+        for _ in range(reps):
+            a, b = ev(), ev()
+            a.record(st)
+            fn()
+            b.record(st)
+            b.synchronize()
+            out.append(a.elapsed_time(b))
+        return out
+
+    if args.copy_calibration:
+        x = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        y = torch.empty_like(x)
+        x.fill_(1.0)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        log("copy calibration: 3 x 1 GiB device copies done")
+        del x, y
+
+    log(f"workload c2: M={M} N={N} d={p.d}; building engines")
+    e32 = B.Engine(p, M=M, seed=w.seed, precision="fp32", mode="store", device=dev)
+
+    if args.only == "kernels":
+        # forward (store) and adjoint alone, a few times each, for the profiler
+        for it in range(args.warmup + args.steps):
+            e32.forward(u, it=it)
+            e32.adjoint(u, it=it)
+        torch.cuda.synchronize()
+        log("kernel timing loop done")
+        print(json.dumps({"kernels_only": True, "calls": args.warmup + args.steps}))
+        return
+
+    # ---- the contract: W warmups, then exactly K timed steps, FP32 stored
+    for it in range(args.warmup):
+        e32.cost_grad(u, it=it)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for it in range(args.steps):
+        e32.cost_grad(u, it=it)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    total = t1 - t0
+    value = M * N * args.steps / total
+    log(f"fp32 store: {total / args.steps * 1e3:.3f} ms/step, {value:.4e} path-steps/s")
+
+    res = {}
+    res["fp32_store_ms"] = time_calls(lambda: e32.cost_grad(u, it=7), args.steps)
+    # per-kernel: jd_forward (table + forward sweep + cost reduction) and
+    # jd_adjoint (table + adjoint sweep + gradient reduction)
+    fwd_ms = time_calls(lambda: e32.forward(u, it=7), max(5, args.steps // 2))
+    adj_ms = time_calls(lambda: e32.adjoint(u, it=7), max(5, args.steps // 2))
+    J32, g32 = e32.cost_grad(u, it=0)
+    J32, g32 = float(J32), g32.cpu().numpy()
+    del e32
+    torch.cuda.empty_cache()
+
+    forms = {}
+    if args.only == "all":
+        er = B.Engine(p, M=M, seed=w.seed, precision="fp32", mode="recompute", K=w.K, device=dev)
+        for it in range(args.warmup):
+            er.cost_grad(u, it=it)
+        res["fp32_recompute_ms"] = time_calls(lambda: er.cost_grad(u, it=7), args.steps)
+        Jr, gr = er.cost_grad(u, it=0)
+        recompute_bitwise = float(Jr) == J32 and np.array_equal(gr.cpu().numpy(), g32)
+        del er
+        torch.cuda.empty_cache()
+        e64 = B.Engine(p, M=M, seed=w.seed, precision="fp64", mode="store", device=dev)
+        for it in range(args.warmup):
+            e64.cost_grad(u, it=it)
+        res["fp64_store_ms"] = time_calls(lambda: e64.cost_grad(u, it=7), args.steps)
+        J64, g64 = e64.cost_grad(u, it=0)
+        J64, g64 = float(J64), g64.cpu().numpy()
+        del e64
+        torch.cuda.empty_cache()
+        for k, v in res.items():
+            forms[k.replace("_ms", "")] = {
+                "p50_ms": percentile(v, 50), "p99_ms": percentile(v, 99),
+                "path_steps_per_s_p50": M * N / (percentile(v, 50) * 1e-3)}
+        forms["fp32_recompute"]["bitwise_equal_to_store"] = recompute_bitwise
+        forms["fp32_vs_fp64_full_size"] = {
+            "J_rel": abs(J32 - J64) / abs(J64),
+            "g_rel": float(np.linalg.norm(g32 - g64) / np.linalg.norm(g64))}
+        forms["speedup_fp32_over_fp64_p50"] = (percentile(res["fp64_store_ms"], 50) /
+                                               percentile(res["fp32_store_ms"], 50))
+    t_fwd = percentile(fwd_ms, 50) * 1e-3
+    t_adj = percentile(adj_ms, 50) * 1e-3
+    slots = FWD_SLOTS_PER_PATH_STEP * M * N
+    roofline = {"bound": "alu", "kernel": "k_forward<float,1,store>",
+                "achieved": slots / t_fwd / 1e12, "peak": VALU_PEAK_SLOTS / 1e12,
+                "unit": "TOP/s (full-rate VALU lane-op slots)",
+                "frac": slots / t_fwd / VALU_PEAK_SLOTS, "traffic": None,
+                "slots_per_path_step": FWD_SLOTS_PER_PATH_STEP, "kernel_ms": t_fwd * 1e3}
+    adj_bytes = 4.0 * M * N  # reads X_1..X_N once (FP32)
+    roof_adj = {"bound": "hbm", "kernel": "k_adjoint_stored<float,1>",
+                "achieved": adj_bytes / t_adj / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                "frac": adj_bytes / t_adj / HBM_PEAK, "traffic": None, "kernel_ms": t_adj * 1e3}
+
+    # ---- oracle on a bounded sample of the same workload, and GPU errors there
+    cpu = None
+    sample_err = None
+    if not args.no_cpu_baseline:
+        from oracle import ref
+        Ms = args.cpu_sample_paths
+        nth = ref.default_threads()
+        log(f"oracle: {Ms} paths x {N} steps on {nth} threads")
+        t0 = time.perf_counter()
+        Jo, go = ref.cost_grad(p, Ms, w.seed, 0, np.zeros((N, p.d)), nthreads=nth)
+        tc = time.perf_counter() - t0
+        cpu = {"value": Ms * N / tc, "unit": "path-steps/s", "cores": nth, "kind": "oracle",
+               "sample": f"c2 with M={Ms} of {M} paths, all N={N} steps, forward+adjoint+reductions, "
+                         f"FP64, {tc:.1f} s wall"}
+        sample_err = {}
+        for prec in ("fp32", "fp64"):
+            es = B.Engine(p, M=Ms, seed=w.seed, precision=prec, mode="store", device=dev)
+            Js, gs = es.cost_grad(u, it=0)
+            sample_err[prec] = {"J_rel": abs(float(Js) - Jo) / abs(Jo),
+                                "g_rel": float(np.linalg.norm(gs.cpu().numpy() - go) /
+                                               np.linalg.norm(go))}
+            del es
+        log(f"oracle errors: {sample_err}")
+
+    fp32s = res["fp32_store_ms"]
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "path-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": total / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32 paths, f64 reductions",
+        "data": "synthetic (seeded Philox draws)",
+        "config": {"workload": "c2: 1-D OU jump-diffusion, M=2^20 paths, N=1000 steps, lambda=5, "
+                               "jumps N(-0.1,0.3^2), FP32 paths + FP64 reductions, stored trajectory",
+                   "M": M, "N": N, "d": p.d},
+        "p50_ms": percentile(fp32s, 50),
+        "p99_ms": percentile(fp32s, 99),
+        "roofline": roofline,
+        "roofline_adjoint": roof_adj,
+        "cpu_baseline": cpu,
+        "forms": forms,
+        "oracle_error_on_sample": sample_err,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

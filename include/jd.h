@@ -158,10 +158,13 @@ const char* jd_strerror(int code);
  * invalid.  The same workspace serves every entry point. */
 size_t jd_workspace_bytes(const jd_problem* prob, const jd_run* run);
 
-/* Bytes of the trajectory buffer: JD_STORE holds X_1..X_N as
- * traj[((k-1)*d + c)*ldm + m], JD_RECOMPUTE holds X_{jK} (j = 1..ceil(N/K),
- * the last slot X_N) as ckpt[((j-1)*d + c)*ldm + m], with ldm = M rounded up
- * to a multiple of 64, elements of the run precision.  0 if invalid. */
+/* Bytes of the trajectory buffer.  The buffer holds S slots (JD_STORE: S = N,
+ * slot k-1 = X_k for k = 1..N; JD_RECOMPUTE: S = ceil(N/K), slot j-1 = X_{jK}
+ * for j < S and slot S-1 = X_N) in blocks of 256 paths, elements of the run
+ * precision: component c of slot q of path m is at
+ *   ((m / 256) * S + q) * d * 256 + c * 256 + (m % 256),
+ * i.e. each block of 256 paths owns a contiguous time-major region.  Its size
+ * is S * d * ceil(M/256) * 256 elements.  0 if arguments are invalid. */
 size_t jd_traj_bytes(const jd_problem* prob, const jd_run* run);
 
 /* Forward sweep of all M paths (Section 3, eq. model_approximation; Section 5,
@@ -197,8 +200,9 @@ int jd_optimize(const jd_problem* prob, const jd_run* run, const jd_opt* opt, do
                 jd_iter_log* log, int32_t* iters_done, void* traj, void* ws,
                 size_t ws_bytes, hipStream_t stream);
 
-/* Reads the non-finite flag that the reductions of the last calls on this
- * workspace raised, then clears it.  Synchronizes `stream`.  Returns JD_OK or
+/* Reads the non-finite flag of the most recent entry-point call on this
+ * workspace (each call clears it first; its reductions raise it when J or g is
+ * not finite), then clears it.  Synchronizes `stream`.  Returns JD_OK or
  * JD_ENONFINITE. */
 int jd_check_finite(void* ws, size_t ws_bytes, hipStream_t stream);
 

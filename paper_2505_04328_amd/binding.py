@@ -160,7 +160,7 @@ class Engine:
             raise JdError(JD_EINVAL, "Engine")
         self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
         esz = 4 if precision == "fp32" else 8
-        self.ldm = (M + 63) // 64 * 64
+        self.nblk = (M + 255) // 256
         self.traj = torch.empty(self.traj_bytes // esz, dtype=self.rdtype, device=self.device)
 
     def run(self, it: int = 0, dump: jd_dump | None = None) -> jd_run:
@@ -175,9 +175,11 @@ class Engine:
         return u
 
     def trajectory(self):
-        """The stored trajectory as a (rows, d, ldm) view."""
-        rows = self.traj.numel() // (self.p.d * self.ldm)
-        return self.traj.view(rows, self.p.d, self.ldm)
+        """The trajectory / checkpoint buffer as a (slots, d, M) tensor (a copy:
+        the buffer is blocked by 256 paths, see jd_traj_bytes)."""
+        slots = self.traj.numel() // (self.p.d * self.nblk * 256)
+        t = self.traj.view(self.nblk, slots, self.p.d, 256).permute(1, 2, 0, 3)
+        return t.reshape(slots, self.p.d, self.nblk * 256)[:, :, :self.M]
 
     def forward(self, u, it: int = 0, store: bool = True, dump: jd_dump | None = None):
         torch = _torch()

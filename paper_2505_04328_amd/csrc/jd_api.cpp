@@ -106,9 +106,15 @@ int prepare(const jd_problem* prob, const jd_run* run, HostProblem& p, HostRun& 
         p.B[q] = prob->B[q];
     p.xd = prob->xd;
     poisson_thresholds(prob->lambda * dt, p.thr);
+    p.poisson.jmax = 31;
+    for (int j = 0; j < 32; ++j) {
+        p.poisson.tm1[j] = (uint32_t)(p.thr[j] - 1);  // thr_j >= thr_0 >= 1 since rate*dt <= 2
+        if (p.thr[j] == ((uint64_t)1 << 32) && p.poisson.jmax == 31)
+            p.poisson.jmax = j;
+    }
 
     r.M = run->M;
-    r.ldm = (int64_t)round_up((size_t)run->M, 64);
+    r.ldm = (int64_t)round_up((size_t)run->M, kBlock);
     r.seed = run->seed;
     r.iter = run->iter;
     r.prec = run->precision;
@@ -183,8 +189,8 @@ bool aligned(const void* ptr, size_t a) { return ((uintptr_t)ptr % a) == 0; }
 int enqueue_forward(const HostProblem& p, const HostRun& r, const double* u, void* traj, double* J,
                     const Ws& w, hipStream_t st) {
     const int fm = traj == nullptr ? FWD_COST : (r.mode == JD_RECOMPUTE ? FWD_CKPT : FWD_STORE);
-    JD_TRY(launch_setup(p, r, u, w.tab, st));
-    JD_TRY(launch_forward(p, r, w.tab, traj, fm, w.cpart, st));
+    JD_TRY(launch_setup(p, r, u, w.tab, w.hdr, 1, st));
+    JD_TRY(launch_forward(p, r, w.tab, traj, fm, w.cpart, w.hdr, st));
     JD_TRY(launch_finalize_cost(p, r, w.cpart, u, nullptr, J, w.hdr, 0, st));
     return JD_OK;
 }
@@ -192,10 +198,10 @@ int enqueue_forward(const HostProblem& p, const HostRun& r, const double* u, voi
 int enqueue_cost_grad(const HostProblem& p, const HostRun& r, const double* u, double* J,
                       double* g, void* traj, const Ws& w, hipStream_t st) {
     const int fm = r.mode == JD_RECOMPUTE ? FWD_CKPT : FWD_STORE;
-    JD_TRY(launch_setup(p, r, u, w.tab, st));
-    JD_TRY(launch_forward(p, r, w.tab, traj, fm, w.cpart, st));
-    JD_TRY(launch_adjoint(p, r, w.tab, traj, w.apart, st));
-    JD_TRY(launch_finalize_grad(p, r, w.apart, u, g, st));
+    JD_TRY(launch_setup(p, r, u, w.tab, w.hdr, 1, st));
+    JD_TRY(launch_forward(p, r, w.tab, traj, fm, w.cpart, w.hdr, st));
+    JD_TRY(launch_adjoint(p, r, w.tab, traj, w.apart, w.hdr, st));
+    JD_TRY(launch_finalize_grad(p, r, w.apart, u, g, w.hdr, st));
     JD_TRY(launch_finalize_cost(p, r, w.cpart, u, g, J, w.hdr, 0, st));
     return JD_OK;
 }
@@ -269,9 +275,9 @@ int jd_adjoint(const jd_problem* prob, const jd_run* run, const double* u, const
     Ws w;
     if ((rc = bind_ws(p, r, ws, ws_bytes, w)))
         return rc;
-    JD_TRY(launch_setup(p, r, u, w.tab, stream));
-    JD_TRY(launch_adjoint(p, r, w.tab, traj, w.apart, stream));
-    JD_TRY(launch_finalize_grad(p, r, w.apart, u, grad, stream));
+    JD_TRY(launch_setup(p, r, u, w.tab, w.hdr, 1, stream));
+    JD_TRY(launch_adjoint(p, r, w.tab, traj, w.apart, w.hdr, stream));
+    JD_TRY(launch_finalize_grad(p, r, w.apart, u, grad, w.hdr, stream));
     return JD_OK;
 }
 
@@ -322,8 +328,8 @@ int jd_optimize(const jd_problem* prob, const jd_run* run, const jd_opt* opt, do
         bool accepted = false;
         for (; bt < opt->max_backtracks; ++bt) {
             JD_TRY(launch_trial(u, w.gbuf, zeta, w.ut, nd, stream));
-            JD_TRY(launch_setup(p, r, w.ut, w.tab, stream));
-            JD_TRY(launch_forward(p, r, w.tab, nullptr, FWD_COST, w.cpart, stream));
+            JD_TRY(launch_setup(p, r, w.ut, w.tab, w.hdr, 0, stream));
+            JD_TRY(launch_forward(p, r, w.tab, nullptr, FWD_COST, w.cpart, w.hdr, stream));
             JD_TRY(launch_finalize_cost(p, r, w.cpart, w.ut, nullptr, nullptr, w.hdr, 1, stream));
             JD_TRY(launch_armijo(w.hdr, u, w.ut, nd, opt->c_armijo, zeta, p.dt, stream));
             JD_TRY(hipMemcpyAsync(&h, w.hdr, sizeof(h), hipMemcpyDeviceToHost, stream));

@@ -8,21 +8,30 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "jd_launch.hpp"
+
 namespace jd {
 
 constexpr int kThreads = 256;  // threads per block of every sweep kernel
 
+// Three-input xor in one VALU instruction (gfx950 v_bitop3_b32, truth table
+// 0x96 = a ^ b ^ c).
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).  The counter word c0 is
 // the path index (lane-varying); c1..c3 and the key are wave-uniform, so the
-// compiler keeps the key schedule on the scalar unit.
+// compiler keeps the key schedule on the scalar unit.  Per round: two
+// 32x32->64-bit products (v_mad_u64_u32) and two three-input xors.
 __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                               uint32_t k0, uint32_t k1, uint32_t* out) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        const uint32_t n0 = xor3((uint32_t)(p1 >> 32), c1, k0);
+        const uint32_t n2 = xor3((uint32_t)(p0 >> 32), c3, k1);
         c1 = (uint32_t)p1;
         c3 = (uint32_t)p0;
         c0 = n0;
@@ -43,13 +52,18 @@ __device__ __forceinline__ Real unit_uniform(uint32_t w) {
     return (Real)((w >> 8) | 1u) * (Real)(1.0 / 16777216.0);
 }
 
-// Box-Muller pair from two words: cosine branch and sine branch.
+// Box-Muller pair from two words: cosine branch and sine branch.  FP32 uses
+// the hardware transcendentals directly: v_log_f32 (log2), v_sqrt_f32 and
+// v_sin_f32 / v_cos_f32, whose argument is in revolutions, so sin(2 pi u) is
+// one instruction.  The uniforms are never 0, denormal or 1, so no range
+// handling is needed; the result matches the FP64 transform to within 1e-6
+// absolute, like the correctly-rounded library functions.
 __device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, float& zc, float& zs) {
-    const float r = sqrtf(-2.0f * logf(unit_uniform<float>(a)));
-    float s, c;
-    sincospif(2.0f * unit_uniform<float>(b), &s, &c);
-    zc = r * c;
-    zs = r * s;
+    const float l2 = __builtin_amdgcn_logf(unit_uniform<float>(a));  // log2(u_a)
+    const float r = __builtin_amdgcn_sqrtf(-1.38629436111989061883f * l2);  // sqrt(-2 ln u_a)
+    const float ub = unit_uniform<float>(b);
+    zc = r * __builtin_amdgcn_cosf(ub);
+    zs = r * __builtin_amdgcn_sinf(ub);
 }
 __device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, double& zc, double& zs) {
     const double r = sqrt(-2.0 * log(unit_uniform<double>(a)));
@@ -59,25 +73,20 @@ __device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, double& zc, d
     zs = r * s;
 }
 
-// Inverse-CDF Poisson thresholds, prepared on the host (kernel argument).
-struct PoissonThresholds {
-    uint64_t t[32];
-};
-
 // Word made of the low bytes of the four words of Philox block 0.
 __device__ __forceinline__ uint32_t poisson_word(const uint32_t* w) {
     return (w[0] & 0xFFu) | ((w[1] & 0xFFu) << 8) | ((w[2] & 0xFFu) << 16) | (w[3] << 24);
 }
 
-// Smallest j with P < thr_j.  The first comparison is the common case; the
-// loop runs only in lanes that jump, with a wave-uniform index.
-__device__ __forceinline__ int poisson_count(uint32_t P, const PoissonThresholds& thr) {
-    const uint64_t p = (uint64_t)P;
-    int n = 0;
-    if (p >= thr.t[0]) {
-        n = 1;
-        for (int j = 1; j < 31; ++j) {
-            if (p < thr.t[j])
+// Count for word P.  The first comparison is the common case; the loop runs
+// only in lanes that jump.
+__device__ __forceinline__ int poisson_count(uint32_t P, const PoissonTable* __restrict__ tb) {
+    int n = P > tb->tm1[0] ? 1 : 0;
+    if (n) {
+        const int jmax = tb->jmax;
+#pragma unroll 1
+        for (int j = 1; j < jmax; ++j) {
+            if (P <= tb->tm1[j])
                 break;
             n = j + 1;
         }
@@ -103,7 +112,7 @@ struct Coef {
 // Draws of path-step (m, k) under iteration word `iter`.
 template <typename Real, int D>
 __device__ __forceinline__ void draws(uint32_t m, uint32_t k, uint32_t iter, uint32_t key0,
-                                      uint32_t key1, const PoissonThresholds& thr, Real* zw,
+                                      uint32_t key1, const PoissonTable* __restrict__ thr, Real* zw,
                                       Real* zj, int& n) {
     constexpr int NB = (D + 1) / 2;
     uint32_t w[4 * NB];
@@ -120,7 +129,7 @@ template <typename Real>
 __device__ __forceinline__ Real count_sqrt(int n);
 template <>
 __device__ __forceinline__ float count_sqrt<float>(int n) {
-    return sqrtf((float)n);
+    return __builtin_amdgcn_sqrtf((float)n);
 }
 template <>
 __device__ __forceinline__ double count_sqrt<double>(int n) {
@@ -129,12 +138,11 @@ __device__ __forceinline__ double count_sqrt<double>(int n) {
 
 // One Euler-Maruyama step with additive compound-Poisson jumps:
 //   X <- X + dt (A X - c3 X^3 + Bu_k) + sqrt(dt) s Z^W + n m_J + s_J sqrt(n) Z^J
-// bu = B u_k (per-step table row).
+// bu = B u_k (per-step table row).  The jump term is only evaluated in lanes
+// with n > 0 (a few percent of path-steps).
 template <typename Real, int D>
 __device__ __forceinline__ void euler_step(const Coef<Real, D>& c, const Real* __restrict__ bu,
                                            Real* X, const Real* zw, const Real* zj, int n) {
-    const Real fn = (Real)n;
-    const Real sn = count_sqrt<Real>(n);
     Real Y[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) {
@@ -145,9 +153,14 @@ __device__ __forceinline__ void euler_step(const Coef<Real, D>& c, const Real* _
         const Real x3 = X[i] * X[i] * X[i];
         f = fma(-c.c3, x3, f);
         Real y = fma(c.dt, f, X[i]);
-        y = fma(c.sq[i], zw[i], y);
-        const Real jump = fma(c.js[i] * sn, zj[i], fn * c.jm[i]);
-        Y[i] = y + jump;
+        Y[i] = fma(c.sq[i], zw[i], y);
+    }
+    if (n != 0) {
+        const Real fn = (Real)n;
+        const Real sn = count_sqrt<Real>(n);
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+            Y[i] = Y[i] + fma(c.js[i] * sn, zj[i], fn * c.jm[i]);
     }
 #pragma unroll
     for (int i = 0; i < D; ++i)
@@ -185,6 +198,15 @@ __device__ __forceinline__ Real sq_dist(const Real* X, const Real* __restrict__ 
         e = fma(r, r, e);
     }
     return e;
+}
+
+// Workgroup barrier that orders LDS accesses only.  __syncthreads() also
+// fences global memory, which makes every wave wait for all of its outstanding
+// loads (the prefetched trajectory tiles) at each barrier.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 // Deterministic FP64 sum over a block of kThreads threads (fixed tree).
@@ -227,17 +249,31 @@ struct StepReducer {
     __device__ __forceinline__ void push(int k, const Real* v, double* __restrict__ part, int nblk) {
         if (filled == 0)
             k_first = k;
-#pragma unroll
-        for (int c = 0; c < D; ++c)
-            tile[filled * D + c][threadIdx.x] = (double)v[c];
+        put(filled, v);
         if (++filled == kSteps)
             flush(part, nblk);
+    }
+
+    // Deposit the values of the s-th step of the current tile (no flush).
+    template <typename Real>
+    __device__ __forceinline__ void put(int s, const Real* v) {
+#pragma unroll
+        for (int c = 0; c < D; ++c)
+            tile[s * D + c][threadIdx.x] = (double)v[c];
+    }
+
+    // Flush a tile filled by put() with `count` steps, the first being step k0.
+    __device__ __forceinline__ void flush_tile(int k0, int count, double* __restrict__ part,
+                                               int nblk) {
+        k_first = k0;
+        filled = count;
+        flush(part, nblk);
     }
 
     __device__ __forceinline__ void flush(double* __restrict__ part, int nblk) {
         if (filled == 0)
             return;
-        __syncthreads();
+        lds_barrier();
         const int t = threadIdx.x;
         const int r = t >> 4;
         const int q = t & 15;
@@ -256,7 +292,7 @@ struct StepReducer {
                 part[(size_t)(k * D + c) * nblk + blockIdx.x] = s;
             }
         }
-        __syncthreads();
+        lds_barrier();
         filled = 0;
     }
 };

@@ -23,12 +23,12 @@ namespace jd {
 template <typename Real, int D>
 struct SweepArgs {
     Coef<Real, D> c;
-    PoissonThresholds thr;
-    const Real* tab;  // N rows of 2D: B u_k (D), then x_d(t_k) (D)
+    const PoissonTable* thr;  // staged in the workspace header
     void* traj;       // trajectory or checkpoints
     double* part;     // per-block partial sums
-    int64_t M, ldm;
+    int64_t M;
     int N, d, K;
+    int nslots;  // trajectory slots per block: N (store) or ceil(N/K) (checkpoints)
     uint32_t key0, key1, iter;
     double dt64;
     // per-path diagnostics
@@ -38,26 +38,46 @@ struct SweepArgs {
     double* dcost;
 };
 
-// Trajectory rows: row `row` (= (k-1)*d + c for X_k, or (j-1)*d + c for
-// checkpoint j), column m.
+// Trajectory layout, blocked by the 256 paths of a sweep block: block b owns
+// a contiguous region of nslots * d rows of 256 elements; row (slot*d + c)
+// holds component c of X_k (slot k-1) or of checkpoint j (slot j-1) for the
+// block's paths.  A block therefore streams through one contiguous region
+// (1 KB per FP32 row), and every lane, including lanes past the last path,
+// owns an in-bounds column.  Padded components re-read component d-1 and
+// return 0.
+struct Cols {
+    int64_t stride;  // d * 256: elements between consecutive slots
+};
+
+__device__ __forceinline__ Cols make_cols(int d) {
+    Cols c;
+    c.stride = (int64_t)d * kThreads;
+    return c;
+}
+
+// Start of slot `slot` of this block's region (uniform).
+template <typename Real>
+__device__ __forceinline__ const Real* slot_row(const void* base, const Cols& cl, int nslots,
+                                                int slot) {
+    return (const Real*)base + ((int64_t)blockIdx.x * nslots + slot) * cl.stride;
+}
+
 template <typename Real, int D>
-__device__ __forceinline__ void load_state(const Real* __restrict__ base, int slot, int d,
-                                           int64_t ldm, int64_t m, bool act, Real* X) {
+__device__ __forceinline__ void load_row(const Real* __restrict__ row, int d, Real* X) {
 #pragma unroll
     for (int c = 0; c < D; ++c) {
-        X[c] = (Real)0;
-        if (c < d && act)
-            X[c] = __builtin_nontemporal_load(base + ((size_t)slot * d + c) * ldm + m);
+        const int ce = c < d ? c : d - 1;
+        const Real v = __builtin_nontemporal_load(row + ce * kThreads + threadIdx.x);
+        X[c] = c < d ? v : (Real)0;
     }
 }
 
 template <typename Real, int D>
-__device__ __forceinline__ void store_state(Real* __restrict__ base, int slot, int d, int64_t ldm,
-                                            int64_t m, const Real* X) {
+__device__ __forceinline__ void store_row(Real* __restrict__ row, int d, const Real* X) {
 #pragma unroll
     for (int c = 0; c < D; ++c)
         if (c < d)
-            __builtin_nontemporal_store(X[c], base + ((size_t)slot * d + c) * ldm + m);
+            __builtin_nontemporal_store(X[c], row + c * kThreads + threadIdx.x);
 }
 
 template <typename Real, int D>
@@ -81,8 +101,14 @@ struct BMat {
 template <typename Real, int D>
 __global__ void __launch_bounds__(kThreads)
 k_table(const double* __restrict__ u, const double* __restrict__ xd, Real* __restrict__ tab, int N,
-        int d, BMat B) {
+        int d, BMat B, WsHeader* hdr, int clear_flag, PoissonTable pt) {
     const int idx = blockIdx.x * kThreads + threadIdx.x;
+    if (idx == 0 && clear_flag)
+        hdr->nonfinite = 0;  // every entry point starts here: the flag describes this call
+    if (idx < 32)
+        hdr->poisson.tm1[idx] = pt.tm1[idx];
+    if (idx == 0)
+        hdr->poisson.jmax = pt.jmax;
     if (idx >= N * D)
         return;
     const int k = idx / D, i = idx - k * D;
@@ -97,8 +123,12 @@ k_table(const double* __restrict__ u, const double* __restrict__ xd, Real* __res
 }
 
 // ---------------------------------------------------------------------------
+// The per-step table is a separate __restrict__ argument so that its rows are
+// read with scalar loads (they are wave-uniform), which do not join the
+// in-order vector-memory counter the trajectory loads and stores use.
 template <typename Real, int D, int MODE>
-__global__ void __launch_bounds__(kThreads) k_forward(SweepArgs<Real, D> a, double* __restrict__ cpart) {
+__global__ void __launch_bounds__(kThreads)
+k_forward(SweepArgs<Real, D> a, const Real* __restrict__ tab, double* __restrict__ cpart) {
     __shared__ double sh[kThreads];
     const int64_t m = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     const bool act = m < a.M;
@@ -108,20 +138,23 @@ __global__ void __launch_bounds__(kThreads) k_forward(SweepArgs<Real, D> a, doub
     for (int i = 0; i < D; ++i)
         X[i] = a.c.x0[i];
     double acc = 0.0;
-    Real* traj = (Real*)a.traj;
+    const Cols cl = make_cols(a.d);
+    Real* row = (Real*)slot_row<Real>(a.traj, cl, a.nslots, 0);  // next slot to write
     for (int k = 0; k < N; ++k) {
-        const Real* row = a.tab + (size_t)k * 2 * D;
-        acc += (double)sq_dist<Real, D>(X, row + D);
+        const Real* trow = tab + (size_t)k * 2 * D;
+        acc += (double)sq_dist<Real, D>(X, trow + D);
         Real zw[D], zj[D];
         int n;
         draws<Real, D>((uint32_t)m, (uint32_t)k, a.iter, a.key0, a.key1, a.thr, zw, zj, n);
-        euler_step<Real, D>(a.c, row, X, zw, zj, n);
+        euler_step<Real, D>(a.c, trow, X, zw, zj, n);
         if (MODE == FWD_STORE) {
-            if (act)
-                store_state<Real, D>(traj, k, a.d, a.ldm, m, X);
+            store_row<Real, D>(row, a.d, X);
+            row += cl.stride;
         } else if (MODE == FWD_CKPT) {
-            if (act && ((k + 1) % a.K == 0 || k + 1 == N))
-                store_state<Real, D>(traj, (k + a.K) / a.K - 1, a.d, a.ldm, m, X);
+            if ((k + 1) % a.K == 0 || k + 1 == N) {
+                store_row<Real, D>(row, a.d, X);
+                row += cl.stride;
+            }
         }
     }
     double C = 0.5 * a.dt64 * acc + 0.5 * (double)sq_dist<Real, D>(X, a.c.xT);
@@ -148,38 +181,72 @@ __device__ __forceinline__ void push_masked(StepReducer<D>& red, int k, const Re
     red.push(k, v, part, nblk);
 }
 
+// The stored trajectory is read in tiles of kSteps steps (the reducer's flush
+// granularity): the loads of the next tile are issued before the current tile
+// is swept, so every wave keeps kSteps*D loads in flight.
 template <typename Real, int D>
-__global__ void __launch_bounds__(kThreads) k_adjoint_stored(SweepArgs<Real, D> a) {
+__device__ __forceinline__ void load_tile(const SweepArgs<Real, D>& a, const Cols& cl, int k,
+                                          Real (*X)[D]) {
+    constexpr int S = StepReducer<D>::kSteps;
+    // X_kk lives in slot kk-1; steps below 1 re-read slot 0 (never used)
+    const Real* row = slot_row<Real>(a.traj, cl, a.nslots, k >= 1 ? k - 1 : 0);
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        load_row<Real, D>(row, a.d, X[s]);
+        if (k - s > 1)
+            row -= cl.stride;
+    }
+}
+
+template <typename Real, int D>
+__global__ void __launch_bounds__(kThreads)
+k_adjoint_stored(SweepArgs<Real, D> a, const Real* __restrict__ tab) {
+    constexpr int S = StepReducer<D>::kSteps;
     __shared__ double tile[StepReducer<D>::kRows][kThreads];
     StepReducer<D> red;
     red.init(tile);
     const int64_t m = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     const bool act = m < a.M;
     const int N = a.N, nblk = (int)gridDim.x;
-    const Real* traj = (const Real*)a.traj;
-    Real X[D], lam[D], Xn[D];
-    load_state<Real, D>(traj, N - 1, a.d, a.ldm, m, act, X);
+    const Cols cl = make_cols(a.d);
+    Real lam[D];
+    {
+        Real XN[D];
+        load_row<Real, D>(slot_row<Real>(a.traj, cl, a.nslots, N - 1), a.d, XN);
 #pragma unroll
-    for (int i = 0; i < D; ++i)
-        lam[i] = X[i] - a.c.xT[i];
-    dump_state(a, a.dX, N, m, X);
-    dump_state(a, a.dlam, N, m, lam);
-    if (N >= 2)
-        load_state<Real, D>(traj, N - 2, a.d, a.ldm, m, act, Xn);
-    for (int k = N - 1; k >= 0; --k) {
-        push_masked<Real, D>(red, k, lam, act, a.part, nblk);
-        if (k >= 1) {
-#pragma unroll
-            for (int i = 0; i < D; ++i)
-                X[i] = Xn[i];
-            if (k >= 2)
-                load_state<Real, D>(traj, k - 2, a.d, a.ldm, m, act, Xn);
-            adjoint_step<Real, D>(a.c, a.tab + (size_t)k * 2 * D + D, X, lam);
-            dump_state(a, a.dX, k, m, X);
-            dump_state(a, a.dlam, k, m, lam);
-        }
+        for (int i = 0; i < D; ++i)
+            lam[i] = XN[i] - a.c.xT[i];
+        dump_state(a, a.dX, N, m, XN);
+        dump_state(a, a.dlam, N, m, lam);
     }
-    red.flush(a.part, nblk);
+    Real cur[S][D], nxt[S][D];
+    load_tile<Real, D>(a, cl, N - 1, cur);
+    for (int k = N - 1; k >= 0; k -= S) {
+        if (k - S >= 1)
+            load_tile<Real, D>(a, cl, k - S, nxt);
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const int kk = k - s;
+            if (kk >= 0) {
+                Real v[D];
+#pragma unroll
+                for (int c = 0; c < D; ++c)
+                    v[c] = act ? lam[c] : (Real)0;
+                red.put(s, v);
+                if (kk >= 1) {
+                    adjoint_step<Real, D>(a.c, tab + (size_t)kk * 2 * D + D, cur[s], lam);
+                    dump_state(a, a.dX, kk, m, cur[s]);
+                    dump_state(a, a.dlam, kk, m, lam);
+                }
+            }
+        }
+        red.flush_tile(k, k + 1 < S ? k + 1 : S, a.part, nblk);
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+#pragma unroll
+            for (int c = 0; c < D; ++c)
+                cur[s][c] = nxt[s][c];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -189,7 +256,8 @@ __global__ void __launch_bounds__(kThreads) k_adjoint_stored(SweepArgs<Real, D> 
 // sub-segment, last first, is regenerated into an R-entry register buffer and
 // swept backwards.
 template <typename Real, int D, int R, int SMAX>
-__global__ void __launch_bounds__(kThreads) k_adjoint_recompute(SweepArgs<Real, D> a) {
+__global__ void __launch_bounds__(kThreads)
+k_adjoint_recompute(SweepArgs<Real, D> a, const Real* __restrict__ tab) {
     __shared__ double tile[StepReducer<D>::kRows][kThreads];
     StepReducer<D> red;
     red.init(tile);
@@ -197,11 +265,11 @@ __global__ void __launch_bounds__(kThreads) k_adjoint_recompute(SweepArgs<Real, 
     const bool act = m < a.M;
     const int N = a.N, K = a.K, nblk = (int)gridDim.x;
     const int nseg = (N + K - 1) / K;
-    const Real* ck = (const Real*)a.traj;
+    const Cols cl = make_cols(a.d);
     Real lam[D];
     {
         Real XN[D];
-        load_state<Real, D>(ck, nseg - 1, a.d, a.ldm, m, act, XN);
+        load_row<Real, D>(slot_row<Real>(a.traj, cl, a.nslots, nseg - 1), a.d, XN);
 #pragma unroll
         for (int i = 0; i < D; ++i)
             lam[i] = XN[i] - a.c.xT[i];
@@ -219,7 +287,7 @@ __global__ void __launch_bounds__(kThreads) k_adjoint_recompute(SweepArgs<Real, 
             for (int i = 0; i < D; ++i)
                 X[i] = a.c.x0[i];
         } else {
-            load_state<Real, D>(ck, j - 1, a.d, a.ldm, m, act, X);
+            load_row<Real, D>(slot_row<Real>(a.traj, cl, a.nslots, j - 1), a.d, X);
         }
 #pragma unroll
         for (int i = 0; i < D; ++i)
@@ -229,7 +297,7 @@ __global__ void __launch_bounds__(kThreads) k_adjoint_recompute(SweepArgs<Real, 
                 Real zw[D], zj[D];
                 int n;
                 draws<Real, D>((uint32_t)m, (uint32_t)k, a.iter, a.key0, a.key1, a.thr, zw, zj, n);
-                euler_step<Real, D>(a.c, a.tab + (size_t)k * 2 * D, X, zw, zj, n);
+                euler_step<Real, D>(a.c, tab + (size_t)k * 2 * D, X, zw, zj, n);
             }
 #pragma unroll
             for (int t = 1; t < SMAX; ++t)
@@ -260,7 +328,7 @@ __global__ void __launch_bounds__(kThreads) k_adjoint_recompute(SweepArgs<Real, 
                     Real zw[D], zj[D];
                     int n;
                     draws<Real, D>((uint32_t)m, (uint32_t)k, a.iter, a.key0, a.key1, a.thr, zw, zj, n);
-                    euler_step<Real, D>(a.c, a.tab + (size_t)k * 2 * D, buf[r], zw, zj, n);
+                    euler_step<Real, D>(a.c, tab + (size_t)k * 2 * D, buf[r], zw, zj, n);
                 }
             }
 #pragma unroll
@@ -269,7 +337,7 @@ __global__ void __launch_bounds__(kThreads) k_adjoint_recompute(SweepArgs<Real, 
                     const int k = a0 + r;
                     push_masked<Real, D>(red, k, lam, act, a.part, nblk);
                     if (k >= 1) {
-                        adjoint_step<Real, D>(a.c, a.tab + (size_t)k * 2 * D + D, buf[r], lam);
+                        adjoint_step<Real, D>(a.c, tab + (size_t)k * 2 * D + D, buf[r], lam);
                         dump_state(a, a.dX, k, m, buf[r]);
                         dump_state(a, a.dlam, k, m, lam);
                     }
@@ -285,7 +353,7 @@ __global__ void __launch_bounds__(kThreads) k_adjoint_recompute(SweepArgs<Real, 
 // order, then g_k = nu u_k + B^T (sum / M).
 __global__ void __launch_bounds__(kThreads)
 k_finalize_grad(const double* __restrict__ part, int nblk, int D, int d, int64_t M, double nu,
-                const double* __restrict__ u, BMat B, double* __restrict__ g) {
+                const double* __restrict__ u, BMat B, double* __restrict__ g, WsHeader* hdr) {
     __shared__ double sh[kThreads];
     __shared__ double G[8];
     const int k = blockIdx.x;
@@ -304,7 +372,10 @@ k_finalize_grad(const double* __restrict__ part, int nblk, int D, int d, int64_t
         double v = 0.0;
         for (int j = 0; j < d; ++j)
             v += B.b[j * d + i] * G[j];
-        g[(size_t)k * d + i] = nu * u[(size_t)k * d + i] + v;
+        const double gi = nu * u[(size_t)k * d + i] + v;
+        g[(size_t)k * d + i] = gi;
+        if (!isfinite(gi))
+            hdr->nonfinite = 1;
     }
 }
 
@@ -392,8 +463,15 @@ __global__ void k_clear_flag(WsHeader* hdr) {
 // ---------------------------------------------------------------------------
 template <typename Real, int D>
 __global__ void __launch_bounds__(kThreads)
-k_draws(SweepArgs<Real, D> a, int64_t m0, int64_t mc, int k0, int kc, Real* __restrict__ zw,
-        Real* __restrict__ zj, int32_t* __restrict__ counts) {
+k_draws(SweepArgs<Real, D> a, PoissonTable pt, int64_t m0, int64_t mc, int k0, int kc,
+        Real* __restrict__ zw, Real* __restrict__ zj, int32_t* __restrict__ counts) {
+    __shared__ PoissonTable tb;
+    if (threadIdx.x < 32)
+        tb.tm1[threadIdx.x] = pt.tm1[threadIdx.x];
+    if (threadIdx.x == 0)
+        tb.jmax = pt.jmax;
+    __syncthreads();
+    a.thr = &tb;
     const int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (idx >= mc * kc)
         return;
@@ -475,13 +553,11 @@ static SweepArgs<Real, D> make_args(const HostProblem& p, const HostRun& r) {
     }
     a.c.dt = (Real)p.dt;
     a.c.c3 = (Real)p.cubic;
-    for (int j = 0; j < 32; ++j)
-        a.thr.t[j] = p.thr[j];
-    a.tab = nullptr;
+    a.thr = nullptr;
     a.traj = nullptr;
     a.part = nullptr;
     a.M = r.M;
-    a.ldm = r.ldm;
+    a.nslots = r.mode == JD_RECOMPUTE ? (p.N + r.K - 1) / r.K : p.N;
     a.N = p.N;
     a.d = p.d;
     a.K = r.K;
@@ -534,30 +610,33 @@ static inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kThreads -
     } while (0)
 
 hipError_t launch_setup(const HostProblem& p, const HostRun& r, const double* u, void* tab,
-                        hipStream_t st) {
+                        WsHeader* hdr, int clear_flag, hipStream_t st) {
     const BMat B = make_B(p);
-    const unsigned nb = blocks_for((int64_t)p.N * p.D);
+    const unsigned nb = blocks_for((int64_t)p.N * p.D > 32 ? (int64_t)p.N * p.D : 32);
 #define JD_SETUP(T, DD) \
-    hipLaunchKernelGGL((k_table<T, DD>), dim3(nb), dim3(kThreads), 0, st, u, p.xd, (T*)tab, p.N, p.d, B)
+    hipLaunchKernelGGL((k_table<T, DD>), dim3(nb), dim3(kThreads), 0, st, u, p.xd, (T*)tab, p.N, p.d, B, hdr, clear_flag, p.poisson)
     JD_DISPATCH(r.prec, p.D, JD_SETUP);
 #undef JD_SETUP
     return hipGetLastError();
 }
 
 hipError_t launch_forward(const HostProblem& p, const HostRun& r, const void* tab, void* traj,
-                          int fwd_mode, double* cpart, hipStream_t st) {
+                          int fwd_mode, double* cpart, const WsHeader* hdr, hipStream_t st) {
     const unsigned nb = (unsigned)r.nblk;
 #define JD_FWD(T, DD)                                                                               \
     do {                                                                                            \
         SweepArgs<T, DD> a = make_args<T, DD>(p, r);                                                \
-        a.tab = (const T*)tab;                                                                      \
         a.traj = traj;                                                                              \
+        a.thr = &hdr->poisson;                                                                      \
         if (fwd_mode == FWD_STORE)                                                                  \
-            hipLaunchKernelGGL((k_forward<T, DD, FWD_STORE>), dim3(nb), dim3(kThreads), 0, st, a, cpart); \
+            hipLaunchKernelGGL((k_forward<T, DD, FWD_STORE>), dim3(nb), dim3(kThreads), 0, st, a,     \
+                               (const T*)tab, cpart);                                               \
         else if (fwd_mode == FWD_CKPT)                                                              \
-            hipLaunchKernelGGL((k_forward<T, DD, FWD_CKPT>), dim3(nb), dim3(kThreads), 0, st, a, cpart);  \
+            hipLaunchKernelGGL((k_forward<T, DD, FWD_CKPT>), dim3(nb), dim3(kThreads), 0, st, a,      \
+                               (const T*)tab, cpart);                                               \
         else                                                                                        \
-            hipLaunchKernelGGL((k_forward<T, DD, FWD_COST>), dim3(nb), dim3(kThreads), 0, st, a, cpart);  \
+            hipLaunchKernelGGL((k_forward<T, DD, FWD_COST>), dim3(nb), dim3(kThreads), 0, st, a,      \
+                               (const T*)tab, cpart);                                               \
     } while (0)
     JD_DISPATCH(r.prec, p.D, JD_FWD);
 #undef JD_FWD
@@ -565,20 +644,21 @@ hipError_t launch_forward(const HostProblem& p, const HostRun& r, const void* ta
 }
 
 hipError_t launch_adjoint(const HostProblem& p, const HostRun& r, const void* tab, const void* traj,
-                          double* apart, hipStream_t st) {
+                          double* apart, const WsHeader* hdr, hipStream_t st) {
     const unsigned nb = (unsigned)r.nblk;
 #define JD_ADJ(T, DD)                                                                             \
     do {                                                                                          \
         SweepArgs<T, DD> a = make_args<T, DD>(p, r);                                              \
-        a.tab = (const T*)tab;                                                                    \
         a.traj = const_cast<void*>(traj);                                                         \
         a.part = apart;                                                                           \
+        a.thr = &hdr->poisson;                                                                    \
         if (r.mode == JD_RECOMPUTE)                                                               \
             hipLaunchKernelGGL((k_adjoint_recompute<T, DD, RecomputeShape<T, DD>::R,              \
                                                     RecomputeShape<T, DD>::S>),                   \
-                               dim3(nb), dim3(kThreads), 0, st, a);                               \
+                               dim3(nb), dim3(kThreads), 0, st, a, (const T*)tab);                \
         else                                                                                      \
-            hipLaunchKernelGGL((k_adjoint_stored<T, DD>), dim3(nb), dim3(kThreads), 0, st, a);    \
+            hipLaunchKernelGGL((k_adjoint_stored<T, DD>), dim3(nb), dim3(kThreads), 0, st, a,     \
+                               (const T*)tab);                                                    \
     } while (0)
     JD_DISPATCH(r.prec, p.D, JD_ADJ);
 #undef JD_ADJ
@@ -586,9 +666,9 @@ hipError_t launch_adjoint(const HostProblem& p, const HostRun& r, const void* ta
 }
 
 hipError_t launch_finalize_grad(const HostProblem& p, const HostRun& r, const double* apart,
-                                const double* u, double* g, hipStream_t st) {
+                                const double* u, double* g, WsHeader* hdr, hipStream_t st) {
     hipLaunchKernelGGL(k_finalize_grad, dim3(p.N), dim3(kThreads), 0, st, apart, r.nblk, p.D, p.d,
-                       r.M, p.nu, u, make_B(p), g);
+                       r.M, p.nu, u, make_B(p), g, hdr);
     return hipGetLastError();
 }
 
@@ -623,7 +703,7 @@ hipError_t launch_draws(const HostProblem& p, const HostRun& r, int64_t m0, int6
 #define JD_DRAWS(T, DD)                                                                           \
     do {                                                                                          \
         SweepArgs<T, DD> a = make_args<T, DD>(p, r);                                              \
-        hipLaunchKernelGGL((k_draws<T, DD>), dim3(nb), dim3(kThreads), 0, st, a, m0, mc, k0, kc,  \
+        hipLaunchKernelGGL((k_draws<T, DD>), dim3(nb), dim3(kThreads), 0, st, a, p.poisson, m0, mc, k0, kc,  \
                            (T*)zw, (T*)zj, counts);                                               \
     } while (0)
     JD_DISPATCH(r.prec, p.D, JD_DRAWS);

@@ -97,9 +97,11 @@ def test_workspace_and_traj_sizes(L):
     assert tb64 == 2 * tb
     _, tck = _sizes(L, pr, B.make_run(M, precision="fp32", mode="recompute", K=32))
     assert tck == (p.N // 32 + (p.N % 32 > 0)) * M * 4
-    # rows padded to 64 paths
+    # blocks of 256 paths
     _, t7 = _sizes(L, pr, B.make_run(7, precision="fp32"))
-    assert t7 == p.N * 64 * 4
+    assert t7 == p.N * 256 * 4
+    _, t257 = _sizes(L, pr, B.make_run(257, precision="fp32"))
+    assert t257 == p.N * 512 * 4
 
 
 @host_only

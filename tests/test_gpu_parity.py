@@ -139,7 +139,7 @@ def test_cost_grad_and_paths(dev, oracle_runs, name, precision, mode):
     assert e_J <= tol["J"] and e_J2 <= tol["J"]
     assert e_g <= tol["g"]
     if mode == "store":
-        traj = eng.trajectory()[:, :, :w.M].double().cpu().numpy()  # (N, d, M)
+        traj = eng.trajectory().double().cpu().numpy()  # (N, d, M)
         assert per_path_error(np.transpose(traj, (2, 0, 1)), X[:, 1:, :]) <= tol["path"]
 
 
@@ -195,7 +195,7 @@ EDGE = [
 @pytest.mark.parametrize("mode", ["store", "recompute"])
 def test_edge_shapes(dev, label, d, N, M, K, mode):
     say("edge", label, mode)
-    p = wl.general_problem(d, N, seed=100 + d + N, cubic=0.07, lam=4.0)
+    p = wl.general_problem(d, N, seed=100 + d + N, cubic=0.07, lam=min(4.0, 1.5 * N))
     u = wl.random_control(p, 8, 0.2)
     eng = B.Engine(p, M=M, seed=77, precision="fp32", mode=mode, K=K, device=dev)
     dp, dumps = eng.path_dump(0, M)
