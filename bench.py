@@ -67,6 +67,32 @@ def parse():
     return ap.parse_args()
 
 
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("jd_device.hpp", "jd_kernels.hip", "jd_launch.hpp"):
+        with open(os.path.join(ROOT, "paper_2505_04328_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE passes scaled by a plain copy), if it was
+    taken from the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "c2_sweeps_fp32_store.md")
+    try:
+        with open(path) as fh:
+            for ln in fh:
+                if ln.strip().startswith("TRAFFIC "):
+                    rec = json.loads(ln.strip()[len("TRAFFIC "):])
+                    if rec.get("src") == kernel_source_hash():
+                        return rec["bytes_per_launch"].get(kernel)
+    except OSError:
+        pass
+    return None
+
+
 def percentile(xs, q):
     return float(np.percentile(np.asarray(xs), q))
 
@@ -184,12 +210,14 @@ def main():
     roofline = {"bound": "alu", "kernel": "k_forward<float,1,store>",
                 "achieved": slots / t_fwd / 1e12, "peak": VALU_PEAK_SLOTS / 1e12,
                 "unit": "TOP/s (full-rate VALU lane-op slots)",
-                "frac": slots / t_fwd / VALU_PEAK_SLOTS, "traffic": None,
+                "frac": slots / t_fwd / VALU_PEAK_SLOTS,
+                "traffic": profiled_traffic("jd::k_forward<float, 1, 1>"),
                 "slots_per_path_step": FWD_SLOTS_PER_PATH_STEP, "kernel_ms": t_fwd * 1e3}
     adj_bytes = 4.0 * M * N  # reads X_1..X_N once (FP32)
     roof_adj = {"bound": "hbm", "kernel": "k_adjoint_stored<float,1>",
                 "achieved": adj_bytes / t_adj / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                "frac": adj_bytes / t_adj / HBM_PEAK, "traffic": None, "kernel_ms": t_adj * 1e3}
+                "frac": adj_bytes / t_adj / HBM_PEAK,
+                "traffic": profiled_traffic("jd::k_adjoint_stored<float, 1>"), "kernel_ms": t_adj * 1e3}
 
     # ---- oracle on a bounded sample of the same workload, and GPU errors there
     cpu = None
