@@ -1,0 +1,61 @@
+"""Writes the full-size expected values used by tests/test_gpu_full_size.py.
+
+Calls only the FP64 oracle (oracle/) and the seeded workload generators: for
+the c2, c3 and c4 workloads at their full path counts, iteration word 0, seed 1
+and u = 0, it records J, ||g||_L2, the L2 projections <g, delta_i> on 16 fixed
+random directions (numpy default_rng(2), L2-normalised) and 64 sampled entries
+of g; for c2 also the whole gradient.  Run from the repository root:
+
+    python tests/golden/make_full_size.py            # all three (minutes on 8 cores)
+    python tests/golden/make_full_size.py c2
+"""
+from __future__ import annotations
+
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+from oracle import ref  # noqa: E402
+from paper_2505_04328_amd import workloads as wl  # noqa: E402
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def sample_index(p, count=64, seed=5):
+    rng = np.random.default_rng(seed)
+    return rng.integers(0, p.N * p.d, count)
+
+
+def main(names):
+    for name in names:
+        w = wl.config(name)
+        p = w.problem
+        t0 = time.time()
+        J, g = ref.cost_grad(p, w.M, w.seed, 0, np.zeros((p.N, p.d)))
+        dirs = wl.fd_directions(p, 16, seed=2)
+        proj = [float(p.dt * np.sum(g * dl)) for dl in dirs]
+        idx = sample_index(p)
+        rec = {
+            "config": name, "M": w.M, "N": p.N, "d": p.d, "seed": w.seed, "iter": 0, "u": "zeros",
+            "J": J, "gnorm_L2": float(np.sqrt(p.dt * np.sum(g * g))), "projections": proj,
+            "sample_index": [int(i) for i in idx], "sample_g": [float(g.reshape(-1)[i]) for i in idx],
+            "oracle_seconds": time.time() - t0,
+        }
+        if name == "c2":
+            rec["g"] = [float(x) for x in g.reshape(-1)]
+        path = os.path.join(HERE, f"full_{name}_it0.json")
+        with open(path, "w") as f:
+            f.write("# FP64 oracle, written by tests/golden/make_full_size.py\n")
+            json.dump(rec, f, indent=None)
+            f.write("\n")
+        print(f"{name}: J = {J:.15g}  ({time.time() - t0:.1f} s) -> {path}", flush=True)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:] or ["c2", "c3", "c4"])
