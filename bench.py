@@ -64,7 +64,54 @@ def parse():
                     help="kernels: time jd_forward / jd_adjoint only (for profiler runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")
+    ap.add_argument("--serving", action="store_true",
+                    help="instead: the request-server mix (Poisson arrivals, d in {1,2,4,8})")
+    ap.add_argument("--serving-requests", type=int, default=256)
+    ap.add_argument("--serving-m-hi", type=int, default=1 << 20)
+    ap.add_argument("--serving-n-hi", type=int, default=2000)
+    ap.add_argument("--serving-iters", type=int, default=30)
+    ap.add_argument("--arena-gb", type=float, default=160.0)
     return ap.parse_args()
+
+
+def serving_main(args):
+    """Request mix: Poisson arrivals at 50/s, d in {1,2,4,8}, M uniform in
+    [2^14, M_hi], N uniform in [100, N_hi], rate in [0, 10], 30 iterations each,
+    served by the request server from one device arena (admission by footprint,
+    stored trajectory when it takes at most 1/16 of the arena, else checkpoint
+    recompute)."""
+    import torch
+    from paper_2505_04328_amd import serving as S
+    from paper_2505_04328_amd import workloads as wl
+    reqs = wl.serving_requests(count=args.serving_requests, rate=50.0, seed=11,
+                               M_hi=args.serving_m_hi, N_hi=args.serving_n_hi,
+                               iters=args.serving_iters)
+    arena = int(args.arena_gb * (1 << 30))
+    srv = S.Server(arena, max_active=32, n_streams=4)
+    t_last = [time.perf_counter()]
+
+    def on_done(rec):
+        if time.perf_counter() - t_last[0] > 5:
+            log(f"  request {rec.rid} done, latency {rec.latency:.2f} s")
+            t_last[0] = time.perf_counter()
+
+    log(f"serving {len(reqs)} requests, arena {args.arena_gb} GB")
+    recs, wall = S.run_mix(srv, reqs, precision="fp32", store_limit=arena // 16, on_done=on_done)
+    srv.close()
+    lat = np.array([r.latency for r in recs])
+    ps = sum(r.path_steps for r in recs)
+    sw = sum(r.swept for r in recs)
+    line = {
+        "metric": "serving: request latency p50/p99 and aggregate forward+adjoint path-steps/s",
+        "value": ps / wall, "unit": "path-steps/s", "n_gpus": 1, "higher_is_better": True,
+        "requests": len(recs), "wall_s": wall, "latency_p50_s": float(np.percentile(lat, 50)),
+        "latency_p99_s": float(np.percentile(lat, 99)), "swept_path_steps_per_s": sw / wall,
+        "failed": int(sum(r.status != 0 for r in recs)),
+        "config": {"workload": f"c5 mix: {len(recs)} requests, Poisson 50/s, d in {{1,2,4,8}}, "
+                               f"M in [2^14, {args.serving_m_hi}], N in [100, {args.serving_n_hi}], "
+                               f"lambda in [0,10], {args.serving_iters} iterations, FP32 paths"},
+    }
+    print(json.dumps(line), flush=True)
 
 
 def kernel_source_hash() -> str:
@@ -102,6 +149,8 @@ def main():
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         sys.exit("bench.py: this build runs on one GPU only (the paths shard across GPUs "
                  "by contiguous path ranges, but no multi-GPU path is built); use --gpus 1")
+    if args.serving:
+        return serving_main(args)
     import torch
     from paper_2505_04328_amd import binding as B
     from paper_2505_04328_amd import workloads as wl

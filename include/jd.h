@@ -73,6 +73,7 @@ extern "C" {
 #define JD_ENONFINITE (-4)   /* J or g not finite */
 #define JD_ELINESEARCH (-5)  /* no Armijo step within max_backtracks; u unchanged */
 #define JD_EUNSUPPORTED (-6) /* valid but not built (e.g. checkpoint interval too long) */
+#define JD_EAGAIN (-7)       /* result not ready yet (request server) */
 
 /* Path arithmetic.  Reductions, J, g and the line search are FP64 in both. */
 #define JD_FP32 0

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libjd.so")
 
 JD_OK, JD_EINVAL, JD_EWORKSPACE, JD_EHIP, JD_ENONFINITE, JD_ELINESEARCH, JD_EUNSUPPORTED = (
     0, -1, -2, -3, -4, -5, -6)
+JD_EAGAIN = -7
 JD_FP32, JD_FP64 = 0, 1
 JD_STORE, JD_RECOMPUTE = 0, 1
 

@@ -6,14 +6,13 @@
 #include <stdint.h>
 #include <string.h>
 
-#include "jd_launch.hpp"
+#include "jd_host.hpp"
 
 using namespace jd;
+using namespace jd::host;
 
-namespace {
-
-constexpr size_t kAlign = 256;
-constexpr int64_t kMaxPaths = (int64_t)1 << 31;
+namespace jd {
+namespace host {
 
 size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -125,10 +124,6 @@ int prepare(const jd_problem* prob, const jd_run* run, HostProblem& p, HostRun& 
     return JD_OK;
 }
 
-struct Layout {
-    size_t hdr, tab, cpart, apart, gbuf, ut, total;
-};
-
 Layout layout(const HostProblem& p, const HostRun& r) {
     Layout L;
     size_t off = 0;
@@ -153,15 +148,6 @@ size_t traj_bytes(const HostProblem& p, const HostRun& r) {
     return rows * p.d * (size_t)r.ldm * real_size(r.prec);
 }
 
-struct Ws {
-    WsHeader* hdr;
-    void* tab;
-    double* cpart;
-    double* apart;
-    double* gbuf;
-    double* ut;
-};
-
 int bind_ws(const HostProblem& p, const HostRun& r, void* ws, size_t ws_bytes, Ws& w) {
     if (!ws)
         return JD_EINVAL;
@@ -179,12 +165,6 @@ int bind_ws(const HostProblem& p, const HostRun& r, void* ws, size_t ws_bytes, W
 }
 
 bool aligned(const void* ptr, size_t a) { return ((uintptr_t)ptr % a) == 0; }
-
-#define JD_TRY(expr)                      \
-    do {                                  \
-        if ((expr) != hipSuccess)         \
-            return JD_EHIP;               \
-    } while (0)
 
 int enqueue_forward(const HostProblem& p, const HostRun& r, const double* u, void* traj, double* J,
                     const Ws& w, hipStream_t st) {
@@ -206,7 +186,26 @@ int enqueue_cost_grad(const HostProblem& p, const HostRun& r, const double* u, d
     return JD_OK;
 }
 
-}  // namespace
+int enqueue_trial(const HostProblem& p, const HostRun& r, double* u, const jd_opt& opt, double zeta,
+                  const Ws& w, hipStream_t st) {
+    const int nd = p.N * p.d;
+    JD_TRY(launch_trial(u, w.gbuf, zeta, w.ut, nd, st));
+    JD_TRY(launch_setup(p, r, w.ut, w.tab, w.hdr, 0, st));
+    JD_TRY(launch_forward(p, r, w.tab, nullptr, FWD_COST, w.cpart, w.hdr, st));
+    JD_TRY(launch_finalize_cost(p, r, w.cpart, w.ut, nullptr, nullptr, w.hdr, 1, st));
+    JD_TRY(launch_armijo(w.hdr, u, w.ut, nd, opt.c_armijo, zeta, p.dt, st));
+    return JD_OK;
+}
+
+int validate_opt(const jd_opt* opt) {
+    if (!opt || opt->n_max < 0 || opt->max_backtracks < 1 || !(opt->zeta0 > 0.0) ||
+        !(opt->rho > 0.0) || !(opt->rho < 1.0) || !(opt->c_armijo > 0.0) || !(opt->tol >= 0.0))
+        return JD_EINVAL;
+    return JD_OK;
+}
+
+}  // namespace host
+}  // namespace jd
 
 extern "C" {
 
@@ -221,6 +220,7 @@ const char* jd_strerror(int code) {
     case JD_ENONFINITE: return "non-finite cost or gradient";
     case JD_ELINESEARCH: return "no Armijo step within max_backtracks";
     case JD_EUNSUPPORTED: return "unsupported configuration (checkpoint interval too long)";
+    case JD_EAGAIN: return "not ready";
     default: return "unknown error";
     }
 }
@@ -304,21 +304,16 @@ int jd_optimize(const jd_problem* prob, const jd_run* run, const jd_opt* opt, do
     int rc = prepare(prob, run, p, r);
     if (rc)
         return rc;
-    if (!opt || !u || !traj || !aligned(traj, real_size(r.prec)))
-        return JD_EINVAL;
-    if (opt->n_max < 0 || opt->max_backtracks < 1 || !(opt->zeta0 > 0.0) || !(opt->rho > 0.0) ||
-        !(opt->rho < 1.0) || !(opt->c_armijo > 0.0) || !(opt->tol >= 0.0))
+    if (!u || !traj || !aligned(traj, real_size(r.prec)) || validate_opt(opt))
         return JD_EINVAL;
     Ws w;
     if ((rc = bind_ws(p, r, ws, ws_bytes, w)))
         return rc;
-    const int nd = p.N * p.d;
     if (iters_done)
         *iters_done = 0;
     JD_TRY(launch_clear_flag(w.hdr, stream));
     const uint32_t iter0 = r.iter;
-    int n = 0;
-    for (; n < opt->n_max; ++n) {
+    for (int n = 0; n < opt->n_max; ++n) {
         r.iter = iter0 + (uint32_t)n;
         if ((rc = enqueue_cost_grad(p, r, u, nullptr, w.gbuf, traj, w, stream)))
             return rc;
@@ -327,11 +322,8 @@ int jd_optimize(const jd_problem* prob, const jd_run* run, const jd_opt* opt, do
         int bt = 0;
         bool accepted = false;
         for (; bt < opt->max_backtracks; ++bt) {
-            JD_TRY(launch_trial(u, w.gbuf, zeta, w.ut, nd, stream));
-            JD_TRY(launch_setup(p, r, w.ut, w.tab, w.hdr, 0, stream));
-            JD_TRY(launch_forward(p, r, w.tab, nullptr, FWD_COST, w.cpart, w.hdr, stream));
-            JD_TRY(launch_finalize_cost(p, r, w.cpart, w.ut, nullptr, nullptr, w.hdr, 1, stream));
-            JD_TRY(launch_armijo(w.hdr, u, w.ut, nd, opt->c_armijo, zeta, p.dt, stream));
+            if ((rc = enqueue_trial(p, r, u, *opt, zeta, w, stream)))
+                return rc;
             JD_TRY(hipMemcpyAsync(&h, w.hdr, sizeof(h), hipMemcpyDeviceToHost, stream));
             JD_TRY(hipStreamSynchronize(stream));
             if (h.nonfinite)
@@ -356,10 +348,8 @@ int jd_optimize(const jd_problem* prob, const jd_run* run, const jd_opt* opt, do
         }
         if (iters_done)
             *iters_done = n + 1;
-        if (E <= opt->tol) {
-            ++n;
+        if (E <= opt->tol)
             break;
-        }
     }
     return JD_OK;
 }

@@ -227,19 +227,21 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 
 // Per-step sums over the block's paths of the adjoint (the Monte Carlo
 // gradient's summand), written as FP64 block partials part[row * nblk + blk]
-// with row = k*D + c.  Each thread deposits its values into an LDS tile of
-// kRows rows x kThreads columns; when the tile is full, 16 lanes per row sum
-// 16 columns each (column q, q+16, ...) and combine by an xor butterfly, so
-// the order of every sum is fixed and the result is bit-reproducible.
-template <int D>
+// with row = k*D + c.  Each thread deposits its values, in the path precision
+// T (exact), into an LDS tile of kRows rows x kThreads columns; when the tile
+// is full, 16 lanes per row sum 16 columns each (column q, q+16, ...) in FP64
+// and combine by an xor butterfly, so the order of every sum is fixed and the
+// result is bit-reproducible.  An FP32 tile is 16 KB, which leaves room for
+// eight blocks per CU.
+template <int D, typename T>
 struct StepReducer {
     static constexpr int kRows = 16;
     static constexpr int kSteps = kRows / D;  // steps per flush
-    double (*tile)[kThreads];
+    T (*tile)[kThreads];
     int filled;   // steps deposited since the last flush
     int k_first;  // step index of the first deposited step (steps go downwards)
 
-    __device__ __forceinline__ void init(double (*t)[kThreads]) {
+    __device__ __forceinline__ void init(T (*t)[kThreads]) {
         tile = t;
         filled = 0;
         k_first = 0;
@@ -259,7 +261,7 @@ struct StepReducer {
     __device__ __forceinline__ void put(int s, const Real* v) {
 #pragma unroll
         for (int c = 0; c < D; ++c)
-            tile[s * D + c][threadIdx.x] = (double)v[c];
+            tile[s * D + c][threadIdx.x] = (T)v[c];
     }
 
     // Flush a tile filled by put() with `count` steps, the first being step k0.
@@ -281,7 +283,7 @@ struct StepReducer {
             double s = 0.0;
 #pragma unroll
             for (int j = 0; j < kThreads / 16; ++j)
-                s += tile[r][j * 16 + q];
+                s += (double)tile[r][j * 16 + q];
             s += __shfl_xor(s, 8, 16);
             s += __shfl_xor(s, 4, 16);
             s += __shfl_xor(s, 2, 16);

@@ -172,7 +172,7 @@ k_forward(SweepArgs<Real, D> a, const Real* __restrict__ tab, double* __restrict
 
 // ---------------------------------------------------------------------------
 template <typename Real, int D>
-__device__ __forceinline__ void push_masked(StepReducer<D>& red, int k, const Real* lam, bool act,
+__device__ __forceinline__ void push_masked(StepReducer<D, Real>& red, int k, const Real* lam, bool act,
                                             double* part, int nblk) {
     Real v[D];
 #pragma unroll
@@ -187,7 +187,7 @@ __device__ __forceinline__ void push_masked(StepReducer<D>& red, int k, const Re
 template <typename Real, int D>
 __device__ __forceinline__ void load_tile(const SweepArgs<Real, D>& a, const Cols& cl, int k,
                                           Real (*X)[D]) {
-    constexpr int S = StepReducer<D>::kSteps;
+    constexpr int S = StepReducer<D, Real>::kSteps;
     // X_kk lives in slot kk-1; steps below 1 re-read slot 0 (never used)
     const Real* row = slot_row<Real>(a.traj, cl, a.nslots, k >= 1 ? k - 1 : 0);
 #pragma unroll
@@ -201,9 +201,9 @@ __device__ __forceinline__ void load_tile(const SweepArgs<Real, D>& a, const Col
 template <typename Real, int D>
 __global__ void __launch_bounds__(kThreads)
 k_adjoint_stored(SweepArgs<Real, D> a, const Real* __restrict__ tab) {
-    constexpr int S = StepReducer<D>::kSteps;
-    __shared__ double tile[StepReducer<D>::kRows][kThreads];
-    StepReducer<D> red;
+    constexpr int S = StepReducer<D, Real>::kSteps;
+    __shared__ Real tile[StepReducer<D, Real>::kRows][kThreads];
+    StepReducer<D, Real> red;
     red.init(tile);
     const int64_t m = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     const bool act = m < a.M;
@@ -258,8 +258,8 @@ k_adjoint_stored(SweepArgs<Real, D> a, const Real* __restrict__ tab) {
 template <typename Real, int D, int R, int SMAX>
 __global__ void __launch_bounds__(kThreads)
 k_adjoint_recompute(SweepArgs<Real, D> a, const Real* __restrict__ tab) {
-    __shared__ double tile[StepReducer<D>::kRows][kThreads];
-    StepReducer<D> red;
+    __shared__ Real tile[StepReducer<D, Real>::kRows][kThreads];
+    StepReducer<D, Real> red;
     red.init(tile);
     const int64_t m = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     const bool act = m < a.M;

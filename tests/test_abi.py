@@ -14,7 +14,7 @@ from paper_2505_04328_amd import binding as B
 from paper_2505_04328_amd import workloads as wl
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "jd.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("jd.h", "jd_server.h")]
 
 
 def _gpu_visible() -> bool:
@@ -39,10 +39,12 @@ def L():
 
 
 def declared_functions():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\**\s+\**(jd_[a-z_0-9]+)\s*\(", text,
-                                 flags=re.M)))
+    names = set()
+    for h in HEADERS:
+        text = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\**\s+\**(jd_[a-z_0-9]+)\s*\(", text,
+                                flags=re.M))
+    return sorted(names)
 
 
 def test_every_declared_symbol_is_exported(L):
@@ -53,7 +55,11 @@ def test_every_declared_symbol_is_exported(L):
     exported = {ln.split()[-1] for ln in out.splitlines() if " T " in ln}
     missing = [n for n in names if n not in exported]
     assert not missing, missing
-    assert set(B.EXPORTED) == set(names)
+    assert set(B.EXPORTED) | set(SERVER) == set(names)
+
+
+SERVER = ["jd_server_request_bytes", "jd_server_create", "jd_server_submit",
+          "jd_server_progress", "jd_server_result", "jd_server_destroy"]
 
 
 def test_version_and_strerror(L):
@@ -191,3 +197,25 @@ def test_draws_and_philox_argument_checks(L):
     assert L.jd_philox(1, None, 5, None, None) == B.JD_EINVAL
     assert L.jd_philox(1, None, 0, None, None) == B.JD_OK
     assert L.jd_poisson_thresholds(-1.0, None) == B.JD_EINVAL
+
+
+@host_only
+def test_server_arguments_checked_on_host(L):
+    from paper_2505_04328_amd import serving as S
+    Ls = S.lib()
+    h = C.c_void_p()
+    assert Ls.jd_server_create(None, 1 << 20, 4, 2, C.byref(h)) == B.JD_EINVAL
+    assert Ls.jd_server_create(C.c_void_p(0x1000), 1 << 20, 0, 2, C.byref(h)) == B.JD_EINVAL
+    assert Ls.jd_server_create(C.c_void_p(0x1000), 1 << 20, 4, 17, C.byref(h)) == B.JD_EINVAL
+    assert Ls.jd_server_progress(None, None, None, None) == B.JD_EINVAL
+    assert Ls.jd_server_result(None, 1, None, None, None, None) == B.JD_EINVAL
+    assert Ls.jd_server_submit(None, None, None, None, None, None, None) == B.JD_EINVAL
+
+
+def test_server_request_bytes(L):
+    from paper_2505_04328_amd import serving as S
+    p = wl.general_problem(3, 100, seed=2)
+    nb = S.request_bytes(p, 1000)
+    # control + target + trajectory (100 steps x 3 comps x 1024 columns FP32) + workspace
+    assert nb >= 2 * 100 * 3 * 8 + 100 * 3 * 1024 * 4
+    assert S.request_bytes(p, 1000, mode="recompute", K=10) < nb
