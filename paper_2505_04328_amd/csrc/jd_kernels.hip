@@ -49,6 +49,11 @@ struct Cols {
     int64_t stride;  // d * 256: elements between consecutive slots
 };
 
+// Raw buffer descriptor word 3 for gfx9-family buffer loads of plain dwords,
+// and the non-temporal cache policy bit of buffer/global loads.
+constexpr int kBufferConfig = 0x00020000;
+constexpr int kNontemporal = 2;
+
 __device__ __forceinline__ Cols make_cols(int d) {
     Cols c;
     c.stride = (int64_t)d * kThreads;
@@ -183,7 +188,11 @@ __device__ __forceinline__ void push_masked(StepReducer<D, Real>& red, int k, co
 
 // The stored trajectory is read in tiles of kSteps steps (the reducer's flush
 // granularity): the loads of the next tile are issued before the current tile
-// is swept, so every wave keeps kSteps*D loads in flight.
+// is swept, so every wave keeps kSteps*D loads in flight.  A full tile (all of
+// its steps >= 1) is one contiguous piece of the block's region and is read with
+// raw buffer loads: one scalar descriptor per tile and per-lane byte offsets
+// computed once, so the loads need no address arithmetic.  The last (partial)
+// tile uses ordinary loads with clamped slots.
 template <typename Real, int D>
 __device__ __forceinline__ void load_tile(const SweepArgs<Real, D>& a, const Cols& cl, int k,
                                           Real (*X)[D]) {
@@ -198,7 +207,66 @@ __device__ __forceinline__ void load_tile(const SweepArgs<Real, D>& a, const Col
     }
 }
 
+template <typename Real>
+__device__ __forceinline__ Real buffer_load(__amdgpu_buffer_rsrc_t r, uint32_t off);
+template <>
+__device__ __forceinline__ float buffer_load<float>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, kNontemporal));
+}
+template <>
+__device__ __forceinline__ double buffer_load<double>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, kNontemporal));
+}
+
+// Full tile with top step k: slots k-1 (s = 0) down to k-S (s = S-1).
 template <typename Real, int D>
+__device__ __forceinline__ void load_tile_buffer(const Real* region, int64_t stride, int k,
+                                                 const uint32_t (*voff)[D], int d, Real (*X)[D]) {
+    constexpr int S = StepReducer<D, Real>::kSteps;
+    const Real* base = region + (int64_t)(k - S) * stride;
+    const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)base, (short)0, (int)(S * stride * (int64_t)sizeof(Real)), kBufferConfig);
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            const Real v = buffer_load<Real>(r, voff[s][c]);
+            X[s][c] = c < d ? v : (Real)0;
+        }
+}
+
+// One tile of the backward sweep: steps k, k-1, ..., k-count+1.  FULL tiles
+// have every step >= 1; the last tile may end at step 0, which contributes to
+// the gradient (lam_1) but needs no adjoint step.
+template <typename Real, int D, bool DUMP, bool FULL>
+__device__ __forceinline__ void sweep_tile(const SweepArgs<Real, D>& a, const Real* __restrict__ tab,
+                                           int k, Real (*X)[D], Real* lam, bool act, int64_t m,
+                                           StepReducer<D, Real>& red) {
+    constexpr int S = StepReducer<D, Real>::kSteps;
+    // a full tile's table rows are contiguous: one base, constant offsets
+    const Real* trow = FULL ? tab + (size_t)(k - S + 1) * 2 * D : tab;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        const int kk = k - s;
+        if (!FULL && kk < 0)
+            break;
+        Real v[D];
+#pragma unroll
+        for (int c = 0; c < D; ++c)
+            v[c] = act ? lam[c] : (Real)0;
+        red.put(s, v);
+        if (FULL || kk >= 1) {
+            const Real* xd = FULL ? trow + (S - 1 - s) * 2 * D + D : tab + (size_t)kk * 2 * D + D;
+            adjoint_step<Real, D>(a.c, xd, X[s], lam);
+            if (DUMP) {
+                dump_state(a, a.dX, kk, m, X[s]);
+                dump_state(a, a.dlam, kk, m, lam);
+            }
+        }
+    }
+}
+
+template <typename Real, int D, bool DUMP>
 __global__ void __launch_bounds__(kThreads)
 k_adjoint_stored(SweepArgs<Real, D> a, const Real* __restrict__ tab) {
     constexpr int S = StepReducer<D, Real>::kSteps;
@@ -209,43 +277,51 @@ k_adjoint_stored(SweepArgs<Real, D> a, const Real* __restrict__ tab) {
     const bool act = m < a.M;
     const int N = a.N, nblk = (int)gridDim.x;
     const Cols cl = make_cols(a.d);
+    const Real* region = slot_row<Real>(a.traj, cl, a.nslots, 0);
+    uint32_t voff[S][D];
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            const int ce = c < a.d ? c : a.d - 1;
+            voff[s][c] = (uint32_t)(((S - 1 - s) * cl.stride + ce * kThreads + threadIdx.x) *
+                                    (int64_t)sizeof(Real));
+        }
     Real lam[D];
     {
         Real XN[D];
-        load_row<Real, D>(slot_row<Real>(a.traj, cl, a.nslots, N - 1), a.d, XN);
+        load_row<Real, D>(region + (int64_t)(N - 1) * cl.stride, a.d, XN);
 #pragma unroll
         for (int i = 0; i < D; ++i)
             lam[i] = XN[i] - a.c.xT[i];
-        dump_state(a, a.dX, N, m, XN);
-        dump_state(a, a.dlam, N, m, lam);
+        if (DUMP) {
+            dump_state(a, a.dX, N, m, XN);
+            dump_state(a, a.dlam, N, m, lam);
+        }
     }
     Real cur[S][D], nxt[S][D];
-    load_tile<Real, D>(a, cl, N - 1, cur);
-    for (int k = N - 1; k >= 0; k -= S) {
-        if (k - S >= 1)
-            load_tile<Real, D>(a, cl, k - S, nxt);
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-            const int kk = k - s;
-            if (kk >= 0) {
-                Real v[D];
-#pragma unroll
-                for (int c = 0; c < D; ++c)
-                    v[c] = act ? lam[c] : (Real)0;
-                red.put(s, v);
-                if (kk >= 1) {
-                    adjoint_step<Real, D>(a.c, tab + (size_t)kk * 2 * D + D, cur[s], lam);
-                    dump_state(a, a.dX, kk, m, cur[s]);
-                    dump_state(a, a.dlam, kk, m, lam);
-                }
-            }
-        }
-        red.flush_tile(k, k + 1 < S ? k + 1 : S, a.part, nblk);
+    int k = N - 1;
+    if (k - S + 1 >= 1)
+        load_tile_buffer<Real, D>(region, cl.stride, k, voff, a.d, cur);
+    else
+        load_tile<Real, D>(a, cl, k, cur);
+    for (; k - S + 1 >= 1; k -= S) {
+        const int kn = k - S;
+        if (kn - S + 1 >= 1)
+            load_tile_buffer<Real, D>(region, cl.stride, kn, voff, a.d, nxt);
+        else if (kn >= 1)
+            load_tile<Real, D>(a, cl, kn, nxt);
+        sweep_tile<Real, D, DUMP, true>(a, tab, k, cur, lam, act, m, red);
+        red.flush_tile(k, S, a.part, nblk);
 #pragma unroll
         for (int s = 0; s < S; ++s)
 #pragma unroll
             for (int c = 0; c < D; ++c)
                 cur[s][c] = nxt[s][c];
+    }
+    if (k >= 0) {
+        sweep_tile<Real, D, DUMP, false>(a, tab, k, cur, lam, act, m, red);
+        red.flush_tile(k, k + 1, a.part, nblk);
     }
 }
 
@@ -656,9 +732,12 @@ hipError_t launch_adjoint(const HostProblem& p, const HostRun& r, const void* ta
             hipLaunchKernelGGL((k_adjoint_recompute<T, DD, RecomputeShape<T, DD>::R,              \
                                                     RecomputeShape<T, DD>::S>),                   \
                                dim3(nb), dim3(kThreads), 0, st, a, (const T*)tab);                \
+        else if (r.dump != nullptr)                                                               \
+            hipLaunchKernelGGL((k_adjoint_stored<T, DD, true>), dim3(nb), dim3(kThreads), 0, st,  \
+                               a, (const T*)tab);                                                 \
         else                                                                                      \
-            hipLaunchKernelGGL((k_adjoint_stored<T, DD>), dim3(nb), dim3(kThreads), 0, st, a,     \
-                               (const T*)tab);                                                    \
+            hipLaunchKernelGGL((k_adjoint_stored<T, DD, false>), dim3(nb), dim3(kThreads), 0, st, \
+                               a, (const T*)tab);                                                 \
     } while (0)
     JD_DISPATCH(r.prec, p.D, JD_ADJ);
 #undef JD_ADJ
