@@ -45,6 +45,10 @@ VALU_PEAK_SLOTS = 256 * 4 * 32 * 2.4e9
 #   running cost: difference, square, FP64 convert and accumulate              =  6
 # (the jump term is evaluated only in lanes that jump, ~lambda*dt of them)
 FWD_SLOTS_PER_PATH_STEP = 134
+# Backward step per path-step: X - x_d, the drift transpose, the cubic term
+# (3 products + 1), dt (1), the masked deposit into the reduction tile (1), and
+# the amortised FP64 tile reduction (16 converts + adds per 16 steps, 4 slots)
+ADJ_SLOTS_PER_PATH_STEP = 12
 HBM_PEAK = 8.0e12  # B/s
 METRIC = "forward+adjoint path-steps/s (FP32 vs FP64 GPU) at 1e-6 rel grad err; p50/p99"
 
@@ -192,8 +196,9 @@ def main():
     e32 = B.Engine(p, M=M, seed=w.seed, precision="fp32", mode="store", device=dev)
 
     if args.only == "kernels":
-        # forward (store) and adjoint alone, a few times each, for the profiler
+        # the fused step, then forward (store) and adjoint alone, for the profiler
         for it in range(args.warmup + args.steps):
+            e32.cost_grad(u, it=it)
             e32.forward(u, it=it)
             e32.adjoint(u, it=it)
         torch.cuda.synchronize()
@@ -255,18 +260,30 @@ def main():
                                                percentile(res["fp32_store_ms"], 50))
     t_fwd = percentile(fwd_ms, 50) * 1e-3
     t_adj = percentile(adj_ms, 50) * 1e-3
-    slots = FWD_SLOTS_PER_PATH_STEP * M * N
-    roofline = {"bound": "alu", "kernel": "k_forward<float,1,store>",
-                "achieved": slots / t_fwd / 1e12, "peak": VALU_PEAK_SLOTS / 1e12,
+    t_cg = percentile(res["fp32_store_ms"], 50) * 1e-3
+    # The dominant kernel is the fused per-block forward + adjoint sweep
+    # (k_cost_grad_stored): one launch per step, >99% of the step's time (the
+    # table and the two finalize kernels take ~20 us).  It is VALU-bound; its
+    # HBM traffic (8 B per path-step) overlaps with the forward arithmetic.
+    slots = (FWD_SLOTS_PER_PATH_STEP + ADJ_SLOTS_PER_PATH_STEP) * M * N
+    roofline = {"bound": "alu", "kernel": "k_cost_grad_stored<float,1>",
+                "achieved": slots / t_cg / 1e12, "peak": VALU_PEAK_SLOTS / 1e12,
                 "unit": "TOP/s (full-rate VALU lane-op slots)",
-                "frac": slots / t_fwd / VALU_PEAK_SLOTS,
-                "traffic": profiled_traffic("jd::k_forward<float, 1, 1>"),
-                "slots_per_path_step": FWD_SLOTS_PER_PATH_STEP, "kernel_ms": t_fwd * 1e3}
-    adj_bytes = 4.0 * M * N  # reads X_1..X_N once (FP32)
-    roof_adj = {"bound": "hbm", "kernel": "k_adjoint_stored<float,1>",
-                "achieved": adj_bytes / t_adj / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                "frac": adj_bytes / t_adj / HBM_PEAK,
-                "traffic": profiled_traffic("jd::k_adjoint_stored<float, 1>"), "kernel_ms": t_adj * 1e3}
+                "frac": slots / t_cg / VALU_PEAK_SLOTS,
+                "traffic": profiled_traffic("jd::k_cost_grad_stored<float, 1>"),
+                "slots_per_path_step": FWD_SLOTS_PER_PATH_STEP + ADJ_SLOTS_PER_PATH_STEP,
+                "kernel_ms": t_cg * 1e3,
+                "hbm_bytes_per_path_step": 8, "hbm_frac": 8.0 * M * N / t_cg / HBM_PEAK}
+    fwd_slots = FWD_SLOTS_PER_PATH_STEP * M * N
+    separate = {
+        "forward": {"kernel": "k_forward<float,1,store>", "bound": "alu", "kernel_ms": t_fwd * 1e3,
+                    "achieved": fwd_slots / t_fwd / 1e12, "frac": fwd_slots / t_fwd / VALU_PEAK_SLOTS,
+                    "traffic": profiled_traffic("jd::k_forward<float, 1, 1>")},
+        "adjoint": {"kernel": "k_adjoint_stored<float,1>", "bound": "hbm", "kernel_ms": t_adj * 1e3,
+                    "achieved": 4.0 * M * N / t_adj / 1e9, "unit": "GB/s",
+                    "frac": 4.0 * M * N / t_adj / HBM_PEAK,
+                    "traffic": profiled_traffic("jd::k_adjoint_stored<float, 1, false>")},
+    }
 
     # ---- oracle on a bounded sample of the same workload, and GPU errors there
     cpu = None
@@ -312,7 +329,7 @@ def main():
         "p50_ms": percentile(fp32s, 50),
         "p99_ms": percentile(fp32s, 99),
         "roofline": roofline,
-        "roofline_adjoint": roof_adj,
+        "separate_kernels": separate,
         "cpu_baseline": cpu,
         "forms": forms,
         "oracle_error_on_sample": sample_err,

@@ -177,10 +177,14 @@ int enqueue_forward(const HostProblem& p, const HostRun& r, const double* u, voi
 
 int enqueue_cost_grad(const HostProblem& p, const HostRun& r, const double* u, double* J,
                       double* g, void* traj, const Ws& w, hipStream_t st) {
-    const int fm = r.mode == JD_RECOMPUTE ? FWD_CKPT : FWD_STORE;
     JD_TRY(launch_setup(p, r, u, w.tab, w.hdr, 1, st));
-    JD_TRY(launch_forward(p, r, w.tab, traj, fm, w.cpart, w.hdr, st));
-    JD_TRY(launch_adjoint(p, r, w.tab, traj, w.apart, w.hdr, st));
+    if (r.mode == JD_STORE && r.dump == nullptr) {
+        JD_TRY(launch_cost_grad_stored(p, r, w.tab, traj, w.cpart, w.apart, w.hdr, st));
+    } else {
+        const int fm = r.mode == JD_RECOMPUTE ? FWD_CKPT : FWD_STORE;
+        JD_TRY(launch_forward(p, r, w.tab, traj, fm, w.cpart, w.hdr, st));
+        JD_TRY(launch_adjoint(p, r, w.tab, traj, w.apart, w.hdr, st));
+    }
     JD_TRY(launch_finalize_grad(p, r, w.apart, u, g, w.hdr, st));
     JD_TRY(launch_finalize_cost(p, r, w.cpart, u, g, J, w.hdr, 0, st));
     return JD_OK;

@@ -240,11 +240,13 @@ struct StepReducer {
     T (*tile)[kThreads];
     int filled;   // steps deposited since the last flush
     int k_first;  // step index of the first deposited step (steps go downwards)
+    int col;      // partial-sum column: the 256-path group this block sums
 
-    __device__ __forceinline__ void init(T (*t)[kThreads]) {
+    __device__ __forceinline__ void init(T (*t)[kThreads], int group) {
         tile = t;
         filled = 0;
         k_first = 0;
+        col = group;
     }
 
     template <typename Real>
@@ -291,7 +293,7 @@ struct StepReducer {
             if (q == 0) {
                 const int step = r / D, c = r - step * D;
                 const int k = k_first - step;
-                part[(size_t)(k * D + c) * nblk + blockIdx.x] = s;
+                part[(size_t)(k * D + c) * nblk + col] = s;
             }
         }
         lds_barrier();

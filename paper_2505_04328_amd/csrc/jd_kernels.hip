@@ -4,6 +4,7 @@
 //  k_forward          forward Euler-Maruyama sweep, one path per lane, draws in
 //                     registers, FP64 path cost, trajectory or checkpoint store
 //  k_adjoint_stored   backward adjoint sweep over the stored trajectory
+//  k_cost_grad_stored forward then backward sweep in one launch, per block
 //  k_adjoint_recompute backward adjoint sweep regenerating each checkpoint
 //                     segment with the same counters (bit-identical states)
 //  k_finalize_grad    fixed-order FP64 sum of the per-block partials -> g
@@ -27,6 +28,7 @@ struct SweepArgs {
     void* traj;       // trajectory or checkpoints
     double* part;     // per-block partial sums
     int64_t M;
+    int nblk;  // 256-path groups: ceil(M / 256), the columns of the partial sums
     int N, d, K;
     int nslots;  // trajectory slots per block: N (store) or ceil(N/K) (checkpoints)
     uint32_t key0, key1, iter;
@@ -60,11 +62,11 @@ __device__ __forceinline__ Cols make_cols(int d) {
     return c;
 }
 
-// Start of slot `slot` of this block's region (uniform).
+// Start of slot `slot` of path group g's region (uniform).
 template <typename Real>
 __device__ __forceinline__ const Real* slot_row(const void* base, const Cols& cl, int nslots,
-                                                int slot) {
-    return (const Real*)base + ((int64_t)blockIdx.x * nslots + slot) * cl.stride;
+                                                int64_t g, int slot) {
+    return (const Real*)base + (g * nslots + slot) * cl.stride;
 }
 
 template <typename Real, int D>
@@ -131,21 +133,28 @@ k_table(const double* __restrict__ u, const double* __restrict__ xd, Real* __res
 // The per-step table is a separate __restrict__ argument so that its rows are
 // read with scalar loads (they are wave-uniform), which do not join the
 // in-order vector-memory counter the trajectory loads and stores use.
+// Forward sweep of one 256-path group g, one step at a time: begin(), step(k)
+// for k = 0..N-1, finish().  The path of this lane is m = 256 g + lane.
 template <typename Real, int D, int MODE>
-__global__ void __launch_bounds__(kThreads)
-k_forward(SweepArgs<Real, D> a, const Real* __restrict__ tab, double* __restrict__ cpart) {
-    __shared__ double sh[kThreads];
-    const int64_t m = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    const bool act = m < a.M;
-    const int N = a.N;
+struct ForwardSweep {
     Real X[D];
+    double acc;
+    Real* row;  // next trajectory slot to write
+    int64_t m;
+    bool act;
+
+    __device__ __forceinline__ void begin(const SweepArgs<Real, D>& a, int64_t g) {
+        m = g * kThreads + threadIdx.x;
+        act = m < a.M;
 #pragma unroll
-    for (int i = 0; i < D; ++i)
-        X[i] = a.c.x0[i];
-    double acc = 0.0;
-    const Cols cl = make_cols(a.d);
-    Real* row = (Real*)slot_row<Real>(a.traj, cl, a.nslots, 0);  // next slot to write
-    for (int k = 0; k < N; ++k) {
+        for (int i = 0; i < D; ++i)
+            X[i] = a.c.x0[i];
+        acc = 0.0;
+        row = (Real*)slot_row<Real>(a.traj, make_cols(a.d), a.nslots, g, 0);
+    }
+
+    __device__ __forceinline__ void step(const SweepArgs<Real, D>& a, const Real* __restrict__ tab,
+                                         int k) {
         const Real* trow = tab + (size_t)k * 2 * D;
         acc += (double)sq_dist<Real, D>(X, trow + D);
         Real zw[D], zj[D];
@@ -154,25 +163,42 @@ k_forward(SweepArgs<Real, D> a, const Real* __restrict__ tab, double* __restrict
         euler_step<Real, D>(a.c, trow, X, zw, zj, n);
         if (MODE == FWD_STORE) {
             store_row<Real, D>(row, a.d, X);
-            row += cl.stride;
+            row += (int64_t)a.d * kThreads;
         } else if (MODE == FWD_CKPT) {
-            if ((k + 1) % a.K == 0 || k + 1 == N) {
+            if ((k + 1) % a.K == 0 || k + 1 == a.N) {
                 store_row<Real, D>(row, a.d, X);
-                row += cl.stride;
+                row += (int64_t)a.d * kThreads;
             }
         }
     }
-    double C = 0.5 * a.dt64 * acc + 0.5 * (double)sq_dist<Real, D>(X, a.c.xT);
-    if (!act)
-        C = 0.0;
-    if (a.dcost != nullptr) {
-        const int64_t p = m - a.dm0;
-        if (act && p >= 0 && p < a.dcount)
-            a.dcost[p] = C;
+
+    // Path cost (left-point running cost plus terminal term) and the group's
+    // fixed-order sum into cpart[g].  All threads of the block call it.
+    __device__ __forceinline__ void finish(const SweepArgs<Real, D>& a, double* __restrict__ cpart,
+                                           double* sh, int64_t g) {
+        double C = 0.5 * a.dt64 * acc + 0.5 * (double)sq_dist<Real, D>(X, a.c.xT);
+        if (!act)
+            C = 0.0;
+        if (a.dcost != nullptr) {
+            const int64_t p = m - a.dm0;
+            if (act && p >= 0 && p < a.dcount)
+                a.dcost[p] = C;
+        }
+        const double s = block_sum(C, sh);
+        if (threadIdx.x == 0)
+            cpart[g] = s;
     }
-    const double s = block_sum(C, sh);
-    if (threadIdx.x == 0)
-        cpart[blockIdx.x] = s;
+};
+
+template <typename Real, int D, int MODE>
+__global__ void __launch_bounds__(kThreads)
+k_forward(SweepArgs<Real, D> a, const Real* __restrict__ tab, double* __restrict__ cpart) {
+    __shared__ double sh[kThreads];
+    ForwardSweep<Real, D, MODE> f;
+    f.begin(a, blockIdx.x);
+    for (int k = 0; k < a.N; ++k)
+        f.step(a, tab, k);
+    f.finish(a, cpart, sh, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -194,11 +220,11 @@ __device__ __forceinline__ void push_masked(StepReducer<D, Real>& red, int k, co
 // computed once, so the loads need no address arithmetic.  The last (partial)
 // tile uses ordinary loads with clamped slots.
 template <typename Real, int D>
-__device__ __forceinline__ void load_tile(const SweepArgs<Real, D>& a, const Cols& cl, int k,
-                                          Real (*X)[D]) {
+__device__ __forceinline__ void load_tile(const SweepArgs<Real, D>& a, const Real* region,
+                                          const Cols& cl, int k, Real (*X)[D]) {
     constexpr int S = StepReducer<D, Real>::kSteps;
     // X_kk lives in slot kk-1; steps below 1 re-read slot 0 (never used)
-    const Real* row = slot_row<Real>(a.traj, cl, a.nslots, k >= 1 ? k - 1 : 0);
+    const Real* row = region + (int64_t)(k >= 1 ? k - 1 : 0) * cl.stride;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
         load_row<Real, D>(row, a.d, X[s]);
@@ -266,63 +292,125 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<Real, D>& a, const Re
     }
 }
 
+// Backward sweep of one 256-path group g over its stored trajectory, a tile at
+// a time: begin() sets lam_N and loads the first tile, full_tile() sweeps one
+// full tile while the next one loads, tail() sweeps what is left (down to step
+// 0).  Steps are reduced into partial column g.
 template <typename Real, int D, bool DUMP>
-__global__ void __launch_bounds__(kThreads)
-k_adjoint_stored(SweepArgs<Real, D> a, const Real* __restrict__ tab) {
-    constexpr int S = StepReducer<D, Real>::kSteps;
-    __shared__ Real tile[StepReducer<D, Real>::kRows][kThreads];
+struct StoredAdjoint {
+    static constexpr int S = StepReducer<D, Real>::kSteps;
     StepReducer<D, Real> red;
-    red.init(tile);
-    const int64_t m = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    const bool act = m < a.M;
-    const int N = a.N, nblk = (int)gridDim.x;
-    const Cols cl = make_cols(a.d);
-    const Real* region = slot_row<Real>(a.traj, cl, a.nslots, 0);
+    const Real* region;
     uint32_t voff[S][D];
-#pragma unroll
-    for (int s = 0; s < S; ++s)
-#pragma unroll
-        for (int c = 0; c < D; ++c) {
-            const int ce = c < a.d ? c : a.d - 1;
-            voff[s][c] = (uint32_t)(((S - 1 - s) * cl.stride + ce * kThreads + threadIdx.x) *
-                                    (int64_t)sizeof(Real));
-        }
     Real lam[D];
-    {
+    Real cur[S][D], nxt[S][D];
+    Cols cl;
+    int64_t m;
+    bool act;
+    int k;  // top step of the current tile
+
+    __device__ __forceinline__ void begin(const SweepArgs<Real, D>& a, Real (*tile)[kThreads],
+                                          int64_t g) {
+        red.init(tile, (int)g);
+        m = g * kThreads + threadIdx.x;
+        act = m < a.M;
+        cl = make_cols(a.d);
+        region = slot_row<Real>(a.traj, cl, a.nslots, g, 0);
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                const int ce = c < a.d ? c : a.d - 1;
+                voff[s][c] = (uint32_t)(((S - 1 - s) * cl.stride + ce * kThreads + threadIdx.x) *
+                                        (int64_t)sizeof(Real));
+            }
         Real XN[D];
-        load_row<Real, D>(region + (int64_t)(N - 1) * cl.stride, a.d, XN);
+        load_row<Real, D>(region + (int64_t)(a.N - 1) * cl.stride, a.d, XN);
 #pragma unroll
         for (int i = 0; i < D; ++i)
             lam[i] = XN[i] - a.c.xT[i];
         if (DUMP) {
-            dump_state(a, a.dX, N, m, XN);
-            dump_state(a, a.dlam, N, m, lam);
+            dump_state(a, a.dX, a.N, m, XN);
+            dump_state(a, a.dlam, a.N, m, lam);
         }
+        k = a.N - 1;
+        if (full())
+            load_tile_buffer<Real, D>(region, cl.stride, k, voff, a.d, cur);
+        else
+            load_tile<Real, D>(a, region, cl, k, cur);
     }
-    Real cur[S][D], nxt[S][D];
-    int k = N - 1;
-    if (k - S + 1 >= 1)
-        load_tile_buffer<Real, D>(region, cl.stride, k, voff, a.d, cur);
-    else
-        load_tile<Real, D>(a, cl, k, cur);
-    for (; k - S + 1 >= 1; k -= S) {
+
+    __device__ __forceinline__ bool full() const { return k - S + 1 >= 1; }
+
+    // Issues the next tile's loads; run() then sweeps the current tile.  Work
+    // placed between the two hides the loads.
+    __device__ __forceinline__ void prefetch(const SweepArgs<Real, D>& a) {
         const int kn = k - S;
         if (kn - S + 1 >= 1)
             load_tile_buffer<Real, D>(region, cl.stride, kn, voff, a.d, nxt);
         else if (kn >= 1)
-            load_tile<Real, D>(a, cl, kn, nxt);
+            load_tile<Real, D>(a, region, cl, kn, nxt);
+    }
+
+    __device__ __forceinline__ void run(const SweepArgs<Real, D>& a, const Real* __restrict__ tab) {
         sweep_tile<Real, D, DUMP, true>(a, tab, k, cur, lam, act, m, red);
-        red.flush_tile(k, S, a.part, nblk);
+        red.flush_tile(k, S, a.part, a.nblk);
 #pragma unroll
         for (int s = 0; s < S; ++s)
 #pragma unroll
             for (int c = 0; c < D; ++c)
                 cur[s][c] = nxt[s][c];
+        k -= S;
     }
-    if (k >= 0) {
-        sweep_tile<Real, D, DUMP, false>(a, tab, k, cur, lam, act, m, red);
-        red.flush_tile(k, k + 1, a.part, nblk);
+
+    __device__ __forceinline__ void tail(const SweepArgs<Real, D>& a, const Real* __restrict__ tab) {
+        if (k >= 0) {
+            sweep_tile<Real, D, DUMP, false>(a, tab, k, cur, lam, act, m, red);
+            red.flush_tile(k, k + 1, a.part, a.nblk);
+        }
     }
+};
+
+template <typename Real, int D, bool DUMP>
+__global__ void __launch_bounds__(kThreads)
+k_adjoint_stored(SweepArgs<Real, D> a, const Real* __restrict__ tab) {
+    __shared__ Real tile[StepReducer<D, Real>::kRows][kThreads];
+    StoredAdjoint<Real, D, DUMP> b;
+    b.begin(a, tile, blockIdx.x);
+    while (b.full()) {
+        b.prefetch(a);
+        b.run(a, tab);
+    }
+    b.tail(a, tab);
+}
+
+// Forward sweep with the stored trajectory, then, in the same block, the
+// backward sweep over that block's own paths.  Paths are independent and each
+// thread reads back only what it wrote itself (after a fence), so no grid-wide
+// ordering is needed: while some blocks are in their VALU-bound forward phase,
+// others are in their HBM-bound backward phase, and the two overlap on the
+// device.  Every value is computed exactly as by k_forward followed by
+// k_adjoint_stored.
+template <typename Real, int D>
+__global__ void __launch_bounds__(kThreads)
+k_cost_grad_stored(SweepArgs<Real, D> a, const Real* __restrict__ tab, double* __restrict__ cpart) {
+    __shared__ double sh[kThreads];
+    __shared__ Real tile[StepReducer<D, Real>::kRows][kThreads];
+    {
+        ForwardSweep<Real, D, FWD_STORE> f;
+        f.begin(a, blockIdx.x);
+        for (int k = 0; k < a.N; ++k)
+            f.step(a, tab, k);
+        f.finish(a, cpart, sh, blockIdx.x);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    StoredAdjoint<Real, D, false> b;
+    b.begin(a, tile, blockIdx.x);
+    while (b.full()) {
+        b.prefetch(a);
+        b.run(a, tab);
+    }
+    b.tail(a, tab);
 }
 
 // ---------------------------------------------------------------------------
@@ -336,16 +424,16 @@ __global__ void __launch_bounds__(kThreads)
 k_adjoint_recompute(SweepArgs<Real, D> a, const Real* __restrict__ tab) {
     __shared__ Real tile[StepReducer<D, Real>::kRows][kThreads];
     StepReducer<D, Real> red;
-    red.init(tile);
+    red.init(tile, blockIdx.x);
     const int64_t m = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     const bool act = m < a.M;
-    const int N = a.N, K = a.K, nblk = (int)gridDim.x;
+    const int N = a.N, K = a.K, nblk = a.nblk;
     const int nseg = (N + K - 1) / K;
     const Cols cl = make_cols(a.d);
     Real lam[D];
     {
         Real XN[D];
-        load_row<Real, D>(slot_row<Real>(a.traj, cl, a.nslots, nseg - 1), a.d, XN);
+        load_row<Real, D>(slot_row<Real>(a.traj, cl, a.nslots, blockIdx.x, nseg - 1), a.d, XN);
 #pragma unroll
         for (int i = 0; i < D; ++i)
             lam[i] = XN[i] - a.c.xT[i];
@@ -363,7 +451,7 @@ k_adjoint_recompute(SweepArgs<Real, D> a, const Real* __restrict__ tab) {
             for (int i = 0; i < D; ++i)
                 X[i] = a.c.x0[i];
         } else {
-            load_row<Real, D>(slot_row<Real>(a.traj, cl, a.nslots, j - 1), a.d, X);
+            load_row<Real, D>(slot_row<Real>(a.traj, cl, a.nslots, blockIdx.x, j - 1), a.d, X);
         }
 #pragma unroll
         for (int i = 0; i < D; ++i)
@@ -633,6 +721,7 @@ static SweepArgs<Real, D> make_args(const HostProblem& p, const HostRun& r) {
     a.traj = nullptr;
     a.part = nullptr;
     a.M = r.M;
+    a.nblk = r.nblk;
     a.nslots = r.mode == JD_RECOMPUTE ? (p.N + r.K - 1) / r.K : p.N;
     a.N = p.N;
     a.d = p.d;
@@ -741,6 +830,24 @@ hipError_t launch_adjoint(const HostProblem& p, const HostRun& r, const void* ta
     } while (0)
     JD_DISPATCH(r.prec, p.D, JD_ADJ);
 #undef JD_ADJ
+    return hipGetLastError();
+}
+
+hipError_t launch_cost_grad_stored(const HostProblem& p, const HostRun& r, const void* tab,
+                                  void* traj, double* cpart, double* apart, const WsHeader* hdr,
+                                  hipStream_t st) {
+    const unsigned nb = (unsigned)r.nblk;
+#define JD_CG(T, DD)                                                                              \
+    do {                                                                                          \
+        SweepArgs<T, DD> a = make_args<T, DD>(p, r);                                              \
+        a.traj = traj;                                                                            \
+        a.part = apart;                                                                           \
+        a.thr = &hdr->poisson;                                                                    \
+        hipLaunchKernelGGL((k_cost_grad_stored<T, DD>), dim3(nb), dim3(kThreads), 0, st, a,       \
+                           (const T*)tab, cpart);                                                 \
+    } while (0)
+    JD_DISPATCH(r.prec, p.D, JD_CG);
+#undef JD_CG
     return hipGetLastError();
 }
 

@@ -76,6 +76,10 @@ hipError_t launch_forward(const HostProblem& p, const HostRun& r, const void* ta
                           int fwd_mode, double* cpart, const WsHeader* hdr, hipStream_t st);
 hipError_t launch_adjoint(const HostProblem& p, const HostRun& r, const void* tab, const void* traj,
                           double* apart, const WsHeader* hdr, hipStream_t st);
+// Forward (stored trajectory) and adjoint fused per block (no dump support).
+hipError_t launch_cost_grad_stored(const HostProblem& p, const HostRun& r, const void* tab,
+                                  void* traj, double* cpart, double* apart, const WsHeader* hdr,
+                                  hipStream_t st);
 hipError_t launch_finalize_grad(const HostProblem& p, const HostRun& r, const double* apart,
                                 const double* u, double* g, WsHeader* hdr, hipStream_t st);
 // slot 0: J -> hdr->J (and J_out), with gnorm2 from g if g != nullptr; slot 1: -> hdr->J_trial

@@ -179,7 +179,7 @@ void release(jd_server* S, Request& q) {
     S->arena->release(q.off, q.bytes);
     S->free_mirrors.push_back(q.mirror);
     S->stream_load[q.stream]--;
-    hipEventDestroy(q.ev);
+    (void)hipEventDestroy(q.ev);
     S->active--;
 }
 
@@ -291,8 +291,8 @@ int jd_server_create(void* arena, size_t arena_bytes, int32_t max_active, int32_
         hipStream_t st;
         if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
             for (hipStream_t s : S->streams)
-                hipStreamDestroy(s);
-            hipHostFree(S->mirrors);
+                (void)hipStreamDestroy(s);
+            (void)hipHostFree(S->mirrors);
             return JD_EHIP;
         }
         S->streams.push_back(st);
@@ -416,15 +416,15 @@ int jd_server_destroy(jd_server* S) {
     if (!S)
         return JD_EINVAL;
     for (hipStream_t st : S->streams)
-        hipStreamSynchronize(st);
+        (void)hipStreamSynchronize(st);
     for (auto& kv : S->reqs) {
         Request& q = *kv.second;
         if (q.state == RUNNING || q.state == FINISHING)
-            hipEventDestroy(q.ev);
+            (void)hipEventDestroy(q.ev);
     }
     for (hipStream_t st : S->streams)
-        hipStreamDestroy(st);
-    hipHostFree(S->mirrors);
+        (void)hipStreamDestroy(st);
+    (void)hipHostFree(S->mirrors);
     delete S;
     return JD_OK;
 }
