@@ -20,20 +20,47 @@ __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
     return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
 }
 
-// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).  The counter word c0 is
-// the path index (lane-varying); c1..c3 and the key are wave-uniform, so the
-// compiler keeps the key schedule on the scalar unit.  Per round: two
-// 32x32->64-bit products (v_mad_u64_u32) and two three-input xors.
+// 32x32->64-bit product as (lo, hi).  SCALAR writes it as a 32-bit multiply
+// and a high multiply, which the compiler keeps on the scalar unit for
+// wave-uniform operands; the 64-bit form is matched to the vector
+// v_mad_u64_u32 (one instruction for lane-varying operands) even when the
+// operands are uniform.  Both give the same value.
+template <bool SCALAR>
+__device__ __forceinline__ void mul_wide(uint32_t m, uint32_t c, uint32_t& lo, uint32_t& hi) {
+    if (SCALAR) {
+        lo = m * c;
+        hi = __umulhi(m, c);
+    } else {
+        const uint64_t p = (uint64_t)m * (uint64_t)c;
+        lo = (uint32_t)p;
+        hi = (uint32_t)(p >> 32);
+    }
+}
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).  Per round: two
+// 32x32->64-bit products and two three-input xors.  In a sweep the counter is
+// (path m, step k, iteration, block) with c1..c3 and the key wave-uniform, so
+// round 1's second product, its xor into c0 and round 2's first product are
+// wave-uniform; SWEEP computes those on the scalar unit (v_bitop3 is a vector
+// instruction, so the uniform xor is written as two plain xors).
+template <bool SWEEP = false>
 __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                               uint32_t k0, uint32_t k1, uint32_t* out) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
-        const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
-        const uint32_t n0 = xor3((uint32_t)(p1 >> 32), c1, k0);
-        const uint32_t n2 = xor3((uint32_t)(p0 >> 32), c3, k1);
-        c1 = (uint32_t)p1;
-        c3 = (uint32_t)p0;
+        uint32_t p0lo, p0hi, p1lo, p1hi;
+        if (SWEEP && r == 1)
+            mul_wide<true>(0xD2511F53u, c0, p0lo, p0hi);
+        else
+            mul_wide<false>(0xD2511F53u, c0, p0lo, p0hi);
+        if (SWEEP && r == 0)
+            mul_wide<true>(0xCD9E8D57u, c2, p1lo, p1hi);
+        else
+            mul_wide<false>(0xCD9E8D57u, c2, p1lo, p1hi);
+        const uint32_t n0 = (SWEEP && r == 0) ? (p1hi ^ c1) ^ k0 : xor3(p1hi, c1, k0);
+        const uint32_t n2 = xor3(p0hi, c3, k1);
+        c1 = p1lo;
+        c3 = p0lo;
         c0 = n0;
         c2 = n2;
         k0 += 0x9E3779B9u;
@@ -52,30 +79,33 @@ __device__ __forceinline__ Real unit_uniform(uint32_t w) {
     return (Real)((w >> 8) | 1u) * (Real)(1.0 / 16777216.0);
 }
 
-// Box-Muller pair from two words: cosine branch and sine branch.  FP32 uses
-// the hardware transcendentals directly: v_log_f32 (log2), v_sqrt_f32 and
-// v_sin_f32 / v_cos_f32, whose argument is in revolutions, so sin(2 pi u) is
+// Box-Muller pair from two words (u_a, u_b): radius r = sqrt(-2 ln u_a) and
+// angle 2 pi u_b; the cosine branch r cos(2 pi u_b) and the sine branch
+// r sin(2 pi u_b) are two independent standard normals.  FP32 uses the
+// hardware transcendentals directly: v_log_f32 (log2), v_sqrt_f32 and
+// v_sin_f32 / v_cos_f32, whose argument is in revolutions, so cos(2 pi u) is
 // one instruction.  The uniforms are never 0, denormal or 1, so no range
 // handling is needed; the result matches the FP64 transform to within 1e-6
 // absolute, like the correctly-rounded library functions.
-__device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, float& zc, float& zs) {
+__device__ __forceinline__ float bm_radius(uint32_t a, float) {
     const float l2 = __builtin_amdgcn_logf(unit_uniform<float>(a));  // log2(u_a)
-    const float r = __builtin_amdgcn_sqrtf(-1.38629436111989061883f * l2);  // sqrt(-2 ln u_a)
-    const float ub = unit_uniform<float>(b);
-    zc = r * __builtin_amdgcn_cosf(ub);
-    zs = r * __builtin_amdgcn_sinf(ub);
+    return __builtin_amdgcn_sqrtf(-1.38629436111989061883f * l2);    // sqrt(-2 ln u_a)
 }
-__device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, double& zc, double& zs) {
-    const double r = sqrt(-2.0 * log(unit_uniform<double>(a)));
-    double s, c;
-    sincospi(2.0 * unit_uniform<double>(b), &s, &c);
-    zc = r * c;
-    zs = r * s;
+__device__ __forceinline__ float bm_cos(float r, float ub) { return r * __builtin_amdgcn_cosf(ub); }
+__device__ __forceinline__ float bm_sin(float r, float ub) { return r * __builtin_amdgcn_sinf(ub); }
+__device__ __forceinline__ double bm_radius(uint32_t a, double) {
+    return sqrt(-2.0 * log(unit_uniform<double>(a)));
 }
+__device__ __forceinline__ double bm_cos(double r, double ub) { return r * cospi(2.0 * ub); }
+__device__ __forceinline__ double bm_sin(double r, double ub) { return r * sinpi(2.0 * ub); }
 
-// Word made of the low bytes of the four words of Philox block 0.
+// Word made of the low bytes of the four words of Philox block 0:
+// byte j = low byte of word j.  v_perm_b32 selects bytes of the 8-byte value
+// {S0 (bytes 4-7), S1 (bytes 0-3)}; selector 0x0c gives a zero byte.
 __device__ __forceinline__ uint32_t poisson_word(const uint32_t* w) {
-    return (w[0] & 0xFFu) | ((w[1] & 0xFFu) << 8) | ((w[2] & 0xFFu) << 16) | (w[3] << 24);
+    const uint32_t lo = __builtin_amdgcn_perm(w[1], w[0], 0x0c0c0400u);  // [w0.b0, w1.b0, 0, 0]
+    const uint32_t hi = __builtin_amdgcn_perm(w[3], w[2], 0x04000c0cu);  // [0, 0, w2.b0, w3.b0]
+    return lo | hi;
 }
 
 // Count for word P.  The first comparison is the common case; the loop runs
@@ -109,20 +139,40 @@ struct Coef {
     Real c3;
 };
 
+// Draws of one path-step.  Component i's Gaussian pair comes from one
+// Box-Muller transform of words (2i, 2i+1): Z^W_i is its cosine branch, always
+// needed; Z^J_i its sine branch, evaluated by jump_normal() only where a jump
+// happens.
+template <typename Real, int D>
+struct StepDraws {
+    Real zw[D];
+    Real rad[D];  // Box-Muller radius
+    Real ang[D];  // angle uniform (revolutions)
+    int n;        // Poisson count
+};
+
+template <typename Real, int D>
+__device__ __forceinline__ Real jump_normal(const StepDraws<Real, D>& s, int i) {
+    return bm_sin(s.rad[i], s.ang[i]);
+}
+
 // Draws of path-step (m, k) under iteration word `iter`.
 template <typename Real, int D>
 __device__ __forceinline__ void draws(uint32_t m, uint32_t k, uint32_t iter, uint32_t key0,
-                                      uint32_t key1, const PoissonTable* __restrict__ thr, Real* zw,
-                                      Real* zj, int& n) {
+                                      uint32_t key1, const PoissonTable* __restrict__ thr,
+                                      StepDraws<Real, D>& s) {
     constexpr int NB = (D + 1) / 2;
     uint32_t w[4 * NB];
 #pragma unroll
-    for (int s = 0; s < NB; ++s)
-        philox4x32_10(m, k, iter, (uint32_t)s, key0, key1, &w[4 * s]);
+    for (int b = 0; b < NB; ++b)
+        philox4x32_10<true>(m, k, iter, (uint32_t)b, key0, key1, &w[4 * b]);
 #pragma unroll
-    for (int i = 0; i < D; ++i)
-        box_muller(w[2 * i], w[2 * i + 1], zw[i], zj[i]);
-    n = poisson_count(poisson_word(w), thr);
+    for (int i = 0; i < D; ++i) {
+        s.rad[i] = bm_radius(w[2 * i], (Real)0);
+        s.ang[i] = unit_uniform<Real>(w[2 * i + 1]);
+        s.zw[i] = bm_cos(s.rad[i], s.ang[i]);
+    }
+    s.n = poisson_count(poisson_word(w), thr);
 }
 
 template <typename Real>
@@ -138,11 +188,12 @@ __device__ __forceinline__ double count_sqrt<double>(int n) {
 
 // One Euler-Maruyama step with additive compound-Poisson jumps:
 //   X <- X + dt (A X - c3 X^3 + Bu_k) + sqrt(dt) s Z^W + n m_J + s_J sqrt(n) Z^J
-// bu = B u_k (per-step table row).  The jump term is only evaluated in lanes
-// with n > 0 (a few percent of path-steps).
+// bu = B u_k (per-step table row).  The jump term (with Z^J) is evaluated only
+// in waves where some lane jumps (lambda dt per path-step, so most waves skip
+// it) and applied only in the lanes with n > 0.
 template <typename Real, int D>
 __device__ __forceinline__ void euler_step(const Coef<Real, D>& c, const Real* __restrict__ bu,
-                                           Real* X, const Real* zw, const Real* zj, int n) {
+                                           Real* X, const StepDraws<Real, D>& s) {
     Real Y[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) {
@@ -153,14 +204,16 @@ __device__ __forceinline__ void euler_step(const Coef<Real, D>& c, const Real* _
         const Real x3 = X[i] * X[i] * X[i];
         f = fma(-c.c3, x3, f);
         Real y = fma(c.dt, f, X[i]);
-        Y[i] = fma(c.sq[i], zw[i], y);
+        Y[i] = fma(c.sq[i], s.zw[i], y);
     }
-    if (n != 0) {
-        const Real fn = (Real)n;
-        const Real sn = count_sqrt<Real>(n);
+    if (__builtin_amdgcn_ballot_w64(s.n != 0)) {
+        const Real fn = (Real)s.n;
+        const Real sn = count_sqrt<Real>(s.n);
 #pragma unroll
-        for (int i = 0; i < D; ++i)
-            Y[i] = Y[i] + fma(c.js[i] * sn, zj[i], fn * c.jm[i]);
+        for (int i = 0; i < D; ++i) {
+            const Real yj = Y[i] + fma(c.js[i] * sn, jump_normal(s, i), fn * c.jm[i]);
+            Y[i] = s.n != 0 ? yj : Y[i];
+        }
     }
 #pragma unroll
     for (int i = 0; i < D; ++i)

@@ -157,10 +157,9 @@ struct ForwardSweep {
                                          int k) {
         const Real* trow = tab + (size_t)k * 2 * D;
         acc += (double)sq_dist<Real, D>(X, trow + D);
-        Real zw[D], zj[D];
-        int n;
-        draws<Real, D>((uint32_t)m, (uint32_t)k, a.iter, a.key0, a.key1, a.thr, zw, zj, n);
-        euler_step<Real, D>(a.c, trow, X, zw, zj, n);
+        StepDraws<Real, D> z;
+        draws<Real, D>((uint32_t)m, (uint32_t)k, a.iter, a.key0, a.key1, a.thr, z);
+        euler_step<Real, D>(a.c, trow, X, z);
         if (MODE == FWD_STORE) {
             store_row<Real, D>(row, a.d, X);
             row += (int64_t)a.d * kThreads;
@@ -233,21 +232,26 @@ __device__ __forceinline__ void load_tile(const SweepArgs<Real, D>& a, const Rea
     }
 }
 
+// voff: per-lane byte offset; soff: wave-uniform byte offset (a scalar register).
 template <typename Real>
-__device__ __forceinline__ Real buffer_load(__amdgpu_buffer_rsrc_t r, uint32_t off);
+__device__ __forceinline__ Real buffer_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff);
 template <>
-__device__ __forceinline__ float buffer_load<float>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, kNontemporal));
+__device__ __forceinline__ float buffer_load<float>(__amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                                    uint32_t soff) {
+    return __builtin_bit_cast(float,
+                              __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, kNontemporal));
 }
 template <>
-__device__ __forceinline__ double buffer_load<double>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, kNontemporal));
+__device__ __forceinline__ double buffer_load<double>(__amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                                      uint32_t soff) {
+    return __builtin_bit_cast(double,
+                              __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, kNontemporal));
 }
 
 // Full tile with top step k: slots k-1 (s = 0) down to k-S (s = S-1).
 template <typename Real, int D>
 __device__ __forceinline__ void load_tile_buffer(const Real* region, int64_t stride, int k,
-                                                 const uint32_t (*voff)[D], int d, Real (*X)[D]) {
+                                                 const uint32_t* voff, int d, Real (*X)[D]) {
     constexpr int S = StepReducer<D, Real>::kSteps;
     const Real* base = region + (int64_t)(k - S) * stride;
     const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
@@ -256,7 +260,8 @@ __device__ __forceinline__ void load_tile_buffer(const Real* region, int64_t str
     for (int s = 0; s < S; ++s)
 #pragma unroll
         for (int c = 0; c < D; ++c) {
-            const Real v = buffer_load<Real>(r, voff[s][c]);
+            const Real v = buffer_load<Real>(
+                r, voff[c], (uint32_t)((S - 1 - s) * stride * (int64_t)sizeof(Real)));
             X[s][c] = c < d ? v : (Real)0;
         }
 }
@@ -301,7 +306,7 @@ struct StoredAdjoint {
     static constexpr int S = StepReducer<D, Real>::kSteps;
     StepReducer<D, Real> red;
     const Real* region;
-    uint32_t voff[S][D];
+    uint32_t voff[D];  // lane's byte offset of component c within a slot
     Real lam[D];
     Real cur[S][D], nxt[S][D];
     Cols cl;
@@ -309,7 +314,8 @@ struct StoredAdjoint {
     bool act;
     int k;  // top step of the current tile
 
-    __device__ __forceinline__ void begin(const SweepArgs<Real, D>& a, Real (*tile)[kThreads],
+    // lam_N and the reducer; no tile is loaded yet.
+    __device__ __forceinline__ void start(const SweepArgs<Real, D>& a, Real (*tile)[kThreads],
                                           int64_t g) {
         red.init(tile, (int)g);
         m = g * kThreads + threadIdx.x;
@@ -317,13 +323,10 @@ struct StoredAdjoint {
         cl = make_cols(a.d);
         region = slot_row<Real>(a.traj, cl, a.nslots, g, 0);
 #pragma unroll
-        for (int s = 0; s < S; ++s)
-#pragma unroll
-            for (int c = 0; c < D; ++c) {
-                const int ce = c < a.d ? c : a.d - 1;
-                voff[s][c] = (uint32_t)(((S - 1 - s) * cl.stride + ce * kThreads + threadIdx.x) *
-                                        (int64_t)sizeof(Real));
-            }
+        for (int c = 0; c < D; ++c) {
+            const int ce = c < a.d ? c : a.d - 1;
+            voff[c] = (uint32_t)((ce * kThreads + threadIdx.x) * sizeof(Real));
+        }
         Real XN[D];
         load_row<Real, D>(region + (int64_t)(a.N - 1) * cl.stride, a.d, XN);
 #pragma unroll
@@ -334,10 +337,21 @@ struct StoredAdjoint {
             dump_state(a, a.dlam, a.N, m, lam);
         }
         k = a.N - 1;
+    }
+
+    // Loads the tile with top step k into cur.
+    __device__ __forceinline__ void load(const SweepArgs<Real, D>& a) {
         if (full())
             load_tile_buffer<Real, D>(region, cl.stride, k, voff, a.d, cur);
         else
             load_tile<Real, D>(a, region, cl, k, cur);
+    }
+
+    // Sweeps the full tile in cur and moves to the next one.
+    __device__ __forceinline__ void sweep(const SweepArgs<Real, D>& a, const Real* __restrict__ tab) {
+        sweep_tile<Real, D, DUMP, true>(a, tab, k, cur, lam, act, m, red);
+        red.flush_tile(k, S, a.part, a.nblk);
+        k -= S;
     }
 
     __device__ __forceinline__ bool full() const { return k - S + 1 >= 1; }
@@ -353,14 +367,12 @@ struct StoredAdjoint {
     }
 
     __device__ __forceinline__ void run(const SweepArgs<Real, D>& a, const Real* __restrict__ tab) {
-        sweep_tile<Real, D, DUMP, true>(a, tab, k, cur, lam, act, m, red);
-        red.flush_tile(k, S, a.part, a.nblk);
+        sweep(a, tab);
 #pragma unroll
         for (int s = 0; s < S; ++s)
 #pragma unroll
             for (int c = 0; c < D; ++c)
                 cur[s][c] = nxt[s][c];
-        k -= S;
     }
 
     __device__ __forceinline__ void tail(const SweepArgs<Real, D>& a, const Real* __restrict__ tab) {
@@ -376,7 +388,8 @@ __global__ void __launch_bounds__(kThreads)
 k_adjoint_stored(SweepArgs<Real, D> a, const Real* __restrict__ tab) {
     __shared__ Real tile[StepReducer<D, Real>::kRows][kThreads];
     StoredAdjoint<Real, D, DUMP> b;
-    b.begin(a, tile, blockIdx.x);
+    b.start(a, tile, blockIdx.x);
+    b.load(a);
     while (b.full()) {
         b.prefetch(a);
         b.run(a, tab);
@@ -405,7 +418,8 @@ k_cost_grad_stored(SweepArgs<Real, D> a, const Real* __restrict__ tab, double* _
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     StoredAdjoint<Real, D, false> b;
-    b.begin(a, tile, blockIdx.x);
+    b.start(a, tile, blockIdx.x);
+    b.load(a);
     while (b.full()) {
         b.prefetch(a);
         b.run(a, tab);
@@ -458,10 +472,9 @@ k_adjoint_recompute(SweepArgs<Real, D> a, const Real* __restrict__ tab) {
             sub[0][i] = X[i];
         for (int s = 1; s < ns; ++s) {
             for (int k = s0 + (s - 1) * R; k < s0 + s * R; ++k) {
-                Real zw[D], zj[D];
-                int n;
-                draws<Real, D>((uint32_t)m, (uint32_t)k, a.iter, a.key0, a.key1, a.thr, zw, zj, n);
-                euler_step<Real, D>(a.c, tab + (size_t)k * 2 * D, X, zw, zj, n);
+                StepDraws<Real, D> z;
+                draws<Real, D>((uint32_t)m, (uint32_t)k, a.iter, a.key0, a.key1, a.thr, z);
+                euler_step<Real, D>(a.c, tab + (size_t)k * 2 * D, X, z);
             }
 #pragma unroll
             for (int t = 1; t < SMAX; ++t)
@@ -489,10 +502,9 @@ k_adjoint_recompute(SweepArgs<Real, D> a, const Real* __restrict__ tab) {
 #pragma unroll
                     for (int i = 0; i < D; ++i)
                         buf[r][i] = buf[r - 1][i];
-                    Real zw[D], zj[D];
-                    int n;
-                    draws<Real, D>((uint32_t)m, (uint32_t)k, a.iter, a.key0, a.key1, a.thr, zw, zj, n);
-                    euler_step<Real, D>(a.c, tab + (size_t)k * 2 * D, buf[r], zw, zj, n);
+                    StepDraws<Real, D> z;
+                    draws<Real, D>((uint32_t)m, (uint32_t)k, a.iter, a.key0, a.key1, a.thr, z);
+                    euler_step<Real, D>(a.c, tab + (size_t)k * 2 * D, buf[r], z);
                 }
             }
 #pragma unroll
@@ -641,20 +653,19 @@ k_draws(SweepArgs<Real, D> a, PoissonTable pt, int64_t m0, int64_t mc, int k0, i
         return;
     const int64_t p = idx / kc;
     const int q = (int)(idx - p * kc);
-    Real w[D], j[D];
-    int n;
-    draws<Real, D>((uint32_t)(m0 + p), (uint32_t)(k0 + q), a.iter, a.key0, a.key1, a.thr, w, j, n);
+    StepDraws<Real, D> z;
+    draws<Real, D>((uint32_t)(m0 + p), (uint32_t)(k0 + q), a.iter, a.key0, a.key1, a.thr, z);
 #pragma unroll
     for (int i = 0; i < D; ++i) {
         if (i < a.d) {
             if (zw)
-                zw[idx * a.d + i] = w[i];
+                zw[idx * a.d + i] = z.zw[i];
             if (zj)
-                zj[idx * a.d + i] = j[i];
+                zj[idx * a.d + i] = jump_normal(z, i);
         }
     }
     if (counts)
-        counts[idx] = n;
+        counts[idx] = z.n;
 }
 
 __global__ void __launch_bounds__(kThreads)
