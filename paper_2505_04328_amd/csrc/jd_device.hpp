@@ -128,8 +128,9 @@ __device__ __forceinline__ int poisson_count(uint32_t P, const PoissonTable* __r
 // the padded dimension (1, 2, 4 or 8); padded components have zero rows and
 // columns, zero noise and zero jumps, so they stay exactly zero.
 template <typename Real, int D>
-struct Coef {
+struct alignas(16) Coef {
     Real A[D * D];   // row-major
+    Real AT[D * D];  // A^T, row-major (the adjoint step reads rows of A^T)
     Real sq[D];      // sqrt(dt) * s
     Real jm[D];      // jump mean
     Real js[D];      // jump std
@@ -138,6 +139,63 @@ struct Coef {
     Real dt;
     Real c3;
 };
+
+// Coefficient placement.  Small problems keep every coefficient in scalar
+// registers (the kernel argument).  In the forward step of FP32 d = 8 and of
+// FP64 d >= 2 the drift matrix, the jump law and the endpoints do not fit the
+// scalar register file next to the Philox key schedule and the per-step table
+// rows, and the compiler spills them to vector-register lanes (a v_readlane
+// per use); there each block stages the coefficients in LDS once and every
+// step reads the matrix and the jump law from there.  The adjoint step needs
+// no key schedule: it reads A^T from LDS only in FP64 (d >= 2), where the
+// matrix alone takes 2 d^2 scalar registers.  The scalars of a step
+// (sqrt(dt) s, dt, the cubic coefficient) stay in scalar registers.
+template <typename Real, int D>
+struct CoefInLds {
+    static constexpr bool forward = sizeof(Real) == 8 ? D >= 2 : D >= 8;
+    static constexpr bool adjoint = sizeof(Real) == 8 && D >= 2;
+    static constexpr bool any = forward || adjoint;
+};
+
+// A zero the compiler cannot see through: offsetting the LDS coefficients by
+// it in each step keeps their loads inside the step loop instead of hoisting
+// the whole matrix into registers for the duration of the sweep.
+__device__ __forceinline__ int opaque_zero() {
+    int z = 0;
+    asm volatile("" : "+v"(z));
+    return z;
+}
+
+// Where the matrix comes from LDS, a scheduling barrier after each row of a
+// matrix-vector product keeps at most one row of coefficients in registers
+// (the scheduler would otherwise issue every row's loads at once).
+template <bool LDS>
+__device__ __forceinline__ void row_barrier() {
+    if constexpr (LDS)
+        __builtin_amdgcn_sched_barrier(0);
+}
+
+// The coefficient rows a step reads: the LDS copy (reloaded every step) or
+// the kernel argument.
+template <bool LDS, typename Real, int D>
+__device__ __forceinline__ const Coef<Real, D>& coef_rows(const Coef<Real, D>& arg,
+                                                          const Coef<Real, D>* lds) {
+    if constexpr (LDS)
+        return *(lds + opaque_zero());
+    else
+        return arg;
+}
+
+// The coefficients used once per path (x0, xT): the LDS copy where the
+// kernel staged one (lds != nullptr), without the opaque offset.
+template <typename Real, int D>
+__device__ __forceinline__ const Coef<Real, D>& coef_once(const Coef<Real, D>& arg,
+                                                          const Coef<Real, D>* lds) {
+    if constexpr (CoefInLds<Real, D>::any)
+        return lds != nullptr ? *lds : arg;
+    else
+        return arg;
+}
 
 // Draws of one path-step.  Component i's Gaussian pair comes from one
 // Box-Muller transform of words (2i, 2i+1): Z^W_i is its cosine branch, always
@@ -192,15 +250,19 @@ __device__ __forceinline__ double count_sqrt<double>(int n) {
 // in waves where some lane jumps (lambda dt per path-step, so most waves skip
 // it) and applied only in the lanes with n > 0.
 template <typename Real, int D>
-__device__ __forceinline__ void euler_step(const Coef<Real, D>& c, const Real* __restrict__ bu,
-                                           Real* X, const StepDraws<Real, D>& s) {
+__device__ __forceinline__ void euler_step(const Coef<Real, D>& c, const Coef<Real, D>* lc,
+                                           const Real* __restrict__ bu, Real* X,
+                                           const StepDraws<Real, D>& s) {
+    constexpr bool LDS = CoefInLds<Real, D>::forward;
+    const Coef<Real, D>& rows = coef_rows<LDS>(c, lc);
     Real Y[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) {
         Real f = bu[i];
 #pragma unroll
         for (int j = 0; j < D; ++j)
-            f = fma(c.A[i * D + j], X[j], f);
+            f = fma(rows.A[i * D + j], X[j], f);
+        row_barrier<LDS>();
         const Real x3 = X[i] * X[i] * X[i];
         f = fma(-c.c3, x3, f);
         Real y = fma(c.dt, f, X[i]);
@@ -211,7 +273,7 @@ __device__ __forceinline__ void euler_step(const Coef<Real, D>& c, const Real* _
         const Real sn = count_sqrt<Real>(s.n);
 #pragma unroll
         for (int i = 0; i < D; ++i) {
-            const Real yj = Y[i] + fma(c.js[i] * sn, jump_normal(s, i), fn * c.jm[i]);
+            const Real yj = Y[i] + fma(rows.js[i] * sn, jump_normal(s, i), fn * rows.jm[i]);
             Y[i] = s.n != 0 ? yj : Y[i];
         }
     }
@@ -223,15 +285,18 @@ __device__ __forceinline__ void euler_step(const Coef<Real, D>& c, const Real* _
 // One backward adjoint step at state X_k:
 //   lam <- lam + dt [ (A - 3 c3 diag(X_k^2))^T lam + (X_k - xd_k) ]
 template <typename Real, int D>
-__device__ __forceinline__ void adjoint_step(const Coef<Real, D>& c, const Real* __restrict__ xd,
-                                             const Real* X, Real* lam) {
+__device__ __forceinline__ void adjoint_step(const Coef<Real, D>& c, const Coef<Real, D>* lc,
+                                             const Real* __restrict__ xd, const Real* X, Real* lam) {
+    constexpr bool LDS = CoefInLds<Real, D>::adjoint;
+    const Coef<Real, D>& rows = coef_rows<LDS>(c, lc);
     Real Y[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) {
         Real a = X[i] - xd[i];
 #pragma unroll
         for (int j = 0; j < D; ++j)
-            a = fma(c.A[j * D + i], lam[j], a);
+            a = fma(rows.AT[i * D + j], lam[j], a);
+        row_barrier<LDS>();
         const Real q = (Real)3 * c.c3 * X[i] * X[i];
         a = fma(-q, lam[i], a);
         Y[i] = fma(c.dt, a, lam[i]);
@@ -300,15 +365,6 @@ struct StepReducer {
         filled = 0;
         k_first = 0;
         col = group;
-    }
-
-    template <typename Real>
-    __device__ __forceinline__ void push(int k, const Real* v, double* __restrict__ part, int nblk) {
-        if (filled == 0)
-            k_first = k;
-        put(filled, v);
-        if (++filled == kSteps)
-            flush(part, nblk);
     }
 
     // Deposit the values of the s-th step of the current tile (no flush).

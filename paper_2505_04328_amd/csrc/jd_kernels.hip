@@ -24,6 +24,7 @@ namespace jd {
 template <typename Real, int D>
 struct SweepArgs {
     Coef<Real, D> c;
+    const Coef<Real, D>* lc;  // the block's LDS copy of c (set in the kernel), see CoefInLds
     const PoissonTable* thr;  // staged in the workspace header
     void* traj;       // trajectory or checkpoints
     double* part;     // per-block partial sums
@@ -99,6 +100,19 @@ __device__ __forceinline__ void dump_state(const SweepArgs<Real, D>& a, Real* ds
     }
 }
 
+// Stages the coefficients in LDS when the kernel's steps read them from there
+// (USE; one lane copies the argument struct) and points a.lc at the copy;
+// otherwise does nothing and a.lc stays null.
+template <bool USE, typename Real, int D>
+__device__ __forceinline__ void stage_coef(SweepArgs<Real, D>& a, Coef<Real, D>* sc) {
+    if constexpr (USE) {
+        if (threadIdx.x == 0)
+            *sc = a.c;
+        __syncthreads();
+        a.lc = sc;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // B u_k and x_d rows.  B is passed by value (d*d <= 64 doubles).
 struct BMat {
@@ -148,7 +162,7 @@ struct ForwardSweep {
         act = m < a.M;
 #pragma unroll
         for (int i = 0; i < D; ++i)
-            X[i] = a.c.x0[i];
+            X[i] = coef_once<Real, D>(a.c, a.lc).x0[i];
         acc = 0.0;
         row = (Real*)slot_row<Real>(a.traj, make_cols(a.d), a.nslots, g, 0);
     }
@@ -159,7 +173,7 @@ struct ForwardSweep {
         acc += (double)sq_dist<Real, D>(X, trow + D);
         StepDraws<Real, D> z;
         draws<Real, D>((uint32_t)m, (uint32_t)k, a.iter, a.key0, a.key1, a.thr, z);
-        euler_step<Real, D>(a.c, trow, X, z);
+        euler_step<Real, D>(a.c, a.lc, trow, X, z);
         if (MODE == FWD_STORE) {
             store_row<Real, D>(row, a.d, X);
             row += (int64_t)a.d * kThreads;
@@ -175,7 +189,7 @@ struct ForwardSweep {
     // fixed-order sum into cpart[g].  All threads of the block call it.
     __device__ __forceinline__ void finish(const SweepArgs<Real, D>& a, double* __restrict__ cpart,
                                            double* sh, int64_t g) {
-        double C = 0.5 * a.dt64 * acc + 0.5 * (double)sq_dist<Real, D>(X, a.c.xT);
+        double C = 0.5 * a.dt64 * acc + 0.5 * (double)sq_dist<Real, D>(X, coef_once<Real, D>(a.c, a.lc).xT);
         if (!act)
             C = 0.0;
         if (a.dcost != nullptr) {
@@ -193,6 +207,8 @@ template <typename Real, int D, int MODE>
 __global__ void __launch_bounds__(kThreads)
 k_forward(SweepArgs<Real, D> a, const Real* __restrict__ tab, double* __restrict__ cpart) {
     __shared__ double sh[kThreads];
+    __shared__ Coef<Real, D> sc;
+    stage_coef<CoefInLds<Real, D>::forward>(a, &sc);
     ForwardSweep<Real, D, MODE> f;
     f.begin(a, blockIdx.x);
     for (int k = 0; k < a.N; ++k)
@@ -201,15 +217,6 @@ k_forward(SweepArgs<Real, D> a, const Real* __restrict__ tab, double* __restrict
 }
 
 // ---------------------------------------------------------------------------
-template <typename Real, int D>
-__device__ __forceinline__ void push_masked(StepReducer<D, Real>& red, int k, const Real* lam, bool act,
-                                            double* part, int nblk) {
-    Real v[D];
-#pragma unroll
-    for (int c = 0; c < D; ++c)
-        v[c] = act ? lam[c] : (Real)0;
-    red.push(k, v, part, nblk);
-}
 
 // The stored trajectory is read in tiles of kSteps steps (the reducer's flush
 // granularity): the loads of the next tile are issued before the current tile
@@ -288,7 +295,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<Real, D>& a, const Re
         red.put(s, v);
         if (FULL || kk >= 1) {
             const Real* xd = FULL ? trow + (S - 1 - s) * 2 * D + D : tab + (size_t)kk * 2 * D + D;
-            adjoint_step<Real, D>(a.c, xd, X[s], lam);
+            adjoint_step<Real, D>(a.c, a.lc, xd, X[s], lam);
             if (DUMP) {
                 dump_state(a, a.dX, kk, m, X[s]);
                 dump_state(a, a.dlam, kk, m, lam);
@@ -331,7 +338,7 @@ struct StoredAdjoint {
         load_row<Real, D>(region + (int64_t)(a.N - 1) * cl.stride, a.d, XN);
 #pragma unroll
         for (int i = 0; i < D; ++i)
-            lam[i] = XN[i] - a.c.xT[i];
+            lam[i] = XN[i] - coef_once<Real, D>(a.c, a.lc).xT[i];
         if (DUMP) {
             dump_state(a, a.dX, a.N, m, XN);
             dump_state(a, a.dlam, a.N, m, lam);
@@ -387,6 +394,8 @@ template <typename Real, int D, bool DUMP>
 __global__ void __launch_bounds__(kThreads)
 k_adjoint_stored(SweepArgs<Real, D> a, const Real* __restrict__ tab) {
     __shared__ Real tile[StepReducer<D, Real>::kRows][kThreads];
+    __shared__ Coef<Real, D> sc;
+    stage_coef<CoefInLds<Real, D>::adjoint>(a, &sc);
     StoredAdjoint<Real, D, DUMP> b;
     b.start(a, tile, blockIdx.x);
     b.load(a);
@@ -409,6 +418,8 @@ __global__ void __launch_bounds__(kThreads)
 k_cost_grad_stored(SweepArgs<Real, D> a, const Real* __restrict__ tab, double* __restrict__ cpart) {
     __shared__ double sh[kThreads];
     __shared__ Real tile[StepReducer<D, Real>::kRows][kThreads];
+    __shared__ Coef<Real, D> sc;
+    stage_coef<CoefInLds<Real, D>::any>(a, &sc);
     {
         ForwardSweep<Real, D, FWD_STORE> f;
         f.begin(a, blockIdx.x);
@@ -436,7 +447,11 @@ k_cost_grad_stored(SweepArgs<Real, D> a, const Real* __restrict__ tab, double* _
 template <typename Real, int D, int R, int SMAX>
 __global__ void __launch_bounds__(kThreads)
 k_adjoint_recompute(SweepArgs<Real, D> a, const Real* __restrict__ tab) {
+    constexpr int S = StepReducer<D, Real>::kSteps;
+    static_assert(R % S == 0, "register buffer length must be a multiple of the reducer tile");
     __shared__ Real tile[StepReducer<D, Real>::kRows][kThreads];
+    __shared__ Coef<Real, D> sc;
+    stage_coef<CoefInLds<Real, D>::any>(a, &sc);
     StepReducer<D, Real> red;
     red.init(tile, blockIdx.x);
     const int64_t m = (int64_t)blockIdx.x * kThreads + threadIdx.x;
@@ -450,7 +465,7 @@ k_adjoint_recompute(SweepArgs<Real, D> a, const Real* __restrict__ tab) {
         load_row<Real, D>(slot_row<Real>(a.traj, cl, a.nslots, blockIdx.x, nseg - 1), a.d, XN);
 #pragma unroll
         for (int i = 0; i < D; ++i)
-            lam[i] = XN[i] - a.c.xT[i];
+            lam[i] = XN[i] - coef_once<Real, D>(a.c, a.lc).xT[i];
         dump_state(a, a.dX, N, m, XN);
         dump_state(a, a.dlam, N, m, lam);
     }
@@ -463,7 +478,7 @@ k_adjoint_recompute(SweepArgs<Real, D> a, const Real* __restrict__ tab) {
         if (j == 0) {
 #pragma unroll
             for (int i = 0; i < D; ++i)
-                X[i] = a.c.x0[i];
+                X[i] = coef_once<Real, D>(a.c, a.lc).x0[i];
         } else {
             load_row<Real, D>(slot_row<Real>(a.traj, cl, a.nslots, blockIdx.x, j - 1), a.d, X);
         }
@@ -474,7 +489,7 @@ k_adjoint_recompute(SweepArgs<Real, D> a, const Real* __restrict__ tab) {
             for (int k = s0 + (s - 1) * R; k < s0 + s * R; ++k) {
                 StepDraws<Real, D> z;
                 draws<Real, D>((uint32_t)m, (uint32_t)k, a.iter, a.key0, a.key1, a.thr, z);
-                euler_step<Real, D>(a.c, tab + (size_t)k * 2 * D, X, z);
+                euler_step<Real, D>(a.c, a.lc, tab + (size_t)k * 2 * D, X, z);
             }
 #pragma unroll
             for (int t = 1; t < SMAX; ++t)
@@ -504,24 +519,39 @@ k_adjoint_recompute(SweepArgs<Real, D> a, const Real* __restrict__ tab) {
                         buf[r][i] = buf[r - 1][i];
                     StepDraws<Real, D> z;
                     draws<Real, D>((uint32_t)m, (uint32_t)k, a.iter, a.key0, a.key1, a.thr, z);
-                    euler_step<Real, D>(a.c, tab + (size_t)k * 2 * D, buf[r], z);
+                    euler_step<Real, D>(a.c, a.lc, tab + (size_t)k * 2 * D, buf[r], z);
                 }
             }
+            // Backward over the sub-segment in chunks of one reducer tile
+            // (R is a multiple of the tile height), with one flush per chunk.
+            // A step's partial sum does not depend on the tile it is flushed
+            // in, so the chunking only fixes where the flush code sits.
 #pragma unroll
-            for (int r = R - 1; r >= 0; --r) {
-                if (a0 + r < a1) {
+            for (int c0 = R - S; c0 >= 0; c0 -= S) {
+                const int top = min(a0 + c0 + S, a1) - 1;  // highest step of the chunk
+                if (top < a0 + c0)
+                    continue;
+#pragma unroll
+                for (int i = S - 1; i >= 0; --i) {
+                    const int r = c0 + i;
                     const int k = a0 + r;
-                    push_masked<Real, D>(red, k, lam, act, a.part, nblk);
-                    if (k >= 1) {
-                        adjoint_step<Real, D>(a.c, tab + (size_t)k * 2 * D + D, buf[r], lam);
-                        dump_state(a, a.dX, k, m, buf[r]);
-                        dump_state(a, a.dlam, k, m, lam);
+                    if (k <= top) {
+                        Real v[D];
+#pragma unroll
+                        for (int c = 0; c < D; ++c)
+                            v[c] = act ? lam[c] : (Real)0;
+                        red.put(top - k, v);
+                        if (k >= 1) {
+                            adjoint_step<Real, D>(a.c, a.lc, tab + (size_t)k * 2 * D + D, buf[r], lam);
+                            dump_state(a, a.dX, k, m, buf[r]);
+                            dump_state(a, a.dlam, k, m, lam);
+                        }
                     }
                 }
+                red.flush_tile(top, top - (a0 + c0) + 1, a.part, nblk);
             }
         }
     }
-    red.flush(a.part, nblk);
 }
 
 // ---------------------------------------------------------------------------
@@ -716,8 +746,11 @@ bool recompute_supported(int prec, int D, int K) {
 template <typename Real, int D>
 static SweepArgs<Real, D> make_args(const HostProblem& p, const HostRun& r) {
     SweepArgs<Real, D> a;
-    for (int i = 0; i < D * D; ++i)
-        a.c.A[i] = (Real)p.A[i];
+    for (int i = 0; i < D; ++i)
+        for (int j = 0; j < D; ++j) {
+            a.c.A[i * D + j] = (Real)p.A[i * D + j];
+            a.c.AT[j * D + i] = (Real)p.A[i * D + j];
+        }
     const double sq = sqrt(p.dt);
     for (int i = 0; i < D; ++i) {
         a.c.sq[i] = (Real)(sq * p.s[i]);
@@ -729,6 +762,7 @@ static SweepArgs<Real, D> make_args(const HostProblem& p, const HostRun& r) {
     a.c.dt = (Real)p.dt;
     a.c.c3 = (Real)p.cubic;
     a.thr = nullptr;
+    a.lc = nullptr;
     a.traj = nullptr;
     a.part = nullptr;
     a.M = r.M;
