@@ -10,15 +10,17 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "jd_oracle.c")
+SRC = [os.path.join(HERE, "jd_oracle.c"), os.path.join(HERE, "fb_oracle.c")]
 LIB = os.path.join(HERE, "liboracle.so")
 
 CFLAGS = ["-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
           "-fopenmp", "-Wall", "-Wextra", "-Wno-unused-parameter"]
 
 
-def build(src: str = SRC, out: str = LIB, extra: list | None = None, quiet: bool = True) -> str:
-    cmd = ["gcc", *CFLAGS, *(extra or []), "-o", out + ".tmp", src, "-lm"]
+def build(src=SRC, out: str = LIB, extra: list | None = None, quiet: bool = True) -> str:
+    """Compile `src` (one path or a list of C files) into the shared library `out`."""
+    srcs = [src] if isinstance(src, str) else list(src)
+    cmd = ["gcc", *CFLAGS, *(extra or []), "-o", out + ".tmp", *srcs, "-lm"]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError("oracle build failed:\n" + " ".join(cmd) + "\n" + res.stderr)

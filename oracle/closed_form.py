@@ -16,8 +16,13 @@ With Phi = I + dt A, mu = lam*dt:
               + nu dt/2 sum_k |u_k|^2
     lbar_N  = m_N - xT,  lbar_k = Phi^T lbar_{k+1} + dt (m_k - xd_k)
     E-grad  = nu u_k + B^T lbar_{k+1}
+
+The end of the file holds the same kind of moment recursion for the paper's
+own model problem (oscillator, Keilson-Storer jumps) without control.
 """
 from __future__ import annotations
+
+import math
 
 import numpy as np
 
@@ -133,3 +138,38 @@ def deterministic_path(p, u=None) -> np.ndarray:
             x = x + np.linalg.matrix_power(Phi, k - 1 - j) @ (dt * (p.B @ u[j]))
         X[k] = x
     return X
+
+
+# ---------------------------------------------------------------------------
+# The paper's model problem (fb_oracle.c) without control (mu = 0): the Euler
+# step is linear in z, the jump count n ~ Poisson(lam = sqrt(beta/pi) dt) is
+# independent of the state and of the Brownian normals, so the means and raw
+# second moments follow exact recursions.  With n Keilson-Storer jumps the
+# velocity becomes gamma^n v + N(0, V_n), V_n = (1 - gamma^{2n}) / ((1 - gamma^2) 2 beta),
+# and for a Poisson count E[gamma^n] = exp(-lam (1 - gamma)),
+# E[gamma^{2n}] = exp(-lam (1 - gamma^2)).
+
+def fb_moments(p):
+    """Arrays (N+1) of E[x], E[v], E[x^2], E[x v], E[v^2] for mu = 0."""
+    dt, eta, lam = p.dt, p.eta, p.rate * p.dt
+    g1 = math.exp(-lam * (1.0 - p.gamma))
+    g2 = math.exp(-lam * (1.0 - p.gamma * p.gamma))
+    if abs(1.0 - p.gamma * p.gamma) > 1e-15:
+        EV = (1.0 - g2) / ((1.0 - p.gamma * p.gamma) * 2.0 * p.beta)
+    else:
+        EV = lam / (2.0 * p.beta)
+    if p.init_kind == 0:
+        var = p.s0 ** 2
+    else:
+        var = p.s0 ** 2 / 3.0
+    mx, mv = p.z0[0], p.z0[1]
+    sxx, sxv, svv = mx * mx + var[0], mx * mv, mv * mv + var[1]
+    out = np.zeros((p.N + 1, 5))
+    out[0] = (mx, mv, sxx, sxv, svv)
+    for k in range(p.N):
+        mx, mv = mx + dt * mv, g1 * (mv - dt * eta * mx)
+        sxx, sxv, svv = (sxx + 2 * dt * sxv + dt * dt * svv + p.b1 ** 2 * dt,
+                         g1 * (sxv - dt * eta * sxx + dt * svv - dt * dt * eta * sxv),
+                         g2 * (svv - 2 * dt * eta * sxv + dt * dt * eta * eta * sxx + p.b2 ** 2 * dt) + EV)
+        out[k + 1] = (mx, mv, sxx, sxv, svv)
+    return out

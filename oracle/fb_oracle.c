@@ -1,0 +1,526 @@
+/*
+ * FP64 CPU oracle for the paper's model problem (arXiv 2505.04328): the
+ * controlled oscillator with Keilson-Storer velocity jumps and radial-basis
+ * feedback control.  The definitions are in fb_oracle.h.
+ *
+ * TEST INFRASTRUCTURE ONLY: loaded by the test suite and the benchmark's CPU
+ * baseline, never by the product path.  Plain, one path at a time, FP64,
+ * -ffp-contract=off.  It shares no code with the GPU library; it reuses this
+ * directory's Philox, uniform map and Poisson thresholds (jd_oracle.c).
+ *
+ * Sources in the paper:
+ *   control     eq. control_structure, shape functions as products of a
+ *               position and a velocity bump (Section 5, shape functions,
+ *               eq. Gaussian_RBF) on the cell centres of Section 5,
+ *               discretization;
+ *   dynamics    eq. coefficients and eq. SDE_splitted_drift_Euler (h = 0);
+ *   jumps       eq. jump_law (v <- gamma v + N(0, 1/(2 beta))) at the rate
+ *               of eq. collision_frequency;
+ *   cost        eq. discrete_functional with the tracking cost of
+ *               eq. tracking_cost;
+ *   adjoint     eq. adjoint_eq_approximation with lam = -r and the jump
+ *               condition p <- gamma p (Section 4, adjoint model);
+ *   gradient    eq. definition_Gradient (Psi^T r = phi p);
+ *   iteration   Algorithm 5.4 with eq. Stochastic_Armijo.
+ */
+#include "fb_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "jd_oracle.h"
+
+#define FB_CHUNK 4096
+#define FB_INIT_STEP 0xFFFFFFFFu
+
+static const double FB_TWO_PI = 6.283185307179586476925286766559;
+static const double FB_PI = 3.141592653589793238462643383280;
+
+double fb_bump(double r, double eps)
+{
+    double q = eps * r;
+    if (fabs(q) >= 1.0)
+        return 0.0;
+    return exp(-1.0 / (1.0 - q * q));
+}
+
+/* d/dr exp(-1/(1 - eps^2 r^2)) = b(r) * (-2 eps^2 r) / (1 - eps^2 r^2)^2. */
+double fb_bump_deriv(double r, double eps)
+{
+    double q = eps * r;
+    if (fabs(q) >= 1.0)
+        return 0.0;
+    double s = 1.0 - q * q;
+    return exp(-1.0 / s) * (-2.0 * eps * eps * r) / (s * s);
+}
+
+static void key_of(uint64_t seed, uint32_t key[2])
+{
+    key[0] = (uint32_t)(seed & 0xFFFFFFFFu);
+    key[1] = (uint32_t)(seed >> 32);
+}
+
+/* Initial state from Philox block (m, 0xFFFFFFFF, iter, 0): a Box-Muller pair
+ * of words 0 and 1 (cosine -> x, sine -> v) for the Gaussian law, or the two
+ * uniforms for the box. */
+void fb_initial(const fb_problem* pb, uint64_t seed, uint32_t m, uint32_t iter, double z[2])
+{
+    uint32_t key[2], W[4];
+    uint32_t ctr[4] = {m, FB_INIT_STEP, iter, 0u};
+    key_of(seed, key);
+    or_philox4x32_10(ctr, key, W);
+    double ua = or_uniform(W[0]), ub = or_uniform(W[1]);
+    if (pb->init_kind == 0) {
+        double R = sqrt(-2.0 * log(ua));
+        z[0] = pb->z0[0] + pb->s0[0] * R * cos(FB_TWO_PI * ub);
+        z[1] = pb->z0[1] + pb->s0[1] * R * sin(FB_TWO_PI * ub);
+    } else {
+        z[0] = pb->z0[0] + pb->s0[0] * (2.0 * ua - 1.0);
+        z[1] = pb->z0[1] + pb->s0[1] * (2.0 * ub - 1.0);
+    }
+}
+
+/* Step draws from Philox block (m, k, iter, 0): Box-Muller of words 0 and 1
+ * gives the two Brownian normals (cosine -> x, sine -> v), the cosine branch
+ * of words 2 and 3 the jump normal, the low bytes of the four words the
+ * Poisson word. */
+void fb_step_draws(uint64_t seed, uint32_t m, uint32_t k, uint32_t iter, const uint64_t thr[32],
+                   double Z[3], int* n)
+{
+    uint32_t key[2], W[4];
+    uint32_t ctr[4] = {m, k, iter, 0u};
+    key_of(seed, key);
+    or_philox4x32_10(ctr, key, W);
+    double R = sqrt(-2.0 * log(or_uniform(W[0])));
+    double th = FB_TWO_PI * or_uniform(W[1]);
+    Z[0] = R * cos(th);
+    Z[1] = R * sin(th);
+    double R2 = sqrt(-2.0 * log(or_uniform(W[2])));
+    Z[2] = R2 * cos(FB_TWO_PI * or_uniform(W[3]));
+    uint32_t P = (W[0] & 0xFFu) | ((W[1] & 0xFFu) << 8) | ((W[2] & 0xFFu) << 16) |
+                 ((W[3] & 0xFFu) << 24);
+    *n = or_poisson_count(P, thr);
+}
+
+static int check_problem(const fb_problem* pb)
+{
+    if (!pb || pb->N < 1 || pb->nx < 1 || pb->nv < 1 || pb->nx > 16 || pb->nv > 16)
+        return -1;
+    if (!(pb->T > 0.0) || !(pb->beta > 0.0) || !(pb->eps > 0.0) || !(pb->sigJ > 0.0) || !pb->zd)
+        return -1;
+    if (!(pb->xmax > 0.0) || !(pb->vmax > 0.0) || pb->gamma < -1.0 || pb->gamma > 1.0)
+        return -1;
+    if (sqrt(pb->beta / FB_PI) * (pb->T / (double)pb->N) > 2.0)
+        return -1;
+    return 0;
+}
+
+static double rate_dt(const fb_problem* pb)
+{
+    return sqrt(pb->beta / FB_PI) * (pb->T / (double)pb->N);
+}
+
+/* Shape-function values at z: px[i] = b(x - xc_i), pv[l] = b(v - vc_l) and,
+ * if dpx/dpv are given, their derivatives. */
+static void shapes(const fb_problem* pb, const double z[2], double* px, double* pv, double* dpx,
+                   double* dpv)
+{
+    double dx = 2.0 * pb->xmax / (double)pb->nx, dv = 2.0 * pb->vmax / (double)pb->nv;
+    for (int i = 0; i < pb->nx; ++i) {
+        double r = z[0] - ((i + 0.5) * dx - pb->xmax);
+        px[i] = fb_bump(r, pb->eps);
+        if (dpx)
+            dpx[i] = fb_bump_deriv(r, pb->eps);
+    }
+    for (int l = 0; l < pb->nv; ++l) {
+        double r = z[1] - ((l + 0.5) * dv - pb->vmax);
+        pv[l] = fb_bump(r, pb->eps);
+        if (dpv)
+            dpv[l] = fb_bump_deriv(r, pb->eps);
+    }
+}
+
+/* u = sum_{i,l} mu[i nv + l] px[i] pv[l]. */
+static double control(const fb_problem* pb, const double* mu, const double* px, const double* pv)
+{
+    double u = 0.0;
+    for (int i = 0; i < pb->nx; ++i)
+        for (int l = 0; l < pb->nv; ++l)
+            u += mu[i * pb->nv + l] * px[i] * pv[l];
+    return u;
+}
+
+static double track(const fb_problem* pb, const double z[2], const double* zd)
+{
+    double rx = z[0] - zd[0], rv = z[1] - zd[1];
+    return -exp(-(rx * rx + rv * rv) / (2.0 * pb->sigJ * pb->sigJ));
+}
+
+/* Gradient of the tracking cost: (z - zd)/sigJ^2 * exp(-|z - zd|^2/(2 sigJ^2)). */
+static void track_grad(const fb_problem* pb, const double z[2], const double* zd, double gz[2])
+{
+    double rx = z[0] - zd[0], rv = z[1] - zd[1];
+    double s2 = pb->sigJ * pb->sigJ;
+    double e = exp(-(rx * rx + rv * rv) / (2.0 * s2));
+    gz[0] = rx / s2 * e;
+    gz[1] = rv / s2 * e;
+}
+
+/* gamma^n and V_n = (1/(2 beta)) sum_{i<n} gamma^{2i}: n Keilson-Storer jumps
+ * v <- gamma v + s_i composed (a Gaussian with that variance). */
+static void ks_factors(const fb_problem* pb, int n, double* gn, double* Vn)
+{
+    double g = 1.0, s = 0.0;
+    for (int i = 0; i < n; ++i) {
+        s += g * g;
+        g *= pb->gamma;
+    }
+    *gn = g;
+    *Vn = s / (2.0 * pb->beta);
+}
+
+typedef struct {
+    double *z, *u, *px, *pv, *dpx, *dpv, *lam;
+    int *n;
+} work;
+
+static int work_alloc(const fb_problem* pb, work* w)
+{
+    size_t N = (size_t)pb->N;
+    w->z = (double*)malloc((N + 1) * 2 * sizeof(double));
+    w->lam = (double*)malloc((N + 1) * 2 * sizeof(double));
+    w->u = (double*)malloc(N * sizeof(double));
+    w->n = (int*)malloc(N * sizeof(int));
+    w->px = (double*)malloc(16 * sizeof(double));
+    w->pv = (double*)malloc(16 * sizeof(double));
+    w->dpx = (double*)malloc(16 * sizeof(double));
+    w->dpv = (double*)malloc(16 * sizeof(double));
+    return (w->z && w->lam && w->u && w->n && w->px && w->pv && w->dpx && w->dpv) ? 0 : -2;
+}
+
+static void work_free(work* w)
+{
+    free(w->z);
+    free(w->lam);
+    free(w->u);
+    free(w->n);
+    free(w->px);
+    free(w->pv);
+    free(w->dpx);
+    free(w->dpv);
+}
+
+/* Forward sweep of path m (eq. SDE_splitted_drift_Euler on the fixed grid,
+ * the step's n jumps applied after its Euler update): fills w->z, w->u, w->n
+ * and returns the path cost. */
+static double path_forward(const fb_problem* pb, const uint64_t thr[32], uint64_t seed,
+                           uint32_t iter, uint32_t m, const double* mu, work* w)
+{
+    const int N = pb->N, L = pb->nx * pb->nv;
+    const double dt = pb->T / (double)N, sq = sqrt(dt);
+    fb_initial(pb, seed, m, iter, w->z);
+    double C = 0.0;
+    for (int k = 0; k < N; ++k) {
+        const double* zk = w->z + 2 * k;
+        double* zn = w->z + 2 * (k + 1);
+        shapes(pb, zk, w->px, w->pv, NULL, NULL);
+        double u = control(pb, mu + (size_t)k * L, w->px, w->pv);
+        w->u[k] = u;
+        C += dt * 0.5 * pb->alpha * u * u;
+        double Z[3];
+        int n;
+        fb_step_draws(seed, m, (uint32_t)k, iter, thr, Z, &n);
+        w->n[k] = n;
+        double gn, Vn;
+        ks_factors(pb, n, &gn, &Vn);
+        zn[0] = zk[0] + dt * zk[1] + pb->b1 * sq * Z[0];
+        double vs = zk[1] + dt * (u - pb->eta * zk[0]) + pb->b2 * sq * Z[1];
+        zn[1] = gn * vs + sqrt(Vn) * Z[2];
+        C += dt * track(pb, zn, pb->zd + 2 * (k + 1));
+    }
+    return C;
+}
+
+/* Backward adjoint of the path held in w (eq. adjoint_eq_approximation, lam =
+ * dC/dz = -r): fills w->lam[k] for k = N..1 and, if G is given, adds the
+ * path's gradient summand phi(z_k) (alpha u_k + gamma^{n_k} lam^v_{k+1}) to
+ * G[k*L + l]. */
+static void path_adjoint(const fb_problem* pb, const double* mu, work* w, double* G)
+{
+    const int N = pb->N, L = pb->nx * pb->nv;
+    const double dt = pb->T / (double)N;
+    double gz[2];
+    track_grad(pb, w->z + 2 * N, pb->zd + 2 * N, gz);
+    w->lam[2 * N] = dt * gz[0];
+    w->lam[2 * N + 1] = dt * gz[1];
+    for (int k = N - 1; k >= 0; --k) {
+        const double* zk = w->z + 2 * k;
+        const double lx = w->lam[2 * (k + 1)], lv = w->lam[2 * (k + 1) + 1];
+        const double* mk = mu + (size_t)k * L;
+        shapes(pb, zk, w->px, w->pv, w->dpx, w->dpv);
+        double u = w->u[k];
+        double gn, Vn;
+        ks_factors(pb, w->n[k], &gn, &Vn);
+        if (G) {
+            double wk = pb->alpha * u + gn * lv;
+            for (int i = 0; i < pb->nx; ++i)
+                for (int l = 0; l < pb->nv; ++l)
+                    G[(size_t)k * L + i * pb->nv + l] += w->px[i] * w->pv[l] * wk;
+        }
+        if (k == 0)
+            break;
+        double ux = control(pb, mk, w->dpx, w->pv);
+        double uv = control(pb, mk, w->px, w->dpv);
+        track_grad(pb, zk, pb->zd + 2 * k, gz);
+        w->lam[2 * k] = lx + gn * dt * (ux - pb->eta) * lv + dt * gz[0] + dt * pb->alpha * u * ux;
+        w->lam[2 * k + 1] = dt * lx + gn * (1.0 + dt * uv) * lv + dt * gz[1] + dt * pb->alpha * u * uv;
+    }
+    w->lam[0] = 0.0;
+    w->lam[1] = 0.0;
+}
+
+int fb_paths(const fb_problem* pb, uint64_t seed, uint32_t iter, int64_t m0, int64_t count,
+             const double* mu, double* z, double* lam, double* u, int32_t* jumps, double* C,
+             int nthreads)
+{
+    if (check_problem(pb) || !mu || m0 < 0 || count < 0)
+        return -1;
+    const int N = pb->N;
+    uint64_t thr[32];
+    or_poisson_thresholds(rate_dt(pb), thr);
+    int rc = 0;
+#pragma omp parallel num_threads(nthreads > 0 ? nthreads : 1) reduction(| : rc)
+    {
+        work w;
+        const int ok = work_alloc(pb, &w) == 0;
+        rc |= ok ? 0 : 1;
+        {
+#pragma omp for schedule(dynamic, 16)
+            for (int64_t p = 0; p < count; ++p) {
+                if (!ok)
+                    continue;
+                double c = path_forward(pb, thr, seed, iter, (uint32_t)(m0 + p), mu, &w);
+                if (C)
+                    C[p] = c;
+                if (z)
+                    memcpy(z + (size_t)p * (N + 1) * 2, w.z, (size_t)(N + 1) * 2 * sizeof(double));
+                if (u)
+                    memcpy(u + (size_t)p * N, w.u, (size_t)N * sizeof(double));
+                if (jumps)
+                    for (int k = 0; k < N; ++k)
+                        jumps[(size_t)p * N + k] = w.n[k];
+                if (lam) {
+                    path_adjoint(pb, mu, &w, NULL);
+                    memcpy(lam + (size_t)p * (N + 1) * 2, w.lam, (size_t)(N + 1) * 2 * sizeof(double));
+                }
+            }
+        }
+        work_free(&w);
+    }
+    return rc ? -2 : 0;
+}
+
+/* Monte Carlo reductions in chunks of FB_CHUNK consecutive paths, each chunk
+ * in path order and the chunks in index order (thread-count independent). */
+int fb_cost_grad(const fb_problem* pb, int64_t M, uint64_t seed, uint32_t iter,
+                 const double* mu, double* J, double* g, int nthreads)
+{
+    if (check_problem(pb) || M < 1 || !mu || !J)
+        return -1;
+    const int N = pb->N, L = pb->nx * pb->nv;
+    const size_t nl = (size_t)N * L;
+    const int64_t nchunk = (M + FB_CHUNK - 1) / FB_CHUNK;
+    uint64_t thr[32];
+    or_poisson_thresholds(rate_dt(pb), thr);
+    double* csum = (double*)calloc((size_t)nchunk, sizeof(double));
+    double* gsum = g ? (double*)calloc((size_t)nchunk * nl, sizeof(double)) : NULL;
+    if (!csum || (g && !gsum)) {
+        free(csum);
+        free(gsum);
+        return -2;
+    }
+    int rc = 0;
+#pragma omp parallel num_threads(nthreads > 0 ? nthreads : 1) reduction(| : rc)
+    {
+        work w;
+        const int ok = work_alloc(pb, &w) == 0;
+        rc |= ok ? 0 : 1;
+        {
+#pragma omp for schedule(dynamic, 1)
+            for (int64_t c = 0; c < nchunk; ++c) {
+                if (!ok)
+                    continue;
+                int64_t mb = c * FB_CHUNK, me = mb + FB_CHUNK < M ? mb + FB_CHUNK : M;
+                double cs = 0.0;
+                for (int64_t m = mb; m < me; ++m) {
+                    cs += path_forward(pb, thr, seed, iter, (uint32_t)m, mu, &w);
+                    if (g)
+                        path_adjoint(pb, mu, &w, gsum + (size_t)c * nl);
+                }
+                csum[c] = cs;
+            }
+        }
+        work_free(&w);
+    }
+    if (rc) {
+        free(csum);
+        free(gsum);
+        return -2;
+    }
+    double ctot = 0.0;
+    for (int64_t c = 0; c < nchunk; ++c)
+        ctot += csum[c];
+    *J = ctot / (double)M;
+    if (g) {
+        for (size_t q = 0; q < nl; ++q) {
+            double t = 0.0;
+            for (int64_t c = 0; c < nchunk; ++c)
+                t += gsum[(size_t)c * nl + q];
+            g[q] = t / (double)M;
+        }
+    }
+    free(csum);
+    free(gsum);
+    return 0;
+}
+
+/* Forward-mode derivative of J along dmu: differentiates the Euler step, the
+ * jump composition and the cost directly, independently of the adjoint. */
+int fb_tangent(const fb_problem* pb, int64_t M, uint64_t seed, uint32_t iter,
+               const double* mu, const double* dmu, double* dJ, int nthreads)
+{
+    if (check_problem(pb) || M < 1 || !mu || !dmu || !dJ)
+        return -1;
+    const int N = pb->N, L = pb->nx * pb->nv;
+    const double dt = pb->T / (double)N;
+    const int64_t nchunk = (M + FB_CHUNK - 1) / FB_CHUNK;
+    uint64_t thr[32];
+    or_poisson_thresholds(rate_dt(pb), thr);
+    double* csum = (double*)calloc((size_t)nchunk, sizeof(double));
+    if (!csum)
+        return -2;
+    int rc = 0;
+#pragma omp parallel num_threads(nthreads > 0 ? nthreads : 1) reduction(| : rc)
+    {
+        work w;
+        const int ok = work_alloc(pb, &w) == 0;
+        rc |= ok ? 0 : 1;
+        {
+#pragma omp for schedule(dynamic, 1)
+            for (int64_t c = 0; c < nchunk; ++c) {
+                if (!ok)
+                    continue;
+                int64_t mb = c * FB_CHUNK, me = mb + FB_CHUNK < M ? mb + FB_CHUNK : M;
+                double cs = 0.0;
+                for (int64_t m = mb; m < me; ++m) {
+                    path_forward(pb, thr, seed, iter, (uint32_t)m, mu, &w);
+                    double tx = 0.0, tv = 0.0, dc = 0.0;
+                    for (int k = 0; k < N; ++k) {
+                        const double* zk = w.z + 2 * k;
+                        const double* mk = mu + (size_t)k * L;
+                        shapes(pb, zk, w.px, w.pv, w.dpx, w.dpv);
+                        double u = w.u[k];
+                        double du = control(pb, mk, w.dpx, w.pv) * tx +
+                                    control(pb, mk, w.px, w.dpv) * tv +
+                                    control(pb, dmu + (size_t)k * L, w.px, w.pv);
+                        dc += dt * pb->alpha * u * du;
+                        double gn, Vn;
+                        ks_factors(pb, w.n[k], &gn, &Vn);
+                        double nx = tx + dt * tv;
+                        double nv = gn * (tv + dt * (du - pb->eta * tx));
+                        tx = nx;
+                        tv = nv;
+                        double gz[2];
+                        track_grad(pb, w.z + 2 * (k + 1), pb->zd + 2 * (k + 1), gz);
+                        dc += dt * (gz[0] * tx + gz[1] * tv);
+                    }
+                    cs += dc;
+                }
+                csum[c] = cs;
+            }
+        }
+        work_free(&w);
+    }
+    double tot = 0.0;
+    for (int64_t c = 0; c < nchunk; ++c)
+        tot += csum[c];
+    *dJ = tot / (double)M;
+    free(csum);
+    return rc ? -2 : 0;
+}
+
+/* Algorithm 5.4: iteration n draws with counter iter0 + n, every Armijo trial
+ * of the iteration reuses it; descent along -g with ||v||^2 = dt sum |v_k|^2. */
+int fb_optimize(const fb_problem* pb, int64_t M, uint64_t seed, uint32_t iter0, int32_t n_max,
+                double tol, double zeta0, double rho, double c_armijo, int32_t max_backtracks,
+                double* mu, double* logJ, double* log_gnorm, double* log_zeta, int32_t* log_bt,
+                double* logE, int nthreads)
+{
+    if (check_problem(pb) || !mu || n_max < 0 || max_backtracks < 1)
+        return -1;
+    const int N = pb->N, L = pb->nx * pb->nv;
+    const double dt = pb->T / (double)N;
+    const size_t nl = (size_t)N * L;
+    double* g = (double*)malloc(nl * sizeof(double));
+    double* mt = (double*)malloc(nl * sizeof(double));
+    if (!g || !mt) {
+        free(g);
+        free(mt);
+        return -2;
+    }
+    int n;
+    for (n = 0; n < n_max; ++n) {
+        uint32_t it = iter0 + (uint32_t)n;
+        double J;
+        if (fb_cost_grad(pb, M, seed, it, mu, &J, g, nthreads)) {
+            n = -2;
+            break;
+        }
+        double gg = 0.0;
+        for (size_t q = 0; q < nl; ++q)
+            gg += g[q] * g[q];
+        gg *= dt;
+        double zeta = zeta0;
+        int accepted = 0, bt;
+        for (bt = 0; bt < max_backtracks; ++bt) {
+            for (size_t q = 0; q < nl; ++q)
+                mt[q] = mu[q] - zeta * g[q];
+            double Jt;
+            fb_cost_grad(pb, M, seed, it, mt, &Jt, NULL, nthreads);
+            if (Jt <= J - c_armijo * zeta * gg) {
+                accepted = 1;
+                break;
+            }
+            zeta *= rho;
+        }
+        if (!accepted) {
+            n = -3;
+            break;
+        }
+        double E = 0.0;
+        for (size_t q = 0; q < nl; ++q) {
+            double r = mt[q] - mu[q];
+            E += r * r;
+            mu[q] = mt[q];
+        }
+        E = sqrt(dt * E);
+        if (logJ)
+            logJ[n] = J;
+        if (log_gnorm)
+            log_gnorm[n] = sqrt(gg);
+        if (log_zeta)
+            log_zeta[n] = zeta;
+        if (log_bt)
+            log_bt[n] = bt;
+        if (logE)
+            logE[n] = E;
+        if (E <= tol) {
+            ++n;
+            break;
+        }
+    }
+    free(g);
+    free(mt);
+    return n;
+}

@@ -1,0 +1,81 @@
+/*
+ * FP64 CPU oracle for the paper's own model problem (Bartsch, Borzi,
+ * Ciaramella, Reichle, arXiv 2505.04328, Sections 2 and 5): a particle in
+ * phase space z = (x, v) driven by a harmonic oscillator, Brownian noise,
+ * Keilson-Storer velocity jumps and a feedback control built from
+ * radial-basis shape functions, with a Gaussian tracking cost.
+ *
+ * TEST INFRASTRUCTURE ONLY, like the rest of this directory.
+ *
+ * Conventions (paths m, steps k = 0..N-1, dt = T/N, t_k = k dt):
+ *   centres   xc_i = (i + 1/2) 2 xmax/nx - xmax,  vc_l = (l + 1/2) 2 vmax/nv - vmax
+ *   bump      b(r) = exp(-1/(1 - (eps r)^2)) for |r| < 1/eps, else 0
+ *   shape     phi_{i nv + l}(x, v) = b(x - xc_i) b(v - vc_l),  L = nx nv
+ *   control   u_k = sum_l mu_k[l] phi_l(z_k)              (mu is N x L)
+ *   forward   x_{k+1} = x_k + dt v_k + b1 sqrt(dt) Zx
+ *             v*      = v_k + dt (u_k - eta x_k) + b2 sqrt(dt) Zv
+ *             v_{k+1} = gamma^n v* + sqrt(V_n) ZJ,  V_n = (1/(2 beta)) sum_{i<n} gamma^{2i}
+ *             (n ~ Poisson(sigma dt) Keilson-Storer jumps in the step, sigma = sqrt(beta/pi))
+ *   cost      C = dt sum_{k=1..N} Jt(z_k, zd_k) + dt alpha/2 sum_{k=0..N-1} u_k^2
+ *             Jt(z, zd) = -exp(-|z - zd|^2 / (2 sigJ^2))
+ *   adjoint   lam = dC/dz:  lam_N = dt grad Jt(z_N)
+ *             lam^x_k = lam^x_{k+1} + gamma^n dt (u_x - eta) lam^v_{k+1} + dt dJt/dx + dt alpha u u_x
+ *             lam^v_k = dt lam^x_{k+1} + gamma^n (1 + dt u_v) lam^v_{k+1} + dt dJt/dv + dt alpha u u_v
+ *   gradient  g_k[l] = (1/M) sum_m phi_l(z_k) (alpha u_k + gamma^{n_k} lam^v_{k+1})
+ *             (dJ/dmu_k = dt g_k)
+ */
+#ifndef FB_ORACLE_H
+#define FB_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    int32_t N, nx, nv;
+    double T, eta, b1, b2, gamma, beta;
+    double xmax, vmax, eps, alpha, sigJ;
+    int32_t init_kind;     /* 0: Gaussian z0 + s0 * Z, 1: uniform on [z0 - s0, z0 + s0] */
+    double z0[2], s0[2];
+    const double* zd;      /* (N+1) x 2, row k = desired (x, v) at t_k */
+} fb_problem;
+
+/* Bump b(r) and its derivative b'(r). */
+double fb_bump(double r, double eps);
+double fb_bump_deriv(double r, double eps);
+
+/* Draws of path m under iteration iter: initial state (x, v), and for step k
+ * the normals (Zx, Zv, ZJ) and the jump count n. */
+void fb_initial(const fb_problem* pb, uint64_t seed, uint32_t m, uint32_t iter, double z[2]);
+void fb_step_draws(uint64_t seed, uint32_t m, uint32_t k, uint32_t iter, const uint64_t thr[32],
+                   double Z[3], int* n);
+
+/* Per-path states z (count x (N+1) x 2), adjoints lam (count x (N+1) x 2, row 0
+ * zero), controls u (count x N), jump counts (count x N) and costs C (count),
+ * for paths m0..m0+count-1.  Any output may be NULL. */
+int fb_paths(const fb_problem* pb, uint64_t seed, uint32_t iter, int64_t m0, int64_t count,
+             const double* mu, double* z, double* lam, double* u, int32_t* jumps, double* C,
+             int nthreads);
+
+/* J and g (N x L) over M paths, fixed-order chunked FP64 sums.  g may be NULL. */
+int fb_cost_grad(const fb_problem* pb, int64_t M, uint64_t seed, uint32_t iter,
+                 const double* mu, double* J, double* g, int nthreads);
+
+/* Tangent-linear directional derivative dJ[dmu]. */
+int fb_tangent(const fb_problem* pb, int64_t M, uint64_t seed, uint32_t iter,
+               const double* mu, const double* dmu, double* dJ, int nthreads);
+
+/* Gradient iteration with stochastic Armijo backtracking on the same draws
+ * (Section 5, Algorithm 5.4); mu in/out.  Logs may be NULL. */
+int fb_optimize(const fb_problem* pb, int64_t M, uint64_t seed, uint32_t iter0, int32_t n_max,
+                double tol, double zeta0, double rho, double c_armijo, int32_t max_backtracks,
+                double* mu, double* logJ, double* log_gnorm, double* log_zeta, int32_t* log_bt,
+                double* logE, int nthreads);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

@@ -200,3 +200,140 @@ def optimize(p, M: int, seed: int, it0: int, u0=None, n_max: int = 20, tol: floa
     logs = {k: v[:n] for k, v in logs.items()}
     logs["backtracks"] = bt[:n]
     return u, logs, n
+
+
+# ---------------------------------------------------------------------------
+# The paper's model problem (fb_oracle.c): FeedbackProblem instances.
+
+class _FbProblem(C.Structure):
+    _fields_ = [("N", C.c_int32), ("nx", C.c_int32), ("nv", C.c_int32),
+                ("T", C.c_double), ("eta", C.c_double), ("b1", C.c_double), ("b2", C.c_double),
+                ("gamma", C.c_double), ("beta", C.c_double), ("xmax", C.c_double),
+                ("vmax", C.c_double), ("eps", C.c_double), ("alpha", C.c_double),
+                ("sigJ", C.c_double), ("init_kind", C.c_int32), ("z0", C.c_double * 2),
+                ("s0", C.c_double * 2), ("zd", C.c_void_p)]
+
+
+def _bind_fb(L):
+    if getattr(L, "_fb_bound", False):
+        return L
+    P = C.c_void_p
+    L.fb_bump.argtypes = [C.c_double, C.c_double]
+    L.fb_bump.restype = C.c_double
+    L.fb_bump_deriv.argtypes = [C.c_double, C.c_double]
+    L.fb_bump_deriv.restype = C.c_double
+    L.fb_initial.argtypes = [P, C.c_uint64, C.c_uint32, C.c_uint32, P]
+    L.fb_step_draws.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, P, P, P]
+    L.fb_paths.argtypes = [P, C.c_uint64, C.c_uint32, C.c_int64, C.c_int64, P, P, P, P, P, P, C.c_int]
+    L.fb_paths.restype = C.c_int
+    L.fb_cost_grad.argtypes = [P, C.c_int64, C.c_uint64, C.c_uint32, P, P, P, C.c_int]
+    L.fb_cost_grad.restype = C.c_int
+    L.fb_tangent.argtypes = [P, C.c_int64, C.c_uint64, C.c_uint32, P, P, P, C.c_int]
+    L.fb_tangent.restype = C.c_int
+    L.fb_optimize.argtypes = [P, C.c_int64, C.c_uint64, C.c_uint32, C.c_int32, C.c_double,
+                              C.c_double, C.c_double, C.c_double, C.c_int32, P, P, P, P, P, P,
+                              C.c_int]
+    L.fb_optimize.restype = C.c_int
+    L._fb_bound = True
+    return L
+
+
+def _fb():
+    return _bind_fb(lib())
+
+
+class _Fb:
+    """Keeps the ctypes struct and the arrays it points to alive together."""
+
+    def __init__(self, p):
+        self.zd = np.ascontiguousarray(p.zd, np.float64)
+        self.st = _FbProblem(p.N, p.nx, p.nv, p.T, p.eta, p.b1, p.b2, p.gamma, p.beta, p.xmax,
+                             p.vmax, p.eps, p.alpha, p.sigJ, p.init_kind,
+                             (C.c_double * 2)(*p.z0), (C.c_double * 2)(*p.s0), self.zd.ctypes.data)
+
+    def ref(self):
+        return C.byref(self.st)
+
+
+def _mu(p, mu):
+    return np.ascontiguousarray(np.asarray(mu, np.float64).reshape(p.N, p.L))
+
+
+def fb_bump(r: float, eps: float) -> float:
+    return _fb().fb_bump(float(r), float(eps))
+
+
+def fb_bump_deriv(r: float, eps: float) -> float:
+    return _fb().fb_bump_deriv(float(r), float(eps))
+
+
+def fb_initial(p, seed: int, m: int, it: int) -> np.ndarray:
+    z = np.zeros(2)
+    fb = _Fb(p)
+    _fb().fb_initial(fb.ref(), seed, m, it, _ptr(z))
+    return z
+
+
+def fb_step_draws(p, seed: int, m: int, k: int, it: int):
+    """(Zx, Zv, ZJ), n for path m, step k."""
+    thr = poisson_thresholds(p.rate * p.dt)
+    Z = np.zeros(3)
+    n = C.c_int()
+    _fb().fb_step_draws(seed, m, k, it, _ptr(thr), _ptr(Z), C.byref(n))
+    return Z, n.value
+
+
+def fb_paths(p, seed: int, it: int, m0: int, count: int, mu, nthreads: int | None = None):
+    """Per-path z (count, N+1, 2), lam (count, N+1, 2), u (count, N), jump
+    counts (count, N) and costs (count)."""
+    mu = _mu(p, mu)
+    z = np.zeros((count, p.N + 1, 2))
+    lam = np.zeros((count, p.N + 1, 2))
+    u = np.zeros((count, p.N))
+    n = np.zeros((count, p.N), np.int32)
+    c = np.zeros(count)
+    fb = _Fb(p)
+    rc = _fb().fb_paths(fb.ref(), seed, it, m0, count, _ptr(mu), _ptr(z), _ptr(lam), _ptr(u),
+                        _ptr(n), _ptr(c), nthreads or default_threads())
+    assert rc == 0, rc
+    return z, lam, u, n, c
+
+
+def fb_cost_grad(p, M: int, seed: int, it: int, mu, grad: bool = True,
+                 nthreads: int | None = None):
+    """(J, g) with g of shape (N, L) (None if grad is False)."""
+    mu = _mu(p, mu)
+    J = C.c_double()
+    g = np.zeros((p.N, p.L)) if grad else None
+    fb = _Fb(p)
+    rc = _fb().fb_cost_grad(fb.ref(), M, seed, it, _ptr(mu), C.byref(J),
+                            None if g is None else _ptr(g), nthreads or default_threads())
+    assert rc == 0, rc
+    return J.value, g
+
+
+def fb_tangent(p, M: int, seed: int, it: int, mu, dmu, nthreads: int | None = None) -> float:
+    mu, dmu = _mu(p, mu), _mu(p, dmu)
+    dJ = C.c_double()
+    fb = _Fb(p)
+    rc = _fb().fb_tangent(fb.ref(), M, seed, it, _ptr(mu), _ptr(dmu), C.byref(dJ),
+                          nthreads or default_threads())
+    assert rc == 0, rc
+    return dJ.value
+
+
+def fb_optimize(p, M: int, seed: int, it0: int, mu, n_max: int, tol: float = 0.0,
+                zeta0: float = 1.0, rho: float = 0.5, c_armijo: float = 1e-4,
+                max_backtracks: int = 30, nthreads: int | None = None):
+    """Returns (mu, logs, n) like ``optimize``."""
+    mu = _mu(p, mu).copy()
+    nm = max(n_max, 1)
+    lJ, lg, lz, lE = np.zeros(nm), np.zeros(nm), np.zeros(nm), np.zeros(nm)
+    lb = np.zeros(nm, np.int32)
+    fb = _Fb(p)
+    n = _fb().fb_optimize(fb.ref(), M, seed, it0, n_max, tol, zeta0, rho, c_armijo,
+                          max_backtracks, _ptr(mu), _ptr(lJ), _ptr(lg), _ptr(lz), _ptr(lb),
+                          _ptr(lE), nthreads or default_threads())
+    logs = [dict(J=lJ[i], gnorm=lg[i], zeta=lz[i], backtracks=int(lb[i]), E=lE[i])
+            for i in range(max(n, 0))]
+    return mu, logs, n

@@ -217,3 +217,118 @@ def serving_requests(count: int = 256, rate: float = 50.0, seed: int = 11, M_lo:
         out.append(Request(rid=r, arrival=float(arrivals[r]), problem=p, M=M, seed=r + 1,
                            iters=iters))
     return out
+
+
+# ---------------------------------------------------------------------------
+# The paper's own model problem (Section 5, model equation; Section 6): one
+# particle z = (x, v) per path in a harmonic oscillator with Brownian noise,
+# Keilson-Storer velocity jumps v <- gamma v + N(0, 1/(2 beta)) at rate
+# sqrt(beta/pi), and the feedback control u(z, t_k) = sum_l mu_k[l] phi_l(z)
+# over nx x nv products of compact bump functions on the cell centres of
+# (-xmax, xmax) x (-vmax, vmax).
+
+
+@dataclasses.dataclass
+class FeedbackProblem:
+    """One instance of the paper's model problem (FP64, host memory)."""
+
+    N: int
+    T: float
+    eta: float
+    b1: float
+    b2: float
+    gamma: float
+    beta: float
+    nx: int
+    nv: int
+    xmax: float
+    vmax: float
+    eps: float
+    alpha: float
+    sigJ: float
+    init_kind: int  # 0: Gaussian z0 + s0 * Z, 1: uniform on [z0 - s0, z0 + s0]
+    z0: np.ndarray  # 2
+    s0: np.ndarray  # 2
+    zd: np.ndarray  # (N+1) x 2, row k = desired (x, v) at t_k
+    name: str = ""
+
+    def __post_init__(self):
+        self.N, self.nx, self.nv, self.init_kind = int(self.N), int(self.nx), int(self.nv), int(self.init_kind)
+        for f in ("T", "eta", "b1", "b2", "gamma", "beta", "xmax", "vmax", "eps", "alpha", "sigJ"):
+            setattr(self, f, float(getattr(self, f)))
+        self.z0 = np.ascontiguousarray(np.broadcast_to(np.asarray(self.z0, np.float64), (2,)))
+        self.s0 = np.ascontiguousarray(np.broadcast_to(np.asarray(self.s0, np.float64), (2,)))
+        self.zd = np.ascontiguousarray(np.asarray(self.zd, np.float64).reshape(self.N + 1, 2))
+
+    @property
+    def dt(self) -> float:
+        return self.T / self.N
+
+    @property
+    def L(self) -> int:
+        return self.nx * self.nv
+
+    @property
+    def rate(self) -> float:
+        """Keilson-Storer jump frequency sqrt(beta/pi) (eq. collision_frequency)."""
+        return math.sqrt(self.beta / math.pi)
+
+
+@dataclasses.dataclass
+class FeedbackWorkload:
+    problem: FeedbackProblem
+    M: int
+    seed: int = 1
+
+
+def feedback_problem(N: int = 50, T: float = 5.0, init: str = "gauss", zd=None, eta: float = 1.0,
+                     b1: float = 0.05, b2: float = 0.1, gamma: float = 0.9, beta: float = 10.0,
+                     nx: int = 10, nv: int = 10, xmax: float = 2.0, vmax: float = 2.0,
+                     eps: float = 0.5, alpha: float = 1e-2, sigJ: float = 0.5,
+                     name: str = "") -> FeedbackProblem:
+    """The setting of the paper's Section 6 (xmax = vmax = 2, nx = nv = 10,
+    eps = 0.5, beta = 10, gamma = 0.9, eta = 1, T = 5, N = 50).  The paper does
+    not state alpha, sigma_J, b1, b2; the defaults here are readings.  init
+    'gauss' is N((0.75, 0.75), 0.01 I) (Section 6.1), 'uniform' is [-1, 1]^2."""
+    if init == "gauss":
+        kind, z0, s0 = 0, (0.75, 0.75), (0.1, 0.1)
+    elif init == "uniform":
+        kind, z0, s0 = 1, (0.0, 0.0), (1.0, 1.0)
+    else:
+        raise ValueError(init)
+    if zd is None:
+        zd = np.zeros((N + 1, 2))
+    return FeedbackProblem(N=N, T=T, eta=eta, b1=b1, b2=b2, gamma=gamma, beta=beta, nx=nx, nv=nv,
+                           xmax=xmax, vmax=vmax, eps=eps, alpha=alpha, sigJ=sigJ, init_kind=kind,
+                           z0=z0, s0=s0, zd=zd, name=name)
+
+
+def switching_target(N: int, T: float, amp: float = 0.5) -> np.ndarray:
+    """A non-smooth desired trajectory (Section 6.3 follows one; its formula is
+    not printed): x_d jumps between +amp and -amp at t = T/2, v_d = 0."""
+    t = np.arange(N + 1) * (T / N)
+    zd = np.zeros((N + 1, 2))
+    zd[:, 0] = np.where(t < 0.5 * T, amp, -amp)
+    return zd
+
+
+def feedback_config(name: str) -> FeedbackWorkload:
+    """f1: Section 6.1 centering from a Gaussian cloud, the paper's size
+    (2000 particles, 50 steps).  f2: centering from the uniform box.  f3: the
+    switching target.  f4: the measured size, 2^20 particles and 500 steps
+    (dt = 0.01) of the f1 setting."""
+    if name == "f1":
+        return FeedbackWorkload(feedback_problem(name="f1"), M=2000, seed=1)
+    if name == "f2":
+        return FeedbackWorkload(feedback_problem(init="uniform", name="f2"), M=2000, seed=1)
+    if name == "f3":
+        return FeedbackWorkload(feedback_problem(zd=switching_target(50, 5.0), name="f3"), M=2000,
+                                seed=1)
+    if name == "f4":
+        return FeedbackWorkload(feedback_problem(N=500, name="f4"), M=1 << 20, seed=1)
+    raise KeyError(name)
+
+
+def random_feedback_control(p: FeedbackProblem, seed: int, scale: float = 1.0) -> np.ndarray:
+    """A seeded control mu (N x L), entries N(0, scale^2)."""
+    return np.random.default_rng(seed).normal(0.0, scale, (p.N, p.L))

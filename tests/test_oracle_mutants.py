@@ -17,7 +17,11 @@ import pytest
 from oracle import build
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-PIN_FILES = ["tests/test_oracle_rng.py", "tests/test_oracle_model.py"]
+# pin suites run against a mutant of each oracle source file
+PIN_FILES = {
+    "jd_oracle.c": ["tests/test_oracle_rng.py", "tests/test_oracle_model.py"],
+    "fb_oracle.c": ["tests/test_oracle_fb.py"],
+}
 
 # name: (exact text in jd_oracle.c, replacement)
 MUTANTS = {
@@ -54,27 +58,72 @@ MUTANTS = {
     "descent_sign": ("ut[q] = u[q] - zeta * g[q];", "ut[q] = u[q] + zeta * g[q];"),
 }
 
+# the paper's model problem (fb_oracle.c): name: (exact text, replacement)
+FB_MUTANTS = {
+    "fb_bump_exponent": ("return exp(-1.0 / (1.0 - q * q));", "return exp(-1.0 / (1.0 - q * q * q * q));"),
+    "fb_bump_deriv_eps": ("(-2.0 * eps * eps * r) / (s * s)", "(-2.0 * eps * r) / (s * s)"),
+    "fb_centre_offset": ("double r = z[0] - ((i + 0.5) * dx - pb->xmax);",
+                         "double r = z[0] - ((i + 1.0) * dx - pb->xmax);"),
+    "fb_velocity_centres_use_x": ("double r = z[1] - ((l + 0.5) * dv - pb->vmax);",
+                                  "double r = z[1] - ((l + 0.5) * dx - pb->xmax);"),
+    "fb_control_transposed": ("u += mu[i * pb->nv + l] * px[i] * pv[l];",
+                              "u += mu[l * pb->nx + i] * px[i] * pv[l];"),
+    "fb_position_without_dt": ("zn[0] = zk[0] + dt * zk[1] + pb->b1 * sq * Z[0];",
+                               "zn[0] = zk[0] + zk[1] + pb->b1 * sq * Z[0];"),
+    "fb_spring_sign": ("double vs = zk[1] + dt * (u - pb->eta * zk[0])", "double vs = zk[1] + dt * (u + pb->eta * zk[0])"),
+    "fb_velocity_noise_is_x": ("+ pb->b2 * sq * Z[1];", "+ pb->b2 * sq * Z[0];"),
+    "fb_jump_factor_once": ("zn[1] = gn * vs + sqrt(Vn) * Z[2];", "zn[1] = (w->n[k] ? pb->gamma : 1.0) * vs + sqrt(Vn) * Z[2];"),
+    "fb_jump_variance": ("*Vn = s / (2.0 * pb->beta);", "*Vn = s / pb->beta;"),
+    "fb_jump_rate": ("return sqrt(pb->beta / FB_PI) * (pb->T / (double)pb->N);",
+                     "return sqrt(pb->beta * FB_PI) * (pb->T / (double)pb->N);"),
+    "fb_initial_sine_to_x": ("z[1] = pb->z0[1] + pb->s0[1] * R * sin(FB_TWO_PI * ub);",
+                             "z[1] = pb->z0[1] + pb->s0[1] * R * cos(FB_TWO_PI * ub);"),
+    "fb_track_left_point": ("C += dt * track(pb, zn, pb->zd + 2 * (k + 1));",
+                            "C += dt * track(pb, zk, pb->zd + 2 * k);"),
+    "fb_control_cost_half": ("C += dt * 0.5 * pb->alpha * u * u;", "C += dt * pb->alpha * u * u;"),
+    "fb_adjoint_terminal_without_dt": ("w->lam[2 * N] = dt * gz[0];", "w->lam[2 * N] = gz[0];"),
+    "fb_adjoint_spring_sign": ("gn * dt * (ux - pb->eta) * lv", "gn * dt * (ux + pb->eta) * lv"),
+    "fb_adjoint_position_coupling": ("w->lam[2 * k + 1] = dt * lx +", "w->lam[2 * k + 1] = lx +"),
+    "fb_adjoint_no_jump_factor": ("gn * (1.0 + dt * uv) * lv", "(1.0 + dt * uv) * lv"),
+    "fb_adjoint_uv_dropped": ("gn * (1.0 + dt * uv) * lv", "gn * lv"),
+    "fb_adjoint_track_sign": ("+ dt * gz[1] + dt * pb->alpha * u * uv;", "- dt * gz[1] + dt * pb->alpha * u * uv;"),
+    "fb_adjoint_control_cost_dropped": ("+ dt * gz[0] + dt * pb->alpha * u * ux;", "+ dt * gz[0];"),
+    "fb_gradient_no_jump_factor": ("double wk = pb->alpha * u + gn * lv;", "double wk = pb->alpha * u + lv;"),
+    "fb_gradient_control_term_dropped": ("double wk = pb->alpha * u + gn * lv;", "double wk = gn * lv;"),
+    "fb_track_grad_sign": ("gz[0] = rx / s2 * e;", "gz[0] = -rx / s2 * e;"),
+    "fb_armijo_sign": ("if (Jt <= J - c_armijo * zeta * gg)", "if (Jt <= J + c_armijo * zeta * gg)"),
+}
 
-def _run_mutant(name, tmpdir):
-    src = open(build.SRC).read()
-    old, new = MUTANTS[name]
-    assert src.count(old) == 1, f"mutant {name}: pattern must occur exactly once"
-    msrc = os.path.join(tmpdir, f"{name}.c")
-    with open(msrc, "w") as f:
-        f.write(src.replace(old, new))
+
+ALL = [(n, "jd_oracle.c", old, new) for n, (old, new) in MUTANTS.items()] + \
+      [(n, "fb_oracle.c", old, new) for n, (old, new) in FB_MUTANTS.items()]
+
+
+def _run_mutant(case, tmpdir):
+    name, target, old, new = case
+    srcs = []
+    for path in build.SRC:
+        text = open(path).read()
+        if os.path.basename(path) == target:
+            assert text.count(old) == 1, f"mutant {name}: pattern must occur exactly once"
+            text = text.replace(old, new)
+        msrc = os.path.join(tmpdir, f"{name}__{os.path.basename(path)}")
+        with open(msrc, "w") as f:
+            f.write(text)
+        srcs.append(msrc)
     lib = os.path.join(tmpdir, f"{name}.so")
-    build.build(src=msrc, out=lib, extra=["-I" + os.path.dirname(build.SRC)])
+    build.build(src=srcs, out=lib, extra=["-I" + os.path.dirname(build.SRC[0])])
     env = dict(os.environ, JD_ORACLE_LIB=lib, OMP_NUM_THREADS="1")
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        *PIN_FILES], cwd=ROOT, env=env, capture_output=True, text=True,
-                       timeout=600)
+                        *PIN_FILES[target]], cwd=ROOT, env=env, capture_output=True, text=True,
+                       timeout=900)
     return name, r.returncode, r.stdout[-600:]
 
 
 def test_every_mutant_is_caught(tmp_path):
     workers = max(1, min(8, (os.cpu_count() or 2)))
     with cfut.ThreadPoolExecutor(workers) as ex:
-        results = list(ex.map(lambda n: _run_mutant(n, str(tmp_path)), MUTANTS))
+        results = list(ex.map(lambda c: _run_mutant(c, str(tmp_path)), ALL))
     survivors = [(n, out) for n, rc, out in results if rc == 0]
     assert not survivors, "mutants not caught by any pin: " + ", ".join(n for n, _ in survivors)
     for n, rc, out in results:
