@@ -1,0 +1,120 @@
+/*
+ * jd_feedback.h -- C ABI of libjd for the paper's own model problem
+ * (Bartsch, Borzi, Ciaramella, Reichle, arXiv 2505.04328, Section 5 model
+ * equation, shape functions and jump process; Section 6): one particle
+ * z = (x, v) per path in a harmonic oscillator with Brownian noise and
+ * Keilson-Storer velocity jumps, steered by a feedback control built from
+ * radial-basis shape functions, with a Gaussian tracking cost.
+ *
+ *   centres   x^i = (i + 1/2) 2 xmax/nx - xmax,  v^l = (l + 1/2) 2 vmax/nv - vmax
+ *             (0-based i, l; the cell centres of Section 5, discretization)
+ *   bump      b(r) = exp(-1/(1 - (eps r)^2)) for |r| < 1/eps, else 0 (eq. Gaussian_RBF)
+ *   control   u_k = sum_{i,l} mu_k[i nv + l] b(x_k - x^i) b(v_k - v^l)  (eq. control_structure)
+ *   forward   (eq. SDE_splitted_drift_Euler, h = 0, on the fixed grid t_k = k dt)
+ *             x_{k+1} = x_k + dt v_k + b1 sqrt(dt) Zx_k
+ *             v*      = v_k + dt (u_k - eta x_k) + b2 sqrt(dt) Zv_k
+ *             v_{k+1} = gamma^n v* + sqrt(V_n) ZJ_k,  V_n = (1/(2 beta)) sum_{i<n} gamma^{2i}
+ *             n = n_k ~ Poisson(sqrt(beta/pi) dt): the step's Keilson-Storer jumps
+ *             v <- gamma v + N(0, 1/(2 beta)) (eq. jump_law, eq. collision_frequency),
+ *             composed exactly after the step's Euler update
+ *   cost      C = dt sum_{k=1..N} Jt(z_k, zd_k) + dt alpha/2 sum_{k=0..N-1} u_k^2,
+ *             Jt(z, zd) = -exp(-|z - zd|^2/(2 sigJ^2))  (eq. discrete_functional,
+ *             eq. tracking_cost);  J = (1/M) sum_m C^m
+ *   adjoint   lam = dC/dz = -r (eq. adjoint_eq_approximation, jump condition p <- gamma p):
+ *             lam_N   = dt grad Jt(z_N)
+ *             lam^x_k = lam^x_{k+1} + gamma^n dt (u_x - eta) lam^v_{k+1} + dt dJt/dx + dt alpha u u_x
+ *             lam^v_k = dt lam^x_{k+1} + gamma^n (1 + dt u_v) lam^v_{k+1} + dt dJt/dv + dt alpha u u_v
+ *   gradient  g_k[i nv + l] = (1/M) sum_m b(x_k - x^i) b(v_k - v^l) (alpha u_k + gamma^{n_k} lam^v_{k+1})
+ *             (eq. definition_Gradient; dJ/dmu_k = dt g_k)
+ *
+ * Draws (counter-based, like jd.h): Philox4x32-10 block (m, k, iter, 0) per
+ * path-step; the Box-Muller pair of words 0 and 1 gives Zx (cosine) and Zv
+ * (sine), the cosine branch of words 2 and 3 gives ZJ, the low bytes of the
+ * four words the Poisson word.  The initial state uses block
+ * (m, 0xFFFFFFFF, iter, 0): Gaussian z0 + s0 (R cos, R sin) of words 0 and 1,
+ * or uniform z0 + s0 (2 u - 1) (fresh initial particles every iteration,
+ * Section 5, optimization procedure).
+ *
+ * Conventions are those of jd.h (return codes, caller-owned device buffers,
+ * asynchronous calls on `stream`, validation before any launch).  mu and g
+ * are FP64 device arrays, row-major N x L with L = nx nv.  Only JD_STORE is
+ * supported (JD_RECOMPUTE returns JD_EUNSUPPORTED).
+ */
+#ifndef JD_FEEDBACK_H
+#define JD_FEEDBACK_H
+
+#include "jd.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define JD_FB_INIT_GAUSS 0   /* z_0 = z0 + s0 . (Z1, Z2) */
+#define JD_FB_INIT_UNIFORM 1 /* z_0 uniform on [z0 - s0, z0 + s0] */
+
+typedef struct jd_fb_problem {
+    int32_t N;          /* time steps, >= 1 */
+    int32_t nx, nv;     /* shape-function grid, 1..16 each; L = nx nv */
+    double T;           /* horizon, > 0 */
+    double eta;         /* oscillator stiffness (H = [[0, 1], [-eta, 0]]) */
+    double b1, b2;      /* noise scales of x and v, >= 0 */
+    double gamma;       /* Keilson-Storer gamma in [-1, 1] */
+    double beta;        /* Keilson-Storer beta > 0; jump rate sqrt(beta/pi), rate*dt <= 2 */
+    double xmax, vmax;  /* shape-function domain (-xmax, xmax) x (-vmax, vmax), > 0 */
+    double eps;         /* bump shape parameter, > 0 */
+    double alpha;       /* control-cost weight, >= 0 */
+    double sigJ;        /* tracking-cost width, > 0 */
+    int32_t init_kind;  /* JD_FB_INIT_GAUSS or JD_FB_INIT_UNIFORM */
+    double z0[2], s0[2];/* initial law: centre and scale (s0 >= 0) */
+    const double* zd;   /* DEVICE, (N+1) x 2 FP64: desired (x, v) at t_0..t_N */
+} jd_fb_problem;
+
+/* Per-path diagnostics for the feedback model, as jd_dump with these layouts
+ * (DEVICE pointers, run precision for z and lam):
+ *   X[(k*2 + c)*count + p]   = z_k,c of path m0+p, k = 0..N   (jd_fb_forward)
+ *   lam[(k*2 + c)*count + p] = lam_k,c,                k = 1..N (jd_fb_adjoint)
+ *   cost[p]                  = C^(m0+p), FP64                  (jd_fb_forward) */
+
+/* Workspace and trajectory bytes (0 if the arguments are invalid).  The
+ * trajectory holds z_0..z_N in blocks of 256 paths: component c of z_k of
+ * path m is element ((m / 256) (N+1) + k) 2 256 + c 256 + (m % 256). */
+size_t jd_fb_workspace_bytes(const jd_fb_problem* prob, const jd_run* run);
+size_t jd_fb_traj_bytes(const jd_fb_problem* prob, const jd_run* run);
+
+/* Forward sweep (Algorithms 5.1-5.2 on the fixed grid) of all M particles:
+ * stores the trajectory (traj may be NULL for a cost-only sweep) and J(mu)
+ * into *J (device FP64).  mu: device FP64 N x L. */
+int jd_fb_forward(const jd_fb_problem* prob, const jd_run* run, const double* mu, void* traj,
+                  double* J, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Backward adjoint sweep over the trajectory of jd_fb_forward (same prob,
+ * run, mu) and the Monte Carlo gradient g (device FP64 N x L, no dt factor).
+ * The per-step sum over particles of phi(z) (alpha u + gamma^n lam^v) is a
+ * dense 16 x 16 contraction over paths and runs on the FP64 matrix cores. */
+int jd_fb_adjoint(const jd_fb_problem* prob, const jd_run* run, const double* mu,
+                  const void* traj, double* grad, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Forward + adjoint + reductions (Algorithm 5.3): J -> *J, g -> grad. */
+int jd_fb_cost_grad(const jd_fb_problem* prob, const jd_run* run, const double* mu, double* J,
+                    double* grad, void* traj, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Gradient iteration (Algorithm 5.4 with eq. Stochastic_Armijo), exactly as
+ * jd_optimize: iteration n uses counter word run->iter + n for the gradient
+ * and every trial; mu (device FP64 N x L) is updated in place. */
+int jd_fb_optimize(const jd_fb_problem* prob, const jd_run* run, const jd_opt* opt, double* mu,
+                   jd_iter_log* log, int32_t* iters_done, void* traj, void* ws, size_t ws_bytes,
+                   hipStream_t stream);
+
+/* The draws of paths [m0, m0+mc): initial states z_init (mc x 2) and, for steps
+ * [k0, k0+kc), the normals Z ((p kc + q) 3 + {0: Zx, 1: Zv, 2: ZJ}) and jump
+ * counts counts[p kc + q] (device buffers, run precision for z_init and Z,
+ * each may be NULL), for checking the draws against an independent
+ * implementation. */
+int jd_fb_draws(const jd_fb_problem* prob, const jd_run* run, int64_t m0, int64_t mc, int32_t k0,
+                int32_t kc, void* z_init, void* Z, int32_t* counts, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

@@ -24,6 +24,9 @@ JD_STORE, JD_RECOMPUTE = 0, 1
 EXPORTED = ["jd_version", "jd_strerror", "jd_workspace_bytes", "jd_traj_bytes", "jd_forward",
             "jd_adjoint", "jd_cost_grad", "jd_optimize", "jd_check_finite", "jd_draws",
             "jd_philox", "jd_poisson_thresholds"]
+# include/jd_feedback.h
+EXPORTED_FB = ["jd_fb_workspace_bytes", "jd_fb_traj_bytes", "jd_fb_forward", "jd_fb_adjoint",
+               "jd_fb_cost_grad", "jd_fb_optimize", "jd_fb_draws"]
 
 
 class JdError(RuntimeError):
@@ -91,6 +94,17 @@ def lib():
         for name in EXPORTED:
             if name not in ("jd_version", "jd_strerror", "jd_workspace_bytes", "jd_traj_bytes"):
                 getattr(L, name).restype = C.c_int
+        L.jd_fb_workspace_bytes.argtypes = [P, P]
+        L.jd_fb_workspace_bytes.restype = C.c_size_t
+        L.jd_fb_traj_bytes.argtypes = [P, P]
+        L.jd_fb_traj_bytes.restype = C.c_size_t
+        L.jd_fb_forward.argtypes = [P, P, P, P, P, P, C.c_size_t, P]
+        L.jd_fb_adjoint.argtypes = [P, P, P, P, P, P, C.c_size_t, P]
+        L.jd_fb_cost_grad.argtypes = [P, P, P, P, P, P, P, C.c_size_t, P]
+        L.jd_fb_optimize.argtypes = [P, P, P, P, P, P, P, P, C.c_size_t, P]
+        L.jd_fb_draws.argtypes = [P, P, C.c_int64, C.c_int64, C.c_int32, C.c_int32, P, P, P, P]
+        for name in EXPORTED_FB[2:]:
+            getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
 
@@ -277,3 +291,153 @@ def poisson_thresholds(mu: float) -> np.ndarray:
     t = np.zeros(32, np.uint64)
     check(lib().jd_poisson_thresholds(float(mu), t.ctypes.data), "jd_poisson_thresholds")
     return t
+
+
+# ---------------------------------------------------------------------------
+# The paper's model problem (include/jd_feedback.h).
+
+JD_FB_INIT_GAUSS, JD_FB_INIT_UNIFORM = 0, 1
+
+
+class jd_fb_problem(C.Structure):
+    _fields_ = [("N", C.c_int32), ("nx", C.c_int32), ("nv", C.c_int32), ("T", C.c_double),
+                ("eta", C.c_double), ("b1", C.c_double), ("b2", C.c_double),
+                ("gamma", C.c_double), ("beta", C.c_double), ("xmax", C.c_double),
+                ("vmax", C.c_double), ("eps", C.c_double), ("alpha", C.c_double),
+                ("sigJ", C.c_double), ("init_kind", C.c_int32), ("z0", C.c_double * 2),
+                ("s0", C.c_double * 2), ("zd", C.c_void_p)]
+
+
+class FbProblem:
+    """A workloads.FeedbackProblem packed for the C ABI, z_d on the device."""
+
+    def __init__(self, p, device="cuda:0"):
+        torch = _torch()
+        self.p = p
+        self.device = torch.device(device)
+        self.zd = torch.from_numpy(np.ascontiguousarray(p.zd, np.float64)).to(self.device)
+        self.st = jd_fb_problem(p.N, p.nx, p.nv, p.T, p.eta, p.b1, p.b2, p.gamma, p.beta, p.xmax,
+                                p.vmax, p.eps, p.alpha, p.sigJ, p.init_kind,
+                                (C.c_double * 2)(*p.z0), (C.c_double * 2)(*p.s0),
+                                self.zd.data_ptr())
+
+    @property
+    def ref(self):
+        return C.byref(self.st)
+
+
+class FbEngine:
+    """Feedback-model problem + Monte Carlo configuration with its workspace and
+    trajectory buffers (torch allocations)."""
+
+    def __init__(self, problem, M: int, seed: int = 1, precision: str = "fp32", device="cuda:0"):
+        torch = _torch()
+        self.prob = problem if isinstance(problem, FbProblem) else FbProblem(problem, device)
+        self.p = self.prob.p
+        self.M, self.seed, self.precision = M, seed, precision
+        self.device = self.prob.device
+        self.rdtype = torch.float32 if precision == "fp32" else torch.float64
+        run = make_run(M, seed, 0, precision, "store")
+        L = lib()
+        self.ws_bytes = L.jd_fb_workspace_bytes(self.prob.ref, C.byref(run))
+        self.traj_bytes = L.jd_fb_traj_bytes(self.prob.ref, C.byref(run))
+        if self.ws_bytes == 0 or self.traj_bytes == 0:
+            raise JdError(JD_EINVAL, "FbEngine")
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        esz = 4 if precision == "fp32" else 8
+        self.nblk = (M + 255) // 256
+        self.traj = torch.empty(self.traj_bytes // esz, dtype=self.rdtype, device=self.device)
+
+    def run(self, it: int = 0, dump: jd_dump | None = None) -> jd_run:
+        return make_run(self.M, self.seed, it, self.precision, "store", 0, dump)
+
+    def _mu(self, mu):
+        torch = _torch()
+        if isinstance(mu, np.ndarray):
+            mu = torch.from_numpy(np.ascontiguousarray(mu, np.float64))
+        mu = mu.to(device=self.device, dtype=torch.float64).contiguous()
+        assert tuple(mu.shape) == (self.p.N, self.p.L), mu.shape
+        return mu
+
+    def trajectory(self):
+        """z_0..z_N as an (N+1, 2, M) tensor (a copy of the blocked buffer)."""
+        t = self.traj.view(self.nblk, self.p.N + 1, 2, 256).permute(1, 2, 0, 3)
+        return t.reshape(self.p.N + 1, 2, self.nblk * 256)[:, :, :self.M]
+
+    def forward(self, mu, it: int = 0, store: bool = True, dump: jd_dump | None = None):
+        torch = _torch()
+        mu = self._mu(mu)
+        J = torch.empty((), dtype=torch.float64, device=self.device)
+        run = self.run(it, dump)
+        check(lib().jd_fb_forward(self.prob.ref, C.byref(run), mu.data_ptr(),
+                                  self.traj.data_ptr() if store else None, J.data_ptr(),
+                                  self.ws.data_ptr(), self.ws_bytes, _stream_ptr(self.device)),
+              "jd_fb_forward")
+        return J
+
+    def adjoint(self, mu, it: int = 0, dump: jd_dump | None = None):
+        torch = _torch()
+        mu = self._mu(mu)
+        g = torch.empty((self.p.N, self.p.L), dtype=torch.float64, device=self.device)
+        run = self.run(it, dump)
+        check(lib().jd_fb_adjoint(self.prob.ref, C.byref(run), mu.data_ptr(),
+                                  self.traj.data_ptr(), g.data_ptr(), self.ws.data_ptr(),
+                                  self.ws_bytes, _stream_ptr(self.device)), "jd_fb_adjoint")
+        return g
+
+    def cost_grad(self, mu, it: int = 0, J=None, g=None):
+        torch = _torch()
+        mu = self._mu(mu)
+        if J is None:
+            J = torch.empty((), dtype=torch.float64, device=self.device)
+        if g is None:
+            g = torch.empty((self.p.N, self.p.L), dtype=torch.float64, device=self.device)
+        run = self.run(it)
+        check(lib().jd_fb_cost_grad(self.prob.ref, C.byref(run), mu.data_ptr(), J.data_ptr(),
+                                    g.data_ptr(), self.traj.data_ptr(), self.ws.data_ptr(),
+                                    self.ws_bytes, _stream_ptr(self.device)), "jd_fb_cost_grad")
+        return J, g
+
+    def optimize(self, mu, n_max: int, it0: int = 0, tol: float = 0.0, zeta0: float = 1.0,
+                 rho: float = 0.5, c_armijo: float = 1e-4, max_backtracks: int = 30):
+        mu = self._mu(mu)
+        opt = jd_opt(n_max, max_backtracks, tol, zeta0, rho, c_armijo)
+        logs = (jd_iter_log * max(n_max, 1))()
+        done = C.c_int32(0)
+        run = self.run(it0)
+        rc = lib().jd_fb_optimize(self.prob.ref, C.byref(run), C.byref(opt), mu.data_ptr(), logs,
+                                  C.byref(done), self.traj.data_ptr(), self.ws.data_ptr(),
+                                  self.ws_bytes, _stream_ptr(self.device))
+        out = [dict(iter=l.iter, backtracks=l.backtracks, J=l.J, gnorm=l.gnorm, zeta=l.zeta,
+                    J_new=l.J_new, E=l.E) for l in logs[:done.value]]
+        check(rc, "jd_fb_optimize")
+        return mu, out
+
+    def check_finite(self) -> bool:
+        rc = lib().jd_check_finite(self.ws.data_ptr(), self.ws_bytes, _stream_ptr(self.device))
+        if rc == JD_ENONFINITE:
+            return False
+        check(rc, "jd_check_finite")
+        return True
+
+    def draws(self, m0: int, mc: int, k0: int, kc: int, it: int = 0):
+        """(z_init (mc, 2), Z (mc, kc, 3), counts (mc, kc))."""
+        torch = _torch()
+        zi = torch.empty((mc, 2), dtype=self.rdtype, device=self.device)
+        Z = torch.empty((mc, kc, 3), dtype=self.rdtype, device=self.device)
+        n = torch.empty((mc, kc), dtype=torch.int32, device=self.device)
+        run = self.run(it)
+        check(lib().jd_fb_draws(self.prob.ref, C.byref(run), m0, mc, k0, kc, zi.data_ptr(),
+                                Z.data_ptr(), n.data_ptr(), _stream_ptr(self.device)),
+              "jd_fb_draws")
+        return zi, Z, n
+
+    def path_dump(self, m0: int, count: int):
+        """Dump buffers for particles [m0, m0+count): z and lam (N+1, 2, count), cost."""
+        torch = _torch()
+        N = self.p.N
+        X = torch.zeros((N + 1, 2, count), dtype=self.rdtype, device=self.device)
+        lam = torch.zeros((N + 1, 2, count), dtype=self.rdtype, device=self.device)
+        cost = torch.zeros(count, dtype=torch.float64, device=self.device)
+        dp = jd_dump(m0, count, X.data_ptr(), lam.data_ptr(), cost.data_ptr())
+        return dp, dict(X=X, lam=lam, cost=cost)

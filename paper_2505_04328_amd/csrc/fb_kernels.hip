@@ -1,0 +1,630 @@
+// Kernels of the paper's model problem (include/jd_feedback.h) on gfx950:
+//
+//  k_fb_table          mu (FP64) -> path-precision rows padded to nvp, targets,
+//                      Keilson-Storer factors; stages the Poisson table
+//  k_fb_forward        forward sweep, one particle per lane: shape functions,
+//                      feedback control, draws, Euler step, jumps, FP64 cost
+//  k_fb_adjoint        backward sweep over the stored trajectory; the per-step
+//                      gradient sum over particles runs on the FP64 matrix cores
+//  k_fb_finalize_grad  fixed-order FP64 sum of the per-block gradient partials
+//  k_fb_finalize_cost  fixed-order FP64 sum of the path costs, ||g||^2
+//  k_fb_draws          initial states, normals and jump counts (parity checks)
+//
+// The paper's method: model equation and jump law (Section 5, eq.
+// SDE_splitted_drift_Euler, eq. jump_law, eq. collision_frequency), control
+// and shape functions (eq. control_structure, eq. Gaussian_RBF), cost (eq.
+// discrete_functional, eq. tracking_cost), adjoint (eq.
+// adjoint_eq_approximation), gradient (eq. definition_Gradient).
+#include "fb_launch.hpp"
+#include "jd_device.hpp"
+
+namespace jd {
+
+constexpr uint32_t kFbInitStep = 0xFFFFFFFFu;  // counter word 1 of the initial-state draws
+
+// gamma^n and sqrt(V_n), n = 0..31, passed by value to the table kernel.
+struct FbKs {
+    double v[64];
+};
+
+template <typename Real>
+struct FbArgs {
+    int64_t M;
+    int nblk, N, nx, nv;
+    Real dt, sqb1, sqb2, eta, eps, alpha, hadt, inv2s2, invs2;
+    Real xc0, dxc, vc0, dvc;  // centres x^i = xc0 + i dxc, v^l = vc0 + l dvc
+    Real z0x, z0v, s0x, s0v;
+    int init_kind;
+    uint32_t key0, key1, iter;
+    const PoissonTable* thr;
+    double dt64;
+    int64_t dm0, dcount;  // per-path dumps
+    Real* dX;
+    Real* dlam;
+    double* dcost;
+};
+
+// b(r) = exp(-1/(1 - (eps r)^2)) inside the support, 0 outside, and b'(r) =
+// b(r) (-2 eps^2 r) / (1 - (eps r)^2)^2.  s = 1 - (eps r)^2 is clamped below
+// at 1e-3: there the exact value exp(-1/s) <= e^-1000 is 0 in FP32 and FP64
+// alike, and so is the clamped one, so the clamp is exact and needs no branch.
+__device__ __forceinline__ float bump(float r, float eps) {
+    const float q = eps * r;
+    const float s = fmaxf(fmaf(-q, q, 1.0f), 1e-3f);
+    return __builtin_amdgcn_exp2f(-1.44269504088896340736f * __builtin_amdgcn_rcpf(s));
+}
+__device__ __forceinline__ double bump(double r, double eps) {
+    const double q = eps * r;
+    const double s = fmax(fma(-q, q, 1.0), 1e-3);
+    return exp(-1.0 / s);
+}
+__device__ __forceinline__ float bump_d(float r, float eps, float& d) {
+    const float q = eps * r;
+    const float s = fmaxf(fmaf(-q, q, 1.0f), 1e-3f);
+    const float rs = __builtin_amdgcn_rcpf(s);
+    const float b = __builtin_amdgcn_exp2f(-1.44269504088896340736f * rs);
+    d = b * (-2.0f * eps * eps * r) * rs * rs;
+    return b;
+}
+__device__ __forceinline__ double bump_d(double r, double eps, double& d) {
+    const double q = eps * r;
+    const double s = fmax(fma(-q, q, 1.0), 1e-3);
+    const double rs = 1.0 / s;
+    const double b = exp(-rs);
+    d = b * (-2.0 * eps * eps * r) * rs * rs;
+    return b;
+}
+
+template <typename Real>
+__device__ __forceinline__ Real fb_exp(Real x);
+template <>
+__device__ __forceinline__ float fb_exp<float>(float x) {
+    return __builtin_amdgcn_exp2f(1.44269504088896340736f * x);
+}
+template <>
+__device__ __forceinline__ double fb_exp<double>(double x) {
+    return exp(x);
+}
+
+// Initial state of particle m (counter (m, 0xFFFFFFFF, iter, 0)).
+template <typename Real>
+__device__ __forceinline__ void fb_initial(const FbArgs<Real>& a, uint32_t m, Real& x, Real& v) {
+    uint32_t w[4];
+    philox4x32_10<true>(m, kFbInitStep, a.iter, 0u, a.key0, a.key1, w);
+    if (a.init_kind == 0) {
+        const Real R = bm_radius(w[0], (Real)0);
+        const Real ub = unit_uniform<Real>(w[1]);
+        x = fma(a.s0x, bm_cos(R, ub), a.z0x);
+        v = fma(a.s0v, bm_sin(R, ub), a.z0v);
+    } else {
+        x = fma(a.s0x, fma((Real)2, unit_uniform<Real>(w[0]), (Real)-1), a.z0x);
+        v = fma(a.s0v, fma((Real)2, unit_uniform<Real>(w[1]), (Real)-1), a.z0v);
+    }
+}
+
+// The Keilson-Storer jumps of a step: gamma^n and sqrt(V_n) from the table.
+template <typename Real>
+__device__ __forceinline__ void ks_factors(const Real* __restrict__ ks, int n, Real& gn, Real& sv) {
+    gn = ks[2 * n];
+    sv = ks[2 * n + 1];
+}
+
+// Shape functions of the velocity, b(v - v^l) for l < NVP (entries l >= nv
+// meet zero control coefficients).
+template <typename Real, int NVP>
+__device__ __forceinline__ void shapes_v(const FbArgs<Real>& a, Real v, Real* pv) {
+#pragma unroll
+    for (int l = 0; l < NVP; ++l)
+        pv[l] = bump(v - fma((Real)l, a.dvc, a.vc0), a.eps);
+}
+
+// One forward step of one particle: control, draws, Euler step, jumps.
+// Returns the control u_k.
+template <typename Real, int NVP>
+__device__ __forceinline__ Real fb_step(const FbArgs<Real>& a, const Real* __restrict__ mk,
+                                        const Real* __restrict__ ks, uint32_t m, int k, Real& x,
+                                        Real& v) {
+    Real pv[NVP];
+    shapes_v<Real, NVP>(a, v, pv);
+    Real u = 0;
+#pragma unroll 1
+    for (int i = 0; i < a.nx; ++i) {
+        const Real bx = bump(x - fma((Real)i, a.dxc, a.xc0), a.eps);
+        const Real* rw = mk + i * NVP;
+        Real t = 0;
+#pragma unroll
+        for (int l = 0; l < NVP; ++l)
+            t = fma(rw[l], pv[l], t);
+        u = fma(bx, t, u);
+    }
+    uint32_t w[4];
+    philox4x32_10<true>(m, (uint32_t)k, a.iter, 0u, a.key0, a.key1, w);
+    const Real R = bm_radius(w[0], (Real)0);
+    const Real ub = unit_uniform<Real>(w[1]);
+    const int n = poisson_count(poisson_word(w), a.thr);
+    const Real xn = fma(a.sqb1, bm_cos(R, ub), fma(a.dt, v, x));
+    Real vs = fma(a.sqb2, bm_sin(R, ub), fma(a.dt, fma(-a.eta, x, u), v));
+    if (__builtin_amdgcn_ballot_w64(n != 0)) {
+        Real gn, sv;
+        ks_factors(ks, n, gn, sv);
+        const Real zj = bm_cos(bm_radius(w[2], (Real)0), unit_uniform<Real>(w[3]));
+        const Real vj = fma(sv, zj, gn * vs);
+        vs = n != 0 ? vj : vs;
+    }
+    x = xn;
+    v = vs;
+    return u;
+}
+
+template <typename Real>
+__device__ __forceinline__ void fb_dump(const FbArgs<Real>& a, Real* dst, int k, int64_t m, Real x,
+                                        Real v) {
+    const int64_t p = m - a.dm0;
+    if (dst != nullptr && p >= 0 && p < a.dcount) {
+        dst[(size_t)(k * 2) * a.dcount + p] = x;
+        dst[(size_t)(k * 2 + 1) * a.dcount + p] = v;
+    }
+}
+
+// Tracking cost -exp(-|z - zd|^2/(2 sigJ^2)) and its gradient.
+template <typename Real>
+__device__ __forceinline__ Real track(const FbArgs<Real>& a, Real x, Real v, const Real* zd) {
+    const Real rx = x - zd[0], rv = v - zd[1];
+    return -fb_exp<Real>(-fma(rx, rx, rv * rv) * a.inv2s2);
+}
+template <typename Real>
+__device__ __forceinline__ void track_grad(const FbArgs<Real>& a, Real x, Real v, const Real* zd,
+                                           Real& gx, Real& gv) {
+    const Real rx = x - zd[0], rv = v - zd[1];
+    const Real e = fb_exp<Real>(-fma(rx, rx, rv * rv) * a.inv2s2) * a.invs2;
+    gx = rx * e;
+    gv = rv * e;
+}
+
+// Trajectory: block b owns (N+1) slots x 2 rows x 256 elements.
+template <typename Real>
+__device__ __forceinline__ Real* fb_row(void* traj, int N, int64_t blk) {
+    return (Real*)traj + (size_t)blk * (N + 1) * 2 * kThreads + threadIdx.x;
+}
+
+// ---------------------------------------------------------------------------
+template <typename Real>
+__global__ void __launch_bounds__(kThreads)
+k_fb_table(const double* __restrict__ mu, const double* __restrict__ zd, Real* __restrict__ tab,
+           int N, int nx, int nv, int nvp, size_t off_zd, size_t off_ks, FbKs ks, WsHeader* hdr,
+           int clear_flag, PoissonTable pt) {
+    const int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    const int64_t nmu = (int64_t)N * nx * nvp;
+    if (idx < nmu) {
+        const int64_t k = idx / (nx * nvp);
+        const int rem = (int)(idx - k * nx * nvp);
+        const int i = rem / nvp, l = rem - i * nvp;
+        tab[idx] = l < nv ? (Real)mu[(k * nx + i) * nv + l] : (Real)0;
+    }
+    if (idx < 2 * (int64_t)(N + 1))
+        tab[off_zd + idx] = (Real)zd[idx];
+    if (idx < 64)
+        tab[off_ks + idx] = (Real)ks.v[idx];
+    if (idx == 0) {
+        if (clear_flag)
+            hdr->nonfinite = 0;
+        hdr->poisson = pt;
+    }
+}
+
+template <typename Real, int NVP, bool STORE>
+__global__ void __launch_bounds__(kThreads)
+k_fb_forward(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __restrict__ zd,
+             const Real* __restrict__ ks, void* traj, double* __restrict__ cpart) {
+    __shared__ double sh[kThreads];
+    const int64_t m = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    const bool act = m < a.M;
+    Real x, v;
+    fb_initial(a, (uint32_t)m, x, v);
+    Real* row = STORE ? fb_row<Real>(traj, a.N, blockIdx.x) : nullptr;
+    if (STORE) {
+        __builtin_nontemporal_store(x, row);
+        __builtin_nontemporal_store(v, row + kThreads);
+    }
+    fb_dump(a, a.dX, 0, m, x, v);
+    double acc = 0.0;
+    for (int k = 0; k < a.N; ++k) {
+        const Real u = fb_step<Real, NVP>(a, mu + (size_t)k * a.nx * NVP, ks, (uint32_t)m, k, x, v);
+        acc += (double)(a.hadt * u * u);
+        acc += (double)(a.dt * track(a, x, v, zd + 2 * (k + 1)));
+        if (STORE) {
+            Real* r = row + (size_t)(k + 1) * 2 * kThreads;
+            __builtin_nontemporal_store(x, r);
+            __builtin_nontemporal_store(v, r + kThreads);
+        }
+        fb_dump(a, a.dX, k + 1, m, x, v);
+    }
+    const double C = act ? acc : 0.0;
+    if (a.dcost != nullptr) {
+        const int64_t p = m - a.dm0;
+        if (act && p >= 0 && p < a.dcount)
+            a.dcost[p] = C;
+    }
+    const double s = block_sum(C, sh);
+    if (threadIdx.x == 0)
+        cpart[blockIdx.x] = s;
+}
+
+// Orders LDS accesses of one wavefront (its own writes, read back by other
+// lanes of the same wave).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+}
+
+typedef double fb_d4 __attribute__((ext_vector_type(4)));
+
+template <typename Real, int NVP>
+__global__ void __launch_bounds__(kThreads)
+k_fb_adjoint(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __restrict__ zd,
+             const Real* __restrict__ ks, const void* traj, double* __restrict__ apart) {
+    constexpr int kW = kThreads / 64;   // waves per block
+    constexpr int kS = kFbMaxGrid + 1;  // padded row stride of the transposes
+    __shared__ Real phx[kW][64][kS];
+    __shared__ Real phv[kW][64][kS];
+    __shared__ Real wts[kW][64];
+    __shared__ double cb[kW][kFbMaxGrid * kFbMaxGrid];
+    const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+    const int64_t m = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    const bool act = m < a.M;
+    const int N = a.N, L = a.nx * a.nv;
+    const Real* row = fb_row<Real>(const_cast<void*>(traj), N, blockIdx.x);
+    Real x = __builtin_nontemporal_load(row + (size_t)N * 2 * kThreads);
+    Real v = __builtin_nontemporal_load(row + (size_t)N * 2 * kThreads + kThreads);
+    Real lx, lv;
+    {
+        Real gx, gv;
+        track_grad(a, x, v, zd + 2 * N, gx, gv);
+        lx = a.dt * gx;
+        lv = a.dt * gv;
+    }
+    fb_dump(a, a.dlam, N, m, lx, lv);
+    // the MFMA operands of this lane: A[i = ln % 16][p], B[p][j = ln % 16]
+    const int ii = ln & 15;
+    Real xn = __builtin_nontemporal_load(row + (size_t)(N - 1) * 2 * kThreads);
+    Real vn = __builtin_nontemporal_load(row + (size_t)(N - 1) * 2 * kThreads + kThreads);
+    for (int k = N - 1; k >= 0; --k) {
+        x = xn;
+        v = vn;
+        if (k >= 1) {  // next state, loaded one step ahead
+            xn = __builtin_nontemporal_load(row + (size_t)(k - 1) * 2 * kThreads);
+            vn = __builtin_nontemporal_load(row + (size_t)(k - 1) * 2 * kThreads + kThreads);
+        }
+        Real pv[NVP], dpv[NVP];
+#pragma unroll
+        for (int l = 0; l < NVP; ++l)
+            pv[l] = bump_d(v - fma((Real)l, a.dvc, a.vc0), a.eps, dpv[l]);
+        const Real* mk = mu + (size_t)k * a.nx * NVP;
+        Real u = 0, ux = 0, uv = 0;
+#pragma unroll 1
+        for (int i = 0; i < a.nx; ++i) {
+            Real dbx;
+            const Real bx = bump_d(x - fma((Real)i, a.dxc, a.xc0), a.eps, dbx);
+            const Real* rw = mk + i * NVP;
+            Real t = 0, s = 0;
+#pragma unroll
+            for (int l = 0; l < NVP; ++l) {
+                t = fma(rw[l], pv[l], t);
+                s = fma(rw[l], dpv[l], s);
+            }
+            u = fma(bx, t, u);
+            ux = fma(dbx, t, ux);
+            uv = fma(bx, s, uv);
+            phx[wv][ln][i] = bx;
+        }
+        uint32_t w[4];
+        philox4x32_10<true>((uint32_t)m, (uint32_t)k, a.iter, 0u, a.key0, a.key1, w);
+        const int n = poisson_count(poisson_word(w), a.thr);
+        Real gn = 1;
+        if (n != 0) {
+            Real sv;
+            ks_factors(ks, n, gn, sv);
+        }
+        const Real wk = act ? fma(a.alpha, u, gn * lv) : (Real)0;
+#pragma unroll
+        for (int l = 0; l < NVP; ++l)
+            phv[wv][ln][l] = pv[l];
+        wts[wv][ln] = wk;
+        wave_lds_sync();
+        // G_k[i][j] += sum over the wave's 64 particles of phx_i w * phv_j:
+        // 16 MFMAs of K = 4 particles (lane i + 16 k holds A[i][k] and B[k][i]).
+        fb_d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int p = 4 * q + (ln >> 4);
+            const double av = ii < a.nx ? (double)phx[wv][p][ii] * (double)wts[wv][p] : 0.0;
+            const double bv = ii < NVP ? (double)phv[wv][p][ii] : 0.0;
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+        }
+        // D[i][j] sits in lane j + 16 (i % 4), register i / 4
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            cb[wv][(4 * r + (ln >> 4)) * kFbMaxGrid + ii] = acc[r];
+        __syncthreads();
+        {
+            const int t = threadIdx.x, i = t >> 4, j = t & 15;
+            if (i < a.nx && j < a.nv) {
+                double s = cb[0][t];
+#pragma unroll
+                for (int q = 1; q < kW; ++q)
+                    s += cb[q][t];
+                apart[((size_t)blockIdx.x * N + k) * L + i * a.nv + j] = s;
+            }
+        }
+        __syncthreads();
+        if (k >= 1) {
+            Real gx, gv;
+            track_grad(a, x, v, zd + 2 * k, gx, gv);
+            const Real au = a.alpha * u;
+            const Real nlx = fma(a.dt, fma(au, ux, gx), fma(gn * a.dt * (ux - a.eta), lv, lx));
+            const Real nlv = fma(a.dt, fma(au, uv, gv), fma(gn, fma(a.dt, uv, (Real)1) * lv, a.dt * lx));
+            lx = nlx;
+            lv = nlv;
+            fb_dump(a, a.dlam, k, m, lx, lv);
+        }
+    }
+}
+
+// One thread per gradient entry (k, e): fixed-order sum over the blocks.
+__global__ void __launch_bounds__(kThreads)
+k_fb_finalize_grad(const double* __restrict__ apart, int nblk, int64_t NL, int64_t M,
+                   double* __restrict__ g, WsHeader* hdr) {
+    const int64_t q = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (q >= NL)
+        return;
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b)
+        s += apart[(size_t)b * NL + q];
+    const double gq = s / (double)M;
+    g[q] = gq;
+    if (!isfinite(gq))
+        hdr->nonfinite = 1;
+}
+
+// One block: J = (1/M) sum of the block costs and, with g, dt sum g^2.
+__global__ void __launch_bounds__(kThreads)
+k_fb_finalize_cost(const double* __restrict__ cpart, int nblk, int64_t M, double dt,
+                   const double* __restrict__ g, int64_t NL, double* __restrict__ J_out,
+                   WsHeader* hdr, int slot) {
+    __shared__ double sh[kThreads];
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += kThreads)
+        s += cpart[b];
+    const double csum = block_sum(s, sh);
+    double gg = 0.0;
+    if (g != nullptr) {
+        for (int64_t q = threadIdx.x; q < NL; q += kThreads)
+            gg += g[q] * g[q];
+        gg = block_sum(gg, sh);
+    }
+    if (threadIdx.x == 0) {
+        const double J = csum / (double)M;
+        if (slot == 0) {
+            hdr->J = J;
+            if (g != nullptr)
+                hdr->gnorm2 = dt * gg;
+        } else {
+            hdr->J_trial = J;
+        }
+        if (J_out != nullptr)
+            *J_out = J;
+        if (!isfinite(J) || !isfinite(gg))
+            hdr->nonfinite = 1;
+    }
+}
+
+template <typename Real>
+__global__ void __launch_bounds__(kThreads)
+k_fb_draws(FbArgs<Real> a, PoissonTable pt, int64_t m0, int64_t mc, int k0, int kc,
+           Real* __restrict__ zi, Real* __restrict__ Z, int32_t* __restrict__ counts) {
+    __shared__ PoissonTable tb;
+    if (threadIdx.x < 32)
+        tb.tm1[threadIdx.x] = pt.tm1[threadIdx.x];
+    if (threadIdx.x == 0)
+        tb.jmax = pt.jmax;
+    __syncthreads();
+    a.thr = &tb;
+    const int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (idx >= mc * kc)
+        return;
+    const int64_t p = idx / kc;
+    const int q = (int)(idx - p * kc);
+    const uint32_t m = (uint32_t)(m0 + p);
+    if (q == 0 && zi != nullptr) {
+        Real x, v;
+        fb_initial(a, m, x, v);
+        zi[2 * p] = x;
+        zi[2 * p + 1] = v;
+    }
+    uint32_t w[4];
+    philox4x32_10<false>(m, (uint32_t)(k0 + q), a.iter, 0u, a.key0, a.key1, w);
+    const Real R = bm_radius(w[0], (Real)0);
+    const Real ub = unit_uniform<Real>(w[1]);
+    if (Z != nullptr) {
+        Z[3 * idx] = bm_cos(R, ub);
+        Z[3 * idx + 1] = bm_sin(R, ub);
+        Z[3 * idx + 2] = bm_cos(bm_radius(w[2], (Real)0), unit_uniform<Real>(w[3]));
+    }
+    if (counts != nullptr)
+        counts[idx] = poisson_count(poisson_word(w), a.thr);
+}
+
+// ===========================================================================
+// Launchers.
+
+FbTable fb_table_layout(const FbHost& p) {
+    FbTable t;
+    auto up = [](size_t x) { return (x + 63) / 64 * 64; };
+    t.mu = 0;
+    t.zd = up((size_t)p.N * p.nx * p.nvp);
+    t.ks = t.zd + up((size_t)(p.N + 1) * 2);
+    t.count = t.ks + 64;
+    return t;
+}
+
+template <typename Real>
+static FbArgs<Real> fb_args(const FbHost& p, const HostRun& r) {
+    FbArgs<Real> a;
+    a.M = r.M;
+    a.nblk = r.nblk;
+    a.N = p.N;
+    a.nx = p.nx;
+    a.nv = p.nv;
+    a.dt = (Real)p.dt;
+    a.sqb1 = (Real)(p.b1 * sqrt(p.dt));
+    a.sqb2 = (Real)(p.b2 * sqrt(p.dt));
+    a.eta = (Real)p.eta;
+    a.eps = (Real)p.eps;
+    a.alpha = (Real)p.alpha;
+    a.hadt = (Real)(0.5 * p.alpha * p.dt);
+    a.inv2s2 = (Real)(1.0 / (2.0 * p.sigJ * p.sigJ));
+    a.invs2 = (Real)(1.0 / (p.sigJ * p.sigJ));
+    const double dx = 2.0 * p.xmax / p.nx, dv = 2.0 * p.vmax / p.nv;
+    a.xc0 = (Real)(0.5 * dx - p.xmax);
+    a.dxc = (Real)dx;
+    a.vc0 = (Real)(0.5 * dv - p.vmax);
+    a.dvc = (Real)dv;
+    a.z0x = (Real)p.z0[0];
+    a.z0v = (Real)p.z0[1];
+    a.s0x = (Real)p.s0[0];
+    a.s0v = (Real)p.s0[1];
+    a.init_kind = p.init_kind;
+    a.key0 = (uint32_t)(r.seed & 0xFFFFFFFFu);
+    a.key1 = (uint32_t)(r.seed >> 32);
+    a.iter = r.iter;
+    a.thr = nullptr;
+    a.dt64 = p.dt;
+    a.dm0 = 0;
+    a.dcount = 0;
+    a.dX = nullptr;
+    a.dlam = nullptr;
+    a.dcost = nullptr;
+    if (r.dump != nullptr) {
+        a.dm0 = r.dump->m0;
+        a.dcount = r.dump->count;
+        a.dX = (Real*)r.dump->X;
+        a.dlam = (Real*)r.dump->lam;
+        a.dcost = r.dump->cost;
+    }
+    return a;
+}
+
+static inline unsigned fb_blocks(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
+
+hipError_t fb_launch_table(const FbHost& p, const HostRun& r, const double* mu, void* tab,
+                           WsHeader* hdr, int clear_flag, hipStream_t st) {
+    const FbTable t = fb_table_layout(p);
+    FbKs ks;
+    for (int i = 0; i < 64; ++i)
+        ks.v[i] = p.ks[i];
+    int64_t n = (int64_t)p.N * p.nx * p.nvp;
+    if (n < 2 * (int64_t)(p.N + 1))
+        n = 2 * (int64_t)(p.N + 1);
+    if (n < 64)
+        n = 64;
+    if (r.prec == JD_FP64)
+        hipLaunchKernelGGL(k_fb_table<double>, dim3(fb_blocks(n)), dim3(kThreads), 0, st, mu, p.zd,
+                           (double*)tab, p.N, p.nx, p.nv, p.nvp, t.zd, t.ks, ks, hdr, clear_flag,
+                           p.poisson);
+    else
+        hipLaunchKernelGGL(k_fb_table<float>, dim3(fb_blocks(n)), dim3(kThreads), 0, st, mu, p.zd,
+                           (float*)tab, p.N, p.nx, p.nv, p.nvp, t.zd, t.ks, ks, hdr, clear_flag,
+                           p.poisson);
+    return hipGetLastError();
+}
+
+#define FB_DISPATCH_NVP(nvp, FN)           \
+    do {                                   \
+        switch (nvp) {                     \
+        case 4: FN(4); break;              \
+        case 8: FN(8); break;              \
+        case 12: FN(12); break;            \
+        default: FN(16); break;            \
+        }                                  \
+    } while (0)
+
+template <typename Real>
+static hipError_t fb_forward_t(const FbHost& p, const HostRun& r, const void* tab, void* traj,
+                               double* cpart, const WsHeader* hdr, hipStream_t st) {
+    const FbTable t = fb_table_layout(p);
+    FbArgs<Real> a = fb_args<Real>(p, r);
+    a.thr = &hdr->poisson;
+    const Real* tb = (const Real*)tab;
+#define FB_FWD(NVP)                                                                              \
+    do {                                                                                         \
+        if (traj != nullptr)                                                                     \
+            hipLaunchKernelGGL((k_fb_forward<Real, NVP, true>), dim3(r.nblk), dim3(kThreads), 0, \
+                               st, a, tb + t.mu, tb + t.zd, tb + t.ks, traj, cpart);             \
+        else                                                                                     \
+            hipLaunchKernelGGL((k_fb_forward<Real, NVP, false>), dim3(r.nblk), dim3(kThreads), 0, \
+                               st, a, tb + t.mu, tb + t.zd, tb + t.ks, traj, cpart);             \
+    } while (0)
+    FB_DISPATCH_NVP(p.nvp, FB_FWD);
+#undef FB_FWD
+    return hipGetLastError();
+}
+
+hipError_t fb_launch_forward(const FbHost& p, const HostRun& r, const void* tab, void* traj,
+                             double* cpart, const WsHeader* hdr, hipStream_t st) {
+    return r.prec == JD_FP64 ? fb_forward_t<double>(p, r, tab, traj, cpart, hdr, st)
+                             : fb_forward_t<float>(p, r, tab, traj, cpart, hdr, st);
+}
+
+template <typename Real>
+static hipError_t fb_adjoint_t(const FbHost& p, const HostRun& r, const void* tab, const void* traj,
+                               double* apart, const WsHeader* hdr, hipStream_t st) {
+    const FbTable t = fb_table_layout(p);
+    FbArgs<Real> a = fb_args<Real>(p, r);
+    a.thr = &hdr->poisson;
+    const Real* tb = (const Real*)tab;
+#define FB_ADJ(NVP)                                                                               \
+    hipLaunchKernelGGL((k_fb_adjoint<Real, NVP>), dim3(r.nblk), dim3(kThreads), 0, st, a,        \
+                       tb + t.mu, tb + t.zd, tb + t.ks, traj, apart)
+    FB_DISPATCH_NVP(p.nvp, FB_ADJ);
+#undef FB_ADJ
+    return hipGetLastError();
+}
+
+hipError_t fb_launch_adjoint(const FbHost& p, const HostRun& r, const void* tab, const void* traj,
+                             double* apart, const WsHeader* hdr, hipStream_t st) {
+    return r.prec == JD_FP64 ? fb_adjoint_t<double>(p, r, tab, traj, apart, hdr, st)
+                             : fb_adjoint_t<float>(p, r, tab, traj, apart, hdr, st);
+}
+
+hipError_t fb_launch_finalize_grad(const FbHost& p, const HostRun& r, const double* apart,
+                                   double* g, WsHeader* hdr, hipStream_t st) {
+    const int64_t NL = (int64_t)p.N * p.L;
+    hipLaunchKernelGGL(k_fb_finalize_grad, dim3(fb_blocks(NL)), dim3(kThreads), 0, st, apart,
+                       r.nblk, NL, r.M, g, hdr);
+    return hipGetLastError();
+}
+
+hipError_t fb_launch_finalize_cost(const FbHost& p, const HostRun& r, const double* cpart,
+                                   const double* g, double* J_out, WsHeader* hdr, int slot,
+                                   hipStream_t st) {
+    hipLaunchKernelGGL(k_fb_finalize_cost, dim3(1), dim3(kThreads), 0, st, cpart, r.nblk, r.M,
+                       p.dt, g, (int64_t)p.N * p.L, J_out, hdr, slot);
+    return hipGetLastError();
+}
+
+hipError_t fb_launch_draws(const FbHost& p, const HostRun& r, int64_t m0, int64_t mc, int k0,
+                           int kc, void* z_init, void* Z, int32_t* counts, hipStream_t st) {
+    const unsigned nb = fb_blocks(mc * kc);
+    if (r.prec == JD_FP64)
+        hipLaunchKernelGGL(k_fb_draws<double>, dim3(nb), dim3(kThreads), 0, st,
+                           fb_args<double>(p, r), p.poisson, m0, mc, k0, kc, (double*)z_init,
+                           (double*)Z, counts);
+    else
+        hipLaunchKernelGGL(k_fb_draws<float>, dim3(nb), dim3(kThreads), 0, st,
+                           fb_args<float>(p, r), p.poisson, m0, mc, k0, kc, (float*)z_init,
+                           (float*)Z, counts);
+    return hipGetLastError();
+}
+
+}  // namespace jd

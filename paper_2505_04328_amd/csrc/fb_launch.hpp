@@ -1,0 +1,46 @@
+// Host-side form of the feedback-model problem (include/jd_feedback.h) and
+// the typed launchers of its kernels (fb_kernels.hip).
+#pragma once
+
+#include <stdint.h>
+
+#include "jd_launch.hpp"
+
+namespace jd {
+
+constexpr int kFbMaxGrid = 16;  // nx, nv <= 16: one 16 x 16 matrix-core tile per step
+
+struct FbHost {
+    int N, nx, nv, nvp, L;  // nvp = nv rounded up to 4 (zero-padded control rows)
+    double T, dt, eta, b1, b2, gamma, beta, rate;
+    double xmax, vmax, eps, alpha, sigJ;
+    int init_kind;
+    double z0[2], s0[2];
+    const double* zd;     // device (N+1) x 2
+    double ks[64];        // gamma^n and sqrt(V_n) for n = 0..31
+    uint64_t thr[32];     // Poisson(rate dt) thresholds
+    PoissonTable poisson;
+};
+
+// Per-step table in the path precision: mu rows (N x nx x nvp, zero-padded),
+// targets ((N+1) x 2) and the Keilson-Storer factors (32 x 2).
+struct FbTable {
+    size_t mu, zd, ks, count;  // element offsets and total elements
+};
+FbTable fb_table_layout(const FbHost& p);
+
+hipError_t fb_launch_table(const FbHost& p, const HostRun& r, const double* mu, void* tab,
+                           WsHeader* hdr, int clear_flag, hipStream_t st);
+hipError_t fb_launch_forward(const FbHost& p, const HostRun& r, const void* tab, void* traj,
+                             double* cpart, const WsHeader* hdr, hipStream_t st);
+hipError_t fb_launch_adjoint(const FbHost& p, const HostRun& r, const void* tab, const void* traj,
+                             double* apart, const WsHeader* hdr, hipStream_t st);
+hipError_t fb_launch_finalize_grad(const FbHost& p, const HostRun& r, const double* apart,
+                                   double* g, WsHeader* hdr, hipStream_t st);
+hipError_t fb_launch_finalize_cost(const FbHost& p, const HostRun& r, const double* cpart,
+                                   const double* g, double* J_out, WsHeader* hdr, int slot,
+                                   hipStream_t st);
+hipError_t fb_launch_draws(const FbHost& p, const HostRun& r, int64_t m0, int64_t mc, int k0,
+                           int kc, void* z_init, void* Z, int32_t* counts, hipStream_t st);
+
+}  // namespace jd

@@ -43,6 +43,17 @@ void poisson_thresholds(double mu, uint64_t* thr) {
     thr[31] = (uint64_t)1 << 32;
 }
 
+PoissonTable poisson_table(const uint64_t* thr) {
+    PoissonTable t;
+    t.jmax = 31;
+    for (int j = 0; j < 32; ++j) {
+        t.tm1[j] = (uint32_t)(thr[j] - 1);  // thr_j >= thr_0 >= 1 since rate*dt <= 2
+        if (thr[j] == ((uint64_t)1 << 32) && t.jmax == 31)
+            t.jmax = j;
+    }
+    return t;
+}
+
 int prepare(const jd_problem* prob, const jd_run* run, HostProblem& p, HostRun& r) {
     if (!prob || !run)
         return JD_EINVAL;
@@ -105,12 +116,7 @@ int prepare(const jd_problem* prob, const jd_run* run, HostProblem& p, HostRun& 
         p.B[q] = prob->B[q];
     p.xd = prob->xd;
     poisson_thresholds(prob->lambda * dt, p.thr);
-    p.poisson.jmax = 31;
-    for (int j = 0; j < 32; ++j) {
-        p.poisson.tm1[j] = (uint32_t)(p.thr[j] - 1);  // thr_j >= thr_0 >= 1 since rate*dt <= 2
-        if (p.thr[j] == ((uint64_t)1 << 32) && p.poisson.jmax == 31)
-            p.poisson.jmax = j;
-    }
+    p.poisson = poisson_table(p.thr);
 
     r.M = run->M;
     r.ldm = (int64_t)round_up((size_t)run->M, kBlock);

@@ -1,0 +1,326 @@
+// C-ABI layer of libjd for the paper's model problem (include/jd_feedback.h):
+// validation, the host-side problem form (cell-centre grid, Keilson-Storer
+// factors, Poisson thresholds), workspace layout, launch order per entry point
+// and the host loop of the gradient iteration.  No device memory is
+// allocated; every buffer comes from the caller.
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include "../../include/jd_feedback.h"
+#include "fb_launch.hpp"
+#include "jd_host.hpp"
+
+using namespace jd;
+using namespace jd::host;
+
+namespace {
+
+bool finite(double x) { return isfinite(x) != 0; }
+
+int fb_prepare(const jd_fb_problem* prob, const jd_run* run, FbHost& p, HostRun& r) {
+    if (!prob || !run)
+        return JD_EINVAL;
+    const jd_fb_problem& q = *prob;
+    if (q.N < 1 || q.nx < 1 || q.nv < 1 || q.nx > kFbMaxGrid || q.nv > kFbMaxGrid)
+        return JD_EINVAL;
+    if (!(q.T > 0.0) || !finite(q.T) || !(q.beta > 0.0) || !finite(q.beta) || !(q.eps > 0.0) ||
+        !finite(q.eps) || !(q.sigJ > 0.0) || !finite(q.sigJ) || !(q.xmax > 0.0) ||
+        !finite(q.xmax) || !(q.vmax > 0.0) || !finite(q.vmax))
+        return JD_EINVAL;
+    if (!finite(q.eta) || !(q.b1 >= 0.0) || !finite(q.b1) || !(q.b2 >= 0.0) || !finite(q.b2) ||
+        !(q.alpha >= 0.0) || !finite(q.alpha) || !(q.gamma >= -1.0) || !(q.gamma <= 1.0))
+        return JD_EINVAL;
+    if (q.init_kind != JD_FB_INIT_GAUSS && q.init_kind != JD_FB_INIT_UNIFORM)
+        return JD_EINVAL;
+    for (int c = 0; c < 2; ++c)
+        if (!finite(q.z0[c]) || !(q.s0[c] >= 0.0) || !finite(q.s0[c]))
+            return JD_EINVAL;
+    if (!q.zd)
+        return JD_EINVAL;
+    const double dt = q.T / (double)q.N;
+    const double rate = sqrt(q.beta / 3.141592653589793238462643383280);
+    if (rate * dt > 2.0)
+        return JD_EINVAL;
+    if (run->M < 1 || run->M > kMaxPaths)
+        return JD_EINVAL;
+    if (run->precision != JD_FP32 && run->precision != JD_FP64)
+        return JD_EINVAL;
+    if (run->mode == JD_RECOMPUTE)
+        return JD_EUNSUPPORTED;
+    if (run->mode != JD_STORE)
+        return JD_EINVAL;
+    if (run->dump) {
+        const jd_dump* dp = run->dump;
+        if (dp->m0 < 0 || dp->count < 0 || dp->m0 + dp->count > run->M)
+            return JD_EINVAL;
+    }
+
+    memset(&p, 0, sizeof(p));
+    p.N = q.N;
+    p.nx = q.nx;
+    p.nv = q.nv;
+    p.nvp = (q.nv + 3) / 4 * 4;
+    p.L = q.nx * q.nv;
+    p.T = q.T;
+    p.dt = dt;
+    p.eta = q.eta;
+    p.b1 = q.b1;
+    p.b2 = q.b2;
+    p.gamma = q.gamma;
+    p.beta = q.beta;
+    p.rate = rate;
+    p.xmax = q.xmax;
+    p.vmax = q.vmax;
+    p.eps = q.eps;
+    p.alpha = q.alpha;
+    p.sigJ = q.sigJ;
+    p.init_kind = q.init_kind;
+    for (int c = 0; c < 2; ++c) {
+        p.z0[c] = q.z0[c];
+        p.s0[c] = q.s0[c];
+    }
+    p.zd = q.zd;
+    // n jumps v <- gamma v + N(0, 1/(2 beta)) composed: gamma^n v + N(0, V_n),
+    // V_n = (1/(2 beta)) sum_{i<n} gamma^{2i}
+    double g = 1.0, s = 0.0;
+    for (int n = 0; n < 32; ++n) {
+        p.ks[2 * n] = g;
+        p.ks[2 * n + 1] = sqrt(s / (2.0 * q.beta));
+        s += g * g;
+        g *= q.gamma;
+    }
+    poisson_thresholds(rate * dt, p.thr);
+    p.poisson = poisson_table(p.thr);
+
+    r.M = run->M;
+    r.ldm = (int64_t)round_up((size_t)run->M, kBlock);
+    r.seed = run->seed;
+    r.iter = run->iter;
+    r.prec = run->precision;
+    r.mode = JD_STORE;
+    r.K = 0;
+    r.nblk = (int)((run->M + kBlock - 1) / kBlock);
+    r.dump = run->dump;
+    return JD_OK;
+}
+
+struct FbLayout {
+    size_t hdr, tab, cpart, apart, gbuf, ut, total;
+};
+
+FbLayout fb_layout(const FbHost& p, const HostRun& r) {
+    FbLayout L;
+    size_t off = 0;
+    L.hdr = off;
+    off += round_up(sizeof(WsHeader), kAlign);
+    L.tab = off;
+    off += round_up(fb_table_layout(p).count * real_size(r.prec), kAlign);
+    L.cpart = off;
+    off += round_up((size_t)r.nblk * sizeof(double), kAlign);
+    L.apart = off;
+    off += round_up((size_t)r.nblk * p.N * p.L * sizeof(double), kAlign);
+    L.gbuf = off;
+    off += round_up((size_t)p.N * p.L * sizeof(double), kAlign);
+    L.ut = off;
+    off += round_up((size_t)p.N * p.L * sizeof(double), kAlign);
+    L.total = off + kAlign;
+    return L;
+}
+
+size_t fb_traj_bytes(const FbHost& p, const HostRun& r) {
+    return (size_t)(p.N + 1) * 2 * (size_t)r.ldm * real_size(r.prec);
+}
+
+struct FbWs {
+    WsHeader* hdr;
+    void* tab;
+    double* cpart;
+    double* apart;
+    double* gbuf;
+    double* ut;
+};
+
+int fb_bind(const FbHost& p, const HostRun& r, void* ws, size_t ws_bytes, FbWs& w) {
+    if (!ws)
+        return JD_EINVAL;
+    const FbLayout L = fb_layout(p, r);
+    if (ws_bytes < L.total)
+        return JD_EWORKSPACE;
+    char* base = (char*)round_up((size_t)(uintptr_t)ws, kAlign);
+    w.hdr = (WsHeader*)(base + L.hdr);
+    w.tab = base + L.tab;
+    w.cpart = (double*)(base + L.cpart);
+    w.apart = (double*)(base + L.apart);
+    w.gbuf = (double*)(base + L.gbuf);
+    w.ut = (double*)(base + L.ut);
+    return JD_OK;
+}
+
+int fb_enqueue_cost_grad(const FbHost& p, const HostRun& r, const double* mu, double* J, double* g,
+                         void* traj, const FbWs& w, hipStream_t st) {
+    JD_TRY(fb_launch_table(p, r, mu, w.tab, w.hdr, 1, st));
+    JD_TRY(fb_launch_forward(p, r, w.tab, traj, w.cpart, w.hdr, st));
+    JD_TRY(fb_launch_adjoint(p, r, w.tab, traj, w.apart, w.hdr, st));
+    JD_TRY(fb_launch_finalize_grad(p, r, w.apart, g, w.hdr, st));
+    JD_TRY(fb_launch_finalize_cost(p, r, w.cpart, g, J, w.hdr, 0, st));
+    return JD_OK;
+}
+
+int fb_enqueue_trial(const FbHost& p, const HostRun& r, double* mu, const jd_opt& opt, double zeta,
+                     const FbWs& w, hipStream_t st) {
+    const int nl = p.N * p.L;
+    JD_TRY(launch_trial(mu, w.gbuf, zeta, w.ut, nl, st));
+    JD_TRY(fb_launch_table(p, r, w.ut, w.tab, w.hdr, 0, st));
+    JD_TRY(fb_launch_forward(p, r, w.tab, nullptr, w.cpart, w.hdr, st));
+    JD_TRY(fb_launch_finalize_cost(p, r, w.cpart, nullptr, nullptr, w.hdr, 1, st));
+    JD_TRY(launch_armijo(w.hdr, mu, w.ut, nl, opt.c_armijo, zeta, p.dt, st));
+    return JD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t jd_fb_workspace_bytes(const jd_fb_problem* prob, const jd_run* run) {
+    FbHost p;
+    HostRun r;
+    if (fb_prepare(prob, run, p, r) != JD_OK)
+        return 0;
+    return fb_layout(p, r).total;
+}
+
+size_t jd_fb_traj_bytes(const jd_fb_problem* prob, const jd_run* run) {
+    FbHost p;
+    HostRun r;
+    if (fb_prepare(prob, run, p, r) != JD_OK)
+        return 0;
+    return fb_traj_bytes(p, r);
+}
+
+int jd_fb_forward(const jd_fb_problem* prob, const jd_run* run, const double* mu, void* traj,
+                  double* J, void* ws, size_t ws_bytes, hipStream_t stream) {
+    FbHost p;
+    HostRun r;
+    int rc = fb_prepare(prob, run, p, r);
+    if (rc)
+        return rc;
+    if (!mu || !J || (traj && !aligned(traj, real_size(r.prec))))
+        return JD_EINVAL;
+    FbWs w;
+    if ((rc = fb_bind(p, r, ws, ws_bytes, w)))
+        return rc;
+    JD_TRY(fb_launch_table(p, r, mu, w.tab, w.hdr, 1, stream));
+    JD_TRY(fb_launch_forward(p, r, w.tab, traj, w.cpart, w.hdr, stream));
+    JD_TRY(fb_launch_finalize_cost(p, r, w.cpart, nullptr, J, w.hdr, 0, stream));
+    return JD_OK;
+}
+
+int jd_fb_adjoint(const jd_fb_problem* prob, const jd_run* run, const double* mu, const void* traj,
+                  double* grad, void* ws, size_t ws_bytes, hipStream_t stream) {
+    FbHost p;
+    HostRun r;
+    int rc = fb_prepare(prob, run, p, r);
+    if (rc)
+        return rc;
+    if (!mu || !traj || !grad || !aligned(traj, real_size(r.prec)))
+        return JD_EINVAL;
+    FbWs w;
+    if ((rc = fb_bind(p, r, ws, ws_bytes, w)))
+        return rc;
+    JD_TRY(fb_launch_table(p, r, mu, w.tab, w.hdr, 1, stream));
+    JD_TRY(fb_launch_adjoint(p, r, w.tab, traj, w.apart, w.hdr, stream));
+    JD_TRY(fb_launch_finalize_grad(p, r, w.apart, grad, w.hdr, stream));
+    return JD_OK;
+}
+
+int jd_fb_cost_grad(const jd_fb_problem* prob, const jd_run* run, const double* mu, double* J,
+                    double* grad, void* traj, void* ws, size_t ws_bytes, hipStream_t stream) {
+    FbHost p;
+    HostRun r;
+    int rc = fb_prepare(prob, run, p, r);
+    if (rc)
+        return rc;
+    if (!mu || !J || !grad || !traj || !aligned(traj, real_size(r.prec)))
+        return JD_EINVAL;
+    FbWs w;
+    if ((rc = fb_bind(p, r, ws, ws_bytes, w)))
+        return rc;
+    return fb_enqueue_cost_grad(p, r, mu, J, grad, traj, w, stream);
+}
+
+int jd_fb_optimize(const jd_fb_problem* prob, const jd_run* run, const jd_opt* opt, double* mu,
+                   jd_iter_log* log, int32_t* iters_done, void* traj, void* ws, size_t ws_bytes,
+                   hipStream_t stream) {
+    FbHost p;
+    HostRun r;
+    int rc = fb_prepare(prob, run, p, r);
+    if (rc)
+        return rc;
+    if (!mu || !traj || !aligned(traj, real_size(r.prec)) || validate_opt(opt))
+        return JD_EINVAL;
+    FbWs w;
+    if ((rc = fb_bind(p, r, ws, ws_bytes, w)))
+        return rc;
+    if (iters_done)
+        *iters_done = 0;
+    JD_TRY(launch_clear_flag(w.hdr, stream));
+    const uint32_t iter0 = r.iter;
+    for (int n = 0; n < opt->n_max; ++n) {
+        r.iter = iter0 + (uint32_t)n;
+        if ((rc = fb_enqueue_cost_grad(p, r, mu, nullptr, w.gbuf, traj, w, stream)))
+            return rc;
+        double zeta = opt->zeta0;
+        WsHeader h;
+        int bt = 0;
+        bool accepted = false;
+        for (; bt < opt->max_backtracks; ++bt) {
+            if ((rc = fb_enqueue_trial(p, r, mu, *opt, zeta, w, stream)))
+                return rc;
+            JD_TRY(hipMemcpyAsync(&h, w.hdr, sizeof(h), hipMemcpyDeviceToHost, stream));
+            JD_TRY(hipStreamSynchronize(stream));
+            if (h.nonfinite)
+                return JD_ENONFINITE;
+            if (h.accept) {
+                accepted = true;
+                break;
+            }
+            zeta *= opt->rho;
+        }
+        if (!accepted)
+            return JD_ELINESEARCH;
+        const double E = sqrt(h.E2);
+        if (log) {
+            log[n].iter = r.iter;
+            log[n].backtracks = bt;
+            log[n].J = h.J;
+            log[n].gnorm = sqrt(h.gnorm2);
+            log[n].zeta = zeta;
+            log[n].J_new = h.J_trial;
+            log[n].E = E;
+        }
+        if (iters_done)
+            *iters_done = n + 1;
+        if (E <= opt->tol)
+            break;
+    }
+    return JD_OK;
+}
+
+int jd_fb_draws(const jd_fb_problem* prob, const jd_run* run, int64_t m0, int64_t mc, int32_t k0,
+                int32_t kc, void* z_init, void* Z, int32_t* counts, hipStream_t stream) {
+    FbHost p;
+    HostRun r;
+    int rc = fb_prepare(prob, run, p, r);
+    if (rc)
+        return rc;
+    if (m0 < 0 || mc < 0 || k0 < 0 || kc < 0 || m0 + mc > ((int64_t)1 << 32) ||
+        (int64_t)k0 + kc > ((int64_t)1 << 31) - 1 || mc * (int64_t)kc > ((int64_t)1 << 40))
+        return JD_EINVAL;
+    if (mc == 0 || kc == 0)
+        return JD_OK;
+    JD_TRY(fb_launch_draws(p, r, m0, mc, k0, kc, z_init, Z, counts, stream));
+    return JD_OK;
+}
+
+}  // extern "C"

@@ -22,6 +22,11 @@ constexpr int64_t kMaxPaths = (int64_t)1 << 31;
 
 size_t round_up(size_t x, size_t a);
 
+// Poisson(mu) inverse-CDF thresholds against a 32-bit word (32 entries).
+void poisson_thresholds(double mu, uint64_t* thr);
+// The 32-bit thresholds minus one and the last index below 2^32, for the kernels.
+PoissonTable poisson_table(const uint64_t* thr);
+
 // Validates the problem and run and fills the padded host-side form.
 int prepare(const jd_problem* prob, const jd_run* run, HostProblem& p, HostRun& r);
 int validate_opt(const jd_opt* opt);

@@ -14,7 +14,7 @@ from paper_2505_04328_amd import binding as B
 from paper_2505_04328_amd import workloads as wl
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADERS = [os.path.join(ROOT, "include", h) for h in ("jd.h", "jd_server.h")]
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("jd.h", "jd_server.h", "jd_feedback.h")]
 
 
 def _gpu_visible() -> bool:
@@ -55,7 +55,7 @@ def test_every_declared_symbol_is_exported(L):
     exported = {ln.split()[-1] for ln in out.splitlines() if " T " in ln}
     missing = [n for n in names if n not in exported]
     assert not missing, missing
-    assert set(B.EXPORTED) | set(SERVER) == set(names)
+    assert set(B.EXPORTED) | set(SERVER) | set(B.EXPORTED_FB) == set(names)
 
 
 SERVER = ["jd_server_request_bytes", "jd_server_create", "jd_server_submit",
@@ -219,3 +219,62 @@ def test_server_request_bytes(L):
     # control + target + trajectory (100 steps x 3 comps x 1024 columns FP32) + workspace
     assert nb >= 2 * 100 * 3 * 8 + 100 * 3 * 1024 * 4
     assert S.request_bytes(p, 1000, mode="recompute", K=10) < nb
+
+
+# ---------------------------------------------------------------- feedback model
+class _FbDummy:
+    """A feedback problem whose z_d pointer is a fake non-null address."""
+
+    def __init__(self, p):
+        self.p = p
+        self.st = B.jd_fb_problem(p.N, p.nx, p.nv, p.T, p.eta, p.b1, p.b2, p.gamma, p.beta,
+                                  p.xmax, p.vmax, p.eps, p.alpha, p.sigJ, p.init_kind,
+                                  (C.c_double * 2)(*p.z0), (C.c_double * 2)(*p.s0), 0x1000)
+
+
+def test_fb_workspace_and_traj_sizes(L):
+    p = wl.feedback_config("f4").problem
+    pr = _FbDummy(p)
+    M = 1 << 20
+    run = B.make_run(M, precision="fp32")
+    tb = L.jd_fb_traj_bytes(C.byref(pr.st), C.byref(run))
+    assert tb == (p.N + 1) * 2 * M * 4
+    ws = L.jd_fb_workspace_bytes(C.byref(pr.st), C.byref(run))
+    assert ws >= (M // 256) * p.N * p.L * 8  # per-block FP64 gradient partials
+    run7 = B.make_run(7, precision="fp64")
+    assert L.jd_fb_traj_bytes(C.byref(pr.st), C.byref(run7)) == (p.N + 1) * 2 * 256 * 8
+    rec = B.make_run(1000, precision="fp32", mode="recompute", K=10)
+    assert L.jd_fb_traj_bytes(C.byref(pr.st), C.byref(rec)) == 0
+
+
+@host_only
+def test_fb_invalid_arguments_rejected_before_launch(L):
+    run = B.make_run(1000)
+    fake = C.c_void_p(0x2000)
+    ws = 1 << 30
+
+    def call(**kw):
+        q = _FbDummy(wl.feedback_problem(N=20, T=2.0))
+        for k, v in kw.items():
+            setattr(q.st, k, v)
+        return L.jd_fb_forward(C.byref(q.st), C.byref(run), fake, fake, fake, fake, ws, None)
+
+    for kw in (dict(N=0), dict(nx=0), dict(nx=17), dict(nv=17), dict(T=0.0), dict(beta=0.0),
+               dict(eps=-1.0), dict(sigJ=0.0), dict(gamma=1.5), dict(b1=-0.1), dict(alpha=-1.0),
+               dict(init_kind=3), dict(zd=None), dict(xmax=0.0), dict(T=float("nan"))):
+        assert call(**kw) == B.JD_EINVAL, kw
+    # rate * dt > 2
+    assert call(beta=1e4, N=2, T=2.0) == B.JD_EINVAL
+    pr = _FbDummy(wl.feedback_problem(N=20, T=2.0))
+    P = C.byref(pr.st)
+    assert L.jd_fb_forward(P, C.byref(run), None, fake, fake, fake, ws, None) == B.JD_EINVAL
+    assert L.jd_fb_forward(P, C.byref(run), fake, fake, fake, fake, 100, None) == B.JD_EWORKSPACE
+    assert L.jd_fb_cost_grad(P, C.byref(run), fake, fake, fake, None, fake, ws, None) == B.JD_EINVAL
+    assert L.jd_fb_adjoint(P, C.byref(run), fake, None, fake, fake, ws, None) == B.JD_EINVAL
+    rec = B.make_run(1000, mode="recompute", K=5)
+    assert L.jd_fb_forward(P, C.byref(rec), fake, fake, fake, fake, ws, None) == B.JD_EUNSUPPORTED
+    bad_opt = B.jd_opt(3, 0, 0.0, 1.0, 0.5, 1e-4)
+    assert L.jd_fb_optimize(P, C.byref(run), C.byref(bad_opt), fake, None, None, fake, fake, ws,
+                            None) == B.JD_EINVAL
+    assert L.jd_fb_draws(P, C.byref(run), -1, 4, 0, 4, fake, fake, fake, None) == B.JD_EINVAL
+    assert L.jd_fb_draws(P, C.byref(run), 0, 0, 0, 4, fake, fake, fake, None) == B.JD_OK

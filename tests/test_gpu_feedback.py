@@ -1,0 +1,158 @@
+"""GPU parity of the paper's model problem (include/jd_feedback.h) against the
+FP64 oracle (oracle/fb_oracle.c) on the same counter-based draws.
+
+Draws: jump counts bit-exact, normals and initial states to rounding.  Sweeps:
+per-particle states z_0..z_N, adjoints lam_1..lam_N and path costs to the
+per-path tolerance, J and the gradient (the matrix-core reduction) to the J / g
+tolerances of parity_util, over shapes that cover a ragged last block, padded
+shape-function rows (nv = 5 -> 8, 10 -> 12), the full 16 x 16 grid, a negative
+gamma, both initial laws and both path precisions; edge shapes; and the
+gradient iteration replayed against the oracle's."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import ref
+from paper_2505_04328_amd import binding as B
+from paper_2505_04328_amd import workloads as wl
+
+from parity_util import TOL, gpu_device, norm_err, per_path_error, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    return gpu_device()
+
+
+def _track(N, T):
+    t = np.arange(N + 1) * (T / N)
+    return np.stack([0.4 * np.cos(2 * t), -0.3 * np.sin(t)], axis=1)
+
+
+CASES = {
+    # name: (problem kwargs, M, seed, mu scale)
+    "paper_f1": (dict(), 2000, 1, 1.0),
+    "small_6x6": (dict(N=20, T=2.0, nx=6, nv=6, alpha=0.1, sigJ=0.7, gamma=0.8), 1500, 3, 1.0),
+    "grid_3x5_uniform": (dict(N=30, T=3.0, nx=3, nv=5, init="uniform", b1=0.2, b2=0.3), 700, 5, 2.0),
+    "grid_16x16": (dict(N=12, T=1.2, nx=16, nv=16, eps=0.8, alpha=0.05), 600, 7, 0.5),
+    "gamma_negative": (dict(N=25, T=2.5, gamma=-0.6, beta=4.0, sigJ=1.2), 900, 9, 1.0),
+}
+
+
+def _problem(name):
+    kw, M, seed, scale = CASES[name]
+    kw = dict(kw)
+    N, T = kw.get("N", 50), kw.get("T", 5.0)
+    kw.setdefault("zd", _track(N, T))
+    return wl.feedback_problem(**kw), M, seed, scale
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_fb_draws_match_oracle(dev, precision):
+    p, M, seed, _ = _problem("small_6x6")
+    say("fb draws", precision)
+    eng = B.FbEngine(p, M=300, seed=seed, precision=precision, device=dev)
+    zi, Z, n = eng.draws(m0=5, mc=40, k0=3, kc=12, it=2)
+    zi, Z, n = zi.double().cpu().numpy(), Z.double().cpu().numpy(), n.cpu().numpy()
+    tol = 2e-6 if precision == "fp32" else 1e-14
+    for pi in range(40):
+        zr = ref.fb_initial(p, seed, 5 + pi, 2)
+        assert np.max(np.abs(zi[pi] - zr) / np.maximum(1.0, np.abs(zr))) <= tol
+        for q in range(12):
+            Zr, nr = ref.fb_step_draws(p, seed, 5 + pi, 3 + q, 2)
+            assert n[pi, q] == nr
+            assert np.max(np.abs(Z[pi, q] - Zr) / np.maximum(1.0, np.abs(Zr))) <= tol
+    assert n.sum() > 0
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("name", list(CASES))
+def test_fb_cost_grad_and_paths(dev, name, precision):
+    p, M, seed, scale = _problem(name)
+    say(name, precision, f"M={M} N={p.N} nx={p.nx} nv={p.nv}")
+    mu = wl.random_feedback_control(p, 4, scale)
+    it = 3
+    z, lam, _, _, C = ref.fb_paths(p, seed, it, 0, M, mu)
+    J_ref, g_ref = ref.fb_cost_grad(p, M, seed, it, mu)
+    eng = B.FbEngine(p, M=M, seed=seed, precision=precision, device=dev)
+    dp, d = eng.path_dump(0, M)
+    J = eng.forward(mu, it=it, dump=dp)
+    eng.adjoint(mu, it=it, dump=dp)
+    Jc, gc = eng.cost_grad(mu, it=it)
+    import torch
+    torch.cuda.synchronize()
+    assert eng.check_finite()
+    tol = TOL[precision]
+    zg = np.transpose(d["X"].double().cpu().numpy(), (2, 0, 1))
+    lg = np.transpose(d["lam"].double().cpu().numpy(), (2, 0, 1))
+    e_z = per_path_error(zg, z)
+    e_l = per_path_error(lg[:, 1:], lam[:, 1:])
+    e_c = float(np.max(np.abs(d["cost"].cpu().numpy() - C) / (np.abs(C) + np.sqrt(np.mean(C * C)))))
+    e_J, e_J2 = rel_err(float(J), J_ref), rel_err(float(Jc), J_ref)
+    e_g = norm_err(gc.cpu().numpy(), g_ref)
+    say(f"   errors: z {e_z:.2e} lam {e_l:.2e} C {e_c:.2e} J {e_J:.2e} g {e_g:.2e}")
+    assert e_z <= tol["path"]
+    assert e_l <= tol["path"]
+    assert e_c <= tol["path"]
+    assert e_J <= tol["J"] and e_J2 <= tol["J"]
+    assert e_g <= tol["g"]
+    traj = np.transpose(eng.trajectory().double().cpu().numpy(), (2, 0, 1))
+    assert per_path_error(traj, z) <= tol["path"]
+
+
+EDGE = [
+    # (label, N, nx, nv, M)
+    ("one particle", 10, 4, 4, 1),
+    ("one block minus one", 8, 5, 3, 255),
+    ("one block plus one", 8, 2, 7, 257),
+    ("one step", 1, 6, 6, 300),
+    ("one shape function", 15, 1, 1, 400),
+]
+
+
+@pytest.mark.parametrize("label,N,nx,nv,M", EDGE)
+def test_fb_edge_shapes(dev, label, N, nx, nv, M):
+    say("fb edge", label)
+    p = wl.feedback_problem(N=N, T=0.1 * N, nx=nx, nv=nv, zd=_track(N, 0.1 * N), alpha=0.2)
+    mu = wl.random_feedback_control(p, 6, 1.0)
+    eng = B.FbEngine(p, M=M, seed=13, precision="fp32", device=dev)
+    J, g = eng.cost_grad(mu, it=1)
+    J_ref, g_ref = ref.fb_cost_grad(p, M, 13, 1, mu)
+    assert rel_err(float(J), J_ref) <= TOL["fp32"]["J"]
+    assert norm_err(g.cpu().numpy(), g_ref) <= TOL["fp32"]["g"]
+
+
+def test_fb_zero_control_gradient_is_tracking_only(dev):
+    """mu = 0 and alpha = 0: the gradient is E[phi(z_k) gamma^n lam^v_{k+1}]
+    alone; with the targets out of reach the cost and the gradient are 0."""
+    p = wl.feedback_problem(N=10, T=1.0, zd=np.full((11, 2), 1e3), alpha=0.0)
+    eng = B.FbEngine(p, M=512, seed=2, precision="fp32", device=dev)
+    J, g = eng.cost_grad(np.zeros((p.N, p.L)), it=0)
+    assert float(J) == 0.0
+    assert float(g.abs().max()) == 0.0
+
+
+def test_fb_optimize_matches_oracle(dev):
+    """FP64: the gradient iteration takes the oracle's steps (same Armijo
+    decisions, same control up to rounding)."""
+    p, M, seed, _ = _problem("small_6x6")
+    mu0 = wl.random_feedback_control(p, 9, 0.5)
+    say("fb optimize fp64", M)
+    mu_o, logs_o, n_o = ref.fb_optimize(p, M, seed, 0, mu0, n_max=4, zeta0=8.0)
+    eng = B.FbEngine(p, M=M, seed=seed, precision="fp64", device=dev)
+    import torch
+    mu = torch.tensor(mu0, dtype=torch.float64, device=dev)
+    _, logs = eng.optimize(mu, n_max=4, zeta0=8.0)
+    assert n_o == 4 and len(logs) == 4
+    for a, b in zip(logs, logs_o):
+        assert a["zeta"] == b["zeta"] and a["backtracks"] == b["backtracks"]
+        assert abs(a["J"] - b["J"]) <= 1e-12 * abs(b["J"])
+    assert norm_err(mu.cpu().numpy(), mu_o) <= 1e-11
