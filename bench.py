@@ -52,6 +52,20 @@ FWD_SLOTS_PER_PATH_STEP = 115
 # (3 products + 1), dt (1), the masked deposit into the reduction tile (1), and
 # the amortised FP64 tile reduction (16 converts + adds per 16 steps, 4 slots)
 ADJ_SLOTS_PER_PATH_STEP = 12
+# The paper's model problem (include/jd_feedback.h, f4: 2^20 particles, 500
+# steps, nx = nv = 10 shape functions), algorithmic slots per particle-step:
+# forward  20 bumps (difference, scale, 1 - q^2, clamp, reciprocal 4, scale,
+#          exp2 4 = 13 each) 260, control sum_i b_x,i sum_l mu_il b_v,l 110,
+#          Philox 77 + Poisson 4, Box-Muller both halves 27, Euler 6, FP64 cost
+#          (control and tracking terms, one exp) 18                      = 502
+# adjoint  20 bumps with derivatives (3 more products each: 16) 320, control,
+#          u_x and u_v (two dot products per row) 230, jump count regenerated
+#          (Philox 77 + Poisson 4), gradient weight, adjoint update and the
+#          tracking gradient (one exp) 24                                 = 655
+# plus, on the FP64 matrix cores, 2 nx nv = 200 flops per particle-step for the
+# gradient's outer products.
+FB_FWD_SLOTS = 502
+FB_ADJ_SLOTS = 655
 HBM_PEAK = 8.0e12  # B/s
 METRIC = "forward+adjoint path-steps/s (FP32 vs FP64 GPU) at 1e-6 rel grad err; p50/p99"
 
@@ -66,6 +80,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-feedback", action="store_true",
+                    help="skip the paper's model problem (feedback control) section")
+    ap.add_argument("--fb-sample-paths", type=int, default=1 << 15)
     ap.add_argument("--cpu-sample-paths", type=int, default=1 << 19)
     ap.add_argument("--only", choices=["all", "fp32_store", "kernels"], default="all",
                     help="kernels: time jd_forward / jd_adjoint only (for profiler runs)")
@@ -149,6 +166,76 @@ def profiled_traffic(kernel: str):
 
 def percentile(xs, q):
     return float(np.percentile(np.asarray(xs), q))
+
+
+def feedback_section(args, time_calls, dev):
+    """The paper's own model problem (RBF feedback control, Keilson-Storer
+    jumps) at 2^20 particles x 500 steps: per-call times of jd_fb_cost_grad
+    (FP32 and FP64 paths), the forward and adjoint kernels alone, the slot
+    roofline, and the oracle on a bounded sample."""
+    import torch
+    from paper_2505_04328_amd import binding as B
+    from paper_2505_04328_amd import workloads as wl
+    w = wl.feedback_config("f4")
+    p = w.problem
+    mu = torch.tensor(wl.random_feedback_control(p, 4, 0.5), device=dev)
+    out = {"workload": "f4: paper's model problem (Section 5/6), 2^20 particles, 500 steps, "
+                       "10 x 10 bump shape functions, Keilson-Storer jumps beta 10 gamma 0.9",
+           "M": w.M, "N": p.N, "L": p.L}
+    ps = w.M * p.N
+    res = {}
+    for prec in ("fp32", "fp64"):
+        e = B.FbEngine(p, M=w.M, seed=w.seed, precision=prec, device=dev)
+        for it in range(args.warmup):
+            e.cost_grad(mu, it=it)
+        cg = time_calls(lambda: e.cost_grad(mu, it=5), args.steps)
+        fw = time_calls(lambda: e.forward(mu, it=5), max(5, args.steps // 2))
+        ad = time_calls(lambda: e.adjoint(mu, it=5), max(5, args.steps // 2))
+        J, g = e.cost_grad(mu, it=0)
+        res[prec] = (float(J), g.cpu().numpy())
+        out[prec] = {"p50_ms": percentile(cg, 50), "p99_ms": percentile(cg, 99),
+                     "path_steps_per_s_p50": ps / (percentile(cg, 50) * 1e-3),
+                     "forward_ms": float(np.mean(fw)), "adjoint_ms": float(np.mean(ad))}
+        del e
+        torch.cuda.empty_cache()
+    t_f, t_a = out["fp32"]["forward_ms"] * 1e-3, out["fp32"]["adjoint_ms"] * 1e-3
+    t_cg = out["fp32"]["p50_ms"] * 1e-3
+    out["roofline"] = {
+        "bound": "alu", "kernel": "k_fb_adjoint<float,12,2>",
+        "achieved": FB_ADJ_SLOTS * ps / t_a / 1e12, "peak": VALU_PEAK_SLOTS / 1e12,
+        "unit": "TOP/s (full-rate VALU lane-op slots)",
+        "frac": FB_ADJ_SLOTS * ps / t_a / VALU_PEAK_SLOTS, "traffic": None,
+        "slots_per_path_step": FB_ADJ_SLOTS, "kernel_ms": t_a * 1e3}
+    out["forward_roofline"] = {"kernel": "k_fb_forward<float,12,true>", "bound": "alu",
+                               "frac": FB_FWD_SLOTS * ps / t_f / VALU_PEAK_SLOTS,
+                               "slots_per_path_step": FB_FWD_SLOTS}
+    out["step_frac"] = (FB_FWD_SLOTS + FB_ADJ_SLOTS) * ps / t_cg / VALU_PEAK_SLOTS
+    J64, g64 = res["fp64"]
+    J32, g32 = res["fp32"]
+    out["fp32_vs_fp64_full_size"] = {"J_rel": abs(J32 - J64) / abs(J64),
+                                     "g_rel": float(np.linalg.norm(g32 - g64) / np.linalg.norm(g64))}
+    if not args.no_cpu_baseline:
+        from oracle import ref
+        Ms = args.fb_sample_paths
+        nth = ref.default_threads()
+        log(f"feedback oracle: {Ms} particles x {p.N} steps on {nth} threads")
+        t0 = time.perf_counter()
+        Jo, go = ref.fb_cost_grad(p, Ms, w.seed, 0, mu.cpu().numpy(), nthreads=nth)
+        tc = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": Ms * p.N / tc, "unit": "path-steps/s", "cores": nth,
+                               "kind": "oracle",
+                               "sample": f"f4 with M={Ms} of {w.M} particles, all {p.N} steps, "
+                                         f"forward+adjoint+reductions, FP64, {tc:.1f} s wall"}
+        errs = {}
+        for prec in ("fp32", "fp64"):
+            es = B.FbEngine(p, M=Ms, seed=w.seed, precision=prec, device=dev)
+            Js, gs = es.cost_grad(mu, it=0)
+            errs[prec] = {"J_rel": abs(float(Js) - Jo) / abs(Jo),
+                          "g_rel": float(np.linalg.norm(gs.cpu().numpy() - go) / np.linalg.norm(go))}
+            del es
+        out["oracle_error_on_sample"] = errs
+        log(f"feedback oracle errors: {errs}")
+    return out
 
 
 def main():
@@ -314,6 +401,11 @@ def main():
             del es
         log(f"oracle errors: {sample_err}")
 
+    feedback = None
+    if not args.no_feedback and args.only == "all":
+        log("feedback model (f4)")
+        feedback = feedback_section(args, time_calls, dev)
+
     fp32s = res["fp32_store_ms"]
     line = {
         "metric": METRIC,
@@ -338,6 +430,7 @@ def main():
         "cpu_baseline": cpu,
         "forms": forms,
         "oracle_error_on_sample": sample_err,
+        "feedback": feedback,
     }
     print(json.dumps(line), flush=True)
 

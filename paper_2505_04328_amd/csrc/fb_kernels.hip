@@ -260,114 +260,147 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 typedef double fb_d4 __attribute__((ext_vector_type(4)));
 
-template <typename Real, int NVP>
+// The adjoint state of one particle between steps.
+template <typename Real>
+struct FbAdj {
+    Real x, v;    // z_k (current step)
+    Real xn, vn;  // z_{k-1}, loaded one step ahead
+    Real lx, lv;  // lam_{k+1} on entry to step k
+};
+
+// Backward sweep.  Each lane carries G particles (groups blockIdx.x G + j of
+// 256, j < G) through the steps together; at step k each particle in turn puts
+// its shape functions and weight w = alpha u + gamma^n lam^v into the wave's
+// LDS transpose and the wave adds its 64 particles' outer products
+// phi_x(x) w phi_v(v)^T to four independent matrix-core accumulators (16
+// MFMAs of K = 4 particles).  The four waves' sums are then combined in a
+// fixed order into one FP64 partial per block and step.
+template <typename Real, int NVP, int G>
 __global__ void __launch_bounds__(kThreads)
 k_fb_adjoint(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __restrict__ zd,
              const Real* __restrict__ ks, const void* traj, double* __restrict__ apart) {
     constexpr int kW = kThreads / 64;   // waves per block
     constexpr int kS = kFbMaxGrid + 1;  // padded row stride of the transposes
-    __shared__ Real phx[kW][64][kS];
+    static_assert(sizeof(Real) * 64 * kS >= sizeof(double) * kFbMaxGrid * kFbMaxGrid,
+                  "a wave's transpose buffer must hold its 16 x 16 FP64 tile");
+    __shared__ Real phx[kW][64][kS];  // after the MFMAs: the wave's FP64 tile
     __shared__ Real phv[kW][64][kS];
     __shared__ Real wts[kW][64];
-    __shared__ double cb[kW][kFbMaxGrid * kFbMaxGrid];
     const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
-    const int64_t m = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    const bool act = m < a.M;
     const int N = a.N, L = a.nx * a.nv;
-    const Real* row = fb_row<Real>(const_cast<void*>(traj), N, blockIdx.x);
-    Real x = __builtin_nontemporal_load(row + (size_t)N * 2 * kThreads);
-    Real v = __builtin_nontemporal_load(row + (size_t)N * 2 * kThreads + kThreads);
-    Real lx, lv;
-    {
+    const int ii = ln & 15;  // this lane's row of A and column of B
+    FbAdj<Real> s[G];
+    const Real* row[G];
+    bool act[G];
+    int64_t m[G];
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+        const int64_t g = (int64_t)blockIdx.x * G + j;
+        m[j] = g * kThreads + threadIdx.x;
+        act[j] = m[j] < a.M && g < a.nblk;
+        row[j] = fb_row<Real>(const_cast<void*>(traj), N, g < a.nblk ? g : a.nblk - 1);
+        s[j].x = __builtin_nontemporal_load(row[j] + (size_t)N * 2 * kThreads);
+        s[j].v = __builtin_nontemporal_load(row[j] + (size_t)N * 2 * kThreads + kThreads);
         Real gx, gv;
-        track_grad(a, x, v, zd + 2 * N, gx, gv);
-        lx = a.dt * gx;
-        lv = a.dt * gv;
+        track_grad(a, s[j].x, s[j].v, zd + 2 * N, gx, gv);
+        s[j].lx = a.dt * gx;
+        s[j].lv = a.dt * gv;
+        if (act[j])
+            fb_dump(a, a.dlam, N, m[j], s[j].lx, s[j].lv);
+        s[j].xn = __builtin_nontemporal_load(row[j] + (size_t)(N - 1) * 2 * kThreads);
+        s[j].vn = __builtin_nontemporal_load(row[j] + (size_t)(N - 1) * 2 * kThreads + kThreads);
     }
-    fb_dump(a, a.dlam, N, m, lx, lv);
-    // the MFMA operands of this lane: A[i = ln % 16][p], B[p][j = ln % 16]
-    const int ii = ln & 15;
-    Real xn = __builtin_nontemporal_load(row + (size_t)(N - 1) * 2 * kThreads);
-    Real vn = __builtin_nontemporal_load(row + (size_t)(N - 1) * 2 * kThreads + kThreads);
     for (int k = N - 1; k >= 0; --k) {
-        x = xn;
-        v = vn;
-        if (k >= 1) {  // next state, loaded one step ahead
-            xn = __builtin_nontemporal_load(row + (size_t)(k - 1) * 2 * kThreads);
-            vn = __builtin_nontemporal_load(row + (size_t)(k - 1) * 2 * kThreads + kThreads);
-        }
-        Real pv[NVP], dpv[NVP];
-#pragma unroll
-        for (int l = 0; l < NVP; ++l)
-            pv[l] = bump_d(v - fma((Real)l, a.dvc, a.vc0), a.eps, dpv[l]);
         const Real* mk = mu + (size_t)k * a.nx * NVP;
-        Real u = 0, ux = 0, uv = 0;
-#pragma unroll 1
-        for (int i = 0; i < a.nx; ++i) {
-            Real dbx;
-            const Real bx = bump_d(x - fma((Real)i, a.dxc, a.xc0), a.eps, dbx);
-            const Real* rw = mk + i * NVP;
-            Real t = 0, s = 0;
+        fb_d4 acc[4];
 #pragma unroll
-            for (int l = 0; l < NVP; ++l) {
-                t = fma(rw[l], pv[l], t);
-                s = fma(rw[l], dpv[l], s);
+        for (int c = 0; c < 4; ++c)
+            acc[c] = fb_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
+            FbAdj<Real>& st = s[j];
+            st.x = st.xn;
+            st.v = st.vn;
+            if (k >= 1) {
+                st.xn = __builtin_nontemporal_load(row[j] + (size_t)(k - 1) * 2 * kThreads);
+                st.vn = __builtin_nontemporal_load(row[j] + (size_t)(k - 1) * 2 * kThreads + kThreads);
             }
-            u = fma(bx, t, u);
-            ux = fma(dbx, t, ux);
-            uv = fma(bx, s, uv);
-            phx[wv][ln][i] = bx;
-        }
-        uint32_t w[4];
-        philox4x32_10<true>((uint32_t)m, (uint32_t)k, a.iter, 0u, a.key0, a.key1, w);
-        const int n = poisson_count(poisson_word(w), a.thr);
-        Real gn = 1;
-        if (n != 0) {
-            Real sv;
-            ks_factors(ks, n, gn, sv);
-        }
-        const Real wk = act ? fma(a.alpha, u, gn * lv) : (Real)0;
+            Real pv[NVP], dpv[NVP];
 #pragma unroll
-        for (int l = 0; l < NVP; ++l)
-            phv[wv][ln][l] = pv[l];
-        wts[wv][ln] = wk;
-        wave_lds_sync();
-        // G_k[i][j] += sum over the wave's 64 particles of phx_i w * phv_j:
-        // 16 MFMAs of K = 4 particles (lane i + 16 k holds A[i][k] and B[k][i]).
-        fb_d4 acc = {0.0, 0.0, 0.0, 0.0};
+            for (int l = 0; l < NVP; ++l)
+                pv[l] = bump_d(st.v - fma((Real)l, a.dvc, a.vc0), a.eps, dpv[l]);
+            Real u = 0, ux = 0, uv = 0;
+#pragma unroll 1
+            for (int i = 0; i < a.nx; ++i) {
+                Real dbx;
+                const Real bx = bump_d(st.x - fma((Real)i, a.dxc, a.xc0), a.eps, dbx);
+                const Real* rw = mk + i * NVP;
+                Real t = 0, sv = 0;
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int p = 4 * q + (ln >> 4);
-            const double av = ii < a.nx ? (double)phx[wv][p][ii] * (double)wts[wv][p] : 0.0;
-            const double bv = ii < NVP ? (double)phv[wv][p][ii] : 0.0;
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+                for (int l = 0; l < NVP; ++l) {
+                    t = fma(rw[l], pv[l], t);
+                    sv = fma(rw[l], dpv[l], sv);
+                }
+                u = fma(bx, t, u);
+                ux = fma(dbx, t, ux);
+                uv = fma(bx, sv, uv);
+                phx[wv][ln][i] = bx;
+            }
+            uint32_t w[4];
+            philox4x32_10<true>((uint32_t)m[j], (uint32_t)k, a.iter, 0u, a.key0, a.key1, w);
+            const int n = poisson_count(poisson_word(w), a.thr);
+            Real gn = 1;
+            if (n != 0) {
+                Real svn;
+                ks_factors(ks, n, gn, svn);
+            }
+            const Real wk = act[j] ? fma(a.alpha, u, gn * st.lv) : (Real)0;
+#pragma unroll
+            for (int l = 0; l < NVP; ++l)
+                phv[wv][ln][l] = pv[l];
+            wts[wv][ln] = wk;
+            wave_lds_sync();
+            // A[i][kk] = phi_x_i(p) w_p, B[kk][jj] = phi_v_jj(p) for the
+            // particle p = 4q + kk (lane i + 16 kk supplies both)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int p = 4 * q + (ln >> 4);
+                const double av = ii < a.nx ? (double)phx[wv][p][ii] * (double)wts[wv][p] : 0.0;
+                const double bv = ii < NVP ? (double)phv[wv][p][ii] : 0.0;
+                acc[q & 3] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[q & 3], 0, 0, 0);
+            }
+            wave_lds_sync();
+            if (k >= 1) {
+                Real gx, gv;
+                track_grad(a, st.x, st.v, zd + 2 * k, gx, gv);
+                const Real au = a.alpha * u;
+                const Real nlx = fma(a.dt, fma(au, ux, gx), fma(gn * a.dt * (ux - a.eta), st.lv, st.lx));
+                const Real nlv = fma(a.dt, fma(au, uv, gv),
+                                     fma(gn, fma(a.dt, uv, (Real)1) * st.lv, a.dt * st.lx));
+                st.lx = nlx;
+                st.lv = nlv;
+                if (act[j])
+                    fb_dump(a, a.dlam, k, m[j], st.lx, st.lv);
+            }
         }
-        // D[i][j] sits in lane j + 16 (i % 4), register i / 4
+        // D[i][jj] sits in lane jj + 16 (i % 4), register i / 4; the wave's
+        // tile goes into its own transpose buffer (its reads are done)
+        double* cb = (double*)&phx[wv][0][0];
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-            cb[wv][(4 * r + (ln >> 4)) * kFbMaxGrid + ii] = acc[r];
+            cb[(4 * r + (ln >> 4)) * kFbMaxGrid + ii] = (acc[0][r] + acc[1][r]) + (acc[2][r] + acc[3][r]);
         __syncthreads();
         {
-            const int t = threadIdx.x, i = t >> 4, j = t & 15;
-            if (i < a.nx && j < a.nv) {
-                double s = cb[0][t];
+            const int t = threadIdx.x, i = t >> 4, jj = t & 15;
+            if (i < a.nx && jj < a.nv) {
+                double sum = ((const double*)&phx[0][0][0])[t];
 #pragma unroll
                 for (int q = 1; q < kW; ++q)
-                    s += cb[q][t];
-                apart[((size_t)blockIdx.x * N + k) * L + i * a.nv + j] = s;
+                    sum += ((const double*)&phx[q][0][0])[t];
+                apart[((size_t)blockIdx.x * N + k) * L + i * a.nv + jj] = sum;
             }
         }
         __syncthreads();
-        if (k >= 1) {
-            Real gx, gv;
-            track_grad(a, x, v, zd + 2 * k, gx, gv);
-            const Real au = a.alpha * u;
-            const Real nlx = fma(a.dt, fma(au, ux, gx), fma(gn * a.dt * (ux - a.eta), lv, lx));
-            const Real nlv = fma(a.dt, fma(au, uv, gv), fma(gn, fma(a.dt, uv, (Real)1) * lv, a.dt * lx));
-            lx = nlx;
-            lv = nlv;
-            fb_dump(a, a.dlam, k, m, lx, lv);
-        }
     }
 }
 
@@ -576,6 +609,12 @@ hipError_t fb_launch_forward(const FbHost& p, const HostRun& r, const void* tab,
                              : fb_forward_t<float>(p, r, tab, traj, cpart, hdr, st);
 }
 
+// Particles per lane of the adjoint: two 256-particle groups per block halve
+// the per-step gradient partials (one per block) once at least 1024 blocks
+// remain.  Measured on 2^20 x 500 (FP32): adjoint 16.2 / 15.5 / 18.3 ms with
+// 1 / 2 / 4 groups (four groups need 115 VGPRs: 3 waves per SIMD).
+int fb_adjoint_groups(int nblk) { return nblk >= 2048 ? 2 : 1; }
+
 template <typename Real>
 static hipError_t fb_adjoint_t(const FbHost& p, const HostRun& r, const void* tab, const void* traj,
                                double* apart, const WsHeader* hdr, hipStream_t st) {
@@ -583,9 +622,20 @@ static hipError_t fb_adjoint_t(const FbHost& p, const HostRun& r, const void* ta
     FbArgs<Real> a = fb_args<Real>(p, r);
     a.thr = &hdr->poisson;
     const Real* tb = (const Real*)tab;
+    const int G = fb_adjoint_groups(r.nblk);
+    const unsigned nb = (unsigned)((r.nblk + G - 1) / G);
 #define FB_ADJ(NVP)                                                                               \
-    hipLaunchKernelGGL((k_fb_adjoint<Real, NVP>), dim3(r.nblk), dim3(kThreads), 0, st, a,        \
-                       tb + t.mu, tb + t.zd, tb + t.ks, traj, apart)
+    do {                                                                                          \
+        if (G == 4)                                                                               \
+            hipLaunchKernelGGL((k_fb_adjoint<Real, NVP, 4>), dim3(nb), dim3(kThreads), 0, st, a,  \
+                               tb + t.mu, tb + t.zd, tb + t.ks, traj, apart);                     \
+        else if (G == 2)                                                                          \
+            hipLaunchKernelGGL((k_fb_adjoint<Real, NVP, 2>), dim3(nb), dim3(kThreads), 0, st, a,  \
+                               tb + t.mu, tb + t.zd, tb + t.ks, traj, apart);                     \
+        else                                                                                      \
+            hipLaunchKernelGGL((k_fb_adjoint<Real, NVP, 1>), dim3(nb), dim3(kThreads), 0, st, a,  \
+                               tb + t.mu, tb + t.zd, tb + t.ks, traj, apart);                     \
+    } while (0)
     FB_DISPATCH_NVP(p.nvp, FB_ADJ);
 #undef FB_ADJ
     return hipGetLastError();
@@ -600,8 +650,10 @@ hipError_t fb_launch_adjoint(const FbHost& p, const HostRun& r, const void* tab,
 hipError_t fb_launch_finalize_grad(const FbHost& p, const HostRun& r, const double* apart,
                                    double* g, WsHeader* hdr, hipStream_t st) {
     const int64_t NL = (int64_t)p.N * p.L;
+    const int G = fb_adjoint_groups(r.nblk);
+    const int nparts = (r.nblk + G - 1) / G;
     hipLaunchKernelGGL(k_fb_finalize_grad, dim3(fb_blocks(NL)), dim3(kThreads), 0, st, apart,
-                       r.nblk, NL, r.M, g, hdr);
+                       nparts, NL, r.M, g, hdr);
     return hipGetLastError();
 }
 

@@ -4,10 +4,12 @@ Calls only the FP64 oracle (oracle/) and the seeded workload generators: for
 the c2, c3 and c4 workloads at their full path counts, iteration word 0, seed 1
 and u = 0, it records J, ||g||_L2, the L2 projections <g, delta_i> on 16 fixed
 random directions (numpy default_rng(2), L2-normalised) and 64 sampled entries
-of g; for c2 also the whole gradient.  Run from the repository root:
+of g; for c2 also the whole gradient.  For the paper's model problem at its
+measured size (f4: 2^20 particles, 500 steps) the same record is written at the
+control mu = random_feedback_control(p, 4, 0.5).  Run from the repository root:
 
-    python tests/golden/make_full_size.py            # all three (minutes on 8 cores)
-    python tests/golden/make_full_size.py c2
+    python tests/golden/make_full_size.py            # c2, c3, c4 (minutes on 8 cores)
+    python tests/golden/make_full_size.py c2 f4
 """
 from __future__ import annotations
 
@@ -32,8 +34,43 @@ def sample_index(p, count=64, seed=5):
     return rng.integers(0, p.N * p.d, count)
 
 
+def fb_directions(p, count=16, seed=2):
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        d = rng.normal(size=(p.N, p.L))
+        out.append(d / np.sqrt(p.dt * np.sum(d * d)))
+    return out
+
+
+def feedback(name):
+    w = wl.feedback_config(name)
+    p = w.problem
+    t0 = time.time()
+    mu = wl.random_feedback_control(p, 4, 0.5)
+    J, g = ref.fb_cost_grad(p, w.M, w.seed, 0, mu)
+    proj = [float(p.dt * np.sum(g * dl)) for dl in fb_directions(p)]
+    idx = np.random.default_rng(5).integers(0, p.N * p.L, 64)
+    rec = {
+        "config": name, "M": w.M, "N": p.N, "L": p.L, "seed": w.seed, "iter": 0,
+        "mu": "random_feedback_control(p, 4, 0.5)", "J": J,
+        "gnorm_L2": float(np.sqrt(p.dt * np.sum(g * g))), "projections": proj,
+        "sample_index": [int(i) for i in idx], "sample_g": [float(g.reshape(-1)[i]) for i in idx],
+        "oracle_seconds": time.time() - t0,
+    }
+    path = os.path.join(HERE, f"full_{name}_it0.json")
+    with open(path, "w") as f:
+        f.write("# FP64 oracle, written by tests/golden/make_full_size.py\n")
+        json.dump(rec, f, indent=None)
+        f.write("\n")
+    print(f"{name}: J = {J:.15g}  ({time.time() - t0:.1f} s) -> {path}", flush=True)
+
+
 def main(names):
     for name in names:
+        if name.startswith("f"):
+            feedback(name)
+            continue
         w = wl.config(name)
         p = w.problem
         t0 = time.time()

@@ -156,3 +156,66 @@ def test_fb_optimize_matches_oracle(dev):
         assert a["zeta"] == b["zeta"] and a["backtracks"] == b["backtracks"]
         assert abs(a["J"] - b["J"]) <= 1e-12 * abs(b["J"])
     assert norm_err(mu.cpu().numpy(), mu_o) <= 1e-11
+
+
+def test_fb_full_size_f4(dev):
+    """The measured size (2^20 particles x 500 steps, FP32 paths) in the launch
+    configuration the benchmark times: J, ||g||, 16 projections and 64 sampled
+    entries of g against the oracle values of tests/golden/full_f4_it0.json
+    (written by tests/golden/make_full_size.py); per-particle states, adjoints
+    and costs of the first and last 4096 particles against the oracle here."""
+    import json
+    import os
+    import torch
+    with open(os.path.join(os.path.dirname(__file__), "golden", "full_f4_it0.json")) as f:
+        gd = json.loads("".join(ln for ln in f if not ln.startswith("#")))
+    w = wl.feedback_config("f4")
+    p = w.problem
+    say("fb full size f4", w.M, p.N)
+    mu = wl.random_feedback_control(p, 4, 0.5)
+    eng = B.FbEngine(p, M=w.M, seed=w.seed, precision="fp32", device=dev)
+    J, g = eng.cost_grad(mu, it=0)
+    J, g = float(J), g.cpu().numpy()
+    tol = TOL["fp32"]
+    say(f"   J {J:.12g} vs {gd['J']:.12g}")
+    assert rel_err(J, gd["J"]) <= tol["J"]
+    gn = np.sqrt(p.dt * np.sum(g * g))
+    assert rel_err(gn, gd["gnorm_L2"]) <= tol["g"]
+    rng = np.random.default_rng(2)
+    for pr in gd["projections"]:
+        d = rng.normal(size=(p.N, p.L))
+        d = d / np.sqrt(p.dt * np.sum(d * d))
+        assert abs(p.dt * np.sum(g * d) - pr) <= tol["g"] * gd["gnorm_L2"]
+    flat = g.reshape(-1)
+    for i, v in zip(gd["sample_index"], gd["sample_g"]):
+        assert abs(flat[i] - v) <= tol["g"] * gd["gnorm_L2"]
+    for m0 in (0, w.M - 4096):
+        dp, dd = eng.path_dump(m0, 4096)
+        eng.forward(mu, it=0, dump=dp)
+        eng.adjoint(mu, it=0, dump=dp)
+        torch.cuda.synchronize()
+        z, lam, _, _, C = ref.fb_paths(p, w.seed, 0, m0, 4096, mu)
+        zg = np.transpose(dd["X"].double().cpu().numpy(), (2, 0, 1))
+        lg = np.transpose(dd["lam"].double().cpu().numpy(), (2, 0, 1))
+        e_z, e_l = per_path_error(zg, z), per_path_error(lg[:, 1:], lam[:, 1:])
+        say(f"   paths {m0}+4096: z {e_z:.2e} lam {e_l:.2e}")
+        assert e_z <= tol["path"] and e_l <= tol["path"]
+        assert np.max(np.abs(dd["cost"].cpu().numpy() - C) / (np.abs(C) + np.sqrt(np.mean(C * C)))) <= tol["path"]
+
+
+# 2^19 + 100: 2049 groups, the last block holds a ragged group (100 particles)
+# and an empty one; 2^19 + 356: 2050 groups, the last block a full and a ragged one
+@pytest.mark.parametrize("M", [(1 << 19) + 100, (1 << 19) + 356])
+def test_fb_several_particles_per_lane(dev, M):
+    """M >= 2^19 runs the adjoint with 2 groups of 256 particles per block, the
+    last block holding a ragged group and an empty one, or two groups, the
+    second ragged: J and g against the oracle at the full M (short horizon)."""
+    p = wl.feedback_problem(N=8, T=0.8, zd=_track(8, 0.8), alpha=0.1)
+    mu = wl.random_feedback_control(p, 3, 1.0)
+    say("fb groups per block, M =", M)
+    eng = B.FbEngine(p, M=M, seed=17, precision="fp32", device=dev)
+    J, g = eng.cost_grad(mu, it=2)
+    J_ref, g_ref = ref.fb_cost_grad(p, M, 17, 2, mu)
+    e_J, e_g = rel_err(float(J), J_ref), norm_err(g.cpu().numpy(), g_ref)
+    say(f"   J {e_J:.2e} g {e_g:.2e}")
+    assert e_J <= TOL["fp32"]["J"] and e_g <= TOL["fp32"]["g"]
