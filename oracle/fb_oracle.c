@@ -103,6 +103,22 @@ void fb_step_draws(uint64_t seed, uint32_t m, uint32_t k, uint32_t iter, const u
     *n = or_poisson_count(P, thr);
 }
 
+/* Surrogate state: zd_k + sqrt(var(t_k)) (R cos, R sin) from the Box-Muller
+ * pair of words 0 and 1 of block (m, k, iter, 1). */
+void fb_surrogate_state(const fb_problem* pb, uint64_t seed, uint32_t m, uint32_t k, uint32_t iter,
+                        double z[2])
+{
+    uint32_t key[2], W[4];
+    uint32_t ctr[4] = {m, k, iter, 1u};
+    key_of(seed, key);
+    or_philox4x32_10(ctr, key, W);
+    double R = sqrt(-2.0 * log(or_uniform(W[0])));
+    double th = FB_TWO_PI * or_uniform(W[1]);
+    double t = (double)k * (pb->T / (double)pb->N);
+    z[0] = pb->zd[2 * k] + sqrt(pb->svar0[0] + pb->svar1[0] * t) * R * cos(th);
+    z[1] = pb->zd[2 * k + 1] + sqrt(pb->svar0[1] + pb->svar1[1] * t) * R * sin(th);
+}
+
 static int check_problem(const fb_problem* pb)
 {
     if (!pb || pb->N < 1 || pb->nx < 1 || pb->nv < 1 || pb->nx > 16 || pb->nv > 16)
@@ -113,6 +129,9 @@ static int check_problem(const fb_problem* pb)
         return -1;
     if (sqrt(pb->beta / FB_PI) * (pb->T / (double)pb->N) > 2.0)
         return -1;
+    for (int c = 0; c < 2; ++c)
+        if (!(pb->svar0[c] >= 0.0) || !(pb->svar1[c] >= 0.0))
+            return -1;
     return 0;
 }
 
@@ -379,6 +398,115 @@ int fb_cost_grad(const fb_problem* pb, int64_t M, uint64_t seed, uint32_t iter,
                 t += gsum[(size_t)c * nl + q];
             g[q] = t / (double)M;
         }
+    }
+    free(csum);
+    free(gsum);
+    return 0;
+}
+
+/* The surrogate adjoint of path m (forward jump counts in w->n): the recursion
+ * of path_adjoint at the states zs_k; adds gamma^{n_k} ls^v_{k+1} phi(zs_k) to
+ * G.  Writes the surrogate adjoint into w->lam. */
+static void path_adjoint_surrogate(const fb_problem* pb, const double* mu, uint64_t seed,
+                                   uint32_t iter, uint32_t m, work* w, double* G)
+{
+    const int N = pb->N, L = pb->nx * pb->nv;
+    const double dt = pb->T / (double)N;
+    double zs[2], gz[2];
+    fb_surrogate_state(pb, seed, m, (uint32_t)N, iter, zs);
+    track_grad(pb, zs, pb->zd + 2 * N, gz);
+    double lx = dt * gz[0], lv = dt * gz[1];
+    w->lam[2 * N] = lx;
+    w->lam[2 * N + 1] = lv;
+    for (int k = N - 1; k >= 0; --k) {
+        const double* mk = mu + (size_t)k * L;
+        fb_surrogate_state(pb, seed, m, (uint32_t)k, iter, zs);
+        shapes(pb, zs, w->px, w->pv, w->dpx, w->dpv);
+        double gn, Vn;
+        ks_factors(pb, w->n[k], &gn, &Vn);
+        for (int i = 0; i < pb->nx; ++i)
+            for (int l = 0; l < pb->nv; ++l)
+                G[(size_t)k * L + i * pb->nv + l] += w->px[i] * w->pv[l] * (gn * lv);
+        if (k == 0)
+            break;
+        double u = control(pb, mk, w->px, w->pv);
+        double ux = control(pb, mk, w->dpx, w->pv);
+        double uv = control(pb, mk, w->px, w->dpv);
+        track_grad(pb, zs, pb->zd + 2 * k, gz);
+        double nlx = lx + gn * dt * (ux - pb->eta) * lv + dt * gz[0] + dt * pb->alpha * u * ux;
+        double nlv = dt * lx + gn * (1.0 + dt * uv) * lv + dt * gz[1] + dt * pb->alpha * u * uv;
+        lx = nlx;
+        lv = nlv;
+        w->lam[2 * k] = lx;
+        w->lam[2 * k + 1] = lv;
+    }
+    w->lam[0] = 0.0;
+    w->lam[1] = 0.0;
+}
+
+/* Surrogate gradient (Section 6.5): the forward adds alpha u_k phi(z_k) as it
+ * goes, the adjoint runs on the surrogate states; nothing is stored. */
+int fb_cost_grad_surrogate(const fb_problem* pb, int64_t M, uint64_t seed, uint32_t iter,
+                           const double* mu, double* J, double* g, int nthreads)
+{
+    if (check_problem(pb) || M < 1 || !mu || !J || !g)
+        return -1;
+    const int N = pb->N, L = pb->nx * pb->nv;
+    const size_t nl = (size_t)N * L;
+    const int64_t nchunk = (M + FB_CHUNK - 1) / FB_CHUNK;
+    uint64_t thr[32];
+    or_poisson_thresholds(rate_dt(pb), thr);
+    double* csum = (double*)calloc((size_t)nchunk, sizeof(double));
+    double* gsum = (double*)calloc((size_t)nchunk * nl, sizeof(double));
+    if (!csum || !gsum) {
+        free(csum);
+        free(gsum);
+        return -2;
+    }
+    int rc = 0;
+#pragma omp parallel num_threads(nthreads > 0 ? nthreads : 1) reduction(| : rc)
+    {
+        work w;
+        const int ok = work_alloc(pb, &w) == 0;
+        rc |= ok ? 0 : 1;
+        {
+#pragma omp for schedule(dynamic, 1)
+            for (int64_t c = 0; c < nchunk; ++c) {
+                if (!ok)
+                    continue;
+                int64_t mb = c * FB_CHUNK, me = mb + FB_CHUNK < M ? mb + FB_CHUNK : M;
+                double cs = 0.0;
+                double* G = gsum + (size_t)c * nl;
+                for (int64_t m = mb; m < me; ++m) {
+                    cs += path_forward(pb, thr, seed, iter, (uint32_t)m, mu, &w);
+                    for (int k = 0; k < N; ++k) {
+                        shapes(pb, w.z + 2 * k, w.px, w.pv, NULL, NULL);
+                        double au = pb->alpha * w.u[k];
+                        for (int i = 0; i < pb->nx; ++i)
+                            for (int l = 0; l < pb->nv; ++l)
+                                G[(size_t)k * L + i * pb->nv + l] += w.px[i] * w.pv[l] * au;
+                    }
+                    path_adjoint_surrogate(pb, mu, seed, iter, (uint32_t)m, &w, G);
+                }
+                csum[c] = cs;
+            }
+        }
+        work_free(&w);
+    }
+    if (rc) {
+        free(csum);
+        free(gsum);
+        return -2;
+    }
+    double ctot = 0.0;
+    for (int64_t c = 0; c < nchunk; ++c)
+        ctot += csum[c];
+    *J = ctot / (double)M;
+    for (size_t q = 0; q < nl; ++q) {
+        double t = 0.0;
+        for (int64_t c = 0; c < nchunk; ++c)
+            t += gsum[(size_t)c * nl + q];
+        g[q] = t / (double)M;
     }
     free(csum);
     free(gsum);

@@ -23,6 +23,14 @@
  *             lam^v_k = dt lam^x_{k+1} + gamma^n (1 + dt u_v) lam^v_{k+1} + dt dJt/dv + dt alpha u u_v
  *   gradient  g_k[l] = (1/M) sum_m phi_l(z_k) (alpha u_k + gamma^{n_k} lam^v_{k+1})
  *             (dJ/dmu_k = dt g_k)
+ *
+ * Surrogate gradient (Section 6.5, the adjoint independent of the forward
+ * trajectories): the adjoint runs on states zs_k ~ N(zd_k, diag(var(t_k))),
+ * drawn from Philox block (m, k, iter, 1) (Box-Muller pair of words 0, 1),
+ * with the forward's jump counts; no trajectory is stored:
+ *   gs_k[l] = (1/M) sum_m [ alpha u_k phi_l(z_k) + gamma^{n_k} ls^v_{k+1} phi_l(zs_k) ]
+ * where ls is the adjoint recursion above evaluated at zs (u, u_x, u_v and
+ * grad Jt at zs_k).
  */
 #ifndef FB_ORACLE_H
 #define FB_ORACLE_H
@@ -39,6 +47,7 @@ typedef struct {
     double xmax, vmax, eps, alpha, sigJ;
     int32_t init_kind;     /* 0: Gaussian z0 + s0 * Z, 1: uniform on [z0 - s0, z0 + s0] */
     double z0[2], s0[2];
+    double svar0[2], svar1[2]; /* surrogate-state variance var_c(t) = svar0[c] + svar1[c] t */
     const double* zd;      /* (N+1) x 2, row k = desired (x, v) at t_k */
 } fb_problem;
 
@@ -62,6 +71,14 @@ int fb_paths(const fb_problem* pb, uint64_t seed, uint32_t iter, int64_t m0, int
 /* J and g (N x L) over M paths, fixed-order chunked FP64 sums.  g may be NULL. */
 int fb_cost_grad(const fb_problem* pb, int64_t M, uint64_t seed, uint32_t iter,
                  const double* mu, double* J, double* g, int nthreads);
+
+/* Surrogate state of path m at step k. */
+void fb_surrogate_state(const fb_problem* pb, uint64_t seed, uint32_t m, uint32_t k, uint32_t iter,
+                        double z[2]);
+
+/* J (exact) and the surrogate gradient gs (N x L). */
+int fb_cost_grad_surrogate(const fb_problem* pb, int64_t M, uint64_t seed, uint32_t iter,
+                           const double* mu, double* J, double* g, int nthreads);
 
 /* Tangent-linear directional derivative dJ[dmu]. */
 int fb_tangent(const fb_problem* pb, int64_t M, uint64_t seed, uint32_t iter,

@@ -211,7 +211,8 @@ class _FbProblem(C.Structure):
                 ("gamma", C.c_double), ("beta", C.c_double), ("xmax", C.c_double),
                 ("vmax", C.c_double), ("eps", C.c_double), ("alpha", C.c_double),
                 ("sigJ", C.c_double), ("init_kind", C.c_int32), ("z0", C.c_double * 2),
-                ("s0", C.c_double * 2), ("zd", C.c_void_p)]
+                ("s0", C.c_double * 2), ("svar0", C.c_double * 2), ("svar1", C.c_double * 2),
+                ("zd", C.c_void_p)]
 
 
 def _bind_fb(L):
@@ -228,6 +229,9 @@ def _bind_fb(L):
     L.fb_paths.restype = C.c_int
     L.fb_cost_grad.argtypes = [P, C.c_int64, C.c_uint64, C.c_uint32, P, P, P, C.c_int]
     L.fb_cost_grad.restype = C.c_int
+    L.fb_surrogate_state.argtypes = [P, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, P]
+    L.fb_cost_grad_surrogate.argtypes = [P, C.c_int64, C.c_uint64, C.c_uint32, P, P, P, C.c_int]
+    L.fb_cost_grad_surrogate.restype = C.c_int
     L.fb_tangent.argtypes = [P, C.c_int64, C.c_uint64, C.c_uint32, P, P, P, C.c_int]
     L.fb_tangent.restype = C.c_int
     L.fb_optimize.argtypes = [P, C.c_int64, C.c_uint64, C.c_uint32, C.c_int32, C.c_double,
@@ -249,7 +253,9 @@ class _Fb:
         self.zd = np.ascontiguousarray(p.zd, np.float64)
         self.st = _FbProblem(p.N, p.nx, p.nv, p.T, p.eta, p.b1, p.b2, p.gamma, p.beta, p.xmax,
                              p.vmax, p.eps, p.alpha, p.sigJ, p.init_kind,
-                             (C.c_double * 2)(*p.z0), (C.c_double * 2)(*p.s0), self.zd.ctypes.data)
+                             (C.c_double * 2)(*p.z0), (C.c_double * 2)(*p.s0),
+                             (C.c_double * 2)(*p.svar0), (C.c_double * 2)(*p.svar1),
+                             self.zd.ctypes.data)
 
     def ref(self):
         return C.byref(self.st)
@@ -308,6 +314,25 @@ def fb_cost_grad(p, M: int, seed: int, it: int, mu, grad: bool = True,
     fb = _Fb(p)
     rc = _fb().fb_cost_grad(fb.ref(), M, seed, it, _ptr(mu), C.byref(J),
                             None if g is None else _ptr(g), nthreads or default_threads())
+    assert rc == 0, rc
+    return J.value, g
+
+
+def fb_surrogate_state(p, seed: int, m: int, k: int, it: int) -> np.ndarray:
+    z = np.zeros(2)
+    fb = _Fb(p)
+    _fb().fb_surrogate_state(fb.ref(), seed, m, k, it, _ptr(z))
+    return z
+
+
+def fb_cost_grad_surrogate(p, M: int, seed: int, it: int, mu, nthreads: int | None = None):
+    """(J, gs): the exact cost and the surrogate gradient of Section 6.5."""
+    mu = _mu(p, mu)
+    J = C.c_double()
+    g = np.zeros((p.N, p.L))
+    fb = _Fb(p)
+    rc = _fb().fb_cost_grad_surrogate(fb.ref(), M, seed, it, _ptr(mu), C.byref(J), _ptr(g),
+                                      nthreads or default_threads())
     assert rc == 0, rc
     return J.value, g
 

@@ -251,6 +251,11 @@ class FeedbackProblem:
     s0: np.ndarray  # 2
     zd: np.ndarray  # (N+1) x 2, row k = desired (x, v) at t_k
     name: str = ""
+    # variance of the surrogate adjoint states, var_c(t) = svar0[c] + svar1[c] t
+    # (Section 6.5); None: the initial variance plus the noise and jump
+    # variance rates (b1^2, b2^2 + rate / (2 beta))
+    svar0: np.ndarray | None = None
+    svar1: np.ndarray | None = None
 
     def __post_init__(self):
         self.N, self.nx, self.nv, self.init_kind = int(self.N), int(self.nx), int(self.nv), int(self.init_kind)
@@ -259,6 +264,12 @@ class FeedbackProblem:
         self.z0 = np.ascontiguousarray(np.broadcast_to(np.asarray(self.z0, np.float64), (2,)))
         self.s0 = np.ascontiguousarray(np.broadcast_to(np.asarray(self.s0, np.float64), (2,)))
         self.zd = np.ascontiguousarray(np.asarray(self.zd, np.float64).reshape(self.N + 1, 2))
+        if self.svar0 is None:
+            self.svar0 = self.s0 ** 2 if self.init_kind == 0 else self.s0 ** 2 / 3.0
+        if self.svar1 is None:
+            self.svar1 = (self.b1 ** 2, self.b2 ** 2 + math.sqrt(self.beta / math.pi) / (2.0 * self.beta))
+        self.svar0 = np.ascontiguousarray(np.broadcast_to(np.asarray(self.svar0, np.float64), (2,)))
+        self.svar1 = np.ascontiguousarray(np.broadcast_to(np.asarray(self.svar1, np.float64), (2,)))
 
     @property
     def dt(self) -> float:
@@ -285,22 +296,25 @@ def feedback_problem(N: int = 50, T: float = 5.0, init: str = "gauss", zd=None, 
                      b1: float = 0.05, b2: float = 0.1, gamma: float = 0.9, beta: float = 10.0,
                      nx: int = 10, nv: int = 10, xmax: float = 2.0, vmax: float = 2.0,
                      eps: float = 0.5, alpha: float = 1e-2, sigJ: float = 0.5,
-                     name: str = "") -> FeedbackProblem:
+                     name: str = "", s0=None, z0=None, svar0=None, svar1=None) -> FeedbackProblem:
     """The setting of the paper's Section 6 (xmax = vmax = 2, nx = nv = 10,
     eps = 0.5, beta = 10, gamma = 0.9, eta = 1, T = 5, N = 50).  The paper does
     not state alpha, sigma_J, b1, b2; the defaults here are readings.  init
-    'gauss' is N((0.75, 0.75), 0.01 I) (Section 6.1), 'uniform' is [-1, 1]^2."""
+    'gauss' is N((0.75, 0.75), 0.01 I) (Section 6.1), 'uniform' is [-1, 1]^2;
+    z0 and s0 override the law's centre and scale."""
     if init == "gauss":
-        kind, z0, s0 = 0, (0.75, 0.75), (0.1, 0.1)
+        kind, z0d, s0d = 0, (0.75, 0.75), (0.1, 0.1)
     elif init == "uniform":
-        kind, z0, s0 = 1, (0.0, 0.0), (1.0, 1.0)
+        kind, z0d, s0d = 1, (0.0, 0.0), (1.0, 1.0)
     else:
         raise ValueError(init)
+    z0 = z0d if z0 is None else z0
+    s0 = s0d if s0 is None else s0
     if zd is None:
         zd = np.zeros((N + 1, 2))
     return FeedbackProblem(N=N, T=T, eta=eta, b1=b1, b2=b2, gamma=gamma, beta=beta, nx=nx, nv=nv,
                            xmax=xmax, vmax=vmax, eps=eps, alpha=alpha, sigJ=sigJ, init_kind=kind,
-                           z0=z0, s0=s0, zd=zd, name=name)
+                           z0=z0, s0=s0, zd=zd, name=name, svar0=svar0, svar1=svar1)
 
 
 def switching_target(N: int, T: float, amp: float = 0.5) -> np.ndarray:

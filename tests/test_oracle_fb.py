@@ -10,7 +10,10 @@ away except at one step); the control's index structure (a single non-zero
 coefficient against the paper's cell-centre formula, Section 5,
 discretization); central differences of J under common random numbers and the
 tangent-linear duality for the adjoint and the gradient (Section 4,
-eq. definition_Gradient); and a replay of the Armijo iteration (Algorithm 5.4).
+eq. definition_Gradient); a replay of the Armijo iteration (Algorithm 5.4); and
+for the surrogate gradient of Section 6.5, the law of the surrogate states, the
+exact gradient recovered when the surrogate states land on a particle's own
+path, and the one-step definition.
 """
 import math
 
@@ -221,3 +224,83 @@ def test_descent_on_the_paper_setting():
     J0, _ = ref.fb_cost_grad(p, 20000, 77, 1000, np.zeros((p.N, p.L)), grad=False)
     J1, _ = ref.fb_cost_grad(p, 20000, 77, 1000, mu, grad=False)
     assert J1 < J0
+
+
+# ---------------------------------------------------------------- surrogate adjoint (Section 6.5)
+def test_surrogate_states_law():
+    """zs_k ~ N(zd_k, diag(svar0 + svar1 t_k)), components uncorrelated."""
+    p = wl.feedback_problem(N=10, T=2.0, zd=_moving_target(10, 2.0), svar0=(0.04, 0.09),
+                            svar1=(0.3, 0.05))
+    M = 20000
+    for k in (0, 4, 10):
+        zs = np.array([ref.fb_surrogate_state(p, 7, m, k, 3) for m in range(M)])
+        t = k * p.dt
+        var = np.array([0.04 + 0.3 * t, 0.09 + 0.05 * t])
+        mean_err = np.abs(zs.mean(axis=0) - p.zd[k])
+        assert np.all(mean_err <= 5 * np.sqrt(var / M)), (k, mean_err)
+        v = zs.var(axis=0, ddof=1)
+        assert np.all(np.abs(v - var) <= 5 * var * np.sqrt(2.0 / M)), (k, v, var)
+        c = np.corrcoef(zs[:, 0], zs[:, 1])[0, 1]
+        assert abs(c) <= 5 / np.sqrt(M)
+
+
+def _moving_target(N, T):
+    t = np.arange(N + 1) * (T / N)
+    return np.stack([0.5 * np.cos(t), -0.4 * np.sin(t)], axis=1)
+
+
+@pytest.mark.parametrize("gamma", [0.8, -0.5])
+def test_surrogate_on_own_path_equals_exact(gamma):
+    """One particle, and a target shifted so that the surrogate states land on
+    the particle's own realised path: the surrogate offsets sigma_k Z_k come
+    from the counters and do not depend on the target, so with
+    zd'_k = z_k - sigma_k Z_k the surrogate states are z_k while the tracking
+    sources grad Jt(z_k; zd'_k) stay non-zero.  The surrogate gradient must then
+    be the exact (difference-pinned) gradient.  Noise and jumps included."""
+    kw = dict(gamma=gamma, b1=0.3, b2=0.4, beta=40.0, svar0=(0.05, 0.08), svar1=(0.2, 0.1))
+    base = small_problem(**kw)
+    mu = wl.random_feedback_control(base, 3, 1.0)
+    seed, it = 5, 2
+    z, _, _, n, _ = ref.fb_paths(base, seed, it, 0, 1, mu)
+    assert n.sum() > 0  # the particle jumps
+    zero = small_problem(zd=np.zeros((base.N + 1, 2)), **kw)
+    offs = np.array([ref.fb_surrogate_state(zero, seed, 0, k, it) for k in range(base.N + 1)])
+    p = small_problem(zd=z[0] - offs, **kw)
+    zs = np.array([ref.fb_surrogate_state(p, seed, 0, k, it) for k in range(p.N + 1)])
+    np.testing.assert_allclose(zs, z[0], rtol=0, atol=1e-14)
+    J, g = ref.fb_cost_grad(p, 1, seed, it, mu)
+    Js, gs = ref.fb_cost_grad_surrogate(p, 1, seed, it, mu)
+    assert Js == J
+    np.testing.assert_allclose(gs, g, rtol=1e-10, atol=1e-12 * np.abs(g).max())
+    # the tracking sources are active: the same particle against the unshifted
+    # target has a different gradient
+    _, g0 = ref.fb_cost_grad(base, 1, seed, it, mu)
+    assert np.abs(g0 - g).max() > 1e-3 * np.abs(g).max()
+
+
+def test_surrogate_one_step_definition():
+    """N = 1: gs_0 = (1/M) sum_m [alpha u_0 phi(z_0) + gamma^n dt dJt/dv(zs_1) phi(zs_0)]."""
+    p = wl.feedback_problem(N=1, T=0.5, zd=np.array([[0.2, -0.1], [0.4, 0.3]]), alpha=0.3,
+                            sigJ=0.6, nx=4, nv=5, svar0=(0.05, 0.02), svar1=(0.1, 0.2))
+    mu = wl.random_feedback_control(p, 2, 1.0)
+    M, seed, it = 5, 8, 1
+    z, _, u, n, _ = ref.fb_paths(p, seed, it, 0, M, mu)
+    _, gs = ref.fb_cost_grad_surrogate(p, M, seed, it, mu)
+    dx, dv = 2 * p.xmax / p.nx, 2 * p.vmax / p.nv
+    xc = (np.arange(p.nx) + 0.5) * dx - p.xmax
+    vc = (np.arange(p.nv) + 0.5) * dv - p.vmax
+
+    def phi(zz):
+        bx = np.array([ref.fb_bump(zz[0] - c, p.eps) for c in xc])
+        bv = np.array([ref.fb_bump(zz[1] - c, p.eps) for c in vc])
+        return np.outer(bx, bv).reshape(-1)
+
+    want = np.zeros(p.L)
+    for m in range(M):
+        zs0 = ref.fb_surrogate_state(p, seed, m, 0, it)
+        zs1 = ref.fb_surrogate_state(p, seed, m, 1, it)
+        r = zs1 - p.zd[1]
+        dJv = r[1] / p.sigJ ** 2 * np.exp(-np.sum(r * r) / (2 * p.sigJ ** 2))
+        gn = p.gamma ** n[m, 0]
+        want += p.alpha * u[m, 0] * phi(z[m, 0]) + gn * p.dt * dJv * phi(zs0)
+    np.testing.assert_allclose(gs[0], want / M, rtol=1e-12, atol=1e-15)

@@ -3,7 +3,8 @@ of the oracle source (on the CPU), build it, and run the pin suites against the
 mutant.  Every mutant must make at least one pin fail; the unmodified source
 must pass them all (the pin suites themselves run that case).
 
-Not listed: the byte layout of the Poisson word.  Which bits feed the count is a
+Not listed: the byte layout of the Poisson word, and which Philox block feeds
+the surrogate states of the feedback model.  Which bits feed the count is a
 convention, not a law: any layout using bits the uniforms do not read gives the
 same distribution, so no pin of the law can see it.  It is fixed only by the
 bit-exact agreement of the two independent implementations (oracle and GPU)."""
@@ -82,16 +83,29 @@ FB_MUTANTS = {
                             "C += dt * track(pb, zk, pb->zd + 2 * k);"),
     "fb_control_cost_half": ("C += dt * 0.5 * pb->alpha * u * u;", "C += dt * pb->alpha * u * u;"),
     "fb_adjoint_terminal_without_dt": ("w->lam[2 * N] = dt * gz[0];", "w->lam[2 * N] = gz[0];"),
-    "fb_adjoint_spring_sign": ("gn * dt * (ux - pb->eta) * lv", "gn * dt * (ux + pb->eta) * lv"),
+    "fb_adjoint_spring_sign": ("w->lam[2 * k] = lx + gn * dt * (ux - pb->eta) * lv + dt * gz[0] + dt * pb->alpha * u * ux;", "w->lam[2 * k] = lx + gn * dt * (ux + pb->eta) * lv + dt * gz[0] + dt * pb->alpha * u * ux;"),
     "fb_adjoint_position_coupling": ("w->lam[2 * k + 1] = dt * lx +", "w->lam[2 * k + 1] = lx +"),
-    "fb_adjoint_no_jump_factor": ("gn * (1.0 + dt * uv) * lv", "(1.0 + dt * uv) * lv"),
-    "fb_adjoint_uv_dropped": ("gn * (1.0 + dt * uv) * lv", "gn * lv"),
-    "fb_adjoint_track_sign": ("+ dt * gz[1] + dt * pb->alpha * u * uv;", "- dt * gz[1] + dt * pb->alpha * u * uv;"),
-    "fb_adjoint_control_cost_dropped": ("+ dt * gz[0] + dt * pb->alpha * u * ux;", "+ dt * gz[0];"),
+    "fb_adjoint_no_jump_factor": ("w->lam[2 * k + 1] = dt * lx + gn * (1.0 + dt * uv) * lv + dt * gz[1] + dt * pb->alpha * u * uv;", "w->lam[2 * k + 1] = dt * lx + (1.0 + dt * uv) * lv + dt * gz[1] + dt * pb->alpha * u * uv;"),
+    "fb_adjoint_uv_dropped": ("w->lam[2 * k + 1] = dt * lx + gn * (1.0 + dt * uv) * lv + dt * gz[1] + dt * pb->alpha * u * uv;", "w->lam[2 * k + 1] = dt * lx + gn * lv + dt * gz[1] + dt * pb->alpha * u * uv;"),
+    "fb_adjoint_track_sign": ("w->lam[2 * k + 1] = dt * lx + gn * (1.0 + dt * uv) * lv + dt * gz[1] + dt * pb->alpha * u * uv;", "w->lam[2 * k + 1] = dt * lx + gn * (1.0 + dt * uv) * lv - dt * gz[1] + dt * pb->alpha * u * uv;"),
+    "fb_adjoint_control_cost_dropped": ("w->lam[2 * k] = lx + gn * dt * (ux - pb->eta) * lv + dt * gz[0] + dt * pb->alpha * u * ux;", "w->lam[2 * k] = lx + gn * dt * (ux - pb->eta) * lv + dt * gz[0];"),
     "fb_gradient_no_jump_factor": ("double wk = pb->alpha * u + gn * lv;", "double wk = pb->alpha * u + lv;"),
     "fb_gradient_control_term_dropped": ("double wk = pb->alpha * u + gn * lv;", "double wk = gn * lv;"),
     "fb_track_grad_sign": ("gz[0] = rx / s2 * e;", "gz[0] = -rx / s2 * e;"),
     "fb_armijo_sign": ("if (Jt <= J - c_armijo * zeta * gg)", "if (Jt <= J + c_armijo * zeta * gg)"),
+    "fb_surr_no_jump_factor": ("G[(size_t)k * L + i * pb->nv + l] += w->px[i] * w->pv[l] * (gn * lv);",
+                               "G[(size_t)k * L + i * pb->nv + l] += w->px[i] * w->pv[l] * lv;"),
+    "fb_surr_var_no_sqrt": ("z[0] = pb->zd[2 * k] + sqrt(pb->svar0[0] + pb->svar1[0] * t) * R * cos(th);",
+                            "z[0] = pb->zd[2 * k] + (pb->svar0[0] + pb->svar1[0] * t) * R * cos(th);"),
+    "fb_surr_time_next_step": ("double t = (double)k * (pb->T / (double)pb->N);",
+                               "double t = (double)(k + 1) * (pb->T / (double)pb->N);"),
+    "fb_surr_track_sign": ("double nlv = dt * lx + gn * (1.0 + dt * uv) * lv + dt * gz[1]",
+                           "double nlv = dt * lx + gn * (1.0 + dt * uv) * lv - dt * gz[1]"),
+    "fb_surr_terminal_without_dt": ("double lx = dt * gz[0], lv = dt * gz[1];",
+                                    "double lx = dt * gz[0], lv = gz[1];"),
+    "fb_surr_forward_term_dropped": ("double au = pb->alpha * w.u[k];", "double au = 0.0 * w.u[k];"),
+    "fb_surr_control_cost_source_dropped": ("double nlx = lx + gn * dt * (ux - pb->eta) * lv + dt * gz[0] + dt * pb->alpha * u * ux;",
+                                            "double nlx = lx + gn * dt * (ux - pb->eta) * lv + dt * gz[0];"),
 }
 
 
