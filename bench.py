@@ -198,6 +198,16 @@ def feedback_section(args, time_calls, dev):
                      "forward_ms": float(np.mean(fw)), "adjoint_ms": float(np.mean(ad))}
         del e
         torch.cuda.empty_cache()
+    # the storage-free surrogate gradient (Section 6.5): no trajectory buffer
+    es = B.FbEngine(p, M=w.M, seed=w.seed, precision="fp32", device=dev, mode="surrogate")
+    for it in range(args.warmup):
+        es.cost_grad(mu, it=it)
+    sg = time_calls(lambda: es.cost_grad(mu, it=5), args.steps)
+    out["fp32_surrogate"] = {"p50_ms": percentile(sg, 50), "p99_ms": percentile(sg, 99),
+                             "path_steps_per_s_p50": ps / (percentile(sg, 50) * 1e-3),
+                             "trajectory_bytes_saved": (p.N + 1) * 2 * 4 * es.nblk * 256}
+    del es
+    torch.cuda.empty_cache()
     t_f, t_a = out["fp32"]["forward_ms"] * 1e-3, out["fp32"]["adjoint_ms"] * 1e-3
     t_cg = out["fp32"]["p50_ms"] * 1e-3
     out["roofline"] = {

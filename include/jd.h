@@ -82,6 +82,7 @@ extern "C" {
 /* Trajectory handling between the forward and the adjoint sweep. */
 #define JD_STORE 0     /* store X_1..X_N */
 #define JD_RECOMPUTE 1 /* store X every K steps, regenerate segments in the adjoint */
+#define JD_SURROGATE 2 /* feedback model only (jd_feedback.h): storage-free surrogate gradient */
 
 /* Problem data (the paper's Section 2 problem statement reduced to the model
  * above).  All pointers except xd are HOST memory read during the call. */

@@ -35,10 +35,20 @@
  * or uniform z0 + s0 (2 u - 1) (fresh initial particles every iteration,
  * Section 5, optimization procedure).
  *
+ * Surrogate gradient (run->mode = JD_SURROGATE; Section 6.5, the adjoint
+ * independent of the forward trajectories): nothing is stored.  The forward
+ * adds alpha u_k phi(z_k) to the gradient as it goes; the adjoint recursion
+ * above runs on surrogate states zs_k = zd_k + sqrt(svar0 + svar1 t_k) . (Z1, Z2)
+ * (Box-Muller pair of words 0, 1 of Philox block (m, k, iter, 1)) with the
+ * forward's jump counts, and adds gamma^{n_k} ls^v_{k+1} phi(zs_k).  J is the
+ * exact cost.  The gradient is biased (it is not the derivative of J).
+ *
  * Conventions are those of jd.h (return codes, caller-owned device buffers,
  * asynchronous calls on `stream`, validation before any launch).  mu and g
- * are FP64 device arrays, row-major N x L with L = nx nv.  Only JD_STORE is
- * supported (JD_RECOMPUTE returns JD_EUNSUPPORTED).
+ * are FP64 device arrays, row-major N x L with L = nx nv.  Modes: JD_STORE
+ * (exact gradient over the stored trajectory) and JD_SURROGATE (jd_fb_forward,
+ * jd_fb_cost_grad, jd_fb_optimize; traj may be NULL); JD_RECOMPUTE returns
+ * JD_EUNSUPPORTED.
  */
 #ifndef JD_FEEDBACK_H
 #define JD_FEEDBACK_H
@@ -66,6 +76,7 @@ typedef struct jd_fb_problem {
     double sigJ;        /* tracking-cost width, > 0 */
     int32_t init_kind;  /* JD_FB_INIT_GAUSS or JD_FB_INIT_UNIFORM */
     double z0[2], s0[2];/* initial law: centre and scale (s0 >= 0) */
+    double svar0[2], svar1[2]; /* surrogate-state variance svar0 + svar1 t (>= 0), JD_SURROGATE */
     const double* zd;   /* DEVICE, (N+1) x 2 FP64: desired (x, v) at t_0..t_N */
 } jd_fb_problem;
 
@@ -88,13 +99,15 @@ int jd_fb_forward(const jd_fb_problem* prob, const jd_run* run, const double* mu
                   double* J, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* Backward adjoint sweep over the trajectory of jd_fb_forward (same prob,
- * run, mu) and the Monte Carlo gradient g (device FP64 N x L, no dt factor).
+ * run, mu) and the Monte Carlo gradient g (device FP64 N x L, no dt factor);
+ * JD_STORE only (JD_SURROGATE: JD_EUNSUPPORTED, use jd_fb_cost_grad).
  * The per-step sum over particles of phi(z) (alpha u + gamma^n lam^v) is a
  * dense 16 x 16 contraction over paths and runs on the FP64 matrix cores. */
 int jd_fb_adjoint(const jd_fb_problem* prob, const jd_run* run, const double* mu,
                   const void* traj, double* grad, void* ws, size_t ws_bytes, hipStream_t stream);
 
-/* Forward + adjoint + reductions (Algorithm 5.3): J -> *J, g -> grad. */
+/* Forward + adjoint + reductions (Algorithm 5.3): J -> *J, g -> grad (the
+ * surrogate gradient under JD_SURROGATE, where traj may be NULL). */
 int jd_fb_cost_grad(const jd_fb_problem* prob, const jd_run* run, const double* mu, double* J,
                     double* grad, void* traj, void* ws, size_t ws_bytes, hipStream_t stream);
 

@@ -444,6 +444,34 @@ static void path_adjoint_surrogate(const fb_problem* pb, const double* mu, uint6
     w->lam[1] = 0.0;
 }
 
+int fb_paths_surrogate(const fb_problem* pb, uint64_t seed, uint32_t iter, int64_t m0, int64_t count,
+                       const double* mu, double* lam, int nthreads)
+{
+    if (check_problem(pb) || !mu || !lam || m0 < 0 || count < 0)
+        return -1;
+    const int N = pb->N, L = pb->nx * pb->nv;
+    uint64_t thr[32];
+    or_poisson_thresholds(rate_dt(pb), thr);
+    double* G = (double*)calloc((size_t)N * L, sizeof(double));
+    if (!G)
+        return -2;
+    int rc = 0;
+    work w;
+    if (work_alloc(pb, &w) == 0) {
+        for (int64_t p = 0; p < count; ++p) {
+            path_forward(pb, thr, seed, iter, (uint32_t)(m0 + p), mu, &w);
+            path_adjoint_surrogate(pb, mu, seed, iter, (uint32_t)(m0 + p), &w, G);
+            memcpy(lam + (size_t)p * (N + 1) * 2, w.lam, (size_t)(N + 1) * 2 * sizeof(double));
+        }
+    } else {
+        rc = -2;
+    }
+    work_free(&w);
+    free(G);
+    (void)nthreads;
+    return rc;
+}
+
 /* Surrogate gradient (Section 6.5): the forward adds alpha u_k phi(z_k) as it
  * goes, the adjoint runs on the surrogate states; nothing is stored. */
 int fb_cost_grad_surrogate(const fb_problem* pb, int64_t M, uint64_t seed, uint32_t iter,
@@ -583,7 +611,7 @@ int fb_tangent(const fb_problem* pb, int64_t M, uint64_t seed, uint32_t iter,
 int fb_optimize(const fb_problem* pb, int64_t M, uint64_t seed, uint32_t iter0, int32_t n_max,
                 double tol, double zeta0, double rho, double c_armijo, int32_t max_backtracks,
                 double* mu, double* logJ, double* log_gnorm, double* log_zeta, int32_t* log_bt,
-                double* logE, int nthreads)
+                double* logE, int surrogate, int nthreads)
 {
     if (check_problem(pb) || !mu || n_max < 0 || max_backtracks < 1)
         return -1;
@@ -601,7 +629,9 @@ int fb_optimize(const fb_problem* pb, int64_t M, uint64_t seed, uint32_t iter0, 
     for (n = 0; n < n_max; ++n) {
         uint32_t it = iter0 + (uint32_t)n;
         double J;
-        if (fb_cost_grad(pb, M, seed, it, mu, &J, g, nthreads)) {
+        int grc = surrogate ? fb_cost_grad_surrogate(pb, M, seed, it, mu, &J, g, nthreads)
+                            : fb_cost_grad(pb, M, seed, it, mu, &J, g, nthreads);
+        if (grc) {
             n = -2;
             break;
         }

@@ -76,6 +76,10 @@ int fb_cost_grad(const fb_problem* pb, int64_t M, uint64_t seed, uint32_t iter,
 void fb_surrogate_state(const fb_problem* pb, uint64_t seed, uint32_t m, uint32_t k, uint32_t iter,
                         double z[2]);
 
+/* Per-path surrogate adjoints ls (count x (N+1) x 2, row 0 zero). */
+int fb_paths_surrogate(const fb_problem* pb, uint64_t seed, uint32_t iter, int64_t m0, int64_t count,
+                       const double* mu, double* lam, int nthreads);
+
 /* J (exact) and the surrogate gradient gs (N x L). */
 int fb_cost_grad_surrogate(const fb_problem* pb, int64_t M, uint64_t seed, uint32_t iter,
                            const double* mu, double* J, double* g, int nthreads);
@@ -85,11 +89,12 @@ int fb_tangent(const fb_problem* pb, int64_t M, uint64_t seed, uint32_t iter,
                const double* mu, const double* dmu, double* dJ, int nthreads);
 
 /* Gradient iteration with stochastic Armijo backtracking on the same draws
- * (Section 5, Algorithm 5.4); mu in/out.  Logs may be NULL. */
+ * (Section 5, Algorithm 5.4); mu in/out.  Logs may be NULL.  surrogate != 0
+ * steps along the surrogate gradient (the Armijo test uses the exact cost). */
 int fb_optimize(const fb_problem* pb, int64_t M, uint64_t seed, uint32_t iter0, int32_t n_max,
                 double tol, double zeta0, double rho, double c_armijo, int32_t max_backtracks,
                 double* mu, double* logJ, double* log_gnorm, double* log_zeta, int32_t* log_bt,
-                double* logE, int nthreads);
+                double* logE, int surrogate, int nthreads);
 
 #ifdef __cplusplus
 }

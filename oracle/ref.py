@@ -236,7 +236,9 @@ def _bind_fb(L):
     L.fb_tangent.restype = C.c_int
     L.fb_optimize.argtypes = [P, C.c_int64, C.c_uint64, C.c_uint32, C.c_int32, C.c_double,
                               C.c_double, C.c_double, C.c_double, C.c_int32, P, P, P, P, P, P,
-                              C.c_int]
+                              C.c_int, C.c_int]
+    L.fb_paths_surrogate.argtypes = [P, C.c_uint64, C.c_uint32, C.c_int64, C.c_int64, P, P, C.c_int]
+    L.fb_paths_surrogate.restype = C.c_int
     L.fb_optimize.restype = C.c_int
     L._fb_bound = True
     return L
@@ -325,6 +327,16 @@ def fb_surrogate_state(p, seed: int, m: int, k: int, it: int) -> np.ndarray:
     return z
 
 
+def fb_paths_surrogate(p, seed: int, it: int, m0: int, count: int, mu) -> np.ndarray:
+    """Per-path surrogate adjoints (count, N+1, 2)."""
+    mu = _mu(p, mu)
+    lam = np.zeros((count, p.N + 1, 2))
+    fb = _Fb(p)
+    rc = _fb().fb_paths_surrogate(fb.ref(), seed, it, m0, count, _ptr(mu), _ptr(lam), 1)
+    assert rc == 0, rc
+    return lam
+
+
 def fb_cost_grad_surrogate(p, M: int, seed: int, it: int, mu, nthreads: int | None = None):
     """(J, gs): the exact cost and the surrogate gradient of Section 6.5."""
     mu = _mu(p, mu)
@@ -349,7 +361,7 @@ def fb_tangent(p, M: int, seed: int, it: int, mu, dmu, nthreads: int | None = No
 
 def fb_optimize(p, M: int, seed: int, it0: int, mu, n_max: int, tol: float = 0.0,
                 zeta0: float = 1.0, rho: float = 0.5, c_armijo: float = 1e-4,
-                max_backtracks: int = 30, nthreads: int | None = None):
+                max_backtracks: int = 30, surrogate: bool = False, nthreads: int | None = None):
     """Returns (mu, logs, n) like ``optimize``."""
     mu = _mu(p, mu).copy()
     nm = max(n_max, 1)
@@ -358,7 +370,7 @@ def fb_optimize(p, M: int, seed: int, it0: int, mu, n_max: int, tol: float = 0.0
     fb = _Fb(p)
     n = _fb().fb_optimize(fb.ref(), M, seed, it0, n_max, tol, zeta0, rho, c_armijo,
                           max_backtracks, _ptr(mu), _ptr(lJ), _ptr(lg), _ptr(lz), _ptr(lb),
-                          _ptr(lE), nthreads or default_threads())
+                          _ptr(lE), 1 if surrogate else 0, nthreads or default_threads())
     logs = [dict(J=lJ[i], gnorm=lg[i], zeta=lz[i], backtracks=int(lb[i]), E=lE[i])
             for i in range(max(n, 0))]
     return mu, logs, n

@@ -19,7 +19,7 @@ JD_OK, JD_EINVAL, JD_EWORKSPACE, JD_EHIP, JD_ENONFINITE, JD_ELINESEARCH, JD_EUNS
     0, -1, -2, -3, -4, -5, -6)
 JD_EAGAIN = -7
 JD_FP32, JD_FP64 = 0, 1
-JD_STORE, JD_RECOMPUTE = 0, 1
+JD_STORE, JD_RECOMPUTE, JD_SURROGATE = 0, 1, 2
 
 EXPORTED = ["jd_version", "jd_strerror", "jd_workspace_bytes", "jd_traj_bytes", "jd_forward",
             "jd_adjoint", "jd_cost_grad", "jd_optimize", "jd_check_finite", "jd_draws",
@@ -151,7 +151,7 @@ class Problem:
 def make_run(M: int, seed: int = 1, it: int = 0, precision: str = "fp32", mode: str = "store",
              K: int = 0, dump: jd_dump | None = None) -> jd_run:
     prec = {"fp32": JD_FP32, "fp64": JD_FP64}[precision]
-    md = {"store": JD_STORE, "recompute": JD_RECOMPUTE}[mode]
+    md = {"store": JD_STORE, "recompute": JD_RECOMPUTE, "surrogate": JD_SURROGATE}[mode]
     return jd_run(M, seed, it, prec, md, K, C.pointer(dump) if dump is not None else None)
 
 
@@ -305,7 +305,8 @@ class jd_fb_problem(C.Structure):
                 ("gamma", C.c_double), ("beta", C.c_double), ("xmax", C.c_double),
                 ("vmax", C.c_double), ("eps", C.c_double), ("alpha", C.c_double),
                 ("sigJ", C.c_double), ("init_kind", C.c_int32), ("z0", C.c_double * 2),
-                ("s0", C.c_double * 2), ("zd", C.c_void_p)]
+                ("s0", C.c_double * 2), ("svar0", C.c_double * 2), ("svar1", C.c_double * 2),
+                ("zd", C.c_void_p)]
 
 
 class FbProblem:
@@ -319,6 +320,7 @@ class FbProblem:
         self.st = jd_fb_problem(p.N, p.nx, p.nv, p.T, p.eta, p.b1, p.b2, p.gamma, p.beta, p.xmax,
                                 p.vmax, p.eps, p.alpha, p.sigJ, p.init_kind,
                                 (C.c_double * 2)(*p.z0), (C.c_double * 2)(*p.s0),
+                                (C.c_double * 2)(*p.svar0), (C.c_double * 2)(*p.svar1),
                                 self.zd.data_ptr())
 
     @property
@@ -330,14 +332,17 @@ class FbEngine:
     """Feedback-model problem + Monte Carlo configuration with its workspace and
     trajectory buffers (torch allocations)."""
 
-    def __init__(self, problem, M: int, seed: int = 1, precision: str = "fp32", device="cuda:0"):
+    def __init__(self, problem, M: int, seed: int = 1, precision: str = "fp32", device="cuda:0",
+                 mode: str = "store"):
+        """mode 'store' (exact gradient over the stored trajectory) or
+        'surrogate' (the storage-free surrogate gradient of Section 6.5)."""
         torch = _torch()
         self.prob = problem if isinstance(problem, FbProblem) else FbProblem(problem, device)
         self.p = self.prob.p
-        self.M, self.seed, self.precision = M, seed, precision
+        self.M, self.seed, self.precision, self.mode = M, seed, precision, mode
         self.device = self.prob.device
         self.rdtype = torch.float32 if precision == "fp32" else torch.float64
-        run = make_run(M, seed, 0, precision, "store")
+        run = make_run(M, seed, 0, precision, mode)
         L = lib()
         self.ws_bytes = L.jd_fb_workspace_bytes(self.prob.ref, C.byref(run))
         self.traj_bytes = L.jd_fb_traj_bytes(self.prob.ref, C.byref(run))
@@ -349,7 +354,7 @@ class FbEngine:
         self.traj = torch.empty(self.traj_bytes // esz, dtype=self.rdtype, device=self.device)
 
     def run(self, it: int = 0, dump: jd_dump | None = None) -> jd_run:
-        return make_run(self.M, self.seed, it, self.precision, "store", 0, dump)
+        return make_run(self.M, self.seed, it, self.precision, self.mode, 0, dump)
 
     def _mu(self, mu):
         torch = _torch()

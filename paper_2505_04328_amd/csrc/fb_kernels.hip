@@ -34,6 +34,7 @@ struct FbArgs {
     Real dt, sqb1, sqb2, eta, eps, alpha, hadt, inv2s2, invs2;
     Real xc0, dxc, vc0, dvc;  // centres x^i = xc0 + i dxc, v^l = vc0 + l dvc
     Real z0x, z0v, s0x, s0v;
+    Real var0x, var0v, var1x, var1v;  // surrogate-state variance var(t) = var0 + var1 t
     int init_kind;
     uint32_t key0, key1, iter;
     const PoissonTable* thr;
@@ -118,12 +119,21 @@ __device__ __forceinline__ void shapes_v(const FbArgs<Real>& a, Real v, Real* pv
         pv[l] = bump(v - fma((Real)l, a.dvc, a.vc0), a.eps);
 }
 
+// Receives the shape-function values a step computes (the wave transposes of
+// the gradient reduction); NoSink drops them.
+struct NoSink {
+    template <typename Real>
+    __device__ __forceinline__ void put_x(int, Real) const {}
+    template <typename Real, int NVP>
+    __device__ __forceinline__ void put_v(const Real*) const {}
+};
+
 // One forward step of one particle: control, draws, Euler step, jumps.
-// Returns the control u_k.
-template <typename Real, int NVP>
+// Returns the control u_k; the bump values go to the sink.
+template <typename Real, int NVP, typename Sink = NoSink>
 __device__ __forceinline__ Real fb_step(const FbArgs<Real>& a, const Real* __restrict__ mk,
                                         const Real* __restrict__ ks, uint32_t m, int k, Real& x,
-                                        Real& v) {
+                                        Real& v, const Sink& sink = Sink()) {
     Real pv[NVP];
     shapes_v<Real, NVP>(a, v, pv);
     Real u = 0;
@@ -136,7 +146,9 @@ __device__ __forceinline__ Real fb_step(const FbArgs<Real>& a, const Real* __res
         for (int l = 0; l < NVP; ++l)
             t = fma(rw[l], pv[l], t);
         u = fma(bx, t, u);
+        sink.put_x(i, bx);
     }
+    sink.template put_v<Real, NVP>(pv);
     uint32_t w[4];
     philox4x32_10<true>(m, (uint32_t)k, a.iter, 0u, a.key0, a.key1, w);
     const Real R = bm_radius(w[0], (Real)0);
@@ -154,6 +166,20 @@ __device__ __forceinline__ Real fb_step(const FbArgs<Real>& a, const Real* __res
     x = xn;
     v = vs;
     return u;
+}
+
+// Surrogate state of particle m at step k (Section 6.5): zd_k + sqrt(var(t_k))
+// times the Box-Muller pair of words 0, 1 of Philox block (m, k, iter, 1).
+template <typename Real>
+__device__ __forceinline__ void fb_surrogate(const FbArgs<Real>& a, const Real* __restrict__ zd,
+                                             uint32_t m, int k, Real& x, Real& v) {
+    uint32_t w[4];
+    philox4x32_10<true>(m, (uint32_t)k, a.iter, 1u, a.key0, a.key1, w);
+    const Real R = bm_radius(w[0], (Real)0);
+    const Real ub = unit_uniform<Real>(w[1]);
+    const Real t = (Real)k * a.dt;
+    x = fma(sqrt(fma(a.var1x, t, a.var0x)), bm_cos(R, ub), zd[2 * k]);
+    v = fma(sqrt(fma(a.var1v, t, a.var0v)), bm_sin(R, ub), zd[2 * k + 1]);
 }
 
 template <typename Real>
@@ -260,35 +286,178 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 typedef double fb_d4 __attribute__((ext_vector_type(4)));
 
+constexpr int kFbWaves = kThreads / 64;  // waves per block
+constexpr int kFbStride = kFbMaxGrid + 1;  // padded row stride of the transposes
+
+// One wave's share of the per-step gradient sum over particles,
+// G_k[i][j] += sum_p b(x_p - x^i) w_p b(v_p - v^j): the particles' bump values
+// go through an LDS transpose (row p = particle, lane i + 16 kk reads A[i][kk] =
+// phx[4q + kk][i] w[4q + kk] and B[kk][i] = phv[4q + kk][i]) into sixteen
+// v_mfma_f64_16x16x4f64 per 64 particles, accumulated in four independent
+// chains.  The operand and result layouts were measured on the device:
+// A[i][kk] and B[kk][j] in lane i + 16 kk, D[i][j] in lane j + 16 (i % 4),
+// register i / 4.
+template <typename Real>
+struct FbWave {
+    Real (*phx)[kFbStride];
+    Real (*phv)[kFbStride];
+    Real* wts;
+    int ln, ii;
+    fb_d4 acc[4];
+
+    __device__ __forceinline__ void clear() {
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            acc[c] = fb_d4{0.0, 0.0, 0.0, 0.0};
+    }
+    template <typename R>
+    __device__ __forceinline__ void put_x(int i, R b) const { phx[ln][i] = b; }
+    template <typename R, int NVP>
+    __device__ __forceinline__ void put_v(const R* pv) const {
+#pragma unroll
+        for (int l = 0; l < NVP; ++l)
+            phv[ln][l] = pv[l];
+    }
+    // Adds the wave's 64 particles (weight w each; rows i >= nx and columns
+    // j >= nvp are zero).
+    template <int NVP>
+    __device__ __forceinline__ void add(Real w, int nx) {
+        wts[ln] = w;
+        wave_lds_sync();
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int p = 4 * q + (ln >> 4);
+            const double av = ii < nx ? (double)phx[p][ii] * (double)wts[p] : 0.0;
+            const double bv = ii < NVP ? (double)phv[p][ii] : 0.0;
+            acc[q & 3] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[q & 3], 0, 0, 0);
+        }
+        wave_lds_sync();
+    }
+};
+
+// The block's LDS for the reduction: per wave, the two transposes and the weights.
+template <typename Real>
+struct FbShared {
+    Real phx[kFbWaves][64][kFbStride];  // after a step: the wave's FP64 tile
+    Real phv[kFbWaves][64][kFbStride];
+    Real wts[kFbWaves][64];
+};
+
+template <typename Real>
+__device__ __forceinline__ FbWave<Real> fb_wave(FbShared<Real>& sh) {
+    static_assert(sizeof(Real) * 64 * kFbStride >= sizeof(double) * kFbMaxGrid * kFbMaxGrid,
+                  "a wave's transpose buffer must hold its 16 x 16 FP64 tile");
+    FbWave<Real> w;
+    const int wv = threadIdx.x >> 6;
+    w.phx = sh.phx[wv];
+    w.phv = sh.phv[wv];
+    w.wts = sh.wts[wv];
+    w.ln = threadIdx.x & 63;
+    w.ii = w.ln & 15;
+    w.clear();
+    return w;
+}
+
+// Sums the four waves' tiles in a fixed order into the block's partial of
+// step k (ADD: added to what the partial holds).
+template <bool ADD, typename Real>
+__device__ __forceinline__ void fb_block_partial(FbShared<Real>& sh, const FbWave<Real>& w, int k,
+                                                 int N, int nx, int nv, double* __restrict__ apart) {
+    double* cb = (double*)&w.phx[0][0];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        cb[(4 * r + (w.ln >> 4)) * kFbMaxGrid + w.ii] = (w.acc[0][r] + w.acc[1][r]) + (w.acc[2][r] + w.acc[3][r]);
+    __syncthreads();
+    const int t = threadIdx.x, i = t >> 4, j = t & 15;
+    if (i < nx && j < nv) {
+        double sum = ((const double*)&sh.phx[0][0][0])[t];
+#pragma unroll
+        for (int q = 1; q < kFbWaves; ++q)
+            sum += ((const double*)&sh.phx[q][0][0])[t];
+        double* dst = apart + ((size_t)blockIdx.x * N + k) * (nx * nv) + i * nv + j;
+        *dst = ADD ? *dst + sum : sum;
+    }
+    __syncthreads();
+}
+
+// Storage-free forward of the surrogate gradient (Section 6.5): G particles
+// per lane step together; each step adds alpha u_k phi(z_k) to the block's
+// partial and each particle's cost to the block's cost.
+template <typename Real, int NVP, int G>
+__global__ void __launch_bounds__(kThreads)
+k_fb_forward_grad(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __restrict__ zd,
+                  const Real* __restrict__ ks, double* __restrict__ cpart,
+                  double* __restrict__ apart) {
+    __shared__ FbShared<Real> sh;
+    __shared__ double red[kThreads];
+    FbWave<Real> wave = fb_wave(sh);
+    const int N = a.N;
+    Real x[G], v[G];
+    double acc[G];
+    int64_t m[G];
+    bool act[G];
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+        const int64_t g = (int64_t)blockIdx.x * G + j;
+        m[j] = g * kThreads + threadIdx.x;
+        act[j] = m[j] < a.M && g < a.nblk;
+        fb_initial(a, (uint32_t)m[j], x[j], v[j]);
+        fb_dump(a, a.dX, 0, m[j], x[j], v[j]);
+        acc[j] = 0.0;
+    }
+    for (int k = 0; k < N; ++k) {
+        const Real* mk = mu + (size_t)k * a.nx * NVP;
+        wave.clear();
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
+            const Real u = fb_step<Real, NVP>(a, mk, ks, (uint32_t)m[j], k, x[j], v[j], wave);
+            wave.template add<NVP>(act[j] ? a.alpha * u : (Real)0, a.nx);
+            acc[j] += (double)(a.hadt * u * u);
+            acc[j] += (double)(a.dt * track(a, x[j], v[j], zd + 2 * (k + 1)));
+            fb_dump(a, a.dX, k + 1, m[j], x[j], v[j]);
+        }
+        fb_block_partial<false>(sh, wave, k, N, a.nx, a.nv, apart);
+    }
+    double C = 0.0;
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+        const double c = act[j] ? acc[j] : 0.0;
+        if (a.dcost != nullptr) {
+            const int64_t p = m[j] - a.dm0;
+            if (act[j] && p >= 0 && p < a.dcount)
+                a.dcost[p] = c;
+        }
+        C += c;
+    }
+    const double s = block_sum(C, red);
+    if (threadIdx.x == 0)
+        cpart[blockIdx.x] = s;
+}
+
 // The adjoint state of one particle between steps.
 template <typename Real>
 struct FbAdj {
     Real x, v;    // z_k (current step)
-    Real xn, vn;  // z_{k-1}, loaded one step ahead
+    Real xn, vn;  // z_{k-1}, loaded one step ahead (stored trajectory)
     Real lx, lv;  // lam_{k+1} on entry to step k
 };
 
 // Backward sweep.  Each lane carries G particles (groups blockIdx.x G + j of
-// 256, j < G) through the steps together; at step k each particle in turn puts
-// its shape functions and weight w = alpha u + gamma^n lam^v into the wave's
-// LDS transpose and the wave adds its 64 particles' outer products
-// phi_x(x) w phi_v(v)^T to four independent matrix-core accumulators (16
-// MFMAs of K = 4 particles).  The four waves' sums are then combined in a
-// fixed order into one FP64 partial per block and step.
-template <typename Real, int NVP, int G>
+// 256, j < G) through the steps together; at step k each particle in turn adds
+// its shape functions times its weight to the wave's matrix-core sums, and the
+// four waves' sums form one FP64 partial per block and step.
+//   SURR = false: the states are the stored trajectory and the weight is
+//                 alpha u + gamma^n lam^v (the exact gradient);
+//   SURR = true:  the states are the surrogate states of Section 6.5 and the
+//                 weight gamma^n lam^v is added to the partials of
+//                 k_fb_forward_grad (which hold alpha u phi(z)).
+template <typename Real, int NVP, int G, bool SURR>
 __global__ void __launch_bounds__(kThreads)
 k_fb_adjoint(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __restrict__ zd,
              const Real* __restrict__ ks, const void* traj, double* __restrict__ apart) {
-    constexpr int kW = kThreads / 64;   // waves per block
-    constexpr int kS = kFbMaxGrid + 1;  // padded row stride of the transposes
-    static_assert(sizeof(Real) * 64 * kS >= sizeof(double) * kFbMaxGrid * kFbMaxGrid,
-                  "a wave's transpose buffer must hold its 16 x 16 FP64 tile");
-    __shared__ Real phx[kW][64][kS];  // after the MFMAs: the wave's FP64 tile
-    __shared__ Real phv[kW][64][kS];
-    __shared__ Real wts[kW][64];
-    const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
-    const int N = a.N, L = a.nx * a.nv;
-    const int ii = ln & 15;  // this lane's row of A and column of B
+    __shared__ FbShared<Real> sh;
+    FbWave<Real> wave = fb_wave(sh);
+    const int N = a.N;
     FbAdj<Real> s[G];
     const Real* row[G];
     bool act[G];
@@ -298,32 +467,38 @@ k_fb_adjoint(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __restrict
         const int64_t g = (int64_t)blockIdx.x * G + j;
         m[j] = g * kThreads + threadIdx.x;
         act[j] = m[j] < a.M && g < a.nblk;
-        row[j] = fb_row<Real>(const_cast<void*>(traj), N, g < a.nblk ? g : a.nblk - 1);
-        s[j].x = __builtin_nontemporal_load(row[j] + (size_t)N * 2 * kThreads);
-        s[j].v = __builtin_nontemporal_load(row[j] + (size_t)N * 2 * kThreads + kThreads);
+        if (SURR) {
+            row[j] = nullptr;
+            fb_surrogate(a, zd, (uint32_t)m[j], N, s[j].x, s[j].v);
+        } else {
+            row[j] = fb_row<Real>(const_cast<void*>(traj), N, g < a.nblk ? g : a.nblk - 1);
+            s[j].x = __builtin_nontemporal_load(row[j] + (size_t)N * 2 * kThreads);
+            s[j].v = __builtin_nontemporal_load(row[j] + (size_t)N * 2 * kThreads + kThreads);
+            s[j].xn = __builtin_nontemporal_load(row[j] + (size_t)(N - 1) * 2 * kThreads);
+            s[j].vn = __builtin_nontemporal_load(row[j] + (size_t)(N - 1) * 2 * kThreads + kThreads);
+        }
         Real gx, gv;
         track_grad(a, s[j].x, s[j].v, zd + 2 * N, gx, gv);
         s[j].lx = a.dt * gx;
         s[j].lv = a.dt * gv;
         if (act[j])
             fb_dump(a, a.dlam, N, m[j], s[j].lx, s[j].lv);
-        s[j].xn = __builtin_nontemporal_load(row[j] + (size_t)(N - 1) * 2 * kThreads);
-        s[j].vn = __builtin_nontemporal_load(row[j] + (size_t)(N - 1) * 2 * kThreads + kThreads);
     }
     for (int k = N - 1; k >= 0; --k) {
         const Real* mk = mu + (size_t)k * a.nx * NVP;
-        fb_d4 acc[4];
-#pragma unroll
-        for (int c = 0; c < 4; ++c)
-            acc[c] = fb_d4{0.0, 0.0, 0.0, 0.0};
+        wave.clear();
 #pragma unroll
         for (int j = 0; j < G; ++j) {
             FbAdj<Real>& st = s[j];
-            st.x = st.xn;
-            st.v = st.vn;
-            if (k >= 1) {
-                st.xn = __builtin_nontemporal_load(row[j] + (size_t)(k - 1) * 2 * kThreads);
-                st.vn = __builtin_nontemporal_load(row[j] + (size_t)(k - 1) * 2 * kThreads + kThreads);
+            if (SURR) {
+                fb_surrogate(a, zd, (uint32_t)m[j], k, st.x, st.v);
+            } else {
+                st.x = st.xn;
+                st.v = st.vn;
+                if (k >= 1) {
+                    st.xn = __builtin_nontemporal_load(row[j] + (size_t)(k - 1) * 2 * kThreads);
+                    st.vn = __builtin_nontemporal_load(row[j] + (size_t)(k - 1) * 2 * kThreads + kThreads);
+                }
             }
             Real pv[NVP], dpv[NVP];
 #pragma unroll
@@ -344,8 +519,9 @@ k_fb_adjoint(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __restrict
                 u = fma(bx, t, u);
                 ux = fma(dbx, t, ux);
                 uv = fma(bx, sv, uv);
-                phx[wv][ln][i] = bx;
+                wave.put_x(i, bx);
             }
+            wave.template put_v<Real, NVP>(pv);
             uint32_t w[4];
             philox4x32_10<true>((uint32_t)m[j], (uint32_t)k, a.iter, 0u, a.key0, a.key1, w);
             const int n = poisson_count(poisson_word(w), a.thr);
@@ -354,22 +530,8 @@ k_fb_adjoint(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __restrict
                 Real svn;
                 ks_factors(ks, n, gn, svn);
             }
-            const Real wk = act[j] ? fma(a.alpha, u, gn * st.lv) : (Real)0;
-#pragma unroll
-            for (int l = 0; l < NVP; ++l)
-                phv[wv][ln][l] = pv[l];
-            wts[wv][ln] = wk;
-            wave_lds_sync();
-            // A[i][kk] = phi_x_i(p) w_p, B[kk][jj] = phi_v_jj(p) for the
-            // particle p = 4q + kk (lane i + 16 kk supplies both)
-#pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                const int p = 4 * q + (ln >> 4);
-                const double av = ii < a.nx ? (double)phx[wv][p][ii] * (double)wts[wv][p] : 0.0;
-                const double bv = ii < NVP ? (double)phv[wv][p][ii] : 0.0;
-                acc[q & 3] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[q & 3], 0, 0, 0);
-            }
-            wave_lds_sync();
+            const Real wk = SURR ? gn * st.lv : fma(a.alpha, u, gn * st.lv);
+            wave.template add<NVP>(act[j] ? wk : (Real)0, a.nx);
             if (k >= 1) {
                 Real gx, gv;
                 track_grad(a, st.x, st.v, zd + 2 * k, gx, gv);
@@ -383,24 +545,7 @@ k_fb_adjoint(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __restrict
                     fb_dump(a, a.dlam, k, m[j], st.lx, st.lv);
             }
         }
-        // D[i][jj] sits in lane jj + 16 (i % 4), register i / 4; the wave's
-        // tile goes into its own transpose buffer (its reads are done)
-        double* cb = (double*)&phx[wv][0][0];
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-            cb[(4 * r + (ln >> 4)) * kFbMaxGrid + ii] = (acc[0][r] + acc[1][r]) + (acc[2][r] + acc[3][r]);
-        __syncthreads();
-        {
-            const int t = threadIdx.x, i = t >> 4, jj = t & 15;
-            if (i < a.nx && jj < a.nv) {
-                double sum = ((const double*)&phx[0][0][0])[t];
-#pragma unroll
-                for (int q = 1; q < kW; ++q)
-                    sum += ((const double*)&phx[q][0][0])[t];
-                apart[((size_t)blockIdx.x * N + k) * L + i * a.nv + jj] = sum;
-            }
-        }
-        __syncthreads();
+        fb_block_partial<SURR>(sh, wave, k, N, a.nx, a.nv, apart);
     }
 }
 
@@ -527,6 +672,10 @@ static FbArgs<Real> fb_args(const FbHost& p, const HostRun& r) {
     a.z0v = (Real)p.z0[1];
     a.s0x = (Real)p.s0[0];
     a.s0v = (Real)p.s0[1];
+    a.var0x = (Real)p.svar0[0];
+    a.var0v = (Real)p.svar0[1];
+    a.var1x = (Real)p.svar1[0];
+    a.var1v = (Real)p.svar1[1];
     a.init_kind = p.init_kind;
     a.key0 = (uint32_t)(r.seed & 0xFFFFFFFFu);
     a.key1 = (uint32_t)(r.seed >> 32);
@@ -617,50 +766,85 @@ int fb_adjoint_groups(int nblk) { return nblk >= 2048 ? 2 : 1; }
 
 template <typename Real>
 static hipError_t fb_adjoint_t(const FbHost& p, const HostRun& r, const void* tab, const void* traj,
-                               double* apart, const WsHeader* hdr, hipStream_t st) {
+                               double* apart, const WsHeader* hdr, bool surr, hipStream_t st) {
     const FbTable t = fb_table_layout(p);
     FbArgs<Real> a = fb_args<Real>(p, r);
     a.thr = &hdr->poisson;
     const Real* tb = (const Real*)tab;
     const int G = fb_adjoint_groups(r.nblk);
     const unsigned nb = (unsigned)((r.nblk + G - 1) / G);
+#define FB_ADJ_G(NVP, GG, S)                                                                      \
+    hipLaunchKernelGGL((k_fb_adjoint<Real, NVP, GG, S>), dim3(nb), dim3(kThreads), 0, st, a,      \
+                       tb + t.mu, tb + t.zd, tb + t.ks, traj, apart)
 #define FB_ADJ(NVP)                                                                               \
     do {                                                                                          \
-        if (G == 4)                                                                               \
-            hipLaunchKernelGGL((k_fb_adjoint<Real, NVP, 4>), dim3(nb), dim3(kThreads), 0, st, a,  \
-                               tb + t.mu, tb + t.zd, tb + t.ks, traj, apart);                     \
-        else if (G == 2)                                                                          \
-            hipLaunchKernelGGL((k_fb_adjoint<Real, NVP, 2>), dim3(nb), dim3(kThreads), 0, st, a,  \
-                               tb + t.mu, tb + t.zd, tb + t.ks, traj, apart);                     \
-        else                                                                                      \
-            hipLaunchKernelGGL((k_fb_adjoint<Real, NVP, 1>), dim3(nb), dim3(kThreads), 0, st, a,  \
-                               tb + t.mu, tb + t.zd, tb + t.ks, traj, apart);                     \
+        if (G == 2) {                                                                             \
+            if (surr) FB_ADJ_G(NVP, 2, true);                                                     \
+            else FB_ADJ_G(NVP, 2, false);                                                         \
+        } else {                                                                                  \
+            if (surr) FB_ADJ_G(NVP, 1, true);                                                     \
+            else FB_ADJ_G(NVP, 1, false);                                                         \
+        }                                                                                         \
     } while (0)
     FB_DISPATCH_NVP(p.nvp, FB_ADJ);
 #undef FB_ADJ
+#undef FB_ADJ_G
     return hipGetLastError();
 }
 
 hipError_t fb_launch_adjoint(const FbHost& p, const HostRun& r, const void* tab, const void* traj,
-                             double* apart, const WsHeader* hdr, hipStream_t st) {
-    return r.prec == JD_FP64 ? fb_adjoint_t<double>(p, r, tab, traj, apart, hdr, st)
-                             : fb_adjoint_t<float>(p, r, tab, traj, apart, hdr, st);
+                             double* apart, const WsHeader* hdr, bool surrogate, hipStream_t st) {
+    return r.prec == JD_FP64 ? fb_adjoint_t<double>(p, r, tab, traj, apart, hdr, surrogate, st)
+                             : fb_adjoint_t<float>(p, r, tab, traj, apart, hdr, surrogate, st);
+}
+
+template <typename Real>
+static hipError_t fb_forward_grad_t(const FbHost& p, const HostRun& r, const void* tab,
+                                    double* cpart, double* apart, const WsHeader* hdr,
+                                    hipStream_t st) {
+    const FbTable t = fb_table_layout(p);
+    FbArgs<Real> a = fb_args<Real>(p, r);
+    a.thr = &hdr->poisson;
+    const Real* tb = (const Real*)tab;
+    const int G = fb_adjoint_groups(r.nblk);
+    const unsigned nb = (unsigned)((r.nblk + G - 1) / G);
+#define FB_FG(NVP)                                                                                \
+    do {                                                                                          \
+        if (G == 2)                                                                               \
+            hipLaunchKernelGGL((k_fb_forward_grad<Real, NVP, 2>), dim3(nb), dim3(kThreads), 0, st, \
+                               a, tb + t.mu, tb + t.zd, tb + t.ks, cpart, apart);                 \
+        else                                                                                      \
+            hipLaunchKernelGGL((k_fb_forward_grad<Real, NVP, 1>), dim3(nb), dim3(kThreads), 0, st, \
+                               a, tb + t.mu, tb + t.zd, tb + t.ks, cpart, apart);                 \
+    } while (0)
+    FB_DISPATCH_NVP(p.nvp, FB_FG);
+#undef FB_FG
+    return hipGetLastError();
+}
+
+hipError_t fb_launch_forward_grad(const FbHost& p, const HostRun& r, const void* tab, double* cpart,
+                                  double* apart, const WsHeader* hdr, hipStream_t st) {
+    return r.prec == JD_FP64 ? fb_forward_grad_t<double>(p, r, tab, cpart, apart, hdr, st)
+                             : fb_forward_grad_t<float>(p, r, tab, cpart, apart, hdr, st);
+}
+
+int fb_partial_blocks(const HostRun& r) {
+    const int G = fb_adjoint_groups(r.nblk);
+    return (r.nblk + G - 1) / G;
 }
 
 hipError_t fb_launch_finalize_grad(const FbHost& p, const HostRun& r, const double* apart,
                                    double* g, WsHeader* hdr, hipStream_t st) {
     const int64_t NL = (int64_t)p.N * p.L;
-    const int G = fb_adjoint_groups(r.nblk);
-    const int nparts = (r.nblk + G - 1) / G;
     hipLaunchKernelGGL(k_fb_finalize_grad, dim3(fb_blocks(NL)), dim3(kThreads), 0, st, apart,
-                       nparts, NL, r.M, g, hdr);
+                       fb_partial_blocks(r), NL, r.M, g, hdr);
     return hipGetLastError();
 }
 
 hipError_t fb_launch_finalize_cost(const FbHost& p, const HostRun& r, const double* cpart,
-                                   const double* g, double* J_out, WsHeader* hdr, int slot,
-                                   hipStream_t st) {
-    hipLaunchKernelGGL(k_fb_finalize_cost, dim3(1), dim3(kThreads), 0, st, cpart, r.nblk, r.M,
+                                   int ncpart, const double* g, double* J_out, WsHeader* hdr,
+                                   int slot, hipStream_t st) {
+    hipLaunchKernelGGL(k_fb_finalize_cost, dim3(1), dim3(kThreads), 0, st, cpart, ncpart, r.M,
                        p.dt, g, (int64_t)p.N * p.L, J_out, hdr, slot);
     return hipGetLastError();
 }

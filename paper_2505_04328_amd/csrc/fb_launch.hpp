@@ -16,6 +16,7 @@ struct FbHost {
     double xmax, vmax, eps, alpha, sigJ;
     int init_kind;
     double z0[2], s0[2];
+    double svar0[2], svar1[2];  // surrogate-state variance var(t) = svar0 + svar1 t
     const double* zd;     // device (N+1) x 2
     double ks[64];        // gamma^n and sqrt(V_n) for n = 0..31
     uint64_t thr[32];     // Poisson(rate dt) thresholds
@@ -33,13 +34,21 @@ hipError_t fb_launch_table(const FbHost& p, const HostRun& r, const double* mu, 
                            WsHeader* hdr, int clear_flag, hipStream_t st);
 hipError_t fb_launch_forward(const FbHost& p, const HostRun& r, const void* tab, void* traj,
                              double* cpart, const WsHeader* hdr, hipStream_t st);
+// surrogate: the adjoint on the surrogate states, added to the partials of
+// fb_launch_forward_grad (Section 6.5); else the exact adjoint over traj.
 hipError_t fb_launch_adjoint(const FbHost& p, const HostRun& r, const void* tab, const void* traj,
-                             double* apart, const WsHeader* hdr, hipStream_t st);
+                             double* apart, const WsHeader* hdr, bool surrogate, hipStream_t st);
+// Storage-free forward that also writes the alpha u phi(z) part of the
+// gradient partials (surrogate gradient) and the per-block costs.
+hipError_t fb_launch_forward_grad(const FbHost& p, const HostRun& r, const void* tab, double* cpart,
+                                  double* apart, const WsHeader* hdr, hipStream_t st);
+// Number of per-block partials of the adjoint / forward_grad kernels.
+int fb_partial_blocks(const HostRun& r);
 hipError_t fb_launch_finalize_grad(const FbHost& p, const HostRun& r, const double* apart,
                                    double* g, WsHeader* hdr, hipStream_t st);
 hipError_t fb_launch_finalize_cost(const FbHost& p, const HostRun& r, const double* cpart,
-                                   const double* g, double* J_out, WsHeader* hdr, int slot,
-                                   hipStream_t st);
+                                   int ncpart, const double* g, double* J_out, WsHeader* hdr,
+                                   int slot, hipStream_t st);
 hipError_t fb_launch_draws(const FbHost& p, const HostRun& r, int64_t m0, int64_t mc, int k0,
                            int kc, void* z_init, void* Z, int32_t* counts, hipStream_t st);
 

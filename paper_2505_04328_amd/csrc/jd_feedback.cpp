@@ -34,7 +34,8 @@ int fb_prepare(const jd_fb_problem* prob, const jd_run* run, FbHost& p, HostRun&
     if (q.init_kind != JD_FB_INIT_GAUSS && q.init_kind != JD_FB_INIT_UNIFORM)
         return JD_EINVAL;
     for (int c = 0; c < 2; ++c)
-        if (!finite(q.z0[c]) || !(q.s0[c] >= 0.0) || !finite(q.s0[c]))
+        if (!finite(q.z0[c]) || !(q.s0[c] >= 0.0) || !finite(q.s0[c]) || !(q.svar0[c] >= 0.0) ||
+            !finite(q.svar0[c]) || !(q.svar1[c] >= 0.0) || !finite(q.svar1[c]))
             return JD_EINVAL;
     if (!q.zd)
         return JD_EINVAL;
@@ -48,7 +49,7 @@ int fb_prepare(const jd_fb_problem* prob, const jd_run* run, FbHost& p, HostRun&
         return JD_EINVAL;
     if (run->mode == JD_RECOMPUTE)
         return JD_EUNSUPPORTED;
-    if (run->mode != JD_STORE)
+    if (run->mode != JD_STORE && run->mode != JD_SURROGATE)
         return JD_EINVAL;
     if (run->dump) {
         const jd_dump* dp = run->dump;
@@ -79,6 +80,8 @@ int fb_prepare(const jd_fb_problem* prob, const jd_run* run, FbHost& p, HostRun&
     for (int c = 0; c < 2; ++c) {
         p.z0[c] = q.z0[c];
         p.s0[c] = q.s0[c];
+        p.svar0[c] = q.svar0[c];
+        p.svar1[c] = q.svar1[c];
     }
     p.zd = q.zd;
     // n jumps v <- gamma v + N(0, 1/(2 beta)) composed: gamma^n v + N(0, V_n),
@@ -98,7 +101,7 @@ int fb_prepare(const jd_fb_problem* prob, const jd_run* run, FbHost& p, HostRun&
     r.seed = run->seed;
     r.iter = run->iter;
     r.prec = run->precision;
-    r.mode = JD_STORE;
+    r.mode = run->mode;
     r.K = 0;
     r.nblk = (int)((run->M + kBlock - 1) / kBlock);
     r.dump = run->dump;
@@ -160,10 +163,17 @@ int fb_bind(const FbHost& p, const HostRun& r, void* ws, size_t ws_bytes, FbWs& 
 int fb_enqueue_cost_grad(const FbHost& p, const HostRun& r, const double* mu, double* J, double* g,
                          void* traj, const FbWs& w, hipStream_t st) {
     JD_TRY(fb_launch_table(p, r, mu, w.tab, w.hdr, 1, st));
+    if (r.mode == JD_SURROGATE) {
+        JD_TRY(fb_launch_forward_grad(p, r, w.tab, w.cpart, w.apart, w.hdr, st));
+        JD_TRY(fb_launch_adjoint(p, r, w.tab, nullptr, w.apart, w.hdr, true, st));
+        JD_TRY(fb_launch_finalize_grad(p, r, w.apart, g, w.hdr, st));
+        JD_TRY(fb_launch_finalize_cost(p, r, w.cpart, fb_partial_blocks(r), g, J, w.hdr, 0, st));
+        return JD_OK;
+    }
     JD_TRY(fb_launch_forward(p, r, w.tab, traj, w.cpart, w.hdr, st));
-    JD_TRY(fb_launch_adjoint(p, r, w.tab, traj, w.apart, w.hdr, st));
+    JD_TRY(fb_launch_adjoint(p, r, w.tab, traj, w.apart, w.hdr, false, st));
     JD_TRY(fb_launch_finalize_grad(p, r, w.apart, g, w.hdr, st));
-    JD_TRY(fb_launch_finalize_cost(p, r, w.cpart, g, J, w.hdr, 0, st));
+    JD_TRY(fb_launch_finalize_cost(p, r, w.cpart, r.nblk, g, J, w.hdr, 0, st));
     return JD_OK;
 }
 
@@ -173,7 +183,7 @@ int fb_enqueue_trial(const FbHost& p, const HostRun& r, double* mu, const jd_opt
     JD_TRY(launch_trial(mu, w.gbuf, zeta, w.ut, nl, st));
     JD_TRY(fb_launch_table(p, r, w.ut, w.tab, w.hdr, 0, st));
     JD_TRY(fb_launch_forward(p, r, w.tab, nullptr, w.cpart, w.hdr, st));
-    JD_TRY(fb_launch_finalize_cost(p, r, w.cpart, nullptr, nullptr, w.hdr, 1, st));
+    JD_TRY(fb_launch_finalize_cost(p, r, w.cpart, r.nblk, nullptr, nullptr, w.hdr, 1, st));
     JD_TRY(launch_armijo(w.hdr, mu, w.ut, nl, opt.c_armijo, zeta, p.dt, st));
     return JD_OK;
 }
@@ -212,7 +222,7 @@ int jd_fb_forward(const jd_fb_problem* prob, const jd_run* run, const double* mu
         return rc;
     JD_TRY(fb_launch_table(p, r, mu, w.tab, w.hdr, 1, stream));
     JD_TRY(fb_launch_forward(p, r, w.tab, traj, w.cpart, w.hdr, stream));
-    JD_TRY(fb_launch_finalize_cost(p, r, w.cpart, nullptr, J, w.hdr, 0, stream));
+    JD_TRY(fb_launch_finalize_cost(p, r, w.cpart, r.nblk, nullptr, J, w.hdr, 0, stream));
     return JD_OK;
 }
 
@@ -223,13 +233,15 @@ int jd_fb_adjoint(const jd_fb_problem* prob, const jd_run* run, const double* mu
     int rc = fb_prepare(prob, run, p, r);
     if (rc)
         return rc;
+    if (r.mode == JD_SURROGATE)
+        return JD_EUNSUPPORTED;
     if (!mu || !traj || !grad || !aligned(traj, real_size(r.prec)))
         return JD_EINVAL;
     FbWs w;
     if ((rc = fb_bind(p, r, ws, ws_bytes, w)))
         return rc;
     JD_TRY(fb_launch_table(p, r, mu, w.tab, w.hdr, 1, stream));
-    JD_TRY(fb_launch_adjoint(p, r, w.tab, traj, w.apart, w.hdr, stream));
+    JD_TRY(fb_launch_adjoint(p, r, w.tab, traj, w.apart, w.hdr, false, stream));
     JD_TRY(fb_launch_finalize_grad(p, r, w.apart, grad, w.hdr, stream));
     return JD_OK;
 }
@@ -241,7 +253,8 @@ int jd_fb_cost_grad(const jd_fb_problem* prob, const jd_run* run, const double* 
     int rc = fb_prepare(prob, run, p, r);
     if (rc)
         return rc;
-    if (!mu || !J || !grad || !traj || !aligned(traj, real_size(r.prec)))
+    const bool need_traj = r.mode == JD_STORE;
+    if (!mu || !J || !grad || (need_traj && !traj) || (traj && !aligned(traj, real_size(r.prec))))
         return JD_EINVAL;
     FbWs w;
     if ((rc = fb_bind(p, r, ws, ws_bytes, w)))
@@ -257,7 +270,9 @@ int jd_fb_optimize(const jd_fb_problem* prob, const jd_run* run, const jd_opt* o
     int rc = fb_prepare(prob, run, p, r);
     if (rc)
         return rc;
-    if (!mu || !traj || !aligned(traj, real_size(r.prec)) || validate_opt(opt))
+    const bool need_traj = r.mode == JD_STORE;
+    if (!mu || (need_traj && !traj) || (traj && !aligned(traj, real_size(r.prec))) ||
+        validate_opt(opt))
         return JD_EINVAL;
     FbWs w;
     if ((rc = fb_bind(p, r, ws, ws_bytes, w)))

@@ -229,7 +229,8 @@ class _FbDummy:
         self.p = p
         self.st = B.jd_fb_problem(p.N, p.nx, p.nv, p.T, p.eta, p.b1, p.b2, p.gamma, p.beta,
                                   p.xmax, p.vmax, p.eps, p.alpha, p.sigJ, p.init_kind,
-                                  (C.c_double * 2)(*p.z0), (C.c_double * 2)(*p.s0), 0x1000)
+                                  (C.c_double * 2)(*p.z0), (C.c_double * 2)(*p.s0),
+                                  (C.c_double * 2)(*p.svar0), (C.c_double * 2)(*p.svar1), 0x1000)
 
 
 def test_fb_workspace_and_traj_sizes(L):
@@ -265,6 +266,8 @@ def test_fb_invalid_arguments_rejected_before_launch(L):
         assert call(**kw) == B.JD_EINVAL, kw
     # rate * dt > 2
     assert call(beta=1e4, N=2, T=2.0) == B.JD_EINVAL
+    assert call(svar0=(C.c_double * 2)(-1.0, 0.0)) == B.JD_EINVAL
+    assert call(svar1=(C.c_double * 2)(0.0, float("inf"))) == B.JD_EINVAL
     pr = _FbDummy(wl.feedback_problem(N=20, T=2.0))
     P = C.byref(pr.st)
     assert L.jd_fb_forward(P, C.byref(run), None, fake, fake, fake, ws, None) == B.JD_EINVAL
@@ -273,6 +276,11 @@ def test_fb_invalid_arguments_rejected_before_launch(L):
     assert L.jd_fb_adjoint(P, C.byref(run), fake, None, fake, fake, ws, None) == B.JD_EINVAL
     rec = B.make_run(1000, mode="recompute", K=5)
     assert L.jd_fb_forward(P, C.byref(rec), fake, fake, fake, fake, ws, None) == B.JD_EUNSUPPORTED
+    sur = B.make_run(1000, mode="surrogate")
+    assert L.jd_fb_adjoint(P, C.byref(sur), fake, fake, fake, fake, ws, None) == B.JD_EUNSUPPORTED
+    # the storage-free surrogate gradient takes no trajectory, the exact one needs it
+    assert L.jd_fb_cost_grad(P, C.byref(sur), fake, fake, fake, None, fake, 100, None) == B.JD_EWORKSPACE
+    assert L.jd_fb_cost_grad(P, C.byref(run), fake, fake, fake, None, fake, 100, None) == B.JD_EINVAL
     bad_opt = B.jd_opt(3, 0, 0.0, 1.0, 0.5, 1e-4)
     assert L.jd_fb_optimize(P, C.byref(run), C.byref(bad_opt), fake, None, None, fake, fake, ws,
                             None) == B.JD_EINVAL

@@ -219,3 +219,73 @@ def test_fb_several_particles_per_lane(dev, M):
     e_J, e_g = rel_err(float(J), J_ref), norm_err(g.cpu().numpy(), g_ref)
     say(f"   J {e_J:.2e} g {e_g:.2e}")
     assert e_J <= TOL["fp32"]["J"] and e_g <= TOL["fp32"]["g"]
+
+
+# ---------------------------------------------------------------- surrogate gradient (Section 6.5)
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("name", ["paper_f1", "grid_3x5_uniform", "gamma_negative"])
+def test_fb_surrogate_cost_grad_and_paths(dev, name, precision):
+    """Storage-free surrogate gradient: J (exact cost), the surrogate gradient,
+    the forward states and costs, and the surrogate adjoints per particle."""
+    p, M, seed, scale = _problem(name)
+    say("surrogate", name, precision, f"M={M}")
+    mu = wl.random_feedback_control(p, 4, scale)
+    it = 2
+    z, _, _, _, C = ref.fb_paths(p, seed, it, 0, M, mu)
+    ls = ref.fb_paths_surrogate(p, seed, it, 0, M, mu)
+    J_ref, g_ref = ref.fb_cost_grad_surrogate(p, M, seed, it, mu)
+    eng = B.FbEngine(p, M=M, seed=seed, precision=precision, device=dev, mode="surrogate")
+    dp, d = eng.path_dump(0, M)
+    import torch
+    J, g = eng.cost_grad(mu, it=it)
+    J, g = float(J), g.cpu().numpy()
+    # the same call with dumps (the dumps do not change any result)
+    run = eng.run(it, dp)
+    Jd = torch.empty((), dtype=torch.float64, device=dev)
+    gd = torch.empty((p.N, p.L), dtype=torch.float64, device=dev)
+    import ctypes as C_
+    B.check(B.lib().jd_fb_cost_grad(eng.prob.ref, C_.byref(run), torch.tensor(mu, device=dev).data_ptr(),
+                                    Jd.data_ptr(), gd.data_ptr(), None, eng.ws.data_ptr(), eng.ws_bytes,
+                                    B._stream_ptr(dev)), "jd_fb_cost_grad")
+    torch.cuda.synchronize()
+    assert float(Jd) == J and np.array_equal(gd.cpu().numpy(), g)
+    tol = TOL[precision]
+    zg = np.transpose(d["X"].double().cpu().numpy(), (2, 0, 1))
+    lg = np.transpose(d["lam"].double().cpu().numpy(), (2, 0, 1))
+    e_z, e_l = per_path_error(zg, z), per_path_error(lg[:, 1:], ls[:, 1:])
+    e_c = float(np.max(np.abs(d["cost"].cpu().numpy() - C) / (np.abs(C) + np.sqrt(np.mean(C * C)))))
+    e_J, e_g = rel_err(J, J_ref), norm_err(g, g_ref)
+    say(f"   errors: z {e_z:.2e} lam {e_l:.2e} C {e_c:.2e} J {e_J:.2e} g {e_g:.2e}")
+    assert e_z <= tol["path"] and e_l <= tol["path"] and e_c <= tol["path"]
+    assert e_J <= tol["J"] and e_g <= tol["g"]
+    # biased: not the exact gradient
+    _, g_exact = ref.fb_cost_grad(p, M, seed, it, mu)
+    assert norm_err(g, g_exact) > 1e-3
+
+
+def test_fb_surrogate_two_groups_per_block(dev):
+    p = wl.feedback_problem(N=8, T=0.8, zd=_track(8, 0.8), alpha=0.1)
+    M = (1 << 19) + 100
+    mu = wl.random_feedback_control(p, 3, 1.0)
+    say("surrogate groups per block, M =", M)
+    eng = B.FbEngine(p, M=M, seed=17, precision="fp32", device=dev, mode="surrogate")
+    J, g = eng.cost_grad(mu, it=2)
+    J_ref, g_ref = ref.fb_cost_grad_surrogate(p, M, 17, 2, mu)
+    assert rel_err(float(J), J_ref) <= TOL["fp32"]["J"]
+    assert norm_err(g.cpu().numpy(), g_ref) <= TOL["fp32"]["g"]
+
+
+def test_fb_surrogate_optimize_matches_oracle(dev):
+    p, M, seed, _ = _problem("small_6x6")
+    mu0 = wl.random_feedback_control(p, 9, 0.5)
+    say("surrogate optimize fp64", M)
+    mu_o, logs_o, n_o = ref.fb_optimize(p, M, seed, 0, mu0, n_max=4, zeta0=8.0, surrogate=True)
+    eng = B.FbEngine(p, M=M, seed=seed, precision="fp64", device=dev, mode="surrogate")
+    import torch
+    mu = torch.tensor(mu0, dtype=torch.float64, device=dev)
+    _, logs = eng.optimize(mu, n_max=4, zeta0=8.0)
+    assert n_o == 4 and len(logs) == 4
+    for a, b in zip(logs, logs_o):
+        assert a["zeta"] == b["zeta"] and a["backtracks"] == b["backtracks"]
+        assert abs(a["J"] - b["J"]) <= 1e-12 * abs(b["J"])
+    assert norm_err(mu.cpu().numpy(), mu_o) <= 1e-11
