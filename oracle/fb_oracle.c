@@ -21,7 +21,10 @@
  *   adjoint     eq. adjoint_eq_approximation with lam = -r and the jump
  *               condition p <- gamma p (Section 4, adjoint model);
  *   gradient    eq. definition_Gradient (Psi^T r = phi p);
- *   iteration   Algorithm 5.4 with eq. Stochastic_Armijo.
+ *   iteration   Algorithm 5.4 with eq. Stochastic_Armijo;
+ *   coupling    eq. interacting_model on a ring, the ellipse cost of
+ *               eq. phonon_functional_tracking and the start on the ellipse
+ *               of eq. coupled_ellipse (Section 6.4).
  */
 #include "fb_oracle.h"
 
@@ -75,6 +78,12 @@ void fb_initial(const fb_problem* pb, uint64_t seed, uint32_t m, uint32_t iter, 
         double R = sqrt(-2.0 * log(ua));
         z[0] = pb->z0[0] + pb->s0[0] * R * cos(FB_TWO_PI * ub);
         z[1] = pb->z0[1] + pb->s0[1] * R * sin(FB_TWO_PI * ub);
+    } else if (pb->init_kind == 2) {
+        /* particle j = m mod np of its ring, at parameter angle 2 pi j / np */
+        double th = FB_TWO_PI * (double)(m % (uint32_t)pb->np) / (double)pb->np;
+        double R = sqrt(-2.0 * log(ua));
+        z[0] = pb->ax * cos(th) + pb->s0[0] * R * cos(FB_TWO_PI * ub);
+        z[1] = pb->av * sin(th) + pb->s0[1] * R * sin(FB_TWO_PI * ub);
     } else {
         z[0] = pb->z0[0] + pb->s0[0] * (2.0 * ua - 1.0);
         z[1] = pb->z0[1] + pb->s0[1] * (2.0 * ub - 1.0);
@@ -121,9 +130,15 @@ void fb_surrogate_state(const fb_problem* pb, uint64_t seed, uint32_t m, uint32_
 
 static int check_problem(const fb_problem* pb)
 {
-    if (!pb || pb->N < 1 || pb->nx < 1 || pb->nv < 1 || pb->nx > 16 || pb->nv > 16)
+    if (!pb || pb->N < 1 || pb->nx < 1 || pb->nv < 1 || pb->nx > 16 || pb->nv > 16 || pb->np < 1)
         return -1;
-    if (!(pb->T > 0.0) || !(pb->beta > 0.0) || !(pb->eps > 0.0) || !(pb->sigJ > 0.0) || !pb->zd)
+    if (!(pb->T > 0.0) || !(pb->beta > 0.0) || !(pb->eps > 0.0) || !(pb->sigJ > 0.0))
+        return -1;
+    if (pb->cost_kind != 0 && pb->cost_kind != 1)
+        return -1;
+    if ((pb->cost_kind == 0 && !pb->zd) || pb->init_kind < 0 || pb->init_kind > 2)
+        return -1;
+    if ((pb->cost_kind == 1 || pb->init_kind == 2) && !(pb->ax > 0.0 && pb->av > 0.0))
         return -1;
     if (!(pb->xmax > 0.0) || !(pb->vmax > 0.0) || pb->gamma < -1.0 || pb->gamma > 1.0)
         return -1;
@@ -170,17 +185,39 @@ static double control(const fb_problem* pb, const double* mu, const double* px, 
     return u;
 }
 
-static double track(const fb_problem* pb, const double z[2], const double* zd)
+/* Ellipse defect q = x^2/ax^2 + v^2/av^2 - 1 (zero on the ellipse). */
+static double ellipse_q(const fb_problem* pb, const double z[2])
 {
+    return z[0] * z[0] / (pb->ax * pb->ax) + z[1] * z[1] / (pb->av * pb->av) - 1.0;
+}
+
+/* Running cost at step k: the tracking cost -exp(-|z - zd_k|^2/(2 sigJ^2)), or
+ * the ellipse cost -exp(-q^2/(2 sigJ^2)). */
+static double track(const fb_problem* pb, const double z[2], int k)
+{
+    if (pb->cost_kind == 1) {
+        double q = ellipse_q(pb, z);
+        return -exp(-(q * q) / (2.0 * pb->sigJ * pb->sigJ));
+    }
+    const double* zd = pb->zd + 2 * k;
     double rx = z[0] - zd[0], rv = z[1] - zd[1];
     return -exp(-(rx * rx + rv * rv) / (2.0 * pb->sigJ * pb->sigJ));
 }
 
-/* Gradient of the tracking cost: (z - zd)/sigJ^2 * exp(-|z - zd|^2/(2 sigJ^2)). */
-static void track_grad(const fb_problem* pb, const double z[2], const double* zd, double gz[2])
+/* Its gradient: (z - zd)/sigJ^2 * exp(-|z - zd|^2/(2 sigJ^2)), or
+ * q/sigJ^2 * exp(-q^2/(2 sigJ^2)) * (2x/ax^2, 2v/av^2). */
+static void track_grad(const fb_problem* pb, const double z[2], int k, double gz[2])
 {
-    double rx = z[0] - zd[0], rv = z[1] - zd[1];
     double s2 = pb->sigJ * pb->sigJ;
+    if (pb->cost_kind == 1) {
+        double q = ellipse_q(pb, z);
+        double e = q / s2 * exp(-(q * q) / (2.0 * s2));
+        gz[0] = e * 2.0 * z[0] / (pb->ax * pb->ax);
+        gz[1] = e * 2.0 * z[1] / (pb->av * pb->av);
+        return;
+    }
+    const double* zd = pb->zd + 2 * k;
+    double rx = z[0] - zd[0], rv = z[1] - zd[1];
     double e = exp(-(rx * rx + rv * rv) / (2.0 * s2));
     gz[0] = rx / s2 * e;
     gz[1] = rv / s2 * e;
@@ -199,23 +236,29 @@ static void ks_factors(const fb_problem* pb, int n, double* gn, double* Vn)
     *Vn = s / (2.0 * pb->beta);
 }
 
+/* Work arrays of one system of np particles; z and lam are indexed
+ * [(k np + j) 2 + c], u and n [k np + j]. */
 typedef struct {
-    double *z, *u, *px, *pv, *dpx, *dpv, *lam;
+    double *z, *u, *px, *pv, *dpx, *dpv, *lam, *C, *w;
     int *n;
 } work;
 
 static int work_alloc(const fb_problem* pb, work* w)
 {
-    size_t N = (size_t)pb->N;
-    w->z = (double*)malloc((N + 1) * 2 * sizeof(double));
-    w->lam = (double*)malloc((N + 1) * 2 * sizeof(double));
-    w->u = (double*)malloc(N * sizeof(double));
-    w->n = (int*)malloc(N * sizeof(int));
+    size_t N = (size_t)pb->N, np = (size_t)pb->np;
+    w->z = (double*)malloc((N + 1) * np * 2 * sizeof(double));
+    w->lam = (double*)malloc((N + 1) * np * 2 * sizeof(double));
+    w->u = (double*)malloc(N * np * sizeof(double));
+    w->n = (int*)malloc(N * np * sizeof(int));
+    w->C = (double*)malloc(np * sizeof(double));
+    w->w = (double*)malloc(np * sizeof(double));
     w->px = (double*)malloc(16 * sizeof(double));
     w->pv = (double*)malloc(16 * sizeof(double));
     w->dpx = (double*)malloc(16 * sizeof(double));
     w->dpv = (double*)malloc(16 * sizeof(double));
-    return (w->z && w->lam && w->u && w->n && w->px && w->pv && w->dpx && w->dpv) ? 0 : -2;
+    return (w->z && w->lam && w->u && w->n && w->C && w->w && w->px && w->pv && w->dpx && w->dpv)
+               ? 0
+               : -2;
 }
 
 static void work_free(work* w)
@@ -224,79 +267,136 @@ static void work_free(work* w)
     free(w->lam);
     free(w->u);
     free(w->n);
+    free(w->C);
+    free(w->w);
     free(w->px);
     free(w->pv);
     free(w->dpx);
     free(w->dpv);
 }
 
-/* Forward sweep of path m (eq. SDE_splitted_drift_Euler on the fixed grid,
- * the step's n jumps applied after its Euler update): fills w->z, w->u, w->n
- * and returns the path cost. */
+/* Ring neighbours of particle j. */
+static int left_of(const fb_problem* pb, int j) { return (j + pb->np - 1) % pb->np; }
+static int right_of(const fb_problem* pb, int j) { return (j + 1) % pb->np; }
+
+/* Forward sweep of system m (eq. SDE_splitted_drift_Euler on the fixed grid,
+ * with the nearest-neighbour force of eq. interacting_model; the step's n
+ * jumps applied after its Euler update): fills w->z, w->u, w->n and the
+ * particle costs w->C, and returns their sum. */
 static double path_forward(const fb_problem* pb, const uint64_t thr[32], uint64_t seed,
                            uint32_t iter, uint32_t m, const double* mu, work* w)
 {
-    const int N = pb->N, L = pb->nx * pb->nv;
+    const int N = pb->N, L = pb->nx * pb->nv, np = pb->np;
     const double dt = pb->T / (double)N, sq = sqrt(dt);
-    fb_initial(pb, seed, m, iter, w->z);
-    double C = 0.0;
-    for (int k = 0; k < N; ++k) {
-        const double* zk = w->z + 2 * k;
-        double* zn = w->z + 2 * (k + 1);
-        shapes(pb, zk, w->px, w->pv, NULL, NULL);
-        double u = control(pb, mu + (size_t)k * L, w->px, w->pv);
-        w->u[k] = u;
-        C += dt * 0.5 * pb->alpha * u * u;
-        double Z[3];
-        int n;
-        fb_step_draws(seed, m, (uint32_t)k, iter, thr, Z, &n);
-        w->n[k] = n;
-        double gn, Vn;
-        ks_factors(pb, n, &gn, &Vn);
-        zn[0] = zk[0] + dt * zk[1] + pb->b1 * sq * Z[0];
-        double vs = zk[1] + dt * (u - pb->eta * zk[0]) + pb->b2 * sq * Z[1];
-        zn[1] = gn * vs + sqrt(Vn) * Z[2];
-        C += dt * track(pb, zn, pb->zd + 2 * (k + 1));
+    for (int j = 0; j < np; ++j) {
+        fb_initial(pb, seed, m * (uint32_t)np + (uint32_t)j, iter, w->z + 2 * j);
+        w->C[j] = 0.0;
     }
+    for (int k = 0; k < N; ++k) {
+        for (int j = 0; j < np; ++j) {
+            const double* zk = w->z + 2 * (k * np + j);
+            double* zn = w->z + 2 * ((k + 1) * np + j);
+            const double xl = w->z[2 * (k * np + left_of(pb, j))];
+            const double xr = w->z[2 * (k * np + right_of(pb, j))];
+            shapes(pb, zk, w->px, w->pv, NULL, NULL);
+            double u = control(pb, mu + (size_t)k * L, w->px, w->pv);
+            w->u[k * np + j] = u;
+            w->C[j] += dt * 0.5 * pb->alpha * u * u;
+            double Z[3];
+            int n;
+            fb_step_draws(seed, m * (uint32_t)np + (uint32_t)j, (uint32_t)k, iter, thr, Z, &n);
+            w->n[k * np + j] = n;
+            double gn, Vn;
+            ks_factors(pb, n, &gn, &Vn);
+            zn[0] = zk[0] + dt * zk[1] + pb->b1 * sq * Z[0];
+            double vs = zk[1] + dt * (u - pb->eta * zk[0] - pb->omega * (2.0 * zk[0] - xl - xr))
+                        + pb->b2 * sq * Z[1];
+            zn[1] = gn * vs + sqrt(Vn) * Z[2];
+            w->C[j] += dt * track(pb, zn, k + 1);
+        }
+    }
+    double C = 0.0;
+    for (int j = 0; j < np; ++j)
+        C += w->C[j];
     return C;
 }
 
-/* Backward adjoint of the path held in w (eq. adjoint_eq_approximation, lam =
- * dC/dz = -r): fills w->lam[k] for k = N..1 and, if G is given, adds the
- * path's gradient summand phi(z_k) (alpha u_k + gamma^{n_k} lam^v_{k+1}) to
- * G[k*L + l]. */
+/* Backward adjoint of the system held in w (eq. adjoint_eq_approximation,
+ * lam_j = dC/dz_j for C the sum of the particle costs, lam = -r): fills
+ * w->lam for k = N..1 and, if G is given, adds each particle's gradient
+ * summand phi(z_k) (alpha u_k + gamma^{n_k} lam^v_{k+1}) to G[k*L + l]. */
 static void path_adjoint(const fb_problem* pb, const double* mu, work* w, double* G)
 {
-    const int N = pb->N, L = pb->nx * pb->nv;
+    const int N = pb->N, L = pb->nx * pb->nv, np = pb->np;
     const double dt = pb->T / (double)N;
     double gz[2];
-    track_grad(pb, w->z + 2 * N, pb->zd + 2 * N, gz);
-    w->lam[2 * N] = dt * gz[0];
-    w->lam[2 * N + 1] = dt * gz[1];
-    for (int k = N - 1; k >= 0; --k) {
-        const double* zk = w->z + 2 * k;
-        const double lx = w->lam[2 * (k + 1)], lv = w->lam[2 * (k + 1) + 1];
-        const double* mk = mu + (size_t)k * L;
-        shapes(pb, zk, w->px, w->pv, w->dpx, w->dpv);
-        double u = w->u[k];
-        double gn, Vn;
-        ks_factors(pb, w->n[k], &gn, &Vn);
-        if (G) {
-            double wk = pb->alpha * u + gn * lv;
-            for (int i = 0; i < pb->nx; ++i)
-                for (int l = 0; l < pb->nv; ++l)
-                    G[(size_t)k * L + i * pb->nv + l] += w->px[i] * w->pv[l] * wk;
-        }
-        if (k == 0)
-            break;
-        double ux = control(pb, mk, w->dpx, w->pv);
-        double uv = control(pb, mk, w->px, w->dpv);
-        track_grad(pb, zk, pb->zd + 2 * k, gz);
-        w->lam[2 * k] = lx + gn * dt * (ux - pb->eta) * lv + dt * gz[0] + dt * pb->alpha * u * ux;
-        w->lam[2 * k + 1] = dt * lx + gn * (1.0 + dt * uv) * lv + dt * gz[1] + dt * pb->alpha * u * uv;
+    for (int j = 0; j < np; ++j) {
+        track_grad(pb, w->z + 2 * (N * np + j), N, gz);
+        w->lam[2 * (N * np + j)] = dt * gz[0];
+        w->lam[2 * (N * np + j) + 1] = dt * gz[1];
     }
-    w->lam[0] = 0.0;
-    w->lam[1] = 0.0;
+    for (int k = N - 1; k >= 0; --k) {
+        const double* mk = mu + (size_t)k * L;
+        /* w_j = gamma^{n_j} lam^v_{j,k+1}: what the velocity update passes back */
+        for (int j = 0; j < np; ++j) {
+            double gn, Vn;
+            ks_factors(pb, w->n[k * np + j], &gn, &Vn);
+            w->w[j] = gn * w->lam[2 * ((k + 1) * np + j) + 1];
+        }
+        for (int j = 0; j < np; ++j) {
+            const double* zk = w->z + 2 * (k * np + j);
+            const double lx = w->lam[2 * ((k + 1) * np + j)], lv = w->lam[2 * ((k + 1) * np + j) + 1];
+            shapes(pb, zk, w->px, w->pv, w->dpx, w->dpv);
+            double u = w->u[k * np + j];
+            double gn, Vn;
+            ks_factors(pb, w->n[k * np + j], &gn, &Vn);
+            if (G) {
+                double wk = pb->alpha * u + gn * lv;
+                for (int i = 0; i < pb->nx; ++i)
+                    for (int l = 0; l < pb->nv; ++l)
+                        G[(size_t)k * L + i * pb->nv + l] += w->px[i] * w->pv[l] * wk;
+            }
+            if (k == 0)
+                continue;
+            double ux = control(pb, mk, w->dpx, w->pv);
+            double uv = control(pb, mk, w->px, w->dpv);
+            double cpl = w->w[left_of(pb, j)] + w->w[right_of(pb, j)] - 2.0 * w->w[j];
+            track_grad(pb, zk, k, gz);
+            w->lam[2 * (k * np + j)] = lx + gn * dt * (ux - pb->eta) * lv + dt * pb->omega * cpl +
+                                       dt * gz[0] + dt * pb->alpha * u * ux;
+            w->lam[2 * (k * np + j) + 1] =
+                dt * lx + gn * (1.0 + dt * uv) * lv + dt * gz[1] + dt * pb->alpha * u * uv;
+        }
+    }
+    for (int j = 0; j < np; ++j) {
+        w->lam[2 * j] = 0.0;
+        w->lam[2 * j + 1] = 0.0;
+    }
+}
+
+/* Copies the system's per-particle rows into particle-major outputs. */
+static void copy_rows(const fb_problem* pb, const work* w, int64_t p0, double* z, double* lam,
+                      double* u, int32_t* jumps, double* C)
+{
+    const int N = pb->N, np = pb->np;
+    for (int j = 0; j < np; ++j) {
+        const size_t p = (size_t)p0 + (size_t)j;
+        for (int k = 0; k <= N; ++k)
+            for (int c = 0; c < 2; ++c) {
+                if (z)
+                    z[(p * (N + 1) + k) * 2 + c] = w->z[2 * (k * np + j) + c];
+                if (lam)
+                    lam[(p * (N + 1) + k) * 2 + c] = w->lam[2 * (k * np + j) + c];
+            }
+        for (int k = 0; k < N; ++k) {
+            if (u)
+                u[p * N + k] = w->u[k * np + j];
+            if (jumps)
+                jumps[p * N + k] = w->n[k * np + j];
+        }
+        if (C)
+            C[p] = w->C[j];
+    }
 }
 
 int fb_paths(const fb_problem* pb, uint64_t seed, uint32_t iter, int64_t m0, int64_t count,
@@ -305,7 +405,6 @@ int fb_paths(const fb_problem* pb, uint64_t seed, uint32_t iter, int64_t m0, int
 {
     if (check_problem(pb) || !mu || m0 < 0 || count < 0)
         return -1;
-    const int N = pb->N;
     uint64_t thr[32];
     or_poisson_thresholds(rate_dt(pb), thr);
     int rc = 0;
@@ -319,20 +418,10 @@ int fb_paths(const fb_problem* pb, uint64_t seed, uint32_t iter, int64_t m0, int
             for (int64_t p = 0; p < count; ++p) {
                 if (!ok)
                     continue;
-                double c = path_forward(pb, thr, seed, iter, (uint32_t)(m0 + p), mu, &w);
-                if (C)
-                    C[p] = c;
-                if (z)
-                    memcpy(z + (size_t)p * (N + 1) * 2, w.z, (size_t)(N + 1) * 2 * sizeof(double));
-                if (u)
-                    memcpy(u + (size_t)p * N, w.u, (size_t)N * sizeof(double));
-                if (jumps)
-                    for (int k = 0; k < N; ++k)
-                        jumps[(size_t)p * N + k] = w.n[k];
-                if (lam) {
+                path_forward(pb, thr, seed, iter, (uint32_t)(m0 + p), mu, &w);
+                if (lam)
                     path_adjoint(pb, mu, &w, NULL);
-                    memcpy(lam + (size_t)p * (N + 1) * 2, w.lam, (size_t)(N + 1) * 2 * sizeof(double));
-                }
+                copy_rows(pb, &w, p * pb->np, z, lam, u, jumps, C);
             }
         }
         work_free(&w);
@@ -340,8 +429,15 @@ int fb_paths(const fb_problem* pb, uint64_t seed, uint32_t iter, int64_t m0, int
     return rc ? -2 : 0;
 }
 
-/* Monte Carlo reductions in chunks of FB_CHUNK consecutive paths, each chunk
- * in path order and the chunks in index order (thread-count independent). */
+/* Systems per reduction chunk: FB_CHUNK particles' worth, at least one. */
+static int64_t chunk_systems(const fb_problem* pb)
+{
+    return pb->np >= FB_CHUNK ? 1 : FB_CHUNK / pb->np;
+}
+
+/* Monte Carlo reductions in chunks of consecutive systems, each chunk in
+ * system order and the chunks in index order (thread-count independent);
+ * the means are over the M np particles. */
 int fb_cost_grad(const fb_problem* pb, int64_t M, uint64_t seed, uint32_t iter,
                  const double* mu, double* J, double* g, int nthreads)
 {
@@ -349,7 +445,9 @@ int fb_cost_grad(const fb_problem* pb, int64_t M, uint64_t seed, uint32_t iter,
         return -1;
     const int N = pb->N, L = pb->nx * pb->nv;
     const size_t nl = (size_t)N * L;
-    const int64_t nchunk = (M + FB_CHUNK - 1) / FB_CHUNK;
+    const int64_t cs_sys = chunk_systems(pb);
+    const int64_t nchunk = (M + cs_sys - 1) / cs_sys;
+    const double P = (double)M * (double)pb->np;
     uint64_t thr[32];
     or_poisson_thresholds(rate_dt(pb), thr);
     double* csum = (double*)calloc((size_t)nchunk, sizeof(double));
@@ -370,7 +468,7 @@ int fb_cost_grad(const fb_problem* pb, int64_t M, uint64_t seed, uint32_t iter,
             for (int64_t c = 0; c < nchunk; ++c) {
                 if (!ok)
                     continue;
-                int64_t mb = c * FB_CHUNK, me = mb + FB_CHUNK < M ? mb + FB_CHUNK : M;
+                int64_t mb = c * cs_sys, me = mb + cs_sys < M ? mb + cs_sys : M;
                 double cs = 0.0;
                 for (int64_t m = mb; m < me; ++m) {
                     cs += path_forward(pb, thr, seed, iter, (uint32_t)m, mu, &w);
@@ -390,13 +488,13 @@ int fb_cost_grad(const fb_problem* pb, int64_t M, uint64_t seed, uint32_t iter,
     double ctot = 0.0;
     for (int64_t c = 0; c < nchunk; ++c)
         ctot += csum[c];
-    *J = ctot / (double)M;
+    *J = ctot / P;
     if (g) {
         for (size_t q = 0; q < nl; ++q) {
             double t = 0.0;
             for (int64_t c = 0; c < nchunk; ++c)
                 t += gsum[(size_t)c * nl + q];
-            g[q] = t / (double)M;
+            g[q] = t / P;
         }
     }
     free(csum);
@@ -406,7 +504,7 @@ int fb_cost_grad(const fb_problem* pb, int64_t M, uint64_t seed, uint32_t iter,
 
 /* The surrogate adjoint of path m (forward jump counts in w->n): the recursion
  * of path_adjoint at the states zs_k; adds gamma^{n_k} ls^v_{k+1} phi(zs_k) to
- * G.  Writes the surrogate adjoint into w->lam. */
+ * G.  Writes the surrogate adjoint into w->lam.  Independent particles only. */
 static void path_adjoint_surrogate(const fb_problem* pb, const double* mu, uint64_t seed,
                                    uint32_t iter, uint32_t m, work* w, double* G)
 {
@@ -414,7 +512,7 @@ static void path_adjoint_surrogate(const fb_problem* pb, const double* mu, uint6
     const double dt = pb->T / (double)N;
     double zs[2], gz[2];
     fb_surrogate_state(pb, seed, m, (uint32_t)N, iter, zs);
-    track_grad(pb, zs, pb->zd + 2 * N, gz);
+    track_grad(pb, zs, N, gz);
     double lx = dt * gz[0], lv = dt * gz[1];
     w->lam[2 * N] = lx;
     w->lam[2 * N + 1] = lv;
@@ -432,7 +530,7 @@ static void path_adjoint_surrogate(const fb_problem* pb, const double* mu, uint6
         double u = control(pb, mk, w->px, w->pv);
         double ux = control(pb, mk, w->dpx, w->pv);
         double uv = control(pb, mk, w->px, w->dpv);
-        track_grad(pb, zs, pb->zd + 2 * k, gz);
+        track_grad(pb, zs, k, gz);
         double nlx = lx + gn * dt * (ux - pb->eta) * lv + dt * gz[0] + dt * pb->alpha * u * ux;
         double nlv = dt * lx + gn * (1.0 + dt * uv) * lv + dt * gz[1] + dt * pb->alpha * u * uv;
         lx = nlx;
@@ -444,10 +542,15 @@ static void path_adjoint_surrogate(const fb_problem* pb, const double* mu, uint6
     w->lam[1] = 0.0;
 }
 
+static int check_surrogate(const fb_problem* pb)
+{
+    return check_problem(pb) || pb->np != 1 || !pb->zd ? -1 : 0;
+}
+
 int fb_paths_surrogate(const fb_problem* pb, uint64_t seed, uint32_t iter, int64_t m0, int64_t count,
                        const double* mu, double* lam, int nthreads)
 {
-    if (check_problem(pb) || !mu || !lam || m0 < 0 || count < 0)
+    if (check_surrogate(pb) || !mu || !lam || m0 < 0 || count < 0)
         return -1;
     const int N = pb->N, L = pb->nx * pb->nv;
     uint64_t thr[32];
@@ -477,7 +580,7 @@ int fb_paths_surrogate(const fb_problem* pb, uint64_t seed, uint32_t iter, int64
 int fb_cost_grad_surrogate(const fb_problem* pb, int64_t M, uint64_t seed, uint32_t iter,
                            const double* mu, double* J, double* g, int nthreads)
 {
-    if (check_problem(pb) || M < 1 || !mu || !J || !g)
+    if (check_surrogate(pb) || M < 1 || !mu || !J || !g)
         return -1;
     const int N = pb->N, L = pb->nx * pb->nv;
     const size_t nl = (size_t)N * L;
@@ -541,16 +644,18 @@ int fb_cost_grad_surrogate(const fb_problem* pb, int64_t M, uint64_t seed, uint3
     return 0;
 }
 
-/* Forward-mode derivative of J along dmu: differentiates the Euler step, the
- * jump composition and the cost directly, independently of the adjoint. */
+/* Forward-mode derivative of J along dmu: differentiates the Euler step with
+ * its coupling, the jump composition and the cost directly, independently of
+ * the adjoint.  t holds the tangents (dx_j, dv_j) of the current step. */
 int fb_tangent(const fb_problem* pb, int64_t M, uint64_t seed, uint32_t iter,
                const double* mu, const double* dmu, double* dJ, int nthreads)
 {
     if (check_problem(pb) || M < 1 || !mu || !dmu || !dJ)
         return -1;
-    const int N = pb->N, L = pb->nx * pb->nv;
+    const int N = pb->N, L = pb->nx * pb->nv, np = pb->np;
     const double dt = pb->T / (double)N;
-    const int64_t nchunk = (M + FB_CHUNK - 1) / FB_CHUNK;
+    const int64_t cs_sys = chunk_systems(pb);
+    const int64_t nchunk = (M + cs_sys - 1) / cs_sys;
     uint64_t thr[32];
     or_poisson_thresholds(rate_dt(pb), thr);
     double* csum = (double*)calloc((size_t)nchunk, sizeof(double));
@@ -560,48 +665,60 @@ int fb_tangent(const fb_problem* pb, int64_t M, uint64_t seed, uint32_t iter,
 #pragma omp parallel num_threads(nthreads > 0 ? nthreads : 1) reduction(| : rc)
     {
         work w;
-        const int ok = work_alloc(pb, &w) == 0;
+        double* t = (double*)malloc((size_t)np * 4 * sizeof(double));
+        const int ok = work_alloc(pb, &w) == 0 && t;
         rc |= ok ? 0 : 1;
         {
 #pragma omp for schedule(dynamic, 1)
             for (int64_t c = 0; c < nchunk; ++c) {
                 if (!ok)
                     continue;
-                int64_t mb = c * FB_CHUNK, me = mb + FB_CHUNK < M ? mb + FB_CHUNK : M;
+                int64_t mb = c * cs_sys, me = mb + cs_sys < M ? mb + cs_sys : M;
                 double cs = 0.0;
                 for (int64_t m = mb; m < me; ++m) {
                     path_forward(pb, thr, seed, iter, (uint32_t)m, mu, &w);
-                    double tx = 0.0, tv = 0.0, dc = 0.0;
+                    double* tn = t + 2 * np;
+                    for (int j = 0; j < 2 * np; ++j)
+                        t[j] = 0.0;
+                    double dc = 0.0;
                     for (int k = 0; k < N; ++k) {
-                        const double* zk = w.z + 2 * k;
                         const double* mk = mu + (size_t)k * L;
-                        shapes(pb, zk, w.px, w.pv, w.dpx, w.dpv);
-                        double u = w.u[k];
-                        double du = control(pb, mk, w.dpx, w.pv) * tx +
-                                    control(pb, mk, w.px, w.dpv) * tv +
-                                    control(pb, dmu + (size_t)k * L, w.px, w.pv);
-                        dc += dt * pb->alpha * u * du;
-                        double gn, Vn;
-                        ks_factors(pb, w.n[k], &gn, &Vn);
-                        double nx = tx + dt * tv;
-                        double nv = gn * (tv + dt * (du - pb->eta * tx));
-                        tx = nx;
-                        tv = nv;
-                        double gz[2];
-                        track_grad(pb, w.z + 2 * (k + 1), pb->zd + 2 * (k + 1), gz);
-                        dc += dt * (gz[0] * tx + gz[1] * tv);
+                        for (int j = 0; j < np; ++j) {
+                            const double* zk = w.z + 2 * (k * np + j);
+                            const double tx = t[2 * j], tv = t[2 * j + 1];
+                            shapes(pb, zk, w.px, w.pv, w.dpx, w.dpv);
+                            double u = w.u[k * np + j];
+                            double du = control(pb, mk, w.dpx, w.pv) * tx +
+                                        control(pb, mk, w.px, w.dpv) * tv +
+                                        control(pb, dmu + (size_t)k * L, w.px, w.pv);
+                            dc += dt * pb->alpha * u * du;
+                            double gn, Vn;
+                            ks_factors(pb, w.n[k * np + j], &gn, &Vn);
+                            double txl = t[2 * left_of(pb, j)], txr = t[2 * right_of(pb, j)];
+                            tn[2 * j] = tx + dt * tv;
+                            tn[2 * j + 1] = gn * (tv + dt * (du - pb->eta * tx -
+                                                             pb->omega * (2.0 * tx - txl - txr)));
+                        }
+                        for (int j = 0; j < np; ++j) {
+                            t[2 * j] = tn[2 * j];
+                            t[2 * j + 1] = tn[2 * j + 1];
+                            double gz[2];
+                            track_grad(pb, w.z + 2 * ((k + 1) * np + j), k + 1, gz);
+                            dc += dt * (gz[0] * t[2 * j] + gz[1] * t[2 * j + 1]);
+                        }
                     }
                     cs += dc;
                 }
                 csum[c] = cs;
             }
         }
+        free(t);
         work_free(&w);
     }
     double tot = 0.0;
     for (int64_t c = 0; c < nchunk; ++c)
         tot += csum[c];
-    *dJ = tot / (double)M;
+    *dJ = tot / ((double)M * (double)np);
     free(csum);
     return rc ? -2 : 0;
 }

@@ -24,6 +24,18 @@
  *   gradient  g_k[l] = (1/M) sum_m phi_l(z_k) (alpha u_k + gamma^{n_k} lam^v_{k+1})
  *             (dJ/dmu_k = dt g_k)
  *
+ * Coupled particles (Section 6.4, eq. interacting_model): a system is a ring of
+ * np particles j = 0..np-1 (np = 1: the independent particles above); particle
+ * j of system m is particle p = m np + j and draws with counter word 0 = p.
+ * The velocity update of particle j adds the nearest-neighbour force
+ *   v* = v_k + dt (u_k - eta x_k - omega (2 x_{j,k} - x_{j-1,k} - x_{j+1,k})) + ...
+ * (indices mod np).  The cost of a system is the mean of its particles' costs,
+ * J the mean over all M np particles, and the adjoint of particle j gains
+ *   lam^x_{j,k} += dt omega (w_{j-1} + w_{j+1} - 2 w_j),  w_i = gamma^{n_{i,k}} lam^v_{i,k+1}.
+ * Ellipse cost (eq. phonon_functional_tracking): Jt(z) = -exp(-q^2/(2 sigJ^2)),
+ * q = x^2/ax^2 + v^2/av^2 - 1.  Ellipse start (eq. coupled_ellipse): particle j
+ * at (ax cos th_j, av sin th_j), th_j = 2 pi j / np, plus s0 . (Z1, Z2).
+ *
  * Surrogate gradient (Section 6.5, the adjoint independent of the forward
  * trajectories): the adjoint runs on states zs_k ~ N(zd_k, diag(var(t_k))),
  * drawn from Philox block (m, k, iter, 1) (Box-Muller pair of words 0, 1),
@@ -45,30 +57,37 @@ typedef struct {
     int32_t N, nx, nv;
     double T, eta, b1, b2, gamma, beta;
     double xmax, vmax, eps, alpha, sigJ;
-    int32_t init_kind;     /* 0: Gaussian z0 + s0 * Z, 1: uniform on [z0 - s0, z0 + s0] */
+    int32_t init_kind;     /* 0: Gaussian z0 + s0 * Z, 1: uniform on [z0 - s0, z0 + s0],
+                              2: ellipse points + s0 * Z */
     double z0[2], s0[2];
     double svar0[2], svar1[2]; /* surrogate-state variance var_c(t) = svar0[c] + svar1[c] t */
-    const double* zd;      /* (N+1) x 2, row k = desired (x, v) at t_k */
+    const double* zd;      /* (N+1) x 2, row k = desired (x, v) at t_k (tracking cost) */
+    int32_t np;            /* particles per system (ring), >= 1 */
+    double omega;          /* nearest-neighbour coupling */
+    int32_t cost_kind;     /* 0: tracking cost around zd, 1: ellipse cost */
+    double ax, av;         /* ellipse half-axes (cost_kind 1, init_kind 2) */
 } fb_problem;
 
 /* Bump b(r) and its derivative b'(r). */
 double fb_bump(double r, double eps);
 double fb_bump_deriv(double r, double eps);
 
-/* Draws of path m under iteration iter: initial state (x, v), and for step k
+/* Draws of particle m under iteration iter: initial state (x, v), and for step k
  * the normals (Zx, Zv, ZJ) and the jump count n. */
 void fb_initial(const fb_problem* pb, uint64_t seed, uint32_t m, uint32_t iter, double z[2]);
 void fb_step_draws(uint64_t seed, uint32_t m, uint32_t k, uint32_t iter, const uint64_t thr[32],
                    double Z[3], int* n);
 
-/* Per-path states z (count x (N+1) x 2), adjoints lam (count x (N+1) x 2, row 0
- * zero), controls u (count x N), jump counts (count x N) and costs C (count),
- * for paths m0..m0+count-1.  Any output may be NULL. */
+/* Per-particle states z (P x (N+1) x 2), adjoints lam (P x (N+1) x 2, row 0
+ * zero), controls u (P x N), jump counts (P x N) and costs C (P) of the
+ * P = count np particles of systems m0..m0+count-1, in particle order.  Any
+ * output may be NULL. */
 int fb_paths(const fb_problem* pb, uint64_t seed, uint32_t iter, int64_t m0, int64_t count,
              const double* mu, double* z, double* lam, double* u, int32_t* jumps, double* C,
              int nthreads);
 
-/* J and g (N x L) over M paths, fixed-order chunked FP64 sums.  g may be NULL. */
+/* J and g (N x L) over M systems (M np particles), fixed-order chunked FP64
+ * sums.  g may be NULL. */
 int fb_cost_grad(const fb_problem* pb, int64_t M, uint64_t seed, uint32_t iter,
                  const double* mu, double* J, double* g, int nthreads);
 
@@ -76,7 +95,8 @@ int fb_cost_grad(const fb_problem* pb, int64_t M, uint64_t seed, uint32_t iter,
 void fb_surrogate_state(const fb_problem* pb, uint64_t seed, uint32_t m, uint32_t k, uint32_t iter,
                         double z[2]);
 
-/* Per-path surrogate adjoints ls (count x (N+1) x 2, row 0 zero). */
+/* Per-path surrogate adjoints ls (count x (N+1) x 2, row 0 zero).  The
+ * surrogate functions take independent particles only (np = 1). */
 int fb_paths_surrogate(const fb_problem* pb, uint64_t seed, uint32_t iter, int64_t m0, int64_t count,
                        const double* mu, double* lam, int nthreads);
 

@@ -212,7 +212,8 @@ class _FbProblem(C.Structure):
                 ("vmax", C.c_double), ("eps", C.c_double), ("alpha", C.c_double),
                 ("sigJ", C.c_double), ("init_kind", C.c_int32), ("z0", C.c_double * 2),
                 ("s0", C.c_double * 2), ("svar0", C.c_double * 2), ("svar1", C.c_double * 2),
-                ("zd", C.c_void_p)]
+                ("zd", C.c_void_p), ("np", C.c_int32), ("omega", C.c_double),
+                ("cost_kind", C.c_int32), ("ax", C.c_double), ("av", C.c_double)]
 
 
 def _bind_fb(L):
@@ -257,7 +258,7 @@ class _Fb:
                              p.vmax, p.eps, p.alpha, p.sigJ, p.init_kind,
                              (C.c_double * 2)(*p.z0), (C.c_double * 2)(*p.s0),
                              (C.c_double * 2)(*p.svar0), (C.c_double * 2)(*p.svar1),
-                             self.zd.ctypes.data)
+                             self.zd.ctypes.data, p.np, p.omega, p.cost_kind, p.ax, p.av)
 
     def ref(self):
         return C.byref(self.st)
@@ -292,14 +293,15 @@ def fb_step_draws(p, seed: int, m: int, k: int, it: int):
 
 
 def fb_paths(p, seed: int, it: int, m0: int, count: int, mu, nthreads: int | None = None):
-    """Per-path z (count, N+1, 2), lam (count, N+1, 2), u (count, N), jump
-    counts (count, N) and costs (count)."""
+    """Per-particle z (P, N+1, 2), lam (P, N+1, 2), u (P, N), jump counts (P, N)
+    and costs (P) of systems m0..m0+count-1, P = count np (particle order)."""
     mu = _mu(p, mu)
-    z = np.zeros((count, p.N + 1, 2))
-    lam = np.zeros((count, p.N + 1, 2))
-    u = np.zeros((count, p.N))
-    n = np.zeros((count, p.N), np.int32)
-    c = np.zeros(count)
+    P = count * p.np
+    z = np.zeros((P, p.N + 1, 2))
+    lam = np.zeros((P, p.N + 1, 2))
+    u = np.zeros((P, p.N))
+    n = np.zeros((P, p.N), np.int32)
+    c = np.zeros(P)
     fb = _Fb(p)
     rc = _fb().fb_paths(fb.ref(), seed, it, m0, count, _ptr(mu), _ptr(z), _ptr(lam), _ptr(u),
                         _ptr(n), _ptr(c), nthreads or default_threads())

@@ -246,7 +246,7 @@ class FeedbackProblem:
     eps: float
     alpha: float
     sigJ: float
-    init_kind: int  # 0: Gaussian z0 + s0 * Z, 1: uniform on [z0 - s0, z0 + s0]
+    init_kind: int  # 0: Gaussian z0 + s0 * Z, 1: uniform on [z0 - s0, z0 + s0], 2: ellipse
     z0: np.ndarray  # 2
     s0: np.ndarray  # 2
     zd: np.ndarray  # (N+1) x 2, row k = desired (x, v) at t_k
@@ -256,10 +256,20 @@ class FeedbackProblem:
     # variance rates (b1^2, b2^2 + rate / (2 beta))
     svar0: np.ndarray | None = None
     svar1: np.ndarray | None = None
+    # coupled particles (Section 6.4): rings of np particles with
+    # nearest-neighbour coupling omega; cost_kind 1 is the ellipse cost with
+    # half-axes (ax, av), which init_kind 2 also starts the particles on
+    np: int = 1
+    omega: float = 0.0
+    cost_kind: int = 0
+    ax: float = 1.0
+    av: float = 1.0
 
     def __post_init__(self):
         self.N, self.nx, self.nv, self.init_kind = int(self.N), int(self.nx), int(self.nv), int(self.init_kind)
-        for f in ("T", "eta", "b1", "b2", "gamma", "beta", "xmax", "vmax", "eps", "alpha", "sigJ"):
+        self.np, self.cost_kind = int(self.np), int(self.cost_kind)
+        for f in ("T", "eta", "b1", "b2", "gamma", "beta", "xmax", "vmax", "eps", "alpha", "sigJ",
+                  "omega", "ax", "av"):
             setattr(self, f, float(getattr(self, f)))
         self.z0 = np.ascontiguousarray(np.broadcast_to(np.asarray(self.z0, np.float64), (2,)))
         self.s0 = np.ascontiguousarray(np.broadcast_to(np.asarray(self.s0, np.float64), (2,)))
@@ -296,25 +306,45 @@ def feedback_problem(N: int = 50, T: float = 5.0, init: str = "gauss", zd=None, 
                      b1: float = 0.05, b2: float = 0.1, gamma: float = 0.9, beta: float = 10.0,
                      nx: int = 10, nv: int = 10, xmax: float = 2.0, vmax: float = 2.0,
                      eps: float = 0.5, alpha: float = 1e-2, sigJ: float = 0.5,
-                     name: str = "", s0=None, z0=None, svar0=None, svar1=None) -> FeedbackProblem:
+                     name: str = "", s0=None, z0=None, svar0=None, svar1=None, np_: int = 1,
+                     omega: float = 0.0, cost: str = "track", ax: float = 1.5,
+                     av: float = 1.7071067811865475) -> FeedbackProblem:
     """The setting of the paper's Section 6 (xmax = vmax = 2, nx = nv = 10,
     eps = 0.5, beta = 10, gamma = 0.9, eta = 1, T = 5, N = 50).  The paper does
     not state alpha, sigma_J, b1, b2; the defaults here are readings.  init
-    'gauss' is N((0.75, 0.75), 0.01 I) (Section 6.1), 'uniform' is [-1, 1]^2;
-    z0 and s0 override the law's centre and scale."""
+    'gauss' is N((0.75, 0.75), 0.01 I) (Section 6.1), 'uniform' is [-1, 1]^2,
+    'ellipse' the ring's particles equally spaced in angle on the ellipse
+    (Section 6.4); z0 and s0 override the law's centre and scale.  np_ > 1
+    couples rings of np_ particles with strength omega; cost 'ellipse' is the
+    cost of Section 6.4 with the half-axes ax = 1.5, av = 1.7071067811865475
+    printed there."""
     if init == "gauss":
         kind, z0d, s0d = 0, (0.75, 0.75), (0.1, 0.1)
     elif init == "uniform":
         kind, z0d, s0d = 1, (0.0, 0.0), (1.0, 1.0)
+    elif init == "ellipse":
+        kind, z0d, s0d = 2, (0.0, 0.0), (0.0, 0.0)
     else:
         raise ValueError(init)
+    if cost not in ("track", "ellipse"):
+        raise ValueError(cost)
     z0 = z0d if z0 is None else z0
     s0 = s0d if s0 is None else s0
     if zd is None:
         zd = np.zeros((N + 1, 2))
     return FeedbackProblem(N=N, T=T, eta=eta, b1=b1, b2=b2, gamma=gamma, beta=beta, nx=nx, nv=nv,
                            xmax=xmax, vmax=vmax, eps=eps, alpha=alpha, sigJ=sigJ, init_kind=kind,
-                           z0=z0, s0=s0, zd=zd, name=name, svar0=svar0, svar1=svar1)
+                           z0=z0, s0=s0, zd=zd, name=name, svar0=svar0, svar1=svar1, np=np_,
+                           omega=omega, cost_kind=0 if cost == "track" else 1, ax=ax, av=av)
+
+
+def ring_problem(N: int = 50, T: float = 5.0, np_: int = 2000, omega: float = 0.5, name: str = "",
+                 **kw) -> FeedbackProblem:
+    """Section 6.4: rings of np_ nearest-neighbour coupled oscillators (eta = 1,
+    omega = 0.5) started on the ellipse with ax = 1.5, av = 1.7071067811865475,
+    and the ellipse cost; the other settings as in Section 6."""
+    return feedback_problem(N=N, T=T, init="ellipse", np_=np_, omega=omega, cost="ellipse",
+                            name=name, **kw)
 
 
 def switching_target(N: int, T: float, amp: float = 0.5) -> np.ndarray:
@@ -340,6 +370,17 @@ def feedback_config(name: str) -> FeedbackWorkload:
                                 seed=1)
     if name == "f4":
         return FeedbackWorkload(feedback_problem(N=500, name="f4"), M=1 << 20, seed=1)
+    raise KeyError(name)
+
+
+def ring_config(name: str) -> FeedbackWorkload:
+    """ring1: Section 6.4 at the paper's size, one ring of 2000 particles, 50
+    steps.  ring2: the measured size, 512 independent rings of 2000 particles
+    (1,024,000 particles), 500 steps (dt = 0.01).  M counts rings."""
+    if name == "ring1":
+        return FeedbackWorkload(ring_problem(name="ring1"), M=1, seed=1)
+    if name == "ring2":
+        return FeedbackWorkload(ring_problem(N=500, name="ring2"), M=512, seed=1)
     raise KeyError(name)
 
 

@@ -21,7 +21,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 # pin suites run against a mutant of each oracle source file
 PIN_FILES = {
     "jd_oracle.c": ["tests/test_oracle_rng.py", "tests/test_oracle_model.py"],
-    "fb_oracle.c": ["tests/test_oracle_fb.py"],
+    "fb_oracle.c": ["tests/test_oracle_fb.py", "tests/test_oracle_coupled.py"],
 }
 
 # name: (exact text in jd_oracle.c, replacement)
@@ -71,7 +71,7 @@ FB_MUTANTS = {
                               "u += mu[l * pb->nx + i] * px[i] * pv[l];"),
     "fb_position_without_dt": ("zn[0] = zk[0] + dt * zk[1] + pb->b1 * sq * Z[0];",
                                "zn[0] = zk[0] + zk[1] + pb->b1 * sq * Z[0];"),
-    "fb_spring_sign": ("double vs = zk[1] + dt * (u - pb->eta * zk[0])", "double vs = zk[1] + dt * (u + pb->eta * zk[0])"),
+    "fb_spring_sign": ("double vs = zk[1] + dt * (u - pb->eta * zk[0] -", "double vs = zk[1] + dt * (u + pb->eta * zk[0] -"),
     "fb_velocity_noise_is_x": ("+ pb->b2 * sq * Z[1];", "+ pb->b2 * sq * Z[0];"),
     "fb_jump_factor_once": ("zn[1] = gn * vs + sqrt(Vn) * Z[2];", "zn[1] = (w->n[k] ? pb->gamma : 1.0) * vs + sqrt(Vn) * Z[2];"),
     "fb_jump_variance": ("*Vn = s / (2.0 * pb->beta);", "*Vn = s / pb->beta;"),
@@ -79,16 +79,20 @@ FB_MUTANTS = {
                      "return sqrt(pb->beta * FB_PI) * (pb->T / (double)pb->N);"),
     "fb_initial_sine_to_x": ("z[1] = pb->z0[1] + pb->s0[1] * R * sin(FB_TWO_PI * ub);",
                              "z[1] = pb->z0[1] + pb->s0[1] * R * cos(FB_TWO_PI * ub);"),
-    "fb_track_left_point": ("C += dt * track(pb, zn, pb->zd + 2 * (k + 1));",
-                            "C += dt * track(pb, zk, pb->zd + 2 * k);"),
-    "fb_control_cost_half": ("C += dt * 0.5 * pb->alpha * u * u;", "C += dt * pb->alpha * u * u;"),
-    "fb_adjoint_terminal_without_dt": ("w->lam[2 * N] = dt * gz[0];", "w->lam[2 * N] = gz[0];"),
-    "fb_adjoint_spring_sign": ("w->lam[2 * k] = lx + gn * dt * (ux - pb->eta) * lv + dt * gz[0] + dt * pb->alpha * u * ux;", "w->lam[2 * k] = lx + gn * dt * (ux + pb->eta) * lv + dt * gz[0] + dt * pb->alpha * u * ux;"),
-    "fb_adjoint_position_coupling": ("w->lam[2 * k + 1] = dt * lx +", "w->lam[2 * k + 1] = lx +"),
-    "fb_adjoint_no_jump_factor": ("w->lam[2 * k + 1] = dt * lx + gn * (1.0 + dt * uv) * lv + dt * gz[1] + dt * pb->alpha * u * uv;", "w->lam[2 * k + 1] = dt * lx + (1.0 + dt * uv) * lv + dt * gz[1] + dt * pb->alpha * u * uv;"),
-    "fb_adjoint_uv_dropped": ("w->lam[2 * k + 1] = dt * lx + gn * (1.0 + dt * uv) * lv + dt * gz[1] + dt * pb->alpha * u * uv;", "w->lam[2 * k + 1] = dt * lx + gn * lv + dt * gz[1] + dt * pb->alpha * u * uv;"),
-    "fb_adjoint_track_sign": ("w->lam[2 * k + 1] = dt * lx + gn * (1.0 + dt * uv) * lv + dt * gz[1] + dt * pb->alpha * u * uv;", "w->lam[2 * k + 1] = dt * lx + gn * (1.0 + dt * uv) * lv - dt * gz[1] + dt * pb->alpha * u * uv;"),
-    "fb_adjoint_control_cost_dropped": ("w->lam[2 * k] = lx + gn * dt * (ux - pb->eta) * lv + dt * gz[0] + dt * pb->alpha * u * ux;", "w->lam[2 * k] = lx + gn * dt * (ux - pb->eta) * lv + dt * gz[0];"),
+    "fb_track_left_point": ("w->C[j] += dt * track(pb, zn, k + 1);", "w->C[j] += dt * track(pb, zk, k);"),
+    "fb_control_cost_half": ("w->C[j] += dt * 0.5 * pb->alpha * u * u;", "w->C[j] += dt * pb->alpha * u * u;"),
+    "fb_adjoint_terminal_without_dt": ("w->lam[2 * (N * np + j)] = dt * gz[0];", "w->lam[2 * (N * np + j)] = gz[0];"),
+    "fb_adjoint_spring_sign": ("w->lam[2 * (k * np + j)] = lx + gn * dt * (ux - pb->eta) * lv",
+                               "w->lam[2 * (k * np + j)] = lx + gn * dt * (ux + pb->eta) * lv"),
+    "fb_adjoint_position_coupling": ("=\n                dt * lx + gn * (1.0 + dt * uv) * lv",
+                                     "=\n                lx + gn * (1.0 + dt * uv) * lv"),
+    "fb_adjoint_no_jump_factor": ("=\n                dt * lx + gn * (1.0 + dt * uv) * lv",
+                                  "=\n                dt * lx + (1.0 + dt * uv) * lv"),
+    "fb_adjoint_uv_dropped": ("=\n                dt * lx + gn * (1.0 + dt * uv) * lv", "=\n                dt * lx + gn * lv"),
+    "fb_adjoint_track_sign": ("=\n                dt * lx + gn * (1.0 + dt * uv) * lv + dt * gz[1]",
+                              "=\n                dt * lx + gn * (1.0 + dt * uv) * lv - dt * gz[1]"),
+    "fb_adjoint_control_cost_dropped": ("+\n                                       dt * gz[0] + dt * pb->alpha * u * ux;",
+                                        "+\n                                       dt * gz[0];"),
     "fb_gradient_no_jump_factor": ("double wk = pb->alpha * u + gn * lv;", "double wk = pb->alpha * u + lv;"),
     "fb_gradient_control_term_dropped": ("double wk = pb->alpha * u + gn * lv;", "double wk = gn * lv;"),
     "fb_track_grad_sign": ("gz[0] = rx / s2 * e;", "gz[0] = -rx / s2 * e;"),
@@ -104,6 +108,28 @@ FB_MUTANTS = {
     "fb_surr_terminal_without_dt": ("double lx = dt * gz[0], lv = dt * gz[1];",
                                     "double lx = dt * gz[0], lv = gz[1];"),
     "fb_surr_forward_term_dropped": ("double au = pb->alpha * w.u[k];", "double au = 0.0 * w.u[k];"),
+    # coupled particles (Section 6.4)
+    "fb_coupling_sign": ("- pb->omega * (2.0 * zk[0] - xl - xr)", "+ pb->omega * (2.0 * zk[0] - xl - xr)"),
+    "fb_coupling_one_neighbour": ("(2.0 * zk[0] - xl - xr)", "(2.0 * zk[0] - xl - xl)"),
+    "fb_ring_not_closed": ("return (j + pb->np - 1) % pb->np;", "return j > 0 ? j - 1 : j;"),
+    "fb_particle_counter_shared": ("fb_step_draws(seed, m * (uint32_t)np + (uint32_t)j,",
+                                   "fb_step_draws(seed, m * (uint32_t)np,"),
+    "fb_adjoint_coupling_sign": ("+ dt * pb->omega * cpl", "- dt * pb->omega * cpl"),
+    "fb_adjoint_coupling_self": ("double cpl = w->w[left_of(pb, j)] + w->w[right_of(pb, j)] - 2.0 * w->w[j];",
+                                 "double cpl = 2.0 * w->w[left_of(pb, j)] - 2.0 * w->w[j];"),
+    "fb_adjoint_coupling_no_jump_factor": ("w->w[j] = gn * w->lam[2 * ((k + 1) * np + j) + 1];",
+                                           "w->w[j] = w->lam[2 * ((k + 1) * np + j) + 1];"),
+    "fb_mean_over_systems": ("const double P = (double)M * (double)pb->np;", "const double P = (double)M;"),
+    "fb_ellipse_axes_swapped": ("z[0] * z[0] / (pb->ax * pb->ax) + z[1] * z[1] / (pb->av * pb->av) - 1.0",
+                                "z[0] * z[0] / (pb->av * pb->av) + z[1] * z[1] / (pb->ax * pb->ax) - 1.0"),
+    "fb_ellipse_q_not_squared": ("return -exp(-(q * q) / (2.0 * pb->sigJ * pb->sigJ));",
+                                 "return -exp(-fabs(q) / (2.0 * pb->sigJ * pb->sigJ));"),
+    "fb_ellipse_grad_factor": ("gz[0] = e * 2.0 * z[0] / (pb->ax * pb->ax);", "gz[0] = e * z[0] / (pb->ax * pb->ax);"),
+    "fb_ellipse_grad_axis": ("gz[1] = e * 2.0 * z[1] / (pb->av * pb->av);", "gz[1] = e * 2.0 * z[1] / (pb->ax * pb->ax);"),
+    "fb_ellipse_start_angle": ("(double)(m % (uint32_t)pb->np) / (double)pb->np;",
+                               "(double)(m % (uint32_t)pb->np) / (double)(pb->np + 1);"),
+    "fb_ellipse_start_axes": ("z[0] = pb->ax * cos(th)", "z[0] = pb->av * cos(th)"),
+    "fb_tangent_coupling_neighbour": ("pb->omega * (2.0 * tx - txl - txr)", "pb->omega * (2.0 * tx - txl - txl)"),
     "fb_surr_control_cost_source_dropped": ("double nlx = lx + gn * dt * (ux - pb->eta) * lv + dt * gz[0] + dt * pb->alpha * u * ux;",
                                             "double nlx = lx + gn * dt * (ux - pb->eta) * lv + dt * gz[0];"),
 }
