@@ -35,6 +35,22 @@
  * or uniform z0 + s0 (2 u - 1) (fresh initial particles every iteration,
  * Section 5, optimization procedure).
  *
+ * Coupled particles (Section 6.4, eq. interacting_model): with np > 1 the
+ * M = run->M realizations are rings of np particles (particle j of ring r is
+ * particle p = r np + j, which draws with counter word 0 = p); the velocity
+ * update of particle j gains the nearest-neighbour force
+ *   v* = ... + dt (u_k - eta x_k - omega (2 x_{j,k} - x_{j-1,k} - x_{j+1,k}))
+ * (indices mod np), the adjoint passes w_i = gamma^{n_i} lam^v_{i,k+1} back to
+ * the neighbours,
+ *   lam^x_{j,k} += dt omega (w_{j-1} + w_{j+1} - 2 w_j),
+ * and J and g are means over all M np particles.  Ellipse cost (cost_kind =
+ * JD_FB_COST_ELLIPSE, eq. phonon_functional_tracking): Jt(z) =
+ * -exp(-q^2/(2 sigJ^2)), q = x^2/ax^2 + v^2/av^2 - 1.  Ellipse start
+ * (JD_FB_INIT_ELLIPSE, eq. coupled_ellipse): particle j of its ring at
+ * (ax cos th_j, av sin th_j) + s0 . (Z1, Z2), th_j = 2 pi j / np, (Z1, Z2) the
+ * Gaussian pair of the initial-state block.  One ring runs inside one
+ * workgroup, its neighbours exchanged through LDS.
+ *
  * Surrogate gradient (run->mode = JD_SURROGATE; Section 6.5, the adjoint
  * independent of the forward trajectories): nothing is stored.  The forward
  * adds alpha u_k phi(z_k) to the gradient as it goes; the adjoint recursion
@@ -47,8 +63,9 @@
  * asynchronous calls on `stream`, validation before any launch).  mu and g
  * are FP64 device arrays, row-major N x L with L = nx nv.  Modes: JD_STORE
  * (exact gradient over the stored trajectory) and JD_SURROGATE (jd_fb_forward,
- * jd_fb_cost_grad, jd_fb_optimize; traj may be NULL); JD_RECOMPUTE returns
- * JD_EUNSUPPORTED.
+ * jd_fb_cost_grad, jd_fb_optimize; traj may be NULL; independent particles
+ * only, np = 1, else JD_EUNSUPPORTED); JD_RECOMPUTE returns JD_EUNSUPPORTED.
+ * Particle indices (dumps, jd_fb_draws) count M np particles; M np < 2^32.
  */
 #ifndef JD_FEEDBACK_H
 #define JD_FEEDBACK_H
@@ -61,6 +78,12 @@ extern "C" {
 
 #define JD_FB_INIT_GAUSS 0   /* z_0 = z0 + s0 . (Z1, Z2) */
 #define JD_FB_INIT_UNIFORM 1 /* z_0 uniform on [z0 - s0, z0 + s0] */
+#define JD_FB_INIT_ELLIPSE 2 /* z_0 = ring position on the ellipse + s0 . (Z1, Z2) */
+
+#define JD_FB_COST_TRACK 0   /* tracking cost around zd */
+#define JD_FB_COST_ELLIPSE 1 /* ellipse cost with half-axes ax, av */
+
+#define JD_FB_MAX_RING 2048  /* largest np: one ring per workgroup */
 
 typedef struct jd_fb_problem {
     int32_t N;          /* time steps, >= 1 */
@@ -77,7 +100,12 @@ typedef struct jd_fb_problem {
     int32_t init_kind;  /* JD_FB_INIT_GAUSS or JD_FB_INIT_UNIFORM */
     double z0[2], s0[2];/* initial law: centre and scale (s0 >= 0) */
     double svar0[2], svar1[2]; /* surrogate-state variance svar0 + svar1 t (>= 0), JD_SURROGATE */
-    const double* zd;   /* DEVICE, (N+1) x 2 FP64: desired (x, v) at t_0..t_N */
+    const double* zd;   /* DEVICE, (N+1) x 2 FP64: desired (x, v) at t_0..t_N; may be
+                           NULL with the ellipse cost outside JD_SURROGATE */
+    int32_t np;         /* particles per ring, 1..JD_FB_MAX_RING (1: independent particles) */
+    double omega;       /* nearest-neighbour coupling (finite) */
+    int32_t cost_kind;  /* JD_FB_COST_TRACK or JD_FB_COST_ELLIPSE */
+    double ax, av;      /* ellipse half-axes, > 0 (ellipse cost or start) */
 } jd_fb_problem;
 
 /* Per-path diagnostics for the feedback model, as jd_dump with these layouts
@@ -87,8 +115,11 @@ typedef struct jd_fb_problem {
  *   cost[p]                  = C^(m0+p), FP64                  (jd_fb_forward) */
 
 /* Workspace and trajectory bytes (0 if the arguments are invalid).  The
- * trajectory holds z_0..z_N in blocks of 256 paths: component c of z_k of
- * path m is element ((m / 256) (N+1) + k) 2 256 + c 256 + (m % 256). */
+ * trajectory holds z_0..z_N in rows of 256 slots: component c of z_k of the
+ * particle in slot s is element ((s / 256) (N+1) + k) 2 256 + c 256 + (s % 256).
+ * With np = 1 particle m sits in slot m.  With np > 1 a workgroup holds
+ * R = floor(256 G / np) rings in 256 G slots (G = 1 for np <= 256, else 8):
+ * particle j of ring r sits in slot (r / R) 256 G + (r % R) np + j. */
 size_t jd_fb_workspace_bytes(const jd_fb_problem* prob, const jd_run* run);
 size_t jd_fb_traj_bytes(const jd_fb_problem* prob, const jd_run* run);
 

@@ -296,7 +296,9 @@ def poisson_thresholds(mu: float) -> np.ndarray:
 # ---------------------------------------------------------------------------
 # The paper's model problem (include/jd_feedback.h).
 
-JD_FB_INIT_GAUSS, JD_FB_INIT_UNIFORM = 0, 1
+JD_FB_INIT_GAUSS, JD_FB_INIT_UNIFORM, JD_FB_INIT_ELLIPSE = 0, 1, 2
+JD_FB_COST_TRACK, JD_FB_COST_ELLIPSE = 0, 1
+JD_FB_MAX_RING = 2048
 
 
 class jd_fb_problem(C.Structure):
@@ -306,7 +308,8 @@ class jd_fb_problem(C.Structure):
                 ("vmax", C.c_double), ("eps", C.c_double), ("alpha", C.c_double),
                 ("sigJ", C.c_double), ("init_kind", C.c_int32), ("z0", C.c_double * 2),
                 ("s0", C.c_double * 2), ("svar0", C.c_double * 2), ("svar1", C.c_double * 2),
-                ("zd", C.c_void_p)]
+                ("zd", C.c_void_p), ("np", C.c_int32), ("omega", C.c_double),
+                ("cost_kind", C.c_int32), ("ax", C.c_double), ("av", C.c_double)]
 
 
 class FbProblem:
@@ -321,7 +324,7 @@ class FbProblem:
                                 p.vmax, p.eps, p.alpha, p.sigJ, p.init_kind,
                                 (C.c_double * 2)(*p.z0), (C.c_double * 2)(*p.s0),
                                 (C.c_double * 2)(*p.svar0), (C.c_double * 2)(*p.svar1),
-                                self.zd.data_ptr())
+                                self.zd.data_ptr(), p.np, p.omega, p.cost_kind, p.ax, p.av)
 
     @property
     def ref(self):
@@ -330,7 +333,9 @@ class FbProblem:
 
 class FbEngine:
     """Feedback-model problem + Monte Carlo configuration with its workspace and
-    trajectory buffers (torch allocations)."""
+    trajectory buffers (torch allocations).  M counts realizations: particles
+    for independent particles, rings of np particles otherwise (M np
+    particles); particle indices (dumps, draws) run over all of them."""
 
     def __init__(self, problem, M: int, seed: int = 1, precision: str = "fp32", device="cuda:0",
                  mode: str = "store"):
@@ -350,8 +355,20 @@ class FbEngine:
             raise JdError(JD_EINVAL, "FbEngine")
         self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
         esz = 4 if precision == "fp32" else 8
-        self.nblk = (M + 255) // 256
+        self.particles = M * self.p.np
+        self.nblk = self.traj_bytes // (esz * (self.p.N + 1) * 2 * 256)
         self.traj = torch.empty(self.traj_bytes // esz, dtype=self.rdtype, device=self.device)
+
+    def slots(self) -> np.ndarray:
+        """Trajectory slot of every particle (the layout of include/jd_feedback.h)."""
+        npr = self.p.np
+        if npr == 1:
+            return np.arange(self.M)
+        G = 1 if npr <= 256 else 8
+        R = 256 * G // npr
+        r = np.repeat(np.arange(self.M), npr)
+        j = np.tile(np.arange(npr), self.M)
+        return (r // R) * 256 * G + (r % R) * npr + j
 
     def run(self, it: int = 0, dump: jd_dump | None = None) -> jd_run:
         return make_run(self.M, self.seed, it, self.precision, self.mode, 0, dump)
@@ -365,9 +382,13 @@ class FbEngine:
         return mu
 
     def trajectory(self):
-        """z_0..z_N as an (N+1, 2, M) tensor (a copy of the blocked buffer)."""
+        """z_0..z_N as an (N+1, 2, particles) tensor (a copy of the blocked buffer)."""
+        torch = _torch()
         t = self.traj.view(self.nblk, self.p.N + 1, 2, 256).permute(1, 2, 0, 3)
-        return t.reshape(self.p.N + 1, 2, self.nblk * 256)[:, :, :self.M]
+        t = t.reshape(self.p.N + 1, 2, self.nblk * 256)
+        if self.p.np == 1:
+            return t[:, :, :self.M]
+        return t[:, :, torch.from_numpy(self.slots()).to(self.device)]
 
     def forward(self, mu, it: int = 0, store: bool = True, dump: jd_dump | None = None):
         torch = _torch()

@@ -2,8 +2,9 @@
 //
 //  k_fb_table          mu (FP64) -> path-precision rows padded to nvp, targets,
 //                      Keilson-Storer factors; stages the Poisson table
-//  k_fb_forward        forward sweep, one particle per lane: shape functions,
-//                      feedback control, draws, Euler step, jumps, FP64 cost
+//  k_fb_forward        forward sweep, one particle per lane (G per lane for
+//                      rings): shape functions, feedback control, ring
+//                      coupling, draws, Euler step, jumps, FP64 cost
 //  k_fb_adjoint        backward sweep over the stored trajectory; the per-step
 //                      gradient sum over particles runs on the FP64 matrix cores
 //  k_fb_finalize_grad  fixed-order FP64 sum of the per-block gradient partials
@@ -14,7 +15,9 @@
 // SDE_splitted_drift_Euler, eq. jump_law, eq. collision_frequency), control
 // and shape functions (eq. control_structure, eq. Gaussian_RBF), cost (eq.
 // discrete_functional, eq. tracking_cost), adjoint (eq.
-// adjoint_eq_approximation), gradient (eq. definition_Gradient).
+// adjoint_eq_approximation), gradient (eq. definition_Gradient); coupled
+// particles, the start on the ellipse and the ellipse cost of Section 6.4
+// (eq. interacting_model, eq. coupled_ellipse, eq. phonon_functional_tracking).
 #include "fb_launch.hpp"
 #include "jd_device.hpp"
 
@@ -29,7 +32,11 @@ struct FbKs {
 
 template <typename Real>
 struct FbArgs {
-    int64_t M;
+    int64_t M;     // particles
+    int64_t nsys;  // rings (np > 1)
+    int np, sb;    // particles per ring, rings per workgroup
+    int cost_kind;
+    Real omega, iax2, iav2, ax, av;  // coupling, 1/ax^2, 1/av^2, half-axes
     int nblk, N, nx, nv;
     Real dt, sqb1, sqb2, eta, eps, alpha, hadt, inv2s2, invs2;
     Real xc0, dxc, vc0, dvc;  // centres x^i = xc0 + i dxc, v^l = vc0 + l dvc
@@ -97,6 +104,14 @@ __device__ __forceinline__ void fb_initial(const FbArgs<Real>& a, uint32_t m, Re
         const Real ub = unit_uniform<Real>(w[1]);
         x = fma(a.s0x, bm_cos(R, ub), a.z0x);
         v = fma(a.s0v, bm_sin(R, ub), a.z0v);
+    } else if (a.init_kind == 2) {
+        // particle j = m mod np of its ring at angle 2 pi j / np on the ellipse
+        double sn, cs;
+        sincospi(2.0 * (double)(m % (uint32_t)a.np) / (double)a.np, &sn, &cs);
+        const Real R = bm_radius(w[0], (Real)0);
+        const Real ub = unit_uniform<Real>(w[1]);
+        x = fma(a.s0x, bm_cos(R, ub), (Real)((double)a.ax * cs));
+        v = fma(a.s0v, bm_sin(R, ub), (Real)((double)a.av * sn));
     } else {
         x = fma(a.s0x, fma((Real)2, unit_uniform<Real>(w[0]), (Real)-1), a.z0x);
         v = fma(a.s0v, fma((Real)2, unit_uniform<Real>(w[1]), (Real)-1), a.z0v);
@@ -128,12 +143,13 @@ struct NoSink {
     __device__ __forceinline__ void put_v(const Real*) const {}
 };
 
-// One forward step of one particle: control, draws, Euler step, jumps.
+// One forward step of one particle: control, draws, Euler step, jumps; cpl is
+// the ring force omega (2 x_j - x_{j-1} - x_{j+1}) (a literal 0 without rings).
 // Returns the control u_k; the bump values go to the sink.
 template <typename Real, int NVP, typename Sink = NoSink>
 __device__ __forceinline__ Real fb_step(const FbArgs<Real>& a, const Real* __restrict__ mk,
                                         const Real* __restrict__ ks, uint32_t m, int k, Real& x,
-                                        Real& v, const Sink& sink = Sink()) {
+                                        Real& v, Real cpl, const Sink& sink = Sink()) {
     Real pv[NVP];
     shapes_v<Real, NVP>(a, v, pv);
     Real u = 0;
@@ -155,7 +171,7 @@ __device__ __forceinline__ Real fb_step(const FbArgs<Real>& a, const Real* __res
     const Real ub = unit_uniform<Real>(w[1]);
     const int n = poisson_count(poisson_word(w), a.thr);
     const Real xn = fma(a.sqb1, bm_cos(R, ub), fma(a.dt, v, x));
-    Real vs = fma(a.sqb2, bm_sin(R, ub), fma(a.dt, fma(-a.eta, x, u), v));
+    Real vs = fma(a.sqb2, bm_sin(R, ub), fma(a.dt, fma(-a.eta, x, u) - cpl, v));
     if (__builtin_amdgcn_ballot_w64(n != 0)) {
         Real gn, sv;
         ks_factors(ks, n, gn, sv);
@@ -192,19 +208,63 @@ __device__ __forceinline__ void fb_dump(const FbArgs<Real>& a, Real* dst, int k,
     }
 }
 
-// Tracking cost -exp(-|z - zd|^2/(2 sigJ^2)) and its gradient.
+// Running cost and its gradient: the tracking cost -exp(-|z - zd|^2/(2 sigJ^2))
+// or the ellipse cost -exp(-q^2/(2 sigJ^2)), q = x^2/ax^2 + v^2/av^2 - 1.
 template <typename Real>
 __device__ __forceinline__ Real track(const FbArgs<Real>& a, Real x, Real v, const Real* zd) {
+    if (a.cost_kind == 1) {
+        const Real q = fma(x * x, a.iax2, fma(v * v, a.iav2, (Real)-1));
+        return -fb_exp<Real>(-(q * q) * a.inv2s2);
+    }
     const Real rx = x - zd[0], rv = v - zd[1];
     return -fb_exp<Real>(-fma(rx, rx, rv * rv) * a.inv2s2);
 }
 template <typename Real>
 __device__ __forceinline__ void track_grad(const FbArgs<Real>& a, Real x, Real v, const Real* zd,
                                            Real& gx, Real& gv) {
+    if (a.cost_kind == 1) {
+        const Real q = fma(x * x, a.iax2, fma(v * v, a.iav2, (Real)-1));
+        const Real e = (Real)2 * q * a.invs2 * fb_exp<Real>(-(q * q) * a.inv2s2);
+        gx = e * x * a.iax2;
+        gv = e * v * a.iav2;
+        return;
+    }
     const Real rx = x - zd[0], rv = v - zd[1];
     const Real e = fb_exp<Real>(-fma(rx, rx, rv * rv) * a.inv2s2) * a.invs2;
     gx = rx * e;
     gv = rv * e;
+}
+
+// Slot q = g 256 + threadIdx.x of a workgroup holding G groups of 256 slots:
+// its particle p, whether it holds one, and the workgroup slots of its ring
+// neighbours.  np = 1: particle blockIdx.x 256 G + q.  np > 1: ring
+// blockIdx.x sb + q / np, position q mod np; slots past the sb rings, and
+// rings past the last, hold none (p = M then lies outside every dump range).
+struct FbSlot {
+    uint32_t p;
+    bool act;
+    int lft, rgt;
+};
+template <int G, typename Real>
+__device__ __forceinline__ FbSlot fb_slot(const FbArgs<Real>& a, int g) {
+    FbSlot s;
+    const int q = g * kThreads + (int)threadIdx.x;
+    s.lft = s.rgt = q;
+    if (a.np == 1) {
+        const int64_t m = (int64_t)blockIdx.x * (G * kThreads) + q;
+        s.act = m < a.M;
+        s.p = (uint32_t)m;
+        return s;
+    }
+    const int si = q / a.np, j = q - si * a.np;
+    const int64_t r = (int64_t)blockIdx.x * a.sb + si;
+    s.act = si < a.sb && r < a.nsys;
+    s.p = s.act ? (uint32_t)(r * a.np + j) : (uint32_t)a.M;
+    if (s.act) {
+        s.lft = si * a.np + (j == 0 ? a.np - 1 : j - 1);
+        s.rgt = si * a.np + (j + 1 == a.np ? 0 : j + 1);
+    }
+    return s;
 }
 
 // Trajectory: block b owns (N+1) slots x 2 rows x 256 elements.
@@ -228,7 +288,7 @@ k_fb_table(const double* __restrict__ mu, const double* __restrict__ zd, Real* _
         tab[idx] = l < nv ? (Real)mu[(k * nx + i) * nv + l] : (Real)0;
     }
     if (idx < 2 * (int64_t)(N + 1))
-        tab[off_zd + idx] = (Real)zd[idx];
+        tab[off_zd + idx] = zd != nullptr ? (Real)zd[idx] : (Real)0;
     if (idx < 64)
         tab[off_ks + idx] = (Real)ks.v[idx];
     if (idx == 0) {
@@ -238,38 +298,69 @@ k_fb_table(const double* __restrict__ mu, const double* __restrict__ zd, Real* _
     }
 }
 
-template <typename Real, int NVP, bool STORE>
+// Forward sweep.  Without rings (RING = false, G = 1) one particle per lane and
+// no synchronisation.  With rings each lane carries G particles (slots
+// g 256 + threadIdx.x) and every step first publishes x_k in LDS (double
+// buffered by step parity, one barrier per step) for the ring force.
+template <typename Real, int NVP, bool STORE, int G, bool RING>
 __global__ void __launch_bounds__(kThreads)
 k_fb_forward(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __restrict__ zd,
              const Real* __restrict__ ks, void* traj, double* __restrict__ cpart) {
+    static_assert(RING || G == 1, "independent particles run one per lane");
     __shared__ double sh[kThreads];
-    const int64_t m = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    const bool act = m < a.M;
-    Real x, v;
-    fb_initial(a, (uint32_t)m, x, v);
-    Real* row = STORE ? fb_row<Real>(traj, a.N, blockIdx.x) : nullptr;
-    if (STORE) {
-        __builtin_nontemporal_store(x, row);
-        __builtin_nontemporal_store(v, row + kThreads);
-    }
-    fb_dump(a, a.dX, 0, m, x, v);
-    double acc = 0.0;
-    for (int k = 0; k < a.N; ++k) {
-        const Real u = fb_step<Real, NVP>(a, mu + (size_t)k * a.nx * NVP, ks, (uint32_t)m, k, x, v);
-        acc += (double)(a.hadt * u * u);
-        acc += (double)(a.dt * track(a, x, v, zd + 2 * (k + 1)));
+    __shared__ Real xs[RING ? 2 : 1][RING ? G * kThreads : 1];
+    Real x[G], v[G];
+    double acc[G];
+    FbSlot sl[G];
+    Real* row[G];
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+        sl[j] = fb_slot<G>(a, j);
+        fb_initial(a, sl[j].p, x[j], v[j]);
+        row[j] = STORE ? fb_row<Real>(traj, a.N, (int64_t)blockIdx.x * G + j) : nullptr;
         if (STORE) {
-            Real* r = row + (size_t)(k + 1) * 2 * kThreads;
-            __builtin_nontemporal_store(x, r);
-            __builtin_nontemporal_store(v, r + kThreads);
+            __builtin_nontemporal_store(x[j], row[j]);
+            __builtin_nontemporal_store(v[j], row[j] + kThreads);
         }
-        fb_dump(a, a.dX, k + 1, m, x, v);
+        fb_dump(a, a.dX, 0, sl[j].p, x[j], v[j]);
+        acc[j] = 0.0;
     }
-    const double C = act ? acc : 0.0;
-    if (a.dcost != nullptr) {
-        const int64_t p = m - a.dm0;
-        if (act && p >= 0 && p < a.dcount)
-            a.dcost[p] = C;
+    for (int k = 0; k < a.N; ++k) {
+        Real cpl[G];
+        if (RING) {
+            Real* xb = xs[k & 1];
+#pragma unroll
+            for (int j = 0; j < G; ++j)
+                xb[j * kThreads + threadIdx.x] = x[j];
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < G; ++j)
+                cpl[j] = a.omega * ((Real)2 * x[j] - xb[sl[j].lft] - xb[sl[j].rgt]);
+        }
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
+            const Real u = fb_step<Real, NVP>(a, mu + (size_t)k * a.nx * NVP, ks, sl[j].p, k, x[j],
+                                              v[j], RING ? cpl[j] : (Real)0);
+            acc[j] += (double)(a.hadt * u * u);
+            acc[j] += (double)(a.dt * track(a, x[j], v[j], zd + 2 * (k + 1)));
+            if (STORE) {
+                Real* r = row[j] + (size_t)(k + 1) * 2 * kThreads;
+                __builtin_nontemporal_store(x[j], r);
+                __builtin_nontemporal_store(v[j], r + kThreads);
+            }
+            fb_dump(a, a.dX, k + 1, sl[j].p, x[j], v[j]);
+        }
+    }
+    double C = 0.0;
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+        const double c = sl[j].act ? acc[j] : 0.0;
+        if (a.dcost != nullptr) {
+            const int64_t p = (int64_t)sl[j].p - a.dm0;
+            if (sl[j].act && p >= 0 && p < a.dcount)
+                a.dcost[p] = c;
+        }
+        C += c;
     }
     const double s = block_sum(C, sh);
     if (threadIdx.x == 0)
@@ -410,7 +501,7 @@ k_fb_forward_grad(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __res
         wave.clear();
 #pragma unroll
         for (int j = 0; j < G; ++j) {
-            const Real u = fb_step<Real, NVP>(a, mk, ks, (uint32_t)m[j], k, x[j], v[j], wave);
+            const Real u = fb_step<Real, NVP>(a, mk, ks, (uint32_t)m[j], k, x[j], v[j], (Real)0, wave);
             wave.template add<NVP>(act[j] ? a.alpha * u : (Real)0, a.nx);
             acc[j] += (double)(a.hadt * u * u);
             acc[j] += (double)(a.dt * track(a, x[j], v[j], zd + 2 * (k + 1)));
@@ -451,22 +542,30 @@ struct FbAdj {
 //   SURR = true:  the states are the surrogate states of Section 6.5 and the
 //                 weight gamma^n lam^v is added to the partials of
 //                 k_fb_forward_grad (which hold alpha u phi(z)).
-template <typename Real, int NVP, int G, bool SURR>
+//   RING = true:  rings (slots as in k_fb_forward); each particle's
+//                 w = gamma^n lam^v_{k+1} goes to LDS (double buffered by step
+//                 parity) and, after the block barriers of the gradient
+//                 partial, its neighbours add dt omega w to their lam^x_k.
+template <typename Real, int NVP, int G, bool SURR, bool RING>
 __global__ void __launch_bounds__(kThreads)
 k_fb_adjoint(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __restrict__ zd,
              const Real* __restrict__ ks, const void* traj, double* __restrict__ apart) {
+    static_assert(!(SURR && RING), "the surrogate gradient takes independent particles");
     __shared__ FbShared<Real> sh;
+    __shared__ Real cw[RING ? 2 : 1][RING ? G * kThreads : 1];
     FbWave<Real> wave = fb_wave(sh);
     const int N = a.N;
     FbAdj<Real> s[G];
     const Real* row[G];
     bool act[G];
     int64_t m[G];
+    FbSlot sl[G];
 #pragma unroll
     for (int j = 0; j < G; ++j) {
         const int64_t g = (int64_t)blockIdx.x * G + j;
-        m[j] = g * kThreads + threadIdx.x;
-        act[j] = m[j] < a.M && g < a.nblk;
+        sl[j] = fb_slot<G>(a, j);
+        m[j] = sl[j].p;
+        act[j] = sl[j].act;
         if (SURR) {
             row[j] = nullptr;
             fb_surrogate(a, zd, (uint32_t)m[j], N, s[j].x, s[j].v);
@@ -532,20 +631,34 @@ k_fb_adjoint(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __restrict
             }
             const Real wk = SURR ? gn * st.lv : fma(a.alpha, u, gn * st.lv);
             wave.template add<NVP>(act[j] ? wk : (Real)0, a.nx);
+            if (RING)
+                cw[k & 1][j * kThreads + threadIdx.x] = gn * st.lv;
             if (k >= 1) {
                 Real gx, gv;
                 track_grad(a, st.x, st.v, zd + 2 * k, gx, gv);
                 const Real au = a.alpha * u;
-                const Real nlx = fma(a.dt, fma(au, ux, gx), fma(gn * a.dt * (ux - a.eta), st.lv, st.lx));
+                // ring: the particle's own share -2 omega of its force
+                const Real sx = RING ? ux - a.eta - (Real)2 * a.omega : ux - a.eta;
+                const Real nlx = fma(a.dt, fma(au, ux, gx), fma(gn * a.dt * sx, st.lv, st.lx));
                 const Real nlv = fma(a.dt, fma(au, uv, gv),
                                      fma(gn, fma(a.dt, uv, (Real)1) * st.lv, a.dt * st.lx));
                 st.lx = nlx;
                 st.lv = nlv;
-                if (act[j])
+                if (!RING && act[j])
                     fb_dump(a, a.dlam, k, m[j], st.lx, st.lv);
             }
         }
         fb_block_partial<SURR>(sh, wave, k, N, a.nx, a.nv, apart);
+        if (RING && k >= 1) {
+            const Real* wb = cw[k & 1];
+            const Real dto = a.dt * a.omega;
+#pragma unroll
+            for (int j = 0; j < G; ++j) {
+                s[j].lx = fma(dto, wb[sl[j].lft] + wb[sl[j].rgt], s[j].lx);
+                if (act[j])
+                    fb_dump(a, a.dlam, k, m[j], s[j].lx, s[j].lv);
+            }
+        }
     }
 }
 
@@ -650,6 +763,15 @@ template <typename Real>
 static FbArgs<Real> fb_args(const FbHost& p, const HostRun& r) {
     FbArgs<Real> a;
     a.M = r.M;
+    a.nsys = p.nsys;
+    a.np = p.np;
+    a.sb = p.rings_per_block;
+    a.cost_kind = p.cost_kind;
+    a.omega = (Real)p.omega;
+    a.iax2 = (Real)(1.0 / (p.ax * p.ax));
+    a.iav2 = (Real)(1.0 / (p.av * p.av));
+    a.ax = (Real)p.ax;
+    a.av = (Real)p.av;
     a.nblk = r.nblk;
     a.N = p.N;
     a.nx = p.nx;
@@ -731,6 +853,12 @@ hipError_t fb_launch_table(const FbHost& p, const HostRun& r, const double* mu, 
         }                                  \
     } while (0)
 
+int fb_ring_groups(int np) { return np <= kThreads ? 1 : 8; }
+
+int fb_forward_blocks(const FbHost& p, const HostRun& r) {
+    return p.np == 1 ? r.nblk : r.nblk / p.G;
+}
+
 template <typename Real>
 static hipError_t fb_forward_t(const FbHost& p, const HostRun& r, const void* tab, void* traj,
                                double* cpart, const WsHeader* hdr, hipStream_t st) {
@@ -738,17 +866,25 @@ static hipError_t fb_forward_t(const FbHost& p, const HostRun& r, const void* ta
     FbArgs<Real> a = fb_args<Real>(p, r);
     a.thr = &hdr->poisson;
     const Real* tb = (const Real*)tab;
-#define FB_FWD(NVP)                                                                              \
-    do {                                                                                         \
-        if (traj != nullptr)                                                                     \
-            hipLaunchKernelGGL((k_fb_forward<Real, NVP, true>), dim3(r.nblk), dim3(kThreads), 0, \
-                               st, a, tb + t.mu, tb + t.zd, tb + t.ks, traj, cpart);             \
-        else                                                                                     \
-            hipLaunchKernelGGL((k_fb_forward<Real, NVP, false>), dim3(r.nblk), dim3(kThreads), 0, \
-                               st, a, tb + t.mu, tb + t.zd, tb + t.ks, traj, cpart);             \
+    const unsigned nb = (unsigned)fb_forward_blocks(p, r);
+#define FB_FWD_K(NVP, S, GG, RG)                                                                  \
+    hipLaunchKernelGGL((k_fb_forward<Real, NVP, S, GG, RG>), dim3(nb), dim3(kThreads), 0, st, a,  \
+                       tb + t.mu, tb + t.zd, tb + t.ks, traj, cpart)
+#define FB_FWD_S(NVP, S)                                                                          \
+    do {                                                                                          \
+        if (p.np == 1) FB_FWD_K(NVP, S, 1, false);                                                \
+        else if (p.G == 1) FB_FWD_K(NVP, S, 1, true);                                             \
+        else FB_FWD_K(NVP, S, 8, true);                                                           \
+    } while (0)
+#define FB_FWD(NVP)                                                                               \
+    do {                                                                                          \
+        if (traj != nullptr) FB_FWD_S(NVP, true);                                                 \
+        else FB_FWD_S(NVP, false);                                                                \
     } while (0)
     FB_DISPATCH_NVP(p.nvp, FB_FWD);
 #undef FB_FWD
+#undef FB_FWD_S
+#undef FB_FWD_K
     return hipGetLastError();
 }
 
@@ -771,19 +907,22 @@ static hipError_t fb_adjoint_t(const FbHost& p, const HostRun& r, const void* ta
     FbArgs<Real> a = fb_args<Real>(p, r);
     a.thr = &hdr->poisson;
     const Real* tb = (const Real*)tab;
-    const int G = fb_adjoint_groups(r.nblk);
-    const unsigned nb = (unsigned)((r.nblk + G - 1) / G);
-#define FB_ADJ_G(NVP, GG, S)                                                                      \
-    hipLaunchKernelGGL((k_fb_adjoint<Real, NVP, GG, S>), dim3(nb), dim3(kThreads), 0, st, a,      \
+    const int G = p.np == 1 ? fb_adjoint_groups(r.nblk) : p.G;
+    const unsigned nb = (unsigned)fb_partial_blocks(p, r);
+#define FB_ADJ_G(NVP, GG, S, RG)                                                                  \
+    hipLaunchKernelGGL((k_fb_adjoint<Real, NVP, GG, S, RG>), dim3(nb), dim3(kThreads), 0, st, a,  \
                        tb + t.mu, tb + t.zd, tb + t.ks, traj, apart)
 #define FB_ADJ(NVP)                                                                               \
     do {                                                                                          \
-        if (G == 2) {                                                                             \
-            if (surr) FB_ADJ_G(NVP, 2, true);                                                     \
-            else FB_ADJ_G(NVP, 2, false);                                                         \
+        if (p.np > 1) {                                                                           \
+            if (G == 8) FB_ADJ_G(NVP, 8, false, true);                                            \
+            else FB_ADJ_G(NVP, 1, false, true);                                                   \
+        } else if (G == 2) {                                                                      \
+            if (surr) FB_ADJ_G(NVP, 2, true, false);                                              \
+            else FB_ADJ_G(NVP, 2, false, false);                                                  \
         } else {                                                                                  \
-            if (surr) FB_ADJ_G(NVP, 1, true);                                                     \
-            else FB_ADJ_G(NVP, 1, false);                                                         \
+            if (surr) FB_ADJ_G(NVP, 1, true, false);                                              \
+            else FB_ADJ_G(NVP, 1, false, false);                                                  \
         }                                                                                         \
     } while (0)
     FB_DISPATCH_NVP(p.nvp, FB_ADJ);
@@ -828,7 +967,9 @@ hipError_t fb_launch_forward_grad(const FbHost& p, const HostRun& r, const void*
                              : fb_forward_grad_t<float>(p, r, tab, cpart, apart, hdr, st);
 }
 
-int fb_partial_blocks(const HostRun& r) {
+int fb_partial_blocks(const FbHost& p, const HostRun& r) {
+    if (p.np > 1)
+        return r.nblk / p.G;
     const int G = fb_adjoint_groups(r.nblk);
     return (r.nblk + G - 1) / G;
 }
@@ -837,7 +978,7 @@ hipError_t fb_launch_finalize_grad(const FbHost& p, const HostRun& r, const doub
                                    double* g, WsHeader* hdr, hipStream_t st) {
     const int64_t NL = (int64_t)p.N * p.L;
     hipLaunchKernelGGL(k_fb_finalize_grad, dim3(fb_blocks(NL)), dim3(kThreads), 0, st, apart,
-                       fb_partial_blocks(r), NL, r.M, g, hdr);
+                       fb_partial_blocks(p, r), NL, r.M, g, hdr);
     return hipGetLastError();
 }
 

@@ -17,7 +17,14 @@ struct FbHost {
     int init_kind;
     double z0[2], s0[2];
     double svar0[2], svar1[2];  // surrogate-state variance var(t) = svar0 + svar1 t
-    const double* zd;     // device (N+1) x 2
+    const double* zd;     // device (N+1) x 2, or null (ellipse cost)
+    int np;               // particles per ring (1: independent particles)
+    int G;                // ring kernels: 256-slot groups per workgroup
+    int rings_per_block;  // ring kernels: rings per workgroup
+    int64_t nsys;         // rings (np > 1)
+    double omega;         // nearest-neighbour coupling
+    int cost_kind;        // JD_FB_COST_TRACK / JD_FB_COST_ELLIPSE
+    double ax, av;        // ellipse half-axes
     double ks[64];        // gamma^n and sqrt(V_n) for n = 0..31
     uint64_t thr[32];     // Poisson(rate dt) thresholds
     PoissonTable poisson;
@@ -42,8 +49,12 @@ hipError_t fb_launch_adjoint(const FbHost& p, const HostRun& r, const void* tab,
 // gradient partials (surrogate gradient) and the per-block costs.
 hipError_t fb_launch_forward_grad(const FbHost& p, const HostRun& r, const void* tab, double* cpart,
                                   double* apart, const WsHeader* hdr, hipStream_t st);
-// Number of per-block partials of the adjoint / forward_grad kernels.
-int fb_partial_blocks(const HostRun& r);
+// Number of per-block partials of the adjoint / forward_grad kernels, and of
+// the per-block costs of the forward kernel.
+int fb_partial_blocks(const FbHost& p, const HostRun& r);
+int fb_forward_blocks(const FbHost& p, const HostRun& r);
+// 256-slot groups per workgroup of the ring kernels for rings of np particles.
+int fb_ring_groups(int np);
 hipError_t fb_launch_finalize_grad(const FbHost& p, const HostRun& r, const double* apart,
                                    double* g, WsHeader* hdr, hipStream_t st);
 hipError_t fb_launch_finalize_cost(const FbHost& p, const HostRun& r, const double* cpart,

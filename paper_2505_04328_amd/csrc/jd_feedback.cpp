@@ -31,29 +31,40 @@ int fb_prepare(const jd_fb_problem* prob, const jd_run* run, FbHost& p, HostRun&
     if (!finite(q.eta) || !(q.b1 >= 0.0) || !finite(q.b1) || !(q.b2 >= 0.0) || !finite(q.b2) ||
         !(q.alpha >= 0.0) || !finite(q.alpha) || !(q.gamma >= -1.0) || !(q.gamma <= 1.0))
         return JD_EINVAL;
-    if (q.init_kind != JD_FB_INIT_GAUSS && q.init_kind != JD_FB_INIT_UNIFORM)
+    if (q.init_kind != JD_FB_INIT_GAUSS && q.init_kind != JD_FB_INIT_UNIFORM &&
+        q.init_kind != JD_FB_INIT_ELLIPSE)
+        return JD_EINVAL;
+    if (q.cost_kind != JD_FB_COST_TRACK && q.cost_kind != JD_FB_COST_ELLIPSE)
+        return JD_EINVAL;
+    if (q.np < 1 || q.np > JD_FB_MAX_RING || !finite(q.omega))
+        return JD_EINVAL;
+    if ((q.cost_kind == JD_FB_COST_ELLIPSE || q.init_kind == JD_FB_INIT_ELLIPSE) &&
+        !(q.ax > 0.0 && finite(q.ax) && q.av > 0.0 && finite(q.av)))
         return JD_EINVAL;
     for (int c = 0; c < 2; ++c)
         if (!finite(q.z0[c]) || !(q.s0[c] >= 0.0) || !finite(q.s0[c]) || !(q.svar0[c] >= 0.0) ||
             !finite(q.svar0[c]) || !(q.svar1[c] >= 0.0) || !finite(q.svar1[c]))
             return JD_EINVAL;
-    if (!q.zd)
+    if (!q.zd && (q.cost_kind == JD_FB_COST_TRACK || run->mode == JD_SURROGATE))
         return JD_EINVAL;
     const double dt = q.T / (double)q.N;
     const double rate = sqrt(q.beta / 3.141592653589793238462643383280);
     if (rate * dt > 2.0)
         return JD_EINVAL;
-    if (run->M < 1 || run->M > kMaxPaths)
+    if (run->M < 1 || run->M > kMaxPaths / q.np)
         return JD_EINVAL;
+    const int64_t particles = run->M * (int64_t)q.np;
     if (run->precision != JD_FP32 && run->precision != JD_FP64)
         return JD_EINVAL;
     if (run->mode == JD_RECOMPUTE)
         return JD_EUNSUPPORTED;
     if (run->mode != JD_STORE && run->mode != JD_SURROGATE)
         return JD_EINVAL;
+    if (run->mode == JD_SURROGATE && q.np > 1)
+        return JD_EUNSUPPORTED;
     if (run->dump) {
         const jd_dump* dp = run->dump;
-        if (dp->m0 < 0 || dp->count < 0 || dp->m0 + dp->count > run->M)
+        if (dp->m0 < 0 || dp->count < 0 || dp->m0 + dp->count > particles)
             return JD_EINVAL;
     }
 
@@ -84,6 +95,14 @@ int fb_prepare(const jd_fb_problem* prob, const jd_run* run, FbHost& p, HostRun&
         p.svar1[c] = q.svar1[c];
     }
     p.zd = q.zd;
+    p.np = q.np;
+    p.omega = q.omega;
+    p.cost_kind = q.cost_kind;
+    p.ax = q.ax;
+    p.av = q.av;
+    p.nsys = run->M;
+    p.G = 1;
+    p.rings_per_block = 0;
     // n jumps v <- gamma v + N(0, 1/(2 beta)) composed: gamma^n v + N(0, V_n),
     // V_n = (1/(2 beta)) sum_{i<n} gamma^{2i}
     double g = 1.0, s = 0.0;
@@ -96,15 +115,23 @@ int fb_prepare(const jd_fb_problem* prob, const jd_run* run, FbHost& p, HostRun&
     poisson_thresholds(rate * dt, p.thr);
     p.poisson = poisson_table(p.thr);
 
-    r.M = run->M;
-    r.ldm = (int64_t)round_up((size_t)run->M, kBlock);
+    r.M = particles;
     r.seed = run->seed;
     r.iter = run->iter;
     r.prec = run->precision;
     r.mode = run->mode;
     r.K = 0;
-    r.nblk = (int)((run->M + kBlock - 1) / kBlock);
     r.dump = run->dump;
+    if (q.np == 1) {
+        r.nblk = (int)((particles + kBlock - 1) / kBlock);
+    } else {
+        // whole rings per workgroup of G 256-slot groups
+        p.G = fb_ring_groups(q.np);
+        p.rings_per_block = p.G * (int)kBlock / q.np;
+        const int64_t nb = (run->M + p.rings_per_block - 1) / p.rings_per_block;
+        r.nblk = (int)(nb * p.G);
+    }
+    r.ldm = (int64_t)r.nblk * kBlock;
     return JD_OK;
 }
 
@@ -167,13 +194,13 @@ int fb_enqueue_cost_grad(const FbHost& p, const HostRun& r, const double* mu, do
         JD_TRY(fb_launch_forward_grad(p, r, w.tab, w.cpart, w.apart, w.hdr, st));
         JD_TRY(fb_launch_adjoint(p, r, w.tab, nullptr, w.apart, w.hdr, true, st));
         JD_TRY(fb_launch_finalize_grad(p, r, w.apart, g, w.hdr, st));
-        JD_TRY(fb_launch_finalize_cost(p, r, w.cpart, fb_partial_blocks(r), g, J, w.hdr, 0, st));
+        JD_TRY(fb_launch_finalize_cost(p, r, w.cpart, fb_partial_blocks(p, r), g, J, w.hdr, 0, st));
         return JD_OK;
     }
     JD_TRY(fb_launch_forward(p, r, w.tab, traj, w.cpart, w.hdr, st));
     JD_TRY(fb_launch_adjoint(p, r, w.tab, traj, w.apart, w.hdr, false, st));
     JD_TRY(fb_launch_finalize_grad(p, r, w.apart, g, w.hdr, st));
-    JD_TRY(fb_launch_finalize_cost(p, r, w.cpart, r.nblk, g, J, w.hdr, 0, st));
+    JD_TRY(fb_launch_finalize_cost(p, r, w.cpart, fb_forward_blocks(p, r), g, J, w.hdr, 0, st));
     return JD_OK;
 }
 
@@ -183,7 +210,8 @@ int fb_enqueue_trial(const FbHost& p, const HostRun& r, double* mu, const jd_opt
     JD_TRY(launch_trial(mu, w.gbuf, zeta, w.ut, nl, st));
     JD_TRY(fb_launch_table(p, r, w.ut, w.tab, w.hdr, 0, st));
     JD_TRY(fb_launch_forward(p, r, w.tab, nullptr, w.cpart, w.hdr, st));
-    JD_TRY(fb_launch_finalize_cost(p, r, w.cpart, r.nblk, nullptr, nullptr, w.hdr, 1, st));
+    JD_TRY(fb_launch_finalize_cost(p, r, w.cpart, fb_forward_blocks(p, r), nullptr, nullptr, w.hdr,
+                                   1, st));
     JD_TRY(launch_armijo(w.hdr, mu, w.ut, nl, opt.c_armijo, zeta, p.dt, st));
     return JD_OK;
 }
@@ -222,7 +250,8 @@ int jd_fb_forward(const jd_fb_problem* prob, const jd_run* run, const double* mu
         return rc;
     JD_TRY(fb_launch_table(p, r, mu, w.tab, w.hdr, 1, stream));
     JD_TRY(fb_launch_forward(p, r, w.tab, traj, w.cpart, w.hdr, stream));
-    JD_TRY(fb_launch_finalize_cost(p, r, w.cpart, r.nblk, nullptr, J, w.hdr, 0, stream));
+    JD_TRY(fb_launch_finalize_cost(p, r, w.cpart, fb_forward_blocks(p, r), nullptr, J, w.hdr, 0,
+                                   stream));
     return JD_OK;
 }
 

@@ -230,7 +230,8 @@ class _FbDummy:
         self.st = B.jd_fb_problem(p.N, p.nx, p.nv, p.T, p.eta, p.b1, p.b2, p.gamma, p.beta,
                                   p.xmax, p.vmax, p.eps, p.alpha, p.sigJ, p.init_kind,
                                   (C.c_double * 2)(*p.z0), (C.c_double * 2)(*p.s0),
-                                  (C.c_double * 2)(*p.svar0), (C.c_double * 2)(*p.svar1), 0x1000)
+                                  (C.c_double * 2)(*p.svar0), (C.c_double * 2)(*p.svar1), 0x1000,
+                                  p.np, p.omega, p.cost_kind, p.ax, p.av)
 
 
 def test_fb_workspace_and_traj_sizes(L):
@@ -246,6 +247,26 @@ def test_fb_workspace_and_traj_sizes(L):
     assert L.jd_fb_traj_bytes(C.byref(pr.st), C.byref(run7)) == (p.N + 1) * 2 * 256 * 8
     rec = B.make_run(1000, precision="fp32", mode="recompute", K=10)
     assert L.jd_fb_traj_bytes(C.byref(pr.st), C.byref(rec)) == 0
+
+
+@pytest.mark.parametrize("np_,M,rows", [
+    (3, 100, 2),      # 85 rings of 3 per 256-slot workgroup: 2 workgroups
+    (256, 5, 5),      # one full ring per workgroup
+    (257, 7, 8),      # 8 groups of 256 slots hold 7 rings of 257
+    (2000, 3, 24),    # one ring of 2000 per 2048-slot workgroup
+    (2048, 2, 16),
+])
+def test_fb_ring_traj_sizes(L, np_, M, rows):
+    """Rings: whole rings per workgroup, 256 slots per trajectory row."""
+    p = wl.ring_problem(N=10, T=1.0, np_=np_)
+    pr = _FbDummy(p)
+    run = B.make_run(M, precision="fp32")
+    assert L.jd_fb_traj_bytes(C.byref(pr.st), C.byref(run)) == (p.N + 1) * 2 * rows * 256 * 4
+    assert L.jd_fb_workspace_bytes(C.byref(pr.st), C.byref(run)) >= rows * p.N * p.L * 8 // (
+        1 if np_ <= 256 else 8)
+    # the ellipse cost needs no target outside the surrogate mode
+    pr.st.zd = None
+    assert L.jd_fb_workspace_bytes(C.byref(pr.st), C.byref(run)) > 0
 
 
 @host_only
@@ -285,4 +306,19 @@ def test_fb_invalid_arguments_rejected_before_launch(L):
     assert L.jd_fb_optimize(P, C.byref(run), C.byref(bad_opt), fake, None, None, fake, fake, ws,
                             None) == B.JD_EINVAL
     assert L.jd_fb_draws(P, C.byref(run), -1, 4, 0, 4, fake, fake, fake, None) == B.JD_EINVAL
+    # rings (Section 6.4)
+    for kw in (dict(np=0), dict(np=B.JD_FB_MAX_RING + 1), dict(omega=float("nan")),
+               dict(cost_kind=2), dict(cost_kind=1, ax=0.0), dict(init_kind=2, av=-1.0),
+               dict(cost_kind=0, zd=None)):
+        assert call(**kw) == B.JD_EINVAL, kw
+    ring = _FbDummy(wl.ring_problem(N=20, T=2.0, np_=5))
+    R = C.byref(ring.st)
+    assert L.jd_fb_cost_grad(R, C.byref(sur), fake, fake, fake, None, fake, ws, None) == B.JD_EUNSUPPORTED
+    ring.st.zd = None
+    assert L.jd_fb_workspace_bytes(R, C.byref(sur)) == 0
+    big = B.make_run((1 << 31) // 5 + 1)
+    assert L.jd_fb_workspace_bytes(R, C.byref(big)) == 0
+    dump = B.jd_dump(0, 5 * 1000 + 1, None, None, None)
+    dr = B.make_run(1000, dump=dump)
+    assert L.jd_fb_forward(R, C.byref(dr), fake, fake, fake, fake, ws, None) == B.JD_EINVAL
     assert L.jd_fb_draws(P, C.byref(run), 0, 0, 0, 4, fake, fake, fake, None) == B.JD_OK
