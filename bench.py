@@ -66,6 +66,14 @@ ADJ_SLOTS_PER_PATH_STEP = 12
 # gradient's outer products.
 FB_FWD_SLOTS = 502
 FB_ADJ_SLOTS = 655
+# Coupled rings (Section 6.4, ring2: 512 rings of 2000 particles, 500 steps):
+# the forward adds the ring force omega (2x - x_l - x_r) (4 slots) and the
+# ellipse cost q = x^2/ax^2 + v^2/av^2 - 1, q^2 (2 more than the tracking
+# cost); the adjoint adds -2 omega to u_x - eta (1), the neighbours' dt omega
+# (w_l + w_r) (2) and the ellipse gradient (3 more than the tracking one).  The
+# neighbour exchange itself is LDS traffic and barriers, not VALU work.
+RING_FWD_SLOTS = 508
+RING_ADJ_SLOTS = 661
 HBM_PEAK = 8.0e12  # B/s
 METRIC = "forward+adjoint path-steps/s (FP32 vs FP64 GPU) at 1e-6 rel grad err; p50/p99"
 
@@ -83,6 +91,9 @@ def parse():
     ap.add_argument("--no-feedback", action="store_true",
                     help="skip the paper's model problem (feedback control) section")
     ap.add_argument("--fb-sample-paths", type=int, default=1 << 15)
+    ap.add_argument("--no-ring", action="store_true",
+                    help="skip the coupled-rings section (Section 6.4)")
+    ap.add_argument("--ring-sample-rings", type=int, default=16)
     ap.add_argument("--cpu-sample-paths", type=int, default=1 << 19)
     ap.add_argument("--only", choices=["all", "fp32_store", "kernels"], default="all",
                     help="kernels: time jd_forward / jd_adjoint only (for profiler runs)")
@@ -245,6 +256,82 @@ def feedback_section(args, time_calls, dev):
             del es
         out["oracle_error_on_sample"] = errs
         log(f"feedback oracle errors: {errs}")
+    return out
+
+
+def ring_section(args, time_calls, dev):
+    """Coupled particles (Section 6.4) at the measured size ring2: 512 rings of
+    2000 nearest-neighbour coupled particles, 500 steps, the ellipse cost and
+    the start on the ellipse: per-call times of jd_fb_cost_grad (FP32 and FP64
+    paths), the forward and adjoint kernels alone, the slot roofline, and the
+    oracle on a bounded sample of rings."""
+    import torch
+    from paper_2505_04328_amd import binding as B
+    from paper_2505_04328_amd import workloads as wl
+    w = wl.ring_config("ring2")
+    p = w.problem
+    mu = torch.tensor(wl.random_feedback_control(p, 4, 0.5), device=dev)
+    P = w.M * p.np
+    out = {"workload": "ring2: coupled particles (Section 6.4), 512 rings of 2000 particles "
+                       "(omega 0.5, eta 1), 500 steps, ellipse cost, 10 x 10 bump shape "
+                       "functions, Keilson-Storer jumps beta 10 gamma 0.9",
+           "rings": w.M, "np": p.np, "particles": P, "N": p.N, "L": p.L}
+    ps = P * p.N
+    res = {}
+    for prec in ("fp32", "fp64"):
+        e = B.FbEngine(p, M=w.M, seed=w.seed, precision=prec, device=dev)
+        for it in range(args.warmup):
+            e.cost_grad(mu, it=it)
+        cg = time_calls(lambda: e.cost_grad(mu, it=5), args.steps)
+        fw = time_calls(lambda: e.forward(mu, it=5), max(5, args.steps // 2))
+        ad = time_calls(lambda: e.adjoint(mu, it=5), max(5, args.steps // 2))
+        J, g = e.cost_grad(mu, it=0)
+        res[prec] = (float(J), g.cpu().numpy())
+        out[prec] = {"p50_ms": percentile(cg, 50), "p99_ms": percentile(cg, 99),
+                     "particle_steps_per_s_p50": ps / (percentile(cg, 50) * 1e-3),
+                     "forward_ms": float(np.mean(fw)), "adjoint_ms": float(np.mean(ad))}
+        del e
+        torch.cuda.empty_cache()
+    t_f, t_a = out["fp32"]["forward_ms"] * 1e-3, out["fp32"]["adjoint_ms"] * 1e-3
+    t_cg = out["fp32"]["p50_ms"] * 1e-3
+    out["roofline"] = {
+        "bound": "alu", "kernel": "k_fb_adjoint<float,12,8,false,true>",
+        "achieved": RING_ADJ_SLOTS * ps / t_a / 1e12, "peak": VALU_PEAK_SLOTS / 1e12,
+        "unit": "TOP/s (full-rate VALU lane-op slots)",
+        "frac": RING_ADJ_SLOTS * ps / t_a / VALU_PEAK_SLOTS, "traffic": None,
+        "slots_per_particle_step": RING_ADJ_SLOTS, "kernel_ms": t_a * 1e3}
+    out["forward_roofline"] = {"kernel": "k_fb_forward<float,12,true,8,true>", "bound": "alu",
+                               "frac": RING_FWD_SLOTS * ps / t_f / VALU_PEAK_SLOTS,
+                               "slots_per_particle_step": RING_FWD_SLOTS}
+    out["step_frac"] = (RING_FWD_SLOTS + RING_ADJ_SLOTS) * ps / t_cg / VALU_PEAK_SLOTS
+    J64, g64 = res["fp64"]
+    J32, g32 = res["fp32"]
+    out["fp32_vs_fp64_full_size"] = {"J_rel": abs(J32 - J64) / abs(J64),
+                                     "g_rel": float(np.linalg.norm(g32 - g64) / np.linalg.norm(g64))}
+    if not args.no_cpu_baseline:
+        from oracle import ref
+        Ms = args.ring_sample_rings
+        nth = ref.default_threads()
+        log(f"ring oracle: {Ms} rings of {p.np} x {p.N} steps on {nth} threads")
+        t0 = time.perf_counter()
+        Jo, go = ref.fb_cost_grad(p, Ms, w.seed, 0, mu.cpu().numpy(), nthreads=nth)
+        tc = time.perf_counter() - t0
+        # the oracle splits the rings into chunks of 4096 // np rings, one chunk per thread
+        used = min(nth, -(-Ms // max(1, 4096 // p.np)))
+        out["cpu_baseline"] = {"value": Ms * p.np * p.N / tc, "unit": "particle-steps/s",
+                               "cores": used, "kind": "oracle",
+                               "sample": f"ring2 with {Ms} of {w.M} rings ({Ms * p.np} particles), "
+                                         f"all {p.N} steps, forward+adjoint+reductions, FP64, "
+                                         f"{tc:.1f} s wall"}
+        errs = {}
+        for prec in ("fp32", "fp64"):
+            es = B.FbEngine(p, M=Ms, seed=w.seed, precision=prec, device=dev)
+            Js, gs = es.cost_grad(mu, it=0)
+            errs[prec] = {"J_rel": abs(float(Js) - Jo) / abs(Jo),
+                          "g_rel": float(np.linalg.norm(gs.cpu().numpy() - go) / np.linalg.norm(go))}
+            del es
+        out["oracle_error_on_sample"] = errs
+        log(f"ring oracle errors: {errs}")
     return out
 
 
@@ -415,6 +502,10 @@ def main():
     if not args.no_feedback and args.only == "all":
         log("feedback model (f4)")
         feedback = feedback_section(args, time_calls, dev)
+    rings = None
+    if not args.no_ring and args.only == "all":
+        log("coupled rings (ring2)")
+        rings = ring_section(args, time_calls, dev)
 
     fp32s = res["fp32_store_ms"]
     line = {
@@ -441,6 +532,7 @@ def main():
         "forms": forms,
         "oracle_error_on_sample": sample_err,
         "feedback": feedback,
+        "rings": rings,
     }
     print(json.dumps(line), flush=True)
 

@@ -143,13 +143,26 @@ struct NoSink {
     __device__ __forceinline__ void put_v(const Real*) const {}
 };
 
+// s + e = a + b exactly (Knuth's TwoSum; needs the build's -ffp-contract=off).
+__device__ __forceinline__ float two_sum(float a, float b, float& e) {
+    const float s = a + b;
+    const float bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+    return s;
+}
+
 // One forward step of one particle: control, draws, Euler step, jumps; cpl is
 // the ring force omega (2 x_j - x_{j-1} - x_{j+1}) (a literal 0 without rings).
-// Returns the control u_k; the bump values go to the sink.
+// FP32 paths carry the rounding error of the state updates in (cx, cv) and add
+// it to the next increment (compensated summation): the state then drifts from
+// the exact one by the rounding of the increments, which are small beside the
+// state, instead of by that of the state itself at every step.  FP64 paths
+// update plainly.  Returns the control u_k; the bump values go to the sink.
 template <typename Real, int NVP, typename Sink = NoSink>
 __device__ __forceinline__ Real fb_step(const FbArgs<Real>& a, const Real* __restrict__ mk,
                                         const Real* __restrict__ ks, uint32_t m, int k, Real& x,
-                                        Real& v, Real cpl, const Sink& sink = Sink()) {
+                                        Real& v, Real& cx, Real& cv, Real cpl,
+                                        const Sink& sink = Sink()) {
     Real pv[NVP];
     shapes_v<Real, NVP>(a, v, pv);
     Real u = 0;
@@ -170,17 +183,26 @@ __device__ __forceinline__ Real fb_step(const FbArgs<Real>& a, const Real* __res
     const Real R = bm_radius(w[0], (Real)0);
     const Real ub = unit_uniform<Real>(w[1]);
     const int n = poisson_count(poisson_word(w), a.thr);
-    const Real xn = fma(a.sqb1, bm_cos(R, ub), fma(a.dt, v, x));
-    Real vs = fma(a.sqb2, bm_sin(R, ub), fma(a.dt, fma(-a.eta, x, u) - cpl, v));
+    Real xn, vs, ex = 0, ev = 0;
+    if constexpr (sizeof(Real) == 4) {
+        xn = two_sum(x, fma(a.dt, v, fma(a.sqb1, bm_cos(R, ub), cx)), ex);
+        vs = two_sum(v, fma(a.dt, fma(-a.eta, x, u) - cpl, fma(a.sqb2, bm_sin(R, ub), cv)), ev);
+    } else {
+        xn = fma(a.sqb1, bm_cos(R, ub), fma(a.dt, v, x));
+        vs = fma(a.sqb2, bm_sin(R, ub), fma(a.dt, fma(-a.eta, x, u) - cpl, v));
+    }
     if (__builtin_amdgcn_ballot_w64(n != 0)) {
         Real gn, sv;
         ks_factors(ks, n, gn, sv);
         const Real zj = bm_cos(bm_radius(w[2], (Real)0), unit_uniform<Real>(w[3]));
         const Real vj = fma(sv, zj, gn * vs);
         vs = n != 0 ? vj : vs;
+        ev = n != 0 ? gn * ev : ev;
     }
     x = xn;
     v = vs;
+    cx = ex;
+    cv = ev;
     return u;
 }
 
@@ -309,7 +331,7 @@ k_fb_forward(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __restrict
     static_assert(RING || G == 1, "independent particles run one per lane");
     __shared__ double sh[kThreads];
     __shared__ Real xs[RING ? 2 : 1][RING ? G * kThreads : 1];
-    Real x[G], v[G];
+    Real x[G], v[G], cx[G], cv[G];
     double acc[G];
     FbSlot sl[G];
     Real* row[G];
@@ -324,6 +346,7 @@ k_fb_forward(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __restrict
         }
         fb_dump(a, a.dX, 0, sl[j].p, x[j], v[j]);
         acc[j] = 0.0;
+        cx[j] = cv[j] = 0;
     }
     for (int k = 0; k < a.N; ++k) {
         Real cpl[G];
@@ -340,7 +363,7 @@ k_fb_forward(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __restrict
 #pragma unroll
         for (int j = 0; j < G; ++j) {
             const Real u = fb_step<Real, NVP>(a, mu + (size_t)k * a.nx * NVP, ks, sl[j].p, k, x[j],
-                                              v[j], RING ? cpl[j] : (Real)0);
+                                              v[j], cx[j], cv[j], RING ? cpl[j] : (Real)0);
             acc[j] += (double)(a.hadt * u * u);
             acc[j] += (double)(a.dt * track(a, x[j], v[j], zd + 2 * (k + 1)));
             if (STORE) {
@@ -483,7 +506,7 @@ k_fb_forward_grad(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __res
     __shared__ double red[kThreads];
     FbWave<Real> wave = fb_wave(sh);
     const int N = a.N;
-    Real x[G], v[G];
+    Real x[G], v[G], cx[G], cv[G];
     double acc[G];
     int64_t m[G];
     bool act[G];
@@ -495,13 +518,15 @@ k_fb_forward_grad(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __res
         fb_initial(a, (uint32_t)m[j], x[j], v[j]);
         fb_dump(a, a.dX, 0, m[j], x[j], v[j]);
         acc[j] = 0.0;
+        cx[j] = cv[j] = 0;
     }
     for (int k = 0; k < N; ++k) {
         const Real* mk = mu + (size_t)k * a.nx * NVP;
         wave.clear();
 #pragma unroll
         for (int j = 0; j < G; ++j) {
-            const Real u = fb_step<Real, NVP>(a, mk, ks, (uint32_t)m[j], k, x[j], v[j], (Real)0, wave);
+            const Real u = fb_step<Real, NVP>(a, mk, ks, (uint32_t)m[j], k, x[j], v[j], cx[j], cv[j],
+                                              (Real)0, wave);
             wave.template add<NVP>(act[j] ? a.alpha * u : (Real)0, a.nx);
             acc[j] += (double)(a.hadt * u * u);
             acc[j] += (double)(a.dt * track(a, x[j], v[j], zd + 2 * (k + 1)));

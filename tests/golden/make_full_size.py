@@ -6,10 +6,12 @@ and u = 0, it records J, ||g||_L2, the L2 projections <g, delta_i> on 16 fixed
 random directions (numpy default_rng(2), L2-normalised) and 64 sampled entries
 of g; for c2 also the whole gradient.  For the paper's model problem at its
 measured size (f4: 2^20 particles, 500 steps) the same record is written at the
-control mu = random_feedback_control(p, 4, 0.5).  Run from the repository root:
+control mu = random_feedback_control(p, 4, 0.5), and so for the coupled rings
+of Section 6.4 at their measured size (ring2: 512 rings of 2000 particles, 500
+steps).  Run from the repository root:
 
     python tests/golden/make_full_size.py            # c2, c3, c4 (minutes on 8 cores)
-    python tests/golden/make_full_size.py c2 f4
+    python tests/golden/make_full_size.py c2 f4 ring2
 """
 from __future__ import annotations
 
@@ -44,7 +46,7 @@ def fb_directions(p, count=16, seed=2):
 
 
 def feedback(name):
-    w = wl.feedback_config(name)
+    w = wl.ring_config(name) if name.startswith("ring") else wl.feedback_config(name)
     p = w.problem
     t0 = time.time()
     mu = wl.random_feedback_control(p, 4, 0.5)
@@ -68,7 +70,7 @@ def feedback(name):
 
 def main(names):
     for name in names:
-        if name.startswith("f"):
+        if name.startswith("f") or name.startswith("ring"):
             feedback(name)
             continue
         w = wl.config(name)
