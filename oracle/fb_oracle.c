@@ -24,7 +24,9 @@
  *   iteration   Algorithm 5.4 with eq. Stochastic_Armijo;
  *   coupling    eq. interacting_model on a ring, the ellipse cost of
  *               eq. phonon_functional_tracking and the start on the ellipse
- *               of eq. coupled_ellipse (Section 6.4).
+ *               of eq. coupled_ellipse (Section 6.4);
+ *   grid        the jump-adapted grid of Section 3 (uniform points and jump
+ *               times) integrated as in Algorithms 5.1-5.2.
  */
 #include "fb_oracle.h"
 
@@ -36,6 +38,7 @@
 
 #define FB_CHUNK 4096
 #define FB_INIT_STEP 0xFFFFFFFFu
+#define FB_SUB 32 /* sub-steps of a uniform interval on the jump-adapted grid: <= 31 jumps + 1 */
 
 static const double FB_TWO_PI = 6.283185307179586476925286766559;
 static const double FB_PI = 3.141592653589793238462643383280;
@@ -112,6 +115,39 @@ void fb_step_draws(uint64_t seed, uint32_t m, uint32_t k, uint32_t iter, const u
     *n = or_poisson_count(P, thr);
 }
 
+/* Jump-adapted draws of interval k (see fb_oracle.h): the count and the
+ * sub-step-0 normals of block (m, k, iter, 0); for jump r = 1..n the
+ * Box-Muller pair of words 0, 1 of block (m, k, iter, r) (normals of sub-step
+ * r) and the cosine branch of its words 2, 3 (the jump normal); the offsets as
+ * successive minima of the n uniforms V_r. */
+void fb_adapted_draws(uint64_t seed, uint32_t m, uint32_t k, uint32_t iter, const uint64_t thr[32],
+                      int* n, double* a, double* Z, double* S)
+{
+    uint32_t key[2], W[4];
+    double Z3[3];
+    key_of(seed, key);
+    fb_step_draws(seed, m, k, iter, thr, Z3, n);
+    Z[0] = Z3[0];
+    Z[1] = Z3[1];
+    a[0] = 0.0;
+    for (int r = 1; r <= *n; ++r) {
+        uint32_t c1[4] = {m, k, iter, (uint32_t)r};
+        or_philox4x32_10(c1, key, W);
+        double R = sqrt(-2.0 * log(or_uniform(W[0])));
+        double th = FB_TWO_PI * or_uniform(W[1]);
+        Z[2 * r] = R * cos(th);
+        Z[2 * r + 1] = R * sin(th);
+        double R2 = sqrt(-2.0 * log(or_uniform(W[2])));
+        S[r] = R2 * cos(FB_TWO_PI * or_uniform(W[3]));
+        uint32_t c2[4] = {m, k, iter, 64u + (uint32_t)((r - 1) / 4)};
+        or_philox4x32_10(c2, key, W);
+        double V = or_uniform(W[(r - 1) % 4]);
+        /* the smallest of the n - r + 1 remaining uniforms on (a_{r-1}, 1) */
+        a[r] = a[r - 1] + (1.0 - a[r - 1]) * (1.0 - pow(V, 1.0 / (double)(*n - r + 1)));
+    }
+    a[*n + 1] = 1.0;
+}
+
 /* Surrogate state: zd_k + sqrt(var(t_k)) (R cos, R sin) from the Box-Muller
  * pair of words 0 and 1 of block (m, k, iter, 1). */
 void fb_surrogate_state(const fb_problem* pb, uint64_t seed, uint32_t m, uint32_t k, uint32_t iter,
@@ -131,6 +167,8 @@ void fb_surrogate_state(const fb_problem* pb, uint64_t seed, uint32_t m, uint32_
 static int check_problem(const fb_problem* pb)
 {
     if (!pb || pb->N < 1 || pb->nx < 1 || pb->nv < 1 || pb->nx > 16 || pb->nv > 16 || pb->np < 1)
+        return -1;
+    if ((pb->grid != 0 && pb->grid != 1) || (pb->grid == 1 && pb->np != 1))
         return -1;
     if (!(pb->T > 0.0) || !(pb->beta > 0.0) || !(pb->eps > 0.0) || !(pb->sigJ > 0.0))
         return -1;
@@ -191,22 +229,22 @@ static double ellipse_q(const fb_problem* pb, const double z[2])
     return z[0] * z[0] / (pb->ax * pb->ax) + z[1] * z[1] / (pb->av * pb->av) - 1.0;
 }
 
-/* Running cost at step k: the tracking cost -exp(-|z - zd_k|^2/(2 sigJ^2)), or
- * the ellipse cost -exp(-q^2/(2 sigJ^2)). */
-static double track(const fb_problem* pb, const double z[2], int k)
+/* Running cost against the target zd (ignored by the ellipse cost): the
+ * tracking cost -exp(-|z - zd|^2/(2 sigJ^2)), or the ellipse cost
+ * -exp(-q^2/(2 sigJ^2)). */
+static double track_to(const fb_problem* pb, const double z[2], const double* zd)
 {
     if (pb->cost_kind == 1) {
         double q = ellipse_q(pb, z);
         return -exp(-(q * q) / (2.0 * pb->sigJ * pb->sigJ));
     }
-    const double* zd = pb->zd + 2 * k;
     double rx = z[0] - zd[0], rv = z[1] - zd[1];
     return -exp(-(rx * rx + rv * rv) / (2.0 * pb->sigJ * pb->sigJ));
 }
 
 /* Its gradient: (z - zd)/sigJ^2 * exp(-|z - zd|^2/(2 sigJ^2)), or
  * q/sigJ^2 * exp(-q^2/(2 sigJ^2)) * (2x/ax^2, 2v/av^2). */
-static void track_grad(const fb_problem* pb, const double z[2], int k, double gz[2])
+static void track_grad_to(const fb_problem* pb, const double z[2], const double* zd, double gz[2])
 {
     double s2 = pb->sigJ * pb->sigJ;
     if (pb->cost_kind == 1) {
@@ -216,11 +254,39 @@ static void track_grad(const fb_problem* pb, const double z[2], int k, double gz
         gz[1] = e * 2.0 * z[1] / (pb->av * pb->av);
         return;
     }
-    const double* zd = pb->zd + 2 * k;
     double rx = z[0] - zd[0], rv = z[1] - zd[1];
     double e = exp(-(rx * rx + rv * rv) / (2.0 * s2));
     gz[0] = rx / s2 * e;
     gz[1] = rv / s2 * e;
+}
+
+/* The target at uniform point k (none for the ellipse cost). */
+static const double* target(const fb_problem* pb, int k)
+{
+    return pb->cost_kind == 1 ? NULL : pb->zd + 2 * k;
+}
+
+static double track(const fb_problem* pb, const double z[2], int k)
+{
+    return track_to(pb, z, target(pb, k));
+}
+
+static void track_grad(const fb_problem* pb, const double z[2], int k, double gz[2])
+{
+    track_grad_to(pb, z, target(pb, k), gz);
+}
+
+/* The target at fraction a in (0, 1] of uniform interval k: linear between the
+ * uniform targets, zd_{k+1} itself at a = 1. */
+static const double* target_at(const fb_problem* pb, int k, double a, double buf[2])
+{
+    if (pb->cost_kind == 1)
+        return NULL;
+    if (a == 1.0)
+        return pb->zd + 2 * (k + 1);
+    for (int c = 0; c < 2; ++c)
+        buf[c] = (1.0 - a) * pb->zd[2 * k + c] + a * pb->zd[2 * (k + 1) + c];
+    return buf;
 }
 
 /* gamma^n and V_n = (1/(2 beta)) sum_{i<n} gamma^{2i}: n Keilson-Storer jumps
@@ -241,6 +307,9 @@ static void ks_factors(const fb_problem* pb, int n, double* gn, double* Vn)
 typedef struct {
     double *z, *u, *px, *pv, *dpx, *dpv, *lam, *C, *w;
     int *n;
+    /* jump-adapted grid, per interval k and sub-step r (index k FB_SUB + r):
+     * start states sz (x, v), controls su, lengths sd, start offsets sa */
+    double *sz, *su, *sd, *sa;
 } work;
 
 static int work_alloc(const fb_problem* pb, work* w)
@@ -256,7 +325,13 @@ static int work_alloc(const fb_problem* pb, work* w)
     w->pv = (double*)malloc(16 * sizeof(double));
     w->dpx = (double*)malloc(16 * sizeof(double));
     w->dpv = (double*)malloc(16 * sizeof(double));
-    return (w->z && w->lam && w->u && w->n && w->C && w->w && w->px && w->pv && w->dpx && w->dpv)
+    const size_t ns = pb->grid == 1 ? N * FB_SUB : 1;
+    w->sz = (double*)malloc(ns * 2 * sizeof(double));
+    w->su = (double*)malloc(ns * sizeof(double));
+    w->sd = (double*)malloc(ns * sizeof(double));
+    w->sa = (double*)malloc(ns * sizeof(double));
+    return (w->z && w->lam && w->u && w->n && w->C && w->w && w->px && w->pv && w->dpx && w->dpv &&
+            w->sz && w->su && w->sd && w->sa)
                ? 0
                : -2;
 }
@@ -273,6 +348,10 @@ static void work_free(work* w)
     free(w->pv);
     free(w->dpx);
     free(w->dpv);
+    free(w->sz);
+    free(w->su);
+    free(w->sd);
+    free(w->sa);
 }
 
 /* Ring neighbours of particle j. */
@@ -283,8 +362,8 @@ static int right_of(const fb_problem* pb, int j) { return (j + 1) % pb->np; }
  * with the nearest-neighbour force of eq. interacting_model; the step's n
  * jumps applied after its Euler update): fills w->z, w->u, w->n and the
  * particle costs w->C, and returns their sum. */
-static double path_forward(const fb_problem* pb, const uint64_t thr[32], uint64_t seed,
-                           uint32_t iter, uint32_t m, const double* mu, work* w)
+static double path_forward_fixed(const fb_problem* pb, const uint64_t thr[32], uint64_t seed,
+                                 uint32_t iter, uint32_t m, const double* mu, work* w)
 {
     const int N = pb->N, L = pb->nx * pb->nv, np = pb->np;
     const double dt = pb->T / (double)N, sq = sqrt(dt);
@@ -325,7 +404,7 @@ static double path_forward(const fb_problem* pb, const uint64_t thr[32], uint64_
  * lam_j = dC/dz_j for C the sum of the particle costs, lam = -r): fills
  * w->lam for k = N..1 and, if G is given, adds each particle's gradient
  * summand phi(z_k) (alpha u_k + gamma^{n_k} lam^v_{k+1}) to G[k*L + l]. */
-static void path_adjoint(const fb_problem* pb, const double* mu, work* w, double* G)
+static void path_adjoint_fixed(const fb_problem* pb, const double* mu, work* w, double* G)
 {
     const int N = pb->N, L = pb->nx * pb->nv, np = pb->np;
     const double dt = pb->T / (double)N;
@@ -372,6 +451,126 @@ static void path_adjoint(const fb_problem* pb, const double* mu, work* w, double
         w->lam[2 * j] = 0.0;
         w->lam[2 * j + 1] = 0.0;
     }
+}
+
+/* Forward sweep of particle m on the jump-adapted grid (Algorithms 5.1-5.2):
+ * in each uniform interval, Euler sub-steps up to each jump time, the jump
+ * v <- gamma v + S/sqrt(2 beta) there, and on to the interval's end; the
+ * running cost on every sub-step.  Fills w->z, w->u (at the uniform points),
+ * w->n, the sub-step arrays and w->C[0]; returns the cost. */
+static double path_forward_adapted(const fb_problem* pb, const uint64_t thr[32], uint64_t seed,
+                                   uint32_t iter, uint32_t m, const double* mu, work* w)
+{
+    const int N = pb->N, L = pb->nx * pb->nv;
+    const double dtau = pb->T / (double)N, sb = 1.0 / sqrt(2.0 * pb->beta);
+    double a[FB_SUB + 1], Z[2 * FB_SUB], S[FB_SUB], zt[2];
+    fb_initial(pb, seed, m, iter, w->z);
+    double C = 0.0;
+    for (int k = 0; k < N; ++k) {
+        int n;
+        fb_adapted_draws(seed, m, (uint32_t)k, iter, thr, &n, a, Z, S);
+        w->n[k] = n;
+        double x = w->z[2 * k], v = w->z[2 * k + 1];
+        for (int r = 0; r <= n; ++r) {
+            const int s = k * FB_SUB + r;
+            const double d = (a[r + 1] - a[r]) * dtau;
+            const double zs[2] = {x, v};
+            w->sz[2 * s] = x;
+            w->sz[2 * s + 1] = v;
+            w->sd[s] = d;
+            w->sa[s] = a[r];
+            shapes(pb, zs, w->px, w->pv, NULL, NULL);
+            double u = control(pb, mu + (size_t)k * L, w->px, w->pv);
+            w->su[s] = u;
+            if (r == 0)
+                w->u[k] = u;
+            C += d * 0.5 * pb->alpha * u * u;
+            double xn = x + d * v + pb->b1 * sqrt(d) * Z[2 * r];
+            double vn = v + d * (u - pb->eta * x) + pb->b2 * sqrt(d) * Z[2 * r + 1];
+            if (r < n)
+                vn = pb->gamma * vn + S[r + 1] * sb;
+            x = xn;
+            v = vn;
+            const double ze[2] = {x, v};
+            C += d * track_to(pb, ze, target_at(pb, k, a[r + 1], zt));
+        }
+        w->z[2 * (k + 1)] = x;
+        w->z[2 * (k + 1) + 1] = v;
+    }
+    w->C[0] = C;
+    return C;
+}
+
+/* The exact adjoint of path_forward_adapted, sub-step by sub-step backwards:
+ * at the end of sub-step r the adjoint of the pre-jump state is
+ * (lam^x, gamma lam^v) if a jump ends it, and the start state z_r receives the
+ * Euler transpose, its control cost and the running cost of the sub-step that
+ * ends at it.  Adds d_r/dtau phi(z_r) (alpha u_r + lam^v_-) to G[k L + l]. */
+static void path_adjoint_adapted(const fb_problem* pb, const double* mu, work* w, double* G)
+{
+    const int N = pb->N, L = pb->nx * pb->nv;
+    const double dtau = pb->T / (double)N;
+    double gz[2], zt[2];
+    const double dlast = w->sd[(N - 1) * FB_SUB + w->n[N - 1]];
+    track_grad(pb, w->z + 2 * N, N, gz);
+    double lx = dlast * gz[0], lv = dlast * gz[1];
+    w->lam[2 * N] = lx;
+    w->lam[2 * N + 1] = lv;
+    for (int k = N - 1; k >= 0; --k) {
+        const double* mk = mu + (size_t)k * L;
+        const int n = w->n[k];
+        for (int r = n; r >= 0; --r) {
+            const int s = k * FB_SUB + r;
+            const double* zs = w->sz + 2 * s;
+            const double d = w->sd[s], u = w->su[s];
+            const double lxm = lx, lvm = r < n ? pb->gamma * lv : lv;
+            shapes(pb, zs, w->px, w->pv, w->dpx, w->dpv);
+            if (G) {
+                double wk = (d / dtau) * (pb->alpha * u + lvm);
+                for (int i = 0; i < pb->nx; ++i)
+                    for (int l = 0; l < pb->nv; ++l)
+                        G[(size_t)k * L + i * pb->nv + l] += w->px[i] * w->pv[l] * wk;
+            }
+            if (k == 0 && r == 0)
+                break;
+            /* the sub-step ending at z_r: r - 1 of this interval, or the last of k - 1 */
+            double dprev;
+            const double* tz;
+            if (r > 0) {
+                dprev = w->sd[s - 1];
+                tz = target_at(pb, k, w->sa[s], zt);
+            } else {
+                dprev = w->sd[(k - 1) * FB_SUB + w->n[k - 1]];
+                tz = target(pb, k);
+            }
+            double ux = control(pb, mk, w->dpx, w->pv);
+            double uv = control(pb, mk, w->px, w->dpv);
+            track_grad_to(pb, zs, tz, gz);
+            lx = lxm + d * (ux - pb->eta) * lvm + dprev * gz[0] + d * pb->alpha * u * ux;
+            lv = d * lxm + (1.0 + d * uv) * lvm + dprev * gz[1] + d * pb->alpha * u * uv;
+        }
+        if (k >= 1) {
+            w->lam[2 * k] = lx;
+            w->lam[2 * k + 1] = lv;
+        }
+    }
+    w->lam[0] = 0.0;
+    w->lam[1] = 0.0;
+}
+
+static double path_forward(const fb_problem* pb, const uint64_t thr[32], uint64_t seed,
+                           uint32_t iter, uint32_t m, const double* mu, work* w)
+{
+    return pb->grid == 1 ? path_forward_adapted(pb, thr, seed, iter, m, mu, w)
+                         : path_forward_fixed(pb, thr, seed, iter, m, mu, w);
+}
+
+static void path_adjoint(const fb_problem* pb, const double* mu, work* w, double* G)
+{
+    if (pb->grid == 1)
+        path_adjoint_adapted(pb, mu, w, G);
+    else
+        path_adjoint_fixed(pb, mu, w, G);
 }
 
 /* Copies the system's per-particle rows into particle-major outputs. */
@@ -544,7 +743,7 @@ static void path_adjoint_surrogate(const fb_problem* pb, const double* mu, uint6
 
 static int check_surrogate(const fb_problem* pb)
 {
-    return check_problem(pb) || pb->np != 1 || !pb->zd ? -1 : 0;
+    return check_problem(pb) || pb->np != 1 || pb->grid != 0 || !pb->zd ? -1 : 0;
 }
 
 int fb_paths_surrogate(const fb_problem* pb, uint64_t seed, uint32_t iter, int64_t m0, int64_t count,
@@ -644,6 +843,39 @@ int fb_cost_grad_surrogate(const fb_problem* pb, int64_t M, uint64_t seed, uint3
     return 0;
 }
 
+/* Tangent of particle m's cost on the jump-adapted grid (path in w): each
+ * Euler sub-step and jump differentiated directly. */
+static double tangent_adapted(const fb_problem* pb, const double* mu, const double* dmu, work* w)
+{
+    const int N = pb->N, L = pb->nx * pb->nv;
+    double tx = 0.0, tv = 0.0, dc = 0.0, gz[2], zt[2];
+    for (int k = 0; k < N; ++k) {
+        const double* mk = mu + (size_t)k * L;
+        const int n = w->n[k];
+        for (int r = 0; r <= n; ++r) {
+            const int s = k * FB_SUB + r;
+            const double* zs = w->sz + 2 * s;
+            const double d = w->sd[s], u = w->su[s];
+            shapes(pb, zs, w->px, w->pv, w->dpx, w->dpv);
+            double du = control(pb, mk, w->dpx, w->pv) * tx + control(pb, mk, w->px, w->dpv) * tv +
+                        control(pb, dmu + (size_t)k * L, w->px, w->pv);
+            dc += d * pb->alpha * u * du;
+            double nx = tx + d * tv;
+            double nv = tv + d * (du - pb->eta * tx);
+            if (r < n)
+                nv *= pb->gamma;
+            tx = nx;
+            tv = nv;
+            /* the state at the sub-step's end */
+            const double* ze = r < n ? w->sz + 2 * (s + 1) : w->z + 2 * (k + 1);
+            const double a_end = r < n ? w->sa[s + 1] : 1.0;
+            track_grad_to(pb, ze, target_at(pb, k, a_end, zt), gz);
+            dc += d * (gz[0] * tx + gz[1] * tv);
+        }
+    }
+    return dc;
+}
+
 /* Forward-mode derivative of J along dmu: differentiates the Euler step with
  * its coupling, the jump composition and the cost directly, independently of
  * the adjoint.  t holds the tangents (dx_j, dv_j) of the current step. */
@@ -677,6 +909,10 @@ int fb_tangent(const fb_problem* pb, int64_t M, uint64_t seed, uint32_t iter,
                 double cs = 0.0;
                 for (int64_t m = mb; m < me; ++m) {
                     path_forward(pb, thr, seed, iter, (uint32_t)m, mu, &w);
+                    if (pb->grid == 1) {
+                        cs += tangent_adapted(pb, mu, dmu, &w);
+                        continue;
+                    }
                     double* tn = t + 2 * np;
                     for (int j = 0; j < 2 * np; ++j)
                         t[j] = 0.0;

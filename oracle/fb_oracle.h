@@ -36,6 +36,26 @@
  * q = x^2/ax^2 + v^2/av^2 - 1.  Ellipse start (eq. coupled_ellipse): particle j
  * at (ax cos th_j, av sin th_j), th_j = 2 pi j / np, plus s0 . (Z1, Z2).
  *
+ * Jump-adapted grid (grid = 1; Section 3, the union of the uniform points and
+ * each particle's jump times, integrated as in Algorithms 5.1-5.2; independent
+ * particles).  In uniform interval k the particle has n ~ Poisson(sigma dtau)
+ * jumps (the count of block (m, k, iter, 0)) at offsets a_1 < ... < a_n (in
+ * units of dtau) drawn as the ordered minima of uniforms,
+ *   a_r = a_{r-1} + (1 - a_{r-1}) (1 - V_r^{1/(n-r+1)}),  a_0 = 0, a_{n+1} = 1,
+ * V_r = word (r-1) mod 4 of block (m, k, iter, 64 + (r-1)/4)  (the order
+ * statistics of n uniforms: a Poisson process on the interval).  Sub-step r
+ * (r = 0..n) spans [a_r, a_{r+1}] dtau with length d_r and normals (Zx_r, Zv_r):
+ * the Box-Muller pair of words 0, 1 of block (m, k, iter, r).  Sub-step r < n
+ * ends at jump r+1: v <- gamma v + S_{r+1} / sqrt(2 beta), S_r the cosine branch
+ * of words 2, 3 of block (m, k, iter, r).  Euler on each sub-step with the
+ * interval's control mu_k; the cost is
+ *   C = sum over sub-steps [ d_r Jt(z_end, zd(t_end)) + d_r alpha/2 u_r^2 ]
+ * (z_end the post-jump state, zd linear between the uniform targets), the
+ * adjoint the exact transpose (p <- gamma p at the jumps) and
+ *   g_k[l] = (1/(M dtau)) sum_m sum_r d_r phi_l(z_r) (alpha u_r + lam^v_-(end of r)),
+ * lam^v_- the adjoint of the pre-jump velocity.  With no jumps this is the
+ * fixed-grid model exactly.
+ *
  * Surrogate gradient (Section 6.5, the adjoint independent of the forward
  * trajectories): the adjoint runs on states zs_k ~ N(zd_k, diag(var(t_k))),
  * drawn from Philox block (m, k, iter, 1) (Box-Muller pair of words 0, 1),
@@ -66,6 +86,7 @@ typedef struct {
     double omega;          /* nearest-neighbour coupling */
     int32_t cost_kind;     /* 0: tracking cost around zd, 1: ellipse cost */
     double ax, av;         /* ellipse half-axes (cost_kind 1, init_kind 2) */
+    int32_t grid;          /* 0: fixed grid with Poisson counts, 1: jump-adapted grid */
 } fb_problem;
 
 /* Bump b(r) and its derivative b'(r). */
@@ -77,6 +98,12 @@ double fb_bump_deriv(double r, double eps);
 void fb_initial(const fb_problem* pb, uint64_t seed, uint32_t m, uint32_t iter, double z[2]);
 void fb_step_draws(uint64_t seed, uint32_t m, uint32_t k, uint32_t iter, const uint64_t thr[32],
                    double Z[3], int* n);
+
+/* Jump-adapted draws of interval k of particle m: the count n, the offsets
+ * a[0..n+1], the sub-step normals Z[2r], Z[2r+1] (r = 0..n) and the jump
+ * normals S[r] (r = 1..n).  Arrays hold 33, 33 x 2 and 32 entries. */
+void fb_adapted_draws(uint64_t seed, uint32_t m, uint32_t k, uint32_t iter, const uint64_t thr[32],
+                      int* n, double* a, double* Z, double* S);
 
 /* Per-particle states z (P x (N+1) x 2), adjoints lam (P x (N+1) x 2, row 0
  * zero), controls u (P x N), jump counts (P x N) and costs C (P) of the

@@ -213,7 +213,8 @@ class _FbProblem(C.Structure):
                 ("sigJ", C.c_double), ("init_kind", C.c_int32), ("z0", C.c_double * 2),
                 ("s0", C.c_double * 2), ("svar0", C.c_double * 2), ("svar1", C.c_double * 2),
                 ("zd", C.c_void_p), ("np", C.c_int32), ("omega", C.c_double),
-                ("cost_kind", C.c_int32), ("ax", C.c_double), ("av", C.c_double)]
+                ("cost_kind", C.c_int32), ("ax", C.c_double), ("av", C.c_double),
+                ("grid", C.c_int32)]
 
 
 def _bind_fb(L):
@@ -240,6 +241,7 @@ def _bind_fb(L):
                               C.c_int, C.c_int]
     L.fb_paths_surrogate.argtypes = [P, C.c_uint64, C.c_uint32, C.c_int64, C.c_int64, P, P, C.c_int]
     L.fb_paths_surrogate.restype = C.c_int
+    L.fb_adapted_draws.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, P, P, P, P, P]
     L.fb_optimize.restype = C.c_int
     L._fb_bound = True
     return L
@@ -258,7 +260,7 @@ class _Fb:
                              p.vmax, p.eps, p.alpha, p.sigJ, p.init_kind,
                              (C.c_double * 2)(*p.z0), (C.c_double * 2)(*p.s0),
                              (C.c_double * 2)(*p.svar0), (C.c_double * 2)(*p.svar1),
-                             self.zd.ctypes.data, p.np, p.omega, p.cost_kind, p.ax, p.av)
+                             self.zd.ctypes.data, p.np, p.omega, p.cost_kind, p.ax, p.av, p.grid)
 
     def ref(self):
         return C.byref(self.st)
@@ -290,6 +292,19 @@ def fb_step_draws(p, seed: int, m: int, k: int, it: int):
     n = C.c_int()
     _fb().fb_step_draws(seed, m, k, it, _ptr(thr), _ptr(Z), C.byref(n))
     return Z, n.value
+
+
+def fb_adapted_draws(p, seed: int, m: int, k: int, it: int):
+    """Jump-adapted draws of interval k of particle m: (n, offsets a[0..n+1],
+    sub-step normals (n+1, 2), jump normals S[1..n])."""
+    thr = poisson_thresholds(p.rate * p.dt)
+    n = C.c_int()
+    a = np.zeros(33)
+    Z = np.zeros(66)
+    S = np.zeros(32)
+    _fb().fb_adapted_draws(seed, m, k, it, _ptr(thr), C.byref(n), _ptr(a), _ptr(Z), _ptr(S))
+    n = n.value
+    return n, a[:n + 2].copy(), Z[:2 * (n + 1)].reshape(n + 1, 2).copy(), S[1:n + 1].copy()
 
 
 def fb_paths(p, seed: int, it: int, m0: int, count: int, mu, nthreads: int | None = None):

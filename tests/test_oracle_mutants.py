@@ -3,8 +3,9 @@ of the oracle source (on the CPU), build it, and run the pin suites against the
 mutant.  Every mutant must make at least one pin fail; the unmodified source
 must pass them all (the pin suites themselves run that case).
 
-Not listed: the byte layout of the Poisson word, and which Philox block feeds
-the surrogate states of the feedback model.  Which bits feed the count is a
+Not listed: the byte layout of the Poisson word, which Philox block feeds
+the surrogate states of the feedback model, and which Box-Muller branch gives
+the jump normal on the jump-adapted grid.  Which bits feed the count is a
 convention, not a law: any layout using bits the uniforms do not read gives the
 same distribution, so no pin of the law can see it.  It is fixed only by the
 bit-exact agreement of the two independent implementations (oracle and GPU)."""
@@ -21,7 +22,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 # pin suites run against a mutant of each oracle source file
 PIN_FILES = {
     "jd_oracle.c": ["tests/test_oracle_rng.py", "tests/test_oracle_model.py"],
-    "fb_oracle.c": ["tests/test_oracle_fb.py", "tests/test_oracle_coupled.py"],
+    "fb_oracle.c": ["tests/test_oracle_fb.py", "tests/test_oracle_coupled.py",
+                    "tests/test_oracle_adapted.py"],
 }
 
 # name: (exact text in jd_oracle.c, replacement)
@@ -130,6 +132,28 @@ FB_MUTANTS = {
                                "(double)(m % (uint32_t)pb->np) / (double)(pb->np + 1);"),
     "fb_ellipse_start_axes": ("z[0] = pb->ax * cos(th)", "z[0] = pb->av * cos(th)"),
     "fb_tangent_coupling_neighbour": ("pb->omega * (2.0 * tx - txl - txr)", "pb->omega * (2.0 * tx - txl - txl)"),
+    # jump-adapted grid (Section 3, Algorithms 5.1-5.2)
+    "fb_adapted_offset_exponent": ("pow(V, 1.0 / (double)(*n - r + 1))", "pow(V, 1.0 / (double)(*n - r + 2))"),
+    "fb_adapted_offset_not_ordered": ("a[r] = a[r - 1] + (1.0 - a[r - 1]) * (1.0 - pow(",
+                                      "a[r] = a[r - 1] + (1.0 - a[r - 1]) * (0.5 - 0.5 * pow("),
+    "fb_adapted_uniform_word": ("double V = or_uniform(W[(r - 1) % 4]);", "double V = or_uniform(W[0]);"),
+    "fb_adapted_jump_scale": ("sb = 1.0 / sqrt(2.0 * pb->beta);", "sb = 1.0 / sqrt(pb->beta);"),
+    "fb_adapted_jump_at_interval_end": ("            if (r < n)\n                vn = pb->gamma * vn + S[r + 1] * sb;",
+                                        "            if (r > 0)\n                vn = pb->gamma * vn + S[r] * sb;"),
+    "fb_adapted_substep_noise_dt": ("double xn = x + d * v + pb->b1 * sqrt(d) * Z[2 * r];",
+                                    "double xn = x + d * v + pb->b1 * sqrt(dtau) * Z[2 * r];"),
+    "fb_adapted_cost_weight": ("C += d * track_to(pb, ze, target_at(pb, k, a[r + 1], zt));",
+                               "C += dtau * track_to(pb, ze, target_at(pb, k, a[r + 1], zt));"),
+    "fb_adapted_target_reversed": ("buf[c] = (1.0 - a) * pb->zd[2 * k + c] + a * pb->zd[2 * (k + 1) + c];",
+                                   "buf[c] = a * pb->zd[2 * k + c] + (1.0 - a) * pb->zd[2 * (k + 1) + c];"),
+    "fb_adapted_adjoint_no_jump_factor": ("const double lxm = lx, lvm = r < n ? pb->gamma * lv : lv;",
+                                          "const double lxm = lx, lvm = lv;"),
+    "fb_adapted_adjoint_prev_weight": ("                dprev = w->sd[s - 1];", "                dprev = w->sd[s];"),
+    "fb_adapted_adjoint_terminal_weight": ("double lx = dlast * gz[0], lv = dlast * gz[1];",
+                                           "double lx = dtau * gz[0], lv = dtau * gz[1];"),
+    "fb_adapted_gradient_weight": ("double wk = (d / dtau) * (pb->alpha * u + lvm);",
+                                   "double wk = pb->alpha * u + lvm;"),
+    "fb_adapted_tangent_jump": ("                nv *= pb->gamma;", "                nv *= 1.0;"),
     "fb_surr_control_cost_source_dropped": ("double nlx = lx + gn * dt * (ux - pb->eta) * lv + dt * gz[0] + dt * pb->alpha * u * ux;",
                                             "double nlx = lx + gn * dt * (ux - pb->eta) * lv + dt * gz[0];"),
 }
