@@ -51,6 +51,24 @@
  * Gaussian pair of the initial-state block.  One ring runs inside one
  * workgroup, its neighbours exchanged through LDS.
  *
+ * Jump-adapted grid (grid = JD_FB_GRID_ADAPTED; Section 3 and Algorithms
+ * 5.1-5.2; independent particles, JD_STORE): each particle's grid is the
+ * uniform points t_k plus its jump times.  Interval k holds the n jumps
+ * counted by Philox block (m, k, iter, 0) (the count above), at offsets
+ * a_1 < ... < a_n (units of dt) drawn as successive minima of uniforms,
+ *   a_r = a_{r-1} + (1 - a_{r-1}) (1 - V_r^{1/(n-r+1)}),  a_0 = 0, a_{n+1} = 1,
+ * V_r = word (r-1) mod 4 of block (m, k, iter, 64 + (r-1)/4) (a Poisson process
+ * on the interval).  Sub-step r spans [a_r, a_{r+1}] dt (length d_r) with the
+ * Box-Muller pair of words 0, 1 of block (m, k, iter, r) and the control mu_k;
+ * sub-step r < n ends at jump r+1: v <- gamma v + S / sqrt(2 beta), S the
+ * cosine normal of words 2, 3 of block (m, k, iter, r+1).  The cost is
+ *   C = sum over sub-steps d_r (Jt(z_end, zd(t_end)) + alpha/2 u_r^2)
+ * (z_end post-jump; zd linear between the uniform targets), the adjoint its
+ * exact transpose (lam^v <- gamma lam^v across a jump), and
+ *   g_k[l] = (1/M) sum_m sum_r (d_r/dt) phi_l(z_r) (alpha u_r + lam^v_-(end of r)).
+ * The trajectory, dumps and lam rows hold the uniform points; with no jumps
+ * the model is the fixed-grid one.
+ *
  * Surrogate gradient (run->mode = JD_SURROGATE; Section 6.5, the adjoint
  * independent of the forward trajectories): nothing is stored.  The forward
  * adds alpha u_k phi(z_k) to the gradient as it goes; the adjoint recursion
@@ -85,6 +103,9 @@ extern "C" {
 
 #define JD_FB_MAX_RING 2048  /* largest np: one ring per workgroup */
 
+#define JD_FB_GRID_FIXED 0   /* fixed grid, Poisson jump counts composed per step */
+#define JD_FB_GRID_ADAPTED 1 /* jump-adapted grid: uniform points plus jump times */
+
 typedef struct jd_fb_problem {
     int32_t N;          /* time steps, >= 1 */
     int32_t nx, nv;     /* shape-function grid, 1..16 each; L = nx nv */
@@ -106,6 +127,7 @@ typedef struct jd_fb_problem {
     double omega;       /* nearest-neighbour coupling (finite) */
     int32_t cost_kind;  /* JD_FB_COST_TRACK or JD_FB_COST_ELLIPSE */
     double ax, av;      /* ellipse half-axes, > 0 (ellipse cost or start) */
+    int32_t grid;       /* JD_FB_GRID_FIXED or JD_FB_GRID_ADAPTED (np = 1, JD_STORE) */
 } jd_fb_problem;
 
 /* Per-path diagnostics for the feedback model, as jd_dump with these layouts

@@ -299,6 +299,7 @@ def poisson_thresholds(mu: float) -> np.ndarray:
 JD_FB_INIT_GAUSS, JD_FB_INIT_UNIFORM, JD_FB_INIT_ELLIPSE = 0, 1, 2
 JD_FB_COST_TRACK, JD_FB_COST_ELLIPSE = 0, 1
 JD_FB_MAX_RING = 2048
+JD_FB_GRID_FIXED, JD_FB_GRID_ADAPTED = 0, 1
 
 
 class jd_fb_problem(C.Structure):
@@ -309,7 +310,8 @@ class jd_fb_problem(C.Structure):
                 ("sigJ", C.c_double), ("init_kind", C.c_int32), ("z0", C.c_double * 2),
                 ("s0", C.c_double * 2), ("svar0", C.c_double * 2), ("svar1", C.c_double * 2),
                 ("zd", C.c_void_p), ("np", C.c_int32), ("omega", C.c_double),
-                ("cost_kind", C.c_int32), ("ax", C.c_double), ("av", C.c_double)]
+                ("cost_kind", C.c_int32), ("ax", C.c_double), ("av", C.c_double),
+                ("grid", C.c_int32)]
 
 
 class FbProblem:
@@ -324,7 +326,7 @@ class FbProblem:
                                 p.vmax, p.eps, p.alpha, p.sigJ, p.init_kind,
                                 (C.c_double * 2)(*p.z0), (C.c_double * 2)(*p.s0),
                                 (C.c_double * 2)(*p.svar0), (C.c_double * 2)(*p.svar1),
-                                self.zd.data_ptr(), p.np, p.omega, p.cost_kind, p.ax, p.av)
+                                self.zd.data_ptr(), p.np, p.omega, p.cost_kind, p.ax, p.av, p.grid)
 
     @property
     def ref(self):

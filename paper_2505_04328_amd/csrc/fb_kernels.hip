@@ -39,6 +39,7 @@ struct FbArgs {
     Real omega, iax2, iav2, ax, av;  // coupling, 1/ax^2, 1/av^2, half-axes
     int nblk, N, nx, nv;
     Real dt, sqb1, sqb2, eta, eps, alpha, hadt, inv2s2, invs2;
+    Real b1, b2, gamma, sbeta;  // jump-adapted grid: noise scales, gamma, 1/sqrt(2 beta)
     Real xc0, dxc, vc0, dvc;  // centres x^i = xc0 + i dxc, v^l = vc0 + l dvc
     Real z0x, z0v, s0x, s0v;
     Real var0x, var0v, var1x, var1v;  // surrogate-state variance var(t) = var0 + var1 t
@@ -158,11 +159,11 @@ __device__ __forceinline__ float two_sum(float a, float b, float& e) {
 // the exact one by the rounding of the increments, which are small beside the
 // state, instead of by that of the state itself at every step.  FP64 paths
 // update plainly.  Returns the control u_k; the bump values go to the sink.
+// The feedback control u = sum_i b(x - x^i) sum_l mu_il b(v - v^l); the bump
+// values go to the sink.
 template <typename Real, int NVP, typename Sink = NoSink>
-__device__ __forceinline__ Real fb_step(const FbArgs<Real>& a, const Real* __restrict__ mk,
-                                        const Real* __restrict__ ks, uint32_t m, int k, Real& x,
-                                        Real& v, Real& cx, Real& cv, Real cpl,
-                                        const Sink& sink = Sink()) {
+__device__ __forceinline__ Real fb_control(const FbArgs<Real>& a, const Real* __restrict__ mk,
+                                           Real x, Real v, const Sink& sink = Sink()) {
     Real pv[NVP];
     shapes_v<Real, NVP>(a, v, pv);
     Real u = 0;
@@ -178,6 +179,15 @@ __device__ __forceinline__ Real fb_step(const FbArgs<Real>& a, const Real* __res
         sink.put_x(i, bx);
     }
     sink.template put_v<Real, NVP>(pv);
+    return u;
+}
+
+template <typename Real, int NVP, typename Sink = NoSink>
+__device__ __forceinline__ Real fb_step(const FbArgs<Real>& a, const Real* __restrict__ mk,
+                                        const Real* __restrict__ ks, uint32_t m, int k, Real& x,
+                                        Real& v, Real& cx, Real& cv, Real cpl,
+                                        const Sink& sink = Sink()) {
+    const Real u = fb_control<Real, NVP, Sink>(a, mk, x, v, sink);
     uint32_t w[4];
     philox4x32_10<true>(m, (uint32_t)k, a.iter, 0u, a.key0, a.key1, w);
     const Real R = bm_radius(w[0], (Real)0);
@@ -687,6 +697,267 @@ k_fb_adjoint(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __restrict
     }
 }
 
+// ---------------------------------------------------------------------------
+// Jump-adapted grid (Section 3; Algorithms 5.1-5.2): each particle's grid is
+// the uniform points plus its jump times.  Uniform interval k holds the n jumps
+// counted by Philox block (m, k, iter, 0), at offsets a_1 < ... < a_n (units of
+// dt) that are successive minima of uniforms; sub-step r spans [a_r, a_{r+1}]
+// with the normals of block (m, k, iter, r) (block 0 for r = 0) and, for r < n,
+// ends with the jump v <- gamma v + S sqrt(1/(2 beta)), S the cosine normal of
+// words 2, 3 of block (m, k, iter, r + 1).
+
+// V^(1/c) for V in (0, 1).
+__device__ __forceinline__ float fb_root(float V, int c) {
+    return __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(V) / (float)c);
+}
+__device__ __forceinline__ double fb_root(double V, int c) { return pow(V, 1.0 / (double)c); }
+
+// a_{r+1} from a_r: the smallest of the n - r uniforms left on (a_r, 1), with
+// V_{r+1} = word r mod 4 of block (m, k, iter, 64 + r / 4).
+template <typename Real>
+__device__ __forceinline__ Real fb_next_offset(const FbArgs<Real>& a, uint32_t m, int k, int r,
+                                               int n, Real ar) {
+    uint32_t w[4];
+    philox4x32_10<false>(m, (uint32_t)k, a.iter, 64u + (uint32_t)(r >> 2), a.key0, a.key1, w);
+    const uint32_t wr = (r & 2) ? ((r & 1) ? w[3] : w[2]) : ((r & 1) ? w[1] : w[0]);
+    return fma((Real)1 - ar, (Real)1 - fb_root(unit_uniform<Real>(wr), n - r), ar);
+}
+
+// One Euler sub-step of length d (noise scales sq1 = b1 sqrt(d), sq2 =
+// b2 sqrt(d)) with control u and normals (zx, zv); FP32 compensated as fb_step.
+template <typename Real>
+__device__ __forceinline__ void fb_euler(const FbArgs<Real>& a, Real d, Real sq1, Real sq2, Real u,
+                                         Real zx, Real zv, Real& x, Real& v, Real& cx, Real& cv) {
+    if constexpr (sizeof(Real) == 4) {
+        Real ex, ev;
+        const Real xn = two_sum(x, fma(d, v, fma(sq1, zx, cx)), ex);
+        const Real vn = two_sum(v, fma(d, fma(-a.eta, x, u), fma(sq2, zv, cv)), ev);
+        x = xn;
+        v = vn;
+        cx = ex;
+        cv = ev;
+    } else {
+        const Real xn = fma(sq1, zx, fma(d, v, x));
+        const Real vn = fma(sq2, zv, fma(d, fma(-a.eta, x, u), v));
+        x = xn;
+        v = vn;
+    }
+}
+
+// The target at fraction f in (0, 1] of interval k (zk = zd + 2k): linear
+// between the uniform targets, zd_{k+1} itself at f = 1.
+template <typename Real>
+__device__ __forceinline__ void fb_target(const Real* __restrict__ zk, Real f, Real* t) {
+    if (f == (Real)1) {
+        t[0] = zk[2];
+        t[1] = zk[3];
+    } else {
+        t[0] = fma(f, zk[2], ((Real)1 - f) * zk[0]);
+        t[1] = fma(f, zk[3], ((Real)1 - f) * zk[1]);
+    }
+}
+
+// Sub-steps r0 .. r1 - 1 (at most up to n) of interval k of one particle,
+// from the state at the start of sub-step r0 with its offsets (a0, a1) and
+// normals (zx, zv); the running cost is added to acc when acc is given.  On
+// return the same variables describe the start of sub-step r1 (post-jump).
+template <typename Real, int NVP>
+__device__ __forceinline__ void fb_advance(const FbArgs<Real>& a, const Real* __restrict__ mk,
+                                           const Real* __restrict__ zk, uint32_t m, int k, int n,
+                                           int r0, int r1, Real& x, Real& v, Real& cx, Real& cv,
+                                           Real& a0, Real& a1, Real& zx, Real& zv, double* acc) {
+    for (int r = r0; r < r1 && r <= n; ++r) {
+        const bool whole = n == 0;
+        const Real d = whole ? a.dt : (a1 - a0) * a.dt;
+        const Real u = fb_control<Real, NVP>(a, mk, x, v);
+        if (acc != nullptr)
+            *acc += (double)((whole ? a.hadt : (Real)0.5 * a.alpha * d) * u * u);
+        fb_euler(a, d, whole ? a.sqb1 : a.b1 * sqrt(d), whole ? a.sqb2 : a.b2 * sqrt(d), u, zx, zv,
+                 x, v, cx, cv);
+        if (r < n) {
+            uint32_t w[4];
+            philox4x32_10<false>(m, (uint32_t)k, a.iter, (uint32_t)(r + 1), a.key0, a.key1, w);
+            const Real S = bm_cos(bm_radius(w[2], (Real)0), unit_uniform<Real>(w[3]));
+            v = fma(S, a.sbeta, a.gamma * v);
+            cv = a.gamma * cv;
+            const Real R = bm_radius(w[0], (Real)0);
+            const Real ub = unit_uniform<Real>(w[1]);
+            zx = bm_cos(R, ub);
+            zv = bm_sin(R, ub);
+        }
+        if (acc != nullptr) {
+            Real tg[2];
+            fb_target(zk, a1, tg);
+            *acc += (double)(d * track(a, x, v, tg));
+        }
+        a0 = a1;
+        a1 = r + 1 < n ? fb_next_offset(a, m, k, r + 1, n, a1) : (Real)1;
+    }
+}
+
+// The count and sub-step-0 normals of interval k, and a_1.
+template <typename Real>
+__device__ __forceinline__ int fb_interval(const FbArgs<Real>& a, uint32_t m, int k, Real& zx,
+                                           Real& zv, Real& a1) {
+    uint32_t w[4];
+    philox4x32_10<true>(m, (uint32_t)k, a.iter, 0u, a.key0, a.key1, w);
+    const int n = poisson_count(poisson_word(w), a.thr);
+    const Real R = bm_radius(w[0], (Real)0);
+    const Real ub = unit_uniform<Real>(w[1]);
+    zx = bm_cos(R, ub);
+    zv = bm_sin(R, ub);
+    a1 = n > 0 ? fb_next_offset(a, m, k, 0, n, (Real)0) : (Real)1;
+    return n;
+}
+
+// Forward sweep on the jump-adapted grid, one particle per lane: every
+// interval's sub-steps and jumps (lanes without jumps take one step), the
+// running cost of each sub-step; the trajectory holds the uniform points.
+template <typename Real, int NVP, bool STORE>
+__global__ void __launch_bounds__(kThreads)
+k_fb_forward_adapted(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __restrict__ zd,
+                     void* traj, double* __restrict__ cpart) {
+    __shared__ double sh[kThreads];
+    const FbSlot sl = fb_slot<1>(a, 0);
+    Real x, v, cx = 0, cv = 0;
+    fb_initial(a, sl.p, x, v);
+    Real* row = STORE ? fb_row<Real>(traj, a.N, blockIdx.x) : nullptr;
+    if (STORE) {
+        __builtin_nontemporal_store(x, row);
+        __builtin_nontemporal_store(v, row + kThreads);
+    }
+    fb_dump(a, a.dX, 0, sl.p, x, v);
+    double acc = 0.0;
+    for (int k = 0; k < a.N; ++k) {
+        Real zx, zv, a0 = 0, a1;
+        const int n = fb_interval(a, sl.p, k, zx, zv, a1);
+        fb_advance<Real, NVP>(a, mu + (size_t)k * a.nx * NVP, zd + 2 * k, sl.p, k, n, 0, n + 1, x,
+                              v, cx, cv, a0, a1, zx, zv, &acc);
+        if (STORE) {
+            Real* r = row + (size_t)(k + 1) * 2 * kThreads;
+            __builtin_nontemporal_store(x, r);
+            __builtin_nontemporal_store(v, r + kThreads);
+        }
+        fb_dump(a, a.dX, k + 1, sl.p, x, v);
+    }
+    const double C = sl.act ? acc : 0.0;
+    if (a.dcost != nullptr) {
+        const int64_t p = (int64_t)sl.p - a.dm0;
+        if (sl.act && p >= 0 && p < a.dcount)
+            a.dcost[p] = C;
+    }
+    const double s = block_sum(C, sh);
+    if (threadIdx.x == 0)
+        cpart[blockIdx.x] = s;
+}
+
+// Backward sweep on the jump-adapted grid, one particle per lane.  The lane
+// carries lam~, the adjoint of the interval's end state without the running
+// cost charged there, and the unweighted cost gradient at that state; the
+// length of the interval's last sub-step completes it (and the dump).  The
+// sub-steps then run backwards in a wave-uniform loop over the wave's largest
+// count (each lane recomputes the start of its sub-step r from the stored
+// state at the interval's start), each adding d_r/dt phi(z_r) (alpha u_r +
+// lam^v_-) to the matrix-core sums; lam^v_- carries the jump factor gamma.
+template <typename Real, int NVP>
+__global__ void __launch_bounds__(kThreads)
+k_fb_adjoint_adapted(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __restrict__ zd,
+                     const void* traj, double* __restrict__ apart) {
+    __shared__ FbShared<Real> sh;
+    FbWave<Real> wave = fb_wave(sh);
+    const int N = a.N;
+    const FbSlot sl = fb_slot<1>(a, 0);
+    const Real* row = fb_row<Real>(const_cast<void*>(traj), N, blockIdx.x);
+    const Real xN = __builtin_nontemporal_load(row + (size_t)N * 2 * kThreads);
+    const Real vN = __builtin_nontemporal_load(row + (size_t)N * 2 * kThreads + kThreads);
+    Real gxe, gve;  // unweighted running-cost gradient at the interval's end state
+    track_grad(a, xN, vN, zd + 2 * N, gxe, gve);
+    Real lx = 0, lv = 0;
+    Real xk = __builtin_nontemporal_load(row + (size_t)(N - 1) * 2 * kThreads);
+    Real vk = __builtin_nontemporal_load(row + (size_t)(N - 1) * 2 * kThreads + kThreads);
+    for (int k = N - 1; k >= 0; --k) {
+        const Real* mk = mu + (size_t)k * a.nx * NVP;
+        const Real* zk = zd + 2 * k;
+        Real xp = 0, vp = 0;
+        if (k >= 1) {
+            xp = __builtin_nontemporal_load(row + (size_t)(k - 1) * 2 * kThreads);
+            vp = __builtin_nontemporal_load(row + (size_t)(k - 1) * 2 * kThreads + kThreads);
+        }
+        Real zx0, zv0, a1_0;
+        const int n = fb_interval(a, sl.p, k, zx0, zv0, a1_0);
+        // the last sub-step starts at a_n
+        Real an = 0;
+        if (n > 0) {
+            an = a1_0;
+            for (int r = 1; r < n; ++r)
+                an = fb_next_offset(a, sl.p, k, r, n, an);
+        }
+        const Real dlast = n == 0 ? a.dt : ((Real)1 - an) * a.dt;
+        lx = fma(dlast, gxe, lx);
+        lv = fma(dlast, gve, lv);
+        if (sl.act)
+            fb_dump(a, a.dlam, k + 1, sl.p, lx, lv);
+        int nmax = n;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1)
+            nmax = max(nmax, __shfl_xor(nmax, o));
+        wave.clear();
+        for (int r = nmax; r >= 0; --r) {
+            const bool mine = r <= n;
+            Real x = xk, v = vk, cx = 0, cv = 0, a0 = 0, a1 = a1_0, zx = zx0, zv = zv0;
+            if (mine && r > 0)
+                fb_advance<Real, NVP>(a, mk, zk, sl.p, k, n, 0, r, x, v, cx, cv, a0, a1, zx, zv,
+                                      nullptr);
+            const Real d = n == 0 ? a.dt : (a1 - a0) * a.dt;
+            if (mine && r < n) {
+                // the running cost at the jump ending sub-step r, charged to lam~_{r+1}
+                Real xe = x, ve = v, ce = cx, cve = cv, b0 = a0, b1 = a1, ex = zx, ev = zv;
+                fb_advance<Real, NVP>(a, mk, zk, sl.p, k, n, r, r + 1, xe, ve, ce, cve, b0, b1, ex,
+                                      ev, nullptr);
+                Real tg[2], gx, gv;
+                fb_target(zk, a1, tg);
+                track_grad(a, xe, ve, tg, gx, gv);
+                lx = fma(d, gx, lx);
+                lv = fma(d, gv, lv);
+            }
+            const Real lxm = lx, lvm = r < n ? a.gamma * lv : lv;
+            Real pv[NVP], dpv[NVP];
+#pragma unroll
+            for (int l = 0; l < NVP; ++l)
+                pv[l] = bump_d(v - fma((Real)l, a.dvc, a.vc0), a.eps, dpv[l]);
+            Real u = 0, ux = 0, uv = 0;
+#pragma unroll 1
+            for (int i = 0; i < a.nx; ++i) {
+                Real dbx;
+                const Real bx = bump_d(x - fma((Real)i, a.dxc, a.xc0), a.eps, dbx);
+                const Real* rw = mk + i * NVP;
+                Real t = 0, sv = 0;
+#pragma unroll
+                for (int l = 0; l < NVP; ++l) {
+                    t = fma(rw[l], pv[l], t);
+                    sv = fma(rw[l], dpv[l], sv);
+                }
+                u = fma(bx, t, u);
+                ux = fma(dbx, t, ux);
+                uv = fma(bx, sv, uv);
+                wave.put_x(i, bx);
+            }
+            wave.template put_v<Real, NVP>(pv);
+            const Real wk = n == 0 ? fma(a.alpha, u, lvm) : (d / a.dt) * fma(a.alpha, u, lvm);
+            wave.template add<NVP>(mine && sl.act ? wk : (Real)0, a.nx);
+            if (mine) {
+                const Real au = a.alpha * u;
+                lx = fma(d, fma(au, ux, (ux - a.eta) * lvm), lxm);
+                lv = fma(d, fma(au, uv, fma(uv, lvm, lxm)), lvm);
+            }
+        }
+        track_grad(a, xk, vk, zk, gxe, gve);
+        fb_block_partial<false>(sh, wave, k, N, a.nx, a.nv, apart);
+        xk = xp;
+        vk = vp;
+    }
+}
+
 // One thread per gradient entry (k, e): fixed-order sum over the blocks.
 __global__ void __launch_bounds__(kThreads)
 k_fb_finalize_grad(const double* __restrict__ apart, int nblk, int64_t NL, int64_t M,
@@ -804,6 +1075,10 @@ static FbArgs<Real> fb_args(const FbHost& p, const HostRun& r) {
     a.dt = (Real)p.dt;
     a.sqb1 = (Real)(p.b1 * sqrt(p.dt));
     a.sqb2 = (Real)(p.b2 * sqrt(p.dt));
+    a.b1 = (Real)p.b1;
+    a.b2 = (Real)p.b2;
+    a.gamma = (Real)p.gamma;
+    a.sbeta = (Real)(1.0 / sqrt(2.0 * p.beta));
     a.eta = (Real)p.eta;
     a.eps = (Real)p.eps;
     a.alpha = (Real)p.alpha;
@@ -901,13 +1176,20 @@ static hipError_t fb_forward_t(const FbHost& p, const HostRun& r, const void* ta
         else if (p.G == 1) FB_FWD_K(NVP, S, 1, true);                                             \
         else FB_FWD_K(NVP, S, 8, true);                                                           \
     } while (0)
+#define FB_FWD_A(NVP, S)                                                                          \
+    hipLaunchKernelGGL((k_fb_forward_adapted<Real, NVP, S>), dim3(nb), dim3(kThreads), 0, st, a,  \
+                       tb + t.mu, tb + t.zd, traj, cpart)
 #define FB_FWD(NVP)                                                                               \
     do {                                                                                          \
-        if (traj != nullptr) FB_FWD_S(NVP, true);                                                 \
+        if (p.grid == 1) {                                                                        \
+            if (traj != nullptr) FB_FWD_A(NVP, true);                                             \
+            else FB_FWD_A(NVP, false);                                                            \
+        } else if (traj != nullptr) FB_FWD_S(NVP, true);                                          \
         else FB_FWD_S(NVP, false);                                                                \
     } while (0)
     FB_DISPATCH_NVP(p.nvp, FB_FWD);
 #undef FB_FWD
+#undef FB_FWD_A
 #undef FB_FWD_S
 #undef FB_FWD_K
     return hipGetLastError();
@@ -932,14 +1214,17 @@ static hipError_t fb_adjoint_t(const FbHost& p, const HostRun& r, const void* ta
     FbArgs<Real> a = fb_args<Real>(p, r);
     a.thr = &hdr->poisson;
     const Real* tb = (const Real*)tab;
-    const int G = p.np == 1 ? fb_adjoint_groups(r.nblk) : p.G;
+    const int G = p.grid == 1 ? 1 : p.np == 1 ? fb_adjoint_groups(r.nblk) : p.G;
     const unsigned nb = (unsigned)fb_partial_blocks(p, r);
 #define FB_ADJ_G(NVP, GG, S, RG)                                                                  \
     hipLaunchKernelGGL((k_fb_adjoint<Real, NVP, GG, S, RG>), dim3(nb), dim3(kThreads), 0, st, a,  \
                        tb + t.mu, tb + t.zd, tb + t.ks, traj, apart)
 #define FB_ADJ(NVP)                                                                               \
     do {                                                                                          \
-        if (p.np > 1) {                                                                           \
+        if (p.grid == 1) {                                                                        \
+            hipLaunchKernelGGL((k_fb_adjoint_adapted<Real, NVP>), dim3(nb), dim3(kThreads), 0,    \
+                               st, a, tb + t.mu, tb + t.zd, traj, apart);                         \
+        } else if (p.np > 1) {                                                                    \
             if (G == 8) FB_ADJ_G(NVP, 8, false, true);                                            \
             else FB_ADJ_G(NVP, 1, false, true);                                                   \
         } else if (G == 2) {                                                                      \
@@ -993,6 +1278,8 @@ hipError_t fb_launch_forward_grad(const FbHost& p, const HostRun& r, const void*
 }
 
 int fb_partial_blocks(const FbHost& p, const HostRun& r) {
+    if (p.grid == 1)
+        return r.nblk;
     if (p.np > 1)
         return r.nblk / p.G;
     const int G = fb_adjoint_groups(r.nblk);

@@ -25,6 +25,7 @@ struct FbHost {
     double omega;         // nearest-neighbour coupling
     int cost_kind;        // JD_FB_COST_TRACK / JD_FB_COST_ELLIPSE
     double ax, av;        // ellipse half-axes
+    int grid;             // JD_FB_GRID_FIXED / JD_FB_GRID_ADAPTED
     double ks[64];        // gamma^n and sqrt(V_n) for n = 0..31
     uint64_t thr[32];     // Poisson(rate dt) thresholds
     PoissonTable poisson;

@@ -38,6 +38,8 @@ int fb_prepare(const jd_fb_problem* prob, const jd_run* run, FbHost& p, HostRun&
         return JD_EINVAL;
     if (q.np < 1 || q.np > JD_FB_MAX_RING || !finite(q.omega))
         return JD_EINVAL;
+    if (q.grid != JD_FB_GRID_FIXED && q.grid != JD_FB_GRID_ADAPTED)
+        return JD_EINVAL;
     if ((q.cost_kind == JD_FB_COST_ELLIPSE || q.init_kind == JD_FB_INIT_ELLIPSE) &&
         !(q.ax > 0.0 && finite(q.ax) && q.av > 0.0 && finite(q.av)))
         return JD_EINVAL;
@@ -60,7 +62,9 @@ int fb_prepare(const jd_fb_problem* prob, const jd_run* run, FbHost& p, HostRun&
         return JD_EUNSUPPORTED;
     if (run->mode != JD_STORE && run->mode != JD_SURROGATE)
         return JD_EINVAL;
-    if (run->mode == JD_SURROGATE && q.np > 1)
+    if (run->mode == JD_SURROGATE && (q.np > 1 || q.grid == JD_FB_GRID_ADAPTED))
+        return JD_EUNSUPPORTED;
+    if (q.grid == JD_FB_GRID_ADAPTED && q.np > 1)
         return JD_EUNSUPPORTED;
     if (run->dump) {
         const jd_dump* dp = run->dump;
@@ -100,6 +104,7 @@ int fb_prepare(const jd_fb_problem* prob, const jd_run* run, FbHost& p, HostRun&
     p.cost_kind = q.cost_kind;
     p.ax = q.ax;
     p.av = q.av;
+    p.grid = q.grid;
     p.nsys = run->M;
     p.G = 1;
     p.rings_per_block = 0;

@@ -231,7 +231,7 @@ class _FbDummy:
                                   p.xmax, p.vmax, p.eps, p.alpha, p.sigJ, p.init_kind,
                                   (C.c_double * 2)(*p.z0), (C.c_double * 2)(*p.s0),
                                   (C.c_double * 2)(*p.svar0), (C.c_double * 2)(*p.svar1), 0x1000,
-                                  p.np, p.omega, p.cost_kind, p.ax, p.av)
+                                  p.np, p.omega, p.cost_kind, p.ax, p.av, p.grid)
 
 
 def test_fb_workspace_and_traj_sizes(L):
@@ -309,8 +309,13 @@ def test_fb_invalid_arguments_rejected_before_launch(L):
     # rings (Section 6.4)
     for kw in (dict(np=0), dict(np=B.JD_FB_MAX_RING + 1), dict(omega=float("nan")),
                dict(cost_kind=2), dict(cost_kind=1, ax=0.0), dict(init_kind=2, av=-1.0),
-               dict(cost_kind=0, zd=None)):
+               dict(cost_kind=0, zd=None), dict(grid=2)):
         assert call(**kw) == B.JD_EINVAL, kw
+    # the jump-adapted grid: independent particles, exact gradient only
+    assert call(grid=1, np=3) == B.JD_EUNSUPPORTED
+    ad = _FbDummy(wl.feedback_problem(N=20, T=2.0, grid="adapted"))
+    assert L.jd_fb_cost_grad(C.byref(ad.st), C.byref(sur), fake, fake, fake, None, fake, ws,
+                             None) == B.JD_EUNSUPPORTED
     ring = _FbDummy(wl.ring_problem(N=20, T=2.0, np_=5))
     R = C.byref(ring.st)
     assert L.jd_fb_cost_grad(R, C.byref(sur), fake, fake, fake, None, fake, ws, None) == B.JD_EUNSUPPORTED
