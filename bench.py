@@ -74,6 +74,15 @@ FB_ADJ_SLOTS = 655
 # neighbour exchange itself is LDS traffic and barriers, not VALU work.
 RING_FWD_SLOTS = 508
 RING_ADJ_SLOTS = 661
+# Jump-adapted grid (ja2 / ja3): the fixed-grid work per particle-step plus,
+# per jump (sigma dt of them per particle-step), one more sub-step: forward
+# control 370, Euler 6, the sub-step's Philox block and Box-Muller 104, its
+# offset (a quarter Philox block and one root, 28), running cost 18 = 526;
+# adjoint: the sub-step's adjoint without the count's Philox (574) and its
+# offset (28) = 602.  Recomputing the sub-step's start state and the lanes
+# that wait on a jumping lane in their wave are not algorithmic work.
+ADAPT_FWD_EXTRA = 526
+ADAPT_ADJ_EXTRA = 602
 HBM_PEAK = 8.0e12  # B/s
 METRIC = "forward+adjoint path-steps/s (FP32 vs FP64 GPU) at 1e-6 rel grad err; p50/p99"
 
@@ -94,6 +103,8 @@ def parse():
     ap.add_argument("--no-ring", action="store_true",
                     help="skip the coupled-rings section (Section 6.4)")
     ap.add_argument("--ring-sample-rings", type=int, default=16)
+    ap.add_argument("--no-adapted", action="store_true",
+                    help="skip the jump-adapted grid section (Section 3)")
     ap.add_argument("--cpu-sample-paths", type=int, default=1 << 19)
     ap.add_argument("--only", choices=["all", "fp32_store", "kernels"], default="all",
                     help="kernels: time jd_forward / jd_adjoint only (for profiler runs)")
@@ -256,6 +267,83 @@ def feedback_section(args, time_calls, dev):
             del es
         out["oracle_error_on_sample"] = errs
         log(f"feedback oracle errors: {errs}")
+    return out
+
+
+def adapted_section(args, time_calls, dev):
+    """The jump-adapted grid (Section 3, Algorithms 5.1-5.2) at f4's size
+    (ja2: 2^20 particles, 500 steps of 0.01) in FP32 and FP64, and at the
+    paper's step (ja3: 2^20 particles, 50 steps of 0.1) in FP32: per-call times
+    of jd_fb_cost_grad, the forward and adjoint kernels alone, the slot
+    roofline, and the oracle on a bounded sample."""
+    import torch
+    from paper_2505_04328_amd import binding as B
+    from paper_2505_04328_amd import workloads as wl
+    out = {}
+    for name, precs in (("ja2", ("fp32", "fp64")), ("ja3", ("fp32",))):
+        w = wl.adapted_config(name)
+        p = w.problem
+        mu = torch.tensor(wl.random_feedback_control(p, 4, 0.5), device=dev)
+        ps = w.M * p.N
+        sdt = p.rate * p.dt
+        o = {"M": w.M, "N": p.N, "dt": p.dt, "jumps_per_particle_step": sdt}
+        res = {}
+        for prec in precs:
+            e = B.FbEngine(p, M=w.M, seed=w.seed, precision=prec, device=dev)
+            for it in range(args.warmup):
+                e.cost_grad(mu, it=it)
+            cg = time_calls(lambda: e.cost_grad(mu, it=5), args.steps)
+            fw = time_calls(lambda: e.forward(mu, it=5), max(5, args.steps // 2))
+            ad = time_calls(lambda: e.adjoint(mu, it=5), max(5, args.steps // 2))
+            J, g = e.cost_grad(mu, it=0)
+            res[prec] = (float(J), g.cpu().numpy())
+            o[prec] = {"p50_ms": percentile(cg, 50), "p99_ms": percentile(cg, 99),
+                       "particle_steps_per_s_p50": ps / (percentile(cg, 50) * 1e-3),
+                       "forward_ms": float(np.mean(fw)), "adjoint_ms": float(np.mean(ad))}
+            del e
+            torch.cuda.empty_cache()
+        fs = FB_FWD_SLOTS + sdt * ADAPT_FWD_EXTRA
+        as_ = FB_ADJ_SLOTS + sdt * ADAPT_ADJ_EXTRA
+        t_f, t_a = o["fp32"]["forward_ms"] * 1e-3, o["fp32"]["adjoint_ms"] * 1e-3
+        o["roofline"] = {"bound": "alu", "kernel": "k_fb_adjoint_adapted<float,12>",
+                         "achieved": as_ * ps / t_a / 1e12, "peak": VALU_PEAK_SLOTS / 1e12,
+                         "unit": "TOP/s (full-rate VALU lane-op slots)",
+                         "frac": as_ * ps / t_a / VALU_PEAK_SLOTS, "traffic": None,
+                         "slots_per_particle_step": as_, "kernel_ms": t_a * 1e3}
+        o["forward_roofline"] = {"kernel": "k_fb_forward_adapted<float,12,true>", "bound": "alu",
+                                 "frac": fs * ps / t_f / VALU_PEAK_SLOTS,
+                                 "slots_per_particle_step": fs}
+        if "fp64" in res:
+            J64, g64 = res["fp64"]
+            J32, g32 = res["fp32"]
+            o["fp32_vs_fp64_full_size"] = {
+                "J_rel": abs(J32 - J64) / abs(J64),
+                "g_rel": float(np.linalg.norm(g32 - g64) / np.linalg.norm(g64))}
+        if name == "ja2" and not args.no_cpu_baseline:
+            from oracle import ref
+            Ms = args.fb_sample_paths
+            nth = ref.default_threads()
+            log(f"adapted-grid oracle: {Ms} particles x {p.N} steps on {nth} threads")
+            t0 = time.perf_counter()
+            Jo, go = ref.fb_cost_grad(p, Ms, w.seed, 0, mu.cpu().numpy(), nthreads=nth)
+            tc = time.perf_counter() - t0
+            o["cpu_baseline"] = {"value": Ms * p.N / tc, "unit": "particle-steps/s",
+                                 "cores": min(nth, -(-Ms // 4096)), "kind": "oracle",
+                                 "sample": f"ja2 with M={Ms} of {w.M} particles, all {p.N} steps, "
+                                           f"forward+adjoint+reductions, FP64, {tc:.1f} s wall"}
+            errs = {}
+            for prec in ("fp32", "fp64"):
+                es = B.FbEngine(p, M=Ms, seed=w.seed, precision=prec, device=dev)
+                Js, gs = es.cost_grad(mu, it=0)
+                errs[prec] = {"J_rel": abs(float(Js) - Jo) / abs(Jo),
+                              "g_rel": float(np.linalg.norm(gs.cpu().numpy() - go) / np.linalg.norm(go))}
+                del es
+            o["oracle_error_on_sample"] = errs
+            log(f"adapted-grid oracle errors: {errs}")
+        out[name] = o
+    out["workload"] = ("jump-adapted grid (Section 3): ja2 = f4's model and size (2^20 particles, "
+                       "500 steps of 0.01) and ja3 = 2^20 particles at the paper's step (50 steps of "
+                       "0.1), 10 x 10 bump shape functions, Keilson-Storer jumps beta 10 gamma 0.9")
     return out
 
 
@@ -502,6 +590,10 @@ def main():
     if not args.no_feedback and args.only == "all":
         log("feedback model (f4)")
         feedback = feedback_section(args, time_calls, dev)
+    adapted = None
+    if not args.no_adapted and args.only == "all":
+        log("jump-adapted grid (ja2, ja3)")
+        adapted = adapted_section(args, time_calls, dev)
     rings = None
     if not args.no_ring and args.only == "all":
         log("coupled rings (ring2)")
@@ -533,6 +625,7 @@ def main():
         "oracle_error_on_sample": sample_err,
         "feedback": feedback,
         "rings": rings,
+        "adapted": adapted,
     }
     print(json.dumps(line), flush=True)
 

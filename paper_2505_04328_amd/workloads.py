@@ -380,6 +380,22 @@ def feedback_config(name: str) -> FeedbackWorkload:
     raise KeyError(name)
 
 
+def adapted_config(name: str) -> FeedbackWorkload:
+    """The jump-adapted grid (Section 3).  ja1: the paper's setting (Section
+    6.1, 2000 particles, 50 steps of 0.1).  ja2: the measured size of f4, 2^20
+    particles and 500 steps of 0.01 (a jump in about one interval of 56).  ja3:
+    2^20 particles at the paper's step, 50 steps of 0.1 (a jump in about one
+    interval of six, several in some)."""
+    if name == "ja1":
+        return FeedbackWorkload(feedback_problem(name="ja1", grid="adapted"), M=2000, seed=1)
+    if name == "ja2":
+        return FeedbackWorkload(feedback_problem(N=500, name="ja2", grid="adapted"), M=1 << 20,
+                                seed=1)
+    if name == "ja3":
+        return FeedbackWorkload(feedback_problem(name="ja3", grid="adapted"), M=1 << 20, seed=1)
+    raise KeyError(name)
+
+
 def ring_config(name: str) -> FeedbackWorkload:
     """ring1: Section 6.4 at the paper's size, one ring of 2000 particles, 50
     steps.  ring2: the measured size, 512 independent rings of 2000 particles

@@ -8,10 +8,11 @@ of g; for c2 also the whole gradient.  For the paper's model problem at its
 measured size (f4: 2^20 particles, 500 steps) the same record is written at the
 control mu = random_feedback_control(p, 4, 0.5), and so for the coupled rings
 of Section 6.4 at their measured size (ring2: 512 rings of 2000 particles, 500
-steps).  Run from the repository root:
+steps) and the jump-adapted grid at f4's size (ja2).  Run from the repository
+root:
 
     python tests/golden/make_full_size.py            # c2, c3, c4 (minutes on 8 cores)
-    python tests/golden/make_full_size.py c2 f4 ring2
+    python tests/golden/make_full_size.py c2 f4 ring2 ja2
 """
 from __future__ import annotations
 
@@ -46,7 +47,12 @@ def fb_directions(p, count=16, seed=2):
 
 
 def feedback(name):
-    w = wl.ring_config(name) if name.startswith("ring") else wl.feedback_config(name)
+    if name.startswith("ring"):
+        w = wl.ring_config(name)
+    elif name.startswith("ja"):
+        w = wl.adapted_config(name)
+    else:
+        w = wl.feedback_config(name)
     p = w.problem
     t0 = time.time()
     mu = wl.random_feedback_control(p, 4, 0.5)
@@ -70,7 +76,7 @@ def feedback(name):
 
 def main(names):
     for name in names:
-        if name.startswith("f") or name.startswith("ring"):
+        if name.startswith(("f", "ring", "ja")):
             feedback(name)
             continue
         w = wl.config(name)

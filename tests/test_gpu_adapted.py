@@ -141,3 +141,50 @@ def test_adapted_optimize_matches_oracle(dev, precision):
         assert a["backtracks"] == b["backtracks"]
         assert rel_err(a["J"], b["J"]) <= tol["J"]
     assert norm_err(mu.cpu().numpy(), mu_ref) <= 10 * tol["g"]
+
+
+def test_adapted_full_size_ja2(dev):
+    """The measured size on the jump-adapted grid (2^20 particles x 500 steps,
+    FP32 paths) in the launch configuration the benchmark times: J, ||g||, 16
+    projections and 64 sampled entries of g against the oracle values of
+    tests/golden/full_ja2_it0.json (written by tests/golden/make_full_size.py);
+    per-particle states, adjoints and costs of the first and last 4096
+    particles against the oracle here."""
+    import json
+    import os
+    import torch
+    with open(os.path.join(os.path.dirname(__file__), "golden", "full_ja2_it0.json")) as f:
+        gd = json.loads("".join(ln for ln in f if not ln.startswith("#")))
+    w = wl.adapted_config("ja2")
+    p = w.problem
+    say("adapted full size ja2", w.M, p.N)
+    mu = wl.random_feedback_control(p, 4, 0.5)
+    eng = B.FbEngine(p, M=w.M, seed=w.seed, precision="fp32", device=dev)
+    J, g = eng.cost_grad(mu, it=0)
+    J, g = float(J), g.cpu().numpy()
+    tol = TOL["fp32"]
+    say(f"   J {J:.12g} vs {gd['J']:.12g}")
+    assert rel_err(J, gd["J"]) <= tol["J"]
+    gn = np.sqrt(p.dt * np.sum(g * g))
+    assert rel_err(gn, gd["gnorm_L2"]) <= tol["g"]
+    rng = np.random.default_rng(2)
+    for pr in gd["projections"]:
+        d = rng.normal(size=(p.N, p.L))
+        d = d / np.sqrt(p.dt * np.sum(d * d))
+        assert abs(p.dt * np.sum(g * d) - pr) <= tol["g"] * gd["gnorm_L2"]
+    flat = g.reshape(-1)
+    for i, v in zip(gd["sample_index"], gd["sample_g"]):
+        assert abs(flat[i] - v) <= tol["g"] * gd["gnorm_L2"]
+    for m0 in (0, w.M - 4096):
+        dp, dd = eng.path_dump(m0, 4096)
+        eng.forward(mu, it=0, dump=dp)
+        eng.adjoint(mu, it=0, dump=dp)
+        torch.cuda.synchronize()
+        z, lam, _, _, C = ref.fb_paths(p, w.seed, 0, m0, 4096, mu)
+        zg = np.transpose(dd["X"].double().cpu().numpy(), (2, 0, 1))
+        lg = np.transpose(dd["lam"].double().cpu().numpy(), (2, 0, 1))
+        e_z, e_l = per_path_error(zg, z), per_path_error(lg[:, 1:], lam[:, 1:])
+        say(f"   paths {m0}+4096: z {e_z:.2e} lam {e_l:.2e}")
+        assert e_z <= tol["path"] and e_l <= tol["path"]
+        e_c = float(np.max(np.abs(dd["cost"].cpu().numpy() - C) / (np.abs(C) + np.sqrt(np.mean(C * C)))))
+        assert e_c <= tol["path"]
