@@ -233,12 +233,12 @@ def feedback_section(args, time_calls, dev):
     t_f, t_a = out["fp32"]["forward_ms"] * 1e-3, out["fp32"]["adjoint_ms"] * 1e-3
     t_cg = out["fp32"]["p50_ms"] * 1e-3
     out["roofline"] = {
-        "bound": "alu", "kernel": "k_fb_adjoint<float,12,2>",
+        "bound": "alu", "kernel": "k_fb_adjoint<float,10,2,false,false>",
         "achieved": FB_ADJ_SLOTS * ps / t_a / 1e12, "peak": VALU_PEAK_SLOTS / 1e12,
         "unit": "TOP/s (full-rate VALU lane-op slots)",
         "frac": FB_ADJ_SLOTS * ps / t_a / VALU_PEAK_SLOTS, "traffic": None,
         "slots_per_path_step": FB_ADJ_SLOTS, "kernel_ms": t_a * 1e3}
-    out["forward_roofline"] = {"kernel": "k_fb_forward<float,12,true>", "bound": "alu",
+    out["forward_roofline"] = {"kernel": "k_fb_forward<float,10,true,1,false>", "bound": "alu",
                                "frac": FB_FWD_SLOTS * ps / t_f / VALU_PEAK_SLOTS,
                                "slots_per_path_step": FB_FWD_SLOTS}
     out["step_frac"] = (FB_FWD_SLOTS + FB_ADJ_SLOTS) * ps / t_cg / VALU_PEAK_SLOTS
@@ -305,12 +305,12 @@ def adapted_section(args, time_calls, dev):
         fs = FB_FWD_SLOTS + sdt * ADAPT_FWD_EXTRA
         as_ = FB_ADJ_SLOTS + sdt * ADAPT_ADJ_EXTRA
         t_f, t_a = o["fp32"]["forward_ms"] * 1e-3, o["fp32"]["adjoint_ms"] * 1e-3
-        o["roofline"] = {"bound": "alu", "kernel": "k_fb_adjoint_adapted<float,12>",
+        o["roofline"] = {"bound": "alu", "kernel": "k_fb_adjoint_adapted<float,10>",
                          "achieved": as_ * ps / t_a / 1e12, "peak": VALU_PEAK_SLOTS / 1e12,
                          "unit": "TOP/s (full-rate VALU lane-op slots)",
                          "frac": as_ * ps / t_a / VALU_PEAK_SLOTS, "traffic": None,
                          "slots_per_particle_step": as_, "kernel_ms": t_a * 1e3}
-        o["forward_roofline"] = {"kernel": "k_fb_forward_adapted<float,12,true>", "bound": "alu",
+        o["forward_roofline"] = {"kernel": "k_fb_forward_adapted<float,10,true>", "bound": "alu",
                                  "frac": fs * ps / t_f / VALU_PEAK_SLOTS,
                                  "slots_per_particle_step": fs}
         if "fp64" in res:
@@ -383,12 +383,12 @@ def ring_section(args, time_calls, dev):
     t_f, t_a = out["fp32"]["forward_ms"] * 1e-3, out["fp32"]["adjoint_ms"] * 1e-3
     t_cg = out["fp32"]["p50_ms"] * 1e-3
     out["roofline"] = {
-        "bound": "alu", "kernel": "k_fb_adjoint<float,12,8,false,true>",
+        "bound": "alu", "kernel": "k_fb_adjoint<float,10,8,false,true>",
         "achieved": RING_ADJ_SLOTS * ps / t_a / 1e12, "peak": VALU_PEAK_SLOTS / 1e12,
         "unit": "TOP/s (full-rate VALU lane-op slots)",
         "frac": RING_ADJ_SLOTS * ps / t_a / VALU_PEAK_SLOTS, "traffic": None,
         "slots_per_particle_step": RING_ADJ_SLOTS, "kernel_ms": t_a * 1e3}
-    out["forward_roofline"] = {"kernel": "k_fb_forward<float,12,true,8,true>", "bound": "alu",
+    out["forward_roofline"] = {"kernel": "k_fb_forward<float,10,true,8,true>", "bound": "alu",
                                "frac": RING_FWD_SLOTS * ps / t_f / VALU_PEAK_SLOTS,
                                "slots_per_particle_step": RING_FWD_SLOTS}
     out["step_frac"] = (RING_FWD_SLOTS + RING_ADJ_SLOTS) * ps / t_cg / VALU_PEAK_SLOTS

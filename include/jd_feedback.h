@@ -155,7 +155,8 @@ int jd_fb_forward(const jd_fb_problem* prob, const jd_run* run, const double* mu
  * run, mu) and the Monte Carlo gradient g (device FP64 N x L, no dt factor);
  * JD_STORE only (JD_SURROGATE: JD_EUNSUPPORTED, use jd_fb_cost_grad).
  * The per-step sum over particles of phi(z) (alpha u + gamma^n lam^v) is a
- * dense 16 x 16 contraction over paths and runs on the FP64 matrix cores. */
+ * dense 16 x 16 contraction over paths and runs on the matrix cores (FP64, or
+ * FP32 products with FP64 sums beyond one wave's step for FP32 paths). */
 int jd_fb_adjoint(const jd_fb_problem* prob, const jd_run* run, const double* mu,
                   const void* traj, double* grad, void* ws, size_t ws_bytes, hipStream_t stream);
 

@@ -408,31 +408,59 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
 }
 
+
 typedef double fb_d4 __attribute__((ext_vector_type(4)));
+typedef float fb_f4 __attribute__((ext_vector_type(4)));
 
 constexpr int kFbWaves = kThreads / 64;  // waves per block
 constexpr int kFbStride = kFbMaxGrid + 1;  // padded row stride of the transposes
+
+// The matrix-core product of the path precision.  FP64 paths use
+// v_mfma_f64_16x16x4f64; FP32 paths v_mfma_f32_16x16x4f32 (twice the rate):
+// its FP32 products and sums cover one chain of at most 16 G particles per step
+// (G particles per lane), whose rounding averages out over the 2^20-particle
+// sum far below the gradient's 1e-6 bound; the chains, the waves and the blocks
+// are summed in FP64.  Both take A[i][kk] and B[kk][j] in lane i + 16 kk; row()
+// gives the row of D held in register r of lane ln (the column is ln mod 16).
+// The layouts were measured on the device with one-hot operands.
+template <typename Real>
+struct FbMma;
+template <>
+struct FbMma<double> {
+    typedef fb_d4 acc_t;
+    static __device__ __forceinline__ acc_t mfma(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int ln, int r) { return 4 * r + (ln >> 4); }
+};
+template <>
+struct FbMma<float> {
+    typedef fb_f4 acc_t;
+    static __device__ __forceinline__ acc_t mfma(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int ln, int r) { return 4 * (ln >> 4) + r; }
+};
 
 // One wave's share of the per-step gradient sum over particles,
 // G_k[i][j] += sum_p b(x_p - x^i) w_p b(v_p - v^j): the particles' bump values
 // go through an LDS transpose (row p = particle, lane i + 16 kk reads A[i][kk] =
 // phx[4q + kk][i] w[4q + kk] and B[kk][i] = phv[4q + kk][i]) into sixteen
-// v_mfma_f64_16x16x4f64 per 64 particles, accumulated in four independent
-// chains.  The operand and result layouts were measured on the device:
-// A[i][kk] and B[kk][j] in lane i + 16 kk, D[i][j] in lane j + 16 (i % 4),
-// register i / 4.
+// 16 x 16 x 4 matrix-core products per 64 particles, accumulated in four
+// independent chains.
 template <typename Real>
 struct FbWave {
+    typedef typename FbMma<Real>::acc_t acc_t;
     Real (*phx)[kFbStride];
     Real (*phv)[kFbStride];
     Real* wts;
     int ln, ii;
-    fb_d4 acc[4];
+    acc_t acc[4];
 
     __device__ __forceinline__ void clear() {
 #pragma unroll
         for (int c = 0; c < 4; ++c)
-            acc[c] = fb_d4{0.0, 0.0, 0.0, 0.0};
+            acc[c] = acc_t{0, 0, 0, 0};
     }
     template <typename R>
     __device__ __forceinline__ void put_x(int i, R b) const { phx[ln][i] = b; }
@@ -451,9 +479,9 @@ struct FbWave {
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const int p = 4 * q + (ln >> 4);
-            const double av = ii < nx ? (double)phx[p][ii] * (double)wts[p] : 0.0;
-            const double bv = ii < NVP ? (double)phv[p][ii] : 0.0;
-            acc[q & 3] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[q & 3], 0, 0, 0);
+            const Real av = ii < nx ? phx[p][ii] * wts[p] : (Real)0;
+            const Real bv = ii < NVP ? phv[p][ii] : (Real)0;
+            acc[q & 3] = FbMma<Real>::mfma(av, bv, acc[q & 3]);
         }
         wave_lds_sync();
     }
@@ -482,26 +510,76 @@ __device__ __forceinline__ FbWave<Real> fb_wave(FbShared<Real>& sh) {
     return w;
 }
 
-// Sums the four waves' tiles in a fixed order into the block's partial of
-// step k (ADD: added to what the partial holds).
-template <bool ADD, typename Real>
-__device__ __forceinline__ void fb_block_partial(FbShared<Real>& sh, const FbWave<Real>& w, int k,
-                                                 int N, int nx, int nv, double* __restrict__ apart) {
-    double* cb = (double*)&w.phx[0][0];
+// The wave's FP64 16 x 16 tiles of its last H steps (t[0] the latest), in the
+// D layout of the path precision's matrix-core product.  The four waves of a
+// block combine their tiles once per H steps.  H = 1 for the fixed grid (more
+// held tiles cost occupancy there: 15.4 / 16.8 ms for H = 1 / 2 and 4 on f4);
+// H = 4 for the jump-adapted adjoint (54.9 -> 51.1 ms on ja2).
+template <int H>
+struct FbHist {
+    fb_d4 t[H];
+    int cnt;
+    __device__ __forceinline__ void push(const fb_d4& x) {
+#pragma unroll
+        for (int s = H - 1; s > 0; --s)
+            t[s] = t[s - 1];
+        t[0] = x;
+        ++cnt;
+    }
+};
+
+// The sum of the wave's four chains, in FP64.
+template <typename Real>
+__device__ __forceinline__ fb_d4 fb_tile(const FbWave<Real>& w) {
+    fb_d4 t;
 #pragma unroll
     for (int r = 0; r < 4; ++r)
-        cb[(4 * r + (w.ln >> 4)) * kFbMaxGrid + w.ii] = (w.acc[0][r] + w.acc[1][r]) + (w.acc[2][r] + w.acc[3][r]);
+        t[r] = ((double)w.acc[0][r] + (double)w.acc[1][r]) + ((double)w.acc[2][r] + (double)w.acc[3][r]);
+    return t;
+}
+
+// LDS home of tile s of wave wv during a flush (the wave's transpose buffers,
+// free between steps).
+template <typename Real>
+__device__ __forceinline__ double* fb_tile_lds(FbShared<Real>& sh, int wv, int s) {
+    static_assert(sizeof(Real) * 64 * kFbStride >= 2 * sizeof(double) * kFbMaxGrid * kFbMaxGrid,
+                  "a wave's transpose buffer must hold two 16 x 16 FP64 tiles");
+    return (double*)(s < 2 ? &sh.phx[wv][0][0] : &sh.phv[wv][0][0]) + (s & 1) * kFbMaxGrid * kFbMaxGrid;
+}
+
+// Sums the four waves' held tiles in a fixed order into the block's partials:
+// tile s is step k0 + s dir (ADD: added to what the partial holds).
+template <bool ADD, int H, typename Real>
+__device__ __forceinline__ void fb_hist_flush(FbShared<Real>& sh, const FbWave<Real>& w,
+                                              FbHist<H>& h, int k0, int dir, int N, int nx, int nv,
+                                              double* __restrict__ apart) {
+    const int wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int s = 0; s < H; ++s) {
+        if (s < h.cnt) {
+            double* cb = fb_tile_lds(sh, wv, s);
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                cb[FbMma<Real>::row(w.ln, r) * kFbMaxGrid + w.ii] = h.t[s][r];
+        }
+    }
     __syncthreads();
     const int t = threadIdx.x, i = t >> 4, j = t & 15;
     if (i < nx && j < nv) {
-        double sum = ((const double*)&sh.phx[0][0][0])[t];
 #pragma unroll
-        for (int q = 1; q < kFbWaves; ++q)
-            sum += ((const double*)&sh.phx[q][0][0])[t];
-        double* dst = apart + ((size_t)blockIdx.x * N + k) * (nx * nv) + i * nv + j;
-        *dst = ADD ? *dst + sum : sum;
+        for (int s = 0; s < H; ++s) {
+            if (s < h.cnt) {
+                double sum = fb_tile_lds(sh, 0, s)[t];
+#pragma unroll
+                for (int q = 1; q < kFbWaves; ++q)
+                    sum += fb_tile_lds(sh, q, s)[t];
+                double* dst = apart + ((size_t)blockIdx.x * N + (k0 + s * dir)) * (nx * nv) + i * nv + j;
+                *dst = ADD ? *dst + sum : sum;
+            }
+        }
     }
     __syncthreads();
+    h.cnt = 0;
 }
 
 // Storage-free forward of the surrogate gradient (Section 6.5): G particles
@@ -515,6 +593,8 @@ k_fb_forward_grad(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __res
     __shared__ FbShared<Real> sh;
     __shared__ double red[kThreads];
     FbWave<Real> wave = fb_wave(sh);
+    FbHist<1> hist;
+    hist.cnt = 0;
     const int N = a.N;
     Real x[G], v[G], cx[G], cv[G];
     double acc[G];
@@ -542,7 +622,8 @@ k_fb_forward_grad(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __res
             acc[j] += (double)(a.dt * track(a, x[j], v[j], zd + 2 * (k + 1)));
             fb_dump(a, a.dX, k + 1, m[j], x[j], v[j]);
         }
-        fb_block_partial<false>(sh, wave, k, N, a.nx, a.nv, apart);
+        hist.push(fb_tile(wave));
+        fb_hist_flush<false>(sh, wave, hist, k, -1, N, a.nx, a.nv, apart);
     }
     double C = 0.0;
 #pragma unroll
@@ -579,8 +660,8 @@ struct FbAdj {
 //                 k_fb_forward_grad (which hold alpha u phi(z)).
 //   RING = true:  rings (slots as in k_fb_forward); each particle's
 //                 w = gamma^n lam^v_{k+1} goes to LDS (double buffered by step
-//                 parity) and, after the block barriers of the gradient
-//                 partial, its neighbours add dt omega w to their lam^x_k.
+//                 parity) and, after the block barriers of the step's
+//                 gradient flush, its neighbours add dt omega w to their lam^x_k.
 template <typename Real, int NVP, int G, bool SURR, bool RING>
 __global__ void __launch_bounds__(kThreads)
 k_fb_adjoint(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __restrict__ zd,
@@ -589,6 +670,8 @@ k_fb_adjoint(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __restrict
     __shared__ FbShared<Real> sh;
     __shared__ Real cw[RING ? 2 : 1][RING ? G * kThreads : 1];
     FbWave<Real> wave = fb_wave(sh);
+    FbHist<1> hist;
+    hist.cnt = 0;
     const int N = a.N;
     FbAdj<Real> s[G];
     const Real* row[G];
@@ -683,7 +766,8 @@ k_fb_adjoint(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __restrict
                     fb_dump(a, a.dlam, k, m[j], st.lx, st.lv);
             }
         }
-        fb_block_partial<SURR>(sh, wave, k, N, a.nx, a.nv, apart);
+        hist.push(fb_tile(wave));
+        fb_hist_flush<SURR>(sh, wave, hist, k, 1, N, a.nx, a.nv, apart);
         if (RING && k >= 1) {
             const Real* wb = cw[k & 1];
             const Real dto = a.dt * a.omega;
@@ -865,6 +949,8 @@ k_fb_adjoint_adapted(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __
                      const void* traj, double* __restrict__ apart) {
     __shared__ FbShared<Real> sh;
     FbWave<Real> wave = fb_wave(sh);
+    FbHist<4> hist;
+    hist.cnt = 0;
     const int N = a.N;
     const FbSlot sl = fb_slot<1>(a, 0);
     const Real* row = fb_row<Real>(const_cast<void*>(traj), N, blockIdx.x);
@@ -952,7 +1038,9 @@ k_fb_adjoint_adapted(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __
             }
         }
         track_grad(a, xk, vk, zk, gxe, gve);
-        fb_block_partial<false>(sh, wave, k, N, a.nx, a.nv, apart);
+        hist.push(fb_tile(wave));
+        if (hist.cnt == 4 || k == 0)
+            fb_hist_flush<false>(sh, wave, hist, k, 1, N, a.nx, a.nv, apart);
         xk = xp;
         vk = vp;
     }
@@ -1148,6 +1236,7 @@ hipError_t fb_launch_table(const FbHost& p, const HostRun& r, const double* mu, 
         switch (nvp) {                     \
         case 4: FN(4); break;              \
         case 8: FN(8); break;              \
+        case 10: FN(10); break;            \
         case 12: FN(12); break;            \
         default: FN(16); break;            \
         }                                  \

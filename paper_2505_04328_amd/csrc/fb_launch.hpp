@@ -11,7 +11,7 @@ namespace jd {
 constexpr int kFbMaxGrid = 16;  // nx, nv <= 16: one 16 x 16 matrix-core tile per step
 
 struct FbHost {
-    int N, nx, nv, nvp, L;  // nvp = nv rounded up to 4 (zero-padded control rows)
+    int N, nx, nv, nvp, L;  // nvp: the compiled row width >= nv (zero-padded control rows)
     double T, dt, eta, b1, b2, gamma, beta, rate;
     double xmax, vmax, eps, alpha, sigJ;
     int init_kind;

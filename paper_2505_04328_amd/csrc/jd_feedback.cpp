@@ -76,7 +76,9 @@ int fb_prepare(const jd_fb_problem* prob, const jd_run* run, FbHost& p, HostRun&
     p.N = q.N;
     p.nx = q.nx;
     p.nv = q.nv;
-    p.nvp = (q.nv + 3) / 4 * 4;
+    // control rows padded to a compiled width: 4, 8, 10 (the paper's 10 x 10
+    // grid without padding), 12 or 16
+    p.nvp = q.nv == 9 || q.nv == 10 ? 10 : (q.nv + 3) / 4 * 4;
     p.L = q.nx * q.nv;
     p.T = q.T;
     p.dt = dt;
