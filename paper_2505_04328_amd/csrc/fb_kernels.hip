@@ -1046,20 +1046,37 @@ k_fb_adjoint_adapted(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __
     }
 }
 
-// One thread per gradient entry (k, e): fixed-order sum over the blocks.
+// Gradient entries q = (k, e): the sum over the per-block partials in a fixed
+// order.  A workgroup takes 8 consecutive entries; its thread (e, c) sums the
+// partials b = c, c + 32, ... of entry e in order, and a fixed LDS tree adds
+// the 32 chunk sums (one serial chain of 2048 loads per entry was latency-bound).
+constexpr int kFbFinEntries = 8;
+constexpr int kFbFinChunks = kThreads / kFbFinEntries;
+
 __global__ void __launch_bounds__(kThreads)
 k_fb_finalize_grad(const double* __restrict__ apart, int nblk, int64_t NL, int64_t M,
                    double* __restrict__ g, WsHeader* hdr) {
-    const int64_t q = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (q >= NL)
-        return;
+    __shared__ double sh[kThreads];
+    const int e = threadIdx.x % kFbFinEntries, c = threadIdx.x / kFbFinEntries;
+    const int64_t q = (int64_t)blockIdx.x * kFbFinEntries + e;
     double s = 0.0;
-    for (int b = 0; b < nblk; ++b)
-        s += apart[(size_t)b * NL + q];
-    const double gq = s / (double)M;
-    g[q] = gq;
-    if (!isfinite(gq))
-        hdr->nonfinite = 1;
+    if (q < NL)
+        for (int b = c; b < nblk; b += kFbFinChunks)
+            s += apart[(size_t)b * NL + q];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+#pragma unroll
+    for (int w = kFbFinChunks / 2; w >= 1; w >>= 1) {
+        if (c < w)
+            sh[threadIdx.x] += sh[threadIdx.x + kFbFinEntries * w];
+        __syncthreads();
+    }
+    if (c == 0 && q < NL) {
+        const double gq = sh[e] / (double)M;
+        g[q] = gq;
+        if (!isfinite(gq))
+            hdr->nonfinite = 1;
+    }
 }
 
 // One block: J = (1/M) sum of the block costs and, with g, dt sum g^2.
@@ -1378,8 +1395,9 @@ int fb_partial_blocks(const FbHost& p, const HostRun& r) {
 hipError_t fb_launch_finalize_grad(const FbHost& p, const HostRun& r, const double* apart,
                                    double* g, WsHeader* hdr, hipStream_t st) {
     const int64_t NL = (int64_t)p.N * p.L;
-    hipLaunchKernelGGL(k_fb_finalize_grad, dim3(fb_blocks(NL)), dim3(kThreads), 0, st, apart,
-                       fb_partial_blocks(p, r), NL, r.M, g, hdr);
+    hipLaunchKernelGGL(k_fb_finalize_grad,
+                       dim3((unsigned)((NL + kFbFinEntries - 1) / kFbFinEntries)), dim3(kThreads), 0,
+                       st, apart, fb_partial_blocks(p, r), NL, r.M, g, hdr);
     return hipGetLastError();
 }
 
