@@ -841,15 +841,40 @@ __device__ __forceinline__ void fb_target(const Real* __restrict__ zk, Real f, R
     }
 }
 
+// The per-particle stack of post-jump states on the jump-adapted grid: entry
+// e holds the state after the particle's e-th jump (the start of the sub-step
+// that follows it), kFbJumpCap entries per slot in the trajectory buffer after
+// the uniform points, then one int32 count per slot.  A particle with more
+// jumps than entries has the rest recomputed by the adjoint.
+constexpr int kFbJumpCap = kFbJumpStates;
+
+template <typename Real>
+struct FbJumps {
+    Real* st;        // slot's entry 0, x (entry e component c at st[(2 e + c) 256])
+    int32_t* count;  // slot's jump count
+};
+
+template <typename Real>
+__device__ __forceinline__ FbJumps<Real> fb_jumps(void* traj, int N, int64_t nblk) {
+    FbJumps<Real> j;
+    Real* base = (Real*)traj + (size_t)nblk * (N + 1) * 2 * kThreads;
+    j.st = base + (size_t)blockIdx.x * kFbJumpCap * 2 * kThreads + threadIdx.x;
+    j.count = (int32_t*)(base + (size_t)nblk * kFbJumpCap * 2 * kThreads) +
+              (size_t)blockIdx.x * kThreads + threadIdx.x;
+    return j;
+}
+
 // Sub-steps r0 .. r1 - 1 (at most up to n) of interval k of one particle,
 // from the state at the start of sub-step r0 with its offsets (a0, a1) and
-// normals (zx, zv); the running cost is added to acc when acc is given.  On
+// normals (zx, zv); the running cost is added to acc when acc is given, and
+// each post-jump state pushed as jump entry *nj when jumps is given.  On
 // return the same variables describe the start of sub-step r1 (post-jump).
 template <typename Real, int NVP>
 __device__ __forceinline__ void fb_advance(const FbArgs<Real>& a, const Real* __restrict__ mk,
                                            const Real* __restrict__ zk, uint32_t m, int k, int n,
                                            int r0, int r1, Real& x, Real& v, Real& cx, Real& cv,
-                                           Real& a0, Real& a1, Real& zx, Real& zv, double* acc) {
+                                           Real& a0, Real& a1, Real& zx, Real& zv, double* acc,
+                                           const FbJumps<Real>* jumps = nullptr, int* nj = nullptr) {
     for (int r = r0; r < r1 && r <= n; ++r) {
         const bool whole = n == 0;
         const Real d = whole ? a.dt : (a1 - a0) * a.dt;
@@ -868,6 +893,13 @@ __device__ __forceinline__ void fb_advance(const FbArgs<Real>& a, const Real* __
             const Real ub = unit_uniform<Real>(w[1]);
             zx = bm_cos(R, ub);
             zv = bm_sin(R, ub);
+            if (jumps != nullptr) {
+                if (*nj < kFbJumpCap) {
+                    jumps->st[(size_t)(2 * *nj) * kThreads] = x;
+                    jumps->st[(size_t)(2 * *nj + 1) * kThreads] = v;
+                }
+                ++*nj;
+            }
         }
         if (acc != nullptr) {
             Real tg[2];
@@ -911,12 +943,16 @@ k_fb_forward_adapted(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __
         __builtin_nontemporal_store(v, row + kThreads);
     }
     fb_dump(a, a.dX, 0, sl.p, x, v);
+    FbJumps<Real> jumps;
+    int nj = 0;
+    if (STORE)
+        jumps = fb_jumps<Real>(traj, a.N, a.nblk);
     double acc = 0.0;
     for (int k = 0; k < a.N; ++k) {
         Real zx, zv, a0 = 0, a1;
         const int n = fb_interval(a, sl.p, k, zx, zv, a1);
         fb_advance<Real, NVP>(a, mu + (size_t)k * a.nx * NVP, zd + 2 * k, sl.p, k, n, 0, n + 1, x,
-                              v, cx, cv, a0, a1, zx, zv, &acc);
+                              v, cx, cv, a0, a1, zx, zv, &acc, STORE ? &jumps : nullptr, &nj);
         if (STORE) {
             Real* r = row + (size_t)(k + 1) * 2 * kThreads;
             __builtin_nontemporal_store(x, r);
@@ -924,6 +960,8 @@ k_fb_forward_adapted(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __
         }
         fb_dump(a, a.dX, k + 1, sl.p, x, v);
     }
+    if (STORE)
+        *jumps.count = nj;
     const double C = sl.act ? acc : 0.0;
     if (a.dcost != nullptr) {
         const int64_t p = (int64_t)sl.p - a.dm0;
@@ -940,9 +978,11 @@ k_fb_forward_adapted(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __
 // cost charged there, and the unweighted cost gradient at that state; the
 // length of the interval's last sub-step completes it (and the dump).  The
 // sub-steps then run backwards in a wave-uniform loop over the wave's largest
-// count (each lane recomputes the start of its sub-step r from the stored
-// state at the interval's start), each adding d_r/dt phi(z_r) (alpha u_r +
-// lam^v_-) to the matrix-core sums; lam^v_- carries the jump factor gamma.
+// count (each lane takes the start of its sub-step r, and the state after
+// the jump that ends it, from its stack of post-jump states, recomputing from
+// the interval's start only past the stack's capacity), each adding d_r/dt
+// phi(z_r) (alpha u_r + lam^v_-) to the matrix-core sums; lam^v_- carries the
+// jump factor gamma.
 template <typename Real, int NVP>
 __global__ void __launch_bounds__(kThreads)
 k_fb_adjoint_adapted(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __restrict__ zd,
@@ -954,6 +994,8 @@ k_fb_adjoint_adapted(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __
     const int N = a.N;
     const FbSlot sl = fb_slot<1>(a, 0);
     const Real* row = fb_row<Real>(const_cast<void*>(traj), N, blockIdx.x);
+    const FbJumps<Real> jumps = fb_jumps<Real>(const_cast<void*>(traj), N, a.nblk);
+    int jend = *jumps.count;  // jumps in the intervals up to the current one
     const Real xN = __builtin_nontemporal_load(row + (size_t)N * 2 * kThreads);
     const Real vN = __builtin_nontemporal_load(row + (size_t)N * 2 * kThreads + kThreads);
     Real gxe, gve;  // unweighted running-cost gradient at the interval's end state
@@ -987,19 +1029,39 @@ k_fb_adjoint_adapted(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1)
             nmax = max(nmax, __shfl_xor(nmax, o));
+        const int jb = jend - n;  // stack entry of this interval's first jump
         wave.clear();
         for (int r = nmax; r >= 0; --r) {
             const bool mine = r <= n;
-            Real x = xk, v = vk, cx = 0, cv = 0, a0 = 0, a1 = a1_0, zx = zx0, zv = zv0;
-            if (mine && r > 0)
-                fb_advance<Real, NVP>(a, mk, zk, sl.p, k, n, 0, r, x, v, cx, cv, a0, a1, zx, zv,
-                                      nullptr);
+            Real x = xk, v = vk, a0 = 0, a1 = a1_0;
+            if (mine && r > 0) {
+                for (int q = 1; q <= r; ++q) {
+                    a0 = a1;
+                    a1 = q < n ? fb_next_offset(a, sl.p, k, q, n, a1) : (Real)1;
+                }
+                if (jb + r - 1 < kFbJumpCap) {
+                    x = jumps.st[(size_t)(2 * (jb + r - 1)) * kThreads];
+                    v = jumps.st[(size_t)(2 * (jb + r - 1) + 1) * kThreads];
+                } else {
+                    Real cx = 0, cv = 0, b0 = 0, b1 = a1_0, zx = zx0, zv = zv0;
+                    fb_advance<Real, NVP>(a, mk, zk, sl.p, k, n, 0, r, x, v, cx, cv, b0, b1, zx,
+                                          zv, nullptr);
+                }
+            }
             const Real d = n == 0 ? a.dt : (a1 - a0) * a.dt;
             if (mine && r < n) {
                 // the running cost at the jump ending sub-step r, charged to lam~_{r+1}
-                Real xe = x, ve = v, ce = cx, cve = cv, b0 = a0, b1 = a1, ex = zx, ev = zv;
-                fb_advance<Real, NVP>(a, mk, zk, sl.p, k, n, r, r + 1, xe, ve, ce, cve, b0, b1, ex,
-                                      ev, nullptr);
+                Real xe, ve;
+                if (jb + r < kFbJumpCap) {
+                    xe = jumps.st[(size_t)(2 * (jb + r)) * kThreads];
+                    ve = jumps.st[(size_t)(2 * (jb + r) + 1) * kThreads];
+                } else {
+                    Real cx = 0, cv = 0, b0 = 0, b1 = a1_0, zx = zx0, zv = zv0;
+                    xe = xk;
+                    ve = vk;
+                    fb_advance<Real, NVP>(a, mk, zk, sl.p, k, n, 0, r + 1, xe, ve, cx, cv, b0, b1,
+                                          zx, zv, nullptr);
+                }
                 Real tg[2], gx, gv;
                 fb_target(zk, a1, tg);
                 track_grad(a, xe, ve, tg, gx, gv);
@@ -1037,6 +1099,7 @@ k_fb_adjoint_adapted(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __
                 lv = fma(d, fma(au, uv, fma(uv, lvm, lxm)), lvm);
             }
         }
+        jend = jb;
         track_grad(a, xk, vk, zk, gxe, gve);
         hist.push(fb_tile(wave));
         if (hist.cnt == 4 || k == 0)

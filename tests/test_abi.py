@@ -249,6 +249,17 @@ def test_fb_workspace_and_traj_sizes(L):
     assert L.jd_fb_traj_bytes(C.byref(pr.st), C.byref(rec)) == 0
 
 
+def test_fb_adapted_traj_size(L):
+    """The jump-adapted grid adds 32 post-jump states and a count per slot."""
+    p = wl.adapted_config("ja2").problem
+    pr = _FbDummy(p)
+    for prec, es in (("fp32", 4), ("fp64", 8)):
+        run = B.make_run(1000, precision=prec)
+        slots = 4 * 256
+        want = (p.N + 1) * 2 * slots * es + 32 * 2 * slots * es + slots * 4
+        assert L.jd_fb_traj_bytes(C.byref(pr.st), C.byref(run)) == want
+
+
 @pytest.mark.parametrize("np_,M,rows", [
     (3, 100, 2),      # 85 rings of 3 per 256-slot workgroup: 2 workgroups
     (256, 5, 5),      # one full ring per workgroup

@@ -44,6 +44,9 @@ CASES = {
     "moving_target": (dict(N=40, T=4.0, zd="track", b1=0.2, b2=0.3, gamma=0.8), 900, 5),
     "ellipse": (dict(N=30, T=3.0, cost="ellipse", init="ellipse", s0=(0.1, 0.1), nv=5), 600, 7),
     "grid_16x16": (dict(N=12, T=1.2, nx=16, nv=16, eps=0.8, beta=40.0), 500, 9),
+    # about 40 jumps per particle: most particles overflow the adjoint's stack
+    # of 32 post-jump states and have the rest recomputed
+    "beyond_the_jump_stack": (dict(N=50, T=5.0, beta=200.0, gamma=0.95, b1=0.05, b2=0.05), 300, 11),
 }
 
 
@@ -67,6 +70,8 @@ def test_adapted_cost_grad_and_paths(dev, name, precision):
     z, lam, _, n, C = ref.fb_paths(p, seed, it, 0, M, mu)
     J_ref, g_ref = ref.fb_cost_grad(p, M, seed, it, mu)
     assert n.sum() > 0
+    if name == "beyond_the_jump_stack":
+        assert (n.sum(axis=1) > 32).mean() > 0.5
     eng = B.FbEngine(p, M=M, seed=seed, precision=precision, device=dev)
     dp, d = eng.path_dump(0, M)
     J = eng.forward(mu, it=it, dump=dp)
