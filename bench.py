@@ -426,7 +426,7 @@ def ring_section(args, time_calls, dev):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        sys.exit("bench.py: this build runs on one GPU only (the paths shard across GPUs "
+        sys.exit("bench.py: runs on one GPU only (the paths shard across GPUs "
                  "by contiguous path ranges, but no multi-GPU path is built); use --gpus 1")
     if args.serving:
         return serving_main(args)

@@ -72,8 +72,7 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
-                               "(or python -m paper_2505_04328_amd.build)")
+            raise RuntimeError(f"{LIB_PATH} is not built; run python -m paper_2505_04328_amd.build")
         L = C.CDLL(LIB_PATH)
         P = C.c_void_p
         L.jd_version.restype = C.c_int
