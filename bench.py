@@ -233,7 +233,7 @@ def feedback_section(args, time_calls, dev):
     t_f, t_a = out["fp32"]["forward_ms"] * 1e-3, out["fp32"]["adjoint_ms"] * 1e-3
     t_cg = out["fp32"]["p50_ms"] * 1e-3
     out["roofline"] = {
-        "bound": "alu", "kernel": "k_fb_adjoint<float,10,2,false,false>",
+        "bound": "alu", "kernel": "k_fb_adjoint<float,10,1,false,false>",
         "achieved": FB_ADJ_SLOTS * ps / t_a / 1e12, "peak": VALU_PEAK_SLOTS / 1e12,
         "unit": "TOP/s (full-rate VALU lane-op slots)",
         "frac": FB_ADJ_SLOTS * ps / t_a / VALU_PEAK_SLOTS, "traffic": None,

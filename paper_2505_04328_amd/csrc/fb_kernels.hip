@@ -447,12 +447,12 @@ struct FbMma<float> {
 // go through an LDS transpose (row p = particle, lane i + 16 kk reads A[i][kk] =
 // phx[4q + kk][i] w[4q + kk] and B[kk][i] = phv[4q + kk][i]) into sixteen
 // 16 x 16 x 4 matrix-core products per 64 particles, accumulated in four
-// independent chains.
-template <typename Real>
+// independent chains.  The velocity transpose has rows of PVW >= NVP.
+template <typename Real, int PVW>
 struct FbWave {
     typedef typename FbMma<Real>::acc_t acc_t;
     Real (*phx)[kFbStride];
-    Real (*phv)[kFbStride];
+    Real (*phv)[PVW];
     Real* wts;
     int ln, ii;
     acc_t acc[4];
@@ -474,6 +474,7 @@ struct FbWave {
     // j >= nvp are zero).
     template <int NVP>
     __device__ __forceinline__ void add(Real w, int nx) {
+        static_assert(NVP <= PVW, "velocity rows hold NVP values");
         wts[ln] = w;
         wave_lds_sync();
 #pragma unroll
@@ -487,19 +488,27 @@ struct FbWave {
     }
 };
 
-// The block's LDS for the reduction: per wave, the two transposes and the weights.
-template <typename Real>
+// Row stride of the velocity transpose for a compiled width NVP: the smallest
+// odd stride >= NVP, so a wave's writes of one column and the operand reads of
+// two rows fall in distinct banks, in as little LDS as possible (with NVP = 10
+// a block needs 29.7 KB in FP32, room for five blocks per CU).
+template <int NVP>
+constexpr int fb_pvw() { return NVP % 2 ? NVP : NVP + 1; }
+
+// The block's LDS for the reduction: per wave, the two transposes and the
+// weights; between steps the transposes hold the waves' FP64 tiles.
+template <typename Real, int PVW>
 struct FbShared {
-    Real phx[kFbWaves][64][kFbStride];  // after a step: the wave's FP64 tile
-    Real phv[kFbWaves][64][kFbStride];
+    Real phx[kFbWaves][64][kFbStride];
+    Real phv[kFbWaves][64][PVW];
     Real wts[kFbWaves][64];
 };
 
-template <typename Real>
-__device__ __forceinline__ FbWave<Real> fb_wave(FbShared<Real>& sh) {
+template <typename Real, int PVW>
+__device__ __forceinline__ FbWave<Real, PVW> fb_wave(FbShared<Real, PVW>& sh) {
     static_assert(sizeof(Real) * 64 * kFbStride >= sizeof(double) * kFbMaxGrid * kFbMaxGrid,
                   "a wave's transpose buffer must hold its 16 x 16 FP64 tile");
-    FbWave<Real> w;
+    FbWave<Real, PVW> w;
     const int wv = threadIdx.x >> 6;
     w.phx = sh.phx[wv];
     w.phv = sh.phv[wv];
@@ -529,8 +538,8 @@ struct FbHist {
 };
 
 // The sum of the wave's four chains, in FP64.
-template <typename Real>
-__device__ __forceinline__ fb_d4 fb_tile(const FbWave<Real>& w) {
+template <typename Real, int PVW>
+__device__ __forceinline__ fb_d4 fb_tile(const FbWave<Real, PVW>& w) {
     fb_d4 t;
 #pragma unroll
     for (int r = 0; r < 4; ++r)
@@ -538,21 +547,30 @@ __device__ __forceinline__ fb_d4 fb_tile(const FbWave<Real>& w) {
     return t;
 }
 
+// Number of 16 x 16 FP64 tiles a wave's transposes hold: in phx, in phv.
+constexpr int kFbTile = kFbMaxGrid * kFbMaxGrid;
+template <typename Real>
+constexpr int fb_tiles_x() { return (int)(sizeof(Real) * 64 * kFbStride / (sizeof(double) * kFbTile)); }
+template <typename Real, int PVW>
+constexpr int fb_tiles_v() { return (int)(sizeof(Real) * 64 * PVW / (sizeof(double) * kFbTile)); }
+
 // LDS home of tile s of wave wv during a flush (the wave's transpose buffers,
 // free between steps).
-template <typename Real>
-__device__ __forceinline__ double* fb_tile_lds(FbShared<Real>& sh, int wv, int s) {
-    static_assert(sizeof(Real) * 64 * kFbStride >= 2 * sizeof(double) * kFbMaxGrid * kFbMaxGrid,
-                  "a wave's transpose buffer must hold two 16 x 16 FP64 tiles");
-    return (double*)(s < 2 ? &sh.phx[wv][0][0] : &sh.phv[wv][0][0]) + (s & 1) * kFbMaxGrid * kFbMaxGrid;
+template <typename Real, int PVW>
+__device__ __forceinline__ double* fb_tile_lds(FbShared<Real, PVW>& sh, int wv, int s) {
+    constexpr int TX = fb_tiles_x<Real>();
+    return s < TX ? (double*)&sh.phx[wv][0][0] + s * kFbTile
+                  : (double*)&sh.phv[wv][0][0] + (s - TX) * kFbTile;
 }
 
 // Sums the four waves' held tiles in a fixed order into the block's partials:
 // tile s is step k0 + s dir (ADD: added to what the partial holds).
-template <bool ADD, int H, typename Real>
-__device__ __forceinline__ void fb_hist_flush(FbShared<Real>& sh, const FbWave<Real>& w,
+template <bool ADD, int H, typename Real, int PVW>
+__device__ __forceinline__ void fb_hist_flush(FbShared<Real, PVW>& sh, const FbWave<Real, PVW>& w,
                                               FbHist<H>& h, int k0, int dir, int N, int nx, int nv,
                                               double* __restrict__ apart) {
+    static_assert(H <= fb_tiles_x<Real>() + fb_tiles_v<Real, PVW>(),
+                  "a wave's transposes must hold its H tiles");
     const int wv = threadIdx.x >> 6;
 #pragma unroll
     for (int s = 0; s < H; ++s) {
@@ -590,9 +608,9 @@ __global__ void __launch_bounds__(kThreads)
 k_fb_forward_grad(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __restrict__ zd,
                   const Real* __restrict__ ks, double* __restrict__ cpart,
                   double* __restrict__ apart) {
-    __shared__ FbShared<Real> sh;
+    __shared__ FbShared<Real, fb_pvw<NVP>()> sh;
     __shared__ double red[kThreads];
-    FbWave<Real> wave = fb_wave(sh);
+    auto wave = fb_wave(sh);
     FbHist<1> hist;
     hist.cnt = 0;
     const int N = a.N;
@@ -667,9 +685,9 @@ __global__ void __launch_bounds__(kThreads)
 k_fb_adjoint(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __restrict__ zd,
              const Real* __restrict__ ks, const void* traj, double* __restrict__ apart) {
     static_assert(!(SURR && RING), "the surrogate gradient takes independent particles");
-    __shared__ FbShared<Real> sh;
+    __shared__ FbShared<Real, fb_pvw<NVP>()> sh;
     __shared__ Real cw[RING ? 2 : 1][RING ? G * kThreads : 1];
-    FbWave<Real> wave = fb_wave(sh);
+    auto wave = fb_wave(sh);
     FbHist<1> hist;
     hist.cnt = 0;
     const int N = a.N;
@@ -987,8 +1005,9 @@ template <typename Real, int NVP>
 __global__ void __launch_bounds__(kThreads)
 k_fb_adjoint_adapted(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __restrict__ zd,
                      const void* traj, double* __restrict__ apart) {
-    __shared__ FbShared<Real> sh;
-    FbWave<Real> wave = fb_wave(sh);
+    // four held tiles: FP32 needs the full 17-wide velocity rows for them
+    __shared__ FbShared<Real, sizeof(Real) == 4 ? kFbStride : fb_pvw<NVP>()> sh;
+    auto wave = fb_wave(sh);
     FbHist<4> hist;
     hist.cnt = 0;
     const int N = a.N;
@@ -1370,11 +1389,20 @@ hipError_t fb_launch_forward(const FbHost& p, const HostRun& r, const void* tab,
                              : fb_forward_t<float>(p, r, tab, traj, cpart, hdr, st);
 }
 
-// Particles per lane of the adjoint: two 256-particle groups per block halve
-// the per-step gradient partials (one per block) once at least 1024 blocks
-// remain.  Measured on 2^20 x 500 (FP32): adjoint 16.2 / 15.5 / 18.3 ms with
-// 1 / 2 / 4 groups (four groups need 115 VGPRs: 3 waves per SIMD).
-int fb_adjoint_groups(int nblk) { return nblk >= 2048 ? 2 : 1; }
+// 256-particle groups per block of the independent-particle adjoint (and of
+// the surrogate's forward, which shares its partials).  Several groups per
+// block divide the per-step gradient partials but cost registers.  Measured on
+// 2^20 x 500: FP64 paths 31.1 / 28.9 ms for 1 / 2 groups (16.2 / 15.5 / 18.3 ms
+// for 1 / 2 / 4 on FP32 paths while these used the FP64 matrix cores); FP32
+// paths on the FP32 matrix cores with the compact velocity transposes fit five
+// waves per SIMD with one group: 10.8 ms against 11.3 ms for two (four waves)
+// and 11.0 ms for two forced to five waves (spills).  Rings keep their own G
+// (whole rings per block); the jump-adapted adjoint runs one group.
+static int fb_adjoint_groups(const FbHost& p, const HostRun& r) {
+    if (p.np > 1)
+        return p.G;
+    return p.grid == 0 && r.prec == JD_FP64 && r.nblk >= 2048 ? 2 : 1;
+}
 
 template <typename Real>
 static hipError_t fb_adjoint_t(const FbHost& p, const HostRun& r, const void* tab, const void* traj,
@@ -1383,7 +1411,7 @@ static hipError_t fb_adjoint_t(const FbHost& p, const HostRun& r, const void* ta
     FbArgs<Real> a = fb_args<Real>(p, r);
     a.thr = &hdr->poisson;
     const Real* tb = (const Real*)tab;
-    const int G = p.grid == 1 ? 1 : p.np == 1 ? fb_adjoint_groups(r.nblk) : p.G;
+    const int G = fb_adjoint_groups(p, r);
     const unsigned nb = (unsigned)fb_partial_blocks(p, r);
 #define FB_ADJ_G(NVP, GG, S, RG)                                                                  \
     hipLaunchKernelGGL((k_fb_adjoint<Real, NVP, GG, S, RG>), dim3(nb), dim3(kThreads), 0, st, a,  \
@@ -1424,8 +1452,8 @@ static hipError_t fb_forward_grad_t(const FbHost& p, const HostRun& r, const voi
     FbArgs<Real> a = fb_args<Real>(p, r);
     a.thr = &hdr->poisson;
     const Real* tb = (const Real*)tab;
-    const int G = fb_adjoint_groups(r.nblk);
-    const unsigned nb = (unsigned)((r.nblk + G - 1) / G);
+    const int G = fb_adjoint_groups(p, r);
+    const unsigned nb = (unsigned)fb_partial_blocks(p, r);
 #define FB_FG(NVP)                                                                                \
     do {                                                                                          \
         if (G == 2)                                                                               \
@@ -1447,11 +1475,7 @@ hipError_t fb_launch_forward_grad(const FbHost& p, const HostRun& r, const void*
 }
 
 int fb_partial_blocks(const FbHost& p, const HostRun& r) {
-    if (p.grid == 1)
-        return r.nblk;
-    if (p.np > 1)
-        return r.nblk / p.G;
-    const int G = fb_adjoint_groups(r.nblk);
+    const int G = fb_adjoint_groups(p, r);
     return (r.nblk + G - 1) / G;
 }
 

@@ -203,22 +203,23 @@ def test_fb_full_size_f4(dev):
         assert np.max(np.abs(dd["cost"].cpu().numpy() - C) / (np.abs(C) + np.sqrt(np.mean(C * C)))) <= tol["path"]
 
 
-# 2^19 + 100: 2049 groups, the last block holds a ragged group (100 particles)
-# and an empty one; 2^19 + 356: 2050 groups, the last block a full and a ragged one
+# 2^19 + 100 particles: 2049 groups of 256, the last one ragged (FP64 paths,
+# two groups per adjoint block: the last block a ragged group and an empty
+# one); 2^19 + 356: 2050 groups (FP64: the last block a full and a ragged one)
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
 @pytest.mark.parametrize("M", [(1 << 19) + 100, (1 << 19) + 356])
-def test_fb_several_particles_per_lane(dev, M):
-    """M >= 2^19 runs the adjoint with 2 groups of 256 particles per block, the
-    last block holding a ragged group and an empty one, or two groups, the
-    second ragged: J and g against the oracle at the full M (short horizon)."""
+def test_fb_large_m_ragged_last_block(dev, M, precision):
+    """Half a million particles with a ragged last group: J and g against the
+    oracle at the full M (short horizon)."""
     p = wl.feedback_problem(N=8, T=0.8, zd=_track(8, 0.8), alpha=0.1)
     mu = wl.random_feedback_control(p, 3, 1.0)
-    say("fb groups per block, M =", M)
-    eng = B.FbEngine(p, M=M, seed=17, precision="fp32", device=dev)
+    say("fb large M", M, precision)
+    eng = B.FbEngine(p, M=M, seed=17, precision=precision, device=dev)
     J, g = eng.cost_grad(mu, it=2)
     J_ref, g_ref = ref.fb_cost_grad(p, M, 17, 2, mu)
     e_J, e_g = rel_err(float(J), J_ref), norm_err(g.cpu().numpy(), g_ref)
     say(f"   J {e_J:.2e} g {e_g:.2e}")
-    assert e_J <= TOL["fp32"]["J"] and e_g <= TOL["fp32"]["g"]
+    assert e_J <= TOL[precision]["J"] and e_g <= TOL[precision]["g"]
 
 
 # ---------------------------------------------------------------- surrogate gradient (Section 6.5)
@@ -263,16 +264,19 @@ def test_fb_surrogate_cost_grad_and_paths(dev, name, precision):
     assert norm_err(g, g_exact) > 1e-3
 
 
-def test_fb_surrogate_two_groups_per_block(dev):
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_fb_surrogate_large_m(dev, precision):
+    """2^19 + 100 particles: a ragged last group (FP64 paths: two groups per
+    block, the last block a ragged group and an empty one)."""
     p = wl.feedback_problem(N=8, T=0.8, zd=_track(8, 0.8), alpha=0.1)
     M = (1 << 19) + 100
     mu = wl.random_feedback_control(p, 3, 1.0)
-    say("surrogate groups per block, M =", M)
-    eng = B.FbEngine(p, M=M, seed=17, precision="fp32", device=dev, mode="surrogate")
+    say("surrogate large M", M, precision)
+    eng = B.FbEngine(p, M=M, seed=17, precision=precision, device=dev, mode="surrogate")
     J, g = eng.cost_grad(mu, it=2)
     J_ref, g_ref = ref.fb_cost_grad_surrogate(p, M, 17, 2, mu)
-    assert rel_err(float(J), J_ref) <= TOL["fp32"]["J"]
-    assert norm_err(g.cpu().numpy(), g_ref) <= TOL["fp32"]["g"]
+    assert rel_err(float(J), J_ref) <= TOL[precision]["J"]
+    assert norm_err(g.cpu().numpy(), g_ref) <= TOL[precision]["g"]
 
 
 def test_fb_surrogate_optimize_matches_oracle(dev):
