@@ -233,12 +233,12 @@ def feedback_section(args, time_calls, dev):
     t_f, t_a = out["fp32"]["forward_ms"] * 1e-3, out["fp32"]["adjoint_ms"] * 1e-3
     t_cg = out["fp32"]["p50_ms"] * 1e-3
     out["roofline"] = {
-        "bound": "alu", "kernel": "k_fb_adjoint<float,10,1,false,false>",
+        "bound": "alu", "kernel": "k_fb_adjoint<float,10,1,false,false,256>",
         "achieved": FB_ADJ_SLOTS * ps / t_a / 1e12, "peak": VALU_PEAK_SLOTS / 1e12,
         "unit": "TOP/s (full-rate VALU lane-op slots)",
         "frac": FB_ADJ_SLOTS * ps / t_a / VALU_PEAK_SLOTS, "traffic": None,
         "slots_per_path_step": FB_ADJ_SLOTS, "kernel_ms": t_a * 1e3}
-    out["forward_roofline"] = {"kernel": "k_fb_forward<float,10,true,1,false>", "bound": "alu",
+    out["forward_roofline"] = {"kernel": "k_fb_forward<float,10,true,1,false,256>", "bound": "alu",
                                "frac": FB_FWD_SLOTS * ps / t_f / VALU_PEAK_SLOTS,
                                "slots_per_path_step": FB_FWD_SLOTS}
     out["step_frac"] = (FB_FWD_SLOTS + FB_ADJ_SLOTS) * ps / t_cg / VALU_PEAK_SLOTS
@@ -383,12 +383,12 @@ def ring_section(args, time_calls, dev):
     t_f, t_a = out["fp32"]["forward_ms"] * 1e-3, out["fp32"]["adjoint_ms"] * 1e-3
     t_cg = out["fp32"]["p50_ms"] * 1e-3
     out["roofline"] = {
-        "bound": "alu", "kernel": "k_fb_adjoint<float,10,8,false,true>",
+        "bound": "alu", "kernel": "k_fb_adjoint<float,10,2,false,true,1024>",
         "achieved": RING_ADJ_SLOTS * ps / t_a / 1e12, "peak": VALU_PEAK_SLOTS / 1e12,
         "unit": "TOP/s (full-rate VALU lane-op slots)",
         "frac": RING_ADJ_SLOTS * ps / t_a / VALU_PEAK_SLOTS, "traffic": None,
         "slots_per_particle_step": RING_ADJ_SLOTS, "kernel_ms": t_a * 1e3}
-    out["forward_roofline"] = {"kernel": "k_fb_forward<float,10,true,8,true>", "bound": "alu",
+    out["forward_roofline"] = {"kernel": "k_fb_forward<float,10,true,2,true,1024>", "bound": "alu",
                                "frac": RING_FWD_SLOTS * ps / t_f / VALU_PEAK_SLOTS,
                                "slots_per_particle_step": RING_FWD_SLOTS}
     out["step_frac"] = (RING_FWD_SLOTS + RING_ADJ_SLOTS) * ps / t_cg / VALU_PEAK_SLOTS

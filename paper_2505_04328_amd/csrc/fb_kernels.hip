@@ -267,23 +267,24 @@ __device__ __forceinline__ void track_grad(const FbArgs<Real>& a, Real x, Real v
     gv = rv * e;
 }
 
-// Slot q = g 256 + threadIdx.x of a workgroup holding G groups of 256 slots:
-// its particle p, whether it holds one, and the workgroup slots of its ring
-// neighbours.  np = 1: particle blockIdx.x 256 G + q.  np > 1: ring
-// blockIdx.x sb + q / np, position q mod np; slots past the sb rings, and
-// rings past the last, hold none (p = M then lies outside every dump range).
+// Slot q = g TPB + threadIdx.x of a workgroup of TPB threads holding G
+// particles per lane (G TPB slots): its particle p, whether it holds one, and
+// the workgroup slots of its ring neighbours.  np = 1: particle
+// blockIdx.x TPB G + q.  np > 1: ring blockIdx.x sb + q / np, position
+// q mod np; slots past the sb rings, and rings past the last, hold none (p = M
+// then lies outside every dump range).
 struct FbSlot {
     uint32_t p;
     bool act;
     int lft, rgt;
 };
-template <int G, typename Real>
+template <int G, typename Real, int TPB = kThreads>
 __device__ __forceinline__ FbSlot fb_slot(const FbArgs<Real>& a, int g) {
     FbSlot s;
-    const int q = g * kThreads + (int)threadIdx.x;
+    const int q = g * TPB + (int)threadIdx.x;
     s.lft = s.rgt = q;
     if (a.np == 1) {
-        const int64_t m = (int64_t)blockIdx.x * (G * kThreads) + q;
+        const int64_t m = (int64_t)blockIdx.x * (G * TPB) + q;
         s.act = m < a.M;
         s.p = (uint32_t)m;
         return s;
@@ -303,6 +304,17 @@ __device__ __forceinline__ FbSlot fb_slot(const FbArgs<Real>& a, int g) {
 template <typename Real>
 __device__ __forceinline__ Real* fb_row(void* traj, int N, int64_t blk) {
     return (Real*)traj + (size_t)blk * (N + 1) * 2 * kThreads + threadIdx.x;
+}
+// The trajectory row of workgroup slot g TPB + threadIdx.x (G particles per
+// lane): slots map onto consecutive 256-wide trajectory blocks, the same
+// layout whatever the workgroup size; blocks past the last (empty slots of the
+// last workgroup) read the last one.
+template <typename Real, int G, int TPB>
+__device__ __forceinline__ Real* fb_slot_row(const void* traj, int N, int64_t nblk, int g) {
+    const int q = g * TPB + (int)threadIdx.x;
+    int64_t blk = (int64_t)blockIdx.x * (G * TPB / kThreads) + q / kThreads;
+    blk = blk < nblk ? blk : nblk - 1;
+    return (Real*)const_cast<void*>(traj) + (size_t)blk * (N + 1) * 2 * kThreads + (q % kThreads);
 }
 
 // ---------------------------------------------------------------------------
@@ -331,25 +343,26 @@ k_fb_table(const double* __restrict__ mu, const double* __restrict__ zd, Real* _
 }
 
 // Forward sweep.  Without rings (RING = false, G = 1) one particle per lane and
-// no synchronisation.  With rings each lane carries G particles (slots
-// g 256 + threadIdx.x) and every step first publishes x_k in LDS (double
-// buffered by step parity, one barrier per step) for the ring force.
-template <typename Real, int NVP, bool STORE, int G, bool RING>
-__global__ void __launch_bounds__(kThreads)
+// no synchronisation.  With rings a workgroup of TPB threads carries G
+// particles per lane (slots g TPB + threadIdx.x) and every step first
+// publishes x_k in LDS (double buffered by step parity, one barrier per step)
+// for the ring force.
+template <typename Real, int NVP, bool STORE, int G, bool RING, int TPB = kThreads>
+__global__ void __launch_bounds__(TPB, TPB == 1024 && sizeof(Real) == 4 ? 8 : 1)
 k_fb_forward(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __restrict__ zd,
              const Real* __restrict__ ks, void* traj, double* __restrict__ cpart) {
-    static_assert(RING || G == 1, "independent particles run one per lane");
-    __shared__ double sh[kThreads];
-    __shared__ Real xs[RING ? 2 : 1][RING ? G * kThreads : 1];
+    static_assert(RING || (G == 1 && TPB == kThreads), "independent particles run one per lane");
+    __shared__ double sh[TPB];
+    __shared__ Real xs[RING ? 2 : 1][RING ? G * TPB : 1];
     Real x[G], v[G], cx[G], cv[G];
     double acc[G];
     FbSlot sl[G];
     Real* row[G];
 #pragma unroll
     for (int j = 0; j < G; ++j) {
-        sl[j] = fb_slot<G>(a, j);
+        sl[j] = fb_slot<G, Real, TPB>(a, j);
         fb_initial(a, sl[j].p, x[j], v[j]);
-        row[j] = STORE ? fb_row<Real>(traj, a.N, (int64_t)blockIdx.x * G + j) : nullptr;
+        row[j] = STORE ? fb_slot_row<Real, G, TPB>(traj, a.N, a.nblk, j) : nullptr;
         if (STORE) {
             __builtin_nontemporal_store(x[j], row[j]);
             __builtin_nontemporal_store(v[j], row[j] + kThreads);
@@ -364,7 +377,7 @@ k_fb_forward(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __restrict
             Real* xb = xs[k & 1];
 #pragma unroll
             for (int j = 0; j < G; ++j)
-                xb[j * kThreads + threadIdx.x] = x[j];
+                xb[j * TPB + threadIdx.x] = x[j];
             __syncthreads();
 #pragma unroll
             for (int j = 0; j < G; ++j)
@@ -395,7 +408,7 @@ k_fb_forward(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __restrict
         }
         C += c;
     }
-    const double s = block_sum(C, sh);
+    const double s = block_sum<TPB>(C, sh);
     if (threadIdx.x == 0)
         cpart[blockIdx.x] = s;
 }
@@ -495,17 +508,18 @@ struct FbWave {
 template <int NVP>
 constexpr int fb_pvw() { return NVP % 2 ? NVP : NVP + 1; }
 
-// The block's LDS for the reduction: per wave, the two transposes and the
-// weights; between steps the transposes hold the waves' FP64 tiles.
-template <typename Real, int PVW>
+// The block's LDS for the reduction: per wave (W of them), the two transposes
+// and the weights; between steps the transposes hold the waves' FP64 tiles.
+template <typename Real, int PVW, int W = kFbWaves>
 struct FbShared {
-    Real phx[kFbWaves][64][kFbStride];
-    Real phv[kFbWaves][64][PVW];
-    Real wts[kFbWaves][64];
+    static constexpr int waves = W;
+    Real phx[W][64][kFbStride];
+    Real phv[W][64][PVW];
+    Real wts[W][64];
 };
 
-template <typename Real, int PVW>
-__device__ __forceinline__ FbWave<Real, PVW> fb_wave(FbShared<Real, PVW>& sh) {
+template <typename Real, int PVW, int W>
+__device__ __forceinline__ FbWave<Real, PVW> fb_wave(FbShared<Real, PVW, W>& sh) {
     static_assert(sizeof(Real) * 64 * kFbStride >= sizeof(double) * kFbMaxGrid * kFbMaxGrid,
                   "a wave's transpose buffer must hold its 16 x 16 FP64 tile");
     FbWave<Real, PVW> w;
@@ -556,17 +570,17 @@ constexpr int fb_tiles_v() { return (int)(sizeof(Real) * 64 * PVW / (sizeof(doub
 
 // LDS home of tile s of wave wv during a flush (the wave's transpose buffers,
 // free between steps).
-template <typename Real, int PVW>
-__device__ __forceinline__ double* fb_tile_lds(FbShared<Real, PVW>& sh, int wv, int s) {
+template <typename Real, int PVW, int W>
+__device__ __forceinline__ double* fb_tile_lds(FbShared<Real, PVW, W>& sh, int wv, int s) {
     constexpr int TX = fb_tiles_x<Real>();
     return s < TX ? (double*)&sh.phx[wv][0][0] + s * kFbTile
                   : (double*)&sh.phv[wv][0][0] + (s - TX) * kFbTile;
 }
 
-// Sums the four waves' held tiles in a fixed order into the block's partials:
+// Sums the W waves' held tiles in a fixed order into the block's partials:
 // tile s is step k0 + s dir (ADD: added to what the partial holds).
-template <bool ADD, int H, typename Real, int PVW>
-__device__ __forceinline__ void fb_hist_flush(FbShared<Real, PVW>& sh, const FbWave<Real, PVW>& w,
+template <bool ADD, int H, typename Real, int PVW, int W>
+__device__ __forceinline__ void fb_hist_flush(FbShared<Real, PVW, W>& sh, const FbWave<Real, PVW>& w,
                                               FbHist<H>& h, int k0, int dir, int N, int nx, int nv,
                                               double* __restrict__ apart) {
     static_assert(H <= fb_tiles_x<Real>() + fb_tiles_v<Real, PVW>(),
@@ -589,7 +603,7 @@ __device__ __forceinline__ void fb_hist_flush(FbShared<Real, PVW>& sh, const FbW
             if (s < h.cnt) {
                 double sum = fb_tile_lds(sh, 0, s)[t];
 #pragma unroll
-                for (int q = 1; q < kFbWaves; ++q)
+                for (int q = 1; q < W; ++q)
                     sum += fb_tile_lds(sh, q, s)[t];
                 double* dst = apart + ((size_t)blockIdx.x * N + (k0 + s * dir)) * (nx * nv) + i * nv + j;
                 *dst = ADD ? *dst + sum : sum;
@@ -667,10 +681,11 @@ struct FbAdj {
     Real lx, lv;  // lam_{k+1} on entry to step k
 };
 
-// Backward sweep.  Each lane carries G particles (groups blockIdx.x G + j of
-// 256, j < G) through the steps together; at step k each particle in turn adds
-// its shape functions times its weight to the wave's matrix-core sums, and the
-// four waves' sums form one FP64 partial per block and step.
+// Backward sweep.  Each lane of a workgroup of TPB threads carries G particles
+// (slots j TPB + threadIdx.x, j < G) through the steps together; at step k
+// each particle in turn adds its shape functions times its weight to the
+// wave's matrix-core sums, and the waves' sums form one FP64 partial per
+// workgroup and step.
 //   SURR = false: the states are the stored trajectory and the weight is
 //                 alpha u + gamma^n lam^v (the exact gradient);
 //   SURR = true:  the states are the surrogate states of Section 6.5 and the
@@ -680,13 +695,14 @@ struct FbAdj {
 //                 w = gamma^n lam^v_{k+1} goes to LDS (double buffered by step
 //                 parity) and, after the block barriers of the step's
 //                 gradient flush, its neighbours add dt omega w to their lam^x_k.
-template <typename Real, int NVP, int G, bool SURR, bool RING>
-__global__ void __launch_bounds__(kThreads)
+template <typename Real, int NVP, int G, bool SURR, bool RING, int TPB = kThreads>
+__global__ void __launch_bounds__(TPB)
 k_fb_adjoint(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __restrict__ zd,
              const Real* __restrict__ ks, const void* traj, double* __restrict__ apart) {
     static_assert(!(SURR && RING), "the surrogate gradient takes independent particles");
-    __shared__ FbShared<Real, fb_pvw<NVP>()> sh;
-    __shared__ Real cw[RING ? 2 : 1][RING ? G * kThreads : 1];
+    static_assert(RING || TPB == kThreads, "independent particles run in blocks of 256");
+    __shared__ FbShared<Real, fb_pvw<NVP>(), TPB / 64> sh;
+    __shared__ Real cw[RING ? 2 : 1][RING ? G * TPB : 1];
     auto wave = fb_wave(sh);
     FbHist<1> hist;
     hist.cnt = 0;
@@ -698,15 +714,14 @@ k_fb_adjoint(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __restrict
     FbSlot sl[G];
 #pragma unroll
     for (int j = 0; j < G; ++j) {
-        const int64_t g = (int64_t)blockIdx.x * G + j;
-        sl[j] = fb_slot<G>(a, j);
+        sl[j] = fb_slot<G, Real, TPB>(a, j);
         m[j] = sl[j].p;
         act[j] = sl[j].act;
         if (SURR) {
             row[j] = nullptr;
             fb_surrogate(a, zd, (uint32_t)m[j], N, s[j].x, s[j].v);
         } else {
-            row[j] = fb_row<Real>(const_cast<void*>(traj), N, g < a.nblk ? g : a.nblk - 1);
+            row[j] = fb_slot_row<Real, G, TPB>(traj, N, a.nblk, j);
             s[j].x = __builtin_nontemporal_load(row[j] + (size_t)N * 2 * kThreads);
             s[j].v = __builtin_nontemporal_load(row[j] + (size_t)N * 2 * kThreads + kThreads);
             s[j].xn = __builtin_nontemporal_load(row[j] + (size_t)(N - 1) * 2 * kThreads);
@@ -768,7 +783,7 @@ k_fb_adjoint(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __restrict
             const Real wk = SURR ? gn * st.lv : fma(a.alpha, u, gn * st.lv);
             wave.template add<NVP>(act[j] ? wk : (Real)0, a.nx);
             if (RING)
-                cw[k & 1][j * kThreads + threadIdx.x] = gn * st.lv;
+                cw[k & 1][j * TPB + threadIdx.x] = gn * st.lv;
             if (k >= 1) {
                 Real gx, gv;
                 track_grad(a, st.x, st.v, zd + 2 * k, gx, gv);
@@ -1343,6 +1358,32 @@ hipError_t fb_launch_table(const FbHost& p, const HostRun& r, const double* mu, 
 
 int fb_ring_groups(int np) { return np <= kThreads ? 1 : 8; }
 
+// Rings of more than 256 particles take workgroups of 2048 slots (eight
+// 256-wide trajectory blocks) and are coupled through LDS every step, so one
+// ring's workgroup cannot be split.  With 256 threads (eight particles per
+// lane) ring2 (512 rings of 2000, 500 steps) ran at two waves per SIMD: FP32
+// forward 7.4 ms, adjoint 15.4 ms, against 5.3 / 11.0 ms for rings of 256 at
+// one particle per lane.  The FP32 forward runs 1024 threads (two particles per
+// lane, held to 64 registers for eight waves per SIMD: 5.75 ms, 6.2 ms
+// without), the FP64 forward 512 (four per lane: 23.6 ms against 25.5 ms at
+// 1024, which spills, and 28.1 ms at 256).  The adjoint runs the most threads
+// of 1024 / 512 / 256 whose per-wave transposes and neighbour buffer fit the
+// 160 KB of LDS of a workgroup (FP32: 1024, 12.1 ms; FP64: 512, 30.3 ms against
+// 41.7 ms at 256; 256 for 16-wide FP64 rows).
+constexpr int kFbRingSlots = 8 * kThreads;
+template <typename Real>
+constexpr int fb_ring_fwd_threads() { return sizeof(Real) == 4 ? 1024 : 512; }
+template <typename Real, int NVP>
+constexpr int fb_ring_adj_lds(int tpb) {
+    return (int)sizeof(FbShared<Real, fb_pvw<NVP>(), 16>) / 16 * (tpb / 64) + 2 * kFbRingSlots * (int)sizeof(Real);
+}
+template <typename Real, int NVP>
+constexpr int fb_ring_adj_threads() {
+    return fb_ring_adj_lds<Real, NVP>(1024) <= 160 * 1024   ? 1024
+           : fb_ring_adj_lds<Real, NVP>(512) <= 160 * 1024 ? 512
+                                                            : 256;
+}
+
 int fb_forward_blocks(const FbHost& p, const HostRun& r) {
     return p.np == 1 ? r.nblk : r.nblk / p.G;
 }
@@ -1355,14 +1396,15 @@ static hipError_t fb_forward_t(const FbHost& p, const HostRun& r, const void* ta
     a.thr = &hdr->poisson;
     const Real* tb = (const Real*)tab;
     const unsigned nb = (unsigned)fb_forward_blocks(p, r);
-#define FB_FWD_K(NVP, S, GG, RG)                                                                  \
-    hipLaunchKernelGGL((k_fb_forward<Real, NVP, S, GG, RG>), dim3(nb), dim3(kThreads), 0, st, a,  \
+#define FB_FWD_K(NVP, S, GG, RG, TPB)                                                             \
+    hipLaunchKernelGGL((k_fb_forward<Real, NVP, S, GG, RG, TPB>), dim3(nb), dim3(TPB), 0, st, a,  \
                        tb + t.mu, tb + t.zd, tb + t.ks, traj, cpart)
 #define FB_FWD_S(NVP, S)                                                                          \
     do {                                                                                          \
-        if (p.np == 1) FB_FWD_K(NVP, S, 1, false);                                                \
-        else if (p.G == 1) FB_FWD_K(NVP, S, 1, true);                                             \
-        else FB_FWD_K(NVP, S, 8, true);                                                           \
+        if (p.np == 1) FB_FWD_K(NVP, S, 1, false, kThreads);                                      \
+        else if (p.G == 1) FB_FWD_K(NVP, S, 1, true, kThreads);                                   \
+        else FB_FWD_K(NVP, S, kFbRingSlots / fb_ring_fwd_threads<Real>(), true,                    \
+                      fb_ring_fwd_threads<Real>());                                               \
     } while (0)
 #define FB_FWD_A(NVP, S)                                                                          \
     hipLaunchKernelGGL((k_fb_forward_adapted<Real, NVP, S>), dim3(nb), dim3(kThreads), 0, st, a,  \
@@ -1416,14 +1458,21 @@ static hipError_t fb_adjoint_t(const FbHost& p, const HostRun& r, const void* ta
 #define FB_ADJ_G(NVP, GG, S, RG)                                                                  \
     hipLaunchKernelGGL((k_fb_adjoint<Real, NVP, GG, S, RG>), dim3(nb), dim3(kThreads), 0, st, a,  \
                        tb + t.mu, tb + t.zd, tb + t.ks, traj, apart)
+
 #define FB_ADJ(NVP)                                                                               \
     do {                                                                                          \
         if (p.grid == 1) {                                                                        \
             hipLaunchKernelGGL((k_fb_adjoint_adapted<Real, NVP>), dim3(nb), dim3(kThreads), 0,    \
                                st, a, tb + t.mu, tb + t.zd, traj, apart);                         \
         } else if (p.np > 1) {                                                                    \
-            if (G == 8) FB_ADJ_G(NVP, 8, false, true);                                            \
-            else FB_ADJ_G(NVP, 1, false, true);                                                   \
+            if (G == 8) {                                                                         \
+                constexpr int RT = fb_ring_adj_threads<Real, NVP>();                              \
+                hipLaunchKernelGGL((k_fb_adjoint<Real, NVP, kFbRingSlots / RT, false, true, RT>), \
+                                   dim3(nb), dim3(RT), 0, st, a, tb + t.mu, tb + t.zd, tb + t.ks, \
+                                   traj, apart);                                                  \
+            } else {                                                                              \
+                FB_ADJ_G(NVP, 1, false, true);                                                    \
+            }                                                                                     \
         } else if (G == 2) {                                                                      \
             if (surr) FB_ADJ_G(NVP, 2, true, false);                                              \
             else FB_ADJ_G(NVP, 2, false, false);                                                  \

@@ -327,13 +327,14 @@ __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// Deterministic FP64 sum over a block of kThreads threads (fixed tree).
+// Deterministic FP64 sum over a block of NT threads (fixed tree).
+template <int NT = kThreads>
 __device__ __forceinline__ double block_sum(double v, double* sh) {
     const int t = threadIdx.x;
     sh[t] = v;
     __syncthreads();
 #pragma unroll
-    for (int s = kThreads / 2; s > 0; s >>= 1) {
+    for (int s = NT / 2; s > 0; s >>= 1) {
         if (t < s)
             sh[t] += sh[t + s];
         __syncthreads();
