@@ -20,13 +20,16 @@ CFLAGS = ["-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-s
 def build(src=SRC, out: str = LIB, extra: list | None = None, quiet: bool = True) -> str:
     """Compile `src` (one path or a list of C files) into the shared library `out`."""
     srcs = [src] if isinstance(src, str) else list(src)
-    cmd = ["gcc", *CFLAGS, *(extra or []), "-o", out + ".tmp", *srcs, "-lm"]
+    # a private temporary name: concurrent builds (parallel test workers) each
+    # rename a complete library into place
+    tmp = f"{out}.{os.getpid()}.tmp"
+    cmd = ["gcc", *CFLAGS, *(extra or []), "-o", tmp, *srcs, "-lm"]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError("oracle build failed:\n" + " ".join(cmd) + "\n" + res.stderr)
     if res.stderr and not quiet:
         sys.stderr.write(res.stderr)
-    os.replace(out + ".tmp", out)
+    os.replace(tmp, out)
     return out
 
 
