@@ -534,10 +534,11 @@ __device__ __forceinline__ FbWave<Real, PVW> fb_wave(FbShared<Real, PVW, W>& sh)
 }
 
 // The wave's FP64 16 x 16 tiles of its last H steps (t[0] the latest), in the
-// D layout of the path precision's matrix-core product.  The four waves of a
-// block combine their tiles once per H steps.  H = 1 for the fixed grid (more
-// held tiles cost occupancy there: 15.4 / 16.8 ms for H = 1 / 2 and 4 on f4);
-// H = 4 for the jump-adapted adjoint (54.9 -> 51.1 ms on ja2).
+// D layout of the path precision's matrix-core product.  The waves of a block
+// combine their tiles once per H steps: H = 2 for independent particles on
+// the fixed grid (kFbAdjHold), 1 for rings (whose neighbour exchange needs the
+// flush's barriers every step) and the surrogate's forward, 4 for the
+// jump-adapted adjoint (54.9 -> 51.1 ms on ja2).
 template <int H>
 struct FbHist {
     fb_d4 t[H];
@@ -695,8 +696,20 @@ struct FbAdj {
 //                 w = gamma^n lam^v_{k+1} goes to LDS (double buffered by step
 //                 parity) and, after the block barriers of the step's
 //                 gradient flush, its neighbours add dt omega w to their lam^x_k.
+// Steps whose tiles a wave holds before the block flush (independent
+// particles), and the FP32 kernels held to five waves per SIMD (the matrix-core
+// accumulators then stay in vector registers).  On 2^20 x 500: FP32 10.8 ->
+// 10.7 ms, surrogate gradient 22.0 -> 21.0 ms, FP64 29.3 -> 28.9 ms; two held
+// steps without the five-wave bound fell to four waves (11.6 ms).
+constexpr int kFbAdjHold = 2;
+template <typename Real, int NVP, bool RING>
+constexpr int fb_adj_waves() {
+    constexpr int lds = (int)sizeof(FbShared<Real, fb_pvw<NVP>()>);
+    return !RING && sizeof(Real) == 4 ? (160 * 1024 / lds < 5 ? 160 * 1024 / lds : 5) : 1;
+}
+
 template <typename Real, int NVP, int G, bool SURR, bool RING, int TPB = kThreads>
-__global__ void __launch_bounds__(TPB)
+__global__ void __launch_bounds__(TPB, (fb_adj_waves<Real, NVP, RING>()))
 k_fb_adjoint(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __restrict__ zd,
              const Real* __restrict__ ks, const void* traj, double* __restrict__ apart) {
     static_assert(!(SURR && RING), "the surrogate gradient takes independent particles");
@@ -704,7 +717,9 @@ k_fb_adjoint(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __restrict
     __shared__ FbShared<Real, fb_pvw<NVP>(), TPB / 64> sh;
     __shared__ Real cw[RING ? 2 : 1][RING ? G * TPB : 1];
     auto wave = fb_wave(sh);
-    FbHist<1> hist;
+    // rings flush every step: the flush's barriers order the neighbour exchange
+    constexpr int H = RING ? 1 : kFbAdjHold;
+    FbHist<H> hist;
     hist.cnt = 0;
     const int N = a.N;
     FbAdj<Real> s[G];
@@ -800,7 +815,8 @@ k_fb_adjoint(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __restrict
             }
         }
         hist.push(fb_tile(wave));
-        fb_hist_flush<SURR>(sh, wave, hist, k, 1, N, a.nx, a.nv, apart);
+        if (hist.cnt == H || k == 0)
+            fb_hist_flush<SURR>(sh, wave, hist, k, 1, N, a.nx, a.nv, apart);
         if (RING && k >= 1) {
             const Real* wb = cw[k & 1];
             const Real dto = a.dt * a.omega;
@@ -1474,8 +1490,10 @@ static hipError_t fb_adjoint_t(const FbHost& p, const HostRun& r, const void* ta
                 FB_ADJ_G(NVP, 1, false, true);                                                    \
             }                                                                                     \
         } else if (G == 2) {                                                                      \
-            if (surr) FB_ADJ_G(NVP, 2, true, false);                                              \
-            else FB_ADJ_G(NVP, 2, false, false);                                                  \
+            if constexpr (sizeof(Real) == 8) {                                                    \
+                if (surr) FB_ADJ_G(NVP, 2, true, false);                                          \
+                else FB_ADJ_G(NVP, 2, false, false);                                              \
+            }                                                                                     \
         } else {                                                                                  \
             if (surr) FB_ADJ_G(NVP, 1, true, false);                                              \
             else FB_ADJ_G(NVP, 1, false, false);                                                  \
@@ -1505,12 +1523,15 @@ static hipError_t fb_forward_grad_t(const FbHost& p, const HostRun& r, const voi
     const unsigned nb = (unsigned)fb_partial_blocks(p, r);
 #define FB_FG(NVP)                                                                                \
     do {                                                                                          \
-        if (G == 2)                                                                               \
-            hipLaunchKernelGGL((k_fb_forward_grad<Real, NVP, 2>), dim3(nb), dim3(kThreads), 0, st, \
-                               a, tb + t.mu, tb + t.zd, tb + t.ks, cpart, apart);                 \
-        else                                                                                      \
-            hipLaunchKernelGGL((k_fb_forward_grad<Real, NVP, 1>), dim3(nb), dim3(kThreads), 0, st, \
-                               a, tb + t.mu, tb + t.zd, tb + t.ks, cpart, apart);                 \
+        if constexpr (sizeof(Real) == 8) {                                                        \
+            if (G == 2) {                                                                         \
+                hipLaunchKernelGGL((k_fb_forward_grad<Real, NVP, 2>), dim3(nb), dim3(kThreads), 0, \
+                                   st, a, tb + t.mu, tb + t.zd, tb + t.ks, cpart, apart);         \
+                break;                                                                            \
+            }                                                                                     \
+        }                                                                                         \
+        hipLaunchKernelGGL((k_fb_forward_grad<Real, NVP, 1>), dim3(nb), dim3(kThreads), 0, st, a, \
+                           tb + t.mu, tb + t.zd, tb + t.ks, cpart, apart);                        \
     } while (0)
     FB_DISPATCH_NVP(p.nvp, FB_FG);
 #undef FB_FG
