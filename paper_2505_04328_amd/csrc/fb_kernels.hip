@@ -135,13 +135,13 @@ __device__ __forceinline__ void shapes_v(const FbArgs<Real>& a, Real v, Real* pv
         pv[l] = bump(v - fma((Real)l, a.dvc, a.vc0), a.eps);
 }
 
-// Receives the shape-function values a step computes (the wave transposes of
-// the gradient reduction); NoSink drops them.
+// Receives the shape-function values a step computes, and the control u
+// (the wave transposes of the gradient reduction); NoSink drops them.
 struct NoSink {
     template <typename Real>
     __device__ __forceinline__ void put_x(int, Real) const {}
     template <typename Real, int NVP>
-    __device__ __forceinline__ void put_v(const Real*) const {}
+    __device__ __forceinline__ void put_v(const Real*, Real) const {}
 };
 
 // s + e = a + b exactly (Knuth's TwoSum; needs the build's -ffp-contract=off).
@@ -178,7 +178,7 @@ __device__ __forceinline__ Real fb_control(const FbArgs<Real>& a, const Real* __
         u = fma(bx, t, u);
         sink.put_x(i, bx);
     }
-    sink.template put_v<Real, NVP>(pv);
+    sink.template put_v<Real, NVP>(pv, u);
     return u;
 }
 
@@ -426,7 +426,6 @@ typedef double fb_d4 __attribute__((ext_vector_type(4)));
 typedef float fb_f4 __attribute__((ext_vector_type(4)));
 
 constexpr int kFbWaves = kThreads / 64;  // waves per block
-constexpr int kFbStride = kFbMaxGrid + 1;  // padded row stride of the transposes
 
 // The matrix-core product of the path precision.  FP64 paths use
 // v_mfma_f64_16x16x4f64; FP32 paths v_mfma_f32_16x16x4f32 (twice the rate):
@@ -455,19 +454,32 @@ struct FbMma<float> {
     static __device__ __forceinline__ int row(int ln, int r) { return 4 * (ln >> 4) + r; }
 };
 
+// Row stride (elements) of the transposes: 64 particles plus padding, so that
+// a row offset is 4 dwords mod 32 (FP32: 68 floats; FP64: 66 doubles = 132
+// dwords) and the 16-byte operand reads of the 16 rows of one pass fall in
+// distinct banks.
+template <typename Real>
+constexpr int fb_xs() { return sizeof(Real) == 4 ? 68 : 66; }
+
 // One wave's share of the per-step gradient sum over particles,
-// G_k[i][j] += sum_p b(x_p - x^i) w_p b(v_p - v^j): the particles' bump values
-// go through an LDS transpose (row p = particle, lane i + 16 kk reads A[i][kk] =
-// phx[4q + kk][i] w[4q + kk] and B[kk][i] = phv[4q + kk][i]) into sixteen
-// 16 x 16 x 4 matrix-core products per 64 particles, accumulated in four
-// independent chains.  The velocity transpose has rows of PVW >= NVP.
-template <typename Real, int PVW>
+// G_k[i][j] += sum_p b(x_p - x^i) b(v_p - v^j) w_p: the particles' bump values
+// go through LDS transposes (row = shape function, column = particle; lane p
+// writes column p) into sixteen 16 x 16 x 4 matrix-core products per 64
+// particles, accumulated in four independent chains.  The sum over particles
+// may take them in any order: product q takes particles 16 kk + q for K index
+// kk, so lane i + 16 kk reads A[i][kk] (row i of phx) and B[kk][i] (row i of
+// phv) for q = 0..15 as 16 consecutive elements, in 16-byte loads.  The weight
+// goes into the velocity values as they are written.  Rows of A past nx and
+// columns of B past the row count VR (read from row 0) hold finite leftovers;
+// they only reach entries of the product that no flush reads (i >= nx,
+// j >= nv).
+template <typename Real, int VR>
 struct FbWave {
     typedef typename FbMma<Real>::acc_t acc_t;
-    Real (*phx)[kFbStride];
-    Real (*phv)[PVW];
-    Real* wts;
-    int ln, ii;
+    static constexpr int XS = fb_xs<Real>();
+    Real (*phx)[XS];
+    Real (*phv)[XS];
+    int ln, ii, kb, rv;
     acc_t acc[4];
 
     __device__ __forceinline__ void clear() {
@@ -476,59 +488,73 @@ struct FbWave {
             acc[c] = acc_t{0, 0, 0, 0};
     }
     template <typename R>
-    __device__ __forceinline__ void put_x(int i, R b) const { phx[ln][i] = b; }
+    __device__ __forceinline__ void put_x(int i, R b) const { phx[i][ln] = b; }
+    // The velocity values times the particle's weight w.
     template <typename R, int NVP>
-    __device__ __forceinline__ void put_v(const R* pv) const {
+    __device__ __forceinline__ void put_vw(const R* pv, R w) const {
+        static_assert(NVP <= VR, "velocity rows hold NVP values");
 #pragma unroll
         for (int l = 0; l < NVP; ++l)
-            phv[ln][l] = pv[l];
+            phv[l][ln] = pv[l] * w;
     }
-    // Adds the wave's 64 particles (weight w each; rows i >= nx and columns
-    // j >= nvp are zero).
-    template <int NVP>
-    __device__ __forceinline__ void add(Real w, int nx) {
-        static_assert(NVP <= PVW, "velocity rows hold NVP values");
-        wts[ln] = w;
+    // Adds the wave's 64 particles as put since the last add.
+    __device__ __forceinline__ void add() {
+        typedef Real v16 __attribute__((ext_vector_type(16 / sizeof(Real))));
+        constexpr int E = 16 / sizeof(Real);  // elements per 16-byte load
         wave_lds_sync();
+        const v16* pa = (const v16*)&phx[ii][kb];
+        const v16* pb = (const v16*)&phv[rv][kb];
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int p = 4 * q + (ln >> 4);
-            const Real av = ii < nx ? phx[p][ii] * wts[p] : (Real)0;
-            const Real bv = ii < NVP ? phv[p][ii] : (Real)0;
-            acc[q & 3] = FbMma<Real>::mfma(av, bv, acc[q & 3]);
+        for (int c = 0; c < 16 / E; ++c) {
+            const v16 av = pa[c], bv = pb[c];
+#pragma unroll
+            for (int e = 0; e < E; ++e)
+                acc[(c * E + e) & 3] = FbMma<Real>::mfma(av[e], bv[e], acc[(c * E + e) & 3]);
         }
         wave_lds_sync();
     }
 };
 
-// Row stride of the velocity transpose for a compiled width NVP: the smallest
-// odd stride >= NVP, so a wave's writes of one column and the operand reads of
-// two rows fall in distinct banks, in as little LDS as possible (with NVP = 10
-// a block needs 29.7 KB in FP32, room for five blocks per CU).
-template <int NVP>
-constexpr int fb_pvw() { return NVP % 2 ? NVP : NVP + 1; }
-
-// The block's LDS for the reduction: per wave (W of them), the two transposes
-// and the weights; between steps the transposes hold the waves' FP64 tiles.
-template <typename Real, int PVW, int W = kFbWaves>
-struct FbShared {
-    static constexpr int waves = W;
-    Real phx[W][64][kFbStride];
-    Real phv[W][64][PVW];
-    Real wts[W][64];
+// Sink of the surrogate's forward step: the wave's transposes, the velocity
+// values weighted by alpha u (scale = alpha, or 0 for an empty slot).
+template <typename Real, int VR>
+struct FbControlSink {
+    const FbWave<Real, VR>& w;
+    Real scale;
+    template <typename R>
+    __device__ __forceinline__ void put_x(int i, R b) const { w.put_x(i, b); }
+    template <typename R, int NVP>
+    __device__ __forceinline__ void put_v(const R* pv, R u) const {
+        w.template put_vw<R, NVP>(pv, scale * u);
+    }
 };
 
-template <typename Real, int PVW, int W>
-__device__ __forceinline__ FbWave<Real, PVW> fb_wave(FbShared<Real, PVW, W>& sh) {
-    static_assert(sizeof(Real) * 64 * kFbStride >= sizeof(double) * kFbMaxGrid * kFbMaxGrid,
+// Rows of the velocity transpose for a compiled width NVP.
+template <int NVP>
+constexpr int fb_vrows() { return NVP; }
+
+// The block's LDS for the reduction: per wave (W of them), the two transposes
+// (16 position rows, VR velocity rows); between steps they hold the waves'
+// FP64 tiles.
+template <typename Real, int VR, int W = kFbWaves>
+struct FbShared {
+    static constexpr int waves = W;
+    alignas(16) Real phx[W][kFbMaxGrid][fb_xs<Real>()];
+    alignas(16) Real phv[W][VR][fb_xs<Real>()];
+};
+
+template <typename Real, int VR, int W>
+__device__ __forceinline__ FbWave<Real, VR> fb_wave(FbShared<Real, VR, W>& sh) {
+    static_assert(sizeof(Real) * kFbMaxGrid * fb_xs<Real>() >= sizeof(double) * kFbMaxGrid * kFbMaxGrid,
                   "a wave's transpose buffer must hold its 16 x 16 FP64 tile");
-    FbWave<Real, PVW> w;
+    FbWave<Real, VR> w;
     const int wv = threadIdx.x >> 6;
     w.phx = sh.phx[wv];
     w.phv = sh.phv[wv];
-    w.wts = sh.wts[wv];
     w.ln = threadIdx.x & 63;
     w.ii = w.ln & 15;
+    w.kb = 16 * (w.ln >> 4);
+    w.rv = w.ii < VR ? w.ii : 0;
     w.clear();
     return w;
 }
@@ -565,9 +591,11 @@ __device__ __forceinline__ fb_d4 fb_tile(const FbWave<Real, PVW>& w) {
 // Number of 16 x 16 FP64 tiles a wave's transposes hold: in phx, in phv.
 constexpr int kFbTile = kFbMaxGrid * kFbMaxGrid;
 template <typename Real>
-constexpr int fb_tiles_x() { return (int)(sizeof(Real) * 64 * kFbStride / (sizeof(double) * kFbTile)); }
-template <typename Real, int PVW>
-constexpr int fb_tiles_v() { return (int)(sizeof(Real) * 64 * PVW / (sizeof(double) * kFbTile)); }
+constexpr int fb_tiles_x() {
+    return (int)(sizeof(Real) * kFbMaxGrid * fb_xs<Real>() / (sizeof(double) * kFbTile));
+}
+template <typename Real, int VR>
+constexpr int fb_tiles_v() { return (int)(sizeof(Real) * VR * fb_xs<Real>() / (sizeof(double) * kFbTile)); }
 
 // LDS home of tile s of wave wv during a flush (the wave's transpose buffers,
 // free between steps).
@@ -623,7 +651,7 @@ __global__ void __launch_bounds__(kThreads)
 k_fb_forward_grad(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __restrict__ zd,
                   const Real* __restrict__ ks, double* __restrict__ cpart,
                   double* __restrict__ apart) {
-    __shared__ FbShared<Real, fb_pvw<NVP>()> sh;
+    __shared__ FbShared<Real, fb_vrows<NVP>()> sh;
     __shared__ double red[kThreads];
     auto wave = fb_wave(sh);
     FbHist<1> hist;
@@ -648,9 +676,10 @@ k_fb_forward_grad(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __res
         wave.clear();
 #pragma unroll
         for (int j = 0; j < G; ++j) {
+            const FbControlSink<Real, fb_vrows<NVP>()> sink{wave, act[j] ? a.alpha : (Real)0};
             const Real u = fb_step<Real, NVP>(a, mk, ks, (uint32_t)m[j], k, x[j], v[j], cx[j], cv[j],
-                                              (Real)0, wave);
-            wave.template add<NVP>(act[j] ? a.alpha * u : (Real)0, a.nx);
+                                              (Real)0, sink);
+            wave.add();
             acc[j] += (double)(a.hadt * u * u);
             acc[j] += (double)(a.dt * track(a, x[j], v[j], zd + 2 * (k + 1)));
             fb_dump(a, a.dX, k + 1, m[j], x[j], v[j]);
@@ -704,7 +733,7 @@ struct FbAdj {
 constexpr int kFbAdjHold = 2;
 template <typename Real, int NVP, bool RING>
 constexpr int fb_adj_waves() {
-    constexpr int lds = (int)sizeof(FbShared<Real, fb_pvw<NVP>()>);
+    constexpr int lds = (int)sizeof(FbShared<Real, fb_vrows<NVP>()>);
     return !RING && sizeof(Real) == 4 ? (160 * 1024 / lds < 5 ? 160 * 1024 / lds : 5) : 1;
 }
 
@@ -714,7 +743,7 @@ k_fb_adjoint(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __restrict
              const Real* __restrict__ ks, const void* traj, double* __restrict__ apart) {
     static_assert(!(SURR && RING), "the surrogate gradient takes independent particles");
     static_assert(RING || TPB == kThreads, "independent particles run in blocks of 256");
-    __shared__ FbShared<Real, fb_pvw<NVP>(), TPB / 64> sh;
+    __shared__ FbShared<Real, fb_vrows<NVP>(), TPB / 64> sh;
     __shared__ Real cw[RING ? 2 : 1][RING ? G * TPB : 1];
     auto wave = fb_wave(sh);
     // rings flush every step: the flush's barriers order the neighbour exchange
@@ -765,6 +794,16 @@ k_fb_adjoint(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __restrict
                     st.vn = __builtin_nontemporal_load(row[j] + (size_t)(k - 1) * 2 * kThreads + kThreads);
                 }
             }
+            Real gn = 1;
+            {
+                uint32_t w[4];
+                philox4x32_10<true>((uint32_t)m[j], (uint32_t)k, a.iter, 0u, a.key0, a.key1, w);
+                const int n = poisson_count(poisson_word(w), a.thr);
+                if (n != 0) {
+                    Real svn;
+                    ks_factors(ks, n, gn, svn);
+                }
+            }
             Real pv[NVP], dpv[NVP];
 #pragma unroll
             for (int l = 0; l < NVP; ++l)
@@ -786,17 +825,9 @@ k_fb_adjoint(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __restrict
                 uv = fma(bx, sv, uv);
                 wave.put_x(i, bx);
             }
-            wave.template put_v<Real, NVP>(pv);
-            uint32_t w[4];
-            philox4x32_10<true>((uint32_t)m[j], (uint32_t)k, a.iter, 0u, a.key0, a.key1, w);
-            const int n = poisson_count(poisson_word(w), a.thr);
-            Real gn = 1;
-            if (n != 0) {
-                Real svn;
-                ks_factors(ks, n, gn, svn);
-            }
             const Real wk = SURR ? gn * st.lv : fma(a.alpha, u, gn * st.lv);
-            wave.template add<NVP>(act[j] ? wk : (Real)0, a.nx);
+            wave.template put_vw<Real, NVP>(pv, act[j] ? wk : (Real)0);
+            wave.add();
             if (RING)
                 cw[k & 1][j * TPB + threadIdx.x] = gn * st.lv;
             if (k >= 1) {
@@ -1036,8 +1067,8 @@ template <typename Real, int NVP>
 __global__ void __launch_bounds__(kThreads)
 k_fb_adjoint_adapted(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __restrict__ zd,
                      const void* traj, double* __restrict__ apart) {
-    // four held tiles: FP32 needs the full 17-wide velocity rows for them
-    __shared__ FbShared<Real, sizeof(Real) == 4 ? kFbStride : fb_pvw<NVP>()> sh;
+    // four held tiles: FP32 needs all 16 velocity rows for them
+    __shared__ FbShared<Real, sizeof(Real) == 4 ? kFbMaxGrid : fb_vrows<NVP>()> sh;
     auto wave = fb_wave(sh);
     FbHist<4> hist;
     hist.cnt = 0;
@@ -1140,9 +1171,9 @@ k_fb_adjoint_adapted(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __
                 uv = fma(bx, sv, uv);
                 wave.put_x(i, bx);
             }
-            wave.template put_v<Real, NVP>(pv);
             const Real wk = n == 0 ? fma(a.alpha, u, lvm) : (d / a.dt) * fma(a.alpha, u, lvm);
-            wave.template add<NVP>(mine && sl.act ? wk : (Real)0, a.nx);
+            wave.template put_vw<Real, NVP>(pv, mine && sl.act ? wk : (Real)0);
+            wave.add();
             if (mine) {
                 const Real au = a.alpha * u;
                 lx = fma(d, fma(au, ux, (ux - a.eta) * lvm), lxm);
@@ -1391,7 +1422,7 @@ template <typename Real>
 constexpr int fb_ring_fwd_threads() { return sizeof(Real) == 4 ? 1024 : 512; }
 template <typename Real, int NVP>
 constexpr int fb_ring_adj_lds(int tpb) {
-    return (int)sizeof(FbShared<Real, fb_pvw<NVP>(), 16>) / 16 * (tpb / 64) + 2 * kFbRingSlots * (int)sizeof(Real);
+    return (int)sizeof(FbShared<Real, fb_vrows<NVP>(), 16>) / 16 * (tpb / 64) + 2 * kFbRingSlots * (int)sizeof(Real);
 }
 template <typename Real, int NVP>
 constexpr int fb_ring_adj_threads() {
