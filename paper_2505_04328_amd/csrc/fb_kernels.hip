@@ -161,13 +161,17 @@ __device__ __forceinline__ float two_sum(float a, float b, float& e) {
 // update plainly.  Returns the control u_k; the bump values go to the sink.
 // The feedback control u = sum_i b(x - x^i) sum_l mu_il b(v - v^l); the bump
 // values go to the sink.
-template <typename Real, int NVP, typename Sink = NoSink>
+template <typename Real, int NVP, typename Sink = NoSink, int RU = 2>
 __device__ __forceinline__ Real fb_control(const FbArgs<Real>& a, const Real* __restrict__ mk,
                                            Real x, Real v, const Sink& sink = Sink()) {
     Real pv[NVP];
     shapes_v<Real, NVP>(a, v, pv);
     Real u = 0;
-#pragma unroll 1
+    // RU rows per iteration: the next row's scalar loads overlap this row's
+    // work (two: f4 forward 5.03 -> 4.95 ms, adjoint 9.85 -> 9.61 ms; five
+    // ran out of scalar registers; the ring forward, held to 64 vector
+    // registers, keeps one: 5.7 against 5.9 ms)
+#pragma unroll RU
     for (int i = 0; i < a.nx; ++i) {
         const Real bx = bump(x - fma((Real)i, a.dxc, a.xc0), a.eps);
         const Real* rw = mk + i * NVP;
@@ -182,12 +186,12 @@ __device__ __forceinline__ Real fb_control(const FbArgs<Real>& a, const Real* __
     return u;
 }
 
-template <typename Real, int NVP, typename Sink = NoSink>
+template <typename Real, int NVP, typename Sink = NoSink, int RU = 2>
 __device__ __forceinline__ Real fb_step(const FbArgs<Real>& a, const Real* __restrict__ mk,
                                         const Real* __restrict__ ks, uint32_t m, int k, Real& x,
                                         Real& v, Real& cx, Real& cv, Real cpl,
                                         const Sink& sink = Sink()) {
-    const Real u = fb_control<Real, NVP, Sink>(a, mk, x, v, sink);
+    const Real u = fb_control<Real, NVP, Sink, RU>(a, mk, x, v, sink);
     uint32_t w[4];
     philox4x32_10<true>(m, (uint32_t)k, a.iter, 0u, a.key0, a.key1, w);
     const Real R = bm_radius(w[0], (Real)0);
@@ -385,8 +389,10 @@ k_fb_forward(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __restrict
         }
 #pragma unroll
         for (int j = 0; j < G; ++j) {
-            const Real u = fb_step<Real, NVP>(a, mu + (size_t)k * a.nx * NVP, ks, sl[j].p, k, x[j],
-                                              v[j], cx[j], cv[j], RING ? cpl[j] : (Real)0);
+            constexpr int RU = TPB == 1024 ? 1 : 2;
+            const Real u = fb_step<Real, NVP, NoSink, RU>(a, mu + (size_t)k * a.nx * NVP, ks, sl[j].p,
+                                                          k, x[j], v[j], cx[j], cv[j],
+                                                          RING ? cpl[j] : (Real)0);
             acc[j] += (double)(a.hadt * u * u);
             acc[j] += (double)(a.dt * track(a, x[j], v[j], zd + 2 * (k + 1)));
             if (STORE) {
@@ -809,7 +815,7 @@ k_fb_adjoint(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __restrict
             for (int l = 0; l < NVP; ++l)
                 pv[l] = bump_d(st.v - fma((Real)l, a.dvc, a.vc0), a.eps, dpv[l]);
             Real u = 0, ux = 0, uv = 0;
-#pragma unroll 1
+#pragma unroll 2
             for (int i = 0; i < a.nx; ++i) {
                 Real dbx;
                 const Real bx = bump_d(st.x - fma((Real)i, a.dxc, a.xc0), a.eps, dbx);
@@ -1155,7 +1161,7 @@ k_fb_adjoint_adapted(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __
             for (int l = 0; l < NVP; ++l)
                 pv[l] = bump_d(v - fma((Real)l, a.dvc, a.vc0), a.eps, dpv[l]);
             Real u = 0, ux = 0, uv = 0;
-#pragma unroll 1
+#pragma unroll 2
             for (int i = 0; i < a.nx; ++i) {
                 Real dbx;
                 const Real bx = bump_d(x - fma((Real)i, a.dxc, a.xc0), a.eps, dbx);
