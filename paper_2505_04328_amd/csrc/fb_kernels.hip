@@ -435,10 +435,10 @@ constexpr int kFbWaves = kThreads / 64;  // waves per block
 
 // The matrix-core product of the path precision.  FP64 paths use
 // v_mfma_f64_16x16x4f64; FP32 paths v_mfma_f32_16x16x4f32 (twice the rate):
-// its FP32 products and sums cover one chain of at most 16 G particles per step
-// (G particles per lane), whose rounding averages out over the 2^20-particle
-// sum far below the gradient's 1e-6 bound; the chains, the waves and the blocks
-// are summed in FP64.  Both take A[i][kk] and B[kk][j] in lane i + 16 kk; row()
+// its FP32 products and sums cover one chain of a wave's 64 G particles per
+// step (G particles per lane), whose rounding averages out over the
+// 2^20-particle sum far below the gradient's 1e-6 bound; the waves and the
+// blocks are summed in FP64.  Both take A[i][kk] and B[kk][j] in lane i + 16 kk; row()
 // gives the row of D held in register r of lane ln (the column is ln mod 16).
 // The layouts were measured on the device with one-hot operands.
 template <typename Real>
@@ -471,7 +471,7 @@ constexpr int fb_xs() { return sizeof(Real) == 4 ? 68 : 66; }
 // G_k[i][j] += sum_p b(x_p - x^i) b(v_p - v^j) w_p: the particles' bump values
 // go through LDS transposes (row = shape function, column = particle; lane p
 // writes column p) into sixteen 16 x 16 x 4 matrix-core products per 64
-// particles, accumulated in four independent chains.  The sum over particles
+// particles, accumulated in one chain.  The sum over particles
 // may take them in any order: product q takes particles 16 kk + q for K index
 // kk, so lane i + 16 kk reads A[i][kk] (row i of phx) and B[kk][i] (row i of
 // phv) for q = 0..15 as 16 consecutive elements, in 16-byte loads.  The weight
@@ -486,13 +486,13 @@ struct FbWave {
     Real (*phx)[XS];
     Real (*phv)[XS];
     int ln, ii, kb, rv;
-    acc_t acc[4];
+    // one chain: dependent products issue back to back on the matrix core,
+    // and the tile then needs no sum of chains (four independent chains summed
+    // in FP64 per step: f4 FP32 adjoint 9.64 against 9.41 ms, ja2 20.7
+    // against 18.7 ms)
+    acc_t acc;
 
-    __device__ __forceinline__ void clear() {
-#pragma unroll
-        for (int c = 0; c < 4; ++c)
-            acc[c] = acc_t{0, 0, 0, 0};
-    }
+    __device__ __forceinline__ void clear() { acc = acc_t{0, 0, 0, 0}; }
     template <typename R>
     __device__ __forceinline__ void put_x(int i, R b) const { phx[i][ln] = b; }
     // The velocity values times the particle's weight w.
@@ -515,7 +515,7 @@ struct FbWave {
             const v16 av = pa[c], bv = pb[c];
 #pragma unroll
             for (int e = 0; e < E; ++e)
-                acc[(c * E + e) & 3] = FbMma<Real>::mfma(av[e], bv[e], acc[(c * E + e) & 3]);
+                acc = FbMma<Real>::mfma(av[e], bv[e], acc);
         }
         wave_lds_sync();
     }
@@ -584,13 +584,13 @@ struct FbHist {
     }
 };
 
-// The sum of the wave's four chains, in FP64.
+// The wave's sums, in FP64.
 template <typename Real, int PVW>
 __device__ __forceinline__ fb_d4 fb_tile(const FbWave<Real, PVW>& w) {
     fb_d4 t;
 #pragma unroll
     for (int r = 0; r < 4; ++r)
-        t[r] = ((double)w.acc[0][r] + (double)w.acc[1][r]) + ((double)w.acc[2][r] + (double)w.acc[3][r]);
+        t[r] = (double)w.acc[r];
     return t;
 }
 
