@@ -59,13 +59,16 @@ ADJ_SLOTS_PER_PATH_STEP = 12
 #          Philox 77 + Poisson 4, Box-Muller both halves 27, Euler 6, FP64 cost
 #          (control and tracking terms, one exp) 18                      = 502
 # adjoint  20 bumps with derivatives (3 more products each: 16) 320, control,
-#          u_x and u_v (two dot products per row) 230, jump count regenerated
-#          (Philox 77 + Poisson 4), gradient weight, adjoint update and the
-#          tracking gradient (one exp) 24                                 = 655
-# plus, on the FP64 matrix cores, 2 nx nv = 200 flops per particle-step for the
+#          u_x and u_v (two dot products per row) 230, gradient weight,
+#          adjoint update and the tracking gradient (one exp) 24          = 574
+#          (the jump count is read from the trajectory, one byte the forward
+#          stored; regenerating it, as the jump-adapted and the surrogate
+#          adjoints do, adds Philox 77 + Poisson 4                        = 655)
+# plus, on the matrix cores, 2 nx nv = 200 flops per particle-step for the
 # gradient's outer products.
 FB_FWD_SLOTS = 502
-FB_ADJ_SLOTS = 655
+FB_ADJ_SLOTS = 574
+FB_ADJ_REGEN_SLOTS = 655
 # Coupled rings (Section 6.4, ring2: 512 rings of 2000 particles, 500 steps):
 # the forward adds the ring force omega (2x - x_l - x_r) (4 slots) and the
 # ellipse cost q = x^2/ax^2 + v^2/av^2 - 1, q^2 (2 more than the tracking
@@ -73,7 +76,7 @@ FB_ADJ_SLOTS = 655
 # (w_l + w_r) (2) and the ellipse gradient (3 more than the tracking one).  The
 # neighbour exchange itself is LDS traffic and barriers, not VALU work.
 RING_FWD_SLOTS = 508
-RING_ADJ_SLOTS = 661
+RING_ADJ_SLOTS = 580
 # Jump-adapted grid (ja2 / ja3): the fixed-grid work per particle-step plus,
 # per jump (sigma dt of them per particle-step), one more sub-step: forward
 # control 370, Euler 6, the sub-step's Philox block and Box-Muller 104, its
@@ -303,7 +306,7 @@ def adapted_section(args, time_calls, dev):
             del e
             torch.cuda.empty_cache()
         fs = FB_FWD_SLOTS + sdt * ADAPT_FWD_EXTRA
-        as_ = FB_ADJ_SLOTS + sdt * ADAPT_ADJ_EXTRA
+        as_ = FB_ADJ_REGEN_SLOTS + sdt * ADAPT_ADJ_EXTRA
         t_f, t_a = o["fp32"]["forward_ms"] * 1e-3, o["fp32"]["adjoint_ms"] * 1e-3
         o["roofline"] = {"bound": "alu", "kernel": "k_fb_adjoint_adapted<float,10>",
                          "achieved": as_ * ps / t_a / 1e12, "peak": VALU_PEAK_SLOTS / 1e12,

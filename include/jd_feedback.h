@@ -142,10 +142,15 @@ typedef struct jd_fb_problem {
  * With np = 1 particle m sits in slot m.  With np > 1 a workgroup holds
  * R = floor(256 G / np) rings in 256 G slots (G = 1 for np <= 256, else 8):
  * particle j of ring r sits in slot (r / R) 256 G + (r % R) np + j.  On the
- * jump-adapted grid the buffer continues with the states after each of a
- * slot's first 32 jumps (component c after jump e of slot s: element
- * T + ((s / 256) 32 + e) 2 256 + c 256 + (s % 256), T the trajectory's
- * length) and one int32 jump count per slot, which the adjoint reads. */
+ * fixed grid the buffer continues with one byte per slot and step, the jump
+ * count n_k of step k = 0..N-1 of slot s at byte
+ * B + ((s / 256) N + k) 256 + (s % 256), B the byte length of the states;
+ * jd_fb_forward writes them and jd_fb_adjoint reads them instead of
+ * regenerating the draws.  On the jump-adapted grid the buffer continues with
+ * the states after each of a slot's first 32 jumps (component c after jump e
+ * of slot s: element T + ((s / 256) 32 + e) 2 256 + c 256 + (s % 256), T the
+ * trajectory's length) and one int32 jump count per slot, which the adjoint
+ * reads. */
 size_t jd_fb_workspace_bytes(const jd_fb_problem* prob, const jd_run* run);
 size_t jd_fb_traj_bytes(const jd_fb_problem* prob, const jd_run* run);
 

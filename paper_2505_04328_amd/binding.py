@@ -357,7 +357,13 @@ class FbEngine:
         self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
         esz = 4 if precision == "fp32" else 8
         self.particles = M * self.p.np
-        self.nblk = self.traj_bytes // (esz * (self.p.N + 1) * 2 * 256)
+        npr = self.p.np
+        if npr == 1:
+            self.nblk = (M + 255) // 256
+        else:
+            G = 1 if npr <= 256 else 8
+            R = 256 * G // npr
+            self.nblk = (M + R - 1) // R * G
         self.traj = torch.empty(self.traj_bytes // esz, dtype=self.rdtype, device=self.device)
 
     def slots(self) -> np.ndarray:
@@ -385,7 +391,8 @@ class FbEngine:
     def trajectory(self):
         """z_0..z_N as an (N+1, 2, particles) tensor (a copy of the blocked buffer)."""
         torch = _torch()
-        t = self.traj.view(self.nblk, self.p.N + 1, 2, 256).permute(1, 2, 0, 3)
+        n = self.nblk * (self.p.N + 1) * 2 * 256  # the states; jump data follows
+        t = self.traj[:n].view(self.nblk, self.p.N + 1, 2, 256).permute(1, 2, 0, 3)
         t = t.reshape(self.p.N + 1, 2, self.nblk * 256)
         if self.p.np == 1:
             return t[:, :, :self.M]

@@ -190,13 +190,15 @@ template <typename Real, int NVP, typename Sink = NoSink, int RU = 2>
 __device__ __forceinline__ Real fb_step(const FbArgs<Real>& a, const Real* __restrict__ mk,
                                         const Real* __restrict__ ks, uint32_t m, int k, Real& x,
                                         Real& v, Real& cx, Real& cv, Real cpl,
-                                        const Sink& sink = Sink()) {
+                                        const Sink& sink = Sink(), int* n_out = nullptr) {
     const Real u = fb_control<Real, NVP, Sink, RU>(a, mk, x, v, sink);
     uint32_t w[4];
     philox4x32_10<true>(m, (uint32_t)k, a.iter, 0u, a.key0, a.key1, w);
     const Real R = bm_radius(w[0], (Real)0);
     const Real ub = unit_uniform<Real>(w[1]);
     const int n = poisson_count(poisson_word(w), a.thr);
+    if (n_out != nullptr)
+        *n_out = n;
     Real xn, vs, ex = 0, ev = 0;
     if constexpr (sizeof(Real) == 4) {
         xn = two_sum(x, fma(a.dt, v, fma(a.sqb1, bm_cos(R, ub), cx)), ex);
@@ -320,6 +322,18 @@ __device__ __forceinline__ Real* fb_slot_row(const void* traj, int N, int64_t nb
     blk = blk < nblk ? blk : nblk - 1;
     return (Real*)const_cast<void*>(traj) + (size_t)blk * (N + 1) * 2 * kThreads + (q % kThreads);
 }
+// The fixed grid's jump counts follow the states of all nblk trajectory
+// blocks: one byte per particle and step, step k of block b's lane l at byte
+// (b N + k) 256 + l.  The adjoint reads them instead of regenerating the
+// draws.  Same slot mapping as fb_slot_row.
+template <typename Real, int G, int TPB>
+__device__ __forceinline__ uint8_t* fb_slot_counts(const void* traj, int N, int64_t nblk, int g) {
+    const int q = g * TPB + (int)threadIdx.x;
+    int64_t blk = (int64_t)blockIdx.x * (G * TPB / kThreads) + q / kThreads;
+    blk = blk < nblk ? blk : nblk - 1;
+    uint8_t* base = (uint8_t*)((Real*)const_cast<void*>(traj) + (size_t)nblk * (N + 1) * 2 * kThreads);
+    return base + (size_t)blk * N * kThreads + (q % kThreads);
+}
 
 // ---------------------------------------------------------------------------
 template <typename Real>
@@ -362,11 +376,13 @@ k_fb_forward(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __restrict
     double acc[G];
     FbSlot sl[G];
     Real* row[G];
+    uint8_t* cnt[G];
 #pragma unroll
     for (int j = 0; j < G; ++j) {
         sl[j] = fb_slot<G, Real, TPB>(a, j);
         fb_initial(a, sl[j].p, x[j], v[j]);
         row[j] = STORE ? fb_slot_row<Real, G, TPB>(traj, a.N, a.nblk, j) : nullptr;
+        cnt[j] = STORE ? fb_slot_counts<Real, G, TPB>(traj, a.N, a.nblk, j) : nullptr;
         if (STORE) {
             __builtin_nontemporal_store(x[j], row[j]);
             __builtin_nontemporal_store(v[j], row[j] + kThreads);
@@ -390,15 +406,17 @@ k_fb_forward(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __restrict
 #pragma unroll
         for (int j = 0; j < G; ++j) {
             constexpr int RU = TPB == 1024 ? 1 : 2;
+            int n;
             const Real u = fb_step<Real, NVP, NoSink, RU>(a, mu + (size_t)k * a.nx * NVP, ks, sl[j].p,
                                                           k, x[j], v[j], cx[j], cv[j],
-                                                          RING ? cpl[j] : (Real)0);
+                                                          RING ? cpl[j] : (Real)0, NoSink(), &n);
             acc[j] += (double)(a.hadt * u * u);
             acc[j] += (double)(a.dt * track(a, x[j], v[j], zd + 2 * (k + 1)));
             if (STORE) {
                 Real* r = row[j] + (size_t)(k + 1) * 2 * kThreads;
                 __builtin_nontemporal_store(x[j], r);
                 __builtin_nontemporal_store(v[j], r + kThreads);
+                __builtin_nontemporal_store((uint8_t)n, cnt[j] + (size_t)k * kThreads);
             }
             fb_dump(a, a.dX, k + 1, sl[j].p, x[j], v[j]);
         }
@@ -714,6 +732,7 @@ template <typename Real>
 struct FbAdj {
     Real x, v;    // z_k (current step)
     Real xn, vn;  // z_{k-1}, loaded one step ahead (stored trajectory)
+    int nn;       // jump count of step k, loaded one step ahead (stored)
     Real lx, lv;  // lam_{k+1} on entry to step k
 };
 
@@ -759,6 +778,7 @@ k_fb_adjoint(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __restrict
     const int N = a.N;
     FbAdj<Real> s[G];
     const Real* row[G];
+    const uint8_t* cnt[G];
     bool act[G];
     int64_t m[G];
     FbSlot sl[G];
@@ -769,9 +789,12 @@ k_fb_adjoint(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __restrict
         act[j] = sl[j].act;
         if (SURR) {
             row[j] = nullptr;
+            cnt[j] = nullptr;
             fb_surrogate(a, zd, (uint32_t)m[j], N, s[j].x, s[j].v);
         } else {
             row[j] = fb_slot_row<Real, G, TPB>(traj, N, a.nblk, j);
+            cnt[j] = fb_slot_counts<Real, G, TPB>(traj, N, a.nblk, j);
+            s[j].nn = __builtin_nontemporal_load(cnt[j] + (size_t)(N - 1) * kThreads);
             s[j].x = __builtin_nontemporal_load(row[j] + (size_t)N * 2 * kThreads);
             s[j].v = __builtin_nontemporal_load(row[j] + (size_t)N * 2 * kThreads + kThreads);
             s[j].xn = __builtin_nontemporal_load(row[j] + (size_t)(N - 1) * 2 * kThreads);
@@ -802,9 +825,16 @@ k_fb_adjoint(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __restrict
             }
             Real gn = 1;
             {
-                uint32_t w[4];
-                philox4x32_10<true>((uint32_t)m[j], (uint32_t)k, a.iter, 0u, a.key0, a.key1, w);
-                const int n = poisson_count(poisson_word(w), a.thr);
+                int n;
+                if (SURR) {
+                    uint32_t w[4];
+                    philox4x32_10<true>((uint32_t)m[j], (uint32_t)k, a.iter, 0u, a.key0, a.key1, w);
+                    n = poisson_count(poisson_word(w), a.thr);
+                } else {
+                    n = st.nn;
+                    if (k >= 1)
+                        st.nn = __builtin_nontemporal_load(cnt[j] + (size_t)(k - 1) * kThreads);
+                }
                 if (n != 0) {
                     Real svn;
                     ks_factors(ks, n, gn, svn);

@@ -240,11 +240,12 @@ def test_fb_workspace_and_traj_sizes(L):
     M = 1 << 20
     run = B.make_run(M, precision="fp32")
     tb = L.jd_fb_traj_bytes(C.byref(pr.st), C.byref(run))
-    assert tb == (p.N + 1) * 2 * M * 4
+    # z_0..z_N, then one jump-count byte per particle and step
+    assert tb == (p.N + 1) * 2 * M * 4 + p.N * M
     ws = L.jd_fb_workspace_bytes(C.byref(pr.st), C.byref(run))
     assert ws >= (M // 256) * p.N * p.L * 8  # per-block FP64 gradient partials
     run7 = B.make_run(7, precision="fp64")
-    assert L.jd_fb_traj_bytes(C.byref(pr.st), C.byref(run7)) == (p.N + 1) * 2 * 256 * 8
+    assert L.jd_fb_traj_bytes(C.byref(pr.st), C.byref(run7)) == (p.N + 1) * 2 * 256 * 8 + p.N * 256
     rec = B.make_run(1000, precision="fp32", mode="recompute", K=10)
     assert L.jd_fb_traj_bytes(C.byref(pr.st), C.byref(rec)) == 0
 
@@ -272,7 +273,8 @@ def test_fb_ring_traj_sizes(L, np_, M, rows):
     p = wl.ring_problem(N=10, T=1.0, np_=np_)
     pr = _FbDummy(p)
     run = B.make_run(M, precision="fp32")
-    assert L.jd_fb_traj_bytes(C.byref(pr.st), C.byref(run)) == (p.N + 1) * 2 * rows * 256 * 4
+    assert L.jd_fb_traj_bytes(C.byref(pr.st), C.byref(run)) == ((p.N + 1) * 2 * rows * 256 * 4
+                                                                + p.N * rows * 256)
     assert L.jd_fb_workspace_bytes(C.byref(pr.st), C.byref(run)) >= rows * p.N * p.L * 8 // (
         1 if np_ <= 256 else 8)
     # the ellipse cost needs no target outside the surrogate mode
