@@ -62,13 +62,12 @@ ADJ_SLOTS_PER_PATH_STEP = 12
 #          u_x and u_v (two dot products per row) 230, gradient weight,
 #          adjoint update and the tracking gradient (one exp) 24          = 574
 #          (the jump count is read from the trajectory, one byte the forward
-#          stored; regenerating it, as the jump-adapted and the surrogate
-#          adjoints do, adds Philox 77 + Poisson 4                        = 655)
+#          stored; regenerating it, as the surrogate adjoint does, adds
+#          Philox 77 + Poisson 4                                          = 655)
 # plus, on the matrix cores, 2 nx nv = 200 flops per particle-step for the
 # gradient's outer products.
 FB_FWD_SLOTS = 502
 FB_ADJ_SLOTS = 574
-FB_ADJ_REGEN_SLOTS = 655
 # Coupled rings (Section 6.4, ring2: 512 rings of 2000 particles, 500 steps):
 # the forward adds the ring force omega (2x - x_l - x_r) (4 slots) and the
 # ellipse cost q = x^2/ax^2 + v^2/av^2 - 1, q^2 (2 more than the tracking
@@ -306,7 +305,7 @@ def adapted_section(args, time_calls, dev):
             del e
             torch.cuda.empty_cache()
         fs = FB_FWD_SLOTS + sdt * ADAPT_FWD_EXTRA
-        as_ = FB_ADJ_REGEN_SLOTS + sdt * ADAPT_ADJ_EXTRA
+        as_ = FB_ADJ_SLOTS + sdt * ADAPT_ADJ_EXTRA
         t_f, t_a = o["fp32"]["forward_ms"] * 1e-3, o["fp32"]["adjoint_ms"] * 1e-3
         o["roofline"] = {"bound": "alu", "kernel": "k_fb_adjoint_adapted<float,10>",
                          "achieved": as_ * ps / t_a / 1e12, "peak": VALU_PEAK_SLOTS / 1e12,

@@ -149,8 +149,10 @@ typedef struct jd_fb_problem {
  * regenerating the draws.  On the jump-adapted grid the buffer continues with
  * the states after each of a slot's first 32 jumps (component c after jump e
  * of slot s: element T + ((s / 256) 32 + e) 2 256 + c 256 + (s % 256), T the
- * trajectory's length) and one int32 jump count per slot, which the adjoint
- * reads. */
+ * trajectory's length), one int32 jump count per slot, and then one byte per
+ * slot and interval k, the interval's jump count (byte
+ * C + ((s / 256) N + k) 256 + (s % 256), C where the int32 counts end), all
+ * of which the adjoint reads. */
 size_t jd_fb_workspace_bytes(const jd_fb_problem* prob, const jd_run* run);
 size_t jd_fb_traj_bytes(const jd_fb_problem* prob, const jd_run* run);
 

@@ -964,10 +964,14 @@ __device__ __forceinline__ void fb_target(const Real* __restrict__ zk, Real f, R
 // jumps than entries has the rest recomputed by the adjoint.
 constexpr int kFbJumpCap = kFbJumpStates;
 
+// After the counts: one byte per slot and interval, the interval's jump count
+// (interval k of block b's lane l at byte (b N + k) 256 + l), so that the
+// adjoint need not regenerate it.
 template <typename Real>
 struct FbJumps {
     Real* st;        // slot's entry 0, x (entry e component c at st[(2 e + c) 256])
     int32_t* count;  // slot's jump count
+    uint8_t* per;    // slot's count of interval 0 (interval k at per[k 256])
 };
 
 template <typename Real>
@@ -975,8 +979,10 @@ __device__ __forceinline__ FbJumps<Real> fb_jumps(void* traj, int N, int64_t nbl
     FbJumps<Real> j;
     Real* base = (Real*)traj + (size_t)nblk * (N + 1) * 2 * kThreads;
     j.st = base + (size_t)blockIdx.x * kFbJumpCap * 2 * kThreads + threadIdx.x;
-    j.count = (int32_t*)(base + (size_t)nblk * kFbJumpCap * 2 * kThreads) +
-              (size_t)blockIdx.x * kThreads + threadIdx.x;
+    int32_t* counts = (int32_t*)(base + (size_t)nblk * kFbJumpCap * 2 * kThreads);
+    j.count = counts + (size_t)blockIdx.x * kThreads + threadIdx.x;
+    j.per = (uint8_t*)(counts + (size_t)nblk * kThreads) + (size_t)blockIdx.x * N * kThreads +
+            threadIdx.x;
     return j;
 }
 
@@ -1027,6 +1033,18 @@ __device__ __forceinline__ void fb_advance(const FbArgs<Real>& a, const Real* __
     }
 }
 
+// The sub-step-0 normals of interval k (words 0, 1 of its block 0).
+template <typename Real>
+__device__ __forceinline__ void fb_interval_normals(const FbArgs<Real>& a, uint32_t m, int k,
+                                                    Real& zx, Real& zv) {
+    uint32_t w[4];
+    philox4x32_10<true>(m, (uint32_t)k, a.iter, 0u, a.key0, a.key1, w);
+    const Real R = bm_radius(w[0], (Real)0);
+    const Real ub = unit_uniform<Real>(w[1]);
+    zx = bm_cos(R, ub);
+    zv = bm_sin(R, ub);
+}
+
 // The count and sub-step-0 normals of interval k, and a_1.
 template <typename Real>
 __device__ __forceinline__ int fb_interval(const FbArgs<Real>& a, uint32_t m, int k, Real& zx,
@@ -1067,6 +1085,8 @@ k_fb_forward_adapted(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __
     for (int k = 0; k < a.N; ++k) {
         Real zx, zv, a0 = 0, a1;
         const int n = fb_interval(a, sl.p, k, zx, zv, a1);
+        if (STORE)
+            __builtin_nontemporal_store((uint8_t)n, jumps.per + (size_t)k * kThreads);
         fb_advance<Real, NVP>(a, mu + (size_t)k * a.nx * NVP, zd + 2 * k, sl.p, k, n, 0, n + 1, x,
                               v, cx, cv, a0, a1, zx, zv, &acc, STORE ? &jumps : nullptr, &nj);
         if (STORE) {
@@ -1100,7 +1120,7 @@ k_fb_forward_adapted(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __
 // phi(z_r) (alpha u_r + lam^v_-) to the matrix-core sums; lam^v_- carries the
 // jump factor gamma.
 template <typename Real, int NVP>
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(kThreads, (sizeof(Real) == 4 ? 4 : 1))
 k_fb_adjoint_adapted(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __restrict__ zd,
                      const void* traj, double* __restrict__ apart) {
     // four held tiles: FP32 needs all 16 velocity rows for them
@@ -1113,6 +1133,7 @@ k_fb_adjoint_adapted(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __
     const Real* row = fb_row<Real>(const_cast<void*>(traj), N, blockIdx.x);
     const FbJumps<Real> jumps = fb_jumps<Real>(const_cast<void*>(traj), N, a.nblk);
     int jend = *jumps.count;  // jumps in the intervals up to the current one
+    int nk = __builtin_nontemporal_load(jumps.per + (size_t)(N - 1) * kThreads);
     const Real xN = __builtin_nontemporal_load(row + (size_t)N * 2 * kThreads);
     const Real vN = __builtin_nontemporal_load(row + (size_t)N * 2 * kThreads + kThreads);
     Real gxe, gve;  // unweighted running-cost gradient at the interval's end state
@@ -1128,8 +1149,11 @@ k_fb_adjoint_adapted(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __
             xp = __builtin_nontemporal_load(row + (size_t)(k - 1) * 2 * kThreads);
             vp = __builtin_nontemporal_load(row + (size_t)(k - 1) * 2 * kThreads + kThreads);
         }
-        Real zx0, zv0, a1_0;
-        const int n = fb_interval(a, sl.p, k, zx0, zv0, a1_0);
+        // the count the forward stored; a_1 only where the lane jumps
+        const int n = nk;
+        if (k >= 1)
+            nk = __builtin_nontemporal_load(jumps.per + (size_t)(k - 1) * kThreads);
+        const Real a1_0 = n > 0 ? fb_next_offset(a, sl.p, k, 0, n, (Real)0) : (Real)1;
         // the last sub-step starts at a_n
         Real an = 0;
         if (n > 0) {
@@ -1160,7 +1184,8 @@ k_fb_adjoint_adapted(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __
                     x = jumps.st[(size_t)(2 * (jb + r - 1)) * kThreads];
                     v = jumps.st[(size_t)(2 * (jb + r - 1) + 1) * kThreads];
                 } else {
-                    Real cx = 0, cv = 0, b0 = 0, b1 = a1_0, zx = zx0, zv = zv0;
+                    Real cx = 0, cv = 0, b0 = 0, b1 = a1_0, zx, zv;
+                    fb_interval_normals(a, sl.p, k, zx, zv);
                     fb_advance<Real, NVP>(a, mk, zk, sl.p, k, n, 0, r, x, v, cx, cv, b0, b1, zx,
                                           zv, nullptr);
                 }
@@ -1173,7 +1198,8 @@ k_fb_adjoint_adapted(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __
                     xe = jumps.st[(size_t)(2 * (jb + r)) * kThreads];
                     ve = jumps.st[(size_t)(2 * (jb + r) + 1) * kThreads];
                 } else {
-                    Real cx = 0, cv = 0, b0 = 0, b1 = a1_0, zx = zx0, zv = zv0;
+                    Real cx = 0, cv = 0, b0 = 0, b1 = a1_0, zx, zv;
+                    fb_interval_normals(a, sl.p, k, zx, zv);
                     xe = xk;
                     ve = vk;
                     fb_advance<Real, NVP>(a, mk, zk, sl.p, k, n, 0, r + 1, xe, ve, cx, cv, b0, b1,
