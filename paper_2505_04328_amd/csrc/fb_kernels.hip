@@ -1119,8 +1119,10 @@ k_fb_forward_adapted(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __
 // the interval's start only past the stack's capacity), each adding d_r/dt
 // phi(z_r) (alpha u_r + lam^v_-) to the matrix-core sums; lam^v_- carries the
 // jump factor gamma.
+// Held to four waves per SIMD in FP32 (three without the bound: ja2 19.9
+// against 18.3 ms) and two in FP64 (one without: 80.0 against 54.8 ms).
 template <typename Real, int NVP>
-__global__ void __launch_bounds__(kThreads, (sizeof(Real) == 4 ? 4 : 1))
+__global__ void __launch_bounds__(kThreads, (sizeof(Real) == 4 ? 4 : 2))
 k_fb_adjoint_adapted(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __restrict__ zd,
                      const void* traj, double* __restrict__ apart) {
     // four held tiles: FP32 needs all 16 velocity rows for them
