@@ -193,3 +193,29 @@ def test_adapted_full_size_ja2(dev):
         assert e_z <= tol["path"] and e_l <= tol["path"]
         e_c = float(np.max(np.abs(dd["cost"].cpu().numpy() - C) / (np.abs(C) + np.sqrt(np.mean(C * C)))))
         assert e_c <= tol["path"]
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_adapted_stored_jump_counts(dev, precision):
+    """The jump-adapted forward's per-slot jump totals (int32) and per-interval
+    counts (one byte per slot and interval), laid out as the header states,
+    equal the oracle's counts."""
+    import torch
+    p, M, seed = _problem("paper_step")
+    mu = wl.random_feedback_control(p, 4, 0.5)
+    eng = B.FbEngine(p, M=M, seed=seed, precision=precision, device=dev)
+    eng.forward(mu, it=2)
+    torch.cuda.synchronize()
+    _, _, _, n_ref, _ = ref.fb_paths(p, seed, 2, 0, M, mu)
+    esz = eng.traj.element_size()
+    slots = eng.nblk * 256
+    T = slots * (p.N + 1) * 2 + slots * 32 * 2  # states, then the jump stacks
+    raw = eng.traj.view(torch.uint8)[T * esz:].cpu().numpy()
+    totals = raw[:slots * 4].view(np.int32)[:M]
+    np.testing.assert_array_equal(totals, n_ref.sum(axis=1))
+    per = raw[slots * 4:]
+    assert per.size == eng.nblk * p.N * 256
+    s = np.arange(M)
+    k = np.arange(p.N)
+    got = per[((s[:, None] // 256) * p.N + k[None, :]) * 256 + (s[:, None] % 256)]
+    np.testing.assert_array_equal(got, n_ref)

@@ -293,3 +293,33 @@ def test_fb_surrogate_optimize_matches_oracle(dev):
         assert a["zeta"] == b["zeta"] and a["backtracks"] == b["backtracks"]
         assert abs(a["J"] - b["J"]) <= 1e-12 * abs(b["J"])
     assert norm_err(mu.cpu().numpy(), mu_o) <= 1e-11
+
+
+def _count_bytes(eng, T_elems):
+    """The trajectory buffer's bytes from element T_elems on (the jump data)."""
+    import torch
+    esz = eng.traj.element_size()
+    return eng.traj.view(torch.uint8)[T_elems * esz:].cpu().numpy()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_fb_stored_jump_counts(dev, precision):
+    """The forward's jump counts in the trajectory buffer (one byte per slot
+    and step after the states, the layout of include/jd_feedback.h) equal the
+    oracle's counts, bit for bit."""
+    p, M, seed, scale = _problem("gamma_negative")
+    say("stored jump counts", precision)
+    mu = wl.random_feedback_control(p, 4, scale)
+    eng = B.FbEngine(p, M=M, seed=seed, precision=precision, device=dev)
+    eng.forward(mu, it=2)
+    import torch
+    torch.cuda.synchronize()
+    _, _, _, n_ref, _ = ref.fb_paths(p, seed, 2, 0, M, mu)
+    assert n_ref.sum() > 0
+    T = eng.nblk * (p.N + 1) * 2 * 256
+    cb = _count_bytes(eng, T)
+    assert cb.size == eng.nblk * p.N * 256
+    s = eng.slots()
+    k = np.arange(p.N)
+    got = cb[((s[:, None] // 256) * p.N + k[None, :]) * 256 + (s[:, None] % 256)]
+    np.testing.assert_array_equal(got, n_ref)

@@ -213,3 +213,22 @@ def test_ring_full_size_ring2(dev):
         assert e_z <= tol["path"] and e_l <= tol["path"]
         e_c = float(np.max(np.abs(dd["cost"].cpu().numpy() - C) / (np.abs(C) + np.sqrt(np.mean(C * C)))))
         assert e_c <= tol["path"]
+
+
+def test_ring_stored_jump_counts(dev):
+    """Rings of 300 across a workgroup's 256-slot groups: the stored jump
+    counts, addressed by slot as the header states, equal the oracle's."""
+    p, M, seed = _ring("ring300")
+    mu = wl.random_feedback_control(p, 4, 0.5)
+    eng = B.FbEngine(p, M=M, seed=seed, precision="fp32", device=dev)
+    eng.forward(mu, it=1)
+    import torch
+    torch.cuda.synchronize()
+    _, _, _, n_ref, _ = ref.fb_paths(p, seed, 1, 0, M, mu)
+    assert n_ref.sum() > 0
+    T = eng.nblk * (p.N + 1) * 2 * 256
+    cb = eng.traj.view(torch.uint8)[T * 4:].cpu().numpy()
+    s = eng.slots()
+    k = np.arange(p.N)
+    got = cb[((s[:, None] // 256) * p.N + k[None, :]) * 256 + (s[:, None] % 256)]
+    np.testing.assert_array_equal(got, n_ref)
