@@ -4,9 +4,17 @@
 //                      Keilson-Storer factors; stages the Poisson table
 //  k_fb_forward        forward sweep, one particle per lane (G per lane for
 //                      rings): shape functions, feedback control, ring
-//                      coupling, draws, Euler step, jumps, FP64 cost
-//  k_fb_adjoint        backward sweep over the stored trajectory; the per-step
-//                      gradient sum over particles runs on the FP64 matrix cores
+//                      coupling, draws, Euler step, jumps, FP64 cost; stores
+//                      the trajectory and each step's jump count
+//  k_fb_adjoint        backward sweep over the stored trajectory (or, for the
+//                      surrogate gradient, over counter-drawn surrogate
+//                      states); the per-step gradient sum over particles runs
+//                      on the matrix cores of the path precision
+//  k_fb_forward_grad   the surrogate gradient's forward: forward sweep plus
+//                      the control term of the gradient, nothing stored
+//  k_fb_forward_adapted, k_fb_adjoint_adapted
+//                      the same on the jump-adapted grid (sub-steps between
+//                      each particle's jump times, a stack of post-jump states)
 //  k_fb_finalize_grad  fixed-order FP64 sum of the per-block gradient partials
 //  k_fb_finalize_cost  fixed-order FP64 sum of the path costs, ||g||^2
 //  k_fb_draws          initial states, normals and jump counts (parity checks)
@@ -15,9 +23,11 @@
 // SDE_splitted_drift_Euler, eq. jump_law, eq. collision_frequency), control
 // and shape functions (eq. control_structure, eq. Gaussian_RBF), cost (eq.
 // discrete_functional, eq. tracking_cost), adjoint (eq.
-// adjoint_eq_approximation), gradient (eq. definition_Gradient); coupled
-// particles, the start on the ellipse and the ellipse cost of Section 6.4
-// (eq. interacting_model, eq. coupled_ellipse, eq. phonon_functional_tracking).
+// adjoint_eq_approximation), gradient (eq. definition_Gradient); the
+// jump-adapted grid (Section 3, Algorithms 5.1-5.2); the surrogate adjoint
+// (Section 6.5); coupled particles, the start on the ellipse and the ellipse
+// cost of Section 6.4 (eq. interacting_model, eq. coupled_ellipse, eq.
+// phonon_functional_tracking).
 #include "fb_launch.hpp"
 #include "jd_device.hpp"
 
@@ -603,8 +613,8 @@ struct FbHist {
 };
 
 // The wave's sums, in FP64.
-template <typename Real, int PVW>
-__device__ __forceinline__ fb_d4 fb_tile(const FbWave<Real, PVW>& w) {
+template <typename Real, int VR>
+__device__ __forceinline__ fb_d4 fb_tile(const FbWave<Real, VR>& w) {
     fb_d4 t;
 #pragma unroll
     for (int r = 0; r < 4; ++r)
@@ -623,8 +633,8 @@ constexpr int fb_tiles_v() { return (int)(sizeof(Real) * VR * fb_xs<Real>() / (s
 
 // LDS home of tile s of wave wv during a flush (the wave's transpose buffers,
 // free between steps).
-template <typename Real, int PVW, int W>
-__device__ __forceinline__ double* fb_tile_lds(FbShared<Real, PVW, W>& sh, int wv, int s) {
+template <typename Real, int VR, int W>
+__device__ __forceinline__ double* fb_tile_lds(FbShared<Real, VR, W>& sh, int wv, int s) {
     constexpr int TX = fb_tiles_x<Real>();
     return s < TX ? (double*)&sh.phx[wv][0][0] + s * kFbTile
                   : (double*)&sh.phv[wv][0][0] + (s - TX) * kFbTile;
@@ -632,11 +642,11 @@ __device__ __forceinline__ double* fb_tile_lds(FbShared<Real, PVW, W>& sh, int w
 
 // Sums the W waves' held tiles in a fixed order into the block's partials:
 // tile s is step k0 + s dir (ADD: added to what the partial holds).
-template <bool ADD, int H, typename Real, int PVW, int W>
-__device__ __forceinline__ void fb_hist_flush(FbShared<Real, PVW, W>& sh, const FbWave<Real, PVW>& w,
+template <bool ADD, int H, typename Real, int VR, int W>
+__device__ __forceinline__ void fb_hist_flush(FbShared<Real, VR, W>& sh, const FbWave<Real, VR>& w,
                                               FbHist<H>& h, int k0, int dir, int N, int nx, int nv,
                                               double* __restrict__ apart) {
-    static_assert(H <= fb_tiles_x<Real>() + fb_tiles_v<Real, PVW>(),
+    static_assert(H <= fb_tiles_x<Real>() + fb_tiles_v<Real, VR>(),
                   "a wave's transposes must hold its H tiles");
     const int wv = threadIdx.x >> 6;
 #pragma unroll
@@ -1549,10 +1559,11 @@ hipError_t fb_launch_forward(const FbHost& p, const HostRun& r, const void* tab,
 // block divide the per-step gradient partials but cost registers.  Measured on
 // 2^20 x 500: FP64 paths 31.1 / 28.9 ms for 1 / 2 groups (16.2 / 15.5 / 18.3 ms
 // for 1 / 2 / 4 on FP32 paths while these used the FP64 matrix cores); FP32
-// paths on the FP32 matrix cores with the compact velocity transposes fit five
-// waves per SIMD with one group: 10.8 ms against 11.3 ms for two (four waves)
-// and 11.0 ms for two forced to five waves (spills).  Rings keep their own G
-// (whole rings per block); the jump-adapted adjoint runs one group.
+// paths on the FP32 matrix cores with velocity transposes of the compiled row
+// width fit five waves per SIMD with one group: 10.8 ms against 11.3 ms for
+// two (four waves) and 11.0 ms for two forced to five waves (spills).  Rings
+// keep their own G (whole rings per block); the jump-adapted adjoint runs one
+// group.
 static int fb_adjoint_groups(const FbHost& p, const HostRun& r) {
     if (p.np > 1)
         return p.G;
