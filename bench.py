@@ -108,8 +108,9 @@ def parse():
     ap.add_argument("--no-adapted", action="store_true",
                     help="skip the jump-adapted grid section (Section 3)")
     ap.add_argument("--cpu-sample-paths", type=int, default=1 << 19)
-    ap.add_argument("--only", choices=["all", "fp32_store", "kernels"], default="all",
-                    help="kernels: time jd_forward / jd_adjoint only (for profiler runs)")
+    ap.add_argument("--only", choices=["all", "fp32_store", "kernels", "fb-kernels"], default="all",
+                    help="kernels: time jd_forward / jd_adjoint only; fb-kernels: run the f4 "
+                         "FP32 gradient only (for profiler runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")
     ap.add_argument("--serving", action="store_true",
@@ -437,6 +438,17 @@ def main():
     from paper_2505_04328_amd import workloads as wl
 
     dev = torch.device("cuda:0")
+    if args.only == "fb-kernels":
+        # the feedback model's forward and adjoint at f4, FP32, for counter runs
+        wf = wl.feedback_config("f4")
+        mu = torch.tensor(wl.random_feedback_control(wf.problem, 4, 0.5), device=dev)
+        ef = B.FbEngine(wf.problem, M=wf.M, seed=wf.seed, precision="fp32", device=dev)
+        for it in range(args.warmup + args.steps):
+            ef.cost_grad(mu, it=it)
+        torch.cuda.synchronize()
+        log("feedback-model kernel loop done")
+        print(json.dumps({"fb_kernels_only": True, "calls": args.warmup + args.steps}))
+        return
     w = wl.config("c2")
     p = w.problem
     M, N = w.M, p.N
