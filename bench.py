@@ -245,6 +245,30 @@ def feedback_section(args, time_calls, dev):
                                "frac": FB_FWD_SLOTS * ps / t_f / VALU_PEAK_SLOTS,
                                "slots_per_path_step": FB_FWD_SLOTS}
     out["step_frac"] = (FB_FWD_SLOTS + FB_ADJ_SLOTS) * ps / t_cg / VALU_PEAK_SLOTS
+    # Section 6.5's comparison at the paper's size and setting (f3: 2000
+    # particles, 50 steps, time-dependent target): the gradient iteration from
+    # mu = 0 with the exact and with the surrogate gradient (FP64, 40
+    # iterations at most, Armijo from zeta0 = 10), both scored on a held-out
+    # sample of 2^16 particles with other draws.
+    wc = wl.feedback_config("f3")
+    pc = wc.problem
+    mu0 = torch.zeros((pc.N, pc.L), dtype=torch.float64, device=dev)
+    held = B.FbEngine(pc, M=1 << 16, seed=wc.seed + 100, precision="fp64", device=dev)
+    J0h, _ = held.cost_grad(mu0, it=0)
+    conv = {"workload": "f3 (Section 6.3 / 6.5 setting), FP64", "held_out_J_zero_control": float(J0h)}
+    for mode in ("store", "surrogate"):
+        ec = B.FbEngine(pc, M=wc.M, seed=wc.seed, precision="fp64", device=dev, mode=mode)
+        muc, logs = ec.optimize(mu0.clone(), n_max=40, zeta0=10.0, allow_stall=True)
+        Jh, _ = held.cost_grad(muc, it=0)
+        conv["exact" if mode == "store" else "surrogate"] = {
+            "iterations": len(logs), "stalled": len(logs) < 40,
+            "J": [round(l["J"], 6) for l in logs], "held_out_J": float(Jh)}
+        del ec
+    del held
+    out["surrogate_vs_exact_iteration"] = conv
+    log(f"surrogate vs exact iteration (f3): exact {conv['exact']['iterations']} it -> held-out "
+        f"{conv['exact']['held_out_J']:.4f}, surrogate {conv['surrogate']['iterations']} it -> "
+        f"{conv['surrogate']['held_out_J']:.4f}")
     J64, g64 = res["fp64"]
     J32, g32 = res["fp32"]
     out["fp32_vs_fp64_full_size"] = {"J_rel": abs(J32 - J64) / abs(J64),

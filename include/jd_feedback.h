@@ -73,8 +73,9 @@
  * independent of the forward trajectories): nothing is stored.  The forward
  * adds alpha u_k phi(z_k) to the gradient as it goes; the adjoint recursion
  * above runs on surrogate states zs_k = zd_k + sqrt(svar0 + svar1 t_k) . (Z1, Z2)
- * (Box-Muller pair of words 0, 1 of Philox block (m, k, iter, 1)) with the
- * forward's jump counts, and adds gamma^{n_k} ls^v_{k+1} phi(zs_k).  J is the
+ * with one sample (Z1, Z2) per particle and realization (Box-Muller pair of
+ * words 0, 1 of Philox block (m, 0xFFFFFFFE, iter, 1), the same at every
+ * step) and the forward's jump counts, and adds gamma^{n_k} ls^v_{k+1} phi(zs_k).  J is the
  * exact cost.  The gradient is biased (it is not the derivative of J).
  *
  * Conventions are those of jd.h (return codes, caller-owned device buffers,

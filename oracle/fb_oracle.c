@@ -38,6 +38,7 @@
 
 #define FB_CHUNK 4096
 #define FB_INIT_STEP 0xFFFFFFFFu
+#define FB_SURR_WORD 0xFFFFFFFEu
 #define FB_SUB 32 /* sub-steps of a uniform interval on the jump-adapted grid: <= 31 jumps + 1 */
 
 static const double FB_TWO_PI = 6.283185307179586476925286766559;
@@ -148,13 +149,15 @@ void fb_adapted_draws(uint64_t seed, uint32_t m, uint32_t k, uint32_t iter, cons
     a[*n + 1] = 1.0;
 }
 
-/* Surrogate state: zd_k + sqrt(var(t_k)) (R cos, R sin) from the Box-Muller
- * pair of words 0 and 1 of block (m, k, iter, 1). */
+/* Surrogate state (Section 6.5: one position and velocity sampled for each
+ * particle and realization): zd_k + sqrt(var(t_k)) (R cos, R sin) with the
+ * Box-Muller pair of words 0 and 1 of block (m, 0xFFFFFFFE, iter, 1), the same
+ * pair at every step k. */
 void fb_surrogate_state(const fb_problem* pb, uint64_t seed, uint32_t m, uint32_t k, uint32_t iter,
                         double z[2])
 {
     uint32_t key[2], W[4];
-    uint32_t ctr[4] = {m, k, iter, 1u};
+    uint32_t ctr[4] = {m, FB_SURR_WORD, iter, 1u};
     key_of(seed, key);
     or_philox4x32_10(ctr, key, W);
     double R = sqrt(-2.0 * log(or_uniform(W[0])));

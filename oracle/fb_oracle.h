@@ -58,8 +58,9 @@
  *
  * Surrogate gradient (Section 6.5, the adjoint independent of the forward
  * trajectories): the adjoint runs on states zs_k ~ N(zd_k, diag(var(t_k))),
- * drawn from Philox block (m, k, iter, 1) (Box-Muller pair of words 0, 1),
- * with the forward's jump counts; no trajectory is stored:
+ * one sample per particle and realization, zs_k = zd_k + sqrt(var(t_k)) Z with
+ * Z the Box-Muller pair of words 0, 1 of Philox block (m, 0xFFFFFFFE, iter, 1)
+ * at every step, with the forward's jump counts; no trajectory is stored:
  *   gs_k[l] = (1/M) sum_m [ alpha u_k phi_l(z_k) + gamma^{n_k} ls^v_{k+1} phi_l(zs_k) ]
  * where ls is the adjoint recursion above evaluated at zs (u, u_x, u_v and
  * grad Jt at zs_k).

@@ -433,7 +433,11 @@ class FbEngine:
         return J, g
 
     def optimize(self, mu, n_max: int, it0: int = 0, tol: float = 0.0, zeta0: float = 1.0,
-                 rho: float = 0.5, c_armijo: float = 1e-4, max_backtracks: int = 30):
+                 rho: float = 0.5, c_armijo: float = 1e-4, max_backtracks: int = 30,
+                 allow_stall: bool = False):
+        """The gradient iteration; mu is updated in place.  allow_stall: a line
+        search that finds no Armijo step ends the iteration (JD_ELINESEARCH,
+        mu at the last accepted iterate) instead of raising."""
         mu = self._mu(mu)
         opt = jd_opt(n_max, max_backtracks, tol, zeta0, rho, c_armijo)
         logs = (jd_iter_log * max(n_max, 1))()
@@ -444,7 +448,8 @@ class FbEngine:
                                   self.ws_bytes, _stream_ptr(self.device))
         out = [dict(iter=l.iter, backtracks=l.backtracks, J=l.J, gnorm=l.gnorm, zeta=l.zeta,
                     J_new=l.J_new, E=l.E) for l in logs[:done.value]]
-        check(rc, "jd_fb_optimize")
+        if not (allow_stall and rc == JD_ELINESEARCH):
+            check(rc, "jd_fb_optimize")
         return mu, out
 
     def check_finite(self) -> bool:

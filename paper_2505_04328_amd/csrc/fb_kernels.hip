@@ -34,6 +34,7 @@
 namespace jd {
 
 constexpr uint32_t kFbInitStep = 0xFFFFFFFFu;  // counter word 1 of the initial-state draws
+constexpr uint32_t kFbSurrWord = 0xFFFFFFFEu;  // counter word 1 of the surrogate samples
 
 // gamma^n and sqrt(V_n), n = 0..31, passed by value to the table kernel.
 struct FbKs {
@@ -232,18 +233,26 @@ __device__ __forceinline__ Real fb_step(const FbArgs<Real>& a, const Real* __res
     return u;
 }
 
-// Surrogate state of particle m at step k (Section 6.5): zd_k + sqrt(var(t_k))
-// times the Box-Muller pair of words 0, 1 of Philox block (m, k, iter, 1).
+// The surrogate states of Section 6.5 take one position and velocity sample
+// per particle and realization: the Box-Muller pair (cx, cv) of words 0, 1 of
+// Philox block (m, 0xFFFFFFFE, iter, 1), and at step k the state
+// zd_k + sqrt(var(t_k)) (cx, cv).
 template <typename Real>
-__device__ __forceinline__ void fb_surrogate(const FbArgs<Real>& a, const Real* __restrict__ zd,
-                                             uint32_t m, int k, Real& x, Real& v) {
+__device__ __forceinline__ void fb_surrogate_sample(const FbArgs<Real>& a, uint32_t m, Real& cx,
+                                                    Real& cv) {
     uint32_t w[4];
-    philox4x32_10<true>(m, (uint32_t)k, a.iter, 1u, a.key0, a.key1, w);
+    philox4x32_10<true>(m, kFbSurrWord, a.iter, 1u, a.key0, a.key1, w);
     const Real R = bm_radius(w[0], (Real)0);
     const Real ub = unit_uniform<Real>(w[1]);
+    cx = bm_cos(R, ub);
+    cv = bm_sin(R, ub);
+}
+template <typename Real>
+__device__ __forceinline__ void fb_surrogate(const FbArgs<Real>& a, const Real* __restrict__ zd,
+                                             int k, Real cx, Real cv, Real& x, Real& v) {
     const Real t = (Real)k * a.dt;
-    x = fma(sqrt(fma(a.var1x, t, a.var0x)), bm_cos(R, ub), zd[2 * k]);
-    v = fma(sqrt(fma(a.var1v, t, a.var0v)), bm_sin(R, ub), zd[2 * k + 1]);
+    x = fma(sqrt(fma(a.var1x, t, a.var0x)), cx, zd[2 * k]);
+    v = fma(sqrt(fma(a.var1v, t, a.var0v)), cv, zd[2 * k + 1]);
 }
 
 template <typename Real>
@@ -743,6 +752,7 @@ struct FbAdj {
     Real x, v;    // z_k (current step)
     Real xn, vn;  // z_{k-1}, loaded one step ahead (stored trajectory)
     int nn;       // jump count of step k, loaded one step ahead (stored)
+    Real sx, sv;  // the particle's surrogate sample (surrogate gradient)
     Real lx, lv;  // lam_{k+1} on entry to step k
 };
 
@@ -800,7 +810,8 @@ k_fb_adjoint(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __restrict
         if (SURR) {
             row[j] = nullptr;
             cnt[j] = nullptr;
-            fb_surrogate(a, zd, (uint32_t)m[j], N, s[j].x, s[j].v);
+            fb_surrogate_sample(a, (uint32_t)m[j], s[j].sx, s[j].sv);
+            fb_surrogate(a, zd, N, s[j].sx, s[j].sv, s[j].x, s[j].v);
         } else {
             row[j] = fb_slot_row<Real, G, TPB>(traj, N, a.nblk, j);
             cnt[j] = fb_slot_counts<Real, G, TPB>(traj, N, a.nblk, j);
@@ -824,7 +835,7 @@ k_fb_adjoint(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __restrict
         for (int j = 0; j < G; ++j) {
             FbAdj<Real>& st = s[j];
             if (SURR) {
-                fb_surrogate(a, zd, (uint32_t)m[j], k, st.x, st.v);
+                fb_surrogate(a, zd, k, st.sx, st.sv, st.x, st.v);
             } else {
                 st.x = st.xn;
                 st.v = st.vn;

@@ -228,10 +228,14 @@ def test_descent_on_the_paper_setting():
 
 # ---------------------------------------------------------------- surrogate adjoint (Section 6.5)
 def test_surrogate_states_law():
-    """zs_k ~ N(zd_k, diag(svar0 + svar1 t_k)), components uncorrelated."""
+    """zs_k ~ N(zd_k, diag(svar0 + svar1 t_k)), components uncorrelated, and
+    one sample per particle and realization (Section 6.5): the standardised
+    offset (zs_k - zd_k) / sqrt(var(t_k)) is the same at every step, and
+    differs between particles and between realizations."""
     p = wl.feedback_problem(N=10, T=2.0, zd=_moving_target(10, 2.0), svar0=(0.04, 0.09),
                             svar1=(0.3, 0.05))
     M = 20000
+    xi = {}
     for k in (0, 4, 10):
         zs = np.array([ref.fb_surrogate_state(p, 7, m, k, 3) for m in range(M)])
         t = k * p.dt
@@ -242,6 +246,12 @@ def test_surrogate_states_law():
         assert np.all(np.abs(v - var) <= 5 * var * np.sqrt(2.0 / M)), (k, v, var)
         c = np.corrcoef(zs[:, 0], zs[:, 1])[0, 1]
         assert abs(c) <= 5 / np.sqrt(M)
+        xi[k] = (zs - p.zd[k]) / np.sqrt(var)
+    np.testing.assert_allclose(xi[4], xi[0], rtol=0, atol=1e-12)
+    np.testing.assert_allclose(xi[10], xi[0], rtol=0, atol=1e-12)
+    other = np.array([ref.fb_surrogate_state(p, 7, m, 4, 4) for m in range(200)])
+    assert np.all(np.abs(other - np.array([ref.fb_surrogate_state(p, 7, m, 4, 3)
+                                             for m in range(200)])).max(axis=1) > 0)
 
 
 def _moving_target(N, T):

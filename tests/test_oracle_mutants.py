@@ -103,6 +103,8 @@ FB_MUTANTS = {
                                "G[(size_t)k * L + i * pb->nv + l] += w->px[i] * w->pv[l] * lv;"),
     "fb_surr_var_no_sqrt": ("z[0] = pb->zd[2 * k] + sqrt(pb->svar0[0] + pb->svar1[0] * t) * R * cos(th);",
                             "z[0] = pb->zd[2 * k] + (pb->svar0[0] + pb->svar1[0] * t) * R * cos(th);"),
+    "fb_surr_fresh_sample_per_step": ("uint32_t ctr[4] = {m, FB_SURR_WORD, iter, 1u};",
+                                      "uint32_t ctr[4] = {m, k, iter, 1u};"),
     "fb_surr_time_next_step": ("double t = (double)k * (pb->T / (double)pb->N);",
                                "double t = (double)(k + 1) * (pb->T / (double)pb->N);"),
     "fb_surr_track_sign": ("double nlv = dt * lx + gn * (1.0 + dt * uv) * lv + dt * gz[1]",
