@@ -148,9 +148,11 @@ typedef struct jd_fb_problem {
  * B + ((s / 256) N + k) 256 + (s % 256), B the byte length of the states;
  * jd_fb_forward writes them and jd_fb_adjoint reads them instead of
  * regenerating the draws.  On the jump-adapted grid the buffer continues with
- * the states after each of a slot's first 32 jumps (component c after jump e
- * of slot s: element T + ((s / 256) 32 + e) 2 256 + c 256 + (s % 256), T the
- * trajectory's length), one int32 jump count per slot, and then one byte per
+ * the states after each of a slot's first 32 jumps and the jump times (entry e
+ * of slot s, component c = 0, 1 for x, v and 2 for the jump's offset in its
+ * interval in units of dt: element T + ((s / 256) 32 + e) 3 256 + c 256 +
+ * (s % 256), T the trajectory's length), one int32 jump count per slot, and
+ * then one byte per
  * slot and interval k, the interval's jump count (byte
  * C + ((s / 256) N + k) 256 + (s % 256), C where the int32 counts end), all
  * of which the adjoint reads. */

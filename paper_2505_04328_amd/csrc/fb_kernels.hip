@@ -980,17 +980,19 @@ __device__ __forceinline__ void fb_target(const Real* __restrict__ zk, Real f, R
 
 // The per-particle stack of post-jump states on the jump-adapted grid: entry
 // e holds the state after the particle's e-th jump (the start of the sub-step
-// that follows it), kFbJumpCap entries per slot in the trajectory buffer after
-// the uniform points, then one int32 count per slot.  A particle with more
-// jumps than entries has the rest recomputed by the adjoint.
+// that follows it) and the jump's time in its interval (the offset a, in
+// units of dt), kFbJumpCap entries per slot in the trajectory buffer after the
+// uniform points, then one int32 count per slot.  A particle with more jumps
+// than entries has the rest recomputed by the adjoint.
 constexpr int kFbJumpCap = kFbJumpStates;
+constexpr int kFbJumpComp = 3;  // x, v, a
 
 // After the counts: one byte per slot and interval, the interval's jump count
 // (interval k of block b's lane l at byte (b N + k) 256 + l), so that the
 // adjoint need not regenerate it.
 template <typename Real>
 struct FbJumps {
-    Real* st;        // slot's entry 0, x (entry e component c at st[(2 e + c) 256])
+    Real* st;        // slot's entry 0, x (entry e component c at st[(3 e + c) 256])
     int32_t* count;  // slot's jump count
     uint8_t* per;    // slot's count of interval 0 (interval k at per[k 256])
 };
@@ -999,8 +1001,8 @@ template <typename Real>
 __device__ __forceinline__ FbJumps<Real> fb_jumps(void* traj, int N, int64_t nblk) {
     FbJumps<Real> j;
     Real* base = (Real*)traj + (size_t)nblk * (N + 1) * 2 * kThreads;
-    j.st = base + (size_t)blockIdx.x * kFbJumpCap * 2 * kThreads + threadIdx.x;
-    int32_t* counts = (int32_t*)(base + (size_t)nblk * kFbJumpCap * 2 * kThreads);
+    j.st = base + (size_t)blockIdx.x * kFbJumpCap * kFbJumpComp * kThreads + threadIdx.x;
+    int32_t* counts = (int32_t*)(base + (size_t)nblk * kFbJumpCap * kFbJumpComp * kThreads);
     j.count = counts + (size_t)blockIdx.x * kThreads + threadIdx.x;
     j.per = (uint8_t*)(counts + (size_t)nblk * kThreads) + (size_t)blockIdx.x * N * kThreads +
             threadIdx.x;
@@ -1038,8 +1040,9 @@ __device__ __forceinline__ void fb_advance(const FbArgs<Real>& a, const Real* __
             zv = bm_sin(R, ub);
             if (jumps != nullptr) {
                 if (*nj < kFbJumpCap) {
-                    jumps->st[(size_t)(2 * *nj) * kThreads] = x;
-                    jumps->st[(size_t)(2 * *nj + 1) * kThreads] = v;
+                    jumps->st[(size_t)(kFbJumpComp * *nj) * kThreads] = x;
+                    jumps->st[(size_t)(kFbJumpComp * *nj + 1) * kThreads] = v;
+                    jumps->st[(size_t)(kFbJumpComp * *nj + 2) * kThreads] = a1;
                 }
                 ++*nj;
             }
@@ -1174,17 +1177,27 @@ k_fb_adjoint_adapted(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __
             xp = __builtin_nontemporal_load(row + (size_t)(k - 1) * 2 * kThreads);
             vp = __builtin_nontemporal_load(row + (size_t)(k - 1) * 2 * kThreads + kThreads);
         }
-        // the count the forward stored; a_1 only where the lane jumps
+        // the count the forward stored
         const int n = nk;
         if (k >= 1)
             nk = __builtin_nontemporal_load(jumps.per + (size_t)(k - 1) * kThreads);
-        const Real a1_0 = n > 0 ? fb_next_offset(a, sl.p, k, 0, n, (Real)0) : (Real)1;
+        const int jb = jend - n;  // stack entry of this interval's first jump
+        // the jump times a_q (q = 1..n) from the stack when it holds them all,
+        // else regenerated
+        const bool stk = n > 0 && jb + n - 1 < kFbJumpCap;
+        const Real a1_0 = n == 0 ? (Real)1
+                          : stk  ? jumps.st[(size_t)(kFbJumpComp * jb + 2) * kThreads]
+                                 : fb_next_offset(a, sl.p, k, 0, n, (Real)0);
         // the last sub-step starts at a_n
         Real an = 0;
         if (n > 0) {
-            an = a1_0;
-            for (int r = 1; r < n; ++r)
-                an = fb_next_offset(a, sl.p, k, r, n, an);
+            if (stk) {
+                an = jumps.st[(size_t)(kFbJumpComp * (jb + n - 1) + 2) * kThreads];
+            } else {
+                an = a1_0;
+                for (int r = 1; r < n; ++r)
+                    an = fb_next_offset(a, sl.p, k, r, n, an);
+            }
         }
         const Real dlast = n == 0 ? a.dt : ((Real)1 - an) * a.dt;
         lx = fma(dlast, gxe, lx);
@@ -1195,19 +1208,23 @@ k_fb_adjoint_adapted(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1)
             nmax = max(nmax, __shfl_xor(nmax, o));
-        const int jb = jend - n;  // stack entry of this interval's first jump
         wave.clear();
         for (int r = nmax; r >= 0; --r) {
             const bool mine = r <= n;
             Real x = xk, v = vk, a0 = 0, a1 = a1_0;
             if (mine && r > 0) {
-                for (int q = 1; q <= r; ++q) {
-                    a0 = a1;
-                    a1 = q < n ? fb_next_offset(a, sl.p, k, q, n, a1) : (Real)1;
+                if (stk) {
+                    a0 = jumps.st[(size_t)(kFbJumpComp * (jb + r - 1) + 2) * kThreads];
+                    a1 = r < n ? jumps.st[(size_t)(kFbJumpComp * (jb + r) + 2) * kThreads] : (Real)1;
+                } else {
+                    for (int q = 1; q <= r; ++q) {
+                        a0 = a1;
+                        a1 = q < n ? fb_next_offset(a, sl.p, k, q, n, a1) : (Real)1;
+                    }
                 }
                 if (jb + r - 1 < kFbJumpCap) {
-                    x = jumps.st[(size_t)(2 * (jb + r - 1)) * kThreads];
-                    v = jumps.st[(size_t)(2 * (jb + r - 1) + 1) * kThreads];
+                    x = jumps.st[(size_t)(kFbJumpComp * (jb + r - 1)) * kThreads];
+                    v = jumps.st[(size_t)(kFbJumpComp * (jb + r - 1) + 1) * kThreads];
                 } else {
                     Real cx = 0, cv = 0, b0 = 0, b1 = a1_0, zx, zv;
                     fb_interval_normals(a, sl.p, k, zx, zv);
@@ -1220,8 +1237,8 @@ k_fb_adjoint_adapted(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __
                 // the running cost at the jump ending sub-step r, charged to lam~_{r+1}
                 Real xe, ve;
                 if (jb + r < kFbJumpCap) {
-                    xe = jumps.st[(size_t)(2 * (jb + r)) * kThreads];
-                    ve = jumps.st[(size_t)(2 * (jb + r) + 1) * kThreads];
+                    xe = jumps.st[(size_t)(kFbJumpComp * (jb + r)) * kThreads];
+                    ve = jumps.st[(size_t)(kFbJumpComp * (jb + r) + 1) * kThreads];
                 } else {
                     Real cx = 0, cv = 0, b0 = 0, b1 = a1_0, zx, zv;
                     fb_interval_normals(a, sl.p, k, zx, zv);

@@ -9,7 +9,7 @@
 namespace jd {
 
 constexpr int kFbMaxGrid = 16;  // nx, nv <= 16: one 16 x 16 matrix-core tile per step
-constexpr int kFbJumpStates = 32;  // post-jump states kept per particle (jump-adapted grid)
+constexpr int kFbJumpStates = 32;  // post-jump states (x, v, jump time) kept per particle (jump-adapted grid)
 
 struct FbHost {
     int N, nx, nv, nvp, L;  // nvp: the compiled row width >= nv (zero-padded control rows)

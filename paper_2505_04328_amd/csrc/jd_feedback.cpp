@@ -168,7 +168,7 @@ FbLayout fb_layout(const FbHost& p, const HostRun& r) {
 size_t fb_traj_bytes(const FbHost& p, const HostRun& r) {
     size_t b = (size_t)(p.N + 1) * 2 * (size_t)r.ldm * real_size(r.prec);
     if (p.grid == JD_FB_GRID_ADAPTED)  // the post-jump state stacks and their counts
-        b += (size_t)kFbJumpStates * 2 * (size_t)r.ldm * real_size(r.prec) + (size_t)r.ldm * 4;
+        b += (size_t)kFbJumpStates * 3 * (size_t)r.ldm * real_size(r.prec) + (size_t)r.ldm * 4;
     b += (size_t)p.N * (size_t)r.ldm;  // one jump-count byte per particle and step / interval
     return b;
 }

@@ -251,14 +251,14 @@ def test_fb_workspace_and_traj_sizes(L):
 
 
 def test_fb_adapted_traj_size(L):
-    """The jump-adapted grid adds 32 post-jump states and a count per slot,
-    then a count byte per slot and interval."""
+    """The jump-adapted grid adds 32 post-jump states with their jump times
+    and a count per slot, then a count byte per slot and interval."""
     p = wl.adapted_config("ja2").problem
     pr = _FbDummy(p)
     for prec, es in (("fp32", 4), ("fp64", 8)):
         run = B.make_run(1000, precision=prec)
         slots = 4 * 256
-        want = (p.N + 1) * 2 * slots * es + 32 * 2 * slots * es + slots * 4 + p.N * slots
+        want = (p.N + 1) * 2 * slots * es + 32 * 3 * slots * es + slots * 4 + p.N * slots
         assert L.jd_fb_traj_bytes(C.byref(pr.st), C.byref(run)) == want
 
 

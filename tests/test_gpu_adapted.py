@@ -209,7 +209,7 @@ def test_adapted_stored_jump_counts(dev, precision):
     _, _, _, n_ref, _ = ref.fb_paths(p, seed, 2, 0, M, mu)
     esz = eng.traj.element_size()
     slots = eng.nblk * 256
-    T = slots * (p.N + 1) * 2 + slots * 32 * 2  # states, then the jump stacks
+    T = slots * (p.N + 1) * 2 + slots * 32 * 3  # states, then the jump stacks
     raw = eng.traj.view(torch.uint8)[T * esz:].cpu().numpy()
     totals = raw[:slots * 4].view(np.int32)[:M]
     np.testing.assert_array_equal(totals, n_ref.sum(axis=1))
