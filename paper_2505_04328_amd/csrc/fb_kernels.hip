@@ -1295,10 +1295,12 @@ k_fb_adjoint_adapted(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __
 }
 
 // Gradient entries q = (k, e): the sum over the per-block partials in a fixed
-// order.  A workgroup takes 8 consecutive entries; its thread (e, c) sums the
-// partials b = c, c + 32, ... of entry e in order, and a fixed LDS tree adds
-// the 32 chunk sums (one serial chain of 2048 loads per entry was latency-bound).
-constexpr int kFbFinEntries = 8;
+// order.  A workgroup takes 32 consecutive entries (a block's 256 contiguous
+// bytes of them per load); its thread (e, c) sums the partials b = c, c + 8,
+// ... of entry e in order, and a fixed LDS tree adds the 8 chunk sums (one
+// serial chain of 2048 loads per entry was latency-bound; 8 entries per
+// workgroup read 64-byte pieces: f4 step 13.92 against 13.77 ms).
+constexpr int kFbFinEntries = 32;
 constexpr int kFbFinChunks = kThreads / kFbFinEntries;
 
 __global__ void __launch_bounds__(kThreads)
