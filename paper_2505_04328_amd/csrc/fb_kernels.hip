@@ -197,6 +197,28 @@ __device__ __forceinline__ Real fb_control(const FbArgs<Real>& a, const Real* __
     return u;
 }
 
+// fb_control with the row of one of two steps, chosen per lane (sel: mk1).
+template <typename Real, int NVP>
+__device__ __forceinline__ Real fb_control_of(const FbArgs<Real>& a, const Real* __restrict__ mk0,
+                                              const Real* __restrict__ mk1, bool sel, Real x,
+                                              Real v) {
+    Real pv[NVP];
+    shapes_v<Real, NVP>(a, v, pv);
+    Real u = 0;
+#pragma unroll 2
+    for (int i = 0; i < a.nx; ++i) {
+        const Real bx = bump(x - fma((Real)i, a.dxc, a.xc0), a.eps);
+        const Real* r0 = mk0 + i * NVP;
+        const Real* r1 = mk1 + i * NVP;
+        Real t = 0;
+#pragma unroll
+        for (int l = 0; l < NVP; ++l)
+            t = fma(sel ? r1[l] : r0[l], pv[l], t);
+        u = fma(bx, t, u);
+    }
+    return u;
+}
+
 template <typename Real, int NVP, typename Sink = NoSink, int RU = 2>
 __device__ __forceinline__ Real fb_step(const FbArgs<Real>& a, const Real* __restrict__ mk,
                                         const Real* __restrict__ ks, uint32_t m, int k, Real& x,
@@ -1108,19 +1130,81 @@ k_fb_forward_adapted(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __
     if (STORE)
         jumps = fb_jumps<Real>(traj, a.N, a.nblk);
     double acc = 0.0;
-    for (int k = 0; k < a.N; ++k) {
-        Real zx, zv, a0 = 0, a1;
-        const int n = fb_interval(a, sl.p, k, zx, zv, a1);
-        if (STORE)
-            __builtin_nontemporal_store((uint8_t)n, jumps.per + (size_t)k * kThreads);
-        fb_advance<Real, NVP>(a, mu + (size_t)k * a.nx * NVP, zd + 2 * k, sl.p, k, n, 0, n + 1, x,
-                              v, cx, cv, a0, a1, zx, zv, &acc, STORE ? &jumps : nullptr, &nj);
-        if (STORE) {
-            Real* r = row + (size_t)(k + 1) * 2 * kThreads;
-            __builtin_nontemporal_store(x, r);
-            __builtin_nontemporal_store(v, r + kThreads);
+    // A lane may run one interval ahead of the wave's slowest lane: each
+    // iteration every lane in interval kb (the wave's lowest) or kb + 1 takes
+    // its next sub-step, so a lane's extra sub-steps after a jump overlap the
+    // other lanes' next interval instead of idling them.  The two intervals'
+    // control rows and targets are wave-uniform (scalar loads) and each lane
+    // picks its own.
+    int k = 0, r = 0;
+    Real zx, zv, a0 = 0, a1;
+    int n = fb_interval(a, sl.p, 0, zx, zv, a1);
+    if (STORE)
+        __builtin_nontemporal_store((uint8_t)n, jumps.per);
+    for (int kb = 0; kb < a.N;) {
+        const Real* mk0 = mu + (size_t)kb * a.nx * NVP;
+        const Real* mk1 = kb + 1 < a.N ? mk0 + a.nx * NVP : mk0;
+        const Real* zk0 = zd + 2 * kb;
+        const Real* zk1 = kb + 1 < a.N ? zk0 + 2 : zk0;
+        if (k == kb || (k == kb + 1 && k < a.N)) {
+            const bool sel = k != kb;
+            const bool whole = n == 0;
+            const Real d = whole ? a.dt : (a1 - a0) * a.dt;
+            const Real u = fb_control_of<Real, NVP>(a, mk0, mk1, sel, x, v);
+            acc += (double)((whole ? a.hadt : (Real)0.5 * a.alpha * d) * u * u);
+            fb_euler(a, d, whole ? a.sqb1 : a.b1 * sqrt(d), whole ? a.sqb2 : a.b2 * sqrt(d), u,
+                     zx, zv, x, v, cx, cv);
+            if (r < n) {
+                uint32_t w[4];
+                philox4x32_10<false>(sl.p, (uint32_t)k, a.iter, (uint32_t)(r + 1), a.key0, a.key1,
+                                     w);
+                const Real S = bm_cos(bm_radius(w[2], (Real)0), unit_uniform<Real>(w[3]));
+                v = fma(S, a.sbeta, a.gamma * v);
+                cv = a.gamma * cv;
+                const Real R = bm_radius(w[0], (Real)0);
+                const Real ub = unit_uniform<Real>(w[1]);
+                zx = bm_cos(R, ub);
+                zv = bm_sin(R, ub);
+                if (STORE) {
+                    if (nj < kFbJumpCap) {
+                        jumps.st[(size_t)(kFbJumpComp * nj) * kThreads] = x;
+                        jumps.st[(size_t)(kFbJumpComp * nj + 1) * kThreads] = v;
+                        jumps.st[(size_t)(kFbJumpComp * nj + 2) * kThreads] = a1;
+                    }
+                }
+                ++nj;
+            }
+            {
+                const Real z[4] = {sel ? zk1[0] : zk0[0], sel ? zk1[1] : zk0[1],
+                                   sel ? zk1[2] : zk0[2], sel ? zk1[3] : zk0[3]};
+                Real tg[2];
+                fb_target(z, a1, tg);
+                acc += (double)(d * track(a, x, v, tg));
+            }
+            a0 = a1;
+            a1 = r + 1 < n ? fb_next_offset(a, sl.p, k, r + 1, n, a1) : (Real)1;
+            if (r < n) {
+                ++r;
+            } else {
+                // the interval is done: its end state is z_{k+1}
+                if (STORE) {
+                    Real* rw = row + (size_t)(k + 1) * 2 * kThreads;
+                    __builtin_nontemporal_store(x, rw);
+                    __builtin_nontemporal_store(v, rw + kThreads);
+                }
+                fb_dump(a, a.dX, k + 1, sl.p, x, v);
+                ++k;
+                r = 0;
+                if (k < a.N) {
+                    a0 = 0;
+                    n = fb_interval(a, sl.p, k, zx, zv, a1);
+                    if (STORE)
+                        __builtin_nontemporal_store((uint8_t)n, jumps.per + (size_t)k * kThreads);
+                }
+            }
         }
-        fb_dump(a, a.dX, k + 1, sl.p, x, v);
+        if (!__builtin_amdgcn_ballot_w64(k == kb))
+            ++kb;
     }
     if (STORE)
         *jumps.count = nj;
