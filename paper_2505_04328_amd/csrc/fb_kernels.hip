@@ -538,6 +538,11 @@ constexpr int fb_xs() { return sizeof(Real) == 4 ? 68 : 66; }
 // columns of B past the row count VR (read from row 0) hold finite leftovers;
 // they only reach entries of the product that no flush reads (i >= nx,
 // j >= nv).
+// Most products q that FbWave::add_live issues one by one (scalar operand
+// reads) before it takes the sixteen of add() (ja2 adjoint: 17.8 ms with add()
+// only, 16.9 ms at 4 or 8, 17.8 ms when it never takes add()).
+constexpr int kFbLiveMax = 8;
+
 template <typename Real, int VR>
 struct FbWave {
     typedef typename FbMma<Real>::acc_t acc_t;
@@ -575,6 +580,25 @@ struct FbWave {
 #pragma unroll
             for (int e = 0; e < E; ++e)
                 acc = FbMma<Real>::mfma(av[e], bv[e], acc);
+        }
+        wave_lds_sync();
+    }
+    // add() when only the particles set in the wave-uniform mask `live` carry
+    // a weight (the others put zero): products q that hold no live particle
+    // add exact zeros and are skipped, the rest run in the same order, so the
+    // sum is bitwise that of add().  Pays when few particles are live (a
+    // jump-adapted sub-step run for the wave's jumping lanes).
+    __device__ __forceinline__ void add_live(uint64_t live) {
+        uint32_t qm = (uint32_t)(live | live >> 16 | live >> 32 | live >> 48) & 0xFFFFu;
+        if (__builtin_popcount(qm) > kFbLiveMax) {
+            add();
+            return;
+        }
+        wave_lds_sync();
+        while (qm != 0) {
+            const int q = __builtin_ctz(qm);
+            qm &= qm - 1;
+            acc = FbMma<Real>::mfma(phx[ii][kb + q], phv[rv][kb + q], acc);
         }
         wave_lds_sync();
     }
@@ -1361,7 +1385,7 @@ k_fb_adjoint_adapted(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __
             }
             const Real wk = n == 0 ? fma(a.alpha, u, lvm) : (d / a.dt) * fma(a.alpha, u, lvm);
             wave.template put_vw<Real, NVP>(pv, mine && sl.act ? wk : (Real)0);
-            wave.add();
+            wave.add_live(__builtin_amdgcn_ballot_w64(mine && sl.act));
             if (mine) {
                 const Real au = a.alpha * u;
                 lx = fma(d, fma(au, ux, (ux - a.eta) * lvm), lxm);
