@@ -54,37 +54,39 @@ FWD_SLOTS_PER_PATH_STEP = 115
 ADJ_SLOTS_PER_PATH_STEP = 12
 # The paper's model problem (include/jd_feedback.h, f4: 2^20 particles, 500
 # steps, nx = nv = 10 shape functions), algorithmic slots per particle-step:
-# forward  20 bumps (difference, scale, 1 - q^2, clamp, reciprocal 4, scale,
-#          exp2 4 = 13 each) 260, control sum_i b_x,i sum_l mu_il b_v,l 110,
-#          Philox 77 + Poisson 4, Box-Muller both halves 27, Euler 6, FP64 cost
-#          (control and tracking terms, one exp) 18                      = 502
-# adjoint  20 bumps with derivatives (3 more products each: 16) 320, control,
-#          u_x and u_v (two dot products per row) 230, gradient weight,
-#          adjoint update and the tracking gradient (one exp) 24          = 574
+# forward  20 bumps (scaled distance eps x - i eps dx, 1 - q^2, clamp,
+#          reciprocal 4, scale, exp2 4 = 12 each) 240, control
+#          sum_i b_x,i sum_l mu_il b_v,l 110, Philox 77 + Poisson 4,
+#          Box-Muller both halves 27, Euler 6, FP64 cost (control and
+#          tracking terms, one exp) 18                                    = 482
+# adjoint  20 bumps with derivatives (3 more products each: 15) 300, control,
+#          u_x and u_v (two dot products per row, the derivative's -2 eps
+#          once per sum) 232, gradient weight, adjoint update and the
+#          tracking gradient (one exp) 24                                 = 556
 #          (the jump count is read from the trajectory, one byte the forward
 #          stored; regenerating it, as the surrogate adjoint does, adds
-#          Philox 77 + Poisson 4                                          = 655)
+#          Philox 77 + Poisson 4                                          = 637)
 # plus, on the matrix cores, 2 nx nv = 200 flops per particle-step for the
 # gradient's outer products.
-FB_FWD_SLOTS = 502
-FB_ADJ_SLOTS = 574
+FB_FWD_SLOTS = 482
+FB_ADJ_SLOTS = 556
 # Coupled rings (Section 6.4, ring2: 512 rings of 2000 particles, 500 steps):
 # the forward adds the ring force omega (2x - x_l - x_r) (4 slots) and the
 # ellipse cost q = x^2/ax^2 + v^2/av^2 - 1, q^2 (2 more than the tracking
 # cost); the adjoint adds -2 omega to u_x - eta (1), the neighbours' dt omega
 # (w_l + w_r) (2) and the ellipse gradient (3 more than the tracking one).  The
 # neighbour exchange itself is LDS traffic and barriers, not VALU work.
-RING_FWD_SLOTS = 508
-RING_ADJ_SLOTS = 580
+RING_FWD_SLOTS = 488
+RING_ADJ_SLOTS = 562
 # Jump-adapted grid (ja2 / ja3): the fixed-grid work per particle-step plus,
 # per jump (sigma dt of them per particle-step), one more sub-step: forward
-# control 370, Euler 6, the sub-step's Philox block and Box-Muller 104, its
-# offset (a quarter Philox block and one root, 28), running cost 18 = 526;
-# adjoint: the sub-step's adjoint without the count's Philox (574) and its
-# offset (28) = 602.  Recomputing the sub-step's start state and the lanes
+# control 350, Euler 6, the sub-step's Philox block and Box-Muller 104, its
+# offset (a quarter Philox block and one root, 28), running cost 18 = 506;
+# adjoint: the sub-step's adjoint without the count's Philox (556) and its
+# offset (28) = 584.  Recomputing the sub-step's start state and the lanes
 # that wait on a jumping lane in their wave are not algorithmic work.
-ADAPT_FWD_EXTRA = 526
-ADAPT_ADJ_EXTRA = 602
+ADAPT_FWD_EXTRA = 506
+ADAPT_ADJ_EXTRA = 584
 HBM_PEAK = 8.0e12  # B/s
 METRIC = "forward+adjoint path-steps/s (FP32 vs FP64 GPU) at 1e-6 rel grad err; p50/p99"
 

@@ -64,34 +64,33 @@ struct FbArgs {
     double* dcost;
 };
 
-// b(r) = exp(-1/(1 - (eps r)^2)) inside the support, 0 outside, and b'(r) =
-// b(r) (-2 eps^2 r) / (1 - (eps r)^2)^2.  s = 1 - (eps r)^2 is clamped below
-// at 1e-3: there the exact value exp(-1/s) <= e^-1000 is 0 in FP32 and FP64
-// alike, and so is the clamped one, so the clamp is exact and needs no branch.
-__device__ __forceinline__ float bump(float r, float eps) {
-    const float q = eps * r;
+// The bump of the shape functions at the scaled distance q = eps r:
+// b = exp(-1/(1 - q^2)) inside the support, 0 outside; bump_dq also returns
+// d = b q / (1 - q^2)^2, so that b'(r) = -2 eps d (callers apply -2 eps once
+// to their sums of d).  Callers form q as eps (x - c0) - i eps dc for the
+// centre c0 + i dc.  s = 1 - q^2 is clamped below at 1e-3: there the exact
+// value exp(-1/s) <= e^-1000 is 0 in FP32 and FP64 alike, and so is the
+// clamped one, so the clamp is exact and needs no branch.
+__device__ __forceinline__ float bump_q(float q) {
     const float s = fmaxf(fmaf(-q, q, 1.0f), 1e-3f);
     return __builtin_amdgcn_exp2f(-1.44269504088896340736f * __builtin_amdgcn_rcpf(s));
 }
-__device__ __forceinline__ double bump(double r, double eps) {
-    const double q = eps * r;
+__device__ __forceinline__ double bump_q(double q) {
     const double s = fmax(fma(-q, q, 1.0), 1e-3);
     return exp(-1.0 / s);
 }
-__device__ __forceinline__ float bump_d(float r, float eps, float& d) {
-    const float q = eps * r;
+__device__ __forceinline__ float bump_dq(float q, float& d) {
     const float s = fmaxf(fmaf(-q, q, 1.0f), 1e-3f);
     const float rs = __builtin_amdgcn_rcpf(s);
     const float b = __builtin_amdgcn_exp2f(-1.44269504088896340736f * rs);
-    d = b * (-2.0f * eps * eps * r) * rs * rs;
+    d = b * q * rs * rs;
     return b;
 }
-__device__ __forceinline__ double bump_d(double r, double eps, double& d) {
-    const double q = eps * r;
+__device__ __forceinline__ double bump_dq(double q, double& d) {
     const double s = fmax(fma(-q, q, 1.0), 1e-3);
     const double rs = 1.0 / s;
     const double b = exp(-rs);
-    d = b * (-2.0 * eps * eps * r) * rs * rs;
+    d = b * q * rs * rs;
     return b;
 }
 
@@ -143,7 +142,7 @@ template <typename Real, int NVP>
 __device__ __forceinline__ void shapes_v(const FbArgs<Real>& a, Real v, Real* pv) {
 #pragma unroll
     for (int l = 0; l < NVP; ++l)
-        pv[l] = bump(v - fma((Real)l, a.dvc, a.vc0), a.eps);
+        pv[l] = bump_q(fma(-(Real)l, a.eps * a.dvc, a.eps * (v - a.vc0)));
 }
 
 // Receives the shape-function values a step computes, and the control u
@@ -184,7 +183,7 @@ __device__ __forceinline__ Real fb_control(const FbArgs<Real>& a, const Real* __
     // registers, keeps one: 5.7 against 5.9 ms)
 #pragma unroll RU
     for (int i = 0; i < a.nx; ++i) {
-        const Real bx = bump(x - fma((Real)i, a.dxc, a.xc0), a.eps);
+        const Real bx = bump_q(fma(-(Real)i, a.eps * a.dxc, a.eps * (x - a.xc0)));
         const Real* rw = mk + i * NVP;
         Real t = 0;
 #pragma unroll
@@ -207,7 +206,7 @@ __device__ __forceinline__ Real fb_control_of(const FbArgs<Real>& a, const Real*
     Real u = 0;
 #pragma unroll 2
     for (int i = 0; i < a.nx; ++i) {
-        const Real bx = bump(x - fma((Real)i, a.dxc, a.xc0), a.eps);
+        const Real bx = bump_q(fma(-(Real)i, a.eps * a.dxc, a.eps * (x - a.xc0)));
         const Real* r0 = mk0 + i * NVP;
         const Real* r1 = mk1 + i * NVP;
         Real t = 0;
@@ -910,12 +909,12 @@ k_fb_adjoint(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __restrict
             Real pv[NVP], dpv[NVP];
 #pragma unroll
             for (int l = 0; l < NVP; ++l)
-                pv[l] = bump_d(st.v - fma((Real)l, a.dvc, a.vc0), a.eps, dpv[l]);
+                pv[l] = bump_dq(fma(-(Real)l, a.eps * a.dvc, a.eps * (st.v - a.vc0)), dpv[l]);
             Real u = 0, ux = 0, uv = 0;
 #pragma unroll 2
             for (int i = 0; i < a.nx; ++i) {
                 Real dbx;
-                const Real bx = bump_d(st.x - fma((Real)i, a.dxc, a.xc0), a.eps, dbx);
+                const Real bx = bump_dq(fma(-(Real)i, a.eps * a.dxc, a.eps * (st.x - a.xc0)), dbx);
                 const Real* rw = mk + i * NVP;
                 Real t = 0, sv = 0;
 #pragma unroll
@@ -928,6 +927,8 @@ k_fb_adjoint(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __restrict
                 uv = fma(bx, sv, uv);
                 wave.put_x(i, bx);
             }
+            ux *= (Real)-2 * a.eps;  // d carries b'(r) / (-2 eps)
+            uv *= (Real)-2 * a.eps;
             const Real wk = SURR ? gn * st.lv : fma(a.alpha, u, gn * st.lv);
             wave.template put_vw<Real, NVP>(pv, act[j] ? wk : (Real)0);
             wave.add();
@@ -1365,12 +1366,12 @@ k_fb_adjoint_adapted(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __
             Real pv[NVP], dpv[NVP];
 #pragma unroll
             for (int l = 0; l < NVP; ++l)
-                pv[l] = bump_d(v - fma((Real)l, a.dvc, a.vc0), a.eps, dpv[l]);
+                pv[l] = bump_dq(fma(-(Real)l, a.eps * a.dvc, a.eps * (v - a.vc0)), dpv[l]);
             Real u = 0, ux = 0, uv = 0;
 #pragma unroll 2
             for (int i = 0; i < a.nx; ++i) {
                 Real dbx;
-                const Real bx = bump_d(x - fma((Real)i, a.dxc, a.xc0), a.eps, dbx);
+                const Real bx = bump_dq(fma(-(Real)i, a.eps * a.dxc, a.eps * (x - a.xc0)), dbx);
                 const Real* rw = mk + i * NVP;
                 Real t = 0, sv = 0;
 #pragma unroll
@@ -1383,6 +1384,8 @@ k_fb_adjoint_adapted(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __
                 uv = fma(bx, sv, uv);
                 wave.put_x(i, bx);
             }
+            ux *= (Real)-2 * a.eps;  // d carries b'(r) / (-2 eps)
+            uv *= (Real)-2 * a.eps;
             const Real wk = n == 0 ? fma(a.alpha, u, lvm) : (d / a.dt) * fma(a.alpha, u, lvm);
             wave.template put_vw<Real, NVP>(pv, mine && sl.act ? wk : (Real)0);
             wave.add_live(__builtin_amdgcn_ballot_w64(mine && sl.act));
