@@ -75,9 +75,19 @@ __device__ __forceinline__ float bump_q(float q) {
     const float s = fmaxf(fmaf(-q, q, 1.0f), 1e-3f);
     return __builtin_amdgcn_exp2f(-1.44269504088896340736f * __builtin_amdgcn_rcpf(s));
 }
+// 1/s for s in [1e-3, 1]: the hardware estimate refined by two steps of
+// Newton's iteration r <- r + r (1 - s r), each of which squares the relative
+// error, so the estimate's ~2^-26 ends within an ulp or two of the quotient
+// (an IEEE division costs about twice the instructions: f4 FP64 step 42.4 ->
+// 41.0 ms, ring2 FP64 45.7 -> 43.2 ms).
+__device__ __forceinline__ double fb_rcp(double s) {
+    double r = __builtin_amdgcn_rcp(s);
+    r = fma(fma(-s, r, 1.0), r, r);
+    return fma(fma(-s, r, 1.0), r, r);
+}
 __device__ __forceinline__ double bump_q(double q) {
     const double s = fmax(fma(-q, q, 1.0), 1e-3);
-    return exp(-1.0 / s);
+    return exp(-fb_rcp(s));
 }
 __device__ __forceinline__ float bump_dq(float q, float& d) {
     const float s = fmaxf(fmaf(-q, q, 1.0f), 1e-3f);
@@ -88,7 +98,7 @@ __device__ __forceinline__ float bump_dq(float q, float& d) {
 }
 __device__ __forceinline__ double bump_dq(double q, double& d) {
     const double s = fmax(fma(-q, q, 1.0), 1e-3);
-    const double rs = 1.0 / s;
+    const double rs = fb_rcp(s);
     const double b = exp(-rs);
     d = b * q * rs * rs;
     return b;
