@@ -1396,7 +1396,8 @@ k_fb_adjoint_adapted(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __
             }
             ux *= (Real)-2 * a.eps;  // d carries b'(r) / (-2 eps)
             uv *= (Real)-2 * a.eps;
-            const Real wk = n == 0 ? fma(a.alpha, u, lvm) : (d / a.dt) * fma(a.alpha, u, lvm);
+            // the sub-step's share d / dt of the step is a1 - a0
+            const Real wk = n == 0 ? fma(a.alpha, u, lvm) : (a1 - a0) * fma(a.alpha, u, lvm);
             wave.template put_vw<Real, NVP>(pv, mine && sl.act ? wk : (Real)0);
             wave.add_live(__builtin_amdgcn_ballot_w64(mine && sl.act));
             if (mine) {
