@@ -44,8 +44,10 @@
  *    the library allocates no device memory.  Host arrays inside jd_problem
  *    are read during the call only.
  *  - All work is enqueued on `stream` and the call returns without waiting,
- *    except jd_optimize, which synchronizes the stream once per line-search
- *    trial.  Kernel faults surface as JD_EHIP from a later call on the stream.
+ *    except jd_optimize, which runs the line search on the device and
+ *    synchronizes the stream once per batch of up to 64 iterations (see
+ *    jd_optimize).  Kernel faults surface as JD_EHIP from a later call on the
+ *    stream.
  *  - d in 1..8 (internally padded to 1, 2, 4 or 8 with inert components).
  *  - u and g are FP64, row-major N x d (u[k*d + c]).  J is one FP64.
  *  - Calls on different streams with different workspaces may run
@@ -193,11 +195,21 @@ int jd_cost_grad(const jd_problem* prob, const jd_run* run, const double* u, dou
 /* Gradient iteration (Section 5, Algorithm 5.4): for n = 0, 1, ...: evaluate
  * J(u^n), g^n with counter word run->iter + n, then try u' = u^n - zeta g^n for
  * zeta = zeta0, rho zeta0, ... with the same counter word (common random
- * numbers) until J(u') <= J(u^n) - c zeta ||g^n||^2_L2; stop after n_max
- * iterations or when ||u' - u^n||_L2 <= tol.  u (device FP64 N*d) is updated
- * in place; log (host, n_max entries, may be NULL) gets one record per
- * iteration and *iters_done (host, may be NULL) the number done.  Synchronizes
- * `stream`.  JD_ELINESEARCH leaves u at the last accepted iterate. */
+ * numbers) until J(u') is finite and J(u') <= J(u^n) - c zeta ||g^n||^2_L2
+ * (eq. Stochastic_Armijo; a trial whose cost overflows is rejected like any
+ * other); stop after n_max iterations or when ||u' - u^n||_L2 <= tol.  u
+ * (device FP64 N*d) is updated in place; log (host, n_max entries, may be
+ * NULL) gets one record per iteration and *iters_done (host, may be NULL) the
+ * number done.
+ * The Armijo decisions, the step and the stopping test are taken on the
+ * device: the library enqueues the evaluation and a few trials of each of up
+ * to 64 iterations, each gated by a phase word in the workspace header that
+ * the device advances, then synchronizes `stream` once to read the outcome
+ * and the iterations' log (and again only when an iteration needed more
+ * trials than were enqueued).  The results are those of taking one trial at a
+ * time.  Returns JD_ELINESEARCH (u at the last accepted iterate) when no
+ * trial of max_backtracks is accepted, JD_ENONFINITE when J(u^n) or g^n is not
+ * finite. */
 int jd_optimize(const jd_problem* prob, const jd_run* run, const jd_opt* opt, double* u,
                 jd_iter_log* log, int32_t* iters_done, void* traj, void* ws,
                 size_t ws_bytes, hipStream_t stream);

@@ -180,8 +180,10 @@ int jd_fb_cost_grad(const jd_fb_problem* prob, const jd_run* run, const double* 
                     double* grad, void* traj, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* Gradient iteration (Algorithm 5.4 with eq. Stochastic_Armijo), exactly as
- * jd_optimize: iteration n uses counter word run->iter + n for the gradient
- * and every trial; mu (device FP64 N x L) is updated in place. */
+ * jd_optimize (the line search decided on the device, one synchronization per
+ * batch of up to 64 iterations, a trial whose cost overflows rejected):
+ * iteration n uses counter word run->iter + n for the gradient and every
+ * trial; mu (device FP64 N x L) is updated in place. */
 int jd_fb_optimize(const jd_fb_problem* prob, const jd_run* run, const jd_opt* opt, double* mu,
                    jd_iter_log* log, int32_t* iters_done, void* traj, void* ws, size_t ws_bytes,
                    hipStream_t stream);

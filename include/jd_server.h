@@ -15,10 +15,15 @@
  *
  * Execution: admitted requests are spread over the streams; each request's
  * iteration runs the same kernels as jd_optimize (forward sweep, adjoint
- * sweep, reductions, Armijo trials on the same counters), so a request's
- * result is bit-identical alone and in any mix.  jd_server_progress never
- * blocks: it advances every request whose last enqueued step has completed
- * and admits queued requests.
+ * sweep, reductions, Armijo trials on the same counters, the line search
+ * decided on the device), so a request's result is bit-identical alone and in
+ * any mix.  The server enqueues a few iterations of a request at a time and
+ * looks at it again when they have completed.  jd_server_progress never
+ * blocks: it advances every request whose last enqueued batch has completed
+ * and admits queued requests.  A request that fails after it was queued
+ * (admission, enqueueing, a device error) ends with that error as its status
+ * and returns no control; its memory is reused only after its stream has
+ * drained.
  *
  * Threading: one host thread drives a server.  Errors as in jd.h.
  */

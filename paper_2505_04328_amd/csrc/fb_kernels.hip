@@ -57,6 +57,7 @@ struct FbArgs {
     int init_kind;
     uint32_t key0, key1, iter;
     const PoissonTable* thr;
+    Gate gate;  // launch gate (word null: always runs)
     double dt64;
     int64_t dm0, dcount;  // per-path dumps
     Real* dX;
@@ -417,7 +418,9 @@ template <typename Real>
 __global__ void __launch_bounds__(kThreads)
 k_fb_table(const double* __restrict__ mu, const double* __restrict__ zd, Real* __restrict__ tab,
            int N, int nx, int nv, int nvp, size_t off_zd, size_t off_ks, FbKs ks, WsHeader* hdr,
-           int clear_flag, PoissonTable pt) {
+           int clear_flag, PoissonTable pt, Gate gate) {
+    if (gate_closed(gate))
+        return;
     const int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     const int64_t nmu = (int64_t)N * nx * nvp;
     if (idx < nmu) {
@@ -446,6 +449,8 @@ template <typename Real, int NVP, bool STORE, int G, bool RING, int TPB = kThrea
 __global__ void __launch_bounds__(TPB, TPB == 1024 && sizeof(Real) == 4 ? 8 : 1)
 k_fb_forward(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __restrict__ zd,
              const Real* __restrict__ ks, void* traj, double* __restrict__ cpart) {
+    if (gate_closed(a.gate))
+        return;
     static_assert(RING || (G == 1 && TPB == kThreads), "independent particles run one per lane");
     __shared__ double sh[TPB];
     __shared__ Real xs[RING ? 2 : 1][RING ? G * TPB : 1];
@@ -776,6 +781,8 @@ __global__ void __launch_bounds__(kThreads)
 k_fb_forward_grad(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __restrict__ zd,
                   const Real* __restrict__ ks, double* __restrict__ cpart,
                   double* __restrict__ apart) {
+    if (gate_closed(a.gate))
+        return;
     __shared__ FbShared<Real, fb_vrows<NVP>()> sh;
     __shared__ double red[kThreads];
     auto wave = fb_wave(sh);
@@ -868,6 +875,8 @@ template <typename Real, int NVP, int G, bool SURR, bool RING, int TPB = kThread
 __global__ void __launch_bounds__(TPB, (fb_adj_waves<Real, NVP, RING>()))
 k_fb_adjoint(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __restrict__ zd,
              const Real* __restrict__ ks, const void* traj, double* __restrict__ apart) {
+    if (gate_closed(a.gate))
+        return;
     static_assert(!(SURR && RING), "the surrogate gradient takes independent particles");
     static_assert(RING || TPB == kThreads, "independent particles run in blocks of 256");
     __shared__ FbShared<Real, fb_vrows<NVP>(), TPB / 64> sh;
@@ -1177,6 +1186,8 @@ template <typename Real, int NVP, bool STORE>
 __global__ void __launch_bounds__(kThreads, (sizeof(Real) == 8 ? 3 : 1))
 k_fb_forward_adapted(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __restrict__ zd,
                      void* traj, double* __restrict__ cpart) {
+    if (gate_closed(a.gate))
+        return;
     __shared__ double sh[kThreads];
     const FbSlot sl = fb_slot<1>(a, 0);
     Real x, v, cx = 0, cv = 0;
@@ -1297,6 +1308,8 @@ template <typename Real, int NVP>
 __global__ void __launch_bounds__(kThreads, (sizeof(Real) == 4 ? 4 : 2))
 k_fb_adjoint_adapted(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __restrict__ zd,
                      const void* traj, double* __restrict__ apart) {
+    if (gate_closed(a.gate))
+        return;
     // four held tiles: FP32 needs all 16 velocity rows for them
     __shared__ FbShared<Real, sizeof(Real) == 4 ? kFbMaxGrid : fb_vrows<NVP>()> sh;
     auto wave = fb_wave(sh);
@@ -1454,7 +1467,9 @@ constexpr int kFbFinChunks = kThreads / kFbFinEntries;
 
 __global__ void __launch_bounds__(kThreads)
 k_fb_finalize_grad(const double* __restrict__ apart, int nblk, int64_t NL, int64_t M,
-                   double* __restrict__ g, WsHeader* hdr) {
+                   double* __restrict__ g, WsHeader* hdr, Gate gate) {
+    if (gate_closed(gate))
+        return;
     __shared__ double sh[kThreads];
     const int e = threadIdx.x % kFbFinEntries, c = threadIdx.x / kFbFinEntries;
     const int64_t q = (int64_t)blockIdx.x * kFbFinEntries + e;
@@ -1482,7 +1497,9 @@ k_fb_finalize_grad(const double* __restrict__ apart, int nblk, int64_t NL, int64
 __global__ void __launch_bounds__(kThreads)
 k_fb_finalize_cost(const double* __restrict__ cpart, int nblk, int64_t M, double dt,
                    const double* __restrict__ g, int64_t NL, double* __restrict__ J_out,
-                   WsHeader* hdr, int slot) {
+                   WsHeader* hdr, int slot, Gate gate) {
+    if (gate_closed(gate))
+        return;
     __shared__ double sh[kThreads];
     double s = 0.0;
     for (int b = threadIdx.x; b < nblk; b += kThreads)
@@ -1505,7 +1522,8 @@ k_fb_finalize_cost(const double* __restrict__ cpart, int nblk, int64_t M, double
         }
         if (J_out != nullptr)
             *J_out = J;
-        if (!isfinite(J) || !isfinite(gg))
+        // a trial's cost (slot 1) may overflow: the Armijo test rejects it
+        if (slot == 0 && (!isfinite(J) || !isfinite(gg)))
             hdr->nonfinite = 1;
     }
 }
@@ -1607,6 +1625,7 @@ static FbArgs<Real> fb_args(const FbHost& p, const HostRun& r) {
     a.key1 = (uint32_t)(r.seed >> 32);
     a.iter = r.iter;
     a.thr = nullptr;
+    a.gate = kNoGate;
     a.dt64 = p.dt;
     a.dm0 = 0;
     a.dcount = 0;
@@ -1626,7 +1645,7 @@ static FbArgs<Real> fb_args(const FbHost& p, const HostRun& r) {
 static inline unsigned fb_blocks(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
 
 hipError_t fb_launch_table(const FbHost& p, const HostRun& r, const double* mu, void* tab,
-                           WsHeader* hdr, int clear_flag, hipStream_t st) {
+                           WsHeader* hdr, int clear_flag, hipStream_t st, Gate gate) {
     const FbTable t = fb_table_layout(p);
     FbKs ks;
     for (int i = 0; i < 64; ++i)
@@ -1639,11 +1658,11 @@ hipError_t fb_launch_table(const FbHost& p, const HostRun& r, const double* mu, 
     if (r.prec == JD_FP64)
         hipLaunchKernelGGL(k_fb_table<double>, dim3(fb_blocks(n)), dim3(kThreads), 0, st, mu, p.zd,
                            (double*)tab, p.N, p.nx, p.nv, p.nvp, t.zd, t.ks, ks, hdr, clear_flag,
-                           p.poisson);
+                           p.poisson, gate);
     else
         hipLaunchKernelGGL(k_fb_table<float>, dim3(fb_blocks(n)), dim3(kThreads), 0, st, mu, p.zd,
                            (float*)tab, p.N, p.nx, p.nv, p.nvp, t.zd, t.ks, ks, hdr, clear_flag,
-                           p.poisson);
+                           p.poisson, gate);
     return hipGetLastError();
 }
 
@@ -1692,10 +1711,11 @@ int fb_forward_blocks(const FbHost& p, const HostRun& r) {
 
 template <typename Real>
 static hipError_t fb_forward_t(const FbHost& p, const HostRun& r, const void* tab, void* traj,
-                               double* cpart, const WsHeader* hdr, hipStream_t st) {
+                               double* cpart, const WsHeader* hdr, hipStream_t st, Gate gate) {
     const FbTable t = fb_table_layout(p);
     FbArgs<Real> a = fb_args<Real>(p, r);
     a.thr = &hdr->poisson;
+    a.gate = gate;
     const Real* tb = (const Real*)tab;
     const unsigned nb = (unsigned)fb_forward_blocks(p, r);
 #define FB_FWD_K(NVP, S, GG, RG, TPB)                                                             \
@@ -1728,9 +1748,9 @@ static hipError_t fb_forward_t(const FbHost& p, const HostRun& r, const void* ta
 }
 
 hipError_t fb_launch_forward(const FbHost& p, const HostRun& r, const void* tab, void* traj,
-                             double* cpart, const WsHeader* hdr, hipStream_t st) {
-    return r.prec == JD_FP64 ? fb_forward_t<double>(p, r, tab, traj, cpart, hdr, st)
-                             : fb_forward_t<float>(p, r, tab, traj, cpart, hdr, st);
+                             double* cpart, const WsHeader* hdr, hipStream_t st, Gate gate) {
+    return r.prec == JD_FP64 ? fb_forward_t<double>(p, r, tab, traj, cpart, hdr, st, gate)
+                             : fb_forward_t<float>(p, r, tab, traj, cpart, hdr, st, gate);
 }
 
 // 256-particle groups per block of the independent-particle adjoint (and of
@@ -1751,10 +1771,12 @@ static int fb_adjoint_groups(const FbHost& p, const HostRun& r) {
 
 template <typename Real>
 static hipError_t fb_adjoint_t(const FbHost& p, const HostRun& r, const void* tab, const void* traj,
-                               double* apart, const WsHeader* hdr, bool surr, hipStream_t st) {
+                               double* apart, const WsHeader* hdr, bool surr, hipStream_t st,
+                               Gate gate) {
     const FbTable t = fb_table_layout(p);
     FbArgs<Real> a = fb_args<Real>(p, r);
     a.thr = &hdr->poisson;
+    a.gate = gate;
     const Real* tb = (const Real*)tab;
     const int G = fb_adjoint_groups(p, r);
     const unsigned nb = (unsigned)fb_partial_blocks(p, r);
@@ -1793,18 +1815,21 @@ static hipError_t fb_adjoint_t(const FbHost& p, const HostRun& r, const void* ta
 }
 
 hipError_t fb_launch_adjoint(const FbHost& p, const HostRun& r, const void* tab, const void* traj,
-                             double* apart, const WsHeader* hdr, bool surrogate, hipStream_t st) {
-    return r.prec == JD_FP64 ? fb_adjoint_t<double>(p, r, tab, traj, apart, hdr, surrogate, st)
-                             : fb_adjoint_t<float>(p, r, tab, traj, apart, hdr, surrogate, st);
+                             double* apart, const WsHeader* hdr, bool surrogate, hipStream_t st,
+                             Gate gate) {
+    return r.prec == JD_FP64
+               ? fb_adjoint_t<double>(p, r, tab, traj, apart, hdr, surrogate, st, gate)
+               : fb_adjoint_t<float>(p, r, tab, traj, apart, hdr, surrogate, st, gate);
 }
 
 template <typename Real>
 static hipError_t fb_forward_grad_t(const FbHost& p, const HostRun& r, const void* tab,
                                     double* cpart, double* apart, const WsHeader* hdr,
-                                    hipStream_t st) {
+                                    hipStream_t st, Gate gate) {
     const FbTable t = fb_table_layout(p);
     FbArgs<Real> a = fb_args<Real>(p, r);
     a.thr = &hdr->poisson;
+    a.gate = gate;
     const Real* tb = (const Real*)tab;
     const int G = fb_adjoint_groups(p, r);
     const unsigned nb = (unsigned)fb_partial_blocks(p, r);
@@ -1826,9 +1851,9 @@ static hipError_t fb_forward_grad_t(const FbHost& p, const HostRun& r, const voi
 }
 
 hipError_t fb_launch_forward_grad(const FbHost& p, const HostRun& r, const void* tab, double* cpart,
-                                  double* apart, const WsHeader* hdr, hipStream_t st) {
-    return r.prec == JD_FP64 ? fb_forward_grad_t<double>(p, r, tab, cpart, apart, hdr, st)
-                             : fb_forward_grad_t<float>(p, r, tab, cpart, apart, hdr, st);
+                                  double* apart, const WsHeader* hdr, hipStream_t st, Gate gate) {
+    return r.prec == JD_FP64 ? fb_forward_grad_t<double>(p, r, tab, cpart, apart, hdr, st, gate)
+                             : fb_forward_grad_t<float>(p, r, tab, cpart, apart, hdr, st, gate);
 }
 
 int fb_partial_blocks(const FbHost& p, const HostRun& r) {
@@ -1837,19 +1862,19 @@ int fb_partial_blocks(const FbHost& p, const HostRun& r) {
 }
 
 hipError_t fb_launch_finalize_grad(const FbHost& p, const HostRun& r, const double* apart,
-                                   double* g, WsHeader* hdr, hipStream_t st) {
+                                   double* g, WsHeader* hdr, hipStream_t st, Gate gate) {
     const int64_t NL = (int64_t)p.N * p.L;
     hipLaunchKernelGGL(k_fb_finalize_grad,
                        dim3((unsigned)((NL + kFbFinEntries - 1) / kFbFinEntries)), dim3(kThreads), 0,
-                       st, apart, fb_partial_blocks(p, r), NL, r.M, g, hdr);
+                       st, apart, fb_partial_blocks(p, r), NL, r.M, g, hdr, gate);
     return hipGetLastError();
 }
 
 hipError_t fb_launch_finalize_cost(const FbHost& p, const HostRun& r, const double* cpart,
                                    int ncpart, const double* g, double* J_out, WsHeader* hdr,
-                                   int slot, hipStream_t st) {
+                                   int slot, hipStream_t st, Gate gate) {
     hipLaunchKernelGGL(k_fb_finalize_cost, dim3(1), dim3(kThreads), 0, st, cpart, ncpart, r.M,
-                       p.dt, g, (int64_t)p.N * p.L, J_out, hdr, slot);
+                       p.dt, g, (int64_t)p.N * p.L, J_out, hdr, slot, gate);
     return hipGetLastError();
 }
 

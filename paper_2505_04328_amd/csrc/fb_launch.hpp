@@ -40,17 +40,20 @@ struct FbTable {
 FbTable fb_table_layout(const FbHost& p);
 
 hipError_t fb_launch_table(const FbHost& p, const HostRun& r, const double* mu, void* tab,
-                           WsHeader* hdr, int clear_flag, hipStream_t st);
+                           WsHeader* hdr, int clear_flag, hipStream_t st, Gate gate = kNoGate);
 hipError_t fb_launch_forward(const FbHost& p, const HostRun& r, const void* tab, void* traj,
-                             double* cpart, const WsHeader* hdr, hipStream_t st);
+                             double* cpart, const WsHeader* hdr, hipStream_t st,
+                             Gate gate = kNoGate);
 // surrogate: the adjoint on the surrogate states, added to the partials of
 // fb_launch_forward_grad (Section 6.5); else the exact adjoint over traj.
 hipError_t fb_launch_adjoint(const FbHost& p, const HostRun& r, const void* tab, const void* traj,
-                             double* apart, const WsHeader* hdr, bool surrogate, hipStream_t st);
+                             double* apart, const WsHeader* hdr, bool surrogate, hipStream_t st,
+                             Gate gate = kNoGate);
 // Storage-free forward that also writes the alpha u phi(z) part of the
 // gradient partials (surrogate gradient) and the per-block costs.
 hipError_t fb_launch_forward_grad(const FbHost& p, const HostRun& r, const void* tab, double* cpart,
-                                  double* apart, const WsHeader* hdr, hipStream_t st);
+                                  double* apart, const WsHeader* hdr, hipStream_t st,
+                                  Gate gate = kNoGate);
 // Number of per-block partials of the adjoint / forward_grad kernels, and of
 // the per-block costs of the forward kernel.
 int fb_partial_blocks(const FbHost& p, const HostRun& r);
@@ -58,10 +61,10 @@ int fb_forward_blocks(const FbHost& p, const HostRun& r);
 // 256-slot groups per workgroup of the ring kernels for rings of np particles.
 int fb_ring_groups(int np);
 hipError_t fb_launch_finalize_grad(const FbHost& p, const HostRun& r, const double* apart,
-                                   double* g, WsHeader* hdr, hipStream_t st);
+                                   double* g, WsHeader* hdr, hipStream_t st, Gate gate = kNoGate);
 hipError_t fb_launch_finalize_cost(const FbHost& p, const HostRun& r, const double* cpart,
                                    int ncpart, const double* g, double* J_out, WsHeader* hdr,
-                                   int slot, hipStream_t st);
+                                   int slot, hipStream_t st, Gate gate = kNoGate);
 hipError_t fb_launch_draws(const FbHost& p, const HostRun& r, int64_t m0, int64_t mc, int k0,
                            int kc, void* z_init, void* Z, int32_t* counts, hipStream_t st);
 

@@ -82,12 +82,8 @@ int prepare(const jd_problem* prob, const jd_run* run, HostProblem& p, HostRun& 
     if (run->mode != JD_STORE && run->mode != JD_RECOMPUTE)
         return JD_EINVAL;
     const int D = padded_dim(d);
-    if (run->mode == JD_RECOMPUTE) {
-        if (run->K < 1 || run->K > N)
-            return JD_EINVAL;
-        if (!recompute_supported(run->precision, D, run->K))
-            return JD_EUNSUPPORTED;
-    }
+    if (run->mode == JD_RECOMPUTE && (run->K < 1 || run->K > N))
+        return JD_EINVAL;
     if (run->dump) {
         const jd_dump* dp = run->dump;
         if (dp->m0 < 0 || dp->count < 0 || dp->m0 + dp->count > run->M)
@@ -127,6 +123,8 @@ int prepare(const jd_problem* prob, const jd_run* run, HostProblem& p, HostRun& 
     r.K = run->mode == JD_RECOMPUTE ? run->K : 0;
     r.nblk = (int)((run->M + kBlock - 1) / kBlock);
     r.dump = run->dump;
+    if (r.mode == JD_RECOMPUTE && !recompute_supported(p, r))
+        return JD_EUNSUPPORTED;
     return JD_OK;
 }
 
@@ -135,6 +133,8 @@ Layout layout(const HostProblem& p, const HostRun& r) {
     size_t off = 0;
     L.hdr = off;
     off += round_up(sizeof(WsHeader), kAlign);
+    L.ring = off;
+    off += round_up(kLsLogCap * sizeof(LsLog), kAlign);
     L.tab = off;
     off += round_up((size_t)p.N * 2 * p.D * real_size(r.prec), kAlign);
     L.cpart = off;
@@ -145,6 +145,8 @@ Layout layout(const HostProblem& p, const HostRun& r) {
     off += round_up((size_t)p.N * p.d * sizeof(double), kAlign);
     L.ut = off;
     off += round_up((size_t)p.N * p.d * sizeof(double), kAlign);
+    L.seg = off;
+    off += round_up(seg_scratch_bytes(p, r), kAlign);
     L.total = off + kAlign;  // slack for aligning the caller's pointer
     return L;
 }
@@ -162,11 +164,13 @@ int bind_ws(const HostProblem& p, const HostRun& r, void* ws, size_t ws_bytes, W
         return JD_EWORKSPACE;
     char* base = (char*)round_up((size_t)(uintptr_t)ws, kAlign);
     w.hdr = (WsHeader*)(base + L.hdr);
+    w.ring = (LsLog*)(base + L.ring);
     w.tab = base + L.tab;
     w.cpart = (double*)(base + L.cpart);
     w.apart = (double*)(base + L.apart);
     w.gbuf = (double*)(base + L.gbuf);
     w.ut = (double*)(base + L.ut);
+    w.seg = base + L.seg;
     return JD_OK;
 }
 
@@ -182,33 +186,130 @@ int enqueue_forward(const HostProblem& p, const HostRun& r, const double* u, voi
 }
 
 int enqueue_cost_grad(const HostProblem& p, const HostRun& r, const double* u, double* J,
-                      double* g, void* traj, const Ws& w, hipStream_t st) {
-    JD_TRY(launch_setup(p, r, u, w.tab, w.hdr, 1, st));
+                      double* g, void* traj, const Ws& w, hipStream_t st, Gate gate) {
+    JD_TRY(launch_setup(p, r, u, w.tab, w.hdr, 1, st, gate));
     // One kernel (each block's forward, then its backward sweep) up to d = 4;
     // at d = 8 the separate kernels are faster (FP32 c3: 9.4 against 10.2 ms,
     // c4: 9.8 against 11.6 ms); the results are bitwise the same.
     if (r.mode == JD_STORE && r.dump == nullptr && p.D <= 4) {
-        JD_TRY(launch_cost_grad_stored(p, r, w.tab, traj, w.cpart, w.apart, w.hdr, st));
+        JD_TRY(launch_cost_grad_stored(p, r, w.tab, traj, w.cpart, w.apart, w.hdr, st, gate));
     } else {
         const int fm = r.mode == JD_RECOMPUTE ? FWD_CKPT : FWD_STORE;
-        JD_TRY(launch_forward(p, r, w.tab, traj, fm, w.cpart, w.hdr, st));
-        JD_TRY(launch_adjoint(p, r, w.tab, traj, w.apart, w.hdr, st));
+        JD_TRY(launch_forward(p, r, w.tab, traj, fm, w.cpart, w.hdr, st, gate));
+        JD_TRY(launch_adjoint(p, r, w.tab, traj, w.apart, w.seg, w.hdr, st, gate));
     }
-    JD_TRY(launch_finalize_grad(p, r, w.apart, u, g, w.hdr, st));
-    JD_TRY(launch_finalize_cost(p, r, w.cpart, u, g, J, w.hdr, 0, st));
+    JD_TRY(launch_finalize_grad(p, r, w.apart, u, g, w.hdr, st, gate));
+    JD_TRY(launch_finalize_cost(p, r, w.cpart, u, g, J, w.hdr, 0, st, gate));
     return JD_OK;
 }
 
-int enqueue_trial(const HostProblem& p, const HostRun& r, double* u, const jd_opt& opt, double zeta,
-                  const Ws& w, hipStream_t st) {
+int enqueue_trial(const HostProblem& p, const HostRun& r, const double* u, double zeta,
+                  const Ws& w, hipStream_t st, Gate gate) {
     const int nd = p.N * p.d;
-    JD_TRY(launch_trial(u, w.gbuf, zeta, w.ut, nd, st));
-    JD_TRY(launch_setup(p, r, w.ut, w.tab, w.hdr, 0, st));
-    JD_TRY(launch_forward(p, r, w.tab, nullptr, FWD_COST, w.cpart, w.hdr, st));
-    JD_TRY(launch_finalize_cost(p, r, w.cpart, w.ut, nullptr, nullptr, w.hdr, 1, st));
-    JD_TRY(launch_armijo(w.hdr, u, w.ut, nd, opt.c_armijo, zeta, p.dt, st));
+    JD_TRY(launch_trial(u, w.gbuf, zeta, w.ut, nd, st, gate));
+    JD_TRY(launch_setup(p, r, w.ut, w.tab, w.hdr, 0, st, gate));
+    JD_TRY(launch_forward(p, r, w.tab, nullptr, FWD_COST, w.cpart, w.hdr, st, gate));
+    JD_TRY(launch_finalize_cost(p, r, w.cpart, w.ut, nullptr, nullptr, w.hdr, 1, st, gate));
     return JD_OK;
 }
+
+// ---------------------------------------------------------------------------
+int LsDriver::start(hipStream_t st) {
+    JD_TRY(launch_ls_start(hdr, st));
+    return JD_OK;
+}
+
+int LsDriver::enqueue(LsOps& ops, int iters, hipStream_t st) {
+    const int end = opt.n_max - n_next < iters ? opt.n_max : n_next + iters;
+    int j0 = j_next;
+    for (int n = n_next; n < end; ++n) {
+        int rc;
+        if (j0 < 0) {
+            if ((rc = ops.grad(n, gate_of(hdr, ls_phase(n, -1)), st)))
+                return rc;
+            JD_TRY(launch_ls_after_grad(hdr, n, st));
+            j0 = 0;
+        }
+        // zeta_j = zeta0 rho^j by repeated multiplication, as one trial at a time
+        double zeta = opt.zeta0;
+        for (int j = 0; j < j0; ++j)
+            zeta *= opt.rho;
+        const int jend = opt.max_backtracks - j0 < ahead ? opt.max_backtracks : j0 + ahead;
+        for (int j = j0; j < jend; ++j) {
+            if ((rc = ops.trial(n, zeta, gate_of(hdr, ls_phase(n, j)), st)))
+                return rc;
+            LsArmijo a;
+            a.c_armijo = opt.c_armijo;
+            a.zeta = zeta;
+            a.dt = dt;
+            a.tol = opt.tol;
+            a.n = n;
+            a.j = j;
+            a.n_max = opt.n_max;
+            a.max_backtracks = opt.max_backtracks;
+            a.iter = iter0 + (uint32_t)n;
+            JD_TRY(launch_armijo(hdr, ring, u, ut, nd, a, st));
+            zeta *= opt.rho;
+        }
+        j0 = -1;
+    }
+    return JD_OK;
+}
+
+bool LsDriver::collect(const void* mirror, jd_iter_log* log) {
+    const WsHeader& h = *(const WsHeader*)mirror;
+    const LsLog* rl = (const LsLog*)((const char*)mirror + sizeof(WsHeader));
+    int most = 0;
+    for (int i = copied; i < h.ls_done; ++i) {
+        const LsLog& L = rl[i % kLsLogCap];
+        if (log) {
+            log[i].iter = L.iter;
+            log[i].backtracks = L.backtracks;
+            log[i].J = L.J;
+            log[i].gnorm = sqrt(L.gnorm2);
+            log[i].zeta = L.zeta;
+            log[i].J_new = L.J_new;
+            log[i].E = sqrt(L.E2);
+        }
+        most = L.backtracks > most ? L.backtracks : most;
+    }
+    copied = h.ls_done;
+    if (h.ls_status != kLsRunning) {
+        status = h.ls_status == kLsDone ? JD_OK : h.ls_status;
+        return true;
+    }
+    n_next = (int)(h.ls_phase >> 32);
+    j_next = (int)(uint32_t)(h.ls_phase & 0xFFFFFFFF) - 1;
+    // enqueue as many trials as the batch's iterations needed (twice as many
+    // after an iteration that ran out of them)
+    int want = j_next >= 0 ? 2 * ahead : most + 1;
+    ahead = want < 1 ? 1 : want > opt.max_backtracks ? opt.max_backtracks : want;
+    return false;
+}
+
+namespace {
+
+struct JdOps : LsOps {
+    const HostProblem& p;
+    const HostRun& r;
+    const double* u;
+    void* traj;
+    const Ws& w;
+    JdOps(const HostProblem& p_, const HostRun& r_, const double* u_, void* traj_, const Ws& w_)
+        : p(p_), r(r_), u(u_), traj(traj_), w(w_) {}
+    int grad(int n, Gate gate, hipStream_t st) override {
+        HostRun rn = r;
+        rn.iter = r.iter + (uint32_t)n;
+        return enqueue_cost_grad(p, rn, u, nullptr, w.gbuf, traj, w, st, gate);
+    }
+    int trial(int n, double zeta, Gate gate, hipStream_t st) override {
+        HostRun rn = r;
+        rn.iter = r.iter + (uint32_t)n;
+        return enqueue_trial(p, rn, u, zeta, w, st, gate);
+    }
+};
+
+}  // namespace
 
 int validate_opt(const jd_opt* opt) {
     if (!opt || opt->n_max < 0 || opt->max_backtracks < 1 || !(opt->zeta0 > 0.0) ||
@@ -289,7 +390,7 @@ int jd_adjoint(const jd_problem* prob, const jd_run* run, const double* u, const
     if ((rc = bind_ws(p, r, ws, ws_bytes, w)))
         return rc;
     JD_TRY(launch_setup(p, r, u, w.tab, w.hdr, 1, stream));
-    JD_TRY(launch_adjoint(p, r, w.tab, traj, w.apart, w.hdr, stream));
+    JD_TRY(launch_adjoint(p, r, w.tab, traj, w.apart, w.seg, w.hdr, stream));
     JD_TRY(launch_finalize_grad(p, r, w.apart, u, grad, w.hdr, stream));
     return JD_OK;
 }
@@ -324,47 +425,33 @@ int jd_optimize(const jd_problem* prob, const jd_run* run, const jd_opt* opt, do
         return rc;
     if (iters_done)
         *iters_done = 0;
-    JD_TRY(launch_clear_flag(w.hdr, stream));
-    const uint32_t iter0 = r.iter;
-    for (int n = 0; n < opt->n_max; ++n) {
-        r.iter = iter0 + (uint32_t)n;
-        if ((rc = enqueue_cost_grad(p, r, u, nullptr, w.gbuf, traj, w, stream)))
+    if (opt->n_max == 0)
+        return JD_OK;
+    LsDriver drv;
+    drv.opt = *opt;
+    drv.hdr = w.hdr;
+    drv.ring = w.ring;
+    drv.u = u;
+    drv.ut = w.ut;
+    drv.nd = p.N * p.d;
+    drv.dt = p.dt;
+    drv.iter0 = r.iter;
+    JdOps ops(p, r, u, traj, w);
+    alignas(16) char mirror[kLsMirrorBytes];
+    if ((rc = drv.start(stream)))
+        return rc;
+    for (;;) {
+        if ((rc = drv.enqueue(ops, kLsLogCap, stream)))
             return rc;
-        double zeta = opt->zeta0;
-        WsHeader h;
-        int bt = 0;
-        bool accepted = false;
-        for (; bt < opt->max_backtracks; ++bt) {
-            if ((rc = enqueue_trial(p, r, u, *opt, zeta, w, stream)))
-                return rc;
-            JD_TRY(hipMemcpyAsync(&h, w.hdr, sizeof(h), hipMemcpyDeviceToHost, stream));
-            JD_TRY(hipStreamSynchronize(stream));
-            if (h.nonfinite)
-                return JD_ENONFINITE;
-            if (h.accept) {
-                accepted = true;
-                break;
-            }
-            zeta *= opt->rho;
-        }
-        if (!accepted)
-            return JD_ELINESEARCH;
-        const double E = sqrt(h.E2);
-        if (log) {
-            log[n].iter = r.iter;
-            log[n].backtracks = bt;
-            log[n].J = h.J;
-            log[n].gnorm = sqrt(h.gnorm2);
-            log[n].zeta = zeta;
-            log[n].J_new = h.J_trial;
-            log[n].E = E;
-        }
+        JD_TRY(hipMemcpyAsync(mirror, w.hdr, kLsMirrorBytes, hipMemcpyDeviceToHost, stream));
+        JD_TRY(hipStreamSynchronize(stream));
+        const bool end = drv.collect(mirror, log);
         if (iters_done)
-            *iters_done = n + 1;
-        if (E <= opt->tol)
+            *iters_done = drv.copied;
+        if (end)
             break;
     }
-    return JD_OK;
+    return drv.status;
 }
 
 int jd_check_finite(void* ws, size_t ws_bytes, hipStream_t stream) {

@@ -14,6 +14,13 @@ namespace jd {
 
 constexpr int kThreads = 256;  // threads per block of every sweep kernel
 
+// True when a gated launch must not run (its tag is not the header's phase).
+// The word is read once per block; it is written only by earlier kernels on
+// the stream, so every block of a launch sees the same value.
+__device__ __forceinline__ bool gate_closed(const Gate& g) {
+    return g.word != nullptr && *g.word != g.tag;
+}
+
 // Three-input xor in one VALU instruction (gfx950 v_bitop3_b32, truth table
 // 0x96 = a ^ b ^ c).
 __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
@@ -284,10 +291,12 @@ __device__ __forceinline__ void euler_step(const Coef<Real, D>& c, const Coef<Re
 
 // One backward adjoint step at state X_k:
 //   lam <- lam + dt [ (A - 3 c3 diag(X_k^2))^T lam + (X_k - xd_k) ]
-template <typename Real, int D>
+// LDS: read the rows of A^T from the block's LDS copy (same values, same
+// arithmetic) -- kernels that also run forward steps set it wherever those
+// read their matrix from LDS.
+template <typename Real, int D, bool LDS = CoefInLds<Real, D>::adjoint>
 __device__ __forceinline__ void adjoint_step(const Coef<Real, D>& c, const Coef<Real, D>* lc,
                                              const Real* __restrict__ xd, const Real* X, Real* lam) {
-    constexpr bool LDS = CoefInLds<Real, D>::adjoint;
     const Coef<Real, D>& rows = coef_rows<LDS>(c, lc);
     Real Y[D];
 #pragma unroll

@@ -143,7 +143,7 @@ int fb_prepare(const jd_fb_problem* prob, const jd_run* run, FbHost& p, HostRun&
 }
 
 struct FbLayout {
-    size_t hdr, tab, cpart, apart, gbuf, ut, total;
+    size_t hdr, ring, tab, cpart, apart, gbuf, ut, total;
 };
 
 FbLayout fb_layout(const FbHost& p, const HostRun& r) {
@@ -151,6 +151,8 @@ FbLayout fb_layout(const FbHost& p, const HostRun& r) {
     size_t off = 0;
     L.hdr = off;
     off += round_up(sizeof(WsHeader), kAlign);
+    L.ring = off;
+    off += round_up(kLsLogCap * sizeof(LsLog), kAlign);
     L.tab = off;
     off += round_up(fb_table_layout(p).count * real_size(r.prec), kAlign);
     L.cpart = off;
@@ -175,6 +177,7 @@ size_t fb_traj_bytes(const FbHost& p, const HostRun& r) {
 
 struct FbWs {
     WsHeader* hdr;
+    LsLog* ring;  // follows the header (one copy of kLsMirrorBytes reads both)
     void* tab;
     double* cpart;
     double* apart;
@@ -190,6 +193,7 @@ int fb_bind(const FbHost& p, const HostRun& r, void* ws, size_t ws_bytes, FbWs& 
         return JD_EWORKSPACE;
     char* base = (char*)round_up((size_t)(uintptr_t)ws, kAlign);
     w.hdr = (WsHeader*)(base + L.hdr);
+    w.ring = (LsLog*)(base + L.ring);
     w.tab = base + L.tab;
     w.cpart = (double*)(base + L.cpart);
     w.apart = (double*)(base + L.apart);
@@ -199,33 +203,55 @@ int fb_bind(const FbHost& p, const HostRun& r, void* ws, size_t ws_bytes, FbWs& 
 }
 
 int fb_enqueue_cost_grad(const FbHost& p, const HostRun& r, const double* mu, double* J, double* g,
-                         void* traj, const FbWs& w, hipStream_t st) {
-    JD_TRY(fb_launch_table(p, r, mu, w.tab, w.hdr, 1, st));
+                         void* traj, const FbWs& w, hipStream_t st, Gate gate = kNoGate) {
+    JD_TRY(fb_launch_table(p, r, mu, w.tab, w.hdr, 1, st, gate));
     if (r.mode == JD_SURROGATE) {
-        JD_TRY(fb_launch_forward_grad(p, r, w.tab, w.cpart, w.apart, w.hdr, st));
-        JD_TRY(fb_launch_adjoint(p, r, w.tab, nullptr, w.apart, w.hdr, true, st));
-        JD_TRY(fb_launch_finalize_grad(p, r, w.apart, g, w.hdr, st));
-        JD_TRY(fb_launch_finalize_cost(p, r, w.cpart, fb_partial_blocks(p, r), g, J, w.hdr, 0, st));
+        JD_TRY(fb_launch_forward_grad(p, r, w.tab, w.cpart, w.apart, w.hdr, st, gate));
+        JD_TRY(fb_launch_adjoint(p, r, w.tab, nullptr, w.apart, w.hdr, true, st, gate));
+        JD_TRY(fb_launch_finalize_grad(p, r, w.apart, g, w.hdr, st, gate));
+        JD_TRY(fb_launch_finalize_cost(p, r, w.cpart, fb_partial_blocks(p, r), g, J, w.hdr, 0, st,
+                                       gate));
         return JD_OK;
     }
-    JD_TRY(fb_launch_forward(p, r, w.tab, traj, w.cpart, w.hdr, st));
-    JD_TRY(fb_launch_adjoint(p, r, w.tab, traj, w.apart, w.hdr, false, st));
-    JD_TRY(fb_launch_finalize_grad(p, r, w.apart, g, w.hdr, st));
-    JD_TRY(fb_launch_finalize_cost(p, r, w.cpart, fb_forward_blocks(p, r), g, J, w.hdr, 0, st));
+    JD_TRY(fb_launch_forward(p, r, w.tab, traj, w.cpart, w.hdr, st, gate));
+    JD_TRY(fb_launch_adjoint(p, r, w.tab, traj, w.apart, w.hdr, false, st, gate));
+    JD_TRY(fb_launch_finalize_grad(p, r, w.apart, g, w.hdr, st, gate));
+    JD_TRY(fb_launch_finalize_cost(p, r, w.cpart, fb_forward_blocks(p, r), g, J, w.hdr, 0, st,
+                                   gate));
     return JD_OK;
 }
 
-int fb_enqueue_trial(const FbHost& p, const HostRun& r, double* mu, const jd_opt& opt, double zeta,
-                     const FbWs& w, hipStream_t st) {
+// Trial point mu - zeta g and its cost into the header's J_trial, under gate.
+int fb_enqueue_trial(const FbHost& p, const HostRun& r, const double* mu, double zeta,
+                     const FbWs& w, hipStream_t st, Gate gate) {
     const int nl = p.N * p.L;
-    JD_TRY(launch_trial(mu, w.gbuf, zeta, w.ut, nl, st));
-    JD_TRY(fb_launch_table(p, r, w.ut, w.tab, w.hdr, 0, st));
-    JD_TRY(fb_launch_forward(p, r, w.tab, nullptr, w.cpart, w.hdr, st));
+    JD_TRY(launch_trial(mu, w.gbuf, zeta, w.ut, nl, st, gate));
+    JD_TRY(fb_launch_table(p, r, w.ut, w.tab, w.hdr, 0, st, gate));
+    JD_TRY(fb_launch_forward(p, r, w.tab, nullptr, w.cpart, w.hdr, st, gate));
     JD_TRY(fb_launch_finalize_cost(p, r, w.cpart, fb_forward_blocks(p, r), nullptr, nullptr, w.hdr,
-                                   1, st));
-    JD_TRY(launch_armijo(w.hdr, mu, w.ut, nl, opt.c_armijo, zeta, p.dt, st));
+                                   1, st, gate));
     return JD_OK;
 }
+
+struct FbOps : LsOps {
+    const FbHost& p;
+    const HostRun& r;
+    const double* mu;
+    void* traj;
+    const FbWs& w;
+    FbOps(const FbHost& p_, const HostRun& r_, const double* mu_, void* traj_, const FbWs& w_)
+        : p(p_), r(r_), mu(mu_), traj(traj_), w(w_) {}
+    int grad(int n, Gate gate, hipStream_t st) override {
+        HostRun rn = r;
+        rn.iter = r.iter + (uint32_t)n;
+        return fb_enqueue_cost_grad(p, rn, mu, nullptr, w.gbuf, traj, w, st, gate);
+    }
+    int trial(int n, double zeta, Gate gate, hipStream_t st) override {
+        HostRun rn = r;
+        rn.iter = r.iter + (uint32_t)n;
+        return fb_enqueue_trial(p, rn, mu, zeta, w, st, gate);
+    }
+};
 
 }  // namespace
 
@@ -319,47 +345,33 @@ int jd_fb_optimize(const jd_fb_problem* prob, const jd_run* run, const jd_opt* o
         return rc;
     if (iters_done)
         *iters_done = 0;
-    JD_TRY(launch_clear_flag(w.hdr, stream));
-    const uint32_t iter0 = r.iter;
-    for (int n = 0; n < opt->n_max; ++n) {
-        r.iter = iter0 + (uint32_t)n;
-        if ((rc = fb_enqueue_cost_grad(p, r, mu, nullptr, w.gbuf, traj, w, stream)))
+    if (opt->n_max == 0)
+        return JD_OK;
+    LsDriver drv;
+    drv.opt = *opt;
+    drv.hdr = w.hdr;
+    drv.ring = w.ring;
+    drv.u = mu;
+    drv.ut = w.ut;
+    drv.nd = p.N * p.L;
+    drv.dt = p.dt;
+    drv.iter0 = r.iter;
+    FbOps ops(p, r, mu, traj, w);
+    alignas(16) char mirror[kLsMirrorBytes];
+    if ((rc = drv.start(stream)))
+        return rc;
+    for (;;) {
+        if ((rc = drv.enqueue(ops, kLsLogCap, stream)))
             return rc;
-        double zeta = opt->zeta0;
-        WsHeader h;
-        int bt = 0;
-        bool accepted = false;
-        for (; bt < opt->max_backtracks; ++bt) {
-            if ((rc = fb_enqueue_trial(p, r, mu, *opt, zeta, w, stream)))
-                return rc;
-            JD_TRY(hipMemcpyAsync(&h, w.hdr, sizeof(h), hipMemcpyDeviceToHost, stream));
-            JD_TRY(hipStreamSynchronize(stream));
-            if (h.nonfinite)
-                return JD_ENONFINITE;
-            if (h.accept) {
-                accepted = true;
-                break;
-            }
-            zeta *= opt->rho;
-        }
-        if (!accepted)
-            return JD_ELINESEARCH;
-        const double E = sqrt(h.E2);
-        if (log) {
-            log[n].iter = r.iter;
-            log[n].backtracks = bt;
-            log[n].J = h.J;
-            log[n].gnorm = sqrt(h.gnorm2);
-            log[n].zeta = zeta;
-            log[n].J_new = h.J_trial;
-            log[n].E = E;
-        }
+        JD_TRY(hipMemcpyAsync(mirror, w.hdr, kLsMirrorBytes, hipMemcpyDeviceToHost, stream));
+        JD_TRY(hipStreamSynchronize(stream));
+        const bool end = drv.collect(mirror, log);
         if (iters_done)
-            *iters_done = n + 1;
-        if (E <= opt->tol)
+            *iters_done = drv.copied;
+        if (end)
             break;
     }
-    return JD_OK;
+    return drv.status;
 }
 
 int jd_fb_draws(const jd_fb_problem* prob, const jd_run* run, int64_t m0, int64_t mc, int32_t k0,

@@ -32,19 +32,24 @@ int prepare(const jd_problem* prob, const jd_run* run, HostProblem& p, HostRun& 
 int validate_opt(const jd_opt* opt);
 
 struct Layout {
-    size_t hdr, tab, cpart, apart, gbuf, ut, total;
+    size_t hdr, ring, tab, cpart, apart, gbuf, ut, seg, total;
 };
 Layout layout(const HostProblem& p, const HostRun& r);
 size_t traj_bytes(const HostProblem& p, const HostRun& r);
 
-// The workspace regions, bound to a caller pointer.
+// The workspace regions, bound to a caller pointer.  The line-search log
+// ring directly follows the header, so one copy of kLsMirrorBytes from the
+// workspace start reads both.
+constexpr size_t kLsMirrorBytes = sizeof(WsHeader) + kLsLogCap * sizeof(LsLog);
 struct Ws {
     WsHeader* hdr;
+    LsLog* ring;
     void* tab;
     double* cpart;
     double* apart;
     double* gbuf;
     double* ut;
+    void* seg;  // segment scratch of the recompute adjoint (may be empty)
 };
 int bind_ws(const HostProblem& p, const HostRun& r, void* ws, size_t ws_bytes, Ws& w);
 bool aligned(const void* ptr, size_t a);
@@ -55,9 +60,54 @@ bool aligned(const void* ptr, size_t a);
 int enqueue_forward(const HostProblem& p, const HostRun& r, const double* u, void* traj, double* J,
                     const Ws& w, hipStream_t st);
 int enqueue_cost_grad(const HostProblem& p, const HostRun& r, const double* u, double* J,
-                      double* g, void* traj, const Ws& w, hipStream_t st);
-int enqueue_trial(const HostProblem& p, const HostRun& r, double* u, const jd_opt& opt, double zeta,
-                  const Ws& w, hipStream_t st);
+                      double* g, void* traj, const Ws& w, hipStream_t st, Gate gate = kNoGate);
+// Trial point u' = u - zeta g (g in the workspace) and its cost-only forward
+// into the header's J_trial, all under `gate`; the Armijo test is separate.
+int enqueue_trial(const HostProblem& p, const HostRun& r, const double* u, double zeta,
+                  const Ws& w, hipStream_t st, Gate gate);
+
+// ---------------------------------------------------------------------------
+// Device-driven gradient iteration (Section 5, Algorithm 5.4 with eq.
+// Stochastic_Armijo).  The host enqueues, in the order they can run, the
+// phases of up to a batch of iterations: for each iteration the evaluation of
+// J(u^n), g^n, then `ahead` Armijo trials; every phase is gated by the
+// header's phase word, which the device advances (see LsArmijo), so phases
+// the device does not reach return at once.  After the batch the host reads
+// the header and the log ring (one synchronization or event per batch), and
+// resumes where the device stopped: at the next iteration, or at the next
+// trial of an iteration that needed more trials than were enqueued.  The
+// arithmetic and its order are those of one trial at a time.
+struct LsOps {
+    virtual ~LsOps() {}
+    // J(u^n), g^n with counter word iter0 + n, under gate
+    virtual int grad(int n, Gate gate, hipStream_t st) = 0;
+    // trial point and cost of iteration n at step zeta, under gate
+    virtual int trial(int n, double zeta, Gate gate, hipStream_t st) = 0;
+};
+
+struct LsDriver {
+    jd_opt opt;
+    WsHeader* hdr;   // device
+    LsLog* ring;     // device
+    double* u;       // device, the iterate
+    const double* ut;  // device, the trial point
+    int nd;
+    double dt;
+    uint32_t iter0;
+    int n_next = 0, j_next = -1;  // where the device stopped
+    int ahead = 2;                // trials enqueued per iteration
+    int copied = 0;               // log entries read
+    int status = JD_OK;
+
+    // Opens the iteration on the device (ls_start).
+    int start(hipStream_t st);
+    // Enqueues phases from the resume point for up to `iters` iterations.
+    int enqueue(LsOps& ops, int iters, hipStream_t st);
+    // Reads a completed batch from a host copy of header + ring; appends log
+    // records (host, may be null) and returns true when the iteration ended
+    // (status in `status`).
+    bool collect(const void* mirror, jd_iter_log* log);
+};
 
 }  // namespace host
 }  // namespace jd

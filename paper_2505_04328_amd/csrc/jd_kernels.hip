@@ -26,6 +26,7 @@ struct SweepArgs {
     Coef<Real, D> c;
     const Coef<Real, D>* lc;  // the block's LDS copy of c (set in the kernel), see CoefInLds
     const PoissonTable* thr;  // staged in the workspace header
+    Gate gate;        // launch gate (word null: always runs)
     void* traj;       // trajectory or checkpoints
     double* part;     // per-block partial sums
     int64_t M;
@@ -122,7 +123,9 @@ struct BMat {
 template <typename Real, int D>
 __global__ void __launch_bounds__(kThreads)
 k_table(const double* __restrict__ u, const double* __restrict__ xd, Real* __restrict__ tab, int N,
-        int d, BMat B, WsHeader* hdr, int clear_flag, PoissonTable pt) {
+        int d, BMat B, WsHeader* hdr, int clear_flag, PoissonTable pt, Gate gate) {
+    if (gate_closed(gate))
+        return;
     const int idx = blockIdx.x * kThreads + threadIdx.x;
     if (idx == 0 && clear_flag)
         hdr->nonfinite = 0;  // every entry point starts here: the flag describes this call
@@ -206,6 +209,8 @@ struct ForwardSweep {
 template <typename Real, int D, int MODE>
 __global__ void __launch_bounds__(kThreads)
 k_forward(SweepArgs<Real, D> a, const Real* __restrict__ tab, double* __restrict__ cpart) {
+    if (gate_closed(a.gate))
+        return;
     __shared__ double sh[kThreads];
     __shared__ Coef<Real, D> sc;
     stage_coef<CoefInLds<Real, D>::forward>(a, &sc);
@@ -239,20 +244,14 @@ __device__ __forceinline__ void load_tile(const SweepArgs<Real, D>& a, const Rea
     }
 }
 
-// voff: per-lane byte offset; soff: wave-uniform byte offset (a scalar register).
-template <typename Real>
-__device__ __forceinline__ Real buffer_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff);
-template <>
-__device__ __forceinline__ float buffer_load<float>(__amdgpu_buffer_rsrc_t r, uint32_t voff,
-                                                    uint32_t soff) {
-    return __builtin_bit_cast(float,
-                              __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, kNontemporal));
-}
-template <>
-__device__ __forceinline__ double buffer_load<double>(__amdgpu_buffer_rsrc_t r, uint32_t voff,
-                                                      uint32_t soff) {
-    return __builtin_bit_cast(double,
-                              __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, kNontemporal));
+// voff: per-lane byte offset; soff: wave-uniform byte offset (a scalar
+// register); AUX: cache policy (kNontemporal for data read once).
+template <typename Real, int AUX = kNontemporal>
+__device__ __forceinline__ Real buffer_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    if constexpr (sizeof(Real) == 4)
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, AUX));
+    else
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, AUX));
 }
 
 // Full tile with top step k: slots k-1 (s = 0) down to k-S (s = S-1).
@@ -393,6 +392,8 @@ struct StoredAdjoint {
 template <typename Real, int D, bool DUMP>
 __global__ void __launch_bounds__(kThreads)
 k_adjoint_stored(SweepArgs<Real, D> a, const Real* __restrict__ tab) {
+    if (gate_closed(a.gate))
+        return;
     __shared__ Real tile[StepReducer<D, Real>::kRows][kThreads];
     __shared__ Coef<Real, D> sc;
     stage_coef<CoefInLds<Real, D>::adjoint>(a, &sc);
@@ -416,6 +417,8 @@ k_adjoint_stored(SweepArgs<Real, D> a, const Real* __restrict__ tab) {
 template <typename Real, int D>
 __global__ void __launch_bounds__(kThreads)
 k_cost_grad_stored(SweepArgs<Real, D> a, const Real* __restrict__ tab, double* __restrict__ cpart) {
+    if (gate_closed(a.gate))
+        return;
     __shared__ double sh[kThreads];
     __shared__ Real tile[StepReducer<D, Real>::kRows][kThreads];
     __shared__ Coef<Real, D> sc;
@@ -449,6 +452,8 @@ __global__ void __launch_bounds__(kThreads)
 k_adjoint_recompute(SweepArgs<Real, D> a, const Real* __restrict__ tab) {
     constexpr int S = StepReducer<D, Real>::kSteps;
     static_assert(R % S == 0, "register buffer length must be a multiple of the reducer tile");
+    if (gate_closed(a.gate))
+        return;
     __shared__ Real tile[StepReducer<D, Real>::kRows][kThreads];
     __shared__ Coef<Real, D> sc;
     stage_coef<CoefInLds<Real, D>::any>(a, &sc);
@@ -555,11 +560,186 @@ k_adjoint_recompute(SweepArgs<Real, D> a, const Real* __restrict__ tab) {
 }
 
 // ---------------------------------------------------------------------------
+// Checkpoint-recompute adjoint that regenerates each segment once.  The states
+// of a segment [s0, s1) (K steps) do not fit the registers when d K is large
+// (d = 8, K = 64: 512 values per lane), and the register kernel above then
+// regenerates every step twice.  Here each block owns a scratch region of K
+// slots (slot q = X_{s0+q}, rows of 256 lanes as in the trajectory layout):
+// for each segment, last first, it reloads the checkpoint into slot 0,
+// regenerates X_{s0+1} .. X_{s1-1} into slots 1 .. K-1 (X_{s1} is the next
+// checkpoint and is not needed), and sweeps the segment backwards reading the
+// slots a reducer tile at a time, the next tile's loads issued before the
+// current tile is swept.  Each lane reads back only what it wrote (after a
+// fence).  The grid is persistent: gridDim.x blocks (at most kSegBlocks) take
+// the 256-path groups g = blockIdx.x, blockIdx.x + gridDim.x, ..., so the
+// scratch is gridDim.x regions whatever M is.  The steps, the draws and the
+// reduction are those of the other sweeps: the result is bitwise the stored
+// variant's.
+
+// Slots q, q-1, ..., q-S+1 of a segment region into X[0..S-1] (q >= S-1), by
+// raw buffer loads with the default cache policy (the slots were just written
+// and are read once, soon).
+template <typename Real, int D>
+__device__ __forceinline__ void seg_load_full(const Real* region, int64_t stride, int q,
+                                              const uint32_t* voff, int d, Real (*X)[D]) {
+    constexpr int S = StepReducer<D, Real>::kSteps;
+    const Real* base = region + (int64_t)(q - S + 1) * stride;
+    const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)base, (short)0, (int)(S * stride * (int64_t)sizeof(Real)), kBufferConfig);
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            const Real v = buffer_load<Real, 0>(
+                r, voff[c], (uint32_t)((S - 1 - s) * stride * (int64_t)sizeof(Real)));
+            X[s][c] = c < d ? v : (Real)0;
+        }
+}
+
+// The last tile of a segment (q < S-1): slots q .. 0, then slot 0 again (unused).
+template <typename Real, int D>
+__device__ __forceinline__ void seg_load_tail(const Real* region, int64_t stride, int q, int d,
+                                              Real (*X)[D]) {
+    constexpr int S = StepReducer<D, Real>::kSteps;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        const Real* row = region + (int64_t)(q - s > 0 ? q - s : 0) * stride;
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            const int ce = c < d ? c : d - 1;
+            const Real v = row[ce * kThreads + threadIdx.x];
+            X[s][c] = c < d ? v : (Real)0;
+        }
+    }
+}
+
+template <typename Real, int D>
+__device__ __forceinline__ void seg_load(const Real* region, int64_t stride, int q,
+                                         const uint32_t* voff, int d, Real (*X)[D]) {
+    if (q >= StepReducer<D, Real>::kSteps - 1)
+        seg_load_full<Real, D>(region, stride, q, voff, d, X);
+    else
+        seg_load_tail<Real, D>(region, stride, q, d, X);
+}
+
+template <typename Real, int D>
+__device__ __forceinline__ void seg_store(Real* __restrict__ row, int d, const Real* X) {
+#pragma unroll
+    for (int c = 0; c < D; ++c)
+        if (c < d)
+            row[c * kThreads + threadIdx.x] = X[c];
+}
+
+template <typename Real, int D, bool DUMP>
+__global__ void __launch_bounds__(kThreads, sizeof(Real) == 4 ? 4 : 1)
+k_adjoint_segments(SweepArgs<Real, D> a, const Real* __restrict__ tab, Real* __restrict__ scratch) {
+    constexpr int S = StepReducer<D, Real>::kSteps;
+    if (gate_closed(a.gate))
+        return;
+    __shared__ Real tile[StepReducer<D, Real>::kRows][kThreads];
+    __shared__ Coef<Real, D> sc;
+    stage_coef<CoefInLds<Real, D>::any>(a, &sc);
+    const int N = a.N, K = a.K;
+    const int nseg = (N + K - 1) / K;
+    const Cols cl = make_cols(a.d);
+    Real* region = scratch + (int64_t)blockIdx.x * K * cl.stride;
+    uint32_t voff[D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+        const int ce = c < a.d ? c : a.d - 1;
+        voff[c] = (uint32_t)((ce * kThreads + threadIdx.x) * sizeof(Real));
+    }
+    for (int64_t g = blockIdx.x; g < a.nblk; g += gridDim.x) {
+        StepReducer<D, Real> red;
+        red.init(tile, (int)g);
+        const int64_t m = g * kThreads + threadIdx.x;
+        const bool act = m < a.M;
+        Real lam[D];
+        {
+            Real XN[D];
+            load_row<Real, D>(slot_row<Real>(a.traj, cl, a.nslots, g, nseg - 1), a.d, XN);
+#pragma unroll
+            for (int i = 0; i < D; ++i)
+                lam[i] = XN[i] - coef_once<Real, D>(a.c, a.lc).xT[i];
+            if (DUMP) {
+                dump_state(a, a.dX, N, m, XN);
+                dump_state(a, a.dlam, N, m, lam);
+            }
+        }
+        for (int j = nseg - 1; j >= 0; --j) {
+            const int s0 = j * K;
+            const int s1 = min(s0 + K, N);
+            {
+                Real X[D];
+                if (j == 0) {
+#pragma unroll
+                    for (int i = 0; i < D; ++i)
+                        X[i] = coef_once<Real, D>(a.c, a.lc).x0[i];
+                } else {
+                    load_row<Real, D>(slot_row<Real>(a.traj, cl, a.nslots, g, j - 1), a.d, X);
+                }
+                seg_store<Real, D>(region, a.d, X);
+                Real* row = region + cl.stride;
+                for (int k = s0; k < s1 - 1; ++k) {
+                    StepDraws<Real, D> z;
+                    draws<Real, D>((uint32_t)m, (uint32_t)k, a.iter, a.key0, a.key1, a.thr, z);
+                    euler_step<Real, D>(a.c, a.lc, tab + (size_t)k * 2 * D, X, z);
+                    seg_store<Real, D>(row, a.d, X);
+                    row += cl.stride;
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+            // backwards over the segment, a reducer tile at a time
+            Real cur[S][D], nxt[S][D];
+            int k = s1 - 1;
+            seg_load<Real, D>(region, cl.stride, k - s0, voff, a.d, cur);
+            for (;;) {
+                const int cnt = k - s0 + 1 < S ? k - s0 + 1 : S;
+                const int kn = k - S;
+                if (kn >= s0)
+                    seg_load<Real, D>(region, cl.stride, kn - s0, voff, a.d, nxt);
+#pragma unroll
+                for (int s = 0; s < S; ++s) {
+                    const int kk = k - s;
+                    if (s < cnt) {
+                        Real v[D];
+#pragma unroll
+                        for (int c = 0; c < D; ++c)
+                            v[c] = act ? lam[c] : (Real)0;
+                        red.put(s, v);
+                        if (kk >= 1) {
+                            adjoint_step<Real, D, CoefInLds<Real, D>::any>(
+                                a.c, a.lc, tab + (size_t)kk * 2 * D + D, cur[s], lam);
+                            if (DUMP) {
+                                dump_state(a, a.dX, kk, m, cur[s]);
+                                dump_state(a, a.dlam, kk, m, lam);
+                            }
+                        }
+                    }
+                }
+                red.flush_tile(k, cnt, a.part, a.nblk);
+                if (kn < s0)
+                    break;
+                k = kn;
+#pragma unroll
+                for (int s = 0; s < S; ++s)
+#pragma unroll
+                    for (int c = 0; c < D; ++c)
+                        cur[s][c] = nxt[s][c];
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // One block per step k: sums the d rows (k, c) of block partials in a fixed
 // order, then g_k = nu u_k + B^T (sum / M).
 __global__ void __launch_bounds__(kThreads)
 k_finalize_grad(const double* __restrict__ part, int nblk, int D, int d, int64_t M, double nu,
-                const double* __restrict__ u, BMat B, double* __restrict__ g, WsHeader* hdr) {
+                const double* __restrict__ u, BMat B, double* __restrict__ g, WsHeader* hdr,
+                Gate gate) {
+    if (gate_closed(gate))
+        return;
     __shared__ double sh[kThreads];
     __shared__ double G[8];
     const int k = blockIdx.x;
@@ -590,7 +770,9 @@ k_finalize_grad(const double* __restrict__ part, int nblk, int D, int d, int64_t
 __global__ void __launch_bounds__(kThreads)
 k_finalize_cost(const double* __restrict__ cpart, int nblk, int64_t M, double nu, double dt,
                 const double* __restrict__ u, const double* __restrict__ g, int nd,
-                double* __restrict__ J_out, WsHeader* hdr, int slot) {
+                double* __restrict__ J_out, WsHeader* hdr, int slot, Gate gate) {
+    if (gate_closed(gate))
+        return;
     __shared__ double sh[kThreads];
     double s = 0.0;
     for (int b = threadIdx.x; b < nblk; b += kThreads)
@@ -621,34 +803,51 @@ k_finalize_cost(const double* __restrict__ cpart, int nblk, int64_t M, double nu
         }
         if (J_out != nullptr)
             *J_out = J;
-        if (!isfinite(J) || bad)
+        // a trial's cost (slot 1) may overflow: the Armijo test rejects it
+        if (slot == 0 && (!isfinite(J) || bad))
             hdr->nonfinite = 1;
     }
 }
 
 __global__ void __launch_bounds__(kThreads)
 k_trial(const double* __restrict__ u, const double* __restrict__ g, double zeta,
-        double* __restrict__ ut, int nd) {
+        double* __restrict__ ut, int nd, Gate gate) {
+    if (gate_closed(gate))
+        return;
     const int q = blockIdx.x * kThreads + threadIdx.x;
     if (q < nd)
         ut[q] = u[q] - zeta * g[q];
 }
 
 // Sufficient decrease J(u - zeta g) <= J(u) - c zeta ||g||^2_L2 on the same
-// draws; on acceptance records ||u' - u||^2_L2 and moves u to u'.
+// draws (a non-finite trial cost is rejected); on acceptance records
+// ||u' - u||^2_L2, moves u to u', writes the iteration's log entry and opens
+// the next phase of the device-driven iteration (see LsArmijo).  Gated by the
+// phase of trial (ls.n, ls.j).
 __global__ void __launch_bounds__(kThreads)
-k_armijo(WsHeader* hdr, double* __restrict__ u, const double* __restrict__ ut, int nd,
-         double c_armijo, double zeta, double dt) {
+k_armijo(WsHeader* hdr, LsLog* __restrict__ ring, double* __restrict__ u,
+         const double* __restrict__ ut, int nd, LsArmijo ls) {
+    if (hdr->ls_phase != ls_phase(ls.n, ls.j))
+        return;
     __shared__ double sh[kThreads];
     __shared__ int acc;
     if (threadIdx.x == 0) {
         const double J = hdr->J, Jt = hdr->J_trial;
-        acc = (Jt <= J - c_armijo * zeta * hdr->gnorm2) ? 1 : 0;
+        acc = (isfinite(Jt) && Jt <= J - ls.c_armijo * ls.zeta * hdr->gnorm2) ? 1 : 0;
         hdr->accept = acc;
     }
     __syncthreads();
-    if (!acc)
+    if (!acc) {
+        if (threadIdx.x == 0) {
+            if (ls.j + 1 >= ls.max_backtracks) {
+                hdr->ls_status = JD_ELINESEARCH;
+                hdr->ls_phase = kLsStop;
+            } else {
+                hdr->ls_phase = ls_phase(ls.n, ls.j + 1);
+            }
+        }
         return;
+    }
     double e = 0.0;
     for (int q = threadIdx.x; q < nd; q += kThreads) {
         const double r = ut[q] - u[q];
@@ -657,8 +856,49 @@ k_armijo(WsHeader* hdr, double* __restrict__ u, const double* __restrict__ ut, i
     e = block_sum(e, sh);
     for (int q = threadIdx.x; q < nd; q += kThreads)
         u[q] = ut[q];
-    if (threadIdx.x == 0)
-        hdr->E2 = dt * e;
+    if (threadIdx.x == 0) {
+        const double E2 = ls.dt * e;
+        hdr->E2 = E2;
+        LsLog& L = ring[ls.n % kLsLogCap];
+        L.J = hdr->J;
+        L.gnorm2 = hdr->gnorm2;
+        L.zeta = ls.zeta;
+        L.J_new = hdr->J_trial;
+        L.E2 = E2;
+        L.iter = ls.iter;
+        L.backtracks = ls.j;
+        L.n = ls.n;
+        hdr->ls_done = ls.n + 1;
+        if (ls.n + 1 >= ls.n_max || sqrt(E2) <= ls.tol) {
+            hdr->ls_status = kLsDone;
+            hdr->ls_phase = kLsStop;
+        } else {
+            hdr->ls_phase = ls_phase(ls.n + 1, -1);
+        }
+    }
+}
+
+__global__ void k_ls_start(WsHeader* hdr) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        hdr->nonfinite = 0;
+        hdr->accept = 0;
+        hdr->ls_status = kLsRunning;
+        hdr->ls_phase = ls_phase(0, -1);
+        hdr->ls_done = 0;
+    }
+}
+
+// After the evaluation of J(u^n), g^n: stop on a non-finite result, else
+// open the first trial.
+__global__ void k_ls_after_grad(WsHeader* hdr, int n) {
+    if (threadIdx.x == 0 && blockIdx.x == 0 && hdr->ls_phase == ls_phase(n, -1)) {
+        if (hdr->nonfinite) {
+            hdr->ls_status = JD_ENONFINITE;
+            hdr->ls_phase = kLsStop;
+        } else {
+            hdr->ls_phase = ls_phase(n, 0);
+        }
+    }
 }
 
 __global__ void k_clear_flag(WsHeader* hdr) {
@@ -731,16 +971,42 @@ template <> struct RecomputeShape<double, 8> { static constexpr int R = 4, S = 4
 template <typename Real, int D>
 static int max_K() { return RecomputeShape<Real, D>::R * RecomputeShape<Real, D>::S; }
 
-bool recompute_supported(int prec, int D, int K) {
-    int mk = 0;
-    if (prec == JD_FP64) {
-        mk = D == 1 ? max_K<double, 1>() : D == 2 ? max_K<double, 2>() : D == 4 ? max_K<double, 4>()
-                                                                                  : max_K<double, 8>();
-    } else {
-        mk = D == 1 ? max_K<float, 1>() : D == 2 ? max_K<float, 2>() : D == 4 ? max_K<float, 4>()
-                                                                                : max_K<float, 8>();
-    }
-    return K >= 1 && K <= mk;
+template <typename Real, int D>
+static int reg_R() { return RecomputeShape<Real, D>::R; }
+
+// Longest checkpoint interval of the register kernel, and the longest it
+// sweeps with one regeneration of each step (K <= R: one sub-segment).
+static int register_max_K(int prec, int D) {
+    if (prec == JD_FP64)
+        return D == 1 ? max_K<double, 1>() : D == 2 ? max_K<double, 2>()
+             : D == 4 ? max_K<double, 4>() : max_K<double, 8>();
+    return D == 1 ? max_K<float, 1>() : D == 2 ? max_K<float, 2>()
+         : D == 4 ? max_K<float, 4>() : max_K<float, 8>();
+}
+static int register_single_K(int prec, int D) {
+    if (prec == JD_FP64)
+        return D == 1 ? reg_R<double, 1>() : D == 2 ? reg_R<double, 2>()
+             : D == 4 ? reg_R<double, 4>() : reg_R<double, 8>();
+    return D == 1 ? reg_R<float, 1>() : D == 2 ? reg_R<float, 2>()
+         : D == 4 ? reg_R<float, 4>() : reg_R<float, 8>();
+}
+
+// The segment kernel (one regeneration, workspace scratch) where the register
+// kernel would regenerate every step twice at d = 8, and wherever K exceeds
+// the register kernel's buffers.  At d <= 4 a second regeneration costs less
+// than writing and reading back the states.
+bool recompute_uses_segments(int prec, int D, int K) {
+    return K > register_max_K(prec, D) || (D == 8 && K > register_single_K(prec, D));
+}
+
+size_t seg_scratch_bytes(const HostProblem& p, const HostRun& r) {
+    if (r.mode != JD_RECOMPUTE || !recompute_uses_segments(r.prec, p.D, r.K))
+        return 0;
+    return (size_t)seg_blocks(r) * (size_t)r.K * (size_t)p.d * kThreads * real_size(r.prec);
+}
+
+bool recompute_supported(const HostProblem& p, const HostRun& r) {
+    return r.K >= 1 && seg_scratch_bytes(p, r) <= kSegScratchMax;
 }
 
 template <typename Real, int D>
@@ -763,6 +1029,7 @@ static SweepArgs<Real, D> make_args(const HostProblem& p, const HostRun& r) {
     a.c.c3 = (Real)p.cubic;
     a.thr = nullptr;
     a.lc = nullptr;
+    a.gate = kNoGate;
     a.traj = nullptr;
     a.part = nullptr;
     a.M = r.M;
@@ -820,22 +1087,24 @@ static inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kThreads -
     } while (0)
 
 hipError_t launch_setup(const HostProblem& p, const HostRun& r, const double* u, void* tab,
-                        WsHeader* hdr, int clear_flag, hipStream_t st) {
+                        WsHeader* hdr, int clear_flag, hipStream_t st, Gate gate) {
     const BMat B = make_B(p);
     const unsigned nb = blocks_for((int64_t)p.N * p.D > 32 ? (int64_t)p.N * p.D : 32);
 #define JD_SETUP(T, DD) \
-    hipLaunchKernelGGL((k_table<T, DD>), dim3(nb), dim3(kThreads), 0, st, u, p.xd, (T*)tab, p.N, p.d, B, hdr, clear_flag, p.poisson)
+    hipLaunchKernelGGL((k_table<T, DD>), dim3(nb), dim3(kThreads), 0, st, u, p.xd, (T*)tab, p.N, p.d, B, hdr, clear_flag, p.poisson, gate)
     JD_DISPATCH(r.prec, p.D, JD_SETUP);
 #undef JD_SETUP
     return hipGetLastError();
 }
 
 hipError_t launch_forward(const HostProblem& p, const HostRun& r, const void* tab, void* traj,
-                          int fwd_mode, double* cpart, const WsHeader* hdr, hipStream_t st) {
+                          int fwd_mode, double* cpart, const WsHeader* hdr, hipStream_t st,
+                          Gate gate) {
     const unsigned nb = (unsigned)r.nblk;
 #define JD_FWD(T, DD)                                                                               \
     do {                                                                                            \
         SweepArgs<T, DD> a = make_args<T, DD>(p, r);                                                \
+        a.gate = gate;                                                                              \
         a.traj = traj;                                                                              \
         a.thr = &hdr->poisson;                                                                      \
         if (fwd_mode == FWD_STORE)                                                                  \
@@ -853,16 +1122,49 @@ hipError_t launch_forward(const HostProblem& p, const HostRun& r, const void* ta
     return hipGetLastError();
 }
 
+// Blocks of the persistent segment kernel: as many as are resident at once on
+// the current device (its compute units times the kernel's blocks per unit),
+// at most the scratch regions of the workspace.
+template <typename Real, int D, bool DUMP>
+static unsigned seg_grid_for(const HostRun& r) {
+    static const int per_cu = [] {
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_adjoint_segments<Real, D, DUMP>,
+                                                         kThreads, 0) != hipSuccess || n < 1)
+            n = 1;
+        return n;
+    }();
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus < 1)
+        cus = 1;
+    const int64_t g = (int64_t)cus * per_cu;
+    return (unsigned)(g < seg_blocks(r) ? g : seg_blocks(r));
+}
+
 hipError_t launch_adjoint(const HostProblem& p, const HostRun& r, const void* tab, const void* traj,
-                          double* apart, const WsHeader* hdr, hipStream_t st) {
+                          double* apart, void* seg, const WsHeader* hdr, hipStream_t st,
+                          Gate gate) {
     const unsigned nb = (unsigned)r.nblk;
+    const bool segments = r.mode == JD_RECOMPUTE && recompute_uses_segments(r.prec, p.D, r.K);
 #define JD_ADJ(T, DD)                                                                             \
     do {                                                                                          \
+        const unsigned seg_grid =                                                                 \
+            !segments ? 0u                                                                        \
+            : r.dump != nullptr ? seg_grid_for<T, DD, true>(r) : seg_grid_for<T, DD, false>(r);   \
         SweepArgs<T, DD> a = make_args<T, DD>(p, r);                                              \
+        a.gate = gate;                                                                            \
         a.traj = const_cast<void*>(traj);                                                         \
         a.part = apart;                                                                           \
         a.thr = &hdr->poisson;                                                                    \
-        if (r.mode == JD_RECOMPUTE)                                                               \
+        if (segments && r.dump != nullptr)                                                        \
+            hipLaunchKernelGGL((k_adjoint_segments<T, DD, true>), dim3(seg_grid), dim3(kThreads), \
+                               0, st, a, (const T*)tab, (T*)seg);                                 \
+        else if (segments)                                                                        \
+            hipLaunchKernelGGL((k_adjoint_segments<T, DD, false>), dim3(seg_grid),                \
+                               dim3(kThreads), 0, st, a, (const T*)tab, (T*)seg);                 \
+        else if (r.mode == JD_RECOMPUTE)                                                          \
             hipLaunchKernelGGL((k_adjoint_recompute<T, DD, RecomputeShape<T, DD>::R,              \
                                                     RecomputeShape<T, DD>::S>),                   \
                                dim3(nb), dim3(kThreads), 0, st, a, (const T*)tab);                \
@@ -880,11 +1182,12 @@ hipError_t launch_adjoint(const HostProblem& p, const HostRun& r, const void* ta
 
 hipError_t launch_cost_grad_stored(const HostProblem& p, const HostRun& r, const void* tab,
                                   void* traj, double* cpart, double* apart, const WsHeader* hdr,
-                                  hipStream_t st) {
+                                  hipStream_t st, Gate gate) {
     const unsigned nb = (unsigned)r.nblk;
 #define JD_CG(T, DD)                                                                              \
     do {                                                                                          \
         SweepArgs<T, DD> a = make_args<T, DD>(p, r);                                              \
+        a.gate = gate;                                                                            \
         a.traj = traj;                                                                            \
         a.part = apart;                                                                           \
         a.thr = &hdr->poisson;                                                                    \
@@ -897,29 +1200,41 @@ hipError_t launch_cost_grad_stored(const HostProblem& p, const HostRun& r, const
 }
 
 hipError_t launch_finalize_grad(const HostProblem& p, const HostRun& r, const double* apart,
-                                const double* u, double* g, WsHeader* hdr, hipStream_t st) {
+                                const double* u, double* g, WsHeader* hdr, hipStream_t st,
+                                Gate gate) {
     hipLaunchKernelGGL(k_finalize_grad, dim3(p.N), dim3(kThreads), 0, st, apart, r.nblk, p.D, p.d,
-                       r.M, p.nu, u, make_B(p), g, hdr);
+                       r.M, p.nu, u, make_B(p), g, hdr, gate);
     return hipGetLastError();
 }
 
 hipError_t launch_finalize_cost(const HostProblem& p, const HostRun& r, const double* cpart,
                                 const double* u, const double* g, double* J_out, WsHeader* hdr,
-                                int slot, hipStream_t st) {
+                                int slot, hipStream_t st, Gate gate) {
     hipLaunchKernelGGL(k_finalize_cost, dim3(1), dim3(kThreads), 0, st, cpart, r.nblk, r.M, p.nu,
-                       p.dt, u, g, p.N * p.d, J_out, hdr, slot);
+                       p.dt, u, g, p.N * p.d, J_out, hdr, slot, gate);
     return hipGetLastError();
 }
 
 hipError_t launch_trial(const double* u, const double* g, double zeta, double* ut, int nd,
-                        hipStream_t st) {
-    hipLaunchKernelGGL(k_trial, dim3(blocks_for(nd)), dim3(kThreads), 0, st, u, g, zeta, ut, nd);
+                        hipStream_t st, Gate gate) {
+    hipLaunchKernelGGL(k_trial, dim3(blocks_for(nd)), dim3(kThreads), 0, st, u, g, zeta, ut, nd,
+                       gate);
     return hipGetLastError();
 }
 
-hipError_t launch_armijo(WsHeader* hdr, double* u, const double* ut, int nd, double c_armijo,
-                         double zeta, double dt, hipStream_t st) {
-    hipLaunchKernelGGL(k_armijo, dim3(1), dim3(kThreads), 0, st, hdr, u, ut, nd, c_armijo, zeta, dt);
+hipError_t launch_armijo(WsHeader* hdr, LsLog* ring, double* u, const double* ut, int nd,
+                         const LsArmijo& ls, hipStream_t st) {
+    hipLaunchKernelGGL(k_armijo, dim3(1), dim3(kThreads), 0, st, hdr, ring, u, ut, nd, ls);
+    return hipGetLastError();
+}
+
+hipError_t launch_ls_start(WsHeader* hdr, hipStream_t st) {
+    hipLaunchKernelGGL(k_ls_start, dim3(1), dim3(64), 0, st, hdr);
+    return hipGetLastError();
+}
+
+hipError_t launch_ls_after_grad(WsHeader* hdr, int n, hipStream_t st) {
+    hipLaunchKernelGGL(k_ls_after_grad, dim3(1), dim3(64), 0, st, hdr, n);
     return hipGetLastError();
 }
 

@@ -59,37 +59,111 @@ struct WsHeader {
     int32_t accept;  // last Armijo test
     int32_t nonfinite;
     PoissonTable poisson;  // staged by the table kernel for the sweeps
-    int32_t pad[21];
+    // Line-search state of a device-driven gradient iteration (jd_optimize,
+    // the request server): the phase that may run next, ls_phase(n, j) with
+    // j = -1 the evaluation of J(u^n), g^n and j >= 0 Armijo trial j of
+    // iteration n, or kLsStop; the outcome (kLsRunning, kLsDone or a JD_E*
+    // code); the number of accepted iterations.
+    int32_t ls_status;
+    int64_t ls_phase;
+    int32_t ls_done;
+    int32_t pad[17];
 };
 static_assert(sizeof(WsHeader) == 256, "header is one 256-byte line");
+
+constexpr int32_t kLsRunning = 1;
+constexpr int32_t kLsDone = 0;
+constexpr int64_t kLsStop = -1;
+__host__ __device__ inline int64_t ls_phase(int n, int j) {
+    return ((int64_t)n << 32) | (int64_t)(uint32_t)(j + 1);
+}
+
+// One accepted iteration of a device-driven gradient iteration, written by
+// the Armijo kernel into a ring of kLsLogCap entries that follows the header
+// in the workspace (entry n % kLsLogCap for iteration n).
+struct LsLog {
+    double J, gnorm2, zeta, J_new, E2;
+    uint32_t iter;
+    int32_t backtracks;
+    int32_t n;
+    int32_t pad[3];
+};
+static_assert(sizeof(LsLog) == 64, "log entries are 64 bytes");
+constexpr int kLsLogCap = 64;
+
+// A launch gate: a kernel launched with a gate runs only when the header's
+// phase word equals `tag`, and otherwise returns at once (every block reads
+// the same word, which only a previous kernel on the stream writes).  A null
+// word means an ungated launch.
+struct Gate {
+    const int64_t* word;
+    int64_t tag;
+};
+constexpr Gate kNoGate = {nullptr, 0};
+inline Gate gate_of(WsHeader* hdr, int64_t tag) { return Gate{&hdr->ls_phase, tag}; }
 
 enum FwdMode { FWD_COST = 0, FWD_STORE = 1, FWD_CKPT = 2 };
 
 size_t real_size(int prec);
-bool recompute_supported(int prec, int D, int K);
+
+// Checkpoint-recompute adjoint.  Short intervals run a kernel that rebuilds
+// each segment in registers; where that would regenerate every step twice
+// (d = 8) or the interval exceeds its buffers, a persistent kernel of
+// seg_blocks() blocks regenerates each segment once into a scratch region of
+// K d 256 elements per block in the workspace (seg_scratch_bytes(), at most
+// kSegScratchMax; larger intervals are JD_EUNSUPPORTED).
+constexpr int kSegBlocks = 1024;
+constexpr size_t kSegScratchMax = (size_t)8 << 30;
+inline int seg_blocks(const HostRun& r) { return r.nblk < kSegBlocks ? r.nblk : kSegBlocks; }
+bool recompute_uses_segments(int prec, int D, int K);
+size_t seg_scratch_bytes(const HostProblem& p, const HostRun& r);
+bool recompute_supported(const HostProblem& p, const HostRun& r);
 
 // The table kernel runs first in every entry point and (clear_flag != 0)
-// clears the non-finite flag; the reductions raise it.
+// clears the non-finite flag; the reductions raise it.  Every launcher takes
+// an optional gate (kNoGate: always runs).
 hipError_t launch_setup(const HostProblem& p, const HostRun& r, const double* u, void* tab,
-                        WsHeader* hdr, int clear_flag, hipStream_t st);
+                        WsHeader* hdr, int clear_flag, hipStream_t st, Gate gate = kNoGate);
 hipError_t launch_forward(const HostProblem& p, const HostRun& r, const void* tab, void* traj,
-                          int fwd_mode, double* cpart, const WsHeader* hdr, hipStream_t st);
+                          int fwd_mode, double* cpart, const WsHeader* hdr, hipStream_t st,
+                          Gate gate = kNoGate);
+// seg: the workspace's segment scratch (seg_scratch_bytes(); unused otherwise)
 hipError_t launch_adjoint(const HostProblem& p, const HostRun& r, const void* tab, const void* traj,
-                          double* apart, const WsHeader* hdr, hipStream_t st);
+                          double* apart, void* seg, const WsHeader* hdr, hipStream_t st,
+                          Gate gate = kNoGate);
 // Forward (stored trajectory) and adjoint fused per block (no dump support).
 hipError_t launch_cost_grad_stored(const HostProblem& p, const HostRun& r, const void* tab,
                                   void* traj, double* cpart, double* apart, const WsHeader* hdr,
-                                  hipStream_t st);
+                                  hipStream_t st, Gate gate = kNoGate);
 hipError_t launch_finalize_grad(const HostProblem& p, const HostRun& r, const double* apart,
-                                const double* u, double* g, WsHeader* hdr, hipStream_t st);
-// slot 0: J -> hdr->J (and J_out), with gnorm2 from g if g != nullptr; slot 1: -> hdr->J_trial
+                                const double* u, double* g, WsHeader* hdr, hipStream_t st,
+                                Gate gate = kNoGate);
+// slot 0: J -> hdr->J (and J_out), with gnorm2 from g if g != nullptr, and a
+// non-finite J or g raises the flag; slot 1 (a line-search trial): ->
+// hdr->J_trial, no flag (the Armijo test rejects a non-finite trial cost)
 hipError_t launch_finalize_cost(const HostProblem& p, const HostRun& r, const double* cpart,
                                 const double* u, const double* g, double* J_out, WsHeader* hdr,
-                                int slot, hipStream_t st);
+                                int slot, hipStream_t st, Gate gate = kNoGate);
 hipError_t launch_trial(const double* u, const double* g, double zeta, double* ut, int nd,
-                        hipStream_t st);
-hipError_t launch_armijo(WsHeader* hdr, double* u, const double* ut, int nd, double c_armijo,
-                         double zeta, double dt, hipStream_t st);
+                        hipStream_t st, Gate gate = kNoGate);
+
+// Device-driven line search (Section 5, Algorithm 5.4 with eq.
+// Stochastic_Armijo).  ls_start opens phase (0, -1); ls_after_grad (gated
+// by phase (n, -1)) moves to trial (n, 0), or stops with JD_ENONFINITE when
+// J or g is not finite; the Armijo test of trial (n, j) (gated by its phase)
+// accepts when J_trial is finite and J_trial <= J - c zeta ||g||^2_L2, moves u
+// to the trial point, logs the iteration and opens (n + 1, -1) or stops
+// (n + 1 == n_max, or ||u' - u||_L2 <= tol); on rejection it opens (n, j + 1)
+// or stops with JD_ELINESEARCH after max_backtracks trials.
+struct LsArmijo {
+    double c_armijo, zeta, dt, tol;
+    int n, j, n_max, max_backtracks;
+    uint32_t iter;
+};
+hipError_t launch_ls_start(WsHeader* hdr, hipStream_t st);
+hipError_t launch_ls_after_grad(WsHeader* hdr, int n, hipStream_t st);
+hipError_t launch_armijo(WsHeader* hdr, LsLog* ring, double* u, const double* ut, int nd,
+                         const LsArmijo& ls, hipStream_t st);
 hipError_t launch_draws(const HostProblem& p, const HostRun& r, int64_t m0, int64_t mc, int k0,
                         int kc, void* zw, void* zj, int32_t* counts, hipStream_t st);
 hipError_t launch_philox(uint64_t seed, const uint32_t* ctr, int64_t n, uint32_t* out,

@@ -8,12 +8,16 @@
 //    soon as a slot and an extent of the arena are free.
 //  * Overlap: admitted requests are spread over a few HIP streams; their
 //    sweeps, reductions and line-search kernels run concurrently on the
-//    device.  The host never blocks on one request: each request is a small
-//    state machine advanced when the event after its last enqueued step has
-//    completed (the Armijo outcome is read from a pinned copy of its workspace
-//    header).
+//    device.  Each request's line search runs on the device (the gated phases
+//    of jd_optimize: the device decides every Armijo trial and keeps u and the
+//    counter word); the host enqueues a batch of kServeBatch iterations at a
+//    time and looks at the request again only when the event after that batch
+//    has completed, reading its outcome and log from a pinned copy of the
+//    workspace header.  The host never blocks on one request.
 //  * Results are identical to jd_optimize for the same request alone: the
 //    same kernels run on the same per-request data in the same order.
+//  * A request whose admission or enqueueing fails ends with that error as
+//    its status; its stream is drained before its memory is reused.
 //
 // Single-threaded: one host thread drives a server.
 #include <math.h>
@@ -83,6 +87,11 @@ class Arena {
 
 enum State { QUEUED, RUNNING, FINISHING, DONE };
 
+// Iterations enqueued per request between two looks at it: small enough that
+// requests sharing a stream interleave, large enough that the host is not in
+// the loop of every iteration.
+constexpr int kServeBatch = 4;
+
 struct Request {
     int64_t ticket;
     // host copies of the problem data
@@ -103,10 +112,24 @@ struct Request {
     hipEvent_t ev;
     State state;
     int status;
-    int n, bt;
-    double zeta;
+    LsDriver drv;
     std::vector<jd_iter_log> log;
     std::vector<double> u_out;
+};
+
+struct ReqOps : LsOps {
+    Request& q;
+    explicit ReqOps(Request& q_) : q(q_) {}
+    int grad(int n, Gate gate, hipStream_t st) override {
+        HostRun rn = q.r;
+        rn.iter = q.run.iter + (uint32_t)n;
+        return enqueue_cost_grad(q.p, rn, q.u_dev, nullptr, q.w.gbuf, q.traj, q.w, st, gate);
+    }
+    int trial(int n, double zeta, Gate gate, hipStream_t st) override {
+        HostRun rn = q.r;
+        rn.iter = q.run.iter + (uint32_t)n;
+        return enqueue_trial(q.p, rn, q.u_dev, zeta, q.w, st, gate);
+    }
 };
 
 }  // namespace
@@ -118,7 +141,7 @@ struct jd_server {
     int max_active;
     std::vector<hipStream_t> streams;
     std::vector<int> stream_load;
-    WsHeader* mirrors;  // pinned host memory, one header per active slot
+    char* mirrors;  // pinned host memory, one header + log ring per active slot
     std::vector<int> free_mirrors;
     std::deque<int64_t> queue;
     std::map<int64_t, std::unique_ptr<Request>> reqs;
@@ -138,27 +161,17 @@ size_t footprint(const HostProblem& p, const HostRun& r, size_t* su, size_t* sxd
     return *su + *sxd + *st + *sw;
 }
 
-int enqueue_iteration(jd_server* S, Request& q) {
-    hipStream_t st = S->streams[q.stream];
-    q.r.iter = q.run.iter + (uint32_t)q.n;
-    q.bt = 0;
-    q.zeta = q.opt.zeta0;
-    int rc = enqueue_cost_grad(q.p, q.r, q.u_dev, nullptr, q.w.gbuf, q.traj, q.w, st);
-    if (rc)
-        return rc;
-    if ((rc = enqueue_trial(q.p, q.r, q.u_dev, q.opt, q.zeta, q.w, st)))
-        return rc;
-    JD_TRY(hipMemcpyAsync(&S->mirrors[q.mirror], q.w.hdr, sizeof(WsHeader), hipMemcpyDeviceToHost, st));
-    JD_TRY(hipEventRecord(q.ev, st));
-    return JD_OK;
-}
+char* mirror_of(jd_server* S, const Request& q) { return S->mirrors + (size_t)q.mirror * kLsMirrorBytes; }
 
-int enqueue_retry(jd_server* S, Request& q) {
+// The next batch of the request's iterations, then a copy of its header and
+// log ring and the event the host polls.
+int enqueue_batch(jd_server* S, Request& q) {
     hipStream_t st = S->streams[q.stream];
-    int rc = enqueue_trial(q.p, q.r, q.u_dev, q.opt, q.zeta, q.w, st);
+    ReqOps ops(q);
+    int rc = q.drv.enqueue(ops, kServeBatch, st);
     if (rc)
         return rc;
-    JD_TRY(hipMemcpyAsync(&S->mirrors[q.mirror], q.w.hdr, sizeof(WsHeader), hipMemcpyDeviceToHost, st));
+    JD_TRY(hipMemcpyAsync(mirror_of(S, q), q.w.hdr, kLsMirrorBytes, hipMemcpyDeviceToHost, st));
     JD_TRY(hipEventRecord(q.ev, st));
     return JD_OK;
 }
@@ -183,6 +196,20 @@ void release(jd_server* S, Request& q) {
     S->active--;
 }
 
+// A request that failed after admission: wait until its stream has no more of
+// its work in flight, return its slot, mirror and memory, and end it with the
+// error as its status (no control is returned).
+void fail(jd_server* S, Request& q, int status) {
+    (void)hipStreamSynchronize(S->streams[q.stream]);
+    q.u_out.clear();
+    q.status = status;
+    q.state = DONE;
+    release(S, q);
+    S->completed++;
+}
+
+// 0: admitted; 1: does not fit now; otherwise the request ended with that
+// error (it is DONE and holds nothing).
 int admit(jd_server* S, Request& q) {
     if (!S->arena->alloc(q.bytes, &q.off))
         return 1;  // does not fit now
@@ -193,8 +220,13 @@ int admit(jd_server* S, Request& q) {
     q.ws = base + q.sz_u + q.sz_xd + q.sz_traj;
     q.p.xd = q.xd_dev;
     int rc = bind_ws(q.p, q.r, q.ws, q.sz_ws, q.w);
+    if (rc == JD_OK && hipEventCreateWithFlags(&q.ev, hipEventDisableTiming) != hipSuccess)
+        rc = JD_EHIP;
     if (rc) {
         S->arena->release(q.off, q.bytes);
+        q.status = rc;
+        q.state = DONE;
+        S->completed++;
         return rc;
     }
     int best = 0;
@@ -206,22 +238,35 @@ int admit(jd_server* S, Request& q) {
     q.mirror = S->free_mirrors.back();
     S->free_mirrors.pop_back();
     S->active++;
-    hipStream_t st = S->streams[q.stream];
     q.state = RUNNING;
-    q.n = 0;
-    if (hipEventCreateWithFlags(&q.ev, hipEventDisableTiming) != hipSuccess) {
-        q.ev = nullptr;
-        return JD_EHIP;
-    }
+    hipStream_t st = S->streams[q.stream];
     const size_t nd = (size_t)q.p.N * q.p.d;
-    JD_TRY(hipMemcpyAsync(q.xd_dev, q.xd.data(), nd * sizeof(double), hipMemcpyHostToDevice, st));
-    JD_TRY(hipMemcpyAsync(q.u_dev, q.u0.data(), nd * sizeof(double), hipMemcpyHostToDevice, st));
-    if (q.opt.n_max == 0)
-        return enqueue_finish(S, q, JD_OK);
-    return enqueue_iteration(S, q);
+    q.log.assign((size_t)q.opt.n_max, jd_iter_log());
+    q.drv.opt = q.opt;
+    q.drv.hdr = q.w.hdr;
+    q.drv.ring = q.w.ring;
+    q.drv.u = q.u_dev;
+    q.drv.ut = q.w.ut;
+    q.drv.nd = (int)nd;
+    q.drv.dt = q.p.dt;
+    q.drv.iter0 = q.run.iter;
+    if (hipMemcpyAsync(q.xd_dev, q.xd.data(), nd * sizeof(double), hipMemcpyHostToDevice, st) !=
+            hipSuccess ||
+        hipMemcpyAsync(q.u_dev, q.u0.data(), nd * sizeof(double), hipMemcpyHostToDevice, st) !=
+            hipSuccess)
+        rc = JD_EHIP;
+    else if (q.opt.n_max == 0)
+        rc = enqueue_finish(S, q, JD_OK);
+    else if (!(rc = q.drv.start(st)))
+        rc = enqueue_batch(S, q);
+    if (rc) {
+        fail(S, q, rc);
+        return rc;
+    }
+    return 0;
 }
 
-// Advance one running request whose last step has completed.
+// Advance one running request whose last enqueued batch has completed.
 int advance(jd_server* S, Request& q) {
     if (q.state == FINISHING) {
         q.state = DONE;
@@ -229,28 +274,14 @@ int advance(jd_server* S, Request& q) {
         S->completed++;
         return JD_OK;
     }
-    const WsHeader& h = S->mirrors[q.mirror];
-    if (h.nonfinite)
-        return enqueue_finish(S, q, JD_ENONFINITE);
-    if (h.accept) {
-        jd_iter_log L;
-        L.iter = q.r.iter;
-        L.backtracks = q.bt;
-        L.J = h.J;
-        L.gnorm = sqrt(h.gnorm2);
-        L.zeta = q.zeta;
-        L.J_new = h.J_trial;
-        L.E = sqrt(h.E2);
-        q.log.push_back(L);
-        q.n++;
-        if (q.n >= q.opt.n_max || L.E <= q.opt.tol)
-            return enqueue_finish(S, q, JD_OK);
-        return enqueue_iteration(S, q);
-    }
-    if (++q.bt >= q.opt.max_backtracks)
-        return enqueue_finish(S, q, JD_ELINESEARCH);
-    q.zeta *= q.opt.rho;
-    return enqueue_retry(S, q);
+    int rc;
+    if (q.drv.collect(mirror_of(S, q), q.log.data()))
+        rc = enqueue_finish(S, q, q.drv.status);
+    else
+        rc = enqueue_batch(S, q);
+    if (rc)
+        fail(S, q, rc);
+    return rc;
 }
 
 }  // namespace
@@ -282,7 +313,7 @@ int jd_server_create(void* arena, size_t arena_bytes, int32_t max_active, int32_
     S->next_ticket = 1;
     S->completed = 0;
     S->mirrors = nullptr;
-    if (hipHostMalloc((void**)&S->mirrors, sizeof(WsHeader) * max_active, hipHostMallocDefault) !=
+    if (hipHostMalloc((void**)&S->mirrors, kLsMirrorBytes * max_active, hipHostMallocDefault) !=
         hipSuccess)
         return JD_EHIP;
     for (int i = max_active - 1; i >= 0; --i)
@@ -363,8 +394,12 @@ int jd_server_progress(jd_server* S, int32_t* n_active, int32_t* n_queued, int64
         const hipError_t e = hipEventQuery(q.ev);
         if (e == hipErrorNotReady)
             continue;
-        if (e != hipSuccess)
-            return JD_EHIP;
+        if (e != hipSuccess) {
+            fail(S, q, JD_EHIP);
+            if (!rc)
+                rc = JD_EHIP;
+            continue;
+        }
         const int r2 = advance(S, q);
         if (r2 && !rc)
             rc = r2;
@@ -402,10 +437,10 @@ int jd_server_result(jd_server* S, int64_t ticket, double* u_host, jd_iter_log* 
         return JD_EAGAIN;
     if (u_host)
         memcpy(u_host, q.u_out.data(), q.u_out.size() * sizeof(double));
-    if (log && !q.log.empty())
-        memcpy(log, q.log.data(), q.log.size() * sizeof(jd_iter_log));
+    if (log && q.drv.copied > 0)
+        memcpy(log, q.log.data(), (size_t)q.drv.copied * sizeof(jd_iter_log));
     if (iters)
-        *iters = (int32_t)q.log.size();
+        *iters = (int32_t)q.drv.copied;
     if (status)
         *status = q.status;
     S->reqs.erase(it);

@@ -71,6 +71,11 @@ class Server:
         B.check(lib().jd_server_create(self.arena.data_ptr(), arena_bytes, max_active, n_streams,
                                        C.byref(self.h)), "jd_server_create")
         self.n = {}
+        self.max_active = max_active
+        # what progress() has seen: the most requests admitted and queued at
+        # once, and how many times requests waited in the queue while a slot
+        # was free (that is, for arena memory)
+        self.stats = dict(max_active=0, max_queued=0, waited_for_memory=0)
 
     def submit(self, p, M: int, seed: int, iters: int, precision: str = "fp32",
                mode: str = "store", K: int = 0, it0: int = 0, u0=None, tol: float = 0.0,
@@ -91,6 +96,11 @@ class Server:
         a, q, c = C.c_int32(), C.c_int32(), C.c_int64()
         B.check(lib().jd_server_progress(self.h, C.byref(a), C.byref(q), C.byref(c)),
                 "jd_server_progress")
+        st = self.stats
+        st["max_active"] = max(st["max_active"], a.value)
+        st["max_queued"] = max(st["max_queued"], q.value)
+        if q.value > 0 and a.value < self.max_active:
+            st["waited_for_memory"] += 1
         return a.value, q.value, c.value
 
     def result(self, ticket: int):
@@ -141,15 +151,12 @@ class Record:
 
 
 def choose_mode(p, M: int, precision: str, store_limit: int):
-    """Stored trajectory when it fits store_limit bytes, else the longest
-    checkpoint interval the register buffers support."""
+    """Stored trajectory when it fits store_limit bytes, else checkpoints every
+    64 steps (128 at d = 1)."""
     esz = 4 if precision == "fp32" else 8
     if p.N * p.d * ((M + 255) // 256 * 256) * esz <= store_limit:
         return "store", 0
-    kmax = {1: 128, 2: 64, 4: 64, 8: 64}[max(1, 1 << (p.d - 1).bit_length())]
-    if precision == "fp64":
-        kmax = {1: 64, 2: 32, 4: 32, 8: 16}[max(1, 1 << (p.d - 1).bit_length())]
-    return "recompute", min(kmax, p.N)
+    return "recompute", min(128 if p.d == 1 else 64, p.N)
 
 
 def run_mix(server: Server, requests, precision: str = "fp32", store_limit: int = 8 << 30,

@@ -4,15 +4,16 @@ Calls only the FP64 oracle (oracle/) and the seeded workload generators: for
 the c2, c3 and c4 workloads at their full path counts, iteration word 0, seed 1
 and u = 0, it records J, ||g||_L2, the L2 projections <g, delta_i> on 16 fixed
 random directions (numpy default_rng(2), L2-normalised) and 64 sampled entries
-of g; for c2 also the whole gradient.  For the paper's model problem at its
+of g into full_<name>_it0.json, and the whole gradient (N x d, FP64) into
+full_<name>_it0_g.npz.  For the paper's model problem at its
 measured size (f4: 2^20 particles, 500 steps) the same record is written at the
-control mu = random_feedback_control(p, 4, 0.5), and so for the coupled rings
-of Section 6.4 at their measured size (ring2: 512 rings of 2000 particles, 500
-steps) and the jump-adapted grid at f4's size (ja2).  Run from the repository
+control mu = random_feedback_control(p, 4, 0.5) (whole gradient N x L), and so
+for the coupled rings of Section 6.4 at their measured size (ring2: 512 rings
+of 2000 particles, 500 steps) and the jump-adapted grid at f4's size (ja2).  Run from the repository
 root:
 
-    python tests/golden/make_full_size.py            # c2, c3, c4 (minutes on 8 cores)
-    python tests/golden/make_full_size.py c2 f4 ring2 ja2
+    python tests/golden/make_full_size.py            # every workload (minutes on 8 cores)
+    python tests/golden/make_full_size.py c3 f4      # some of them
 """
 from __future__ import annotations
 
@@ -46,6 +47,16 @@ def fb_directions(p, count=16, seed=2):
     return out
 
 
+def write(name, rec, g):
+    path = os.path.join(HERE, f"full_{name}_it0.json")
+    with open(path, "w") as f:
+        f.write("# FP64 oracle, written by tests/golden/make_full_size.py\n")
+        json.dump(rec, f, indent=None)
+        f.write("\n")
+    np.savez_compressed(os.path.join(HERE, f"full_{name}_it0_g.npz"), g=np.asarray(g, np.float64))
+    return path
+
+
 def feedback(name):
     if name.startswith("ring"):
         w = wl.ring_config(name)
@@ -66,11 +77,7 @@ def feedback(name):
         "sample_index": [int(i) for i in idx], "sample_g": [float(g.reshape(-1)[i]) for i in idx],
         "oracle_seconds": time.time() - t0,
     }
-    path = os.path.join(HERE, f"full_{name}_it0.json")
-    with open(path, "w") as f:
-        f.write("# FP64 oracle, written by tests/golden/make_full_size.py\n")
-        json.dump(rec, f, indent=None)
-        f.write("\n")
+    path = write(name, rec, g)
     print(f"{name}: J = {J:.15g}  ({time.time() - t0:.1f} s) -> {path}", flush=True)
 
 
@@ -92,15 +99,9 @@ def main(names):
             "sample_index": [int(i) for i in idx], "sample_g": [float(g.reshape(-1)[i]) for i in idx],
             "oracle_seconds": time.time() - t0,
         }
-        if name == "c2":
-            rec["g"] = [float(x) for x in g.reshape(-1)]
-        path = os.path.join(HERE, f"full_{name}_it0.json")
-        with open(path, "w") as f:
-            f.write("# FP64 oracle, written by tests/golden/make_full_size.py\n")
-            json.dump(rec, f, indent=None)
-            f.write("\n")
+        path = write(name, rec, g)
         print(f"{name}: J = {J:.15g}  ({time.time() - t0:.1f} s) -> {path}", flush=True)
 
 
 if __name__ == "__main__":
-    main(sys.argv[1:] or ["c2", "c3", "c4"])
+    main(sys.argv[1:] or ["c2", "c3", "c4", "f4", "ring2", "ja2"])

@@ -103,6 +103,15 @@ def test_workspace_and_traj_sizes(L):
     assert tb64 == 2 * tb
     _, tck = _sizes(L, pr, B.make_run(M, precision="fp32", mode="recompute", K=32))
     assert tck == (p.N // 32 + (p.N % 32 > 0)) * M * 4
+    # d = 8, K = 64: the segment scratch of the recompute adjoint, one region of
+    # K d 256 elements for each of min(blocks, 1024) resident blocks
+    p8 = wl.config("c4").problem
+    ws8, _ = _sizes(L, _Dummy(p8), B.make_run(1 << 18, precision="fp32", mode="recompute", K=64))
+    ws8s, _ = _sizes(L, _Dummy(p8), B.make_run(1 << 18, precision="fp32", mode="store"))
+    assert ws8 - ws8s >= 1024 * 64 * 8 * 256 * 4
+    assert ws8 - ws8s < 1024 * 64 * 8 * 256 * 4 + (1 << 20)
+    ws8d, _ = _sizes(L, _Dummy(p8), B.make_run(1 << 18, precision="fp64", mode="recompute", K=64))
+    assert ws8d > 1024 * 64 * 8 * 256 * 8
     # blocks of 256 paths
     _, t7 = _sizes(L, pr, B.make_run(7, precision="fp32"))
     assert t7 == p.N * 256 * 4
@@ -157,10 +166,13 @@ def test_invalid_arguments_rejected_before_launch(L):
     assert badrun(mode=3) == B.JD_EINVAL
     assert badrun(mode=B.JD_RECOMPUTE, K=0) == B.JD_EINVAL
     assert badrun(mode=B.JD_RECOMPUTE, K=21) == B.JD_EINVAL
-    # a checkpoint interval beyond the register buffers is refused, not mis-run
-    q = _Dummy(wl.general_problem(8, 400, seed=2))
-    r = B.make_run(1000, precision="fp32", mode="recompute", K=65)
+    # a checkpoint interval whose segment scratch would exceed 8 GiB (1024
+    # regions of K d 256 elements) is refused, not mis-run
+    q = _Dummy(wl.general_problem(8, 2000, seed=2))
+    r = B.make_run(1 << 20, precision="fp32", mode="recompute", K=1100)
     assert L.jd_forward(C.byref(q.st), C.byref(r), fake, fake, fake, fake, ws, None) == B.JD_EUNSUPPORTED
+    r = B.make_run(1 << 20, precision="fp32", mode="recompute", K=1000)
+    assert L.jd_workspace_bytes(C.byref(q.st), C.byref(r)) > 0
     # dump range outside [0, M)
     dp = B.jd_dump(990, 20, None, None, None)
     r = B.make_run(1000, dump=dp)

@@ -17,7 +17,8 @@ from oracle import ref
 from paper_2505_04328_amd import binding as B
 from paper_2505_04328_amd import workloads as wl
 
-from parity_util import TOL, gpu_device, norm_err, per_path_error, rel_err
+from parity_util import (TOL, assert_grad, golden, golden_g, gpu_device, grad_errors, norm_err,
+                         per_path_error, rel_err)
 
 pytestmark = pytest.mark.gpu
 
@@ -97,13 +98,14 @@ def test_fb_cost_grad_and_paths(dev, name, precision):
     e_l = per_path_error(lg[:, 1:], lam[:, 1:])
     e_c = float(np.max(np.abs(d["cost"].cpu().numpy() - C) / (np.abs(C) + np.sqrt(np.mean(C * C)))))
     e_J, e_J2 = rel_err(float(J), J_ref), rel_err(float(Jc), J_ref)
-    e_g = norm_err(gc.cpu().numpy(), g_ref)
-    say(f"   errors: z {e_z:.2e} lam {e_l:.2e} C {e_c:.2e} J {e_J:.2e} g {e_g:.2e}")
+    e_g, e_ge = grad_errors(gc.cpu().numpy(), g_ref)
+    say(f"   errors: z {e_z:.2e} lam {e_l:.2e} C {e_c:.2e} J {e_J:.2e} g {e_g:.2e} "
+        f"(per entry {e_ge:.2e})")
     assert e_z <= tol["path"]
     assert e_l <= tol["path"]
     assert e_c <= tol["path"]
     assert e_J <= tol["J"] and e_J2 <= tol["J"]
-    assert e_g <= tol["g"]
+    assert e_g <= tol["g"] and e_ge <= tol["g"]
     traj = np.transpose(eng.trajectory().double().cpu().numpy(), (2, 0, 1))
     assert per_path_error(traj, z) <= tol["path"]
 
@@ -127,7 +129,7 @@ def test_fb_edge_shapes(dev, label, N, nx, nv, M):
     J, g = eng.cost_grad(mu, it=1)
     J_ref, g_ref = ref.fb_cost_grad(p, M, 13, 1, mu)
     assert rel_err(float(J), J_ref) <= TOL["fp32"]["J"]
-    assert norm_err(g.cpu().numpy(), g_ref) <= TOL["fp32"]["g"]
+    assert_grad(g.cpu().numpy(), g_ref, TOL["fp32"]["g"])
 
 
 def test_fb_zero_control_gradient_is_tracking_only(dev):
@@ -164,11 +166,8 @@ def test_fb_full_size_f4(dev):
     entries of g against the oracle values of tests/golden/full_f4_it0.json
     (written by tests/golden/make_full_size.py); per-particle states, adjoints
     and costs of the first and last 4096 particles against the oracle here."""
-    import json
-    import os
     import torch
-    with open(os.path.join(os.path.dirname(__file__), "golden", "full_f4_it0.json")) as f:
-        gd = json.loads("".join(ln for ln in f if not ln.startswith("#")))
+    gd = golden("f4")
     w = wl.feedback_config("f4")
     p = w.problem
     say("fb full size f4", w.M, p.N)
@@ -189,6 +188,8 @@ def test_fb_full_size_f4(dev):
     flat = g.reshape(-1)
     for i, v in zip(gd["sample_index"], gd["sample_g"]):
         assert abs(flat[i] - v) <= tol["g"] * gd["gnorm_L2"]
+    en, ee = assert_grad(g, golden_g("f4"), tol["g"])
+    say(f"   g vs oracle: normwise {en:.2e}, per entry {ee:.2e}")
     for m0 in (0, w.M - 4096):
         dp, dd = eng.path_dump(m0, 4096)
         eng.forward(mu, it=0, dump=dp)
@@ -217,9 +218,10 @@ def test_fb_large_m_ragged_last_block(dev, M, precision):
     eng = B.FbEngine(p, M=M, seed=17, precision=precision, device=dev)
     J, g = eng.cost_grad(mu, it=2)
     J_ref, g_ref = ref.fb_cost_grad(p, M, 17, 2, mu)
-    e_J, e_g = rel_err(float(J), J_ref), norm_err(g.cpu().numpy(), g_ref)
-    say(f"   J {e_J:.2e} g {e_g:.2e}")
-    assert e_J <= TOL[precision]["J"] and e_g <= TOL[precision]["g"]
+    e_J = rel_err(float(J), J_ref)
+    e_g, e_ge = grad_errors(g.cpu().numpy(), g_ref)
+    say(f"   J {e_J:.2e} g {e_g:.2e} (per entry {e_ge:.2e})")
+    assert e_J <= TOL[precision]["J"] and e_g <= TOL[precision]["g"] and e_ge <= TOL[precision]["g"]
 
 
 # ---------------------------------------------------------------- surrogate gradient (Section 6.5)
@@ -255,10 +257,12 @@ def test_fb_surrogate_cost_grad_and_paths(dev, name, precision):
     lg = np.transpose(d["lam"].double().cpu().numpy(), (2, 0, 1))
     e_z, e_l = per_path_error(zg, z), per_path_error(lg[:, 1:], ls[:, 1:])
     e_c = float(np.max(np.abs(d["cost"].cpu().numpy() - C) / (np.abs(C) + np.sqrt(np.mean(C * C)))))
-    e_J, e_g = rel_err(J, J_ref), norm_err(g, g_ref)
-    say(f"   errors: z {e_z:.2e} lam {e_l:.2e} C {e_c:.2e} J {e_J:.2e} g {e_g:.2e}")
+    e_J = rel_err(J, J_ref)
+    e_g, e_ge = grad_errors(g, g_ref)
+    say(f"   errors: z {e_z:.2e} lam {e_l:.2e} C {e_c:.2e} J {e_J:.2e} g {e_g:.2e} "
+        f"(per entry {e_ge:.2e})")
     assert e_z <= tol["path"] and e_l <= tol["path"] and e_c <= tol["path"]
-    assert e_J <= tol["J"] and e_g <= tol["g"]
+    assert e_J <= tol["J"] and e_g <= tol["g"] and e_ge <= tol["g"]
     # biased: not the exact gradient
     _, g_exact = ref.fb_cost_grad(p, M, seed, it, mu)
     assert norm_err(g, g_exact) > 1e-3
@@ -276,7 +280,7 @@ def test_fb_surrogate_large_m(dev, precision):
     J, g = eng.cost_grad(mu, it=2)
     J_ref, g_ref = ref.fb_cost_grad_surrogate(p, M, 17, 2, mu)
     assert rel_err(float(J), J_ref) <= TOL[precision]["J"]
-    assert norm_err(g.cpu().numpy(), g_ref) <= TOL[precision]["g"]
+    assert_grad(g.cpu().numpy(), g_ref, TOL[precision]["g"])
 
 
 def test_fb_surrogate_optimize_matches_oracle(dev):

@@ -12,7 +12,7 @@ from oracle import ref
 from paper_2505_04328_amd import binding as B
 from paper_2505_04328_amd import workloads as wl
 
-from parity_util import TOL, gpu_device, norm_err, rel_err
+from parity_util import TOL, assert_grad, gpu_device, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -45,7 +45,7 @@ def _replay(dev, p, M, seed, precision, iters, mode="store", K=0, zeta0=1.0, c=1
         Jg, gg = eng.cost_grad(u_before, it=n)
         assert rel_err(lg["J"], J_ref) <= tol["J"]
         assert rel_err(float(Jg), J_ref) <= tol["J"]
-        assert norm_err(gg.cpu().numpy(), g_ref) <= tol["g"]
+        assert_grad(gg.cpu().numpy(), g_ref, tol["g"], f"iteration {n}")
         gn_ref = np.sqrt(p.dt * np.sum(g_ref * g_ref))
         assert rel_err(lg["gnorm"], gn_ref) <= tol["g"]
         # Armijo on the same draws, and the step is -zeta g
@@ -104,3 +104,65 @@ def test_linesearch_failure_leaves_u(dev):
         eng.optimize(u, n_max=3, it0=0, zeta0=1e6, max_backtracks=1)
     assert e.value.code == B.JD_ELINESEARCH
     assert torch.count_nonzero(u).item() == 0
+
+
+def test_overflowing_trial_is_rejected_fp64(dev):
+    """A first step so large that the trial's cubic drift overflows (J of the
+    trial is not finite): the Armijo test rejects the trial and backtracks, as
+    the oracle does, instead of ending the iteration with JD_ENONFINITE."""
+    say("c4-shaped fp64, overflowing first trials")
+    w = wl.scaled(wl.config("c4"), M=300, N=100)
+    p = w.problem
+    J, _ = ref.cost_grad(p, w.M, w.seed, 0, 1e4 * np.ones((p.N, p.d)), grad=False)
+    assert not np.isfinite(J)  # a step to u ~ 1e4 overflows
+    assert _replay(dev, p, w.M, w.seed, "fp64", 2, zeta0=1e5) == 0
+
+
+def test_overflowing_trial_is_rejected_fp32(dev):
+    import torch
+    w = wl.scaled(wl.config("c4"), M=300, N=100)
+    p = w.problem
+    eng = B.Engine(p, M=w.M, seed=w.seed, precision="fp32", mode="recompute", K=64, device=dev)
+    u = torch.zeros((p.N, p.d), dtype=torch.float64, device=dev)
+    _, logs = eng.optimize(u, n_max=2, zeta0=1e5)
+    assert len(logs) == 2 and logs[0]["backtracks"] > 0
+    assert all(np.isfinite(l["J_new"]) for l in logs)
+
+
+def test_more_iterations_than_one_batch(dev):
+    """70 iterations in one call: more than one batch of the device-driven
+    iteration (64) and its log ring; the logs and the control equal those of
+    70 calls of one iteration each, bit for bit."""
+    import torch
+    w = wl.scaled(wl.config("c1"), M=2000)
+    p = w.problem
+    eng = B.Engine(p, M=w.M, seed=w.seed, precision="fp64", device=dev)
+    u1 = torch.zeros((p.N, 1), dtype=torch.float64, device=dev)
+    _, logs1 = eng.optimize(u1, n_max=70, zeta0=4.0)
+    assert len(logs1) == 70
+    u2 = torch.zeros((p.N, 1), dtype=torch.float64, device=dev)
+    logs2 = []
+    for n in range(70):
+        _, lg = eng.optimize(u2, n_max=1, it0=n, zeta0=4.0)
+        logs2 += lg
+    assert torch.equal(u1, u2)
+    assert logs1 == logs2
+    assert [l["iter"] for l in logs1] == list(range(70))
+    assert any(l["backtracks"] > 0 for l in logs1)
+
+
+def test_tolerance_stops_on_the_device(dev):
+    """tol > 0: the device stops the iteration at the first accepted step with
+    ||u' - u||_L2 <= tol; the call reports the iterations done."""
+    import torch
+    w = wl.scaled(wl.config("c1"), M=2000)
+    p = w.problem
+    eng = B.Engine(p, M=w.M, seed=w.seed, precision="fp64", device=dev)
+    u = torch.zeros((p.N, 1), dtype=torch.float64, device=dev)
+    _, full = eng.optimize(u.clone(), n_max=20)
+    Es = [l["E"] for l in full]
+    tol = sorted(Es)[len(Es) // 2]
+    stop = next(i for i, E in enumerate(Es) if E <= tol)
+    _, logs = eng.optimize(u, n_max=20, tol=tol)
+    assert len(logs) == stop + 1
+    assert logs == full[:stop + 1]
