@@ -313,7 +313,12 @@ typedef struct {
     /* jump-adapted grid, per interval k and sub-step r (index k FB_SUB + r):
      * start states sz (x, v), controls su, lengths sd, start offsets sa */
     double *sz, *su, *sd, *sa;
+    int absval; /* gradient-scale diagnostic: accumulate |summand| */
 } work;
+
+/* A particle's gradient summand as accumulated: itself, or its absolute value
+ * for the gradient-scale diagnostic. */
+static double summand(const work* w, double v) { return w->absval ? fabs(v) : v; }
 
 static int work_alloc(const fb_problem* pb, work* w)
 {
@@ -333,6 +338,7 @@ static int work_alloc(const fb_problem* pb, work* w)
     w->su = (double*)malloc(ns * sizeof(double));
     w->sd = (double*)malloc(ns * sizeof(double));
     w->sa = (double*)malloc(ns * sizeof(double));
+    w->absval = 0;
     return (w->z && w->lam && w->u && w->n && w->C && w->w && w->px && w->pv && w->dpx && w->dpv &&
             w->sz && w->su && w->sd && w->sa)
                ? 0
@@ -436,7 +442,7 @@ static void path_adjoint_fixed(const fb_problem* pb, const double* mu, work* w, 
                 double wk = pb->alpha * u + gn * lv;
                 for (int i = 0; i < pb->nx; ++i)
                     for (int l = 0; l < pb->nv; ++l)
-                        G[(size_t)k * L + i * pb->nv + l] += w->px[i] * w->pv[l] * wk;
+                        G[(size_t)k * L + i * pb->nv + l] += summand(w, w->px[i] * w->pv[l] * wk);
             }
             if (k == 0)
                 continue;
@@ -532,7 +538,7 @@ static void path_adjoint_adapted(const fb_problem* pb, const double* mu, work* w
                 double wk = (d / dtau) * (pb->alpha * u + lvm);
                 for (int i = 0; i < pb->nx; ++i)
                     for (int l = 0; l < pb->nv; ++l)
-                        G[(size_t)k * L + i * pb->nv + l] += w->px[i] * w->pv[l] * wk;
+                        G[(size_t)k * L + i * pb->nv + l] += summand(w, w->px[i] * w->pv[l] * wk);
             }
             if (k == 0 && r == 0)
                 break;
@@ -640,8 +646,8 @@ static int64_t chunk_systems(const fb_problem* pb)
 /* Monte Carlo reductions in chunks of consecutive systems, each chunk in
  * system order and the chunks in index order (thread-count independent);
  * the means are over the M np particles. */
-int fb_cost_grad(const fb_problem* pb, int64_t M, uint64_t seed, uint32_t iter,
-                 const double* mu, double* J, double* g, int nthreads)
+static int cost_grad_impl(const fb_problem* pb, int64_t M, uint64_t seed, uint32_t iter,
+                          const double* mu, double* J, double* g, int nthreads, int absval)
 {
     if (check_problem(pb) || M < 1 || !mu || !J)
         return -1;
@@ -665,6 +671,7 @@ int fb_cost_grad(const fb_problem* pb, int64_t M, uint64_t seed, uint32_t iter,
         work w;
         const int ok = work_alloc(pb, &w) == 0;
         rc |= ok ? 0 : 1;
+        w.absval = absval;
         {
 #pragma omp for schedule(dynamic, 1)
             for (int64_t c = 0; c < nchunk; ++c) {
@@ -704,6 +711,21 @@ int fb_cost_grad(const fb_problem* pb, int64_t M, uint64_t seed, uint32_t iter,
     return 0;
 }
 
+int fb_cost_grad(const fb_problem* pb, int64_t M, uint64_t seed, uint32_t iter,
+                 const double* mu, double* J, double* g, int nthreads)
+{
+    return cost_grad_impl(pb, M, seed, iter, mu, J, g, nthreads, 0);
+}
+
+int fb_grad_scale(const fb_problem* pb, int64_t M, uint64_t seed, uint32_t iter,
+                  const double* mu, double* s, int nthreads)
+{
+    double J;
+    if (!s)
+        return -1;
+    return cost_grad_impl(pb, M, seed, iter, mu, &J, s, nthreads, 1);
+}
+
 /* The surrogate adjoint of path m (forward jump counts in w->n): the recursion
  * of path_adjoint at the states zs_k; adds gamma^{n_k} ls^v_{k+1} phi(zs_k) to
  * G.  Writes the surrogate adjoint into w->lam.  Independent particles only. */
@@ -726,7 +748,7 @@ static void path_adjoint_surrogate(const fb_problem* pb, const double* mu, uint6
         ks_factors(pb, w->n[k], &gn, &Vn);
         for (int i = 0; i < pb->nx; ++i)
             for (int l = 0; l < pb->nv; ++l)
-                G[(size_t)k * L + i * pb->nv + l] += w->px[i] * w->pv[l] * (gn * lv);
+                G[(size_t)k * L + i * pb->nv + l] += summand(w, w->px[i] * w->pv[l] * (gn * lv));
         if (k == 0)
             break;
         double u = control(pb, mk, w->px, w->pv);
@@ -779,8 +801,8 @@ int fb_paths_surrogate(const fb_problem* pb, uint64_t seed, uint32_t iter, int64
 
 /* Surrogate gradient (Section 6.5): the forward adds alpha u_k phi(z_k) as it
  * goes, the adjoint runs on the surrogate states; nothing is stored. */
-int fb_cost_grad_surrogate(const fb_problem* pb, int64_t M, uint64_t seed, uint32_t iter,
-                           const double* mu, double* J, double* g, int nthreads)
+static int surrogate_impl(const fb_problem* pb, int64_t M, uint64_t seed, uint32_t iter,
+                          const double* mu, double* J, double* g, int nthreads, int absval)
 {
     if (check_surrogate(pb) || M < 1 || !mu || !J || !g)
         return -1;
@@ -802,6 +824,7 @@ int fb_cost_grad_surrogate(const fb_problem* pb, int64_t M, uint64_t seed, uint3
         work w;
         const int ok = work_alloc(pb, &w) == 0;
         rc |= ok ? 0 : 1;
+        w.absval = absval;
         {
 #pragma omp for schedule(dynamic, 1)
             for (int64_t c = 0; c < nchunk; ++c) {
@@ -817,7 +840,7 @@ int fb_cost_grad_surrogate(const fb_problem* pb, int64_t M, uint64_t seed, uint3
                         double au = pb->alpha * w.u[k];
                         for (int i = 0; i < pb->nx; ++i)
                             for (int l = 0; l < pb->nv; ++l)
-                                G[(size_t)k * L + i * pb->nv + l] += w.px[i] * w.pv[l] * au;
+                                G[(size_t)k * L + i * pb->nv + l] += summand(&w, w.px[i] * w.pv[l] * au);
                     }
                     path_adjoint_surrogate(pb, mu, seed, iter, (uint32_t)m, &w, G);
                 }
@@ -844,6 +867,21 @@ int fb_cost_grad_surrogate(const fb_problem* pb, int64_t M, uint64_t seed, uint3
     free(csum);
     free(gsum);
     return 0;
+}
+
+int fb_cost_grad_surrogate(const fb_problem* pb, int64_t M, uint64_t seed, uint32_t iter,
+                           const double* mu, double* J, double* g, int nthreads)
+{
+    return surrogate_impl(pb, M, seed, iter, mu, J, g, nthreads, 0);
+}
+
+int fb_grad_scale_surrogate(const fb_problem* pb, int64_t M, uint64_t seed, uint32_t iter,
+                            const double* mu, double* s, int nthreads)
+{
+    double J;
+    if (!s)
+        return -1;
+    return surrogate_impl(pb, M, seed, iter, mu, &J, s, nthreads, 1);
 }
 
 /* Tangent of particle m's cost on the jump-adapted grid (path in w): each

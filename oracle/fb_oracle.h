@@ -119,6 +119,16 @@ int fb_paths(const fb_problem* pb, uint64_t seed, uint32_t iter, int64_t m0, int
 int fb_cost_grad(const fb_problem* pb, int64_t M, uint64_t seed, uint32_t iter,
                  const double* mu, double* J, double* g, int nthreads);
 
+/* Test diagnostic, not part of the method: s (N x L), the mean over the
+ * particles of the absolute value of each particle's gradient summand, from
+ * the same paths and loops as fb_cost_grad / fb_cost_grad_surrogate.  A
+ * gradient entry whose summands cancel is small against s, and rounding in the
+ * per-particle arithmetic moves it in proportion to s, not to its own size. */
+int fb_grad_scale(const fb_problem* pb, int64_t M, uint64_t seed, uint32_t iter,
+                  const double* mu, double* s, int nthreads);
+int fb_grad_scale_surrogate(const fb_problem* pb, int64_t M, uint64_t seed, uint32_t iter,
+                            const double* mu, double* s, int nthreads);
+
 /* Surrogate state of path m at step k. */
 void fb_surrogate_state(const fb_problem* pb, uint64_t seed, uint32_t m, uint32_t k, uint32_t iter,
                         double z[2]);

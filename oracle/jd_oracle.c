@@ -267,7 +267,7 @@ int or_paths(const or_problem* pb, uint64_t seed, uint32_t iter, int64_t m0, int
  * chunk in index order, the chunks combined in index order, so the result does
  * not depend on the thread count. */
 static int cost_grad_impl(const or_problem* pb, int64_t M, uint64_t seed, uint32_t iter,
-                          const double* u, double* J, double* g, int nthreads)
+                          const double* u, double* J, double* g, int nthreads, int absval)
 {
     if (check_problem(pb) || M < 1 || !u || !J)
         return -1;
@@ -304,7 +304,7 @@ static int cost_grad_impl(const or_problem* pb, int64_t M, uint64_t seed, uint32
                             double bl = 0.0;
                             for (int j = 0; j < d; ++j)
                                 bl += pb->B[j * d + i] * l1[j];
-                            gs[(size_t)k * d + i] += bl;
+                            gs[(size_t)k * d + i] += absval ? fabs(bl) : bl;
                         }
                     }
                 }
@@ -326,7 +326,10 @@ static int cost_grad_impl(const or_problem* pb, int64_t M, uint64_t seed, uint32
             double t = 0.0;
             for (int64_t c = 0; c < nchunk; ++c)
                 t += gsum[(size_t)c * nd + q];
-            g[q] = pb->nu * u[q] + t / (double)M;
+            if (absval)
+                g[q] = pb->nu * fabs(u[q]) + t / (double)M;
+            else
+                g[q] = pb->nu * u[q] + t / (double)M;
         }
     }
     free(csum);
@@ -337,7 +340,21 @@ static int cost_grad_impl(const or_problem* pb, int64_t M, uint64_t seed, uint32
 int or_cost_grad(const or_problem* pb, int64_t M, uint64_t seed, uint32_t iter,
                  const double* u, double* J, double* g, int nthreads)
 {
-    return cost_grad_impl(pb, M, seed, iter, u, J, g, nthreads);
+    return cost_grad_impl(pb, M, seed, iter, u, J, g, nthreads, 0);
+}
+
+/* Test diagnostic, not part of the method: the size of what each gradient
+ * entry is the mean of, s_q = nu |u_q| + (1/M) sum_m |(B^T lam^m_{k+1})_i|
+ * (q = k d + i), from the same paths and the same loop as or_cost_grad.  An
+ * entry whose summands cancel is small against s_q, and rounding in the
+ * per-path arithmetic moves it in proportion to s_q, not to its own size. */
+int or_grad_scale(const or_problem* pb, int64_t M, uint64_t seed, uint32_t iter,
+                  const double* u, double* s, int nthreads)
+{
+    double J;
+    if (!s)
+        return -1;
+    return cost_grad_impl(pb, M, seed, iter, u, &J, s, nthreads, 1);
 }
 
 /* Forward-mode (tangent-linear) derivative of J along delta: differentiates the
@@ -429,7 +446,7 @@ int or_optimize(const or_problem* pb, int64_t M, uint64_t seed, uint32_t iter0,
     for (n = 0; n < opt->n_max; ++n) {
         uint32_t it = iter0 + (uint32_t)n;
         double J;
-        if (cost_grad_impl(pb, M, seed, it, u, &J, g, nthreads)) {
+        if (or_cost_grad(pb, M, seed, it, u, &J, g, nthreads)) {
             n = -2;
             break;
         }
@@ -443,7 +460,7 @@ int or_optimize(const or_problem* pb, int64_t M, uint64_t seed, uint32_t iter0,
             for (size_t q = 0; q < nd; ++q)
                 ut[q] = u[q] - zeta * g[q];
             double Jt;
-            cost_grad_impl(pb, M, seed, it, ut, &Jt, NULL, nthreads);
+            or_cost_grad(pb, M, seed, it, ut, &Jt, NULL, nthreads);
             if (Jt <= J - opt->c_armijo * zeta * gg) {
                 accepted = 1;
                 break;

@@ -68,6 +68,11 @@ int or_paths(const or_problem* pb, uint64_t seed, uint32_t iter, int64_t m0, int
 int or_cost_grad(const or_problem* pb, int64_t M, uint64_t seed, uint32_t iter,
                  const double* u, double* J, double* g, int nthreads);
 
+/* Test diagnostic: s (N*d) = nu |u| + (1/M) sum_m |B^T lam^m_{k+1}| per entry,
+ * the scale of each gradient entry's Monte Carlo summands. */
+int or_grad_scale(const or_problem* pb, int64_t M, uint64_t seed, uint32_t iter,
+                  const double* u, double* s, int nthreads);
+
 /* Tangent-linear directional derivative dJ[delta]. */
 int or_tangent(const or_problem* pb, int64_t M, uint64_t seed, uint32_t iter,
                const double* u, const double* delta, double* dJ, int nthreads);

@@ -60,6 +60,8 @@ def _bind(L):
     L.or_paths.restype = C.c_int
     L.or_cost_grad.argtypes = [P, C.c_int64, C.c_uint64, C.c_uint32, P, P, P, C.c_int]
     L.or_cost_grad.restype = C.c_int
+    L.or_grad_scale.argtypes = [P, C.c_int64, C.c_uint64, C.c_uint32, P, P, C.c_int]
+    L.or_grad_scale.restype = C.c_int
     L.or_tangent.argtypes = [P, C.c_int64, C.c_uint64, C.c_uint32, P, P, P, C.c_int]
     L.or_tangent.restype = C.c_int
     L.or_optimize.argtypes = [P, C.c_int64, C.c_uint64, C.c_uint32, P, P, P, P, P, P, P, C.c_int]
@@ -171,6 +173,18 @@ def cost_grad(p, M: int, seed: int, it: int, u=None, grad: bool = True,
     return float(J[0]), g
 
 
+def grad_scale(p, M: int, seed: int, it: int, u=None, nthreads: int | None = None):
+    """Test diagnostic (N, d): per gradient entry, the mean over the paths of
+    the absolute value of the path's summand, nu |u| + mean |B^T lam_{k+1}|."""
+    pr = _ProblemRef(p)
+    u = _u(p, u)
+    s = np.empty((p.N, p.d))
+    rc = lib().or_grad_scale(pr.ref, M, seed, it, _ptr(u), _ptr(s), nthreads or default_threads())
+    if rc:
+        raise ValueError(f"or_grad_scale failed (rc={rc})")
+    return s
+
+
 def tangent(p, M: int, seed: int, it: int, u, delta, nthreads: int | None = None) -> float:
     pr = _ProblemRef(p)
     u = _u(p, u)
@@ -231,6 +245,10 @@ def _bind_fb(L):
     L.fb_paths.restype = C.c_int
     L.fb_cost_grad.argtypes = [P, C.c_int64, C.c_uint64, C.c_uint32, P, P, P, C.c_int]
     L.fb_cost_grad.restype = C.c_int
+    L.fb_grad_scale.argtypes = [P, C.c_int64, C.c_uint64, C.c_uint32, P, P, C.c_int]
+    L.fb_grad_scale.restype = C.c_int
+    L.fb_grad_scale_surrogate.argtypes = [P, C.c_int64, C.c_uint64, C.c_uint32, P, P, C.c_int]
+    L.fb_grad_scale_surrogate.restype = C.c_int
     L.fb_surrogate_state.argtypes = [P, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, P]
     L.fb_cost_grad_surrogate.argtypes = [P, C.c_int64, C.c_uint64, C.c_uint32, P, P, P, C.c_int]
     L.fb_cost_grad_surrogate.restype = C.c_int
@@ -335,6 +353,20 @@ def fb_cost_grad(p, M: int, seed: int, it: int, mu, grad: bool = True,
                             None if g is None else _ptr(g), nthreads or default_threads())
     assert rc == 0, rc
     return J.value, g
+
+
+def fb_grad_scale(p, M: int, seed: int, it: int, mu, surrogate: bool = False,
+                  nthreads: int | None = None) -> np.ndarray:
+    """Test diagnostic (N, L): per gradient entry, the mean over the particles
+    of the absolute value of the particle's summand (of the surrogate gradient
+    when surrogate is set)."""
+    mu = _mu(p, mu)
+    s = np.zeros((p.N, p.L))
+    fb = _Fb(p)
+    fn = _fb().fb_grad_scale_surrogate if surrogate else _fb().fb_grad_scale
+    rc = fn(fb.ref(), M, seed, it, _ptr(mu), _ptr(s), nthreads or default_threads())
+    assert rc == 0, rc
+    return s
 
 
 def fb_surrogate_state(p, seed: int, m: int, k: int, it: int) -> np.ndarray:

@@ -4,8 +4,8 @@ Calls only the FP64 oracle (oracle/) and the seeded workload generators: for
 the c2, c3 and c4 workloads at their full path counts, iteration word 0, seed 1
 and u = 0, it records J, ||g||_L2, the L2 projections <g, delta_i> on 16 fixed
 random directions (numpy default_rng(2), L2-normalised) and 64 sampled entries
-of g into full_<name>_it0.json, and the whole gradient (N x d, FP64) into
-full_<name>_it0_g.npz.  For the paper's model problem at its
+of g into full_<name>_it0.json, and the whole gradient (N x d, FP64) with the
+oracle's per-entry summand scale (ref.grad_scale) into full_<name>_it0_g.npz.  For the paper's model problem at its
 measured size (f4: 2^20 particles, 500 steps) the same record is written at the
 control mu = random_feedback_control(p, 4, 0.5) (whole gradient N x L), and so
 for the coupled rings of Section 6.4 at their measured size (ring2: 512 rings
@@ -47,13 +47,14 @@ def fb_directions(p, count=16, seed=2):
     return out
 
 
-def write(name, rec, g):
+def write(name, rec, g, scale):
     path = os.path.join(HERE, f"full_{name}_it0.json")
     with open(path, "w") as f:
         f.write("# FP64 oracle, written by tests/golden/make_full_size.py\n")
         json.dump(rec, f, indent=None)
         f.write("\n")
-    np.savez_compressed(os.path.join(HERE, f"full_{name}_it0_g.npz"), g=np.asarray(g, np.float64))
+    np.savez_compressed(os.path.join(HERE, f"full_{name}_it0_g.npz"), g=np.asarray(g, np.float64),
+                        scale=np.asarray(scale, np.float64))
     return path
 
 
@@ -68,6 +69,7 @@ def feedback(name):
     t0 = time.time()
     mu = wl.random_feedback_control(p, 4, 0.5)
     J, g = ref.fb_cost_grad(p, w.M, w.seed, 0, mu)
+    scale = ref.fb_grad_scale(p, w.M, w.seed, 0, mu)
     proj = [float(p.dt * np.sum(g * dl)) for dl in fb_directions(p)]
     idx = np.random.default_rng(5).integers(0, p.N * p.L, 64)
     rec = {
@@ -77,7 +79,7 @@ def feedback(name):
         "sample_index": [int(i) for i in idx], "sample_g": [float(g.reshape(-1)[i]) for i in idx],
         "oracle_seconds": time.time() - t0,
     }
-    path = write(name, rec, g)
+    path = write(name, rec, g, scale)
     print(f"{name}: J = {J:.15g}  ({time.time() - t0:.1f} s) -> {path}", flush=True)
 
 
@@ -90,6 +92,7 @@ def main(names):
         p = w.problem
         t0 = time.time()
         J, g = ref.cost_grad(p, w.M, w.seed, 0, np.zeros((p.N, p.d)))
+        scale = ref.grad_scale(p, w.M, w.seed, 0, np.zeros((p.N, p.d)))
         dirs = wl.fd_directions(p, 16, seed=2)
         proj = [float(p.dt * np.sum(g * dl)) for dl in dirs]
         idx = sample_index(p)
@@ -99,7 +102,7 @@ def main(names):
             "sample_index": [int(i) for i in idx], "sample_g": [float(g.reshape(-1)[i]) for i in idx],
             "oracle_seconds": time.time() - t0,
         }
-        path = write(name, rec, g)
+        path = write(name, rec, g, scale)
         print(f"{name}: J = {J:.15g}  ({time.time() - t0:.1f} s) -> {path}", flush=True)
 
 

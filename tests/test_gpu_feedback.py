@@ -83,6 +83,7 @@ def test_fb_cost_grad_and_paths(dev, name, precision):
     it = 3
     z, lam, _, _, C = ref.fb_paths(p, seed, it, 0, M, mu)
     J_ref, g_ref = ref.fb_cost_grad(p, M, seed, it, mu)
+    s_ref = ref.fb_grad_scale(p, M, seed, it, mu)
     eng = B.FbEngine(p, M=M, seed=seed, precision=precision, device=dev)
     dp, d = eng.path_dump(0, M)
     J = eng.forward(mu, it=it, dump=dp)
@@ -98,7 +99,7 @@ def test_fb_cost_grad_and_paths(dev, name, precision):
     e_l = per_path_error(lg[:, 1:], lam[:, 1:])
     e_c = float(np.max(np.abs(d["cost"].cpu().numpy() - C) / (np.abs(C) + np.sqrt(np.mean(C * C)))))
     e_J, e_J2 = rel_err(float(J), J_ref), rel_err(float(Jc), J_ref)
-    e_g, e_ge = grad_errors(gc.cpu().numpy(), g_ref)
+    e_g, e_ge = grad_errors(gc.cpu().numpy(), g_ref, s_ref)
     say(f"   errors: z {e_z:.2e} lam {e_l:.2e} C {e_c:.2e} J {e_J:.2e} g {e_g:.2e} "
         f"(per entry {e_ge:.2e})")
     assert e_z <= tol["path"]
@@ -128,8 +129,9 @@ def test_fb_edge_shapes(dev, label, N, nx, nv, M):
     eng = B.FbEngine(p, M=M, seed=13, precision="fp32", device=dev)
     J, g = eng.cost_grad(mu, it=1)
     J_ref, g_ref = ref.fb_cost_grad(p, M, 13, 1, mu)
+    s_ref = ref.fb_grad_scale(p, M, 13, 1, mu)
     assert rel_err(float(J), J_ref) <= TOL["fp32"]["J"]
-    assert_grad(g.cpu().numpy(), g_ref, TOL["fp32"]["g"])
+    assert_grad(g.cpu().numpy(), g_ref, s_ref, TOL["fp32"]["g"])
 
 
 def test_fb_zero_control_gradient_is_tracking_only(dev):
@@ -188,7 +190,7 @@ def test_fb_full_size_f4(dev):
     flat = g.reshape(-1)
     for i, v in zip(gd["sample_index"], gd["sample_g"]):
         assert abs(flat[i] - v) <= tol["g"] * gd["gnorm_L2"]
-    en, ee = assert_grad(g, golden_g("f4"), tol["g"])
+    en, ee = assert_grad(g, *golden_g("f4"), tol["g"])
     say(f"   g vs oracle: normwise {en:.2e}, per entry {ee:.2e}")
     for m0 in (0, w.M - 4096):
         dp, dd = eng.path_dump(m0, 4096)
@@ -218,8 +220,9 @@ def test_fb_large_m_ragged_last_block(dev, M, precision):
     eng = B.FbEngine(p, M=M, seed=17, precision=precision, device=dev)
     J, g = eng.cost_grad(mu, it=2)
     J_ref, g_ref = ref.fb_cost_grad(p, M, 17, 2, mu)
+    s_ref = ref.fb_grad_scale(p, M, 17, 2, mu)
     e_J = rel_err(float(J), J_ref)
-    e_g, e_ge = grad_errors(g.cpu().numpy(), g_ref)
+    e_g, e_ge = grad_errors(g.cpu().numpy(), g_ref, s_ref)
     say(f"   J {e_J:.2e} g {e_g:.2e} (per entry {e_ge:.2e})")
     assert e_J <= TOL[precision]["J"] and e_g <= TOL[precision]["g"] and e_ge <= TOL[precision]["g"]
 
@@ -237,6 +240,7 @@ def test_fb_surrogate_cost_grad_and_paths(dev, name, precision):
     z, _, _, _, C = ref.fb_paths(p, seed, it, 0, M, mu)
     ls = ref.fb_paths_surrogate(p, seed, it, 0, M, mu)
     J_ref, g_ref = ref.fb_cost_grad_surrogate(p, M, seed, it, mu)
+    s_ref = ref.fb_grad_scale(p, M, seed, it, mu, surrogate=True)
     eng = B.FbEngine(p, M=M, seed=seed, precision=precision, device=dev, mode="surrogate")
     dp, d = eng.path_dump(0, M)
     import torch
@@ -258,7 +262,7 @@ def test_fb_surrogate_cost_grad_and_paths(dev, name, precision):
     e_z, e_l = per_path_error(zg, z), per_path_error(lg[:, 1:], ls[:, 1:])
     e_c = float(np.max(np.abs(d["cost"].cpu().numpy() - C) / (np.abs(C) + np.sqrt(np.mean(C * C)))))
     e_J = rel_err(J, J_ref)
-    e_g, e_ge = grad_errors(g, g_ref)
+    e_g, e_ge = grad_errors(g, g_ref, s_ref)
     say(f"   errors: z {e_z:.2e} lam {e_l:.2e} C {e_c:.2e} J {e_J:.2e} g {e_g:.2e} "
         f"(per entry {e_ge:.2e})")
     assert e_z <= tol["path"] and e_l <= tol["path"] and e_c <= tol["path"]
@@ -279,8 +283,9 @@ def test_fb_surrogate_large_m(dev, precision):
     eng = B.FbEngine(p, M=M, seed=17, precision=precision, device=dev, mode="surrogate")
     J, g = eng.cost_grad(mu, it=2)
     J_ref, g_ref = ref.fb_cost_grad_surrogate(p, M, 17, 2, mu)
+    s_ref = ref.fb_grad_scale(p, M, 17, 2, mu, surrogate=True)
     assert rel_err(float(J), J_ref) <= TOL[precision]["J"]
-    assert_grad(g.cpu().numpy(), g_ref, TOL[precision]["g"])
+    assert_grad(g.cpu().numpy(), g_ref, s_ref, TOL[precision]["g"])
 
 
 def test_fb_surrogate_optimize_matches_oracle(dev):

@@ -33,7 +33,7 @@ def dev():
     return gpu_device()
 
 
-def check_against_golden(p, J, g, gd, g_ref, tol):
+def check_against_golden(p, J, g, gd, g_ref, s_ref, tol):
     assert rel_err(J, gd["J"]) <= tol["J"], (J, gd["J"])
     gn = np.sqrt(p.dt * np.sum(g * g))
     assert rel_err(gn, gd["gnorm_L2"]) <= tol["g"]
@@ -44,7 +44,7 @@ def check_against_golden(p, J, g, gd, g_ref, tol):
     for i, v in zip(gd["sample_index"], gd["sample_g"]):
         assert flat[i] == pytest.approx(v, rel=0, abs=tol["g"] * gd["gnorm_L2"])
     assert g_ref.shape == (p.N, p.d)
-    en, ee = assert_grad(g, g_ref, tol["g"])
+    en, ee = assert_grad(g, g_ref, s_ref, tol["g"])
     say(f"   g vs oracle: normwise {en:.2e}, per entry {ee:.2e}")
 
 
@@ -56,7 +56,8 @@ def test_full_size(dev, name):
     M = w.M
     K = w.K or 64
     gd = golden(name)
-    g_ref = golden_g(name).reshape(p.N, p.d)
+    g_ref, s_ref = golden_g(name)
+    g_ref, s_ref = g_ref.reshape(p.N, p.d), s_ref.reshape(p.N, p.d)
     assert gd["M"] == M and gd["N"] == p.N
     u = np.zeros((p.N, p.d))
     tol = TOL["fp32"]
@@ -65,7 +66,7 @@ def test_full_size(dev, name):
     J, g = e.cost_grad(u, it=0)
     J, g = float(J), g.cpu().numpy()
     assert e.check_finite()
-    check_against_golden(p, J, g, gd, g_ref, tol)
+    check_against_golden(p, J, g, gd, g_ref, s_ref, tol)
     # per-path parity on the first and last 4096 paths
     for m0 in (0, M - 4096):
         say(name, "per-path dump", m0)
@@ -89,7 +90,7 @@ def test_full_size(dev, name):
     e64 = B.Engine(p, M=M, seed=w.seed, precision="fp64", mode="store", device=dev)
     J64, g64 = e64.cost_grad(u, it=0)
     J64, g64 = float(J64), g64.cpu().numpy()
-    check_against_golden(p, J64, g64, gd, g_ref, TOL["fp64"])
+    check_against_golden(p, J64, g64, gd, g_ref, s_ref, TOL["fp64"])
     assert rel_err(J, J64) <= tol["J"] and norm_err(g, g64) <= tol["g"]
     say(f"   {name}: J32 {J:.12f} J64 {J64:.12f} oracle {gd['J']:.12f}; "
         f"g32 rel {norm_err(g, g64):.2e}")

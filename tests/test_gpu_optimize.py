@@ -42,10 +42,11 @@ def _replay(dev, p, M, seed, precision, iters, mode="store", K=0, zeta0=1.0, c=1
         lg = lg[0]
         ub = u_before.cpu().numpy()
         J_ref, g_ref = ref.cost_grad(p, M, seed, n, ub)
+        s_ref = ref.grad_scale(p, M, seed, n, ub)
         Jg, gg = eng.cost_grad(u_before, it=n)
         assert rel_err(lg["J"], J_ref) <= tol["J"]
         assert rel_err(float(Jg), J_ref) <= tol["J"]
-        assert_grad(gg.cpu().numpy(), g_ref, tol["g"], f"iteration {n}")
+        assert_grad(gg.cpu().numpy(), g_ref, s_ref, tol["g"], f"iteration {n}")
         gn_ref = np.sqrt(p.dt * np.sum(g_ref * g_ref))
         assert rel_err(lg["gnorm"], gn_ref) <= tol["g"]
         # Armijo on the same draws, and the step is -zeta g

@@ -75,6 +75,7 @@ def test_ring_cost_grad_and_paths(dev, name, precision):
     it = 2
     z, lam, _, n, C = ref.fb_paths(p, seed, it, 0, M, mu)
     J_ref, g_ref = ref.fb_cost_grad(p, M, seed, it, mu)
+    s_ref = ref.fb_grad_scale(p, M, seed, it, mu)
     assert n.sum() > 0
     eng = B.FbEngine(p, M=M, seed=seed, precision=precision, device=dev)
     dp, d = eng.path_dump(0, P)
@@ -91,7 +92,7 @@ def test_ring_cost_grad_and_paths(dev, name, precision):
     e_l = per_path_error(lg[:, 1:], lam[:, 1:])
     e_c = float(np.max(np.abs(d["cost"].cpu().numpy() - C) / (np.abs(C) + np.sqrt(np.mean(C * C)))))
     e_J, e_J2 = rel_err(float(J), J_ref), rel_err(float(Jc), J_ref)
-    e_g, e_ge = grad_errors(gc.cpu().numpy(), g_ref)
+    e_g, e_ge = grad_errors(gc.cpu().numpy(), g_ref, s_ref)
     say(f"   per-entry g error {e_ge:.2e}")
     say(f"   errors: z {e_z:.2e} lam {e_l:.2e} C {e_c:.2e} J {e_J:.2e} g {e_g:.2e}")
     assert e_z <= tol["path"]
@@ -199,7 +200,7 @@ def test_ring_full_size_ring2(dev):
     flat = g.reshape(-1)
     for i, v in zip(gd["sample_index"], gd["sample_g"]):
         assert abs(flat[i] - v) <= tol["g"] * gd["gnorm_L2"]
-    en, ee = assert_grad(g, golden_g("ring2"), tol["g"])
+    en, ee = assert_grad(g, *golden_g("ring2"), tol["g"])
     say(f"   g vs oracle: normwise {en:.2e}, per entry {ee:.2e}")
     for r0 in (0, w.M - 2):
         cnt = 2 * p.np

@@ -314,3 +314,21 @@ def test_surrogate_one_step_definition():
         gn = p.gamma ** n[m, 0]
         want += p.alpha * u[m, 0] * phi(z[m, 0]) + gn * p.dt * dJv * phi(zs0)
     np.testing.assert_allclose(gs[0], want / M, rtol=1e-12, atol=1e-15)
+
+
+def test_gradient_scale_diagnostic_fb():
+    """The feedback model's per-entry summand scale: never below |g| (fixed
+    grid, jump-adapted grid, surrogate), and equal to |g| for one particle."""
+    p = wl.feedback_problem(N=12, T=1.2, zd=np.zeros((13, 2)), alpha=0.2)
+    mu = wl.random_feedback_control(p, 4, 0.5)
+    for kw in (dict(), dict(grid="adapted")):
+        q = wl.feedback_problem(N=12, T=1.2, zd=np.zeros((13, 2)), alpha=0.2, **kw)
+        _, g = ref.fb_cost_grad(q, 2000, 1, 0, mu)
+        s = ref.fb_grad_scale(q, 2000, 1, 0, mu)
+        assert np.all(s >= np.abs(g) * (1 - 1e-14))
+        _, g1 = ref.fb_cost_grad(q, 1, 1, 0, mu)
+        np.testing.assert_allclose(ref.fb_grad_scale(q, 1, 1, 0, mu), np.abs(g1), rtol=1e-13,
+                                   atol=1e-300)
+    _, gs = ref.fb_cost_grad_surrogate(p, 2000, 1, 0, mu)
+    ss = ref.fb_grad_scale(p, 2000, 1, 0, mu, surrogate=True)
+    assert np.all(ss >= np.abs(gs) * (1 - 1e-14))

@@ -218,3 +218,30 @@ def test_optimizer_resume_is_bitwise(oracle_lib):
     b2, lb2, _ = ref.optimize(p, 1500, seed=2, it0=3, u0=b1, n_max=3)
     assert np.array_equal(a, b2)
     assert np.array_equal(la["J"], np.concatenate([lb1["J"], lb2["J"]]))
+
+
+def test_gradient_scale_diagnostic():
+    """The per-entry summand scale (a test diagnostic of the oracle, the
+    denominator of the GPU tests' entry-by-entry gradient check): never below
+    |g|, and for one path it is nu |u| + |B^T lam|, i.e. nu |u| + |g - nu u|."""
+    p = wl.general_problem(3, 40, seed=5, cubic=0.1, lam=4.0)
+    u = wl.random_control(p, 1, 0.3)
+    J, g = ref.cost_grad(p, 3000, 3, 2, u)
+    s = ref.grad_scale(p, 3000, 3, 2, u)
+    assert np.all(s >= np.abs(g) * (1 - 1e-14))
+    assert np.any(s > 1.5 * np.abs(g))  # some entries' summands cancel
+    _, g1 = ref.cost_grad(p, 1, 3, 2, u)
+    s1 = ref.grad_scale(p, 1, 3, 2, u)
+    np.testing.assert_allclose(s1, p.nu * np.abs(u) + np.abs(g1 - p.nu * u), rtol=1e-13, atol=1e-15)
+
+
+def test_overflowing_trial_backtracks():
+    """A first Armijo trial whose cubic drift overflows (J not finite) is
+    rejected like any other, and the line search backtracks to a finite step
+    (eq. Stochastic_Armijo: the sufficient-decrease test fails)."""
+    w = wl.scaled(wl.config("c4"), M=300, N=100)
+    p = w.problem
+    J, _ = ref.cost_grad(p, w.M, w.seed, 0, 1e4 * np.ones((p.N, p.d)), grad=False)
+    assert not np.isfinite(J)
+    _, lo, n = ref.optimize(p, w.M, w.seed, 0, u0=np.zeros((p.N, p.d)), n_max=1, zeta0=1e5)
+    assert n == 1 and lo["backtracks"][0] > 5 and np.isfinite(lo["J"][0])

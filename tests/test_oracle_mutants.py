@@ -99,8 +99,8 @@ FB_MUTANTS = {
     "fb_gradient_control_term_dropped": ("double wk = pb->alpha * u + gn * lv;", "double wk = gn * lv;"),
     "fb_track_grad_sign": ("gz[0] = rx / s2 * e;", "gz[0] = -rx / s2 * e;"),
     "fb_armijo_sign": ("if (Jt <= J - c_armijo * zeta * gg)", "if (Jt <= J + c_armijo * zeta * gg)"),
-    "fb_surr_no_jump_factor": ("G[(size_t)k * L + i * pb->nv + l] += w->px[i] * w->pv[l] * (gn * lv);",
-                               "G[(size_t)k * L + i * pb->nv + l] += w->px[i] * w->pv[l] * lv;"),
+    "fb_surr_no_jump_factor": ("G[(size_t)k * L + i * pb->nv + l] += summand(w, w->px[i] * w->pv[l] * (gn * lv));",
+                               "G[(size_t)k * L + i * pb->nv + l] += summand(w, w->px[i] * w->pv[l] * lv);"),
     "fb_surr_var_no_sqrt": ("z[0] = pb->zd[2 * k] + sqrt(pb->svar0[0] + pb->svar1[0] * t) * R * cos(th);",
                             "z[0] = pb->zd[2 * k] + (pb->svar0[0] + pb->svar1[0] * t) * R * cos(th);"),
     "fb_surr_fresh_sample_per_step": ("uint32_t ctr[4] = {m, FB_SURR_WORD, iter, 1u};",
