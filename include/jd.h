@@ -214,6 +214,24 @@ int jd_optimize(const jd_problem* prob, const jd_run* run, const jd_opt* opt, do
                 jd_iter_log* log, int32_t* iters_done, void* traj, void* ws,
                 size_t ws_bytes, hipStream_t stream);
 
+/* jd_cost_grad without a caller workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops that forbid
+ * allocation): the workspace comes from a static device array of
+ * jd_noalloc_capacity() bytes (64 MiB) that the library holds on every GPU it
+ * runs on until the process ends.  The caller passes u, J, grad and traj as
+ * for jd_cost_grad (traj: jd_traj_bytes()); results are bitwise those of
+ * jd_cost_grad.  Returns JD_EWORKSPACE, before touching the device, when the
+ * problem's workspace (jd_workspace_bytes() less 256 bytes of alignment
+ * slack) exceeds the capacity: the 1-D workloads up to 2^20 paths x 1000 steps
+ * fit.  The call allocates nothing (the first call on a device looks up the
+ * array's device address once).  All calls on one GPU share the array: calls
+ * that overlap in time on one device (different streams, or host threads)
+ * race on it and must be ordered by the caller; the array keeps the last
+ * call's contents, and every call initialises what it reads. */
+size_t jd_noalloc_capacity(void);
+int jd_cost_grad_noalloc(const jd_problem* prob, const jd_run* run, const double* u, double* J,
+                         double* grad, void* traj, hipStream_t stream);
+
 /* Reads the non-finite flag of the most recent entry-point call on this
  * workspace (each call clears it first; its reductions raise it when J or g is
  * not finite), then clears it.  Synchronizes `stream`.  Returns JD_OK or

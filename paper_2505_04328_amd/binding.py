@@ -23,7 +23,7 @@ JD_STORE, JD_RECOMPUTE, JD_SURROGATE = 0, 1, 2
 
 EXPORTED = ["jd_version", "jd_strerror", "jd_workspace_bytes", "jd_traj_bytes", "jd_forward",
             "jd_adjoint", "jd_cost_grad", "jd_optimize", "jd_check_finite", "jd_draws",
-            "jd_philox", "jd_poisson_thresholds"]
+            "jd_philox", "jd_poisson_thresholds", "jd_noalloc_capacity", "jd_cost_grad_noalloc"]
 # include/jd_feedback.h
 EXPORTED_FB = ["jd_fb_workspace_bytes", "jd_fb_traj_bytes", "jd_fb_forward", "jd_fb_adjoint",
                "jd_fb_cost_grad", "jd_fb_optimize", "jd_fb_draws"]
@@ -90,9 +90,13 @@ def lib():
         L.jd_draws.argtypes = [P, P, C.c_int64, C.c_int64, C.c_int32, C.c_int32, P, P, P, P]
         L.jd_philox.argtypes = [C.c_uint64, P, C.c_int64, P, P]
         L.jd_poisson_thresholds.argtypes = [C.c_double, P]
+        L.jd_noalloc_capacity.argtypes = []
+        L.jd_cost_grad_noalloc.argtypes = [P, P, P, P, P, P, P]
         for name in EXPORTED:
-            if name not in ("jd_version", "jd_strerror", "jd_workspace_bytes", "jd_traj_bytes"):
+            if name not in ("jd_version", "jd_strerror", "jd_workspace_bytes", "jd_traj_bytes",
+                            "jd_noalloc_capacity"):
                 getattr(L, name).restype = C.c_int
+        L.jd_noalloc_capacity.restype = C.c_size_t
         L.jd_fb_workspace_bytes.argtypes = [P, P]
         L.jd_fb_workspace_bytes.restype = C.c_size_t
         L.jd_fb_traj_bytes.argtypes = [P, P]

@@ -9,7 +9,8 @@ import time
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libjd.so")
-SOURCES = ["jd_kernels.hip", "fb_kernels.hip", "jd_api.cpp", "jd_feedback.cpp", "jd_server.cpp"]
+SOURCES = ["jd_kernels.hip", "fb_kernels.hip", "jd_api.cpp", "jd_feedback.cpp", "jd_server.cpp",
+           "jd_noalloc.cpp"]
 HEADERS = ["jd_device.hpp", "jd_launch.hpp", "jd_host.hpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
