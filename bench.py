@@ -68,6 +68,22 @@ ADJ_SLOTS_PER_PATH_STEP = 12
 #          Philox 77 + Poisson 4                                          = 637)
 # plus, on the matrix cores, 2 nx nv = 200 flops per particle-step for the
 # gradient's outer products.
+# d = 8 (c3, c4; FP32 paths), algorithmic slots per path-step:
+# forward  four Philox blocks 308, eight Box-Muller cosine halves 176, the
+#          8 x 8 drift product and per-component Euler terms 104, Poisson 4,
+#          running cost 20                                                = 612
+# adjoint  per component: X - x_d (1), the A^T lam row (8), the cubic term
+#          (3), the dt update (1) = 13, times 8 = 104; the FP64 step
+#          reduction, per component a convert and an FP64 add (2 + 2)      =  32
+#                                                                         = 136
+# The checkpoint-recompute adjoint regenerates each step once more without
+# its cost: 612 - 20 = 592 more.  HBM: the stored trajectory costs 4 d = 32 B
+# per path-step written and read back.
+FWD8_SLOTS = 612
+ADJ8_SLOTS = 136
+REGEN8_SLOTS = FWD8_SLOTS - 20
+# d = 1 (c2): the recompute adjoint's regenerated step without the cost (6)
+REGEN1_SLOTS = FWD_SLOTS_PER_PATH_STEP - 6
 FB_FWD_SLOTS = 482
 FB_ADJ_SLOTS = 556
 # Coupled rings (Section 6.4, ring2: 512 rings of 2000 particles, 500 steps):
@@ -109,14 +125,20 @@ def parse():
     ap.add_argument("--ring-sample-rings", type=int, default=16)
     ap.add_argument("--no-adapted", action="store_true",
                     help="skip the jump-adapted grid section (Section 3)")
-    ap.add_argument("--cpu-sample-paths", type=int, default=1 << 19)
-    ap.add_argument("--only", choices=["all", "fp32_store", "kernels", "fb-kernels"], default="all",
-                    help="kernels: time jd_forward / jd_adjoint only; fb-kernels: run the f4 "
-                         "FP32 gradient only (for profiler runs)")
+    ap.add_argument("--cpu-sample-paths", type=int, default=1 << 20)
+    ap.add_argument("--only", choices=["all", "fp32_store", "kernels", "d8-kernels", "fb-kernels"],
+                    default="all",
+                    help="kernels: c2's jd_cost_grad, jd_forward and jd_adjoint only; d8-kernels: "
+                         "c3's FP32 stored and K = 64 recompute forward and adjoint only; "
+                         "fb-kernels: the f4 FP32 gradient only (for profiler runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")
     ap.add_argument("--serving", action="store_true",
                     help="instead: the request-server mix (Poisson arrivals, d in {1,2,4,8})")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the per-configuration section (c1, c2 iterations, c3, c4)")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the request-server mix in the default run")
     ap.add_argument("--serving-requests", type=int, default=256)
     ap.add_argument("--serving-m-hi", type=int, default=1 << 20)
     ap.add_argument("--serving-n-hi", type=int, default=2000)
@@ -126,41 +148,16 @@ def parse():
 
 
 def serving_main(args):
-    """Request mix: Poisson arrivals at 50/s, d in {1,2,4,8}, M uniform in
+    """Request mix alone: Poisson arrivals at 50/s, d in {1,2,4,8}, M uniform in
     [2^14, M_hi], N uniform in [100, N_hi], rate in [0, 10], 30 iterations each,
     served by the request server from one device arena (admission by footprint,
     stored trajectory when it takes at most 1/16 of the arena, else checkpoint
     recompute)."""
-    import torch
-    from paper_2505_04328_amd import serving as S
-    from paper_2505_04328_amd import workloads as wl
-    reqs = wl.serving_requests(count=args.serving_requests, rate=50.0, seed=11,
-                               M_hi=args.serving_m_hi, N_hi=args.serving_n_hi,
-                               iters=args.serving_iters)
-    arena = int(args.arena_gb * (1 << 30))
-    srv = S.Server(arena, max_active=32, n_streams=4)
-    t_last = [time.perf_counter()]
-
-    def on_done(rec):
-        if time.perf_counter() - t_last[0] > 5:
-            log(f"  request {rec.rid} done, latency {rec.latency:.2f} s")
-            t_last[0] = time.perf_counter()
-
-    log(f"serving {len(reqs)} requests, arena {args.arena_gb} GB")
-    recs, wall = S.run_mix(srv, reqs, precision="fp32", store_limit=arena // 16, on_done=on_done)
-    srv.close()
-    lat = np.array([r.latency for r in recs])
-    ps = sum(r.path_steps for r in recs)
-    sw = sum(r.swept for r in recs)
+    sv = serving_section(args)
     line = {
         "metric": "serving: request latency p50/p99 and aggregate forward+adjoint path-steps/s",
-        "value": ps / wall, "unit": "path-steps/s", "n_gpus": 1, "higher_is_better": True,
-        "requests": len(recs), "wall_s": wall, "latency_p50_s": float(np.percentile(lat, 50)),
-        "latency_p99_s": float(np.percentile(lat, 99)), "swept_path_steps_per_s": sw / wall,
-        "failed": int(sum(r.status != 0 for r in recs)),
-        "config": {"workload": f"c5 mix: {len(recs)} requests, Poisson 50/s, d in {{1,2,4,8}}, "
-                               f"M in [2^14, {args.serving_m_hi}], N in [100, {args.serving_n_hi}], "
-                               f"lambda in [0,10], {args.serving_iters} iterations, FP32 paths"},
+        "value": sv["gradient_path_steps_per_s"], "unit": "path-steps/s", "n_gpus": 1,
+        "higher_is_better": True, "config": {"workload": sv["workload"]}, "serving": sv,
     }
     print(json.dumps(line), flush=True)
 
@@ -193,6 +190,170 @@ def profiled_traffic(kernel: str):
 
 def percentile(xs, q):
     return float(np.percentile(np.asarray(xs), q))
+
+
+def composite_roofline(phases, units, seconds):
+    """The composite roofline of a sequence of kernels: each phase (slots,
+    bytes) per unit bounded by the larger of its VALU time and its HBM time,
+    summed; frac = that time over the measured one."""
+    t_roof = sum(max(sl * units / VALU_PEAK_SLOTS, by * units / HBM_PEAK) for sl, by in phases)
+    return {"t_roof_ms": t_roof * 1e3, "t_ms": seconds * 1e3, "frac": t_roof / seconds,
+            "phases_slots_bytes_per_unit": [list(ph) for ph in phases]}
+
+
+def configs_section(args, time_calls, dev):
+    """Every benchmark configuration: c1 (20 FP64 gradient iterations), c2 (50
+    iterations, stored vs checkpoint-recompute K = 32), c3 (d = 8; stored and
+    K = 64, FP32 and FP64), c4 (the K = 64 forward + backward step of the
+    autograd function J(u)), each against its composite roofline."""
+    import torch
+    from paper_2505_04328_amd import binding as B
+    from paper_2505_04328_amd import workloads as wl
+    from paper_2505_04328_amd.autograd import jd_cost
+    out = {}
+
+    def sync_wall(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, r
+
+    # c1: 10^4 paths x 100 steps, FP64, 20 iterations from u = 0
+    w = wl.config("c1")
+    p = w.problem
+    e = B.Engine(p, M=w.M, seed=w.seed, precision="fp64", device=dev)
+    e.optimize(torch.zeros((p.N, 1), dtype=torch.float64, device=dev), n_max=2)  # warm
+    walls = []
+    for _ in range(3):
+        u = torch.zeros((p.N, 1), dtype=torch.float64, device=dev)
+        wall, (_, logs) = sync_wall(lambda: e.optimize(u, n_max=w.iters))
+        walls.append(wall)
+    trials = sum(1 + l["backtracks"] for l in logs)
+    out["c1"] = {"form": "FP64, 20 gradient iterations (jd_optimize, line search on the device)",
+                 "wall_s_best_of_3": min(walls), "ms_per_iteration": min(walls) / w.iters * 1e3,
+                 "iterations": len(logs), "trials": trials, "J_first": logs[0]["J"],
+                 "J_last_new": logs[-1]["J_new"],
+                 "note": "10^4 paths = 40 blocks of 256: launch- and latency-bound, no roofline"}
+    log(f"c1: {min(walls) * 1e3:.2f} ms for {w.iters} iterations")
+    del e
+
+    # c2: 50 iterations, stored and K = 32 (bitwise the same iterates)
+    w = wl.config("c2")
+    p = w.problem
+    res = {}
+    finals = {}
+    for mode, K in (("store", 0), ("recompute", w.K)):
+        e = B.Engine(p, M=w.M, seed=w.seed, precision="fp32", mode=mode, K=K, device=dev)
+        e.optimize(torch.zeros((p.N, 1), dtype=torch.float64, device=dev), n_max=1)  # warm
+        u = torch.zeros((p.N, 1), dtype=torch.float64, device=dev)
+        wall, (_, logs) = sync_wall(lambda: e.optimize(u, n_max=w.iters))
+        trials = sum(1 + l["backtracks"] for l in logs)
+        finals[mode] = u.cpu().numpy()
+        # swept path-steps: each iteration's forward + adjoint and every trial's forward
+        res[f"{mode}{'_K' + str(K) if K else ''}"] = {
+            "wall_s": wall, "iterations": len(logs), "trials": trials,
+            "ms_per_iteration": wall / len(logs) * 1e3,
+            "gradient_path_steps_per_s": len(logs) * w.M * p.N / wall,
+            "J_first": logs[0]["J"], "J_last_new": logs[-1]["J_new"]}
+        log(f"c2 {mode}: 50 iterations in {wall:.3f} s ({trials} trials)")
+        del e
+        torch.cuda.empty_cache()
+    res["final_u_bitwise_equal"] = bool(np.array_equal(finals["store"], finals["recompute"]))
+    out["c2_iterations"] = res
+
+    # c3 (and c4's stored/FP64 forms): jd_cost_grad per call
+    for name in ("c3", "c4"):
+        w = wl.config(name)
+        p = w.problem
+        MN = w.M * p.N
+        u = torch.zeros((p.N, p.d), dtype=torch.float64, device=dev)
+        res = {}
+        for prec, mode, K in (("fp32", "store", 0), ("fp32", "recompute", 64), ("fp64", "store", 0),
+                              ("fp64", "recompute", 64)):
+            e = B.Engine(p, M=w.M, seed=w.seed, precision=prec, mode=mode, K=K, device=dev)
+            e.cost_grad(u, it=1)
+            reps = 10 if prec == "fp32" else 4
+            t = time_calls(lambda: e.cost_grad(u, it=1), reps)
+            tf = time_calls(lambda: e.forward(u, it=1), reps)
+            ta = time_calls(lambda: e.adjoint(u, it=1), reps)
+            key = f"{prec}_{mode}{'_K' + str(K) if K else ''}"
+            rec = {"p50_ms": percentile(t, 50), "p99_ms": percentile(t, 99),
+                   "forward_ms": percentile(tf, 50), "adjoint_ms": percentile(ta, 50),
+                   "path_steps_per_s": MN / (percentile(t, 50) * 1e-3)}
+            if prec == "fp32":
+                if mode == "store":
+                    ph = [(FWD8_SLOTS, 32), (ADJ8_SLOTS, 32)]
+                else:
+                    ph = [(FWD8_SLOTS, 32.0 / K), (REGEN8_SLOTS + ADJ8_SLOTS, 32.0 / K)]
+                rec["roofline"] = composite_roofline(ph, MN, percentile(t, 50) * 1e-3)
+            res[key] = rec
+            log(f"{name} {key}: {rec['p50_ms']:.2f} ms")
+            del e
+            torch.cuda.empty_cache()
+        res["speedup_fp32_over_fp64_store"] = res["fp64_store"]["p50_ms"] / res["fp32_store"]["p50_ms"]
+        out[name] = res
+
+    # c4: the autograd step J(u).backward() with checkpoints every 64 steps
+    w = wl.config("c4")
+    p = w.problem
+    e = B.Engine(p, M=w.M, seed=w.seed, precision="fp32", mode="recompute", K=w.K, device=dev)
+    u0 = torch.tensor(wl.random_control(p, 3, 0.3), dtype=torch.float64, device=dev)
+
+    def step():
+        u = u0.clone().requires_grad_(True)
+        J = jd_cost(u, e, 0)
+        J.backward()
+        return u.grad
+
+    step()
+    t = time_calls(step, 10)
+    MN = w.M * p.N
+    out["c4_autograd_step"] = {
+        "form": "FP32 paths, checkpoints every 64 steps: jd_forward + jd_adjoint (recompute)",
+        "p50_ms": percentile(t, 50), "p99_ms": percentile(t, 99),
+        "path_steps_per_s": MN / (percentile(t, 50) * 1e-3),
+        "roofline": composite_roofline([(FWD8_SLOTS, 32.0 / w.K),
+                                        (REGEN8_SLOTS + ADJ8_SLOTS, 32.0 / w.K)], MN,
+                                       percentile(t, 50) * 1e-3)}
+    log(f"c4 autograd step: {percentile(t, 50):.2f} ms")
+    del e
+    torch.cuda.empty_cache()
+    return out
+
+
+def serving_section(args):
+    """The request mix (see serving_main) as a dict."""
+    from paper_2505_04328_amd import serving as S
+    from paper_2505_04328_amd import workloads as wl
+    reqs = wl.serving_requests(count=args.serving_requests, rate=50.0, seed=11,
+                               M_hi=args.serving_m_hi, N_hi=args.serving_n_hi,
+                               iters=args.serving_iters)
+    arena = int(args.arena_gb * (1 << 30))
+    srv = S.Server(arena, max_active=32, n_streams=4)
+    t_last = [time.perf_counter()]
+
+    def on_done(rec):
+        if time.perf_counter() - t_last[0] > 5:
+            log(f"  request {rec.rid} done, latency {rec.latency:.2f} s")
+            t_last[0] = time.perf_counter()
+
+    log(f"serving {len(reqs)} requests, arena {args.arena_gb} GB")
+    recs, wall = S.run_mix(srv, reqs, precision="fp32", store_limit=arena // 16, on_done=on_done)
+    srv.close()
+    lat = np.array([r.latency for r in recs])
+    ps = sum(r.path_steps for r in recs)
+    sw = sum(r.swept for r in recs)
+    return {
+        "requests": len(recs), "wall_s": wall, "latency_p50_s": float(np.percentile(lat, 50)),
+        "latency_p99_s": float(np.percentile(lat, 99)),
+        "gradient_path_steps_per_s": ps / wall, "swept_path_steps_per_s": sw / wall,
+        "failed": int(sum(r.status != 0 for r in recs)),
+        "peak_admitted": srv.stats["max_active"], "peak_queued": srv.stats["max_queued"],
+        "workload": f"c5 mix: {len(recs)} requests, Poisson 50/s, d in {{1,2,4,8}}, "
+                    f"M in [2^14, {args.serving_m_hi}], N in [100, {args.serving_n_hi}], "
+                    f"lambda in [0,10], {args.serving_iters} iterations, FP32 paths, arena "
+                    f"{args.arena_gb} GB, 32 slots over 4 streams"}
 
 
 def feedback_section(args, time_calls, dev):
@@ -475,6 +636,23 @@ def main():
         log("feedback-model kernel loop done")
         print(json.dumps({"fb_kernels_only": True, "calls": args.warmup + args.steps}))
         return
+    if args.only == "d8-kernels":
+        # the d = 8 sweeps at c3, FP32: stored forward and adjoint, then the
+        # checkpoint forward and the recompute adjoint (K = 64), for counter runs
+        w3 = wl.config("c3")
+        u3 = torch.zeros((w3.problem.N, w3.problem.d), dtype=torch.float64, device=dev)
+        for mode, K in (("store", 0), ("recompute", 64)):
+            e = B.Engine(w3.problem, M=w3.M, seed=w3.seed, precision="fp32", mode=mode, K=K,
+                         device=dev)
+            for it in range(args.warmup + args.steps):
+                e.forward(u3, it=it)
+                e.adjoint(u3, it=it)
+            torch.cuda.synchronize()
+            del e
+            torch.cuda.empty_cache()
+        log("d = 8 kernel loop done")
+        print(json.dumps({"d8_kernels_only": True, "calls": args.warmup + args.steps}))
+        return
     w = wl.config("c2")
     p = w.problem
     M, N = w.M, p.N
@@ -609,13 +787,16 @@ def main():
         from oracle import ref
         Ms = args.cpu_sample_paths
         nth = ref.default_threads()
-        log(f"oracle: {Ms} paths x {N} steps on {nth} threads")
-        t0 = time.perf_counter()
-        Jo, go = ref.cost_grad(p, Ms, w.seed, 0, np.zeros((N, p.d)), nthreads=nth)
-        tc = time.perf_counter() - t0
+        log(f"oracle: {Ms} paths x {N} steps on {nth} threads, best of 3")
+        tcs = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            Jo, go = ref.cost_grad(p, Ms, w.seed, 0, np.zeros((N, p.d)), nthreads=nth)
+            tcs.append(time.perf_counter() - t0)
+        tc = min(tcs)
         cpu = {"value": Ms * N / tc, "unit": "path-steps/s", "cores": nth, "kind": "oracle",
                "sample": f"c2 with M={Ms} of {M} paths, all N={N} steps, forward+adjoint+reductions, "
-                         f"FP64, {tc:.1f} s wall"}
+                         f"FP64, best of 3 runs ({', '.join(f'{x:.1f}' for x in tcs)} s wall)"}
         sample_err = {}
         for prec in ("fp32", "fp64"):
             es = B.Engine(p, M=Ms, seed=w.seed, precision=prec, mode="store", device=dev)
@@ -638,6 +819,13 @@ def main():
     if not args.no_ring and args.only == "all":
         log("coupled rings (ring2)")
         rings = ring_section(args, time_calls, dev)
+    configs = None
+    if not args.no_configs and args.only == "all":
+        log("configurations c1, c2 iterations, c3, c4")
+        configs = configs_section(args, time_calls, dev)
+    serving = None
+    if not args.no_serving and args.only == "all":
+        serving = serving_section(args)
 
     fp32s = res["fp32_store_ms"]
     line = {
@@ -666,6 +854,8 @@ def main():
         "feedback": feedback,
         "rings": rings,
         "adapted": adapted,
+        "configs": configs,
+        "serving": serving,
     }
     print(json.dumps(line), flush=True)
 
