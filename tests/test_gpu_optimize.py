@@ -167,3 +167,56 @@ def test_tolerance_stops_on_the_device(dev):
     _, logs = eng.optimize(u, n_max=20, tol=tol)
     assert len(logs) == stop + 1
     assert logs == full[:stop + 1]
+
+
+@pytest.mark.timeout(900)
+def test_c2_fifty_iterations_full_size(dev):
+    """c2 at full size (2^20 paths x 1000 steps, FP32 paths): 50 gradient
+    iterations stored and with checkpoints every 32 steps give bitwise the same
+    iterates and logs; iterations 0, 1, 25 and 49 are replayed through the
+    oracle from the GPU's own iterate on the same counter word: J, g (normwise
+    and entry by entry), the accepted step and the backtrack count, and the
+    next iterate."""
+    import torch
+    from parity_util import per_entry_error
+    w = wl.config("c2")
+    p = w.problem
+    assert w.M == 1 << 20 and p.N == 1000 and w.iters == 50
+    tol = TOL["fp32"]
+    say("c2 full size, 50 iterations stored")
+    eng = B.Engine(p, M=w.M, seed=w.seed, precision="fp32", mode="store", device=dev)
+    replay = (0, 1, 25, 49)
+    u = torch.zeros((p.N, 1), dtype=torch.float64, device=dev)
+    snaps, logs = {}, []
+    for n in range(w.iters):
+        if n in replay or n - 1 in replay:
+            snaps[n] = u.cpu().numpy().copy()
+        _, lg = eng.optimize(u, n_max=1, it0=n)
+        logs += lg
+    snaps[w.iters] = u.cpu().numpy().copy()
+    say("c2 full size, 50 iterations with checkpoints every 32 steps, one call")
+    er = B.Engine(p, M=w.M, seed=w.seed, precision="fp32", mode="recompute", K=w.K, device=dev)
+    ur = torch.zeros((p.N, 1), dtype=torch.float64, device=dev)
+    _, logs_r = er.optimize(ur, n_max=w.iters)
+    assert torch.equal(u, ur), "stored and recomputed iterations differ"
+    assert logs_r == logs
+    del er
+    torch.cuda.empty_cache()
+    for n in replay:
+        ub = snaps[n]
+        say(f"   replay iteration {n} through the oracle")
+        J_ref, g_ref = ref.cost_grad(p, w.M, w.seed, n, ub)
+        s_ref = ref.grad_scale(p, w.M, w.seed, n, ub)
+        Jg, gg = eng.cost_grad(torch.tensor(ub, device=dev), it=n)
+        assert rel_err(logs[n]["J"], J_ref) <= tol["J"]
+        assert rel_err(float(Jg), J_ref) <= tol["J"]
+        en, ee = assert_grad(gg.cpu().numpy(), g_ref, s_ref, tol["g"], f"iteration {n}")
+        _, lo, _ = ref.optimize(p, w.M, w.seed, n, u0=ub, n_max=1)
+        assert lo["backtracks"][0] == logs[n]["backtracks"]
+        assert lo["zeta"][0] == logs[n]["zeta"]
+        # the GPU's next iterate against u_n - zeta g_ref, entry by entry
+        zeta = logs[n]["zeta"]
+        step_err = per_entry_error((ub - snaps[n + 1]) / zeta, g_ref, s_ref)
+        assert step_err <= tol["g"], step_err
+        say(f"   iteration {n}: J {logs[n]['J']:.10f} (oracle {J_ref:.10f}), g {en:.1e} / {ee:.1e}, "
+            f"zeta {zeta}, backtracks {logs[n]['backtracks']}")
