@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libjd.so")
 SOURCES = ["jd_kernels.hip", "fb_kernels.hip", "jd_api.cpp", "jd_feedback.cpp", "jd_server.cpp",
-           "jd_noalloc.cpp"]
+           "jd_noalloc.cpp", "jd_shapes.cpp"]
 HEADERS = ["jd_device.hpp", "jd_launch.hpp", "jd_host.hpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

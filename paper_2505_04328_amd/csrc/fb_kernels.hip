@@ -1567,16 +1567,6 @@ k_fb_draws(FbArgs<Real> a, PoissonTable pt, int64_t m0, int64_t mc, int k0, int 
 // ===========================================================================
 // Launchers.
 
-FbTable fb_table_layout(const FbHost& p) {
-    FbTable t;
-    auto up = [](size_t x) { return (x + 63) / 64 * 64; };
-    t.mu = 0;
-    t.zd = up((size_t)p.N * p.nx * p.nvp);
-    t.ks = t.zd + up((size_t)(p.N + 1) * 2);
-    t.count = t.ks + 64;
-    return t;
-}
-
 template <typename Real>
 static FbArgs<Real> fb_args(const FbHost& p, const HostRun& r) {
     FbArgs<Real> a;
@@ -1677,7 +1667,6 @@ hipError_t fb_launch_table(const FbHost& p, const HostRun& r, const double* mu, 
         }                                  \
     } while (0)
 
-int fb_ring_groups(int np) { return np <= kThreads ? 1 : 8; }
 
 // Rings of more than 256 particles take workgroups of 2048 slots (eight
 // 256-wide trajectory blocks) and are coupled through LDS every step, so one
@@ -1705,9 +1694,6 @@ constexpr int fb_ring_adj_threads() {
                                                             : 256;
 }
 
-int fb_forward_blocks(const FbHost& p, const HostRun& r) {
-    return p.np == 1 ? r.nblk : r.nblk / p.G;
-}
 
 template <typename Real>
 static hipError_t fb_forward_t(const FbHost& p, const HostRun& r, const void* tab, void* traj,
@@ -1751,22 +1737,6 @@ hipError_t fb_launch_forward(const FbHost& p, const HostRun& r, const void* tab,
                              double* cpart, const WsHeader* hdr, hipStream_t st, Gate gate) {
     return r.prec == JD_FP64 ? fb_forward_t<double>(p, r, tab, traj, cpart, hdr, st, gate)
                              : fb_forward_t<float>(p, r, tab, traj, cpart, hdr, st, gate);
-}
-
-// 256-particle groups per block of the independent-particle adjoint (and of
-// the surrogate's forward, which shares its partials).  Several groups per
-// block divide the per-step gradient partials but cost registers.  Measured on
-// 2^20 x 500: FP64 paths 31.1 / 28.9 ms for 1 / 2 groups (16.2 / 15.5 / 18.3 ms
-// for 1 / 2 / 4 on FP32 paths while these used the FP64 matrix cores); FP32
-// paths on the FP32 matrix cores with velocity transposes of the compiled row
-// width fit five waves per SIMD with one group: 10.8 ms against 11.3 ms for
-// two (four waves) and 11.0 ms for two forced to five waves (spills).  Rings
-// keep their own G (whole rings per block); the jump-adapted adjoint runs one
-// group.
-static int fb_adjoint_groups(const FbHost& p, const HostRun& r) {
-    if (p.np > 1)
-        return p.G;
-    return p.grid == 0 && r.prec == JD_FP64 && r.nblk >= 2048 ? 2 : 1;
 }
 
 template <typename Real>
@@ -1856,10 +1826,6 @@ hipError_t fb_launch_forward_grad(const FbHost& p, const HostRun& r, const void*
                              : fb_forward_grad_t<float>(p, r, tab, cpart, apart, hdr, st, gate);
 }
 
-int fb_partial_blocks(const FbHost& p, const HostRun& r) {
-    const int G = fb_adjoint_groups(p, r);
-    return (r.nblk + G - 1) / G;
-}
 
 hipError_t fb_launch_finalize_grad(const FbHost& p, const HostRun& r, const double* apart,
                                    double* g, WsHeader* hdr, hipStream_t st, Gate gate) {

@@ -54,6 +54,9 @@ hipError_t fb_launch_adjoint(const FbHost& p, const HostRun& r, const void* tab,
 hipError_t fb_launch_forward_grad(const FbHost& p, const HostRun& r, const void* tab, double* cpart,
                                   double* apart, const WsHeader* hdr, hipStream_t st,
                                   Gate gate = kNoGate);
+// 256-particle groups per block of the adjoint (and of the surrogate's
+// forward, which shares its partials).
+int fb_adjoint_groups(const FbHost& p, const HostRun& r);
 // Number of per-block partials of the adjoint / forward_grad kernels, and of
 // the per-block costs of the forward kernel.
 int fb_partial_blocks(const FbHost& p, const HostRun& r);

@@ -953,62 +953,6 @@ k_philox(uint32_t key0, uint32_t key1, const uint32_t* __restrict__ ctr, int64_t
 // ===========================================================================
 // Launchers.
 
-size_t real_size(int prec) { return prec == JD_FP64 ? sizeof(double) : sizeof(float); }
-
-// Register-buffer shape of the recomputing adjoint: R steps of D values plus
-// SMAX sub-segment starts; a checkpoint interval K is supported up to R * SMAX.
-template <typename Real, int D>
-struct RecomputeShape;
-template <> struct RecomputeShape<float, 1> { static constexpr int R = 32, S = 4; };
-template <> struct RecomputeShape<float, 2> { static constexpr int R = 16, S = 4; };
-template <> struct RecomputeShape<float, 4> { static constexpr int R = 8, S = 8; };
-template <> struct RecomputeShape<float, 8> { static constexpr int R = 8, S = 8; };
-template <> struct RecomputeShape<double, 1> { static constexpr int R = 16, S = 4; };
-template <> struct RecomputeShape<double, 2> { static constexpr int R = 8, S = 4; };
-template <> struct RecomputeShape<double, 4> { static constexpr int R = 4, S = 8; };
-template <> struct RecomputeShape<double, 8> { static constexpr int R = 4, S = 4; };
-
-template <typename Real, int D>
-static int max_K() { return RecomputeShape<Real, D>::R * RecomputeShape<Real, D>::S; }
-
-template <typename Real, int D>
-static int reg_R() { return RecomputeShape<Real, D>::R; }
-
-// Longest checkpoint interval of the register kernel, and the longest it
-// sweeps with one regeneration of each step (K <= R: one sub-segment).
-static int register_max_K(int prec, int D) {
-    if (prec == JD_FP64)
-        return D == 1 ? max_K<double, 1>() : D == 2 ? max_K<double, 2>()
-             : D == 4 ? max_K<double, 4>() : max_K<double, 8>();
-    return D == 1 ? max_K<float, 1>() : D == 2 ? max_K<float, 2>()
-         : D == 4 ? max_K<float, 4>() : max_K<float, 8>();
-}
-static int register_single_K(int prec, int D) {
-    if (prec == JD_FP64)
-        return D == 1 ? reg_R<double, 1>() : D == 2 ? reg_R<double, 2>()
-             : D == 4 ? reg_R<double, 4>() : reg_R<double, 8>();
-    return D == 1 ? reg_R<float, 1>() : D == 2 ? reg_R<float, 2>()
-         : D == 4 ? reg_R<float, 4>() : reg_R<float, 8>();
-}
-
-// The segment kernel (one regeneration, workspace scratch) where the register
-// kernel would regenerate every step twice at d = 8, and wherever K exceeds
-// the register kernel's buffers.  At d <= 4 a second regeneration costs less
-// than writing and reading back the states.
-bool recompute_uses_segments(int prec, int D, int K) {
-    return K > register_max_K(prec, D) || (D == 8 && K > register_single_K(prec, D));
-}
-
-size_t seg_scratch_bytes(const HostProblem& p, const HostRun& r) {
-    if (r.mode != JD_RECOMPUTE || !recompute_uses_segments(r.prec, p.D, r.K))
-        return 0;
-    return (size_t)seg_blocks(r) * (size_t)r.K * (size_t)p.d * kThreads * real_size(r.prec);
-}
-
-bool recompute_supported(const HostProblem& p, const HostRun& r) {
-    return r.K >= 1 && seg_scratch_bytes(p, r) <= kSegScratchMax;
-}
-
 template <typename Real, int D>
 static SweepArgs<Real, D> make_args(const HostProblem& p, const HostRun& r) {
     SweepArgs<Real, D> a;

@@ -106,6 +106,20 @@ enum FwdMode { FWD_COST = 0, FWD_STORE = 1, FWD_CKPT = 2 };
 
 size_t real_size(int prec);
 
+// Register-buffer shape of the recomputing adjoint's register kernel: R steps
+// of D values plus S sub-segment starts; it takes checkpoint intervals up to
+// R S, regenerating every step once for K <= R and twice beyond.
+template <typename Real, int D>
+struct RecomputeShape;
+template <> struct RecomputeShape<float, 1> { static constexpr int R = 32, S = 4; };
+template <> struct RecomputeShape<float, 2> { static constexpr int R = 16, S = 4; };
+template <> struct RecomputeShape<float, 4> { static constexpr int R = 8, S = 8; };
+template <> struct RecomputeShape<float, 8> { static constexpr int R = 8, S = 8; };
+template <> struct RecomputeShape<double, 1> { static constexpr int R = 16, S = 4; };
+template <> struct RecomputeShape<double, 2> { static constexpr int R = 8, S = 4; };
+template <> struct RecomputeShape<double, 4> { static constexpr int R = 4, S = 8; };
+template <> struct RecomputeShape<double, 8> { static constexpr int R = 4, S = 4; };
+
 // Checkpoint-recompute adjoint.  Short intervals run a kernel that rebuilds
 // each segment in registers; where that would regenerate every step twice
 // (d = 8) or the interval exceeds its buffers, a persistent kernel of

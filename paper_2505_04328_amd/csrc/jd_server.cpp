@@ -435,7 +435,7 @@ int jd_server_result(jd_server* S, int64_t ticket, double* u_host, jd_iter_log* 
     Request& q = *it->second;
     if (q.state != DONE)
         return JD_EAGAIN;
-    if (u_host)
+    if (u_host && !q.u_out.empty())  // a request that failed returns no control
         memcpy(u_host, q.u_out.data(), q.u_out.size() * sizeof(double));
     if (log && q.drv.copied > 0)
         memcpy(log, q.log.data(), (size_t)q.drv.copied * sizeof(jd_iter_log));
