@@ -149,6 +149,14 @@ void fb_adapted_draws(uint64_t seed, uint32_t m, uint32_t k, uint32_t iter, cons
     a[*n + 1] = 1.0;
 }
 
+/* Surrogate variance of component c at time t: the line svar0 + svar1 t, or 0
+ * where the line is negative (a fitted line may start below zero). */
+static double surr_var(const fb_problem* pb, int c, double t)
+{
+    double v = pb->svar0[c] + pb->svar1[c] * t;
+    return v > 0.0 ? v : 0.0;
+}
+
 /* Surrogate state (Section 6.5: one position and velocity sampled for each
  * particle and realization): zd_k + sqrt(var(t_k)) (R cos, R sin) with the
  * Box-Muller pair of words 0 and 1 of block (m, 0xFFFFFFFE, iter, 1), the same
@@ -163,8 +171,9 @@ void fb_surrogate_state(const fb_problem* pb, uint64_t seed, uint32_t m, uint32_
     double R = sqrt(-2.0 * log(or_uniform(W[0])));
     double th = FB_TWO_PI * or_uniform(W[1]);
     double t = (double)k * (pb->T / (double)pb->N);
-    z[0] = pb->zd[2 * k] + sqrt(pb->svar0[0] + pb->svar1[0] * t) * R * cos(th);
-    z[1] = pb->zd[2 * k + 1] + sqrt(pb->svar0[1] + pb->svar1[1] * t) * R * sin(th);
+    double vx = surr_var(pb, 0, t), vv = surr_var(pb, 1, t);
+    z[0] = pb->zd[2 * k] + sqrt(vx) * R * cos(th);
+    z[1] = pb->zd[2 * k + 1] + sqrt(vv) * R * sin(th);
 }
 
 static int check_problem(const fb_problem* pb)
@@ -185,8 +194,10 @@ static int check_problem(const fb_problem* pb)
         return -1;
     if (sqrt(pb->beta / FB_PI) * (pb->T / (double)pb->N) > 2.0)
         return -1;
+    if (pb->svar_kind != 0 && pb->svar_kind != 1)
+        return -1;
     for (int c = 0; c < 2; ++c)
-        if (!(pb->svar0[c] >= 0.0) || !(pb->svar1[c] >= 0.0))
+        if (!isfinite(pb->svar0[c]) || !isfinite(pb->svar1[c]))
             return -1;
     return 0;
 }
@@ -774,7 +785,7 @@ static int check_surrogate(const fb_problem* pb)
 int fb_paths_surrogate(const fb_problem* pb, uint64_t seed, uint32_t iter, int64_t m0, int64_t count,
                        const double* mu, double* lam, int nthreads)
 {
-    if (check_surrogate(pb) || !mu || !lam || m0 < 0 || count < 0)
+    if (check_surrogate(pb) || pb->svar_kind != 0 || !mu || !lam || m0 < 0 || count < 0)
         return -1;
     const int N = pb->N, L = pb->nx * pb->nv;
     uint64_t thr[32];
@@ -799,13 +810,127 @@ int fb_paths_surrogate(const fb_problem* pb, uint64_t seed, uint32_t iter, int64
     return rc;
 }
 
+/* Per-step sums over the particles, in chunks of FB_CHUNK consecutive
+ * particles (each chunk in particle order, the chunks in index order):
+ * pass 0 sums z_k,c, pass 1 sums (z_k,c - zbar[k,c])^2. */
+static int ensemble_sums(const fb_problem* pb, int64_t M, uint64_t seed, uint32_t iter,
+                         const double* mu, int pass, const double* zbar, double* out,
+                         int nthreads)
+{
+    const int N = pb->N;
+    const size_t nk = (size_t)(N + 1) * 2;
+    const int64_t nchunk = (M + FB_CHUNK - 1) / FB_CHUNK;
+    uint64_t thr[32];
+    or_poisson_thresholds(rate_dt(pb), thr);
+    double* part = (double*)calloc((size_t)nchunk * nk, sizeof(double));
+    if (!part)
+        return -2;
+    int rc = 0;
+#pragma omp parallel num_threads(nthreads > 0 ? nthreads : 1) reduction(| : rc)
+    {
+        work w;
+        const int ok = work_alloc(pb, &w) == 0;
+        rc |= ok ? 0 : 1;
+        {
+#pragma omp for schedule(dynamic, 1)
+            for (int64_t c = 0; c < nchunk; ++c) {
+                if (!ok)
+                    continue;
+                int64_t mb = c * FB_CHUNK, me = mb + FB_CHUNK < M ? mb + FB_CHUNK : M;
+                double* S = part + (size_t)c * nk;
+                for (int64_t m = mb; m < me; ++m) {
+                    path_forward(pb, thr, seed, iter, (uint32_t)m, mu, &w);
+                    for (size_t q = 0; q < nk; ++q) {
+                        double d = pass == 0 ? w.z[q] : w.z[q] - zbar[q];
+                        S[q] += pass == 0 ? d : d * d;
+                    }
+                }
+            }
+        }
+        work_free(&w);
+    }
+    if (!rc) {
+        for (size_t q = 0; q < nk; ++q) {
+            double t = 0.0;
+            for (int64_t c = 0; c < nchunk; ++c)
+                t += part[(size_t)c * nk + q];
+            out[q] = t;
+        }
+    }
+    free(part);
+    return rc ? -2 : 0;
+}
+
+/* The forward ensemble's variance per step and component (the population
+ * variance about the per-step mean, in two passes) and the ordinary
+ * least-squares line through the points (t_k, V_k,c), k = 0..N, equal weights:
+ * b = sum (t_k - tbar)(V_k - Vbar) / sum (t_k - tbar)^2, a = Vbar - b tbar.
+ * Section 6.5 asks for a surrogate variance that grows linearly in time and
+ * follows the forward model's own variance. */
+int fb_surrogate_fit(const fb_problem* pb, int64_t M, uint64_t seed, uint32_t iter,
+                     const double* mu, double* var, double a[2], double b[2], int nthreads)
+{
+    if (check_surrogate(pb) || M < 1 || !mu || !a || !b)
+        return -1;
+    const int N = pb->N;
+    const size_t nk = (size_t)(N + 1) * 2;
+    const double dt = pb->T / (double)N;
+    double* zbar = (double*)malloc(nk * sizeof(double));
+    double* V = (double*)malloc(nk * sizeof(double));
+    int rc = (zbar && V) ? 0 : -2;
+    if (!rc)
+        rc = ensemble_sums(pb, M, seed, iter, mu, 0, NULL, zbar, nthreads);
+    if (!rc) {
+        for (size_t q = 0; q < nk; ++q)
+            zbar[q] /= (double)M;
+        rc = ensemble_sums(pb, M, seed, iter, mu, 1, zbar, V, nthreads);
+    }
+    if (!rc) {
+        for (size_t q = 0; q < nk; ++q)
+            V[q] /= (double)M;
+        double tbar = 0.0;
+        for (int k = 0; k <= N; ++k)
+            tbar += (double)k * dt;
+        tbar /= (double)(N + 1);
+        for (int c = 0; c < 2; ++c) {
+            double vbar = 0.0;
+            for (int k = 0; k <= N; ++k)
+                vbar += V[2 * k + c];
+            vbar /= (double)(N + 1);
+            double sxy = 0.0, sxx = 0.0;
+            for (int k = 0; k <= N; ++k) {
+                double dtk = (double)k * dt - tbar;
+                sxy += dtk * (V[2 * k + c] - vbar);
+                sxx += dtk * dtk;
+            }
+            b[c] = sxy / sxx;
+            a[c] = vbar - b[c] * tbar;
+        }
+        if (var)
+            memcpy(var, V, nk * sizeof(double));
+    }
+    free(zbar);
+    free(V);
+    return rc;
+}
+
 /* Surrogate gradient (Section 6.5): the forward adds alpha u_k phi(z_k) as it
- * goes, the adjoint runs on the surrogate states; nothing is stored. */
-static int surrogate_impl(const fb_problem* pb, int64_t M, uint64_t seed, uint32_t iter,
+ * goes, the adjoint runs on the surrogate states; nothing is stored.  With
+ * svar_kind 1 the variance line is first fitted to the forward ensemble. */
+static int surrogate_impl(const fb_problem* pb_in, int64_t M, uint64_t seed, uint32_t iter,
                           const double* mu, double* J, double* g, int nthreads, int absval)
 {
-    if (check_surrogate(pb) || M < 1 || !mu || !J || !g)
+    if (check_surrogate(pb_in) || M < 1 || !mu || !J || !g)
         return -1;
+    fb_problem fitted = *pb_in;
+    if (pb_in->svar_kind == 1) {
+        int frc = fb_surrogate_fit(pb_in, M, seed, iter, mu, NULL, fitted.svar0, fitted.svar1,
+                                   nthreads);
+        if (frc)
+            return frc;
+        fitted.svar_kind = 0;
+    }
+    const fb_problem* pb = &fitted;
     const int N = pb->N, L = pb->nx * pb->nv;
     const size_t nl = (size_t)N * L;
     const int64_t nchunk = (M + FB_CHUNK - 1) / FB_CHUNK;

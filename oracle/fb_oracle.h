@@ -63,7 +63,12 @@
  * at every step, with the forward's jump counts; no trajectory is stored:
  *   gs_k[l] = (1/M) sum_m [ alpha u_k phi_l(z_k) + gamma^{n_k} ls^v_{k+1} phi_l(zs_k) ]
  * where ls is the adjoint recursion above evaluated at zs (u, u_x, u_v and
- * grad Jt at zs_k).
+ * grad Jt at zs_k).  The variance is var_c(t) = max(0, svar0[c] + svar1[c] t):
+ * with svar_kind 0 the line as given; with svar_kind 1 the ordinary
+ * least-squares line through the points (t_k, V_k,c), k = 0..N, where
+ *   V_k,c = (1/M) sum_m (z^m_k,c - zbar_k,c)^2,  zbar_k,c = (1/M) sum_m z^m_k,c
+ * is the forward ensemble's own per-step variance under the same mu and draws
+ * (svar0 and svar1 are then ignored).
  */
 #ifndef FB_ORACLE_H
 #define FB_ORACLE_H
@@ -81,13 +86,15 @@ typedef struct {
     int32_t init_kind;     /* 0: Gaussian z0 + s0 * Z, 1: uniform on [z0 - s0, z0 + s0],
                               2: ellipse points + s0 * Z */
     double z0[2], s0[2];
-    double svar0[2], svar1[2]; /* surrogate-state variance var_c(t) = svar0[c] + svar1[c] t */
+    double svar0[2], svar1[2]; /* surrogate-state variance line var_c(t) = svar0[c] + svar1[c] t
+                                  (finite; evaluated as max(0, .)) */
     const double* zd;      /* (N+1) x 2, row k = desired (x, v) at t_k (tracking cost) */
     int32_t np;            /* particles per system (ring), >= 1 */
     double omega;          /* nearest-neighbour coupling */
     int32_t cost_kind;     /* 0: tracking cost around zd, 1: ellipse cost */
     double ax, av;         /* ellipse half-axes (cost_kind 1, init_kind 2) */
     int32_t grid;          /* 0: fixed grid with Poisson counts, 1: jump-adapted grid */
+    int32_t svar_kind;     /* surrogate variance: 0 the given line, 1 fitted to the forward ensemble */
 } fb_problem;
 
 /* Bump b(r) and its derivative b'(r). */
@@ -133,8 +140,16 @@ int fb_grad_scale_surrogate(const fb_problem* pb, int64_t M, uint64_t seed, uint
 void fb_surrogate_state(const fb_problem* pb, uint64_t seed, uint32_t m, uint32_t k, uint32_t iter,
                         double z[2]);
 
-/* Per-path surrogate adjoints ls (count x (N+1) x 2, row 0 zero).  The
- * surrogate functions take independent particles only (np = 1). */
+/* The forward ensemble's per-step variance var ((N+1) x 2, may be NULL) of
+ * the M particles under mu, and the least-squares line a[c] + b[c] t through
+ * it (the fitted surrogate variance, svar_kind 1; computed whatever svar_kind
+ * holds). */
+int fb_surrogate_fit(const fb_problem* pb, int64_t M, uint64_t seed, uint32_t iter,
+                     const double* mu, double* var, double a[2], double b[2], int nthreads);
+
+/* Per-path surrogate adjoints ls (count x (N+1) x 2, row 0 zero); svar_kind 0
+ * only (a fitted line depends on all M particles: pass it as the given line).
+ * The surrogate functions take independent particles only (np = 1). */
 int fb_paths_surrogate(const fb_problem* pb, uint64_t seed, uint32_t iter, int64_t m0, int64_t count,
                        const double* mu, double* lam, int nthreads);
 

@@ -228,7 +228,7 @@ class _FbProblem(C.Structure):
                 ("s0", C.c_double * 2), ("svar0", C.c_double * 2), ("svar1", C.c_double * 2),
                 ("zd", C.c_void_p), ("np", C.c_int32), ("omega", C.c_double),
                 ("cost_kind", C.c_int32), ("ax", C.c_double), ("av", C.c_double),
-                ("grid", C.c_int32)]
+                ("grid", C.c_int32), ("svar_kind", C.c_int32)]
 
 
 def _bind_fb(L):
@@ -259,6 +259,8 @@ def _bind_fb(L):
                               C.c_int, C.c_int]
     L.fb_paths_surrogate.argtypes = [P, C.c_uint64, C.c_uint32, C.c_int64, C.c_int64, P, P, C.c_int]
     L.fb_paths_surrogate.restype = C.c_int
+    L.fb_surrogate_fit.argtypes = [P, C.c_int64, C.c_uint64, C.c_uint32, P, P, P, P, C.c_int]
+    L.fb_surrogate_fit.restype = C.c_int
     L.fb_adapted_draws.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, P, P, P, P, P]
     L.fb_optimize.restype = C.c_int
     L._fb_bound = True
@@ -278,7 +280,8 @@ class _Fb:
                              p.vmax, p.eps, p.alpha, p.sigJ, p.init_kind,
                              (C.c_double * 2)(*p.z0), (C.c_double * 2)(*p.s0),
                              (C.c_double * 2)(*p.svar0), (C.c_double * 2)(*p.svar1),
-                             self.zd.ctypes.data, p.np, p.omega, p.cost_kind, p.ax, p.av, p.grid)
+                             self.zd.ctypes.data, p.np, p.omega, p.cost_kind, p.ax, p.av, p.grid,
+                             p.svar_kind)
 
     def ref(self):
         return C.byref(self.st)
@@ -374,6 +377,19 @@ def fb_surrogate_state(p, seed: int, m: int, k: int, it: int) -> np.ndarray:
     fb = _Fb(p)
     _fb().fb_surrogate_state(fb.ref(), seed, m, k, it, _ptr(z))
     return z
+
+
+def fb_surrogate_fit(p, M: int, seed: int, it: int, mu, nthreads: int | None = None):
+    """(var, a, b): the forward ensemble's per-step variance ((N+1, 2)) of M
+    particles under mu and the least-squares line a + b t through it."""
+    mu = _mu(p, mu)
+    var = np.zeros((p.N + 1, 2))
+    a, b = np.zeros(2), np.zeros(2)
+    fb = _Fb(p)
+    rc = _fb().fb_surrogate_fit(fb.ref(), M, seed, it, _ptr(mu), _ptr(var), _ptr(a), _ptr(b),
+                                nthreads or default_threads())
+    assert rc == 0, rc
+    return var, a, b
 
 
 def fb_paths_surrogate(p, seed: int, it: int, m0: int, count: int, mu) -> np.ndarray:

@@ -267,10 +267,14 @@ class FeedbackProblem:
     # time grid: 0 the fixed grid with Poisson jump counts per step, 1 the
     # jump-adapted grid (uniform points and each particle's jump times)
     grid: int = 0
+    # surrogate variance: 0 the line svar0 + svar1 t, 1 the least-squares line
+    # through the forward ensemble's own per-step variance (Section 6.5)
+    svar_kind: int = 0
 
     def __post_init__(self):
         self.N, self.nx, self.nv, self.init_kind = int(self.N), int(self.nx), int(self.nv), int(self.init_kind)
         self.np, self.cost_kind, self.grid = int(self.np), int(self.cost_kind), int(self.grid)
+        self.svar_kind = int(self.svar_kind)
         for f in ("T", "eta", "b1", "b2", "gamma", "beta", "xmax", "vmax", "eps", "alpha", "sigJ",
                   "omega", "ax", "av"):
             setattr(self, f, float(getattr(self, f)))
@@ -311,7 +315,8 @@ def feedback_problem(N: int = 50, T: float = 5.0, init: str = "gauss", zd=None, 
                      eps: float = 0.5, alpha: float = 1e-2, sigJ: float = 0.5,
                      name: str = "", s0=None, z0=None, svar0=None, svar1=None, np_: int = 1,
                      omega: float = 0.0, cost: str = "track", ax: float = 1.5,
-                     av: float = 1.7071067811865475, grid: str = "fixed") -> FeedbackProblem:
+                     av: float = 1.7071067811865475, grid: str = "fixed",
+                     svar: str = "given") -> FeedbackProblem:
     """The setting of the paper's Section 6 (xmax = vmax = 2, nx = nv = 10,
     eps = 0.5, beta = 10, gamma = 0.9, eta = 1, T = 5, N = 50).  The paper does
     not state alpha, sigma_J, b1, b2; the defaults here are readings.  init
@@ -321,7 +326,9 @@ def feedback_problem(N: int = 50, T: float = 5.0, init: str = "gauss", zd=None, 
     couples rings of np_ particles with strength omega; cost 'ellipse' is the
     cost of Section 6.4 with the half-axes ax = 1.5, av = 1.7071067811865475
     printed there.  grid 'adapted' integrates on the jump-adapted grid of
-    Section 3 (Algorithms 5.1-5.2) instead of the fixed grid."""
+    Section 3 (Algorithms 5.1-5.2) instead of the fixed grid.  svar 'fit' takes
+    the surrogate variance of Section 6.5 from a least-squares line through the
+    forward ensemble's per-step variance instead of svar0 + svar1 t."""
     if init == "gauss":
         kind, z0d, s0d = 0, (0.75, 0.75), (0.1, 0.1)
     elif init == "uniform":
@@ -334,6 +341,8 @@ def feedback_problem(N: int = 50, T: float = 5.0, init: str = "gauss", zd=None, 
         raise ValueError(cost)
     if grid not in ("fixed", "adapted"):
         raise ValueError(grid)
+    if svar not in ("given", "fit"):
+        raise ValueError(svar)
     z0 = z0d if z0 is None else z0
     s0 = s0d if s0 is None else s0
     if zd is None:
@@ -342,7 +351,7 @@ def feedback_problem(N: int = 50, T: float = 5.0, init: str = "gauss", zd=None, 
                            xmax=xmax, vmax=vmax, eps=eps, alpha=alpha, sigJ=sigJ, init_kind=kind,
                            z0=z0, s0=s0, zd=zd, name=name, svar0=svar0, svar1=svar1, np=np_,
                            omega=omega, cost_kind=0 if cost == "track" else 1, ax=ax, av=av,
-                           grid=0 if grid == "fixed" else 1)
+                           grid=0 if grid == "fixed" else 1, svar_kind=0 if svar == "given" else 1)
 
 
 def ring_problem(N: int = 50, T: float = 5.0, np_: int = 2000, omega: float = 0.5, name: str = "",

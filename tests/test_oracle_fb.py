@@ -288,6 +288,84 @@ def test_surrogate_on_own_path_equals_exact(gamma):
     assert np.abs(g0 - g).max() > 1e-3 * np.abs(g).max()
 
 
+def test_surrogate_fit_matches_the_ensemble():
+    """Fitted surrogate variance (Section 6.5: a variance that grows linearly
+    and follows the forward model's own): the per-step variance is numpy's
+    population variance of the oracle's particle states, and the line is
+    numpy's least-squares fit through it."""
+    p = small_problem(b1=0.3, b2=0.4, beta=40.0, svar="fit")
+    mu = wl.random_feedback_control(p, 3, 1.0)
+    M, seed, it = 3000, 5, 2
+    var, a, b = ref.fb_surrogate_fit(p, M, seed, it, mu)
+    z, _, _, n, _ = ref.fb_paths(p, seed, it, 0, M, mu)
+    assert n.sum() > 0
+    want = z.var(axis=0)
+    np.testing.assert_allclose(var, want, rtol=1e-12, atol=1e-15)
+    t = np.arange(p.N + 1) * p.dt
+    for c in range(2):
+        bb, aa = np.polyfit(t, want[:, c], 1)
+        assert abs(b[c] - bb) <= 1e-12 * abs(bb)
+        assert abs(a[c] - aa) <= 1e-12 * (abs(aa) + abs(bb) * p.T)
+
+
+def test_surrogate_fit_velocity_random_walk():
+    """Closed form: without the spring, control and position noise, and with
+    gamma = 1, the velocity is a random walk with Gaussian steps and jumps that
+    add 1/(2 beta) each at the rate sqrt(beta/pi): Var v(t) = s0_v^2 +
+    (b2^2 + sqrt(beta/pi)/(2 beta)) t exactly in expectation, so the fitted
+    velocity line recovers it within the Monte Carlo error."""
+    p = wl.feedback_problem(N=20, T=2.0, eta=0.0, b1=0.0, b2=0.4, beta=40.0, gamma=1.0, nx=4,
+                            nv=4, s0=(0.1, 0.2), svar="fit")
+    _, a, b = ref.fb_surrogate_fit(p, 50000, 5, 2, np.zeros((p.N, p.L)))
+    slope = 0.4 ** 2 + math.sqrt(40.0 / math.pi) / 80.0
+    assert abs(b[1] - slope) <= 0.03 * slope, (b[1], slope)
+    assert abs(a[1] - 0.04) <= 0.03 * 0.04, a[1]
+    # the position variance grows faster than linearly (its integral of a
+    # random walk): the line through it starts below zero
+    assert a[0] < 0 < b[0]
+
+
+def test_surrogate_fit_gradient_is_the_given_line_at_the_fit():
+    """svar_kind 1 is svar_kind 0 at the fitted line, also where the line is
+    negative near t = 0 (the variance is 0 there: the surrogate state is the
+    target)."""
+    kw = dict(eta=0.0, b1=0.0, b2=0.4, beta=40.0, gamma=1.0, s0=(0.1, 0.2))
+    pf = small_problem(svar="fit", **kw)
+    mu = wl.random_feedback_control(pf, 3, 1.0)
+    M, seed, it = 2000, 4, 1
+    _, a, b = ref.fb_surrogate_fit(pf, M, seed, it, mu)
+    assert a[0] < 0
+    pg = small_problem(svar0=a, svar1=b, **kw)
+    Jf, gf = ref.fb_cost_grad_surrogate(pf, M, seed, it, mu)
+    Jg, gg = ref.fb_cost_grad_surrogate(pg, M, seed, it, mu)
+    assert Jf == Jg
+    np.testing.assert_array_equal(gf, gg)
+    z0 = ref.fb_surrogate_state(pg, seed, 3, 0, it)
+    assert z0[0] == pg.zd[0, 0] and z0[1] != pg.zd[0, 1]
+    # the given line the defaults use is another direction
+    _, gd = ref.fb_cost_grad_surrogate(small_problem(**kw), M, seed, it, mu)
+    assert np.abs(gd - gf).max() > 1e-3 * np.abs(gf).max()
+
+
+def test_surrogate_fit_one_particle_is_exact():
+    """One particle has zero ensemble variance, so the fitted surrogate states
+    are the target itself; with the target set to the particle's own realised
+    path the surrogate gradient is the exact (difference-pinned) gradient."""
+    kw = dict(gamma=0.8, b1=0.3, b2=0.4, beta=40.0)
+    base = small_problem(**kw)
+    mu = wl.random_feedback_control(base, 3, 1.0)
+    seed, it = 5, 2
+    z, _, _, n, _ = ref.fb_paths(base, seed, it, 0, 1, mu)
+    assert n.sum() > 0
+    p = small_problem(zd=z[0], svar="fit", **kw)
+    var, a, b = ref.fb_surrogate_fit(p, 1, seed, it, mu)
+    assert np.all(var == 0) and np.all(a == 0) and np.all(b == 0)
+    J, g = ref.fb_cost_grad(p, 1, seed, it, mu)
+    Js, gs = ref.fb_cost_grad_surrogate(p, 1, seed, it, mu)
+    assert Js == J
+    np.testing.assert_allclose(gs, g, rtol=1e-10, atol=1e-12 * np.abs(g).max())
+
+
 def test_surrogate_one_step_definition():
     """N = 1: gs_0 = (1/M) sum_m [alpha u_0 phi(z_0) + gamma^n dt dJt/dv(zs_1) phi(zs_0)]."""
     p = wl.feedback_problem(N=1, T=0.5, zd=np.array([[0.2, -0.1], [0.4, 0.3]]), alpha=0.3,

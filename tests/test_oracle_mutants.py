@@ -101,8 +101,15 @@ FB_MUTANTS = {
     "fb_armijo_sign": ("if (Jt <= J - c_armijo * zeta * gg)", "if (Jt <= J + c_armijo * zeta * gg)"),
     "fb_surr_no_jump_factor": ("G[(size_t)k * L + i * pb->nv + l] += summand(w, w->px[i] * w->pv[l] * (gn * lv));",
                                "G[(size_t)k * L + i * pb->nv + l] += summand(w, w->px[i] * w->pv[l] * lv);"),
-    "fb_surr_var_no_sqrt": ("z[0] = pb->zd[2 * k] + sqrt(pb->svar0[0] + pb->svar1[0] * t) * R * cos(th);",
-                            "z[0] = pb->zd[2 * k] + (pb->svar0[0] + pb->svar1[0] * t) * R * cos(th);"),
+    "fb_surr_var_no_sqrt": ("z[0] = pb->zd[2 * k] + sqrt(vx) * R * cos(th);",
+                            "z[0] = pb->zd[2 * k] + vx * R * cos(th);"),
+    "fb_surr_var_no_clamp": ("return v > 0.0 ? v : 0.0;", "return v;"),
+    "fb_fit_about_zero": ("double d = pass == 0 ? w.z[q] : w.z[q] - zbar[q];", "double d = w.z[q];"),
+    "fb_fit_mean_not_divided": ("            zbar[q] /= (double)M;\n", ""),
+    "fb_fit_sxx_uncentred": ("sxx += dtk * dtk;", "sxx += (double)k * dt * (double)k * dt;"),
+    "fb_fit_intercept_sign": ("a[c] = vbar - b[c] * tbar;", "a[c] = vbar + b[c] * tbar;"),
+    "fb_fit_components_swapped": ("vbar += V[2 * k + c];", "vbar += V[2 * k + 1 - c];"),
+    "fb_fit_line_swapped": ("mu, NULL, fitted.svar0, fitted.svar1,", "mu, NULL, fitted.svar1, fitted.svar0,"),
     "fb_surr_fresh_sample_per_step": ("uint32_t ctr[4] = {m, FB_SURR_WORD, iter, 1u};",
                                       "uint32_t ctr[4] = {m, k, iter, 1u};"),
     "fb_surr_time_next_step": ("double t = (double)k * (pb->T / (double)pb->N);",
