@@ -18,6 +18,7 @@ Prints ONE JSON line on stdout; progress goes to stderr.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -396,6 +397,18 @@ def feedback_section(args, time_calls, dev):
                              "trajectory_bytes_saved": (p.N + 1) * 2 * 4 * es.nblk * 256}
     del es
     torch.cuda.empty_cache()
+    # the same with the variance fitted to the forward ensemble (per-step
+    # moments in the forward, a reduction and the least-squares line between
+    # the sweeps)
+    pf = dataclasses.replace(p, svar_kind=1)
+    es = B.FbEngine(pf, M=w.M, seed=w.seed, precision="fp32", device=dev, mode="surrogate")
+    for it in range(args.warmup):
+        es.cost_grad(mu, it=it)
+    sg = time_calls(lambda: es.cost_grad(mu, it=5), args.steps)
+    out["fp32_surrogate_fit"] = {"p50_ms": percentile(sg, 50), "p99_ms": percentile(sg, 99),
+                                 "path_steps_per_s_p50": ps / (percentile(sg, 50) * 1e-3)}
+    del es
+    torch.cuda.empty_cache()
     t_f, t_a = out["fp32"]["forward_ms"] * 1e-3, out["fp32"]["adjoint_ms"] * 1e-3
     t_cg = out["fp32"]["p50_ms"] * 1e-3
     out["roofline"] = {
@@ -419,19 +432,22 @@ def feedback_section(args, time_calls, dev):
     held = B.FbEngine(pc, M=1 << 16, seed=wc.seed + 100, precision="fp64", device=dev)
     J0h, _ = held.cost_grad(mu0, it=0)
     conv = {"workload": "f3 (Section 6.3 / 6.5 setting), FP64", "held_out_J_zero_control": float(J0h)}
-    for mode in ("store", "surrogate"):
-        ec = B.FbEngine(pc, M=wc.M, seed=wc.seed, precision="fp64", device=dev, mode=mode)
+    for key, mode, pk in (("exact", "store", pc), ("surrogate", "surrogate", pc),
+                          ("surrogate_fitted_variance", "surrogate",
+                           dataclasses.replace(pc, svar_kind=1))):
+        ec = B.FbEngine(pk, M=wc.M, seed=wc.seed, precision="fp64", device=dev, mode=mode)
         muc, logs = ec.optimize(mu0.clone(), n_max=40, zeta0=10.0, allow_stall=True)
         Jh, _ = held.cost_grad(muc, it=0)
-        conv["exact" if mode == "store" else "surrogate"] = {
-            "iterations": len(logs), "stalled": len(logs) < 40,
-            "J": [round(l["J"], 6) for l in logs], "held_out_J": float(Jh)}
+        conv[key] = {"iterations": len(logs), "stalled": len(logs) < 40,
+                     "J": [round(l["J"], 6) for l in logs], "held_out_J": float(Jh)}
         del ec
     del held
     out["surrogate_vs_exact_iteration"] = conv
     log(f"surrogate vs exact iteration (f3): exact {conv['exact']['iterations']} it -> held-out "
         f"{conv['exact']['held_out_J']:.4f}, surrogate {conv['surrogate']['iterations']} it -> "
-        f"{conv['surrogate']['held_out_J']:.4f}")
+        f"{conv['surrogate']['held_out_J']:.4f}, fitted variance "
+        f"{conv['surrogate_fitted_variance']['iterations']} it -> "
+        f"{conv['surrogate_fitted_variance']['held_out_J']:.4f}")
     J64, g64 = res["fp64"]
     J32, g32 = res["fp32"]
     out["fp32_vs_fp64_full_size"] = {"J_rel": abs(J32 - J64) / abs(J64),

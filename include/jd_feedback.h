@@ -76,7 +76,14 @@
  * with one sample (Z1, Z2) per particle and realization (Box-Muller pair of
  * words 0, 1 of Philox block (m, 0xFFFFFFFE, iter, 1), the same at every
  * step) and the forward's jump counts, and adds gamma^{n_k} ls^v_{k+1} phi(zs_k).  J is the
- * exact cost.  The gradient is biased (it is not the derivative of J).
+ * exact cost.  The gradient is biased (it is not the derivative of J).  The
+ * variance is max(0, a + b t) per component: with svar_kind JD_FB_SVAR_GIVEN
+ * the line a = svar0, b = svar1; with JD_FB_SVAR_FIT the ordinary
+ * least-squares line through the points (t_k, V_k), k = 0..N, where V_k is
+ * the population variance over the M particles of the forward sweep's own
+ * z_k (same mu and draws), so that the surrogate variance follows the forward
+ * model's (the forward sums z_k - zd_k and its square per step in FP64; a
+ * short reduction and the fit run between the two sweeps).
  *
  * Conventions are those of jd.h (return codes, caller-owned device buffers,
  * asynchronous calls on `stream`, validation before any launch).  mu and g
@@ -107,6 +114,9 @@ extern "C" {
 #define JD_FB_GRID_FIXED 0   /* fixed grid, Poisson jump counts composed per step */
 #define JD_FB_GRID_ADAPTED 1 /* jump-adapted grid: uniform points plus jump times */
 
+#define JD_FB_SVAR_GIVEN 0   /* surrogate variance svar0 + svar1 t */
+#define JD_FB_SVAR_FIT 1     /* surrogate variance fitted to the forward ensemble */
+
 typedef struct jd_fb_problem {
     int32_t N;          /* time steps, >= 1 */
     int32_t nx, nv;     /* shape-function grid, 1..16 each; L = nx nv */
@@ -121,7 +131,8 @@ typedef struct jd_fb_problem {
     double sigJ;        /* tracking-cost width, > 0 */
     int32_t init_kind;  /* JD_FB_INIT_GAUSS or JD_FB_INIT_UNIFORM */
     double z0[2], s0[2];/* initial law: centre and scale (s0 >= 0) */
-    double svar0[2], svar1[2]; /* surrogate-state variance svar0 + svar1 t (>= 0), JD_SURROGATE */
+    double svar0[2], svar1[2]; /* surrogate-state variance svar0 + svar1 t (>= 0), JD_SURROGATE
+                                  with JD_FB_SVAR_GIVEN (ignored with JD_FB_SVAR_FIT) */
     const double* zd;   /* DEVICE, (N+1) x 2 FP64: desired (x, v) at t_0..t_N; may be
                            NULL with the ellipse cost outside JD_SURROGATE */
     int32_t np;         /* particles per ring, 1..JD_FB_MAX_RING (1: independent particles) */
@@ -129,6 +140,7 @@ typedef struct jd_fb_problem {
     int32_t cost_kind;  /* JD_FB_COST_TRACK or JD_FB_COST_ELLIPSE */
     double ax, av;      /* ellipse half-axes, > 0 (ellipse cost or start) */
     int32_t grid;       /* JD_FB_GRID_FIXED or JD_FB_GRID_ADAPTED (np = 1, JD_STORE) */
+    int32_t svar_kind;  /* JD_FB_SVAR_GIVEN or JD_FB_SVAR_FIT (JD_SURROGATE) */
 } jd_fb_problem;
 
 /* Per-path diagnostics for the feedback model, as jd_dump with these layouts

@@ -303,6 +303,7 @@ JD_FB_INIT_GAUSS, JD_FB_INIT_UNIFORM, JD_FB_INIT_ELLIPSE = 0, 1, 2
 JD_FB_COST_TRACK, JD_FB_COST_ELLIPSE = 0, 1
 JD_FB_MAX_RING = 2048
 JD_FB_GRID_FIXED, JD_FB_GRID_ADAPTED = 0, 1
+JD_FB_SVAR_GIVEN, JD_FB_SVAR_FIT = 0, 1
 
 
 class jd_fb_problem(C.Structure):
@@ -314,7 +315,7 @@ class jd_fb_problem(C.Structure):
                 ("s0", C.c_double * 2), ("svar0", C.c_double * 2), ("svar1", C.c_double * 2),
                 ("zd", C.c_void_p), ("np", C.c_int32), ("omega", C.c_double),
                 ("cost_kind", C.c_int32), ("ax", C.c_double), ("av", C.c_double),
-                ("grid", C.c_int32)]
+                ("grid", C.c_int32), ("svar_kind", C.c_int32)]
 
 
 class FbProblem:
@@ -329,7 +330,8 @@ class FbProblem:
                                 p.vmax, p.eps, p.alpha, p.sigJ, p.init_kind,
                                 (C.c_double * 2)(*p.z0), (C.c_double * 2)(*p.s0),
                                 (C.c_double * 2)(*p.svar0), (C.c_double * 2)(*p.svar1),
-                                self.zd.data_ptr(), p.np, p.omega, p.cost_kind, p.ax, p.av, p.grid)
+                                self.zd.data_ptr(), p.np, p.omega, p.cost_kind, p.ax, p.av, p.grid,
+                                p.svar_kind)
 
     @property
     def ref(self):
@@ -423,14 +425,14 @@ class FbEngine:
                                   self.ws_bytes, _stream_ptr(self.device)), "jd_fb_adjoint")
         return g
 
-    def cost_grad(self, mu, it: int = 0, J=None, g=None):
+    def cost_grad(self, mu, it: int = 0, J=None, g=None, dump: jd_dump | None = None):
         torch = _torch()
         mu = self._mu(mu)
         if J is None:
             J = torch.empty((), dtype=torch.float64, device=self.device)
         if g is None:
             g = torch.empty((self.p.N, self.p.L), dtype=torch.float64, device=self.device)
-        run = self.run(it)
+        run = self.run(it, dump)
         check(lib().jd_fb_cost_grad(self.prob.ref, C.byref(run), mu.data_ptr(), J.data_ptr(),
                                     g.data_ptr(), self.traj.data_ptr(), self.ws.data_ptr(),
                                     self.ws_bytes, _stream_ptr(self.device)), "jd_fb_cost_grad")

@@ -53,7 +53,8 @@ struct FbArgs {
     Real b1, b2, gamma, sbeta;  // jump-adapted grid: noise scales, gamma, 1/sqrt(2 beta)
     Real xc0, dxc, vc0, dvc;  // centres x^i = xc0 + i dxc, v^l = vc0 + l dvc
     Real z0x, z0v, s0x, s0v;
-    Real var0x, var0v, var1x, var1v;  // surrogate-state variance var(t) = var0 + var1 t
+    const Real* sd;  // surrogate states' standard deviations per step ((N+1) x 2)
+    double* mom;     // surrogate forward: per-step moment partials, or null
     int init_kind;
     uint32_t key0, key1, iter;
     const PoissonTable* thr;
@@ -309,9 +310,8 @@ __device__ __forceinline__ void fb_surrogate_sample(const FbArgs<Real>& a, uint3
 template <typename Real>
 __device__ __forceinline__ void fb_surrogate(const FbArgs<Real>& a, const Real* __restrict__ zd,
                                              int k, Real cx, Real cv, Real& x, Real& v) {
-    const Real t = (Real)k * a.dt;
-    x = fma(sqrt(fma(a.var1x, t, a.var0x)), cx, zd[2 * k]);
-    v = fma(sqrt(fma(a.var1v, t, a.var0v)), cv, zd[2 * k + 1]);
+    x = fma(a.sd[2 * k], cx, zd[2 * k]);
+    v = fma(a.sd[2 * k + 1], cv, zd[2 * k + 1]);
 }
 
 template <typename Real>
@@ -736,12 +736,18 @@ __device__ __forceinline__ double* fb_tile_lds(FbShared<Real, VR, W>& sh, int wv
                   : (double*)&sh.phv[wv][0][0] + (s - TX) * kFbTile;
 }
 
+struct FbNoMid {
+    __device__ __forceinline__ void operator()() const {}
+};
+
 // Sums the W waves' held tiles in a fixed order into the block's partials:
-// tile s is step k0 + s dir (ADD: added to what the partial holds).
-template <bool ADD, int H, typename Real, int VR, int W>
+// tile s is step k0 + s dir (ADD: added to what the partial holds).  mid runs
+// between the flush's two barriers (with every wave's LDS writes before the
+// flush visible, and none of the next step's yet).
+template <bool ADD, int H, typename Real, int VR, int W, typename Mid = FbNoMid>
 __device__ __forceinline__ void fb_hist_flush(FbShared<Real, VR, W>& sh, const FbWave<Real, VR>& w,
                                               FbHist<H>& h, int k0, int dir, int N, int nx, int nv,
-                                              double* __restrict__ apart) {
+                                              double* __restrict__ apart, const Mid& mid = Mid()) {
     static_assert(H <= fb_tiles_x<Real>() + fb_tiles_v<Real, VR>(),
                   "a wave's transposes must hold its H tiles");
     const int wv = threadIdx.x >> 6;
@@ -769,9 +775,71 @@ __device__ __forceinline__ void fb_hist_flush(FbShared<Real, VR, W>& sh, const F
             }
         }
     }
+    mid();
     __syncthreads();
     h.cnt = 0;
 }
+
+// Per-step moments of the block's particles for the fitted surrogate
+// variance: with y = z_k - zd_k, the sums of y_x, y_x^2, y_v, y_v^2 (q = 0..3)
+// in FP64.  Each lane puts its particles' values into its wave's transpose
+// buffer after the flush tile (free until the next step's shape functions);
+// after a barrier wave q adds component q over the W waves, lane by lane, and
+// over the 64 lanes by a butterfly, in a fixed order, and lane 0 writes
+// mom[(k nb + block) 4 + q].
+template <typename Real, int VR, int W>
+__device__ __forceinline__ double* fb_mom_lds(FbShared<Real, VR, W>& sh, int wv) {
+    static_assert(sizeof(Real) * kFbMaxGrid * fb_xs<Real>() >= sizeof(double) * (kFbTile + 4 * 64),
+                  "a wave's position transpose must hold its flush tile and its moments");
+    return (double*)&sh.phx[wv][0][0] + kFbTile;
+}
+template <typename Real, int VR, int W, int G>
+__device__ __forceinline__ void fb_mom_put(FbShared<Real, VR, W>& sh, const Real (&x)[G],
+                                           const Real (&v)[G], const bool (&act)[G],
+                                           const Real* __restrict__ zk) {
+    const double zx = (double)zk[0], zv = (double)zk[1];
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+        if (act[j]) {
+            const double yx = (double)x[j] - zx, yv = (double)v[j] - zv;
+            s[0] += yx;
+            s[1] += yx * yx;
+            s[2] += yv;
+            s[3] += yv * yv;
+        }
+    }
+    double* m = fb_mom_lds(sh, threadIdx.x >> 6);
+    const int ln = threadIdx.x & 63;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        m[q * 64 + ln] = s[q];
+}
+template <typename Real, int VR, int W>
+__device__ __forceinline__ void fb_mom_sum(FbShared<Real, VR, W>& sh, double* __restrict__ mom,
+                                           int k) {
+    static_assert(W == 4, "one wave per moment");
+    const int q = threadIdx.x >> 6, ln = threadIdx.x & 63;
+    double s = fb_mom_lds(sh, 0)[q * 64 + ln];
+#pragma unroll
+    for (int wv = 1; wv < W; ++wv)
+        s += fb_mom_lds(sh, wv)[q * 64 + ln];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        s += __shfl_xor(s, o);
+    if (ln == 0)
+        mom[((size_t)k * gridDim.x + blockIdx.x) * 4 + q] = s;
+}
+template <typename Real, int VR, int W>
+struct FbMomMid {
+    FbShared<Real, VR, W>& sh;
+    double* mom;
+    int k;
+    __device__ __forceinline__ void operator()() const {
+        if (mom != nullptr)
+            fb_mom_sum(sh, mom, k);
+    }
+};
 
 // Storage-free forward of the surrogate gradient (Section 6.5): G particles
 // per lane step together; each step adds alpha u_k phi(z_k) to the block's
@@ -803,6 +871,13 @@ k_fb_forward_grad(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __res
         acc[j] = 0.0;
         cx[j] = cv[j] = 0;
     }
+    typedef FbShared<Real, fb_vrows<NVP>()> Sh;
+    if (a.mom != nullptr) {
+        fb_mom_put(sh, x, v, act, zd);
+        __syncthreads();
+        fb_mom_sum(sh, a.mom, 0);
+        __syncthreads();
+    }
     for (int k = 0; k < N; ++k) {
         const Real* mk = mu + (size_t)k * a.nx * NVP;
         wave.clear();
@@ -817,7 +892,10 @@ k_fb_forward_grad(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __res
             fb_dump(a, a.dX, k + 1, m[j], x[j], v[j]);
         }
         hist.push(fb_tile(wave));
-        fb_hist_flush<false>(sh, wave, hist, k, -1, N, a.nx, a.nv, apart);
+        if (a.mom != nullptr)
+            fb_mom_put(sh, x, v, act, zd + 2 * (k + 1));
+        fb_hist_flush<false>(sh, wave, hist, k, -1, N, a.nx, a.nv, apart,
+                             FbMomMid<Real, fb_vrows<NVP>(), Sh::waves>{sh, a.mom, k + 1});
     }
     double C = 0.0;
 #pragma unroll
@@ -1564,6 +1642,92 @@ k_fb_draws(FbArgs<Real> a, PoissonTable pt, int64_t m0, int64_t mc, int k0, int 
         counts[idx] = poisson_count(poisson_word(w), a.thr);
 }
 
+// Per-step variance of the surrogate gradient's forward ensemble (block k =
+// step k): each thread adds the moment partials of blocks t, t + 256, ... in
+// block order, a fixed tree sums the threads, and with y = z_k - zd_k
+// V_c = max(0, sum y_c^2 / M - (sum y_c / M)^2) goes to var[2 k + c].
+__global__ void __launch_bounds__(kThreads)
+k_fb_step_var(const double* __restrict__ mom, int nb, int64_t M, double* __restrict__ var, Gate gate) {
+    if (gate_closed(gate))
+        return;
+    __shared__ double sh[kThreads];
+    const int k = blockIdx.x;
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nb; b += kThreads) {
+        const double* pm = mom + ((size_t)k * nb + b) * 4;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            s[q] += pm[q];
+    }
+    double tot[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        tot[q] = block_sum(s[q], sh);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const double mean = tot[2 * c] / (double)M;
+            const double v = tot[2 * c + 1] / (double)M - mean * mean;
+            var[2 * k + c] = v > 0.0 ? v : 0.0;
+        }
+    }
+}
+
+// The surrogate variance line per component (Section 6.5: a variance growing
+// linearly in time): given (a = svar0, b = svar1), or (fit) the ordinary
+// least-squares line through (t_k, V_k), k = 0..N, from svar[0 .. 2N+1]:
+// b = sum (t_k - tbar)(V_k - Vbar) / sum (t_k - tbar)^2, a = Vbar - b tbar,
+// every sum a fixed tree.  Writes the line to svar[2N+2 ..] (a_x, a_v, b_x,
+// b_v) and sd[2k + c] = sqrt(max(0, a_c + b_c t_k)) in the path precision.
+template <typename Real>
+__global__ void __launch_bounds__(kThreads)
+k_fb_surr_sd(double* __restrict__ svar, int N, double dt, int fit, double a0x, double a0v,
+             double b0x, double b0v, Real* __restrict__ sd, Gate gate) {
+    if (gate_closed(gate))
+        return;
+    __shared__ double sh[kThreads];
+    double a[2] = {a0x, a0v}, b[2] = {b0x, b0v};
+    if (fit) {
+        const double n1 = (double)(N + 1);
+        double st = 0.0, sv[2] = {0.0, 0.0};
+        for (int k = threadIdx.x; k <= N; k += kThreads) {
+            st += (double)k * dt;
+            sv[0] += svar[2 * k];
+            sv[1] += svar[2 * k + 1];
+        }
+        const double tbar = block_sum(st, sh) / n1;
+        double vbar[2];
+        vbar[0] = block_sum(sv[0], sh) / n1;
+        vbar[1] = block_sum(sv[1], sh) / n1;
+        double sxx = 0.0, sxy[2] = {0.0, 0.0};
+        for (int k = threadIdx.x; k <= N; k += kThreads) {
+            const double d = (double)k * dt - tbar;
+            sxx += d * d;
+            sxy[0] += d * (svar[2 * k] - vbar[0]);
+            sxy[1] += d * (svar[2 * k + 1] - vbar[1]);
+        }
+        sxx = block_sum(sxx, sh);
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            b[c] = block_sum(sxy[c], sh) / sxx;
+            a[c] = vbar[c] - b[c] * tbar;
+        }
+    }
+    for (int k = threadIdx.x; k <= N; k += kThreads) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const double v = a[c] + b[c] * ((double)k * dt);
+            sd[2 * k + c] = (Real)sqrt(v > 0.0 ? v : 0.0);
+        }
+    }
+    if (threadIdx.x == 0) {
+        svar[2 * (N + 1)] = a[0];
+        svar[2 * (N + 1) + 1] = a[1];
+        svar[2 * (N + 1) + 2] = b[0];
+        svar[2 * (N + 1) + 3] = b[1];
+    }
+}
+
 // ===========================================================================
 // Launchers.
 
@@ -1606,10 +1770,8 @@ static FbArgs<Real> fb_args(const FbHost& p, const HostRun& r) {
     a.z0v = (Real)p.z0[1];
     a.s0x = (Real)p.s0[0];
     a.s0v = (Real)p.s0[1];
-    a.var0x = (Real)p.svar0[0];
-    a.var0v = (Real)p.svar0[1];
-    a.var1x = (Real)p.svar1[0];
-    a.var1v = (Real)p.svar1[1];
+    a.sd = nullptr;
+    a.mom = nullptr;
     a.init_kind = p.init_kind;
     a.key0 = (uint32_t)(r.seed & 0xFFFFFFFFu);
     a.key1 = (uint32_t)(r.seed >> 32);
@@ -1748,6 +1910,7 @@ static hipError_t fb_adjoint_t(const FbHost& p, const HostRun& r, const void* ta
     a.thr = &hdr->poisson;
     a.gate = gate;
     const Real* tb = (const Real*)tab;
+    a.sd = tb + t.sd;
     const int G = fb_adjoint_groups(p, r);
     const unsigned nb = (unsigned)fb_partial_blocks(p, r);
 #define FB_ADJ_G(NVP, GG, S, RG)                                                                  \
@@ -1794,12 +1957,13 @@ hipError_t fb_launch_adjoint(const FbHost& p, const HostRun& r, const void* tab,
 
 template <typename Real>
 static hipError_t fb_forward_grad_t(const FbHost& p, const HostRun& r, const void* tab,
-                                    double* cpart, double* apart, const WsHeader* hdr,
+                                    double* cpart, double* apart, double* mom, const WsHeader* hdr,
                                     hipStream_t st, Gate gate) {
     const FbTable t = fb_table_layout(p);
     FbArgs<Real> a = fb_args<Real>(p, r);
     a.thr = &hdr->poisson;
     a.gate = gate;
+    a.mom = mom;
     const Real* tb = (const Real*)tab;
     const int G = fb_adjoint_groups(p, r);
     const unsigned nb = (unsigned)fb_partial_blocks(p, r);
@@ -1821,9 +1985,28 @@ static hipError_t fb_forward_grad_t(const FbHost& p, const HostRun& r, const voi
 }
 
 hipError_t fb_launch_forward_grad(const FbHost& p, const HostRun& r, const void* tab, double* cpart,
-                                  double* apart, const WsHeader* hdr, hipStream_t st, Gate gate) {
-    return r.prec == JD_FP64 ? fb_forward_grad_t<double>(p, r, tab, cpart, apart, hdr, st, gate)
-                             : fb_forward_grad_t<float>(p, r, tab, cpart, apart, hdr, st, gate);
+                                  double* apart, double* mom, const WsHeader* hdr, hipStream_t st,
+                                  Gate gate) {
+    return r.prec == JD_FP64
+               ? fb_forward_grad_t<double>(p, r, tab, cpart, apart, mom, hdr, st, gate)
+               : fb_forward_grad_t<float>(p, r, tab, cpart, apart, mom, hdr, st, gate);
+}
+
+hipError_t fb_launch_surrogate_sd(const FbHost& p, const HostRun& r, const double* mom,
+                                  double* svar, void* tab, hipStream_t st, Gate gate) {
+    const FbTable t = fb_table_layout(p);
+    if (mom != nullptr)
+        hipLaunchKernelGGL(k_fb_step_var, dim3((unsigned)(p.N + 1)), dim3(kThreads), 0, st, mom,
+                           fb_partial_blocks(p, r), r.M, svar, gate);
+    if (r.prec == JD_FP64)
+        hipLaunchKernelGGL(k_fb_surr_sd<double>, dim3(1), dim3(kThreads), 0, st, svar, p.N, p.dt,
+                           (int)(mom != nullptr), p.svar0[0], p.svar0[1], p.svar1[0], p.svar1[1],
+                           (double*)tab + t.sd, gate);
+    else
+        hipLaunchKernelGGL(k_fb_surr_sd<float>, dim3(1), dim3(kThreads), 0, st, svar, p.N, p.dt,
+                           (int)(mom != nullptr), p.svar0[0], p.svar0[1], p.svar1[0], p.svar1[1],
+                           (float*)tab + t.sd, gate);
+    return hipGetLastError();
 }
 
 

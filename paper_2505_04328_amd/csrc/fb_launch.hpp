@@ -18,6 +18,7 @@ struct FbHost {
     int init_kind;
     double z0[2], s0[2];
     double svar0[2], svar1[2];  // surrogate-state variance var(t) = svar0 + svar1 t
+    bool svar_fit;              // surrogate variance fitted to the forward ensemble instead
     const double* zd;     // device (N+1) x 2, or null (ellipse cost)
     int np;               // particles per ring (1: independent particles)
     int G;                // ring kernels: 256-slot groups per workgroup
@@ -33,11 +34,17 @@ struct FbHost {
 };
 
 // Per-step table in the path precision: mu rows (N x nx x nvp, zero-padded),
-// targets ((N+1) x 2) and the Keilson-Storer factors (32 x 2).
+// targets ((N+1) x 2), the Keilson-Storer factors (32 x 2) and the surrogate
+// states' standard deviations ((N+1) x 2, surrogate gradient only).
 struct FbTable {
-    size_t mu, zd, ks, count;  // element offsets and total elements
+    size_t mu, zd, ks, sd, count;  // element offsets and total elements
 };
 FbTable fb_table_layout(const FbHost& p);
+// FP64 elements of the surrogate gradient's per-step moment partials
+// ((N+1) x forward blocks x 4) and of its variance record ((N+1) x 2 per-step
+// variances, then the line a_x, a_v, b_x, b_v).
+size_t fb_mom_count(const FbHost& p, const HostRun& r);
+size_t fb_svar_count(const FbHost& p);
 
 hipError_t fb_launch_table(const FbHost& p, const HostRun& r, const double* mu, void* tab,
                            WsHeader* hdr, int clear_flag, hipStream_t st, Gate gate = kNoGate);
@@ -52,8 +59,13 @@ hipError_t fb_launch_adjoint(const FbHost& p, const HostRun& r, const void* tab,
 // Storage-free forward that also writes the alpha u phi(z) part of the
 // gradient partials (surrogate gradient) and the per-block costs.
 hipError_t fb_launch_forward_grad(const FbHost& p, const HostRun& r, const void* tab, double* cpart,
-                                  double* apart, const WsHeader* hdr, hipStream_t st,
+                                  double* apart, double* mom, const WsHeader* hdr, hipStream_t st,
                                   Gate gate = kNoGate);
+// The surrogate variance line (given, or fitted to the moment partials mom of
+// fb_launch_forward_grad when mom is not null) into svar, and the per-step
+// standard deviations into the table.
+hipError_t fb_launch_surrogate_sd(const FbHost& p, const HostRun& r, const double* mom,
+                                  double* svar, void* tab, hipStream_t st, Gate gate = kNoGate);
 // 256-particle groups per block of the adjoint (and of the surrogate's
 // forward, which shares its partials).
 int fb_adjoint_groups(const FbHost& p, const HostRun& r);

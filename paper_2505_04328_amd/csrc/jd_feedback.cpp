@@ -43,10 +43,16 @@ int fb_prepare(const jd_fb_problem* prob, const jd_run* run, FbHost& p, HostRun&
     if ((q.cost_kind == JD_FB_COST_ELLIPSE || q.init_kind == JD_FB_INIT_ELLIPSE) &&
         !(q.ax > 0.0 && finite(q.ax) && q.av > 0.0 && finite(q.av)))
         return JD_EINVAL;
-    for (int c = 0; c < 2; ++c)
-        if (!finite(q.z0[c]) || !(q.s0[c] >= 0.0) || !finite(q.s0[c]) || !(q.svar0[c] >= 0.0) ||
-            !finite(q.svar0[c]) || !(q.svar1[c] >= 0.0) || !finite(q.svar1[c]))
+    if (q.svar_kind != JD_FB_SVAR_GIVEN && q.svar_kind != JD_FB_SVAR_FIT)
+        return JD_EINVAL;
+    for (int c = 0; c < 2; ++c) {
+        if (!finite(q.z0[c]) || !(q.s0[c] >= 0.0) || !finite(q.s0[c]))
             return JD_EINVAL;
+        if (q.svar_kind == JD_FB_SVAR_GIVEN &&
+            (!(q.svar0[c] >= 0.0) || !finite(q.svar0[c]) || !(q.svar1[c] >= 0.0) ||
+             !finite(q.svar1[c])))
+            return JD_EINVAL;
+    }
     if (!q.zd && (q.cost_kind == JD_FB_COST_TRACK || run->mode == JD_SURROGATE))
         return JD_EINVAL;
     const double dt = q.T / (double)q.N;
@@ -100,6 +106,7 @@ int fb_prepare(const jd_fb_problem* prob, const jd_run* run, FbHost& p, HostRun&
         p.svar0[c] = q.svar0[c];
         p.svar1[c] = q.svar1[c];
     }
+    p.svar_fit = q.svar_kind == JD_FB_SVAR_FIT;
     p.zd = q.zd;
     p.np = q.np;
     p.omega = q.omega;
@@ -143,7 +150,7 @@ int fb_prepare(const jd_fb_problem* prob, const jd_run* run, FbHost& p, HostRun&
 }
 
 struct FbLayout {
-    size_t hdr, ring, tab, cpart, apart, gbuf, ut, total;
+    size_t hdr, ring, tab, cpart, apart, gbuf, ut, mom, svar, total;
 };
 
 FbLayout fb_layout(const FbHost& p, const HostRun& r) {
@@ -163,6 +170,14 @@ FbLayout fb_layout(const FbHost& p, const HostRun& r) {
     off += round_up((size_t)p.N * p.L * sizeof(double), kAlign);
     L.ut = off;
     off += round_up((size_t)p.N * p.L * sizeof(double), kAlign);
+    // surrogate gradient: the forward's per-step moment partials (fitted
+    // variance only), the per-step variance and the variance line
+    L.mom = off;
+    if (r.mode == JD_SURROGATE && p.svar_fit)
+        off += round_up(fb_mom_count(p, r) * sizeof(double), kAlign);
+    L.svar = off;
+    if (r.mode == JD_SURROGATE)
+        off += round_up(fb_svar_count(p) * sizeof(double), kAlign);
     L.total = off + kAlign;
     return L;
 }
@@ -183,6 +198,8 @@ struct FbWs {
     double* apart;
     double* gbuf;
     double* ut;
+    double* mom;   // surrogate, fitted variance: per-step moment partials
+    double* svar;  // surrogate: per-step variance and the variance line
 };
 
 int fb_bind(const FbHost& p, const HostRun& r, void* ws, size_t ws_bytes, FbWs& w) {
@@ -199,6 +216,8 @@ int fb_bind(const FbHost& p, const HostRun& r, void* ws, size_t ws_bytes, FbWs& 
     w.apart = (double*)(base + L.apart);
     w.gbuf = (double*)(base + L.gbuf);
     w.ut = (double*)(base + L.ut);
+    w.mom = (double*)(base + L.mom);
+    w.svar = (double*)(base + L.svar);
     return JD_OK;
 }
 
@@ -206,7 +225,9 @@ int fb_enqueue_cost_grad(const FbHost& p, const HostRun& r, const double* mu, do
                          void* traj, const FbWs& w, hipStream_t st, Gate gate = kNoGate) {
     JD_TRY(fb_launch_table(p, r, mu, w.tab, w.hdr, 1, st, gate));
     if (r.mode == JD_SURROGATE) {
-        JD_TRY(fb_launch_forward_grad(p, r, w.tab, w.cpart, w.apart, w.hdr, st, gate));
+        double* mom = p.svar_fit ? w.mom : nullptr;
+        JD_TRY(fb_launch_forward_grad(p, r, w.tab, w.cpart, w.apart, mom, w.hdr, st, gate));
+        JD_TRY(fb_launch_surrogate_sd(p, r, mom, w.svar, w.tab, st, gate));
         JD_TRY(fb_launch_adjoint(p, r, w.tab, nullptr, w.apart, w.hdr, true, st, gate));
         JD_TRY(fb_launch_finalize_grad(p, r, w.apart, g, w.hdr, st, gate));
         JD_TRY(fb_launch_finalize_cost(p, r, w.cpart, fb_partial_blocks(p, r), g, J, w.hdr, 0, st,

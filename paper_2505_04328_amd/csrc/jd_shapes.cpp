@@ -59,9 +59,16 @@ FbTable fb_table_layout(const FbHost& p) {
     t.mu = 0;
     t.zd = up((size_t)p.N * p.nx * p.nvp);
     t.ks = t.zd + up((size_t)(p.N + 1) * 2);
-    t.count = t.ks + 64;
+    t.sd = t.ks + 64;
+    t.count = t.sd + up((size_t)(p.N + 1) * 2);
     return t;
 }
+
+size_t fb_mom_count(const FbHost& p, const HostRun& r) {
+    return (size_t)(p.N + 1) * (size_t)fb_partial_blocks(p, r) * 4;
+}
+
+size_t fb_svar_count(const FbHost& p) { return (size_t)(p.N + 1) * 2 + 4; }
 
 int fb_ring_groups(int np) { return np <= kBlock ? 1 : 8; }
 

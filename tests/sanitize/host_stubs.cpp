@@ -89,7 +89,9 @@ hipError_t fb_launch_forward(const FbHost&, const HostRun&, const void*, void*, 
 hipError_t fb_launch_adjoint(const FbHost&, const HostRun&, const void*, const void*, double*,
                              const WsHeader*, bool, hipStream_t, Gate) { return launched(); }
 hipError_t fb_launch_forward_grad(const FbHost&, const HostRun&, const void*, double*, double*,
-                                  const WsHeader*, hipStream_t, Gate) { return launched(); }
+                                  double*, const WsHeader*, hipStream_t, Gate) { return launched(); }
+hipError_t fb_launch_surrogate_sd(const FbHost&, const HostRun&, const double*, double*, void*,
+                                  hipStream_t, Gate) { return launched(); }
 hipError_t fb_launch_finalize_grad(const FbHost&, const HostRun&, const double*, double*, WsHeader*,
                                    hipStream_t, Gate) { return launched(); }
 hipError_t fb_launch_finalize_cost(const FbHost&, const HostRun&, const double*, int, const double*,

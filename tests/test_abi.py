@@ -243,7 +243,7 @@ class _FbDummy:
                                   p.xmax, p.vmax, p.eps, p.alpha, p.sigJ, p.init_kind,
                                   (C.c_double * 2)(*p.z0), (C.c_double * 2)(*p.s0),
                                   (C.c_double * 2)(*p.svar0), (C.c_double * 2)(*p.svar1), 0x1000,
-                                  p.np, p.omega, p.cost_kind, p.ax, p.av, p.grid)
+                                  p.np, p.omega, p.cost_kind, p.ax, p.av, p.grid, p.svar_kind)
 
 
 def test_fb_workspace_and_traj_sizes(L):
@@ -260,6 +260,23 @@ def test_fb_workspace_and_traj_sizes(L):
     assert L.jd_fb_traj_bytes(C.byref(pr.st), C.byref(run7)) == (p.N + 1) * 2 * 256 * 8 + p.N * 256
     rec = B.make_run(1000, precision="fp32", mode="recompute", K=10)
     assert L.jd_fb_traj_bytes(C.byref(pr.st), C.byref(rec)) == 0
+
+
+def test_fb_surrogate_fit_workspace(L):
+    """The fitted surrogate variance ignores svar0/svar1 and adds the per-step
+    moment partials of the forward's blocks ((N+1) x blocks x 4 FP64)."""
+    p = wl.feedback_config("f4").problem
+    M = 1 << 20
+    sur = B.make_run(M, precision="fp32", mode="surrogate")
+    given = _FbDummy(p)
+    fit = _FbDummy(p)
+    fit.st.svar_kind = B.JD_FB_SVAR_FIT
+    fit.st.svar0 = (C.c_double * 2)(-1.0, float("nan"))
+    wg = L.jd_fb_workspace_bytes(C.byref(given.st), C.byref(sur))
+    wf = L.jd_fb_workspace_bytes(C.byref(fit.st), C.byref(sur))
+    assert wg > 0 and wf >= wg + (p.N + 1) * (M // 256) * 4 * 8
+    given.st.svar0 = (C.c_double * 2)(-1.0, 0.0)
+    assert L.jd_fb_workspace_bytes(C.byref(given.st), C.byref(sur)) == 0
 
 
 def test_fb_adapted_traj_size(L):
@@ -315,6 +332,7 @@ def test_fb_invalid_arguments_rejected_before_launch(L):
     assert call(beta=1e4, N=2, T=2.0) == B.JD_EINVAL
     assert call(svar0=(C.c_double * 2)(-1.0, 0.0)) == B.JD_EINVAL
     assert call(svar1=(C.c_double * 2)(0.0, float("inf"))) == B.JD_EINVAL
+    assert call(svar_kind=2) == B.JD_EINVAL
     pr = _FbDummy(wl.feedback_problem(N=20, T=2.0))
     P = C.byref(pr.st)
     assert L.jd_fb_forward(P, C.byref(run), None, fake, fake, fake, ws, None) == B.JD_EINVAL

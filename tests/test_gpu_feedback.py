@@ -304,6 +304,94 @@ def test_fb_surrogate_optimize_matches_oracle(dev):
     assert norm_err(mu.cpu().numpy(), mu_o) <= 1e-11
 
 
+# ------------------------------------------------- fitted surrogate variance (Section 6.5)
+def _fit_problem(name, **over):
+    kw, M, seed, scale = CASES[name]
+    kw = dict(kw, **over)
+    N, T = kw.get("N", 50), kw.get("T", 5.0)
+    kw.setdefault("zd", _track(N, T))
+    return wl.feedback_problem(svar="fit", **kw), M, seed, scale
+
+
+def _given_at(p, a, b):
+    """The same problem with the fitted line passed as the given one (the
+    oracle's per-path surrogate adjoints take a given line)."""
+    import dataclasses
+    return dataclasses.replace(p, svar0=np.asarray(a), svar1=np.asarray(b), svar_kind=0)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("name,M", [("paper_f1", None), ("gamma_negative", None),
+                                    ("small_6x6", 1), ("grid_3x5_uniform", 257)])
+def test_fb_surrogate_fit_cost_grad_and_paths(dev, name, M, precision):
+    """The surrogate gradient with the variance fitted to the forward ensemble:
+    the forward's per-step moments, their reduction and the least-squares line
+    on the device, against the oracle's two-pass variance and fit; J, the
+    gradient per entry, and the surrogate adjoints per particle (which run on
+    the fitted standard deviations).  M = 1: zero variance, the surrogate
+    states are the target."""
+    p, M0, seed, scale = _fit_problem(name)
+    M = M or M0
+    say("surrogate fit", name, precision, f"M={M}")
+    mu = wl.random_feedback_control(p, 4, scale)
+    it = 3
+    var, a, b = ref.fb_surrogate_fit(p, M, seed, it, mu)
+    if M == 1:
+        assert np.all(a == 0) and np.all(b == 0)
+    ls = ref.fb_paths_surrogate(_given_at(p, a, b), seed, it, 0, M, mu)
+    J_ref, g_ref = ref.fb_cost_grad_surrogate(p, M, seed, it, mu)
+    s_ref = ref.fb_grad_scale(p, M, seed, it, mu, surrogate=True)
+    eng = B.FbEngine(p, M=M, seed=seed, precision=precision, device=dev, mode="surrogate")
+    dp, d = eng.path_dump(0, M)
+    J, g = eng.cost_grad(mu, it=it, dump=dp)
+    J, g = float(J), g.cpu().numpy()
+    tol = TOL[precision]
+    lg = np.transpose(d["lam"].double().cpu().numpy(), (2, 0, 1))
+    e_l = per_path_error(lg[:, 1:], ls[:, 1:])
+    e_J = rel_err(J, J_ref)
+    e_g, e_ge = grad_errors(g, g_ref, s_ref)
+    say(f"   line a={a} b={b}; errors: lam {e_l:.2e} J {e_J:.2e} g {e_g:.2e} (per entry {e_ge:.2e})")
+    assert e_l <= tol["path"] and e_J <= tol["J"] and e_g <= tol["g"] and e_ge <= tol["g"]
+    # the fitted line is not the default given one: the gradients differ
+    if M > 1:
+        _, g_given = ref.fb_cost_grad_surrogate(_given_at(p, p.svar0, p.svar1), M, seed, it, mu)
+        assert norm_err(g, g_given) > 100 * tol["g"]
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_fb_surrogate_fit_large_m(dev, precision):
+    """2^19 + 100 particles: the per-step reduction over 2049 (FP32) or 1025
+    (FP64, two groups per block) block partials, ragged last block."""
+    p = wl.feedback_problem(N=8, T=0.8, zd=_track(8, 0.8), alpha=0.1, b1=0.3, b2=0.4, svar="fit")
+    M = (1 << 19) + 100
+    mu = wl.random_feedback_control(p, 3, 1.0)
+    say("surrogate fit large M", M, precision)
+    eng = B.FbEngine(p, M=M, seed=17, precision=precision, device=dev, mode="surrogate")
+    J, g = eng.cost_grad(mu, it=2)
+    J_ref, g_ref = ref.fb_cost_grad_surrogate(p, M, 17, 2, mu)
+    s_ref = ref.fb_grad_scale(p, M, 17, 2, mu, surrogate=True)
+    assert rel_err(float(J), J_ref) <= TOL[precision]["J"]
+    assert_grad(g.cpu().numpy(), g_ref, s_ref, TOL[precision]["g"])
+
+
+def test_fb_surrogate_fit_optimize_matches_oracle(dev):
+    """The surrogate gradient iteration with the fitted variance (refitted at
+    every iteration's forward sweep) replayed against the oracle's."""
+    p, M, seed, _ = _fit_problem("small_6x6")
+    mu0 = wl.random_feedback_control(p, 9, 0.5)
+    say("surrogate fit optimize fp64", M)
+    mu_o, logs_o, n_o = ref.fb_optimize(p, M, seed, 0, mu0, n_max=4, zeta0=8.0, surrogate=True)
+    eng = B.FbEngine(p, M=M, seed=seed, precision="fp64", device=dev, mode="surrogate")
+    import torch
+    mu = torch.tensor(mu0, dtype=torch.float64, device=dev)
+    _, logs = eng.optimize(mu, n_max=4, zeta0=8.0)
+    assert n_o == 4 and len(logs) == 4
+    for x, y in zip(logs, logs_o):
+        assert x["zeta"] == y["zeta"] and x["backtracks"] == y["backtracks"]
+        assert abs(x["J"] - y["J"]) <= 1e-12 * abs(y["J"])
+    assert norm_err(mu.cpu().numpy(), mu_o) <= 1e-11
+
+
 def _count_bytes(eng, T_elems):
     """The trajectory buffer's bytes from element T_elems on (the jump data)."""
     import torch
