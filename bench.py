@@ -127,11 +127,13 @@ def parse():
     ap.add_argument("--no-adapted", action="store_true",
                     help="skip the jump-adapted grid section (Section 3)")
     ap.add_argument("--cpu-sample-paths", type=int, default=1 << 20)
-    ap.add_argument("--only", choices=["all", "fp32_store", "kernels", "d8-kernels", "fb-kernels"],
+    ap.add_argument("--only", choices=["all", "fp32_store", "kernels", "d8-kernels", "fb-kernels",
+                                       "ja-kernels"],
                     default="all",
                     help="kernels: c2's jd_cost_grad, jd_forward and jd_adjoint only; d8-kernels: "
                          "c3's FP32 stored and K = 64 recompute forward and adjoint only; "
-                         "fb-kernels: the f4 FP32 gradient only (for profiler runs)")
+                         "fb-kernels: the f4 FP32 gradient only; ja-kernels: the ja2 and ja3 "
+                         "FP32 gradients only (for profiler runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")
     ap.add_argument("--serving", action="store_true",
@@ -651,6 +653,20 @@ def main():
         torch.cuda.synchronize()
         log("feedback-model kernel loop done")
         print(json.dumps({"fb_kernels_only": True, "calls": args.warmup + args.steps}))
+        return
+    if args.only == "ja-kernels":
+        # the jump-adapted forward and adjoint at ja2 and ja3, FP32, for counter runs
+        for name in ("ja2", "ja3"):
+            wa = wl.adapted_config(name)
+            mu = torch.tensor(wl.random_feedback_control(wa.problem, 4, 0.5), device=dev)
+            ea = B.FbEngine(wa.problem, M=wa.M, seed=wa.seed, precision="fp32", device=dev)
+            for it in range(args.warmup + args.steps):
+                ea.cost_grad(mu, it=it)
+            torch.cuda.synchronize()
+            del ea
+            torch.cuda.empty_cache()
+            log(f"{name} kernel loop done")
+        print(json.dumps({"ja_kernels_only": True, "calls": args.warmup + args.steps}))
         return
     if args.only == "d8-kernels":
         # the d = 8 sweeps at c3, FP32: stored forward and adjoint, then the

@@ -1370,6 +1370,18 @@ k_fb_forward_adapted(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __
         cpart[blockIdx.x] = s;
 }
 
+// Stack entry e of the slot (x, v and the jump's offset), if want and the
+// stack holds it.
+template <typename Real>
+__device__ __forceinline__ void fb_stack_entry(const FbJumps<Real>& j, int e, bool want, Real& x,
+                                               Real& v, Real& o) {
+    if (want && e >= 0 && e < kFbJumpCap) {
+        x = j.st[(size_t)(kFbJumpComp * e) * kThreads];
+        v = j.st[(size_t)(kFbJumpComp * e + 1) * kThreads];
+        o = j.st[(size_t)(kFbJumpComp * e + 2) * kThreads];
+    }
+}
+
 // Backward sweep on the jump-adapted grid, one particle per lane.  The lane
 // carries lam~, the adjoint of the interval's end state without the running
 // cost charged there, and the unweighted cost gradient at that state; the
@@ -1399,6 +1411,15 @@ k_fb_adjoint_adapted(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __
     const FbJumps<Real> jumps = fb_jumps<Real>(const_cast<void*>(traj), N, a.nblk);
     int jend = *jumps.count;  // jumps in the intervals up to the current one
     int nk = __builtin_nontemporal_load(jumps.per + (size_t)(N - 1) * kThreads);
+    // The stack entry of each interval's first jump (all an interval with one
+    // jump reads) is loaded during the interval before, the jump counts two
+    // intervals ahead, so that no sub-step waits on the stack's memory.
+    // (FP32 paths; the FP64 kernel has no registers to spare for it)
+    constexpr bool PF = sizeof(Real) == 4;
+    int nk2 = PF && N >= 2 ? __builtin_nontemporal_load(jumps.per + (size_t)(N - 2) * kThreads) : 0;
+    Real pfx = 0, pfv = 0, pfa = 0;
+    if (PF)
+        fb_stack_entry(jumps, jend - nk, nk > 0, pfx, pfv, pfa);
     const Real xN = __builtin_nontemporal_load(row + (size_t)N * 2 * kThreads);
     const Real vN = __builtin_nontemporal_load(row + (size_t)N * 2 * kThreads + kThreads);
     Real gxe, gve;  // unweighted running-cost gradient at the interval's end state
@@ -1416,20 +1437,31 @@ k_fb_adjoint_adapted(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __
         }
         // the count the forward stored
         const int n = nk;
-        if (k >= 1)
+        if (PF) {
+            nk = nk2;
+            if (k >= 2)
+                nk2 = __builtin_nontemporal_load(jumps.per + (size_t)(k - 2) * kThreads);
+        } else if (k >= 1) {
             nk = __builtin_nontemporal_load(jumps.per + (size_t)(k - 1) * kThreads);
+        }
         const int jb = jend - n;  // stack entry of this interval's first jump
+        // entry jb (valid when n > 0 and jb < kFbJumpCap); then the next
+        // interval's first entry
+        const Real e0x = pfx, e0v = pfv, e0a = pfa;
+        if (PF && k >= 1)
+            fb_stack_entry(jumps, jb - nk, nk > 0, pfx, pfv, pfa);
         // the jump times a_q (q = 1..n) from the stack when it holds them all,
         // else regenerated
         const bool stk = n > 0 && jb + n - 1 < kFbJumpCap;
         const Real a1_0 = n == 0 ? (Real)1
-                          : stk  ? jumps.st[(size_t)(kFbJumpComp * jb + 2) * kThreads]
+                          : stk  ? (PF ? e0a : jumps.st[(size_t)(kFbJumpComp * jb + 2) * kThreads])
                                  : fb_next_offset(a, sl.p, k, 0, n, (Real)0);
         // the last sub-step starts at a_n
         Real an = 0;
         if (n > 0) {
             if (stk) {
-                an = jumps.st[(size_t)(kFbJumpComp * (jb + n - 1) + 2) * kThreads];
+                an = PF && n == 1 ? e0a
+                                  : jumps.st[(size_t)(kFbJumpComp * (jb + n - 1) + 2) * kThreads];
             } else {
                 an = a1_0;
                 for (int r = 1; r < n; ++r)
@@ -1451,7 +1483,8 @@ k_fb_adjoint_adapted(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __
             Real x = xk, v = vk, a0 = 0, a1 = a1_0;
             if (mine && r > 0) {
                 if (stk) {
-                    a0 = jumps.st[(size_t)(kFbJumpComp * (jb + r - 1) + 2) * kThreads];
+                    a0 = PF && r == 1 ? e0a
+                                      : jumps.st[(size_t)(kFbJumpComp * (jb + r - 1) + 2) * kThreads];
                     a1 = r < n ? jumps.st[(size_t)(kFbJumpComp * (jb + r) + 2) * kThreads] : (Real)1;
                 } else {
                     for (int q = 1; q <= r; ++q) {
@@ -1459,7 +1492,10 @@ k_fb_adjoint_adapted(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __
                         a1 = q < n ? fb_next_offset(a, sl.p, k, q, n, a1) : (Real)1;
                     }
                 }
-                if (jb + r - 1 < kFbJumpCap) {
+                if (PF && r == 1 && jb < kFbJumpCap) {
+                    x = e0x;
+                    v = e0v;
+                } else if (jb + r - 1 < kFbJumpCap) {
                     x = jumps.st[(size_t)(kFbJumpComp * (jb + r - 1)) * kThreads];
                     v = jumps.st[(size_t)(kFbJumpComp * (jb + r - 1) + 1) * kThreads];
                 } else {
@@ -1473,7 +1509,10 @@ k_fb_adjoint_adapted(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __
             if (mine && r < n) {
                 // the running cost at the jump ending sub-step r, charged to lam~_{r+1}
                 Real xe, ve;
-                if (jb + r < kFbJumpCap) {
+                if (PF && r == 0 && jb < kFbJumpCap) {
+                    xe = e0x;
+                    ve = e0v;
+                } else if (jb + r < kFbJumpCap) {
                     xe = jumps.st[(size_t)(kFbJumpComp * (jb + r)) * kThreads];
                     ve = jumps.st[(size_t)(kFbJumpComp * (jb + r) + 1) * kThreads];
                 } else {
