@@ -128,12 +128,13 @@ def parse():
                     help="skip the jump-adapted grid section (Section 3)")
     ap.add_argument("--cpu-sample-paths", type=int, default=1 << 20)
     ap.add_argument("--only", choices=["all", "fp32_store", "kernels", "d8-kernels", "fb-kernels",
-                                       "ja-kernels"],
+                                       "ja-kernels", "fp64-kernels"],
                     default="all",
                     help="kernels: c2's jd_cost_grad, jd_forward and jd_adjoint only; d8-kernels: "
                          "c3's FP32 stored and K = 64 recompute forward and adjoint only; "
                          "fb-kernels: the f4 FP32 gradient only; ja-kernels: the ja2 and ja3 "
-                         "FP32 gradients only (for profiler runs)")
+                         "FP32 gradients only; fp64-kernels: the FP64 gradients of c2, c3 (stored), "
+                         "f4 and ja2 only (for profiler runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")
     ap.add_argument("--serving", action="store_true",
@@ -186,6 +187,45 @@ def profiled_traffic(kernel: str):
                     rec = json.loads(ln.strip()[len("TRAFFIC "):])
                     if rec.get("src") == kernel_source_hash():
                         return rec["bytes_per_launch"].get(kernel)
+    except OSError:
+        pass
+    return None
+
+
+def fb_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("fb_kernels.hip", "fb_launch.hpp", "jd_device.hpp"):
+        with open(os.path.join(ROOT, "paper_2505_04328_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+FP64_FLOP_PEAK = 78.6e12  # published FP64 vector peak, FLOP/s
+
+
+def fp64_counted(kernel: str, units: float, seconds: float):
+    """Issue-rate record of an FP64 kernel from the committed counter summary
+    (counted slots per unit and FP64 flops per unit), if it was taken from the
+    current kernel sources; else None.  frac: counted slots against the slot
+    peak; fp64_flop_frac: FP64 flops against the FP64 vector peak."""
+    path = os.path.join(ROOT, "profiles", "fp64_kernels_sq_counters.md")
+    try:
+        with open(path) as fh:
+            for ln in fh:
+                if ln.strip().startswith("FP64COUNTS "):
+                    rec = json.loads(ln.strip()[len("FP64COUNTS "):])
+                    src = rec["src_fb"] if "k_fb" in kernel else rec["src_jd"]
+                    cur = fb_source_hash() if "k_fb" in kernel else kernel_source_hash()
+                    c = rec["per_unit"].get(kernel)
+                    if c is None or src != cur:
+                        return None
+                    return {"kernel": kernel, "bound": "alu", "basis": "counted instructions",
+                            "counted_slots_per_unit": c["slots"],
+                            "frac": c["slots"] * units / seconds / VALU_PEAK_SLOTS,
+                            "fp64_tflops": c["fp64_flops"] * units / seconds / 1e12,
+                            "fp64_flop_frac": c["fp64_flops"] * units / seconds / FP64_FLOP_PEAK,
+                            "kernel_ms": seconds * 1e3}
     except OSError:
         pass
     return None
@@ -290,6 +330,15 @@ def configs_section(args, time_calls, dev):
                 else:
                     ph = [(FWD8_SLOTS, 32.0 / K), (REGEN8_SLOTS + ADJ8_SLOTS, 32.0 / K)]
                 rec["roofline"] = composite_roofline(ph, MN, percentile(t, 50) * 1e-3)
+            elif mode == "store":
+                if name == "c3":  # counted on c3's linear drift
+                    rec["forward_issue"] = fp64_counted("jd::k_forward<double, 8, 1>", MN,
+                                                        percentile(tf, 50) * 1e-3)
+                # the stored adjoint reads z_k (8 FP64) per path-step: HBM-bound
+                ta_s = percentile(ta, 50) * 1e-3
+                rec["adjoint_roofline"] = {"kernel": "k_adjoint_stored<double,8>", "bound": "hbm",
+                                           "achieved": 64.0 * MN / ta_s / 1e9, "peak": 8000.0,
+                                           "unit": "GB/s", "frac": 64.0 * MN / ta_s / 8e12}
             res[key] = rec
             log(f"{name} {key}: {rec['p50_ms']:.2f} ms")
             del e
@@ -387,6 +436,11 @@ def feedback_section(args, time_calls, dev):
         out[prec] = {"p50_ms": percentile(cg, 50), "p99_ms": percentile(cg, 99),
                      "path_steps_per_s_p50": ps / (percentile(cg, 50) * 1e-3),
                      "forward_ms": float(np.mean(fw)), "adjoint_ms": float(np.mean(ad))}
+        if prec == "fp64":
+            out[prec]["forward_issue"] = fp64_counted(
+                "jd::k_fb_forward<double, 10, true, 1, false, 256>", ps, float(np.mean(fw)) * 1e-3)
+            out[prec]["adjoint_issue"] = fp64_counted(
+                "jd::k_fb_adjoint<double, 10, 2, false, false, 256>", ps, float(np.mean(ad)) * 1e-3)
         del e
         torch.cuda.empty_cache()
     # the storage-free surrogate gradient (Section 6.5): no trajectory buffer
@@ -508,6 +562,11 @@ def adapted_section(args, time_calls, dev):
             o[prec] = {"p50_ms": percentile(cg, 50), "p99_ms": percentile(cg, 99),
                        "particle_steps_per_s_p50": ps / (percentile(cg, 50) * 1e-3),
                        "forward_ms": float(np.mean(fw)), "adjoint_ms": float(np.mean(ad))}
+            if prec == "fp64" and name == "ja2":
+                o[prec]["forward_issue"] = fp64_counted(
+                    "jd::k_fb_forward_adapted<double, 10, true>", ps, float(np.mean(fw)) * 1e-3)
+                o[prec]["adjoint_issue"] = fp64_counted(
+                    "jd::k_fb_adjoint_adapted<double, 10>", ps, float(np.mean(ad)) * 1e-3)
             del e
             torch.cuda.empty_cache()
         fs = FB_FWD_SLOTS + sdt * ADAPT_FWD_EXTRA
@@ -654,6 +713,29 @@ def main():
         log("feedback-model kernel loop done")
         print(json.dumps({"fb_kernels_only": True, "calls": args.warmup + args.steps}))
         return
+    if args.only == "fp64-kernels":
+        # the FP64 sweeps: c2 (fused), c3 stored, f4 and ja2, for counter runs
+        for name in ("c2", "c3"):
+            wc = wl.config(name)
+            uc = torch.zeros((wc.problem.N, wc.problem.d), dtype=torch.float64, device=dev)
+            e = B.Engine(wc.problem, M=wc.M, seed=wc.seed, precision="fp64", mode="store",
+                         device=dev)
+            for it in range(args.warmup + args.steps):
+                e.cost_grad(uc, it=it)
+            torch.cuda.synchronize()
+            del e
+            torch.cuda.empty_cache()
+        for wf in (wl.feedback_config("f4"), wl.adapted_config("ja2")):
+            mu = torch.tensor(wl.random_feedback_control(wf.problem, 4, 0.5), device=dev)
+            ef = B.FbEngine(wf.problem, M=wf.M, seed=wf.seed, precision="fp64", device=dev)
+            for it in range(args.warmup + args.steps):
+                ef.cost_grad(mu, it=it)
+            torch.cuda.synchronize()
+            del ef
+            torch.cuda.empty_cache()
+        log("fp64 kernel loop done")
+        print(json.dumps({"fp64_kernels_only": True, "calls": args.warmup + args.steps}))
+        return
     if args.only == "ja-kernels":
         # the jump-adapted forward and adjoint at ja2 and ja3, FP32, for counter runs
         for name in ("ja2", "ja3"):
@@ -783,6 +865,9 @@ def main():
             "g_rel": float(np.linalg.norm(g32 - g64) / np.linalg.norm(g64))}
         forms["speedup_fp32_over_fp64_p50"] = (percentile(res["fp64_store_ms"], 50) /
                                                percentile(res["fp32_store_ms"], 50))
+        # the fused FP64 kernel is >99% of the call
+        forms["fp64_store"]["issue"] = fp64_counted("jd::k_cost_grad_stored<double, 1>", M * N,
+                                                    percentile(res["fp64_store_ms"], 50) * 1e-3)
     # average launch durations over the event-timed calls (the fused kernel is
     # >99% of a jd_cost_grad call; the table and finalize kernels take ~20 us)
     t_fwd = float(np.mean(fwd_ms)) * 1e-3
