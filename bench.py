@@ -399,6 +399,12 @@ def serving_section(args):
     return {
         "requests": len(recs), "wall_s": wall, "latency_p50_s": float(np.percentile(lat, 50)),
         "latency_p99_s": float(np.percentile(lat, 99)),
+        # the server's own split of each latency: waiting for a slot and arena
+        # memory, then running on the device among the admitted requests
+        "queued_p50_s": float(np.percentile([r.queued for r in recs], 50)),
+        "queued_p99_s": float(np.percentile([r.queued for r in recs], 99)),
+        "service_p50_s": float(np.percentile([r.service for r in recs], 50)),
+        "service_p99_s": float(np.percentile([r.service for r in recs], 99)),
         "gradient_path_steps_per_s": ps / wall, "swept_path_steps_per_s": sw / wall,
         "failed": int(sum(r.status != 0 for r in recs)),
         "peak_admitted": srv.stats["max_active"], "peak_queued": srv.stats["max_queued"],

@@ -66,6 +66,15 @@ int jd_server_progress(jd_server* s, int32_t* n_active, int32_t* n_queued, int64
 int jd_server_result(jd_server* s, int64_t ticket, double* u_host, jd_iter_log* log,
                      int32_t* iters, int32_t* status);
 
+/* Times of a finished request in seconds on the server's host clock, while
+ * its result has not been taken: *queued = admission - submission (all of its
+ * time if it was never admitted), *service = completion - admission.  The
+ * server sees a completion at the first jd_server_progress after the device
+ * has finished, so both are as fine as the caller's polling.  JD_EAGAIN while
+ * the request runs, JD_EINVAL for an unknown ticket; either pointer may be
+ * NULL. */
+int jd_server_times(jd_server* s, int64_t ticket, double* queued, double* service);
+
 /* Waits for all streams, then frees the server (not the arena). */
 int jd_server_destroy(jd_server* s);
 

@@ -23,6 +23,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <chrono>
 #include <deque>
 #include <map>
 #include <memory>
@@ -115,6 +116,9 @@ struct Request {
     LsDriver drv;
     std::vector<jd_iter_log> log;
     std::vector<double> u_out;
+    // host clock (seconds since the server was created): submission,
+    // admission (-1 until admitted) and completion as the server saw them
+    double t_submit, t_admit, t_done;
 };
 
 struct ReqOps : LsOps {
@@ -148,6 +152,10 @@ struct jd_server {
     int active;
     int64_t next_ticket;
     int64_t completed;
+    std::chrono::steady_clock::time_point t0;
+    double now() const {
+        return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
 };
 
 namespace {
@@ -204,6 +212,7 @@ void fail(jd_server* S, Request& q, int status) {
     q.u_out.clear();
     q.status = status;
     q.state = DONE;
+    q.t_done = S->now();
     release(S, q);
     S->completed++;
 }
@@ -226,6 +235,7 @@ int admit(jd_server* S, Request& q) {
         S->arena->release(q.off, q.bytes);
         q.status = rc;
         q.state = DONE;
+        q.t_done = S->now();
         S->completed++;
         return rc;
     }
@@ -239,6 +249,7 @@ int admit(jd_server* S, Request& q) {
     S->free_mirrors.pop_back();
     S->active++;
     q.state = RUNNING;
+    q.t_admit = S->now();
     hipStream_t st = S->streams[q.stream];
     const size_t nd = (size_t)q.p.N * q.p.d;
     q.log.assign((size_t)q.opt.n_max, jd_iter_log());
@@ -270,6 +281,7 @@ int admit(jd_server* S, Request& q) {
 int advance(jd_server* S, Request& q) {
     if (q.state == FINISHING) {
         q.state = DONE;
+        q.t_done = S->now();
         release(S, q);
         S->completed++;
         return JD_OK;
@@ -311,6 +323,7 @@ int jd_server_create(void* arena, size_t arena_bytes, int32_t max_active, int32_
     S->max_active = max_active;
     S->active = 0;
     S->next_ticket = 1;
+    S->t0 = std::chrono::steady_clock::now();
     S->completed = 0;
     S->mirrors = nullptr;
     if (hipHostMalloc((void**)&S->mirrors, kLsMirrorBytes * max_active, hipHostMallocDefault) !=
@@ -376,6 +389,9 @@ int jd_server_submit(jd_server* S, const jd_problem* prob, const double* xd_host
     q->ticket = S->next_ticket++;
     q->state = QUEUED;
     q->status = JD_OK;
+    q->t_submit = S->now();
+    q->t_admit = -1.0;
+    q->t_done = -1.0;
     *ticket = q->ticket;
     S->queue.push_back(q->ticket);
     S->reqs[q->ticket] = std::move(q);
@@ -444,6 +460,23 @@ int jd_server_result(jd_server* S, int64_t ticket, double* u_host, jd_iter_log* 
     if (status)
         *status = q.status;
     S->reqs.erase(it);
+    return JD_OK;
+}
+
+int jd_server_times(jd_server* S, int64_t ticket, double* queued, double* service) {
+    if (!S)
+        return JD_EINVAL;
+    auto it = S->reqs.find(ticket);
+    if (it == S->reqs.end())
+        return JD_EINVAL;
+    const Request& q = *it->second;
+    if (q.state != DONE)
+        return JD_EAGAIN;
+    const double ta = q.t_admit >= 0.0 ? q.t_admit : q.t_done;  // never ran: all queueing
+    if (queued)
+        *queued = ta - q.t_submit;
+    if (service)
+        *service = q.t_done - ta;
     return JD_OK;
 }
 

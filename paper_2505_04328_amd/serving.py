@@ -32,6 +32,8 @@ def _bind_server(L):
     L.jd_server_progress.restype = C.c_int
     L.jd_server_result.argtypes = [P, C.c_int64, P, P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     L.jd_server_result.restype = C.c_int
+    L.jd_server_times.argtypes = [P, C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    L.jd_server_times.restype = C.c_int
     L.jd_server_destroy.argtypes = [P]
     L.jd_server_destroy.restype = C.c_int
     L._server_bound = True
@@ -103,8 +105,21 @@ class Server:
             st["waited_for_memory"] += 1
         return a.value, q.value, c.value
 
+    def times(self, ticket: int):
+        """(queued, service) seconds of a finished request whose result has
+        not been taken, or None while it runs."""
+        qd, sv = C.c_double(), C.c_double()
+        rc = lib().jd_server_times(self.h, ticket, C.byref(qd), C.byref(sv))
+        if rc == -7:  # JD_EAGAIN
+            return None
+        B.check(rc, "jd_server_times")
+        return qd.value, sv.value
+
     def result(self, ticket: int):
-        """None while running; else dict(u, log, status)."""
+        """None while running; else dict(u, log, status, queued, service)."""
+        tm = self.times(ticket)
+        if tm is None:
+            return None
         N, d, iters = self.n[ticket]
         u = np.empty((N, d))
         logs = (B.jd_iter_log * max(iters, 1))()
@@ -116,7 +131,7 @@ class Server:
         del self.n[ticket]
         log = [dict(iter=l.iter, backtracks=l.backtracks, J=l.J, gnorm=l.gnorm, zeta=l.zeta,
                     J_new=l.J_new, E=l.E) for l in logs[:n.value]]
-        return dict(u=u, log=log, status=status.value)
+        return dict(u=u, log=log, status=status.value, queued=tm[0], service=tm[1])
 
     def close(self):
         if self.h:
@@ -137,6 +152,8 @@ class Record:
     arrival: float
     submitted: float = 0.0
     done: float = float("nan")
+    queued: float = float("nan")   # the server's admission - submission
+    service: float = float("nan")  # the server's completion - admission
     status: int = 0
     iterations: int = 0
     trials: int = 0
@@ -186,6 +203,7 @@ def run_mix(server: Server, requests, precision: str = "fp32", store_limit: int 
             rec, r = pending.pop(tk)
             rec.done = time.perf_counter() - t0
             rec.status = res["status"]
+            rec.queued, rec.service = res["queued"], res["service"]
             rec.iterations = len(res["log"])
             rec.trials = sum(1 + l["backtracks"] for l in res["log"])
             rec.path_steps = rec.iterations * r.M * r.problem.N

@@ -274,7 +274,11 @@ static void server() {
         std::vector<double> u((size_t)reqs[i].p->N * reqs[i].p->d, -1.0);
         jd_iter_log log[3];
         int32_t iters = -1, status = 1;
+        double queued = -1.0, service = -1.0;
+        CHECK(jd_server_times(S, tickets[i], &queued, &service) == JD_OK);
+        CHECK(queued >= 0.0 && service >= 0.0);
         CHECK(jd_server_result(S, tickets[i], u.data(), log, &iters, &status) == JD_OK);
+        CHECK(jd_server_times(S, tickets[i], &queued, &service) == JD_EINVAL);
         if (status == JD_EHIP)
             ++failed;
         else

@@ -59,7 +59,7 @@ def test_every_declared_symbol_is_exported(L):
 
 
 SERVER = ["jd_server_request_bytes", "jd_server_create", "jd_server_submit",
-          "jd_server_progress", "jd_server_result", "jd_server_destroy"]
+          "jd_server_progress", "jd_server_result", "jd_server_times", "jd_server_destroy"]
 
 
 def test_version_and_strerror(L):

@@ -56,13 +56,19 @@ def test_mix_equals_alone(dev):
     # requests overlapped on the device, and some waited for arena memory
     assert srv.stats["max_active"] > 1
     assert srv.stats["waited_for_memory"] > 0
+    # the three largest arrive together and one of them waits for the others' memory
+    assert max(rec.queued for rec in recs if rec.rid in {reqs[i].rid for i in big}) > 0
     by_rid = {r.rid: r for r in reqs}
     for rec in recs:
         r = by_rid[rec.rid]
         assert rec.status == 0, rec.status
         assert rec.iterations == r.iters
         say(f"   req {rec.rid}: d={r.problem.d} M={r.M} N={r.problem.N} lam={r.problem.lam:.2f} "
-            f"latency {rec.latency * 1e3:.1f} ms")
+            f"latency {rec.latency * 1e3:.1f} ms (queued {rec.queued * 1e3:.1f}, "
+            f"service {rec.service * 1e3:.1f})")
+        # the server's split of the latency: both parts non-negative and within it
+        assert rec.queued >= 0 and rec.service > 0
+        assert rec.queued + rec.service <= rec.latency + 0.05
         eng = B.Engine(r.problem, M=r.M, seed=r.seed, precision="fp32", mode="store", device=dev)
         u = torch.zeros((r.problem.N, r.problem.d), dtype=torch.float64, device=dev)
         _, log = eng.optimize(u, n_max=r.iters, it0=0)
