@@ -37,9 +37,10 @@ sys.path.insert(0, ROOT)
 VALU_PEAK_SLOTS = 256 * 4 * 32 * 2.4e9
 # Algorithmic slots per path-step of the forward sweep (d = 1, FP32): the work
 # the method needs when counter words 1-3 and the key are wave-uniform.  The
-# path index enters Philox only through counter word 0, so round 1's products
-# and round 2's second product are per path (hoisted out of the step loop), and
-# round 2's first product and round 3's first product are uniform or per path:
+# path index enters Philox only through counter word 0, so the products of the
+# first Philox round and the second product of the second are per path (hoisted
+# out of the step loop), and the first products of the second and third Philox
+# rounds are uniform or per path:
 #   Philox4x32-10 block: 15 lane-varying 32x32->64 products (60) + 17 xor3 (17)  = 77
 #   Box-Muller cosine half: 2 uniforms (8), log2 (4), scale (1), sqrt (4),
 #                           cos (4), product (1)                                 = 22
