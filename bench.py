@@ -45,15 +45,17 @@ VALU_PEAK_SLOTS = 256 * 4 * 32 * 2.4e9
 #   Box-Muller cosine half: 2 uniforms (8), log2 (4), scale (1), sqrt (4),
 #                           cos (4), product (1)                                 = 22
 #   Poisson word (2 byte permutes + or = 3) and the first threshold compare (1)  =  4
-#   Euler step: X^2, X^3, A X + B u, cubic, dt and noise terms                   =  6
+#   Euler step: A X + B u, dt and noise terms (c2's drift has no cubic term;
+#   one adds X^2, X^3 and its product: 3)                                        =  3
 #   running cost: difference, square, FP64 convert (2) and accumulate (2)       =  6
 # The jump term (sine half of Box-Muller, sqrt(n), scaling: ~15 slots) is
 # needed only in lanes that jump, lambda*dt = 0.005 of them (0.08 slots).
-FWD_SLOTS_PER_PATH_STEP = 115
-# Backward step per path-step: X - x_d, the drift transpose, the cubic term
-# (3 products + 1), dt (1), the masked deposit into the reduction tile (1), and
-# the amortised FP64 tile reduction (16 converts + adds per 16 steps, 4 slots)
-ADJ_SLOTS_PER_PATH_STEP = 12
+FWD_SLOTS_PER_PATH_STEP = 112
+# Backward step per path-step: X - x_d, the drift transpose, dt (1), the masked
+# deposit into the reduction tile (1), and the amortised FP64 tile reduction
+# (16 converts + adds per 16 steps, 4 slots); a cubic term would add 3 products
+# and an FMA (4)
+ADJ_SLOTS_PER_PATH_STEP = 8
 # The paper's model problem (include/jd_feedback.h, f4: 2^20 particles, 500
 # steps, nx = nv = 10 shape functions), algorithmic slots per particle-step:
 # forward  20 bumps (scaled distance eps x - i eps dx, 1 - q^2, clamp,
@@ -72,20 +74,21 @@ ADJ_SLOTS_PER_PATH_STEP = 12
 # gradient's outer products.
 # d = 8 (c3, c4; FP32 paths), algorithmic slots per path-step:
 # forward  four Philox blocks 308, eight Box-Muller cosine halves 176, the
-#          8 x 8 drift product and per-component Euler terms 104, Poisson 4,
-#          running cost 20                                                = 612
-# adjoint  per component: X - x_d (1), the A^T lam row (8), the cubic term
-#          (3), the dt update (1) = 13, times 8 = 104; the FP64 step
-#          reduction, per component a convert and an FP64 add (2 + 2)      =  32
-#                                                                         = 136
+#          8 x 8 drift product and per-component Euler terms 80 (c4's cubic
+#          term adds 3 per component: 104), Poisson 4, running cost 20      = 588 (c4: 612)
+# adjoint  per component: X - x_d (1), the A^T lam row (8), the dt update
+#          (1) = 10 (c4's cubic term: 3 more), times 8 = 80 (104); the FP64
+#          step reduction, per component a convert and an FP64 add (2 + 2) =  32
+#                                                                         = 112 (c4: 136)
 # The checkpoint-recompute adjoint regenerates each step once more without
-# its cost: 612 - 20 = 592 more.  HBM: the stored trajectory costs 4 d = 32 B
-# per path-step written and read back.
-FWD8_SLOTS = 612
-ADJ8_SLOTS = 136
-REGEN8_SLOTS = FWD8_SLOTS - 20
-# d = 1 (c2): the recompute adjoint's regenerated step without the cost (6)
-REGEN1_SLOTS = FWD_SLOTS_PER_PATH_STEP - 6
+# its cost (568, c4: 592).  HBM: the stored trajectory costs 4 d = 32 B per
+# path-step written and read back.
+def d8_slots(cubic: bool):
+    """(forward, adjoint, regenerated step) slots per path-step at d = 8."""
+    fwd, adj = (612, 136) if cubic else (588, 112)
+    return fwd, adj, fwd - 20
+
+
 FB_FWD_SLOTS = 482
 FB_ADJ_SLOTS = 556
 # Coupled rings (Section 6.4, ring2: 512 rings of 2000 particles, 500 steps):
@@ -326,14 +329,15 @@ def configs_section(args, time_calls, dev):
                    "forward_ms": percentile(tf, 50), "adjoint_ms": percentile(ta, 50),
                    "path_steps_per_s": MN / (percentile(t, 50) * 1e-3)}
             if prec == "fp32":
+                f8, a8, r8 = d8_slots(p.cubic != 0.0)
                 if mode == "store":
-                    ph = [(FWD8_SLOTS, 32), (ADJ8_SLOTS, 32)]
+                    ph = [(f8, 32), (a8, 32)]
                 else:
-                    ph = [(FWD8_SLOTS, 32.0 / K), (REGEN8_SLOTS + ADJ8_SLOTS, 32.0 / K)]
+                    ph = [(f8, 32.0 / K), (r8 + a8, 32.0 / K)]
                 rec["roofline"] = composite_roofline(ph, MN, percentile(t, 50) * 1e-3)
             elif mode == "store":
                 if name == "c3":  # counted on c3's linear drift
-                    rec["forward_issue"] = fp64_counted("jd::k_forward<double, 8, 1>", MN,
+                    rec["forward_issue"] = fp64_counted("jd::k_forward<double, 8, 1, false>", MN,
                                                         percentile(tf, 50) * 1e-3)
                 # the stored adjoint reads z_k (8 FP64) per path-step: HBM-bound
                 ta_s = percentile(ta, 50) * 1e-3
@@ -366,8 +370,8 @@ def configs_section(args, time_calls, dev):
         "form": "FP32 paths, checkpoints every 64 steps: jd_forward + jd_adjoint (recompute)",
         "p50_ms": percentile(t, 50), "p99_ms": percentile(t, 99),
         "path_steps_per_s": MN / (percentile(t, 50) * 1e-3),
-        "roofline": composite_roofline([(FWD8_SLOTS, 32.0 / w.K),
-                                        (REGEN8_SLOTS + ADJ8_SLOTS, 32.0 / w.K)], MN,
+        "roofline": composite_roofline([(d8_slots(True)[0], 32.0 / w.K),
+                                        (d8_slots(True)[2] + d8_slots(True)[1], 32.0 / w.K)], MN,
                                        percentile(t, 50) * 1e-3)}
     log(f"c4 autograd step: {percentile(t, 50):.2f} ms")
     del e
@@ -873,7 +877,7 @@ def main():
         forms["speedup_fp32_over_fp64_p50"] = (percentile(res["fp64_store_ms"], 50) /
                                                percentile(res["fp32_store_ms"], 50))
         # the fused FP64 kernel is >99% of the call
-        forms["fp64_store"]["issue"] = fp64_counted("jd::k_cost_grad_stored<double, 1>", M * N,
+        forms["fp64_store"]["issue"] = fp64_counted("jd::k_cost_grad_stored<double, 1, false>", M * N,
                                                     percentile(res["fp64_store_ms"], 50) * 1e-3)
     # average launch durations over the event-timed calls (the fused kernel is
     # >99% of a jd_cost_grad call; the table and finalize kernels take ~20 us)
@@ -889,7 +893,7 @@ def main():
                 "achieved": slots / t_cg / 1e12, "peak": VALU_PEAK_SLOTS / 1e12,
                 "unit": "TOP/s (full-rate VALU lane-op slots)",
                 "frac": slots / t_cg / VALU_PEAK_SLOTS,
-                "traffic": profiled_traffic("jd::k_cost_grad_stored<float, 1>"),
+                "traffic": profiled_traffic("jd::k_cost_grad_stored<float, 1, false>"),
                 "slots_per_path_step": FWD_SLOTS_PER_PATH_STEP + ADJ_SLOTS_PER_PATH_STEP,
                 "kernel_ms": t_cg * 1e3,
                 "hbm_bytes_per_path_step": 8, "hbm_frac": 8.0 * M * N / t_cg / HBM_PEAK}
@@ -897,11 +901,11 @@ def main():
     separate = {
         "forward": {"kernel": "k_forward<float,1,store>", "bound": "alu", "kernel_ms": t_fwd * 1e3,
                     "achieved": fwd_slots / t_fwd / 1e12, "frac": fwd_slots / t_fwd / VALU_PEAK_SLOTS,
-                    "traffic": profiled_traffic("jd::k_forward<float, 1, 1>")},
+                    "traffic": profiled_traffic("jd::k_forward<float, 1, 1, false>")},
         "adjoint": {"kernel": "k_adjoint_stored<float,1>", "bound": "hbm", "kernel_ms": t_adj * 1e3,
                     "achieved": 4.0 * M * N / t_adj / 1e9, "unit": "GB/s",
                     "frac": 4.0 * M * N / t_adj / HBM_PEAK,
-                    "traffic": profiled_traffic("jd::k_adjoint_stored<float, 1, false>")},
+                    "traffic": profiled_traffic("jd::k_adjoint_stored<float, 1, false, false>")},
     }
 
     # ---- oracle on a bounded sample of the same workload, and GPU errors there

@@ -255,8 +255,10 @@ __device__ __forceinline__ double count_sqrt<double>(int n) {
 //   X <- X + dt (A X - c3 X^3 + Bu_k) + sqrt(dt) s Z^W + n m_J + s_J sqrt(n) Z^J
 // bu = B u_k (per-step table row).  The jump term (with Z^J) is evaluated only
 // in waves where some lane jumps (lambda dt per path-step, so most waves skip
-// it) and applied only in the lanes with n > 0.
-template <typename Real, int D>
+// it) and applied only in the lanes with n > 0.  CUBIC = false compiles the
+// step of a drift without the cubic term (the kernels are instantiated for
+// both and launched by whether c3 is zero).
+template <typename Real, int D, bool CUBIC = true>
 __device__ __forceinline__ void euler_step(const Coef<Real, D>& c, const Coef<Real, D>* lc,
                                            const Real* __restrict__ bu, Real* X,
                                            const StepDraws<Real, D>& s) {
@@ -270,8 +272,10 @@ __device__ __forceinline__ void euler_step(const Coef<Real, D>& c, const Coef<Re
         for (int j = 0; j < D; ++j)
             f = fma(rows.A[i * D + j], X[j], f);
         row_barrier<LDS>();
-        const Real x3 = X[i] * X[i] * X[i];
-        f = fma(-c.c3, x3, f);
+        if (CUBIC) {
+            const Real x3 = X[i] * X[i] * X[i];
+            f = fma(-c.c3, x3, f);
+        }
         Real y = fma(c.dt, f, X[i]);
         Y[i] = fma(c.sq[i], s.zw[i], y);
     }
@@ -294,7 +298,8 @@ __device__ __forceinline__ void euler_step(const Coef<Real, D>& c, const Coef<Re
 // LDS: read the rows of A^T from the block's LDS copy (same values, same
 // arithmetic) -- kernels that also run forward steps set it wherever those
 // read their matrix from LDS.
-template <typename Real, int D, bool LDS = CoefInLds<Real, D>::adjoint>
+template <typename Real, int D, bool LDS = CoefInLds<Real, D>::adjoint,
+          bool CUBIC = true>
 __device__ __forceinline__ void adjoint_step(const Coef<Real, D>& c, const Coef<Real, D>* lc,
                                              const Real* __restrict__ xd, const Real* X, Real* lam) {
     const Coef<Real, D>& rows = coef_rows<LDS>(c, lc);
@@ -306,8 +311,10 @@ __device__ __forceinline__ void adjoint_step(const Coef<Real, D>& c, const Coef<
         for (int j = 0; j < D; ++j)
             a = fma(rows.AT[i * D + j], lam[j], a);
         row_barrier<LDS>();
-        const Real q = (Real)3 * c.c3 * X[i] * X[i];
-        a = fma(-q, lam[i], a);
+        if (CUBIC) {
+            const Real q = (Real)3 * c.c3 * X[i] * X[i];
+            a = fma(-q, lam[i], a);
+        }
         Y[i] = fma(c.dt, a, lam[i]);
     }
 #pragma unroll

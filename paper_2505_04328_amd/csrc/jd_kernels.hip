@@ -152,7 +152,7 @@ k_table(const double* __restrict__ u, const double* __restrict__ xd, Real* __res
 // in-order vector-memory counter the trajectory loads and stores use.
 // Forward sweep of one 256-path group g, one step at a time: begin(), step(k)
 // for k = 0..N-1, finish().  The path of this lane is m = 256 g + lane.
-template <typename Real, int D, int MODE>
+template <typename Real, int D, int MODE, bool CB>
 struct ForwardSweep {
     Real X[D];
     double acc;
@@ -176,7 +176,7 @@ struct ForwardSweep {
         acc += (double)sq_dist<Real, D>(X, trow + D);
         StepDraws<Real, D> z;
         draws<Real, D>((uint32_t)m, (uint32_t)k, a.iter, a.key0, a.key1, a.thr, z);
-        euler_step<Real, D>(a.c, a.lc, trow, X, z);
+        euler_step<Real, D, CB>(a.c, a.lc, trow, X, z);
         if (MODE == FWD_STORE) {
             store_row<Real, D>(row, a.d, X);
             row += (int64_t)a.d * kThreads;
@@ -206,7 +206,7 @@ struct ForwardSweep {
     }
 };
 
-template <typename Real, int D, int MODE>
+template <typename Real, int D, int MODE, bool CB>
 __global__ void __launch_bounds__(kThreads)
 k_forward(SweepArgs<Real, D> a, const Real* __restrict__ tab, double* __restrict__ cpart) {
     if (gate_closed(a.gate))
@@ -214,7 +214,7 @@ k_forward(SweepArgs<Real, D> a, const Real* __restrict__ tab, double* __restrict
     __shared__ double sh[kThreads];
     __shared__ Coef<Real, D> sc;
     stage_coef<CoefInLds<Real, D>::forward>(a, &sc);
-    ForwardSweep<Real, D, MODE> f;
+    ForwardSweep<Real, D, MODE, CB> f;
     f.begin(a, blockIdx.x);
     for (int k = 0; k < a.N; ++k)
         f.step(a, tab, k);
@@ -275,7 +275,7 @@ __device__ __forceinline__ void load_tile_buffer(const Real* region, int64_t str
 // One tile of the backward sweep: steps k, k-1, ..., k-count+1.  FULL tiles
 // have every step >= 1; the last tile may end at step 0, which contributes to
 // the gradient (lam_1) but needs no adjoint step.
-template <typename Real, int D, bool DUMP, bool FULL>
+template <typename Real, int D, bool DUMP, bool FULL, bool CB>
 __device__ __forceinline__ void sweep_tile(const SweepArgs<Real, D>& a, const Real* __restrict__ tab,
                                            int k, Real (*X)[D], Real* lam, bool act, int64_t m,
                                            StepReducer<D, Real>& red) {
@@ -294,7 +294,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<Real, D>& a, const Re
         red.put(s, v);
         if (FULL || kk >= 1) {
             const Real* xd = FULL ? trow + (S - 1 - s) * 2 * D + D : tab + (size_t)kk * 2 * D + D;
-            adjoint_step<Real, D>(a.c, a.lc, xd, X[s], lam);
+            adjoint_step<Real, D, CoefInLds<Real, D>::adjoint, CB>(a.c, a.lc, xd, X[s], lam);
             if (DUMP) {
                 dump_state(a, a.dX, kk, m, X[s]);
                 dump_state(a, a.dlam, kk, m, lam);
@@ -307,7 +307,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<Real, D>& a, const Re
 // a time: begin() sets lam_N and loads the first tile, full_tile() sweeps one
 // full tile while the next one loads, tail() sweeps what is left (down to step
 // 0).  Steps are reduced into partial column g.
-template <typename Real, int D, bool DUMP>
+template <typename Real, int D, bool DUMP, bool CB>
 struct StoredAdjoint {
     static constexpr int S = StepReducer<D, Real>::kSteps;
     StepReducer<D, Real> red;
@@ -355,7 +355,7 @@ struct StoredAdjoint {
 
     // Sweeps the full tile in cur and moves to the next one.
     __device__ __forceinline__ void sweep(const SweepArgs<Real, D>& a, const Real* __restrict__ tab) {
-        sweep_tile<Real, D, DUMP, true>(a, tab, k, cur, lam, act, m, red);
+        sweep_tile<Real, D, DUMP, true, CB>(a, tab, k, cur, lam, act, m, red);
         red.flush_tile(k, S, a.part, a.nblk);
         k -= S;
     }
@@ -383,13 +383,13 @@ struct StoredAdjoint {
 
     __device__ __forceinline__ void tail(const SweepArgs<Real, D>& a, const Real* __restrict__ tab) {
         if (k >= 0) {
-            sweep_tile<Real, D, DUMP, false>(a, tab, k, cur, lam, act, m, red);
+            sweep_tile<Real, D, DUMP, false, CB>(a, tab, k, cur, lam, act, m, red);
             red.flush_tile(k, k + 1, a.part, a.nblk);
         }
     }
 };
 
-template <typename Real, int D, bool DUMP>
+template <typename Real, int D, bool DUMP, bool CB>
 __global__ void __launch_bounds__(kThreads)
 k_adjoint_stored(SweepArgs<Real, D> a, const Real* __restrict__ tab) {
     if (gate_closed(a.gate))
@@ -397,7 +397,7 @@ k_adjoint_stored(SweepArgs<Real, D> a, const Real* __restrict__ tab) {
     __shared__ Real tile[StepReducer<D, Real>::kRows][kThreads];
     __shared__ Coef<Real, D> sc;
     stage_coef<CoefInLds<Real, D>::adjoint>(a, &sc);
-    StoredAdjoint<Real, D, DUMP> b;
+    StoredAdjoint<Real, D, DUMP, CB> b;
     b.start(a, tile, blockIdx.x);
     b.load(a);
     while (b.full()) {
@@ -414,7 +414,7 @@ k_adjoint_stored(SweepArgs<Real, D> a, const Real* __restrict__ tab) {
 // others are in their HBM-bound backward phase, and the two overlap on the
 // device.  Every value is computed exactly as by k_forward followed by
 // k_adjoint_stored.
-template <typename Real, int D>
+template <typename Real, int D, bool CB>
 __global__ void __launch_bounds__(kThreads)
 k_cost_grad_stored(SweepArgs<Real, D> a, const Real* __restrict__ tab, double* __restrict__ cpart) {
     if (gate_closed(a.gate))
@@ -424,14 +424,14 @@ k_cost_grad_stored(SweepArgs<Real, D> a, const Real* __restrict__ tab, double* _
     __shared__ Coef<Real, D> sc;
     stage_coef<CoefInLds<Real, D>::any>(a, &sc);
     {
-        ForwardSweep<Real, D, FWD_STORE> f;
+        ForwardSweep<Real, D, FWD_STORE, CB> f;
         f.begin(a, blockIdx.x);
         for (int k = 0; k < a.N; ++k)
             f.step(a, tab, k);
         f.finish(a, cpart, sh, blockIdx.x);
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-    StoredAdjoint<Real, D, false> b;
+    StoredAdjoint<Real, D, false, CB> b;
     b.start(a, tile, blockIdx.x);
     b.load(a);
     while (b.full()) {
@@ -447,7 +447,7 @@ k_cost_grad_stored(SweepArgs<Real, D> a, const Real* __restrict__ tab, double* _
 // the sub-segment starts (at most SMAX of them) in registers, then each
 // sub-segment, last first, is regenerated into an R-entry register buffer and
 // swept backwards.
-template <typename Real, int D, int R, int SMAX>
+template <typename Real, int D, int R, int SMAX, bool CB>
 __global__ void __launch_bounds__(kThreads)
 k_adjoint_recompute(SweepArgs<Real, D> a, const Real* __restrict__ tab) {
     constexpr int S = StepReducer<D, Real>::kSteps;
@@ -494,7 +494,7 @@ k_adjoint_recompute(SweepArgs<Real, D> a, const Real* __restrict__ tab) {
             for (int k = s0 + (s - 1) * R; k < s0 + s * R; ++k) {
                 StepDraws<Real, D> z;
                 draws<Real, D>((uint32_t)m, (uint32_t)k, a.iter, a.key0, a.key1, a.thr, z);
-                euler_step<Real, D>(a.c, a.lc, tab + (size_t)k * 2 * D, X, z);
+                euler_step<Real, D, CB>(a.c, a.lc, tab + (size_t)k * 2 * D, X, z);
             }
 #pragma unroll
             for (int t = 1; t < SMAX; ++t)
@@ -524,7 +524,7 @@ k_adjoint_recompute(SweepArgs<Real, D> a, const Real* __restrict__ tab) {
                         buf[r][i] = buf[r - 1][i];
                     StepDraws<Real, D> z;
                     draws<Real, D>((uint32_t)m, (uint32_t)k, a.iter, a.key0, a.key1, a.thr, z);
-                    euler_step<Real, D>(a.c, a.lc, tab + (size_t)k * 2 * D, buf[r], z);
+                    euler_step<Real, D, CB>(a.c, a.lc, tab + (size_t)k * 2 * D, buf[r], z);
                 }
             }
             // Backward over the sub-segment in chunks of one reducer tile
@@ -547,7 +547,8 @@ k_adjoint_recompute(SweepArgs<Real, D> a, const Real* __restrict__ tab) {
                             v[c] = act ? lam[c] : (Real)0;
                         red.put(top - k, v);
                         if (k >= 1) {
-                            adjoint_step<Real, D>(a.c, a.lc, tab + (size_t)k * 2 * D + D, buf[r], lam);
+                            adjoint_step<Real, D, CoefInLds<Real, D>::adjoint, CB>(
+                                a.c, a.lc, tab + (size_t)k * 2 * D + D, buf[r], lam);
                             dump_state(a, a.dX, k, m, buf[r]);
                             dump_state(a, a.dlam, k, m, lam);
                         }
@@ -630,7 +631,7 @@ __device__ __forceinline__ void seg_store(Real* __restrict__ row, int d, const R
             row[c * kThreads + threadIdx.x] = X[c];
 }
 
-template <typename Real, int D, bool DUMP>
+template <typename Real, int D, bool DUMP, bool CB>
 __global__ void __launch_bounds__(kThreads, sizeof(Real) == 4 ? 4 : 1)
 k_adjoint_segments(SweepArgs<Real, D> a, const Real* __restrict__ tab, Real* __restrict__ scratch) {
     constexpr int S = StepReducer<D, Real>::kSteps;
@@ -683,7 +684,7 @@ k_adjoint_segments(SweepArgs<Real, D> a, const Real* __restrict__ tab, Real* __r
                 for (int k = s0; k < s1 - 1; ++k) {
                     StepDraws<Real, D> z;
                     draws<Real, D>((uint32_t)m, (uint32_t)k, a.iter, a.key0, a.key1, a.thr, z);
-                    euler_step<Real, D>(a.c, a.lc, tab + (size_t)k * 2 * D, X, z);
+                    euler_step<Real, D, CB>(a.c, a.lc, tab + (size_t)k * 2 * D, X, z);
                     seg_store<Real, D>(row, a.d, X);
                     row += cl.stride;
                 }
@@ -708,7 +709,7 @@ k_adjoint_segments(SweepArgs<Real, D> a, const Real* __restrict__ tab, Real* __r
                             v[c] = act ? lam[c] : (Real)0;
                         red.put(s, v);
                         if (kk >= 1) {
-                            adjoint_step<Real, D, CoefInLds<Real, D>::any>(
+                            adjoint_step<Real, D, CoefInLds<Real, D>::any, CB>(
                                 a.c, a.lc, tab + (size_t)kk * 2 * D + D, cur[s], lam);
                             if (DUMP) {
                                 dump_state(a, a.dX, kk, m, cur[s]);
@@ -1045,35 +1046,43 @@ hipError_t launch_forward(const HostProblem& p, const HostRun& r, const void* ta
                           int fwd_mode, double* cpart, const WsHeader* hdr, hipStream_t st,
                           Gate gate) {
     const unsigned nb = (unsigned)r.nblk;
-#define JD_FWD(T, DD)                                                                               \
+#define JD_FWD_CB(T, DD, CB)                                                                        \
     do {                                                                                            \
         SweepArgs<T, DD> a = make_args<T, DD>(p, r);                                                \
         a.gate = gate;                                                                              \
         a.traj = traj;                                                                              \
         a.thr = &hdr->poisson;                                                                      \
         if (fwd_mode == FWD_STORE)                                                                  \
-            hipLaunchKernelGGL((k_forward<T, DD, FWD_STORE>), dim3(nb), dim3(kThreads), 0, st, a,     \
-                               (const T*)tab, cpart);                                               \
+            hipLaunchKernelGGL((k_forward<T, DD, FWD_STORE, CB>), dim3(nb), dim3(kThreads), 0, st,  \
+                               a, (const T*)tab, cpart);                                            \
         else if (fwd_mode == FWD_CKPT)                                                              \
-            hipLaunchKernelGGL((k_forward<T, DD, FWD_CKPT>), dim3(nb), dim3(kThreads), 0, st, a,      \
-                               (const T*)tab, cpart);                                               \
+            hipLaunchKernelGGL((k_forward<T, DD, FWD_CKPT, CB>), dim3(nb), dim3(kThreads), 0, st,   \
+                               a, (const T*)tab, cpart);                                            \
         else                                                                                        \
-            hipLaunchKernelGGL((k_forward<T, DD, FWD_COST>), dim3(nb), dim3(kThreads), 0, st, a,      \
-                               (const T*)tab, cpart);                                               \
+            hipLaunchKernelGGL((k_forward<T, DD, FWD_COST, CB>), dim3(nb), dim3(kThreads), 0, st,   \
+                               a, (const T*)tab, cpart);                                            \
+    } while (0)
+#define JD_FWD(T, DD)                                                                               \
+    do {                                                                                            \
+        if (p.cubic != 0.0)                                                                         \
+            JD_FWD_CB(T, DD, true);                                                                 \
+        else                                                                                        \
+            JD_FWD_CB(T, DD, false);                                                                \
     } while (0)
     JD_DISPATCH(r.prec, p.D, JD_FWD);
 #undef JD_FWD
+#undef JD_FWD_CB
     return hipGetLastError();
 }
 
 // Blocks of the persistent segment kernel: as many as are resident at once on
 // the current device (its compute units times the kernel's blocks per unit),
 // at most the scratch regions of the workspace.
-template <typename Real, int D, bool DUMP>
+template <typename Real, int D, bool DUMP, bool CB>
 static unsigned seg_grid_for(const HostRun& r) {
     static const int per_cu = [] {
         int n = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_adjoint_segments<Real, D, DUMP>,
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_adjoint_segments<Real, D, DUMP, CB>,
                                                          kThreads, 0) != hipSuccess || n < 1)
             n = 1;
         return n;
@@ -1092,35 +1101,43 @@ hipError_t launch_adjoint(const HostProblem& p, const HostRun& r, const void* ta
                           Gate gate) {
     const unsigned nb = (unsigned)r.nblk;
     const bool segments = r.mode == JD_RECOMPUTE && recompute_uses_segments(r.prec, p.D, r.K);
-#define JD_ADJ(T, DD)                                                                             \
+#define JD_ADJ_CB(T, DD, CB)                                                                      \
     do {                                                                                          \
-        const unsigned seg_grid =                                                                 \
-            !segments ? 0u                                                                        \
-            : r.dump != nullptr ? seg_grid_for<T, DD, true>(r) : seg_grid_for<T, DD, false>(r);   \
+        const unsigned seg_grid = !segments ? 0u                                                  \
+                                  : r.dump != nullptr ? seg_grid_for<T, DD, true, CB>(r)          \
+                                                      : seg_grid_for<T, DD, false, CB>(r);        \
         SweepArgs<T, DD> a = make_args<T, DD>(p, r);                                              \
         a.gate = gate;                                                                            \
         a.traj = const_cast<void*>(traj);                                                         \
         a.part = apart;                                                                           \
         a.thr = &hdr->poisson;                                                                    \
         if (segments && r.dump != nullptr)                                                        \
-            hipLaunchKernelGGL((k_adjoint_segments<T, DD, true>), dim3(seg_grid), dim3(kThreads), \
-                               0, st, a, (const T*)tab, (T*)seg);                                 \
+            hipLaunchKernelGGL((k_adjoint_segments<T, DD, true, CB>), dim3(seg_grid),             \
+                               dim3(kThreads), 0, st, a, (const T*)tab, (T*)seg);                 \
         else if (segments)                                                                        \
-            hipLaunchKernelGGL((k_adjoint_segments<T, DD, false>), dim3(seg_grid),                \
+            hipLaunchKernelGGL((k_adjoint_segments<T, DD, false, CB>), dim3(seg_grid),            \
                                dim3(kThreads), 0, st, a, (const T*)tab, (T*)seg);                 \
         else if (r.mode == JD_RECOMPUTE)                                                          \
             hipLaunchKernelGGL((k_adjoint_recompute<T, DD, RecomputeShape<T, DD>::R,              \
-                                                    RecomputeShape<T, DD>::S>),                   \
+                                                    RecomputeShape<T, DD>::S, CB>),               \
                                dim3(nb), dim3(kThreads), 0, st, a, (const T*)tab);                \
         else if (r.dump != nullptr)                                                               \
-            hipLaunchKernelGGL((k_adjoint_stored<T, DD, true>), dim3(nb), dim3(kThreads), 0, st,  \
-                               a, (const T*)tab);                                                 \
+            hipLaunchKernelGGL((k_adjoint_stored<T, DD, true, CB>), dim3(nb), dim3(kThreads), 0,  \
+                               st, a, (const T*)tab);                                             \
         else                                                                                      \
-            hipLaunchKernelGGL((k_adjoint_stored<T, DD, false>), dim3(nb), dim3(kThreads), 0, st, \
-                               a, (const T*)tab);                                                 \
+            hipLaunchKernelGGL((k_adjoint_stored<T, DD, false, CB>), dim3(nb), dim3(kThreads), 0, \
+                               st, a, (const T*)tab);                                             \
+    } while (0)
+#define JD_ADJ(T, DD)                                                                             \
+    do {                                                                                          \
+        if (p.cubic != 0.0)                                                                       \
+            JD_ADJ_CB(T, DD, true);                                                               \
+        else                                                                                      \
+            JD_ADJ_CB(T, DD, false);                                                              \
     } while (0)
     JD_DISPATCH(r.prec, p.D, JD_ADJ);
 #undef JD_ADJ
+#undef JD_ADJ_CB
     return hipGetLastError();
 }
 
@@ -1135,8 +1152,12 @@ hipError_t launch_cost_grad_stored(const HostProblem& p, const HostRun& r, const
         a.traj = traj;                                                                            \
         a.part = apart;                                                                           \
         a.thr = &hdr->poisson;                                                                    \
-        hipLaunchKernelGGL((k_cost_grad_stored<T, DD>), dim3(nb), dim3(kThreads), 0, st, a,       \
-                           (const T*)tab, cpart);                                                 \
+        if (p.cubic != 0.0)                                                                       \
+            hipLaunchKernelGGL((k_cost_grad_stored<T, DD, true>), dim3(nb), dim3(kThreads), 0,    \
+                               st, a, (const T*)tab, cpart);                                      \
+        else                                                                                      \
+            hipLaunchKernelGGL((k_cost_grad_stored<T, DD, false>), dim3(nb), dim3(kThreads), 0,   \
+                               st, a, (const T*)tab, cpart);                                      \
     } while (0)
     JD_DISPATCH(r.prec, p.D, JD_CG);
 #undef JD_CG
