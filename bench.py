@@ -293,13 +293,17 @@ def configs_section(args, time_calls, dev):
     for mode, K in (("store", 0), ("recompute", w.K)):
         e = B.Engine(p, M=w.M, seed=w.seed, precision="fp32", mode=mode, K=K, device=dev)
         e.optimize(torch.zeros((p.N, 1), dtype=torch.float64, device=dev), n_max=1)  # warm
-        u = torch.zeros((p.N, 1), dtype=torch.float64, device=dev)
-        wall, (_, logs) = sync_wall(lambda: e.optimize(u, n_max=w.iters))
+        walls = []
+        for _ in range(3):  # best of 3, each from u = 0 (the same iterates every time)
+            u = torch.zeros((p.N, 1), dtype=torch.float64, device=dev)
+            wall, (_, logs) = sync_wall(lambda: e.optimize(u, n_max=w.iters))
+            walls.append(wall)
+        wall = min(walls)
         trials = sum(1 + l["backtracks"] for l in logs)
         finals[mode] = u.cpu().numpy()
         # swept path-steps: each iteration's forward + adjoint and every trial's forward
         res[f"{mode}{'_K' + str(K) if K else ''}"] = {
-            "wall_s": wall, "iterations": len(logs), "trials": trials,
+            "wall_s_best_of_3": wall, "iterations": len(logs), "trials": trials,
             "ms_per_iteration": wall / len(logs) * 1e3,
             "gradient_path_steps_per_s": len(logs) * w.M * p.N / wall,
             "J_first": logs[0]["J"], "J_last_new": logs[-1]["J_new"]}
