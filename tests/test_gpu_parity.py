@@ -289,3 +289,27 @@ def test_rate_at_the_abi_limit(dev, precision):
         assert e.check_finite()
         assert rel_err(float(J), J_ref) <= tol["J"]
         assert_grad(g.cpu().numpy(), g_ref, s_ref, tol["g"], f"{mode}")
+
+
+@pytest.mark.parametrize("d,mode,K", [(1, "store", 0), (1, "recompute", 16), (2, "store", 0),
+                                      (8, "store", 0), (8, "recompute", 64)])
+def test_sweeps_without_cubic_term_are_bitwise_the_term_times_zero(dev, d, mode, K):
+    """The sweeps are compiled without the cubic term when c3 = 0.  A cubic
+    coefficient of 1e-300 is non-zero on the host, so it takes the
+    instantiation with the term, but it rounds to 0 in FP32: the term then
+    adds -0 * X^3, and every bit of J, g and the paths must equal the run
+    without it."""
+    say("cubic term compiled out", d, mode, K)
+    base = wl.general_problem(d, 96, seed=40 + d, cubic=0.0, lam=3.0)
+    tiny = dataclasses.replace(base, cubic=1e-300)
+    out = []
+    for p in (base, tiny):
+        eng = B.Engine(p, M=700, seed=3, precision="fp32", mode=mode, K=K, device=dev)
+        dp, dd = eng.path_dump(0, 700)
+        J, g = eng.cost_grad(np.zeros((p.N, p.d)), it=2)
+        eng.forward(np.zeros((p.N, p.d)), it=2, dump=dp)
+        eng.adjoint(np.zeros((p.N, p.d)), it=2, dump=dp)
+        out.append((float(J), g.cpu().numpy(), dd["X"].cpu().numpy(), dd["lam"].cpu().numpy()))
+    assert out[0][0] == out[1][0]
+    for a, b in zip(out[0][1:], out[1][1:]):
+        np.testing.assert_array_equal(a, b)
