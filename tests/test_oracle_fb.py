@@ -308,6 +308,15 @@ def test_surrogate_fit_matches_the_ensemble():
         assert abs(a[c] - aa) <= 1e-12 * (abs(aa) + abs(bb) * p.T)
 
 
+def test_surrogate_fit_two_points_is_their_line():
+    """N = 1: the least-squares line through two points passes through both."""
+    p = small_problem(N=1, T=0.5, b1=0.3, b2=0.4, svar="fit")
+    mu = wl.random_feedback_control(p, 2, 1.0)
+    var, a, b = ref.fb_surrogate_fit(p, 4000, 3, 1, mu)
+    np.testing.assert_allclose(a, var[0], rtol=1e-13, atol=1e-16)
+    np.testing.assert_allclose(b, (var[1] - var[0]) / p.dt, rtol=1e-12, atol=1e-15)
+
+
 def test_surrogate_fit_velocity_random_walk():
     """Closed form: without the spring, control and position noise, and with
     gamma = 1, the velocity is a random walk with Gaussian steps and jumps that
