@@ -266,24 +266,35 @@ def configs_section(args, time_calls, dev):
         torch.cuda.synchronize()
         return time.perf_counter() - t0, r
 
-    # c1: 10^4 paths x 100 steps, FP64, 20 iterations from u = 0
+    # c1: 10^4 paths x 100 steps, FP64, 20 iterations from u = 0; the draws
+    # from the iteration's noise table (the automatic choice at this size) and
+    # computed in the sweeps, which give bitwise the same iterates
     w = wl.config("c1")
     p = w.problem
-    e = B.Engine(p, M=w.M, seed=w.seed, precision="fp64", device=dev)
-    e.optimize(torch.zeros((p.N, 1), dtype=torch.float64, device=dev), n_max=2)  # warm
-    walls = []
-    for _ in range(3):
-        u = torch.zeros((p.N, 1), dtype=torch.float64, device=dev)
-        wall, (_, logs) = sync_wall(lambda: e.optimize(u, n_max=w.iters))
-        walls.append(wall)
+    c1 = {}
+    for noise in ("table", "inline"):
+        e = B.Engine(p, M=w.M, seed=w.seed, precision="fp64", device=dev, noise=noise)
+        e.optimize(torch.zeros((p.N, 1), dtype=torch.float64, device=dev), n_max=2)  # warm
+        walls = []
+        for _ in range(3):
+            u = torch.zeros((p.N, 1), dtype=torch.float64, device=dev)
+            wall, (_, logs) = sync_wall(lambda: e.optimize(u, n_max=w.iters))
+            walls.append(wall)
+        c1[noise] = (min(walls), logs, u.cpu().numpy())
+        del e
+    wall, logs, u_tab = c1["table"]
     trials = sum(1 + l["backtracks"] for l in logs)
-    out["c1"] = {"form": "FP64, 20 gradient iterations (jd_optimize, line search on the device)",
-                 "wall_s_best_of_3": min(walls), "ms_per_iteration": min(walls) / w.iters * 1e3,
+    out["c1"] = {"form": "FP64, 20 gradient iterations (jd_optimize, line search on the device), "
+                         "draws from the per-iteration noise table",
+                 "wall_s_best_of_3": wall, "ms_per_iteration": wall / w.iters * 1e3,
+                 "wall_s_inline_draws_best_of_3": c1["inline"][0],
+                 "inline_bitwise_equal": bool(logs == c1["inline"][1]
+                                              and np.array_equal(u_tab, c1["inline"][2])),
                  "iterations": len(logs), "trials": trials, "J_first": logs[0]["J"],
                  "J_last_new": logs[-1]["J_new"],
                  "note": "10^4 paths = 40 blocks of 256: launch- and latency-bound, no roofline"}
-    log(f"c1: {min(walls) * 1e3:.2f} ms for {w.iters} iterations")
-    del e
+    log(f"c1: {wall * 1e3:.2f} ms for {w.iters} iterations "
+        f"({c1['inline'][0] * 1e3:.2f} ms with the draws in the sweeps)")
 
     # c2: 50 iterations, stored and K = 32 (bitwise the same iterates)
     w = wl.config("c2")
@@ -341,7 +352,7 @@ def configs_section(args, time_calls, dev):
                 rec["roofline"] = composite_roofline(ph, MN, percentile(t, 50) * 1e-3)
             elif mode == "store":
                 if name == "c3":  # counted on c3's linear drift
-                    rec["forward_issue"] = fp64_counted("jd::k_forward<double, 8, 1, false>", MN,
+                    rec["forward_issue"] = fp64_counted("jd::k_forward<double, 8, 1, false, false>", MN,
                                                         percentile(tf, 50) * 1e-3)
                 # the stored adjoint reads z_k (8 FP64) per path-step: HBM-bound
                 ta_s = percentile(ta, 50) * 1e-3
@@ -881,7 +892,7 @@ def main():
         forms["speedup_fp32_over_fp64_p50"] = (percentile(res["fp64_store_ms"], 50) /
                                                percentile(res["fp32_store_ms"], 50))
         # the fused FP64 kernel is >99% of the call
-        forms["fp64_store"]["issue"] = fp64_counted("jd::k_cost_grad_stored<double, 1, false>", M * N,
+        forms["fp64_store"]["issue"] = fp64_counted("jd::k_cost_grad_stored<double, 1, false, false>", M * N,
                                                     percentile(res["fp64_store_ms"], 50) * 1e-3)
     # average launch durations over the event-timed calls (the fused kernel is
     # >99% of a jd_cost_grad call; the table and finalize kernels take ~20 us)
@@ -897,7 +908,7 @@ def main():
                 "achieved": slots / t_cg / 1e12, "peak": VALU_PEAK_SLOTS / 1e12,
                 "unit": "TOP/s (full-rate VALU lane-op slots)",
                 "frac": slots / t_cg / VALU_PEAK_SLOTS,
-                "traffic": profiled_traffic("jd::k_cost_grad_stored<float, 1, false>"),
+                "traffic": profiled_traffic("jd::k_cost_grad_stored<float, 1, false, false>"),
                 "slots_per_path_step": FWD_SLOTS_PER_PATH_STEP + ADJ_SLOTS_PER_PATH_STEP,
                 "kernel_ms": t_cg * 1e3,
                 "hbm_bytes_per_path_step": 8, "hbm_frac": 8.0 * M * N / t_cg / HBM_PEAK}
@@ -905,7 +916,7 @@ def main():
     separate = {
         "forward": {"kernel": "k_forward<float,1,store>", "bound": "alu", "kernel_ms": t_fwd * 1e3,
                     "achieved": fwd_slots / t_fwd / 1e12, "frac": fwd_slots / t_fwd / VALU_PEAK_SLOTS,
-                    "traffic": profiled_traffic("jd::k_forward<float, 1, 1, false>")},
+                    "traffic": profiled_traffic("jd::k_forward<float, 1, 1, false, false>")},
         "adjoint": {"kernel": "k_adjoint_stored<float,1>", "bound": "hbm", "kernel_ms": t_adj * 1e3,
                     "achieved": 4.0 * M * N / t_adj / 1e9, "unit": "GB/s",
                     "frac": 4.0 * M * N / t_adj / HBM_PEAK,

@@ -65,7 +65,7 @@
 extern "C" {
 #endif
 
-#define JD_VERSION 100
+#define JD_VERSION 101
 
 /* Error codes. */
 #define JD_OK 0
@@ -105,6 +105,20 @@ typedef struct jd_problem {
     const double* xd;        /* DEVICE, N*d FP64: x_d(t_k), row k */
 } jd_problem;
 
+/* Where the forward sweeps take the draws of a path-step from.  Every choice
+ * gives bitwise the same results; they differ in speed only.  A sweep runs one
+ * path per lane, so a run of few paths leaves most of the GPU idle and waits on
+ * the latency of each step's draw chain (Philox, Box-Muller, the Poisson
+ * count).  The table moves that chain into one launch over all path-steps per
+ * gradient iteration, which the line-search trials of the iteration reuse
+ * (they run on the iteration's draws). */
+#define JD_NOISE_AUTO 0   /* the table for M <= 65536 paths in FP64 and
+                             M <= 16384 in FP32 if it takes at most 1 GiB
+                             (N*d*2 values per path), inline otherwise */
+#define JD_NOISE_INLINE 1 /* each sweep computes its draws */
+#define JD_NOISE_TABLE 2  /* the table, whatever the size: the workspace grows by
+                             2*N*d*ceil(M/256)*256 values of the run precision */
+
 /* One Monte Carlo evaluation. */
 typedef struct jd_dump jd_dump;
 typedef struct jd_run {
@@ -115,6 +129,8 @@ typedef struct jd_run {
     int32_t mode;       /* JD_STORE or JD_RECOMPUTE */
     int32_t K;          /* checkpoint interval for JD_RECOMPUTE (1..N); ignored for JD_STORE */
     const jd_dump* dump;/* optional per-path diagnostics, NULL normally */
+    int32_t noise;      /* JD_NOISE_*; the feedback model (jd_feedback.h) checks the
+                           value and always draws in the sweep */
 } jd_run;
 
 /* Per-path diagnostics for paths [m0, m0+count) (DEVICE pointers, each may be

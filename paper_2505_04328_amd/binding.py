@@ -20,6 +20,7 @@ JD_OK, JD_EINVAL, JD_EWORKSPACE, JD_EHIP, JD_ENONFINITE, JD_ELINESEARCH, JD_EUNS
 JD_EAGAIN = -7
 JD_FP32, JD_FP64 = 0, 1
 JD_STORE, JD_RECOMPUTE, JD_SURROGATE = 0, 1, 2
+JD_NOISE_AUTO, JD_NOISE_INLINE, JD_NOISE_TABLE = 0, 1, 2
 
 EXPORTED = ["jd_version", "jd_strerror", "jd_workspace_bytes", "jd_traj_bytes", "jd_forward",
             "jd_adjoint", "jd_cost_grad", "jd_optimize", "jd_check_finite", "jd_draws",
@@ -50,7 +51,7 @@ class jd_dump(C.Structure):
 class jd_run(C.Structure):
     _fields_ = [("M", C.c_int64), ("seed", C.c_uint64), ("iter", C.c_uint32),
                 ("precision", C.c_int32), ("mode", C.c_int32), ("K", C.c_int32),
-                ("dump", C.POINTER(jd_dump))]
+                ("dump", C.POINTER(jd_dump)), ("noise", C.c_int32)]
 
 
 class jd_opt(C.Structure):
@@ -151,11 +152,15 @@ class Problem:
         return C.byref(self.st)
 
 
+NOISE = {"auto": JD_NOISE_AUTO, "inline": JD_NOISE_INLINE, "table": JD_NOISE_TABLE}
+
+
 def make_run(M: int, seed: int = 1, it: int = 0, precision: str = "fp32", mode: str = "store",
-             K: int = 0, dump: jd_dump | None = None) -> jd_run:
+             K: int = 0, dump: jd_dump | None = None, noise: str = "auto") -> jd_run:
     prec = {"fp32": JD_FP32, "fp64": JD_FP64}[precision]
     md = {"store": JD_STORE, "recompute": JD_RECOMPUTE, "surrogate": JD_SURROGATE}[mode]
-    return jd_run(M, seed, it, prec, md, K, C.pointer(dump) if dump is not None else None)
+    return jd_run(M, seed, it, prec, md, K, C.pointer(dump) if dump is not None else None,
+                  NOISE[noise])
 
 
 class Engine:
@@ -163,14 +168,15 @@ class Engine:
     (workspace and trajectory/checkpoint buffer) allocated by torch."""
 
     def __init__(self, problem, M: int, seed: int = 1, precision: str = "fp32",
-                 mode: str = "store", K: int = 0, device="cuda:0"):
+                 mode: str = "store", K: int = 0, device="cuda:0", noise: str = "auto"):
         torch = _torch()
         self.prob = problem if isinstance(problem, Problem) else Problem(problem, device)
         self.p = self.prob.p
         self.M, self.seed, self.precision, self.mode, self.K = M, seed, precision, mode, K
+        self.noise = noise
         self.device = self.prob.device
         self.rdtype = torch.float32 if precision == "fp32" else torch.float64
-        run = make_run(M, seed, 0, precision, mode, K)
+        run = make_run(M, seed, 0, precision, mode, K, noise=noise)
         L = lib()
         self.ws_bytes = L.jd_workspace_bytes(self.prob.ref, C.byref(run))
         self.traj_bytes = L.jd_traj_bytes(self.prob.ref, C.byref(run))
@@ -182,7 +188,8 @@ class Engine:
         self.traj = torch.empty(self.traj_bytes // esz, dtype=self.rdtype, device=self.device)
 
     def run(self, it: int = 0, dump: jd_dump | None = None) -> jd_run:
-        return make_run(self.M, self.seed, it, self.precision, self.mode, self.K, dump)
+        return make_run(self.M, self.seed, it, self.precision, self.mode, self.K, dump,
+                        self.noise)
 
     def _u(self, u):
         torch = _torch()

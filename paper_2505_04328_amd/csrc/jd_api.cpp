@@ -89,6 +89,9 @@ int prepare(const jd_problem* prob, const jd_run* run, HostProblem& p, HostRun& 
         if (dp->m0 < 0 || dp->count < 0 || dp->m0 + dp->count > run->M)
             return JD_EINVAL;
     }
+    if (run->noise != JD_NOISE_AUTO && run->noise != JD_NOISE_INLINE &&
+        run->noise != JD_NOISE_TABLE)
+        return JD_EINVAL;
 
     memset(&p, 0, sizeof(p));
     p.d = d;
@@ -123,9 +126,18 @@ int prepare(const jd_problem* prob, const jd_run* run, HostProblem& p, HostRun& 
     r.K = run->mode == JD_RECOMPUTE ? run->K : 0;
     r.nblk = (int)((run->M + kBlock - 1) / kBlock);
     r.dump = run->dump;
+    r.noise = false;
+    if (run->noise == JD_NOISE_TABLE)
+        r.noise = true;
+    else if (run->noise == JD_NOISE_AUTO)
+        r.noise = r.nblk <= noise_max_blocks(r.prec) && noise_bytes(p, r) <= kNoiseMaxBytes;
     if (r.mode == JD_RECOMPUTE && !recompute_supported(p, r))
         return JD_EUNSUPPORTED;
     return JD_OK;
+}
+
+size_t noise_bytes(const HostProblem& p, const HostRun& r) {
+    return (size_t)r.ldm * (size_t)p.N * 2 * (size_t)p.d * real_size(r.prec);
 }
 
 Layout layout(const HostProblem& p, const HostRun& r) {
@@ -147,6 +159,8 @@ Layout layout(const HostProblem& p, const HostRun& r) {
     off += round_up((size_t)p.N * p.d * sizeof(double), kAlign);
     L.seg = off;
     off += round_up(seg_scratch_bytes(p, r), kAlign);
+    L.noise = off;
+    off += r.noise ? round_up(noise_bytes(p, r), kAlign) : 0;
     L.total = off + kAlign;  // slack for aligning the caller's pointer
     return L;
 }
@@ -171,6 +185,7 @@ int bind_ws(const HostProblem& p, const HostRun& r, void* ws, size_t ws_bytes, W
     w.gbuf = (double*)(base + L.gbuf);
     w.ut = (double*)(base + L.ut);
     w.seg = base + L.seg;
+    w.noise = r.noise ? base + L.noise : nullptr;
     return JD_OK;
 }
 
@@ -180,7 +195,9 @@ int enqueue_forward(const HostProblem& p, const HostRun& r, const double* u, voi
                     const Ws& w, hipStream_t st) {
     const int fm = traj == nullptr ? FWD_COST : (r.mode == JD_RECOMPUTE ? FWD_CKPT : FWD_STORE);
     JD_TRY(launch_setup(p, r, u, w.tab, w.hdr, 1, st));
-    JD_TRY(launch_forward(p, r, w.tab, traj, fm, w.cpart, w.hdr, st));
+    if (w.noise)
+        JD_TRY(launch_noise(p, r, w.noise, w.hdr, st));
+    JD_TRY(launch_forward(p, r, w.tab, traj, fm, w.cpart, w.hdr, st, kNoGate, w.noise));
     JD_TRY(launch_finalize_cost(p, r, w.cpart, u, nullptr, J, w.hdr, 0, st));
     return JD_OK;
 }
@@ -188,14 +205,17 @@ int enqueue_forward(const HostProblem& p, const HostRun& r, const double* u, voi
 int enqueue_cost_grad(const HostProblem& p, const HostRun& r, const double* u, double* J,
                       double* g, void* traj, const Ws& w, hipStream_t st, Gate gate) {
     JD_TRY(launch_setup(p, r, u, w.tab, w.hdr, 1, st, gate));
+    if (w.noise)
+        JD_TRY(launch_noise(p, r, w.noise, w.hdr, st, gate));
     // One kernel (each block's forward, then its backward sweep) up to d = 4;
     // at d = 8 the separate kernels are faster (FP32 c3: 9.4 against 10.2 ms,
     // c4: 9.8 against 11.6 ms); the results are bitwise the same.
     if (r.mode == JD_STORE && r.dump == nullptr && p.D <= 4) {
-        JD_TRY(launch_cost_grad_stored(p, r, w.tab, traj, w.cpart, w.apart, w.hdr, st, gate));
+        JD_TRY(launch_cost_grad_stored(p, r, w.tab, traj, w.cpart, w.apart, w.hdr, st, gate,
+                                       w.noise));
     } else {
         const int fm = r.mode == JD_RECOMPUTE ? FWD_CKPT : FWD_STORE;
-        JD_TRY(launch_forward(p, r, w.tab, traj, fm, w.cpart, w.hdr, st, gate));
+        JD_TRY(launch_forward(p, r, w.tab, traj, fm, w.cpart, w.hdr, st, gate, w.noise));
         JD_TRY(launch_adjoint(p, r, w.tab, traj, w.apart, w.seg, w.hdr, st, gate));
     }
     JD_TRY(launch_finalize_grad(p, r, w.apart, u, g, w.hdr, st, gate));
@@ -208,7 +228,7 @@ int enqueue_trial(const HostProblem& p, const HostRun& r, const double* u, doubl
     const int nd = p.N * p.d;
     JD_TRY(launch_trial(u, w.gbuf, zeta, w.ut, nd, st, gate));
     JD_TRY(launch_setup(p, r, w.ut, w.tab, w.hdr, 0, st, gate));
-    JD_TRY(launch_forward(p, r, w.tab, nullptr, FWD_COST, w.cpart, w.hdr, st, gate));
+    JD_TRY(launch_forward(p, r, w.tab, nullptr, FWD_COST, w.cpart, w.hdr, st, gate, w.noise));
     JD_TRY(launch_finalize_cost(p, r, w.cpart, w.ut, nullptr, nullptr, w.hdr, 1, st, gate));
     return JD_OK;
 }

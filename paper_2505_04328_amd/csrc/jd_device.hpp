@@ -251,20 +251,15 @@ __device__ __forceinline__ double count_sqrt<double>(int n) {
     return sqrt((double)n);
 }
 
-// One Euler-Maruyama step with additive compound-Poisson jumps:
-//   X <- X + dt (A X - c3 X^3 + Bu_k) + sqrt(dt) s Z^W + n m_J + s_J sqrt(n) Z^J
-// bu = B u_k (per-step table row).  The jump term (with Z^J) is evaluated only
-// in waves where some lane jumps (lambda dt per path-step, so most waves skip
-// it) and applied only in the lanes with n > 0.  CUBIC = false compiles the
-// step of a drift without the cubic term (the kernels are instantiated for
-// both and launched by whether c3 is zero).
-template <typename Real, int D, bool CUBIC = true>
-__device__ __forceinline__ void euler_step(const Coef<Real, D>& c, const Coef<Real, D>* lc,
-                                           const Real* __restrict__ bu, Real* X,
-                                           const StepDraws<Real, D>& s) {
-    constexpr bool LDS = CoefInLds<Real, D>::forward;
-    const Coef<Real, D>& rows = coef_rows<LDS>(c, lc);
-    Real Y[D];
+// The deterministic part of one Euler-Maruyama step and the Brownian term:
+//   Y = X + dt (A X - c3 X^3 + Bu_k) + sqrt(dt) s Z^W
+// bu = B u_k (per-step table row), zw = Z^W.  CUBIC = false compiles the step
+// of a drift without the cubic term (the kernels are instantiated for both
+// and launched by whether c3 is zero).
+template <typename Real, int D, bool LDS, bool CUBIC>
+__device__ __forceinline__ void euler_drift(const Coef<Real, D>& c, const Coef<Real, D>& rows,
+                                            const Real* __restrict__ bu, const Real* X,
+                                            const Real* zw, Real* Y) {
 #pragma unroll
     for (int i = 0; i < D; ++i) {
         Real f = bu[i];
@@ -277,20 +272,60 @@ __device__ __forceinline__ void euler_step(const Coef<Real, D>& c, const Coef<Re
             f = fma(-c.c3, x3, f);
         }
         Real y = fma(c.dt, f, X[i]);
-        Y[i] = fma(c.sq[i], s.zw[i], y);
+        Y[i] = fma(c.sq[i], zw[i], y);
     }
+}
+
+// Jump increment of component i for a path-step with count n > 0:
+//   n m_J + s_J sqrt(n) Z^J.
+template <typename Real, int D>
+__device__ __forceinline__ Real jump_increment(const Coef<Real, D>& rows,
+                                               const StepDraws<Real, D>& s, int i) {
+    const Real fn = (Real)s.n;
+    const Real sn = count_sqrt<Real>(s.n);
+    return fma(rows.js[i] * sn, jump_normal(s, i), fn * rows.jm[i]);
+}
+
+// One Euler-Maruyama step with additive compound-Poisson jumps:
+//   X <- X + dt (A X - c3 X^3 + Bu_k) + sqrt(dt) s Z^W + n m_J + s_J sqrt(n) Z^J
+// The jump term (with Z^J) is evaluated only in waves where some lane jumps
+// (lambda dt per path-step, so most waves skip it) and applied only in the
+// lanes with n > 0.
+template <typename Real, int D, bool CUBIC = true>
+__device__ __forceinline__ void euler_step(const Coef<Real, D>& c, const Coef<Real, D>* lc,
+                                           const Real* __restrict__ bu, Real* X,
+                                           const StepDraws<Real, D>& s) {
+    constexpr bool LDS = CoefInLds<Real, D>::forward;
+    const Coef<Real, D>& rows = coef_rows<LDS>(c, lc);
+    Real Y[D];
+    euler_drift<Real, D, LDS, CUBIC>(c, rows, bu, X, s.zw, Y);
     if (__builtin_amdgcn_ballot_w64(s.n != 0)) {
-        const Real fn = (Real)s.n;
-        const Real sn = count_sqrt<Real>(s.n);
 #pragma unroll
         for (int i = 0; i < D; ++i) {
-            const Real yj = Y[i] + fma(rows.js[i] * sn, jump_normal(s, i), fn * rows.jm[i]);
+            const Real yj = Y[i] + jump_increment<Real, D>(rows, s, i);
             Y[i] = s.n != 0 ? yj : Y[i];
         }
     }
 #pragma unroll
     for (int i = 0; i < D; ++i)
         X[i] = Y[i];
+}
+
+// The same step with its noise read from a precomputed table: zw = Z^W and
+// jinc = the jump increment of the path-step, or -0.0 where the count is
+// zero (y + (-0.0) is y for every y, signed zeros and NaN included), so the
+// result equals euler_step's bit for bit.
+template <typename Real, int D, bool CUBIC = true>
+__device__ __forceinline__ void euler_step_noise(const Coef<Real, D>& c, const Coef<Real, D>* lc,
+                                                 const Real* __restrict__ bu, Real* X,
+                                                 const Real* zw, const Real* jinc) {
+    constexpr bool LDS = CoefInLds<Real, D>::forward;
+    const Coef<Real, D>& rows = coef_rows<LDS>(c, lc);
+    Real Y[D];
+    euler_drift<Real, D, LDS, CUBIC>(c, rows, bu, X, zw, Y);
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+        X[i] = Y[i] + jinc[i];
 }
 
 // One backward adjoint step at state X_k:

@@ -77,6 +77,10 @@ int fb_prepare(const jd_fb_problem* prob, const jd_run* run, FbHost& p, HostRun&
         if (dp->m0 < 0 || dp->count < 0 || dp->m0 + dp->count > particles)
             return JD_EINVAL;
     }
+    // the particle sweeps always draw inline; the field is only checked
+    if (run->noise != JD_NOISE_AUTO && run->noise != JD_NOISE_INLINE &&
+        run->noise != JD_NOISE_TABLE)
+        return JD_EINVAL;
 
     memset(&p, 0, sizeof(p));
     p.N = q.N;
@@ -135,6 +139,7 @@ int fb_prepare(const jd_fb_problem* prob, const jd_run* run, FbHost& p, HostRun&
     r.prec = run->precision;
     r.mode = run->mode;
     r.K = 0;
+    r.noise = false;
     r.dump = run->dump;
     if (q.np == 1) {
         r.nblk = (int)((particles + kBlock - 1) / kBlock);

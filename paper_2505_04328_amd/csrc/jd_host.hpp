@@ -20,6 +20,17 @@ namespace host {
 constexpr size_t kAlign = 256;
 constexpr int64_t kMaxPaths = (int64_t)1 << 31;
 
+// JD_NOISE_AUTO takes the noise table for grids of at most
+// noise_max_blocks(prec) blocks whose table takes at most kNoiseMaxBytes.
+// Measured on c1's model (100 steps, 20 iterations, MI355X): FP64 with the
+// table 2.13 / 3.37 ms at 10^4 / 65536 paths against 3.42 / 3.53 inline, and
+// 9.97 against 8.49 at 2^18; FP32 1.96 against 2.11 ms at 10^4 paths and
+// 2.21 against 2.15 at 3 10^4 (the table's HBM traffic, written once and
+// read by every sweep, outweighs the draws an FP32 sweep computes sooner).
+inline int noise_max_blocks(int prec) { return prec == JD_FP64 ? 256 : 64; }
+constexpr size_t kNoiseMaxBytes = (size_t)1 << 30;
+size_t noise_bytes(const HostProblem& p, const HostRun& r);
+
 size_t round_up(size_t x, size_t a);
 
 // Poisson(mu) inverse-CDF thresholds against a 32-bit word (32 entries).
@@ -32,7 +43,7 @@ int prepare(const jd_problem* prob, const jd_run* run, HostProblem& p, HostRun& 
 int validate_opt(const jd_opt* opt);
 
 struct Layout {
-    size_t hdr, ring, tab, cpart, apart, gbuf, ut, seg, total;
+    size_t hdr, ring, tab, cpart, apart, gbuf, ut, seg, noise, total;
 };
 Layout layout(const HostProblem& p, const HostRun& r);
 size_t traj_bytes(const HostProblem& p, const HostRun& r);
@@ -50,6 +61,7 @@ struct Ws {
     double* gbuf;
     double* ut;
     void* seg;  // segment scratch of the recompute adjoint (may be empty)
+    void* noise;  // the iteration's noise table, or nullptr (draws in the sweeps)
 };
 int bind_ws(const HostProblem& p, const HostRun& r, void* ws, size_t ws_bytes, Ws& w);
 bool aligned(const void* ptr, size_t a);
@@ -63,6 +75,8 @@ int enqueue_cost_grad(const HostProblem& p, const HostRun& r, const double* u, d
                       double* g, void* traj, const Ws& w, hipStream_t st, Gate gate = kNoGate);
 // Trial point u' = u - zeta g (g in the workspace) and its cost-only forward
 // into the header's J_trial, all under `gate`; the Armijo test is separate.
+// With the noise table it reads the table that enqueue_cost_grad of the same
+// iteration (r.iter) wrote into the workspace.
 int enqueue_trial(const HostProblem& p, const HostRun& r, const double* u, double zeta,
                   const Ws& w, hipStream_t st, Gate gate);
 

@@ -2,7 +2,9 @@
 //
 //  k_table            per-step table: B u_k and x_d(t_k) in the path precision
 //  k_forward          forward Euler-Maruyama sweep, one path per lane, draws in
-//                     registers, FP64 path cost, trajectory or checkpoint store
+//                     registers (or read from the noise table), FP64 path cost,
+//                     trajectory or checkpoint store
+//  k_noise            the draws of one iteration as a table, for small grids
 //  k_adjoint_stored   backward adjoint sweep over the stored trajectory
 //  k_cost_grad_stored forward then backward sweep in one launch, per block
 //  k_adjoint_recompute backward adjoint sweep regenerating each checkpoint
@@ -177,6 +179,21 @@ struct ForwardSweep {
         StepDraws<Real, D> z;
         draws<Real, D>((uint32_t)m, (uint32_t)k, a.iter, a.key0, a.key1, a.thr, z);
         euler_step<Real, D, CB>(a.c, a.lc, trow, X, z);
+        put(a, k);
+    }
+
+    // Step k with its noise from the iteration's noise table.
+    __device__ __forceinline__ void step_noise(const SweepArgs<Real, D>& a,
+                                               const Real* __restrict__ tab, int k, const Real* zw,
+                                               const Real* jinc) {
+        const Real* trow = tab + (size_t)k * 2 * D;
+        acc += (double)sq_dist<Real, D>(X, trow + D);
+        euler_step_noise<Real, D, CB>(a.c, a.lc, trow, X, zw, jinc);
+        put(a, k);
+    }
+
+    // Stores X_{k+1} where the mode keeps it.
+    __device__ __forceinline__ void put(const SweepArgs<Real, D>& a, int k) {
         if (MODE == FWD_STORE) {
             store_row<Real, D>(row, a.d, X);
             row += (int64_t)a.d * kThreads;
@@ -206,9 +223,102 @@ struct ForwardSweep {
     }
 };
 
-template <typename Real, int D, int MODE, bool CB>
+// ---------------------------------------------------------------------------
+// Noise table of one gradient iteration, for grids that leave most of the
+// chip idle.  The draws of a path-step depend only on (path, step, iteration
+// word, seed); a sweep of a few blocks spends its time on the latency of the
+// per-step draw chain, which nothing else hides.  There one launch over all
+// path-steps computes the draws, and every forward sweep of the iteration (the
+// gradient's and its line-search trials', which reuse the iteration's draws)
+// reads them.  Layout, blocked by the 256 paths of a sweep block like the
+// trajectory: group g owns N steps of 2d rows of 256 elements; row (k*2d + c)
+// holds Z^W_c of step k and row (k*2d + d + c) the jump increment of component
+// c (-0.0 where the count is zero).  Lanes past the last path get their
+// draws like in a sweep.
+template <typename Real, int D>
 __global__ void __launch_bounds__(kThreads)
-k_forward(SweepArgs<Real, D> a, const Real* __restrict__ tab, double* __restrict__ cpart) {
+k_noise(SweepArgs<Real, D> a, Real* __restrict__ noise) {
+    if (gate_closed(a.gate))
+        return;
+    const int64_t nb = (int64_t)a.nblk * a.N;
+    const int64_t rows = 2 * (int64_t)a.d * kThreads;
+    for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
+        const int64_t g = b / a.N;
+        const int k = (int)(b - g * a.N);
+        const int64_t m = g * kThreads + threadIdx.x;
+        StepDraws<Real, D> z;
+        draws<Real, D>((uint32_t)m, (uint32_t)k, a.iter, a.key0, a.key1, a.thr, z);
+        Real* out = noise + b * rows + threadIdx.x;  // b = g N + k: step k of group g
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            if (i < a.d) {
+                out[i * kThreads] = z.zw[i];
+                out[(a.d + i) * kThreads] =
+                    z.n != 0 ? jump_increment<Real, D>(a.c, z, i) : (Real)-0.0;
+            }
+        }
+    }
+}
+
+// P consecutive steps of the noise table in registers (P D = 16 values of
+// each kind).  Padded components read component d-1 and take Z^W = 0 and
+// increment -0.0, which leave them zero as the drawn values do (their noise
+// scales are zero).
+template <typename Real, int D>
+struct NoiseTile {
+    static constexpr int P = 16 / D;
+    Real zw[P][D];
+    Real ji[P][D];
+
+    // Steps k0 .. k0+P-1 (clamped to N-1) of the block's region.
+    __device__ __forceinline__ void load(const Real* __restrict__ region, int d, int N, int k0) {
+        const int64_t rows = 2 * (int64_t)d * kThreads;
+#pragma unroll
+        for (int s = 0; s < P; ++s) {
+            const int kk = k0 + s < N ? k0 + s : N - 1;
+            const Real* r = region + kk * rows + threadIdx.x;
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                const int ce = c < d ? c : d - 1;
+                const Real z = r[ce * kThreads];
+                const Real j = r[(d + ce) * kThreads];
+                zw[s][c] = c < d ? z : (Real)0;
+                ji[s][c] = c < d ? j : (Real)-0.0;
+            }
+        }
+    }
+};
+
+// All N steps of a forward sweep from the noise table: the next tile's loads
+// are issued before the current tile is swept.
+template <typename Real, int D, int MODE, bool CB>
+__device__ __forceinline__ void sweep_noise(ForwardSweep<Real, D, MODE, CB>& f,
+                                            const SweepArgs<Real, D>& a,
+                                            const Real* __restrict__ tab,
+                                            const Real* __restrict__ noise) {
+    constexpr int P = NoiseTile<Real, D>::P;
+    const Real* region = noise + (int64_t)blockIdx.x * a.N * 2 * a.d * kThreads;
+    NoiseTile<Real, D> cur, nxt;
+    cur.load(region, a.d, a.N, 0);
+    for (int k0 = 0;; k0 += P) {
+        const bool more = k0 + P < a.N;
+        if (more)
+            nxt.load(region, a.d, a.N, k0 + P);
+#pragma unroll
+        for (int s = 0; s < P; ++s)
+            if (k0 + s < a.N)
+                f.step_noise(a, tab, k0 + s, cur.zw[s], cur.ji[s]);
+        if (!more)
+            break;
+        cur = nxt;
+    }
+}
+
+// NOISE: the draws come from the iteration's noise table.
+template <typename Real, int D, int MODE, bool CB, bool NOISE>
+__global__ void __launch_bounds__(kThreads)
+k_forward(SweepArgs<Real, D> a, const Real* __restrict__ tab, double* __restrict__ cpart,
+          const Real* __restrict__ noise) {
     if (gate_closed(a.gate))
         return;
     __shared__ double sh[kThreads];
@@ -216,8 +326,12 @@ k_forward(SweepArgs<Real, D> a, const Real* __restrict__ tab, double* __restrict
     stage_coef<CoefInLds<Real, D>::forward>(a, &sc);
     ForwardSweep<Real, D, MODE, CB> f;
     f.begin(a, blockIdx.x);
-    for (int k = 0; k < a.N; ++k)
-        f.step(a, tab, k);
+    if constexpr (NOISE) {
+        sweep_noise<Real, D, MODE, CB>(f, a, tab, noise);
+    } else {
+        for (int k = 0; k < a.N; ++k)
+            f.step(a, tab, k);
+    }
     f.finish(a, cpart, sh, blockIdx.x);
 }
 
@@ -414,9 +528,10 @@ k_adjoint_stored(SweepArgs<Real, D> a, const Real* __restrict__ tab) {
 // others are in their HBM-bound backward phase, and the two overlap on the
 // device.  Every value is computed exactly as by k_forward followed by
 // k_adjoint_stored.
-template <typename Real, int D, bool CB>
+template <typename Real, int D, bool CB, bool NOISE>
 __global__ void __launch_bounds__(kThreads)
-k_cost_grad_stored(SweepArgs<Real, D> a, const Real* __restrict__ tab, double* __restrict__ cpart) {
+k_cost_grad_stored(SweepArgs<Real, D> a, const Real* __restrict__ tab, double* __restrict__ cpart,
+                   const Real* __restrict__ noise) {
     if (gate_closed(a.gate))
         return;
     __shared__ double sh[kThreads];
@@ -426,8 +541,12 @@ k_cost_grad_stored(SweepArgs<Real, D> a, const Real* __restrict__ tab, double* _
     {
         ForwardSweep<Real, D, FWD_STORE, CB> f;
         f.begin(a, blockIdx.x);
-        for (int k = 0; k < a.N; ++k)
-            f.step(a, tab, k);
+        if constexpr (NOISE) {
+            sweep_noise<Real, D, FWD_STORE, CB>(f, a, tab, noise);
+        } else {
+            for (int k = 0; k < a.N; ++k)
+                f.step(a, tab, k);
+        }
         f.finish(a, cpart, sh, blockIdx.x);
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
@@ -1046,23 +1165,30 @@ hipError_t launch_setup(const HostProblem& p, const HostRun& r, const double* u,
 
 hipError_t launch_forward(const HostProblem& p, const HostRun& r, const void* tab, void* traj,
                           int fwd_mode, double* cpart, const WsHeader* hdr, hipStream_t st,
-                          Gate gate) {
+                          Gate gate, const void* noise) {
     const unsigned nb = (unsigned)r.nblk;
-#define JD_FWD_CB(T, DD, CB)                                                                        \
+#define JD_FWD_NZ(T, DD, CB, NZ)                                                                    \
     do {                                                                                            \
         SweepArgs<T, DD> a = make_args<T, DD>(p, r);                                                \
         a.gate = gate;                                                                              \
         a.traj = traj;                                                                              \
         a.thr = &hdr->poisson;                                                                      \
         if (fwd_mode == FWD_STORE)                                                                  \
-            hipLaunchKernelGGL((k_forward<T, DD, FWD_STORE, CB>), dim3(nb), dim3(kThreads), 0, st,  \
-                               a, (const T*)tab, cpart);                                            \
+            hipLaunchKernelGGL((k_forward<T, DD, FWD_STORE, CB, NZ>), dim3(nb), dim3(kThreads), 0,  \
+                               st, a, (const T*)tab, cpart, (const T*)noise);                       \
         else if (fwd_mode == FWD_CKPT)                                                              \
-            hipLaunchKernelGGL((k_forward<T, DD, FWD_CKPT, CB>), dim3(nb), dim3(kThreads), 0, st,   \
-                               a, (const T*)tab, cpart);                                            \
+            hipLaunchKernelGGL((k_forward<T, DD, FWD_CKPT, CB, NZ>), dim3(nb), dim3(kThreads), 0,   \
+                               st, a, (const T*)tab, cpart, (const T*)noise);                       \
         else                                                                                        \
-            hipLaunchKernelGGL((k_forward<T, DD, FWD_COST, CB>), dim3(nb), dim3(kThreads), 0, st,   \
-                               a, (const T*)tab, cpart);                                            \
+            hipLaunchKernelGGL((k_forward<T, DD, FWD_COST, CB, NZ>), dim3(nb), dim3(kThreads), 0,   \
+                               st, a, (const T*)tab, cpart, (const T*)noise);                       \
+    } while (0)
+#define JD_FWD_CB(T, DD, CB)                                                                        \
+    do {                                                                                            \
+        if (noise != nullptr)                                                                       \
+            JD_FWD_NZ(T, DD, CB, true);                                                             \
+        else                                                                                        \
+            JD_FWD_NZ(T, DD, CB, false);                                                            \
     } while (0)
 #define JD_FWD(T, DD)                                                                               \
     do {                                                                                            \
@@ -1074,6 +1200,23 @@ hipError_t launch_forward(const HostProblem& p, const HostRun& r, const void* ta
     JD_DISPATCH(r.prec, p.D, JD_FWD);
 #undef JD_FWD
 #undef JD_FWD_CB
+#undef JD_FWD_NZ
+    return hipGetLastError();
+}
+
+hipError_t launch_noise(const HostProblem& p, const HostRun& r, void* noise, const WsHeader* hdr,
+                        hipStream_t st, Gate gate) {
+    const int64_t nb = (int64_t)r.nblk * p.N;
+    const unsigned grid = (unsigned)(nb < kNoiseGrid ? nb : kNoiseGrid);
+#define JD_NOISE(T, DD)                                                                           \
+    do {                                                                                          \
+        SweepArgs<T, DD> a = make_args<T, DD>(p, r);                                              \
+        a.gate = gate;                                                                            \
+        a.thr = &hdr->poisson;                                                                    \
+        hipLaunchKernelGGL((k_noise<T, DD>), dim3(grid), dim3(kThreads), 0, st, a, (T*)noise);    \
+    } while (0)
+    JD_DISPATCH(r.prec, p.D, JD_NOISE);
+#undef JD_NOISE
     return hipGetLastError();
 }
 
@@ -1145,8 +1288,11 @@ hipError_t launch_adjoint(const HostProblem& p, const HostRun& r, const void* ta
 
 hipError_t launch_cost_grad_stored(const HostProblem& p, const HostRun& r, const void* tab,
                                   void* traj, double* cpart, double* apart, const WsHeader* hdr,
-                                  hipStream_t st, Gate gate) {
+                                  hipStream_t st, Gate gate, const void* noise) {
     const unsigned nb = (unsigned)r.nblk;
+#define JD_CG_NZ(T, DD, CB, NZ)                                                                   \
+    hipLaunchKernelGGL((k_cost_grad_stored<T, DD, CB, NZ>), dim3(nb), dim3(kThreads), 0, st, a,   \
+                       (const T*)tab, cpart, (const T*)noise)
 #define JD_CG(T, DD)                                                                              \
     do {                                                                                          \
         SweepArgs<T, DD> a = make_args<T, DD>(p, r);                                              \
@@ -1154,15 +1300,21 @@ hipError_t launch_cost_grad_stored(const HostProblem& p, const HostRun& r, const
         a.traj = traj;                                                                            \
         a.part = apart;                                                                           \
         a.thr = &hdr->poisson;                                                                    \
-        if (p.cubic != 0.0)                                                                       \
-            hipLaunchKernelGGL((k_cost_grad_stored<T, DD, true>), dim3(nb), dim3(kThreads), 0,    \
-                               st, a, (const T*)tab, cpart);                                      \
-        else                                                                                      \
-            hipLaunchKernelGGL((k_cost_grad_stored<T, DD, false>), dim3(nb), dim3(kThreads), 0,   \
-                               st, a, (const T*)tab, cpart);                                      \
+        if (p.cubic != 0.0) {                                                                     \
+            if (noise != nullptr)                                                                 \
+                JD_CG_NZ(T, DD, true, true);                                                      \
+            else                                                                                  \
+                JD_CG_NZ(T, DD, true, false);                                                     \
+        } else {                                                                                  \
+            if (noise != nullptr)                                                                 \
+                JD_CG_NZ(T, DD, false, true);                                                     \
+            else                                                                                  \
+                JD_CG_NZ(T, DD, false, false);                                                    \
+        }                                                                                         \
     } while (0)
     JD_DISPATCH(r.prec, p.D, JD_CG);
 #undef JD_CG
+#undef JD_CG_NZ
     return hipGetLastError();
 }
 

@@ -47,6 +47,7 @@ struct HostRun {
     int mode;  // JD_STORE / JD_RECOMPUTE
     int K;
     int nblk;  // blocks of the sweeps = ceil(M / kBlock)
+    bool noise;  // forward sweeps read the iteration's noise table
     const jd_dump* dump;
 };
 
@@ -138,9 +139,17 @@ bool recompute_supported(const HostProblem& p, const HostRun& r);
 // an optional gate (kNoGate: always runs).
 hipError_t launch_setup(const HostProblem& p, const HostRun& r, const double* u, void* tab,
                         WsHeader* hdr, int clear_flag, hipStream_t st, Gate gate = kNoGate);
+// noise: the iteration's noise table (launch_noise) or nullptr (draws in the
+// sweep); the results are bitwise the same.
 hipError_t launch_forward(const HostProblem& p, const HostRun& r, const void* tab, void* traj,
                           int fwd_mode, double* cpart, const WsHeader* hdr, hipStream_t st,
-                          Gate gate = kNoGate);
+                          Gate gate = kNoGate, const void* noise = nullptr);
+// The noise table of iteration r.iter (noise_bytes()): the Brownian normals
+// and jump increments of every path-step.  Reads the Poisson thresholds that
+// launch_setup stages.  Grid: min(nblk N, kNoiseGrid) blocks.
+constexpr int64_t kNoiseGrid = 65536;
+hipError_t launch_noise(const HostProblem& p, const HostRun& r, void* noise, const WsHeader* hdr,
+                        hipStream_t st, Gate gate = kNoGate);
 // seg: the workspace's segment scratch (seg_scratch_bytes(); unused otherwise)
 hipError_t launch_adjoint(const HostProblem& p, const HostRun& r, const void* tab, const void* traj,
                           double* apart, void* seg, const WsHeader* hdr, hipStream_t st,
@@ -148,7 +157,8 @@ hipError_t launch_adjoint(const HostProblem& p, const HostRun& r, const void* ta
 // Forward (stored trajectory) and adjoint fused per block (no dump support).
 hipError_t launch_cost_grad_stored(const HostProblem& p, const HostRun& r, const void* tab,
                                   void* traj, double* cpart, double* apart, const WsHeader* hdr,
-                                  hipStream_t st, Gate gate = kNoGate);
+                                  hipStream_t st, Gate gate = kNoGate,
+                                  const void* noise = nullptr);
 hipError_t launch_finalize_grad(const HostProblem& p, const HostRun& r, const double* apart,
                                 const double* u, double* g, WsHeader* hdr, hipStream_t st,
                                 Gate gate = kNoGate);

@@ -62,7 +62,10 @@ int jd_cost_grad_noalloc(const jd_problem* prob, const jd_run* run, const double
         return rc;
     if (!u || !J || !grad || !traj || !aligned(traj, real_size(r.prec)))
         return JD_EINVAL;
-    // the array is 256-byte aligned, so the layout needs no alignment slack
+    // the array is 256-byte aligned, so the layout needs no alignment slack;
+    // a noise table chosen by JD_NOISE_AUTO gives way to inline draws
+    if (layout(p, r).total - kAlign > kNoAllocBytes && r.noise && run->noise == JD_NOISE_AUTO)
+        r.noise = false;
     if (layout(p, r).total - kAlign > kNoAllocBytes)
         return JD_EWORKSPACE;
     void* ws = nullptr;

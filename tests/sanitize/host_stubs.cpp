@@ -58,11 +58,15 @@ static hipError_t launched() {
 hipError_t launch_setup(const HostProblem&, const HostRun&, const double*, void*, WsHeader*, int,
                         hipStream_t, Gate) { return launched(); }
 hipError_t launch_forward(const HostProblem&, const HostRun&, const void*, void*, int, double*,
-                          const WsHeader*, hipStream_t, Gate) { return launched(); }
+                          const WsHeader*, hipStream_t, Gate, const void*) { return launched(); }
+hipError_t launch_noise(const HostProblem&, const HostRun&, void*, const WsHeader*, hipStream_t,
+                        Gate) { return launched(); }
 hipError_t launch_adjoint(const HostProblem&, const HostRun&, const void*, const void*, double*,
                           void*, const WsHeader*, hipStream_t, Gate) { return launched(); }
 hipError_t launch_cost_grad_stored(const HostProblem&, const HostRun&, const void*, void*, double*,
-                                   double*, const WsHeader*, hipStream_t, Gate) { return launched(); }
+                                   double*, const WsHeader*, hipStream_t, Gate, const void*) {
+    return launched();
+}
 hipError_t launch_finalize_grad(const HostProblem&, const HostRun&, const double*, const double*,
                                 double*, WsHeader*, hipStream_t, Gate) { return launched(); }
 hipError_t launch_finalize_cost(const HostProblem&, const HostRun&, const double*, const double*,

@@ -63,7 +63,7 @@ SERVER = ["jd_server_request_bytes", "jd_server_create", "jd_server_submit",
 
 
 def test_version_and_strerror(L):
-    assert L.jd_version() == 100
+    assert L.jd_version() == 101
     for code in (0, -1, -2, -3, -4, -5, -6, -99):
         assert isinstance(L.jd_strerror(code), bytes)
 
@@ -119,6 +119,36 @@ def test_workspace_and_traj_sizes(L):
     assert t257 == p.N * 512 * 4
 
 
+def test_noise_table_workspace(L):
+    """The noise table adds 2 N d ldm values of the run precision to the
+    workspace; JD_NOISE_AUTO takes it for grids of at most 256 (FP64) or 64
+    (FP32) blocks of 256 paths, and the trajectory buffer does not change."""
+    p = wl.config("c1").problem
+    pr = _Dummy(p)
+    for prec, esz, nmax in (("fp32", 4, 64), ("fp64", 8, 256)):
+        for M in (10_000, 257, 256 * nmax):
+            ldm = (M + 255) // 256 * 256
+            wi, ti = _sizes(L, pr, B.make_run(M, precision=prec, noise="inline"))
+            wt, tt = _sizes(L, pr, B.make_run(M, precision=prec, noise="table"))
+            wa, ta = _sizes(L, pr, B.make_run(M, precision=prec))
+            tab = 2 * p.N * p.d * ldm * esz
+            assert wt - wi == (tab + 255) // 256 * 256
+            assert wa == wt  # at most 256 blocks: the table
+            assert ti == tt == ta
+        # one block more: draws in the sweeps unless asked for
+        M = 256 * nmax + 1
+        wi, _ = _sizes(L, pr, B.make_run(M, precision=prec, noise="inline"))
+        wa, _ = _sizes(L, pr, B.make_run(M, precision=prec))
+        wt, _ = _sizes(L, pr, B.make_run(M, precision=prec, noise="table"))
+        assert wa == wi < wt
+    # a table beyond 1 GiB is not taken by the automatic choice: d = 8,
+    # 5000 steps, 2^16 paths in FP64 would need 2 * 5000 * 8 * 65536 * 8 bytes
+    q = _Dummy(wl.general_problem(8, 5000, seed=2))
+    wi, _ = _sizes(L, q, B.make_run(1 << 16, precision="fp64", noise="inline"))
+    wa, _ = _sizes(L, q, B.make_run(1 << 16, precision="fp64"))
+    assert wa == wi
+
+
 @host_only
 def test_invalid_arguments_rejected_before_launch(L):
     p = wl.general_problem(3, 20, seed=1)
@@ -166,6 +196,8 @@ def test_invalid_arguments_rejected_before_launch(L):
     assert badrun(mode=3) == B.JD_EINVAL
     assert badrun(mode=B.JD_RECOMPUTE, K=0) == B.JD_EINVAL
     assert badrun(mode=B.JD_RECOMPUTE, K=21) == B.JD_EINVAL
+    assert badrun(noise=3) == B.JD_EINVAL
+    assert badrun(noise=-1) == B.JD_EINVAL
     # a checkpoint interval whose segment scratch would exceed 8 GiB (1024
     # regions of K d 256 elements) is refused, not mis-run
     q = _Dummy(wl.general_problem(8, 2000, seed=2))
@@ -350,6 +382,13 @@ def test_fb_invalid_arguments_rejected_before_launch(L):
     assert L.jd_fb_optimize(P, C.byref(run), C.byref(bad_opt), fake, None, None, fake, fake, ws,
                             None) == B.JD_EINVAL
     assert L.jd_fb_draws(P, C.byref(run), -1, 4, 0, 4, fake, fake, fake, None) == B.JD_EINVAL
+    # the noise policy is checked; every valid value leaves the workspace as is
+    bad_noise = B.make_run(1000)
+    bad_noise.noise = 3
+    assert L.jd_fb_forward(P, C.byref(bad_noise), fake, fake, fake, fake, ws, None) == B.JD_EINVAL
+    sizes = {L.jd_fb_workspace_bytes(P, C.byref(B.make_run(1000, noise=n)))
+             for n in ("auto", "inline", "table")}
+    assert len(sizes) == 1 and 0 not in sizes
     # rings (Section 6.4)
     for kw in (dict(np=0), dict(np=B.JD_FB_MAX_RING + 1), dict(omega=float("nan")),
                dict(cost_kind=2), dict(cost_kind=1, ax=0.0), dict(init_kind=2, av=-1.0),

@@ -152,6 +152,29 @@ def test_more_iterations_than_one_batch(dev):
     assert any(l["backtracks"] > 0 for l in logs1)
 
 
+@pytest.mark.parametrize("precision,mode,K,zeta0", [("fp64", "store", 0, 4.0),
+                                                     ("fp32", "recompute", 25, 64.0)])
+def test_noise_table_iterates_bitwise_inline(dev, precision, mode, K, zeta0):
+    """The line-search trials of an iteration read the noise table its
+    gradient evaluation wrote, also across the device-driven batches (70
+    iterations, backtracking): logs and control equal the inline draws', bit
+    for bit."""
+    import torch
+    say("noise table iterates", precision, mode)
+    w = wl.scaled(wl.config("c1"), M=3000)
+    p = w.problem
+    res = []
+    for noise in ("table", "inline"):
+        eng = B.Engine(p, M=w.M, seed=w.seed, precision=precision, mode=mode, K=K, device=dev,
+                       noise=noise)
+        u = torch.zeros((p.N, 1), dtype=torch.float64, device=dev)
+        _, logs = eng.optimize(u, n_max=70, zeta0=zeta0)
+        res.append((u.cpu().numpy(), logs))
+    np.testing.assert_array_equal(res[0][0], res[1][0])
+    assert res[0][1] == res[1][1]
+    assert len(res[0][1]) == 70 and any(l["backtracks"] > 0 for l in res[0][1])
+
+
 def test_tolerance_stops_on_the_device(dev):
     """tol > 0: the device stops the iteration at the first accepted step with
     ||u' - u||_L2 <= tol; the call reports the iterations done."""

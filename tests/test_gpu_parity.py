@@ -104,17 +104,19 @@ def _control(p, name):
     return np.zeros((p.N, p.d)) if name in ("c1", "c2") else wl.random_control(p, 3, 0.3)
 
 
+@pytest.mark.parametrize("noise", ["table", "inline"])
 @pytest.mark.parametrize("mode", ["store", "recompute"])
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
 @pytest.mark.parametrize("name", list(CASES))
-def test_cost_grad_and_paths(dev, oracle_runs, name, precision, mode):
+def test_cost_grad_and_paths(dev, oracle_runs, name, precision, mode, noise):
     w, K = CASES[name]
     p = w.problem
-    say(name, precision, mode, f"M={w.M} N={p.N} d={p.d} K={K}")
+    say(name, precision, mode, noise, f"M={w.M} N={p.N} d={p.d} K={K}")
     u = _control(p, name)
     it = 3
     X, lam, C, J_ref, g_ref, s_ref = oracle_runs(name, it, u)
-    eng = B.Engine(p, M=w.M, seed=w.seed, precision=precision, mode=mode, K=K, device=dev)
+    eng = B.Engine(p, M=w.M, seed=w.seed, precision=precision, mode=mode, K=K, device=dev,
+                   noise=noise)
     tol = TOL[precision]
     # forward with per-path cost dump
     dp, dumps = eng.path_dump(0, w.M)
@@ -313,3 +315,46 @@ def test_sweeps_without_cubic_term_are_bitwise_the_term_times_zero(dev, d, mode,
     assert out[0][0] == out[1][0]
     for a, b in zip(out[0][1:], out[1][1:]):
         np.testing.assert_array_equal(a, b)
+
+
+# (label, d, N, M, K, cubic): N on both sides of the table's register tile
+# (16 / padded d steps), ragged blocks, padded dimensions
+NOISE_SHAPES = [
+    ("d1 one path", 1, 50, 1, 7, 0.07),
+    ("d1 N = tile", 1, 16, 300, 4, 0.0),
+    ("d1 N = tile + 1", 1, 17, 513, 17, 0.07),
+    ("d2 one step", 2, 1, 255, 1, 0.07),
+    ("d3 ragged", 3, 37, 1300, 9, 0.1),
+    ("d4 two tiles", 4, 8, 257, 3, 0.0),
+    ("d6 padded", 6, 45, 700, 9, 0.05),
+    ("d8 N = 2 tiles + 1", 8, 5, 300, 5, 0.07),
+    ("d8 c4-like", 8, 64, 600, 16, 0.0),
+]
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("mode", ["store", "recompute"])
+@pytest.mark.parametrize("label,d,N,M,K,cubic", NOISE_SHAPES)
+def test_noise_table_is_bitwise_the_inline_draws(dev, label, d, N, M, K, cubic, mode, precision):
+    """The forward sweeps read the iteration's draws from the noise table or
+    compute them in the sweep; every bit of J, g, the per-path states, adjoints
+    and costs and the stored trajectory must agree."""
+    say("noise table", label, mode, precision)
+    p = wl.general_problem(d, N, seed=200 + d + N, cubic=cubic, lam=min(5.0, 2.0 * N))
+    u = wl.random_control(p, 4, 0.3)
+    out = []
+    for noise in ("table", "inline"):
+        eng = B.Engine(p, M=M, seed=11, precision=precision, mode=mode, K=K, device=dev,
+                       noise=noise)
+        dp, dd = eng.path_dump(0, M)
+        J, g = eng.cost_grad(u, it=6)
+        Jf = eng.forward(u, it=6, dump=dp)
+        eng.adjoint(u, it=6, dump=dp)
+        Jf2 = eng.forward(u, it=6, store=False)
+        out.append((float(J), float(Jf), float(Jf2), g.cpu().numpy(), dd["X"].cpu().numpy(),
+                    dd["lam"].cpu().numpy(), dd["cost"].cpu().numpy(),
+                    eng.trajectory().cpu().numpy()))
+    a, b = out
+    assert a[:3] == b[:3]
+    for x, y in zip(a[3:], b[3:]):
+        np.testing.assert_array_equal(x, y)
