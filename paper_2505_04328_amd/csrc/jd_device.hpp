@@ -115,10 +115,12 @@ __device__ __forceinline__ uint32_t poisson_word(const uint32_t* w) {
     return lo | hi;
 }
 
-// Count for word P.  The first comparison is the common case; the loop runs
-// only in lanes that jump.
-__device__ __forceinline__ int poisson_count(uint32_t P, const PoissonTable* __restrict__ tb) {
-    int n = P > tb->tm1[0] ? 1 : 0;
+// Count for word P.  The first comparison (against t0 = tm1[0], which a sweep
+// keeps in a register) is the common case; the loop runs only in lanes that
+// jump.
+__device__ __forceinline__ int poisson_count(uint32_t P, uint32_t t0,
+                                             const PoissonTable* __restrict__ tb) {
+    int n = P > t0 ? 1 : 0;
     if (n) {
         const int jmax = tb->jmax;
 #pragma unroll 1
@@ -129,6 +131,9 @@ __device__ __forceinline__ int poisson_count(uint32_t P, const PoissonTable* __r
         }
     }
     return n;
+}
+__device__ __forceinline__ int poisson_count(uint32_t P, const PoissonTable* __restrict__ tb) {
+    return poisson_count(P, tb->tm1[0], tb);
 }
 
 // Path-independent coefficients of the Euler step in the path precision.  D is
@@ -221,11 +226,11 @@ __device__ __forceinline__ Real jump_normal(const StepDraws<Real, D>& s, int i) 
     return bm_sin(s.rad[i], s.ang[i]);
 }
 
-// Draws of path-step (m, k) under iteration word `iter`.
+// Draws of path-step (m, k) under iteration word `iter`; t0 = thr->tm1[0].
 template <typename Real, int D>
 __device__ __forceinline__ void draws(uint32_t m, uint32_t k, uint32_t iter, uint32_t key0,
                                       uint32_t key1, const PoissonTable* __restrict__ thr,
-                                      StepDraws<Real, D>& s) {
+                                      uint32_t t0, StepDraws<Real, D>& s) {
     constexpr int NB = (D + 1) / 2;
     uint32_t w[4 * NB];
 #pragma unroll
@@ -237,7 +242,7 @@ __device__ __forceinline__ void draws(uint32_t m, uint32_t k, uint32_t iter, uin
         s.ang[i] = unit_uniform<Real>(w[2 * i + 1]);
         s.zw[i] = bm_cos(s.rad[i], s.ang[i]);
     }
-    s.n = poisson_count(poisson_word(w), thr);
+    s.n = poisson_count(poisson_word(w), t0, thr);
 }
 
 template <typename Real>

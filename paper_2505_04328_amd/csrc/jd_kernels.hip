@@ -27,7 +27,8 @@ template <typename Real, int D>
 struct SweepArgs {
     Coef<Real, D> c;
     const Coef<Real, D>* lc;  // the block's LDS copy of c (set in the kernel), see CoefInLds
-    const PoissonTable* thr;  // staged in the workspace header
+    const PoissonTable* thr;  // staged in the workspace header, then in the block's LDS
+    uint32_t thr0;            // thr->tm1[0], read once per block
     Gate gate;        // launch gate (word null: always runs)
     void* traj;       // trajectory or checkpoints
     double* part;     // per-block partial sums
@@ -83,12 +84,48 @@ __device__ __forceinline__ void load_row(const Real* __restrict__ row, int d, Re
     }
 }
 
+typedef unsigned int U32x2 __attribute__((__vector_size__(2 * sizeof(unsigned int))));
+
+// One state row (d components of 256 lanes) by raw buffer stores: one
+// descriptor per row, the lane's byte offset in a vector register and each
+// component's offset in a scalar one, so no 64-bit address is formed per
+// component (global stores reach only 4 KB past a base).  With every
+// component present (d = D) the stores need no per-component branch.
+// AUX: cache policy.
+template <typename Real, int D, int AUX>
+__device__ __forceinline__ void buffer_store_row(Real* row, int d, const Real* X) {
+    const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)row, (short)0, (int)(d * kThreads * (int)sizeof(Real)), kBufferConfig);
+    const uint32_t voff = threadIdx.x * (uint32_t)sizeof(Real);
+    auto put = [&](int c) {
+        // the byte offset split into a multiple of 4 KB (scalar operand) and
+        // the rest (folded into the instruction's 12-bit immediate)
+        const uint32_t off = (uint32_t)(c * kThreads * (int)sizeof(Real));
+        const uint32_t soff = off & ~4095u;
+        const uint32_t vo = voff + (off & 4095u);
+        if constexpr (sizeof(Real) == 4)
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, (float)X[c]), r,
+                                                  vo, soff, AUX);
+        else
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U32x2, (double)X[c]), r,
+                                                  vo, soff, AUX);
+    };
+    if (d == D) {
+#pragma unroll
+        for (int c = 0; c < D; ++c)
+            put(c);
+    } else {
+#pragma unroll
+        for (int c = 0; c < D; ++c)
+            if (c < d)
+                put(c);
+    }
+}
+
+// Trajectory and checkpoint rows are read once, by the adjoint: non-temporal.
 template <typename Real, int D>
 __device__ __forceinline__ void store_row(Real* __restrict__ row, int d, const Real* X) {
-#pragma unroll
-    for (int c = 0; c < D; ++c)
-        if (c < d)
-            __builtin_nontemporal_store(X[c], row + c * kThreads + threadIdx.x);
+    buffer_store_row<Real, D, kNontemporal>(row, d, X);
 }
 
 template <typename Real, int D>
@@ -114,6 +151,24 @@ __device__ __forceinline__ void stage_coef(SweepArgs<Real, D>& a, Coef<Real, D>*
         __syncthreads();
         a.lc = sc;
     }
+}
+
+// Stages the Poisson thresholds in LDS and points a.thr at the copy.  Sweeps
+// that store to global memory inside their step loop need it: the compiler
+// cannot tell those stores from the thresholds in the workspace header, so it
+// would reload the first threshold with a vector load in every step and wait
+// for all of the wave's outstanding stores before the comparison (the
+// vector-memory counter covers stores too).  LDS cannot alias global memory,
+// so the copy's loads stay off that counter.
+template <typename Real, int D>
+__device__ __forceinline__ void stage_thresholds(SweepArgs<Real, D>& a, PoissonTable* st) {
+    if (threadIdx.x < 32)
+        st->tm1[threadIdx.x] = a.thr->tm1[threadIdx.x];
+    if (threadIdx.x == 0)
+        st->jmax = a.thr->jmax;
+    __syncthreads();
+    a.thr = st;
+    a.thr0 = st->tm1[0];
 }
 
 // ---------------------------------------------------------------------------
@@ -177,7 +232,7 @@ struct ForwardSweep {
         const Real* trow = tab + (size_t)k * 2 * D;
         acc += (double)sq_dist<Real, D>(X, trow + D);
         StepDraws<Real, D> z;
-        draws<Real, D>((uint32_t)m, (uint32_t)k, a.iter, a.key0, a.key1, a.thr, z);
+        draws<Real, D>((uint32_t)m, (uint32_t)k, a.iter, a.key0, a.key1, a.thr, a.thr0, z);
         euler_step<Real, D, CB>(a.c, a.lc, trow, X, z);
         put(a, k);
     }
@@ -240,6 +295,8 @@ __global__ void __launch_bounds__(kThreads)
 k_noise(SweepArgs<Real, D> a, Real* __restrict__ noise) {
     if (gate_closed(a.gate))
         return;
+    __shared__ PoissonTable thr;
+    stage_thresholds(a, &thr);
     const int64_t nb = (int64_t)a.nblk * a.N;
     const int64_t rows = 2 * (int64_t)a.d * kThreads;
     for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
@@ -247,7 +304,7 @@ k_noise(SweepArgs<Real, D> a, Real* __restrict__ noise) {
         const int k = (int)(b - g * a.N);
         const int64_t m = g * kThreads + threadIdx.x;
         StepDraws<Real, D> z;
-        draws<Real, D>((uint32_t)m, (uint32_t)k, a.iter, a.key0, a.key1, a.thr, z);
+        draws<Real, D>((uint32_t)m, (uint32_t)k, a.iter, a.key0, a.key1, a.thr, a.thr0, z);
         Real* out = noise + b * rows + threadIdx.x;  // b = g N + k: step k of group g
 #pragma unroll
         for (int i = 0; i < D; ++i) {
@@ -324,6 +381,8 @@ k_forward(SweepArgs<Real, D> a, const Real* __restrict__ tab, double* __restrict
     __shared__ double sh[kThreads];
     __shared__ Coef<Real, D> sc;
     stage_coef<CoefInLds<Real, D>::forward>(a, &sc);
+    __shared__ PoissonTable thr;
+    stage_thresholds(a, &thr);
     ForwardSweep<Real, D, MODE, CB> f;
     f.begin(a, blockIdx.x);
     if constexpr (NOISE) {
@@ -538,6 +597,8 @@ k_cost_grad_stored(SweepArgs<Real, D> a, const Real* __restrict__ tab, double* _
     __shared__ Real tile[StepReducer<D, Real>::kRows][kThreads];
     __shared__ Coef<Real, D> sc;
     stage_coef<CoefInLds<Real, D>::any>(a, &sc);
+    __shared__ PoissonTable thr;
+    stage_thresholds(a, &thr);
     {
         ForwardSweep<Real, D, FWD_STORE, CB> f;
         f.begin(a, blockIdx.x);
@@ -576,6 +637,8 @@ k_adjoint_recompute(SweepArgs<Real, D> a, const Real* __restrict__ tab) {
     __shared__ Real tile[StepReducer<D, Real>::kRows][kThreads];
     __shared__ Coef<Real, D> sc;
     stage_coef<CoefInLds<Real, D>::any>(a, &sc);
+    __shared__ PoissonTable thr;
+    stage_thresholds(a, &thr);
     StepReducer<D, Real> red;
     red.init(tile, blockIdx.x);
     const int64_t m = (int64_t)blockIdx.x * kThreads + threadIdx.x;
@@ -612,7 +675,7 @@ k_adjoint_recompute(SweepArgs<Real, D> a, const Real* __restrict__ tab) {
         for (int s = 1; s < ns; ++s) {
             for (int k = s0 + (s - 1) * R; k < s0 + s * R; ++k) {
                 StepDraws<Real, D> z;
-                draws<Real, D>((uint32_t)m, (uint32_t)k, a.iter, a.key0, a.key1, a.thr, z);
+                draws<Real, D>((uint32_t)m, (uint32_t)k, a.iter, a.key0, a.key1, a.thr, a.thr0, z);
                 euler_step<Real, D, CB>(a.c, a.lc, tab + (size_t)k * 2 * D, X, z);
             }
 #pragma unroll
@@ -642,7 +705,7 @@ k_adjoint_recompute(SweepArgs<Real, D> a, const Real* __restrict__ tab) {
                     for (int i = 0; i < D; ++i)
                         buf[r][i] = buf[r - 1][i];
                     StepDraws<Real, D> z;
-                    draws<Real, D>((uint32_t)m, (uint32_t)k, a.iter, a.key0, a.key1, a.thr, z);
+                    draws<Real, D>((uint32_t)m, (uint32_t)k, a.iter, a.key0, a.key1, a.thr, a.thr0, z);
                     euler_step<Real, D, CB>(a.c, a.lc, tab + (size_t)k * 2 * D, buf[r], z);
                 }
             }
@@ -746,10 +809,7 @@ __device__ __forceinline__ void seg_load(const Real* region, int64_t stride, int
 
 template <typename Real, int D>
 __device__ __forceinline__ void seg_store(Real* __restrict__ row, int d, const Real* X) {
-#pragma unroll
-    for (int c = 0; c < D; ++c)
-        if (c < d)
-            row[c * kThreads + threadIdx.x] = X[c];
+    buffer_store_row<Real, D, 0>(row, d, X);
 }
 
 template <typename Real, int D, bool DUMP, bool CB>
@@ -761,6 +821,8 @@ k_adjoint_segments(SweepArgs<Real, D> a, const Real* __restrict__ tab, Real* __r
     __shared__ Real tile[StepReducer<D, Real>::kRows][kThreads];
     __shared__ Coef<Real, D> sc;
     stage_coef<CoefInLds<Real, D>::any>(a, &sc);
+    __shared__ PoissonTable thr;
+    stage_thresholds(a, &thr);
     const int N = a.N, K = a.K;
     const int nseg = (N + K - 1) / K;
     const Cols cl = make_cols(a.d);
@@ -804,7 +866,7 @@ k_adjoint_segments(SweepArgs<Real, D> a, const Real* __restrict__ tab, Real* __r
                 Real* row = region + cl.stride;
                 for (int k = s0; k < s1 - 1; ++k) {
                     StepDraws<Real, D> z;
-                    draws<Real, D>((uint32_t)m, (uint32_t)k, a.iter, a.key0, a.key1, a.thr, z);
+                    draws<Real, D>((uint32_t)m, (uint32_t)k, a.iter, a.key0, a.key1, a.thr, a.thr0, z);
                     euler_step<Real, D, CB>(a.c, a.lc, tab + (size_t)k * 2 * D, X, z);
                     seg_store<Real, D>(row, a.d, X);
                     row += cl.stride;
@@ -1040,13 +1102,14 @@ k_draws(SweepArgs<Real, D> a, PoissonTable pt, int64_t m0, int64_t mc, int k0, i
         tb.jmax = pt.jmax;
     __syncthreads();
     a.thr = &tb;
+    a.thr0 = tb.tm1[0];
     const int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (idx >= mc * kc)
         return;
     const int64_t p = idx / kc;
     const int q = (int)(idx - p * kc);
     StepDraws<Real, D> z;
-    draws<Real, D>((uint32_t)(m0 + p), (uint32_t)(k0 + q), a.iter, a.key0, a.key1, a.thr, z);
+    draws<Real, D>((uint32_t)(m0 + p), (uint32_t)(k0 + q), a.iter, a.key0, a.key1, a.thr, a.thr0, z);
 #pragma unroll
     for (int i = 0; i < D; ++i) {
         if (i < a.d) {
@@ -1094,6 +1157,7 @@ static SweepArgs<Real, D> make_args(const HostProblem& p, const HostRun& r) {
     a.c.dt = (Real)p.dt;
     a.c.c3 = (Real)p.cubic;
     a.thr = nullptr;
+    a.thr0 = 0;
     a.lc = nullptr;
     a.gate = kNoGate;
     a.traj = nullptr;
