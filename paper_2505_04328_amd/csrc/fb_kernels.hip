@@ -57,7 +57,8 @@ struct FbArgs {
     double* mom;     // surrogate forward: per-step moment partials, or null
     int init_kind;
     uint32_t key0, key1, iter;
-    const PoissonTable* thr;
+    const PoissonTable* thr;  // in the workspace header, then in the block's LDS
+    uint32_t thr0;            // thr->tm1[0], read once per block
     Gate gate;  // launch gate (word null: always runs)
     double dt64;
     int64_t dm0, dcount;  // per-path dumps
@@ -257,6 +258,33 @@ __device__ __forceinline__ Real fb_control_of(const FbArgs<Real>& a, const Real*
     return u;
 }
 
+// The Poisson thresholds in the block's LDS, the first one in a register:
+// the sweeps store trajectory rows inside their step loops, and with the
+// thresholds in global memory the compiler reloads the first one every step
+// and waits for the wave's outstanding stores before the comparison.
+template <typename Real>
+__device__ __forceinline__ void fb_stage_thresholds(FbArgs<Real>& a, PoissonTable* st) {
+    if (threadIdx.x < 32)
+        st->tm1[threadIdx.x] = a.thr->tm1[threadIdx.x];
+    if (threadIdx.x == 0)
+        st->jmax = a.thr->jmax;
+    __syncthreads();
+    a.thr = st;
+    a.thr0 = st->tm1[0];
+}
+
+// The jump factor table (64 values) in the block's LDS: its per-lane reads
+// (indexed by each lane's jump count) would otherwise wait, through the
+// in-order vector-memory counter, for every trajectory load or store the wave
+// has in flight.  Returns the LDS copy.
+template <typename Real>
+__device__ __forceinline__ const Real* fb_stage_ks(const Real* __restrict__ ks, Real* st) {
+    if (threadIdx.x < 64)
+        st[threadIdx.x] = ks[threadIdx.x];
+    __syncthreads();
+    return st;
+}
+
 template <typename Real, int NVP, typename Sink = NoSink, int RU = 2>
 __device__ __forceinline__ Real fb_step(const FbArgs<Real>& a, const Real* __restrict__ mk,
                                         const Real* __restrict__ ks, uint32_t m, int k, Real& x,
@@ -267,7 +295,7 @@ __device__ __forceinline__ Real fb_step(const FbArgs<Real>& a, const Real* __res
     philox4x32_10<true>(m, (uint32_t)k, a.iter, 0u, a.key0, a.key1, w);
     const Real R = bm_radius(w[0], (Real)0);
     const Real ub = unit_uniform<Real>(w[1]);
-    const int n = poisson_count(poisson_word(w), a.thr);
+    const int n = poisson_count(poisson_word(w), a.thr0, a.thr);
     if (n_out != nullptr)
         *n_out = n;
     Real xn, vs, ex = 0, ev = 0;
@@ -451,6 +479,10 @@ k_fb_forward(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __restrict
              const Real* __restrict__ ks, void* traj, double* __restrict__ cpart) {
     if (gate_closed(a.gate))
         return;
+    __shared__ PoissonTable thr;
+    fb_stage_thresholds(a, &thr);
+    __shared__ Real ks_lds[64];
+    ks = fb_stage_ks(ks, ks_lds);
     static_assert(RING || (G == 1 && TPB == kThreads), "independent particles run one per lane");
     __shared__ double sh[TPB];
     __shared__ Real xs[RING ? 2 : 1][RING ? G * TPB : 1];
@@ -851,6 +883,10 @@ k_fb_forward_grad(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __res
                   double* __restrict__ apart) {
     if (gate_closed(a.gate))
         return;
+    __shared__ PoissonTable thr;
+    fb_stage_thresholds(a, &thr);
+    __shared__ Real ks_lds[64];
+    ks = fb_stage_ks(ks, ks_lds);
     __shared__ FbShared<Real, fb_vrows<NVP>()> sh;
     __shared__ double red[kThreads];
     auto wave = fb_wave(sh);
@@ -955,6 +991,11 @@ k_fb_adjoint(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __restrict
              const Real* __restrict__ ks, const void* traj, double* __restrict__ apart) {
     if (gate_closed(a.gate))
         return;
+    __shared__ PoissonTable thr;
+    if constexpr (SURR)
+        fb_stage_thresholds(a, &thr);
+    __shared__ Real ks_lds[64];
+    ks = fb_stage_ks(ks, ks_lds);
     static_assert(!(SURR && RING), "the surrogate gradient takes independent particles");
     static_assert(RING || TPB == kThreads, "independent particles run in blocks of 256");
     __shared__ FbShared<Real, fb_vrows<NVP>(), TPB / 64> sh;
@@ -1019,7 +1060,7 @@ k_fb_adjoint(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __restrict
                 if (SURR) {
                     uint32_t w[4];
                     philox4x32_10<true>((uint32_t)m[j], (uint32_t)k, a.iter, 0u, a.key0, a.key1, w);
-                    n = poisson_count(poisson_word(w), a.thr);
+                    n = poisson_count(poisson_word(w), a.thr0, a.thr);
                 } else {
                     n = st.nn;
                     if (k >= 1)
@@ -1246,7 +1287,7 @@ __device__ __forceinline__ int fb_interval(const FbArgs<Real>& a, uint32_t m, in
                                            Real& zv, Real& a1) {
     uint32_t w[4];
     philox4x32_10<true>(m, (uint32_t)k, a.iter, 0u, a.key0, a.key1, w);
-    const int n = poisson_count(poisson_word(w), a.thr);
+    const int n = poisson_count(poisson_word(w), a.thr0, a.thr);
     const Real R = bm_radius(w[0], (Real)0);
     const Real ub = unit_uniform<Real>(w[1]);
     zx = bm_cos(R, ub);
@@ -1266,6 +1307,8 @@ k_fb_forward_adapted(FbArgs<Real> a, const Real* __restrict__ mu, const Real* __
                      void* traj, double* __restrict__ cpart) {
     if (gate_closed(a.gate))
         return;
+    __shared__ PoissonTable thr;
+    fb_stage_thresholds(a, &thr);
     __shared__ double sh[kThreads];
     const FbSlot sl = fb_slot<1>(a, 0);
     Real x, v, cx = 0, cv = 0;
@@ -1656,6 +1699,7 @@ k_fb_draws(FbArgs<Real> a, PoissonTable pt, int64_t m0, int64_t mc, int k0, int 
         tb.jmax = pt.jmax;
     __syncthreads();
     a.thr = &tb;
+    a.thr0 = tb.tm1[0];
     const int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (idx >= mc * kc)
         return;
@@ -1678,7 +1722,7 @@ k_fb_draws(FbArgs<Real> a, PoissonTable pt, int64_t m0, int64_t mc, int k0, int 
         Z[3 * idx + 2] = bm_cos(bm_radius(w[2], (Real)0), unit_uniform<Real>(w[3]));
     }
     if (counts != nullptr)
-        counts[idx] = poisson_count(poisson_word(w), a.thr);
+        counts[idx] = poisson_count(poisson_word(w), a.thr0, a.thr);
 }
 
 // Per-step variance of the surrogate gradient's forward ensemble (block k =
@@ -1816,6 +1860,7 @@ static FbArgs<Real> fb_args(const FbHost& p, const HostRun& r) {
     a.key1 = (uint32_t)(r.seed >> 32);
     a.iter = r.iter;
     a.thr = nullptr;
+    a.thr0 = 0;
     a.gate = kNoGate;
     a.dt64 = p.dt;
     a.dm0 = 0;
