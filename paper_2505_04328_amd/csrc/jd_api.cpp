@@ -203,7 +203,8 @@ int enqueue_forward(const HostProblem& p, const HostRun& r, const double* u, voi
 }
 
 int enqueue_cost_grad(const HostProblem& p, const HostRun& r, const double* u, double* J,
-                      double* g, void* traj, const Ws& w, hipStream_t st, Gate gate) {
+                      double* g, void* traj, const Ws& w, hipStream_t st, Gate gate,
+                      const LsTail* tail) {
     JD_TRY(launch_setup(p, r, u, w.tab, w.hdr, 1, st, gate));
     if (w.noise)
         JD_TRY(launch_noise(p, r, w.noise, w.hdr, st, gate));
@@ -219,17 +220,15 @@ int enqueue_cost_grad(const HostProblem& p, const HostRun& r, const double* u, d
         JD_TRY(launch_adjoint(p, r, w.tab, traj, w.apart, w.seg, w.hdr, st, gate));
     }
     JD_TRY(launch_finalize_grad(p, r, w.apart, u, g, w.hdr, st, gate));
-    JD_TRY(launch_finalize_cost(p, r, w.cpart, u, g, J, w.hdr, 0, st, gate));
+    JD_TRY(launch_finalize_cost(p, r, w.cpart, u, g, J, w.hdr, 0, st, gate, tail));
     return JD_OK;
 }
 
 int enqueue_trial(const HostProblem& p, const HostRun& r, const double* u, double zeta,
-                  const Ws& w, hipStream_t st, Gate gate) {
-    const int nd = p.N * p.d;
-    JD_TRY(launch_trial(u, w.gbuf, zeta, w.ut, nd, st, gate));
-    JD_TRY(launch_setup(p, r, w.ut, w.tab, w.hdr, 0, st, gate));
+                  const Ws& w, hipStream_t st, Gate gate, const LsTail* tail) {
+    JD_TRY(launch_setup_trial(p, r, u, w.gbuf, zeta, w.ut, w.tab, w.hdr, st, gate));
     JD_TRY(launch_forward(p, r, w.tab, nullptr, FWD_COST, w.cpart, w.hdr, st, gate, w.noise));
-    JD_TRY(launch_finalize_cost(p, r, w.cpart, w.ut, nullptr, nullptr, w.hdr, 1, st, gate));
+    JD_TRY(launch_finalize_cost(p, r, w.cpart, w.ut, nullptr, nullptr, w.hdr, 1, st, gate, tail));
     return JD_OK;
 }
 
@@ -245,9 +244,13 @@ int LsDriver::enqueue(LsOps& ops, int iters, hipStream_t st) {
     for (int n = n_next; n < end; ++n) {
         int rc;
         if (j0 < 0) {
-            if ((rc = ops.grad(n, gate_of(hdr, ls_phase(n, -1)), st)))
+            LsTail tg{};
+            tg.mode = kLsTailAfterGrad;
+            tg.n = n;
+            if ((rc = ops.grad(n, tg, gate_of(hdr, ls_phase(n, -1)), st)))
                 return rc;
-            JD_TRY(launch_ls_after_grad(hdr, n, st));
+            if (!ops.fused())
+                JD_TRY(launch_ls_after_grad(hdr, n, st));
             j0 = 0;
         }
         // zeta_j = zeta0 rho^j by repeated multiplication, as one trial at a time
@@ -256,8 +259,6 @@ int LsDriver::enqueue(LsOps& ops, int iters, hipStream_t st) {
             zeta *= opt.rho;
         const int jend = opt.max_backtracks - j0 < ahead ? opt.max_backtracks : j0 + ahead;
         for (int j = j0; j < jend; ++j) {
-            if ((rc = ops.trial(n, zeta, gate_of(hdr, ls_phase(n, j)), st)))
-                return rc;
             LsArmijo a;
             a.c_armijo = opt.c_armijo;
             a.zeta = zeta;
@@ -268,7 +269,18 @@ int LsDriver::enqueue(LsOps& ops, int iters, hipStream_t st) {
             a.n_max = opt.n_max;
             a.max_backtracks = opt.max_backtracks;
             a.iter = iter0 + (uint32_t)n;
-            JD_TRY(launch_armijo(hdr, ring, u, ut, nd, a, st));
+            LsTail ta{};
+            ta.mode = kLsTailArmijo;
+            ta.n = n;
+            ta.ls = a;
+            ta.ring = ring;
+            ta.u = u;
+            ta.ut = ut;
+            ta.nd = nd;
+            if ((rc = ops.trial(n, zeta, ta, gate_of(hdr, ls_phase(n, j)), st)))
+                return rc;
+            if (!ops.fused())
+                JD_TRY(launch_armijo(hdr, ring, u, ut, nd, a, st));
             zeta *= opt.rho;
         }
         j0 = -1;
@@ -317,16 +329,17 @@ struct JdOps : LsOps {
     const Ws& w;
     JdOps(const HostProblem& p_, const HostRun& r_, const double* u_, void* traj_, const Ws& w_)
         : p(p_), r(r_), u(u_), traj(traj_), w(w_) {}
-    int grad(int n, Gate gate, hipStream_t st) override {
+    int grad(int n, const LsTail& tail, Gate gate, hipStream_t st) override {
         HostRun rn = r;
         rn.iter = r.iter + (uint32_t)n;
-        return enqueue_cost_grad(p, rn, u, nullptr, w.gbuf, traj, w, st, gate);
+        return enqueue_cost_grad(p, rn, u, nullptr, w.gbuf, traj, w, st, gate, &tail);
     }
-    int trial(int n, double zeta, Gate gate, hipStream_t st) override {
+    int trial(int n, double zeta, const LsTail& tail, Gate gate, hipStream_t st) override {
         HostRun rn = r;
         rn.iter = r.iter + (uint32_t)n;
-        return enqueue_trial(p, rn, u, zeta, w, st, gate);
+        return enqueue_trial(p, rn, u, zeta, w, st, gate, &tail);
     }
+    bool fused() const override { return true; }
 };
 
 }  // namespace

@@ -267,12 +267,12 @@ struct FbOps : LsOps {
     const FbWs& w;
     FbOps(const FbHost& p_, const HostRun& r_, const double* mu_, void* traj_, const FbWs& w_)
         : p(p_), r(r_), mu(mu_), traj(traj_), w(w_) {}
-    int grad(int n, Gate gate, hipStream_t st) override {
+    int grad(int n, const LsTail&, Gate gate, hipStream_t st) override {
         HostRun rn = r;
         rn.iter = r.iter + (uint32_t)n;
         return fb_enqueue_cost_grad(p, rn, mu, nullptr, w.gbuf, traj, w, st, gate);
     }
-    int trial(int n, double zeta, Gate gate, hipStream_t st) override {
+    int trial(int n, double zeta, const LsTail&, Gate gate, hipStream_t st) override {
         HostRun rn = r;
         rn.iter = r.iter + (uint32_t)n;
         return fb_enqueue_trial(p, rn, mu, zeta, w, st, gate);

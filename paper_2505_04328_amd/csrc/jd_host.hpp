@@ -71,14 +71,18 @@ bool aligned(const void* ptr, size_t a);
 // acceptance; the outcome is in the workspace header.
 int enqueue_forward(const HostProblem& p, const HostRun& r, const double* u, void* traj, double* J,
                     const Ws& w, hipStream_t st);
+// tail (may be null): the line-search step that the final cost reduction
+// runs (the after-gradient step).
 int enqueue_cost_grad(const HostProblem& p, const HostRun& r, const double* u, double* J,
-                      double* g, void* traj, const Ws& w, hipStream_t st, Gate gate = kNoGate);
+                      double* g, void* traj, const Ws& w, hipStream_t st, Gate gate = kNoGate,
+                      const LsTail* tail = nullptr);
 // Trial point u' = u - zeta g (g in the workspace) and its cost-only forward
-// into the header's J_trial, all under `gate`; the Armijo test is separate.
-// With the noise table it reads the table that enqueue_cost_grad of the same
-// iteration (r.iter) wrote into the workspace.
+// into the header's J_trial, all under `gate`; tail (may be null): the Armijo
+// test, run by the trial's cost reduction.  With the noise table it reads
+// the table that enqueue_cost_grad of the same iteration (r.iter) wrote into
+// the workspace.
 int enqueue_trial(const HostProblem& p, const HostRun& r, const double* u, double zeta,
-                  const Ws& w, hipStream_t st, Gate gate);
+                  const Ws& w, hipStream_t st, Gate gate, const LsTail* tail = nullptr);
 
 // ---------------------------------------------------------------------------
 // Device-driven gradient iteration (Section 5, Algorithm 5.4 with eq.
@@ -93,10 +97,14 @@ int enqueue_trial(const HostProblem& p, const HostRun& r, const double* u, doubl
 // arithmetic and its order are those of one trial at a time.
 struct LsOps {
     virtual ~LsOps() {}
-    // J(u^n), g^n with counter word iter0 + n, under gate
-    virtual int grad(int n, Gate gate, hipStream_t st) = 0;
-    // trial point and cost of iteration n at step zeta, under gate
-    virtual int trial(int n, double zeta, Gate gate, hipStream_t st) = 0;
+    // J(u^n), g^n with counter word iter0 + n, under gate; tail: the
+    // after-gradient step, which fused() evaluations run themselves
+    virtual int grad(int n, const LsTail& tail, Gate gate, hipStream_t st) = 0;
+    // trial point and cost of iteration n at step zeta, under gate; tail: the
+    // Armijo test, which fused() trials run themselves
+    virtual int trial(int n, double zeta, const LsTail& tail, Gate gate, hipStream_t st) = 0;
+    // the tails run inside grad() and trial() (no launches of their own)
+    virtual bool fused() const { return false; }
 };
 
 struct LsDriver {

@@ -177,10 +177,15 @@ struct BMat {
     double b[64];
 };
 
+// g != nullptr: a line-search trial.  The table is built for ut = u - zeta g,
+// which the lanes of components i < d also write out (each lane evaluates the
+// trial entries of its row with k_trial's expression, so the table and ut
+// are bitwise those of k_trial followed by the plain table).
 template <typename Real, int D>
 __global__ void __launch_bounds__(kThreads)
 k_table(const double* __restrict__ u, const double* __restrict__ xd, Real* __restrict__ tab, int N,
-        int d, BMat B, WsHeader* hdr, int clear_flag, PoissonTable pt, Gate gate) {
+        int d, BMat B, WsHeader* hdr, int clear_flag, PoissonTable pt, Gate gate,
+        const double* __restrict__ g, double zeta, double* __restrict__ ut) {
     if (gate_closed(gate))
         return;
     const int idx = blockIdx.x * kThreads + threadIdx.x;
@@ -193,11 +198,17 @@ k_table(const double* __restrict__ u, const double* __restrict__ xd, Real* __res
     if (idx >= N * D)
         return;
     const int k = idx / D, i = idx - k * D;
+    auto uk = [&](int j) {
+        const size_t q = (size_t)k * d + j;
+        return g != nullptr ? u[q] - zeta * g[q] : u[q];
+    };
     double bu = 0.0, x = 0.0;
     if (i < d) {
         for (int j = 0; j < d; ++j)
-            bu += B.b[i * d + j] * u[(size_t)k * d + j];
+            bu += B.b[i * d + j] * uk(j);
         x = xd[(size_t)k * d + i];
+        if (g != nullptr)
+            ut[(size_t)k * d + i] = uk(i);
     }
     tab[(size_t)k * 2 * D + i] = (Real)bu;
     tab[(size_t)k * 2 * D + D + i] = (Real)x;
@@ -949,71 +960,14 @@ k_finalize_grad(const double* __restrict__ part, int nblk, int D, int d, int64_t
     }
 }
 
-// One block: J = (1/M) sum C + nu dt/2 sum |u|^2, and if g is given also
-// dt sum |g|^2; flags non-finite results.
-__global__ void __launch_bounds__(kThreads)
-k_finalize_cost(const double* __restrict__ cpart, int nblk, int64_t M, double nu, double dt,
-                const double* __restrict__ u, const double* __restrict__ g, int nd,
-                double* __restrict__ J_out, WsHeader* hdr, int slot, Gate gate) {
-    if (gate_closed(gate))
-        return;
-    __shared__ double sh[kThreads];
-    double s = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += kThreads)
-        s += cpart[b];
-    const double csum = block_sum(s, sh);
-    double uu = 0.0;
-    for (int q = threadIdx.x; q < nd; q += kThreads)
-        uu += u[q] * u[q];
-    uu = block_sum(uu, sh);
-    double gg = 0.0;
-    int bad = 0;
-    if (g != nullptr) {
-        for (int q = threadIdx.x; q < nd; q += kThreads) {
-            gg += g[q] * g[q];
-            bad |= !isfinite(g[q]);
-        }
-        gg = block_sum(gg, sh);
-        bad = (int)block_sum((double)bad, sh);
-    }
-    if (threadIdx.x == 0) {
-        const double J = csum / (double)M + 0.5 * nu * dt * uu;
-        if (slot == 0) {
-            hdr->J = J;
-            if (g != nullptr)
-                hdr->gnorm2 = dt * gg;
-        } else {
-            hdr->J_trial = J;
-        }
-        if (J_out != nullptr)
-            *J_out = J;
-        // a trial's cost (slot 1) may overflow: the Armijo test rejects it
-        if (slot == 0 && (!isfinite(J) || bad))
-            hdr->nonfinite = 1;
-    }
-}
-
-__global__ void __launch_bounds__(kThreads)
-k_trial(const double* __restrict__ u, const double* __restrict__ g, double zeta,
-        double* __restrict__ ut, int nd, Gate gate) {
-    if (gate_closed(gate))
-        return;
-    const int q = blockIdx.x * kThreads + threadIdx.x;
-    if (q < nd)
-        ut[q] = u[q] - zeta * g[q];
-}
-
 // Sufficient decrease J(u - zeta g) <= J(u) - c zeta ||g||^2_L2 on the same
 // draws (a non-finite trial cost is rejected); on acceptance records
 // ||u' - u||^2_L2, moves u to u', writes the iteration's log entry and opens
-// the next phase of the device-driven iteration (see LsArmijo).  Gated by the
-// phase of trial (ls.n, ls.j).
-__global__ void __launch_bounds__(kThreads)
-k_armijo(WsHeader* hdr, LsLog* __restrict__ ring, double* __restrict__ u,
-         const double* __restrict__ ut, int nd, LsArmijo ls) {
-    if (hdr->ls_phase != ls_phase(ls.n, ls.j))
-        return;
-    __shared__ double sh[kThreads];
+// the next phase of the device-driven iteration (see LsArmijo).  All threads
+// of one block; sh: kThreads doubles of LDS.
+__device__ __forceinline__ void armijo_step(WsHeader* hdr, LsLog* __restrict__ ring,
+                                            double* __restrict__ u, const double* __restrict__ ut,
+                                            int nd, const LsArmijo& ls, double* sh) {
     __shared__ int acc;
     if (threadIdx.x == 0) {
         const double J = hdr->J, Jt = hdr->J_trial;
@@ -1062,6 +1016,89 @@ k_armijo(WsHeader* hdr, LsLog* __restrict__ ring, double* __restrict__ u,
     }
 }
 
+// Gated by the phase of trial (ls.n, ls.j).
+__global__ void __launch_bounds__(kThreads)
+k_armijo(WsHeader* hdr, LsLog* __restrict__ ring, double* __restrict__ u,
+         const double* __restrict__ ut, int nd, LsArmijo ls) {
+    if (hdr->ls_phase != ls_phase(ls.n, ls.j))
+        return;
+    __shared__ double sh[kThreads];
+    armijo_step(hdr, ring, u, ut, nd, ls, sh);
+}
+
+// After the gradient of iteration n (one thread): on to trial (n, 0), or stop
+// with JD_ENONFINITE.
+__device__ __forceinline__ void ls_after_grad_step(WsHeader* hdr, int n) {
+    if (hdr->ls_phase == ls_phase(n, -1)) {
+        if (hdr->nonfinite) {
+            hdr->ls_status = JD_ENONFINITE;
+            hdr->ls_phase = kLsStop;
+        } else {
+            hdr->ls_phase = ls_phase(n, 0);
+        }
+    }
+}
+
+// One block: J = (1/M) sum C + nu dt/2 sum |u|^2, and if g is given also
+// dt sum |g|^2; flags non-finite results.
+__global__ void __launch_bounds__(kThreads)
+k_finalize_cost(const double* __restrict__ cpart, int nblk, int64_t M, double nu, double dt,
+                const double* __restrict__ u, const double* __restrict__ g, int nd,
+                double* __restrict__ J_out, WsHeader* hdr, int slot, Gate gate, LsTail tail) {
+    if (gate_closed(gate))
+        return;
+    __shared__ double sh[kThreads];
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += kThreads)
+        s += cpart[b];
+    const double csum = block_sum(s, sh);
+    double uu = 0.0;
+    for (int q = threadIdx.x; q < nd; q += kThreads)
+        uu += u[q] * u[q];
+    uu = block_sum(uu, sh);
+    double gg = 0.0;
+    int bad = 0;
+    if (g != nullptr) {
+        for (int q = threadIdx.x; q < nd; q += kThreads) {
+            gg += g[q] * g[q];
+            bad |= !isfinite(g[q]);
+        }
+        gg = block_sum(gg, sh);
+        bad = (int)block_sum((double)bad, sh);
+    }
+    if (threadIdx.x == 0) {
+        const double J = csum / (double)M + 0.5 * nu * dt * uu;
+        if (slot == 0) {
+            hdr->J = J;
+            if (g != nullptr)
+                hdr->gnorm2 = dt * gg;
+        } else {
+            hdr->J_trial = J;
+        }
+        if (J_out != nullptr)
+            *J_out = J;
+        // a trial's cost (slot 1) may overflow: the Armijo test rejects it
+        if (slot == 0 && (!isfinite(J) || bad))
+            hdr->nonfinite = 1;
+        if (tail.mode == kLsTailAfterGrad)
+            ls_after_grad_step(hdr, tail.n);
+    }
+    if (tail.mode == kLsTailArmijo) {
+        __syncthreads();
+        armijo_step(hdr, tail.ring, tail.u, tail.ut, tail.nd, tail.ls, sh);
+    }
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_trial(const double* __restrict__ u, const double* __restrict__ g, double zeta,
+        double* __restrict__ ut, int nd, Gate gate) {
+    if (gate_closed(gate))
+        return;
+    const int q = blockIdx.x * kThreads + threadIdx.x;
+    if (q < nd)
+        ut[q] = u[q] - zeta * g[q];
+}
+
 __global__ void k_ls_start(WsHeader* hdr) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         hdr->nonfinite = 0;
@@ -1075,14 +1112,8 @@ __global__ void k_ls_start(WsHeader* hdr) {
 // After the evaluation of J(u^n), g^n: stop on a non-finite result, else
 // open the first trial.
 __global__ void k_ls_after_grad(WsHeader* hdr, int n) {
-    if (threadIdx.x == 0 && blockIdx.x == 0 && hdr->ls_phase == ls_phase(n, -1)) {
-        if (hdr->nonfinite) {
-            hdr->ls_status = JD_ENONFINITE;
-            hdr->ls_phase = kLsStop;
-        } else {
-            hdr->ls_phase = ls_phase(n, 0);
-        }
-    }
+    if (threadIdx.x == 0 && blockIdx.x == 0)
+        ls_after_grad_step(hdr, n);
 }
 
 __global__ void k_clear_flag(WsHeader* hdr) {
@@ -1220,8 +1251,22 @@ hipError_t launch_setup(const HostProblem& p, const HostRun& r, const double* u,
                         WsHeader* hdr, int clear_flag, hipStream_t st, Gate gate) {
     const BMat B = make_B(p);
     const unsigned nb = blocks_for((int64_t)p.N * p.D > 32 ? (int64_t)p.N * p.D : 32);
-#define JD_SETUP(T, DD) \
-    hipLaunchKernelGGL((k_table<T, DD>), dim3(nb), dim3(kThreads), 0, st, u, p.xd, (T*)tab, p.N, p.d, B, hdr, clear_flag, p.poisson, gate)
+#define JD_SETUP(T, DD)                                                                           \
+    hipLaunchKernelGGL((k_table<T, DD>), dim3(nb), dim3(kThreads), 0, st, u, p.xd, (T*)tab, p.N,    \
+                       p.d, B, hdr, clear_flag, p.poisson, gate, nullptr, 0.0, nullptr)
+    JD_DISPATCH(r.prec, p.D, JD_SETUP);
+#undef JD_SETUP
+    return hipGetLastError();
+}
+
+hipError_t launch_setup_trial(const HostProblem& p, const HostRun& r, const double* u,
+                              const double* g, double zeta, double* ut, void* tab, WsHeader* hdr,
+                              hipStream_t st, Gate gate) {
+    const BMat B = make_B(p);
+    const unsigned nb = blocks_for((int64_t)p.N * p.D > 32 ? (int64_t)p.N * p.D : 32);
+#define JD_SETUP(T, DD)                                                                           \
+    hipLaunchKernelGGL((k_table<T, DD>), dim3(nb), dim3(kThreads), 0, st, u, p.xd, (T*)tab, p.N,    \
+                       p.d, B, hdr, 0, p.poisson, gate, g, zeta, ut)
     JD_DISPATCH(r.prec, p.D, JD_SETUP);
 #undef JD_SETUP
     return hipGetLastError();
@@ -1392,9 +1437,13 @@ hipError_t launch_finalize_grad(const HostProblem& p, const HostRun& r, const do
 
 hipError_t launch_finalize_cost(const HostProblem& p, const HostRun& r, const double* cpart,
                                 const double* u, const double* g, double* J_out, WsHeader* hdr,
-                                int slot, hipStream_t st, Gate gate) {
+                                int slot, hipStream_t st, Gate gate, const LsTail* tail) {
+    LsTail t{};
+    t.mode = kLsTailNone;
+    if (tail != nullptr)
+        t = *tail;
     hipLaunchKernelGGL(k_finalize_cost, dim3(1), dim3(kThreads), 0, st, cpart, r.nblk, r.M, p.nu,
-                       p.dt, u, g, p.N * p.d, J_out, hdr, slot, gate);
+                       p.dt, u, g, p.N * p.d, J_out, hdr, slot, gate, t);
     return hipGetLastError();
 }
 

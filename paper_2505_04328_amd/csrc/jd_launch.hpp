@@ -162,15 +162,6 @@ hipError_t launch_cost_grad_stored(const HostProblem& p, const HostRun& r, const
 hipError_t launch_finalize_grad(const HostProblem& p, const HostRun& r, const double* apart,
                                 const double* u, double* g, WsHeader* hdr, hipStream_t st,
                                 Gate gate = kNoGate);
-// slot 0: J -> hdr->J (and J_out), with gnorm2 from g if g != nullptr, and a
-// non-finite J or g raises the flag; slot 1 (a line-search trial): ->
-// hdr->J_trial, no flag (the Armijo test rejects a non-finite trial cost)
-hipError_t launch_finalize_cost(const HostProblem& p, const HostRun& r, const double* cpart,
-                                const double* u, const double* g, double* J_out, WsHeader* hdr,
-                                int slot, hipStream_t st, Gate gate = kNoGate);
-hipError_t launch_trial(const double* u, const double* g, double zeta, double* ut, int nd,
-                        hipStream_t st, Gate gate = kNoGate);
-
 // Device-driven line search (Section 5, Algorithm 5.4 with eq.
 // Stochastic_Armijo).  ls_start opens phase (0, -1); ls_after_grad (gated
 // by phase (n, -1)) moves to trial (n, 0), or stops with JD_ENONFINITE when
@@ -184,6 +175,40 @@ struct LsArmijo {
     int n, j, n_max, max_backtracks;
     uint32_t iter;
 };
+
+// A line-search step run by the cost reduction that precedes it
+// (launch_finalize_cost), in place of its own launch: the after-gradient step
+// of iteration n, or the Armijo test of a trial (ring, u, ut, nd as for
+// launch_armijo).  The reduction's gate is the step's phase.
+constexpr int kLsTailNone = 0;
+constexpr int kLsTailAfterGrad = 1;
+constexpr int kLsTailArmijo = 2;
+struct LsTail {
+    int mode;
+    int n;
+    LsArmijo ls;
+    LsLog* ring;
+    double* u;
+    const double* ut;
+    int nd;
+};
+
+// slot 0: J -> hdr->J (and J_out), with gnorm2 from g if g != nullptr, and a
+// non-finite J or g raises the flag; slot 1 (a line-search trial): ->
+// hdr->J_trial, no flag (the Armijo test rejects a non-finite trial cost).
+// tail (may be null): the line-search step that follows.
+hipError_t launch_finalize_cost(const HostProblem& p, const HostRun& r, const double* cpart,
+                                const double* u, const double* g, double* J_out, WsHeader* hdr,
+                                int slot, hipStream_t st, Gate gate = kNoGate,
+                                const LsTail* tail = nullptr);
+hipError_t launch_trial(const double* u, const double* g, double zeta, double* ut, int nd,
+                        hipStream_t st, Gate gate = kNoGate);
+// launch_trial and launch_setup(ut) in one launch: ut = u - zeta g and the
+// per-step table of ut (no flag clearing), bitwise the two launches' results.
+hipError_t launch_setup_trial(const HostProblem& p, const HostRun& r, const double* u,
+                              const double* g, double zeta, double* ut, void* tab, WsHeader* hdr,
+                              hipStream_t st, Gate gate = kNoGate);
+
 hipError_t launch_ls_start(WsHeader* hdr, hipStream_t st);
 hipError_t launch_ls_after_grad(WsHeader* hdr, int n, hipStream_t st);
 hipError_t launch_armijo(WsHeader* hdr, LsLog* ring, double* u, const double* ut, int nd,

@@ -124,16 +124,18 @@ struct Request {
 struct ReqOps : LsOps {
     Request& q;
     explicit ReqOps(Request& q_) : q(q_) {}
-    int grad(int n, Gate gate, hipStream_t st) override {
+    int grad(int n, const LsTail& tail, Gate gate, hipStream_t st) override {
         HostRun rn = q.r;
         rn.iter = q.run.iter + (uint32_t)n;
-        return enqueue_cost_grad(q.p, rn, q.u_dev, nullptr, q.w.gbuf, q.traj, q.w, st, gate);
+        return enqueue_cost_grad(q.p, rn, q.u_dev, nullptr, q.w.gbuf, q.traj, q.w, st, gate,
+                                 &tail);
     }
-    int trial(int n, double zeta, Gate gate, hipStream_t st) override {
+    int trial(int n, double zeta, const LsTail& tail, Gate gate, hipStream_t st) override {
         HostRun rn = q.r;
         rn.iter = q.run.iter + (uint32_t)n;
-        return enqueue_trial(q.p, rn, q.u_dev, zeta, q.w, st, gate);
+        return enqueue_trial(q.p, rn, q.u_dev, zeta, q.w, st, gate, &tail);
     }
+    bool fused() const override { return true; }
 };
 
 }  // namespace

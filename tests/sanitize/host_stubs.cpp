@@ -70,7 +70,12 @@ hipError_t launch_cost_grad_stored(const HostProblem&, const HostRun&, const voi
 hipError_t launch_finalize_grad(const HostProblem&, const HostRun&, const double*, const double*,
                                 double*, WsHeader*, hipStream_t, Gate) { return launched(); }
 hipError_t launch_finalize_cost(const HostProblem&, const HostRun&, const double*, const double*,
-                                const double*, double*, WsHeader*, int, hipStream_t, Gate) {
+                                const double*, double*, WsHeader*, int, hipStream_t, Gate,
+                                const LsTail*) {
+    return launched();
+}
+hipError_t launch_setup_trial(const HostProblem&, const HostRun&, const double*, const double*,
+                              double, double*, void*, WsHeader*, hipStream_t, Gate) {
     return launched();
 }
 hipError_t launch_trial(const double*, const double*, double, double*, int, hipStream_t, Gate) {
