@@ -151,6 +151,10 @@ def parse():
     ap.add_argument("--serving-m-hi", type=int, default=1 << 20)
     ap.add_argument("--serving-n-hi", type=int, default=2000)
     ap.add_argument("--serving-iters", type=int, default=30)
+    ap.add_argument("--serving-moderate-requests", type=int, default=48,
+                    help="requests of the second, below-capacity mix (0: skip it)")
+    ap.add_argument("--serving-moderate-rate", type=float, default=3.0,
+                    help="arrival rate of the below-capacity mix (requests/s)")
     ap.add_argument("--arena-gb", type=float, default=160.0)
     return ap.parse_args()
 
@@ -394,13 +398,14 @@ def configs_section(args, time_calls, dev):
     return out
 
 
-def serving_section(args):
-    """The request mix (see serving_main) as a dict."""
+def serving_run(args, count: int, rate: float):
+    """One request mix through a fresh server: Poisson arrivals at `rate`,
+    d in {1,2,4,8}, M uniform in [2^14, M_hi], N uniform in [100, N_hi], rate
+    in [0, 10], the set number of iterations each (see serving_main)."""
     from paper_2505_04328_amd import serving as S
     from paper_2505_04328_amd import workloads as wl
-    reqs = wl.serving_requests(count=args.serving_requests, rate=50.0, seed=11,
-                               M_hi=args.serving_m_hi, N_hi=args.serving_n_hi,
-                               iters=args.serving_iters)
+    reqs = wl.serving_requests(count=count, rate=rate, seed=11, M_hi=args.serving_m_hi,
+                               N_hi=args.serving_n_hi, iters=args.serving_iters)
     arena = int(args.arena_gb * (1 << 30))
     srv = S.Server(arena, max_active=32, n_streams=4)
     t_last = [time.perf_counter()]
@@ -410,7 +415,7 @@ def serving_section(args):
             log(f"  request {rec.rid} done, latency {rec.latency:.2f} s")
             t_last[0] = time.perf_counter()
 
-    log(f"serving {len(reqs)} requests, arena {args.arena_gb} GB")
+    log(f"serving {len(reqs)} requests at {rate}/s, arena {args.arena_gb} GB")
     recs, wall = S.run_mix(srv, reqs, precision="fp32", store_limit=arena // 16, on_done=on_done)
     srv.close()
     lat = np.array([r.latency for r in recs])
@@ -428,10 +433,23 @@ def serving_section(args):
         "gradient_path_steps_per_s": ps / wall, "swept_path_steps_per_s": sw / wall,
         "failed": int(sum(r.status != 0 for r in recs)),
         "peak_admitted": srv.stats["max_active"], "peak_queued": srv.stats["max_queued"],
-        "workload": f"c5 mix: {len(recs)} requests, Poisson 50/s, d in {{1,2,4,8}}, "
+        "workload": f"{len(recs)} requests, Poisson {rate}/s, d in {{1,2,4,8}}, "
                     f"M in [2^14, {args.serving_m_hi}], N in [100, {args.serving_n_hi}], "
                     f"lambda in [0,10], {args.serving_iters} iterations, FP32 paths, arena "
                     f"{args.arena_gb} GB, 32 slots over 4 streams"}
+
+
+def serving_section(args):
+    """The c5 request mix (Poisson 50/s, about 12 times what the device
+    serves, so its latency is mostly the admission queue), then a smaller mix
+    below capacity, whose latency is the service time of requests sharing
+    the device."""
+    out = serving_run(args, args.serving_requests, 50.0)
+    out["workload"] = "c5 mix: " + out["workload"]
+    if args.serving_moderate_requests > 0:
+        out["below_capacity"] = serving_run(args, args.serving_moderate_requests,
+                                            args.serving_moderate_rate)
+    return out
 
 
 def feedback_section(args, time_calls, dev):
