@@ -239,7 +239,9 @@ int jd_optimize(const jd_problem* prob, const jd_run* run, const jd_opt* opt, do
  * jd_cost_grad.  Returns JD_EWORKSPACE, before touching the device, when the
  * problem's workspace (jd_workspace_bytes() less 256 bytes of alignment
  * slack) exceeds the capacity: the 1-D workloads up to 2^20 paths x 1000 steps
- * fit.  The call allocates nothing (the first call on a device looks up the
+ * fit.  A noise table chosen by JD_NOISE_AUTO that does not fit is left out
+ * (the sweeps draw inline; the results do not change), so the check is on the
+ * workspace without it.  The call allocates nothing (the first call on a device looks up the
  * array's device address once).  All calls on one GPU share the array: calls
  * that overlap in time on one device (different streams, or host threads)
  * race on it and must be ordered by the caller; the array keeps the last

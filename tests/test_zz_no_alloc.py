@@ -51,6 +51,29 @@ def test_noalloc_equals_cost_grad():
         torch.cuda.empty_cache()
 
 
+def test_noalloc_leaves_out_an_automatic_noise_table_that_does_not_fit():
+    """c1's model at 65536 paths in FP64: the automatic choice takes the noise
+    table (105 MB, beyond the static array), which the allocation-free entry
+    point replaces by draws in the sweeps; J and g are bitwise the same."""
+    import torch
+    dev = gpu_device()
+    w = wl.config("c1")
+    p = w.problem
+    say("noalloc without the noise table", f"M=65536 N={p.N} FP64")
+    eng = B.Engine(p, M=65536, seed=w.seed, precision="fp64", device=dev)
+    inline = B.make_run(65536, precision="fp64", noise="inline")
+    assert eng.ws_bytes - 256 > B.lib().jd_noalloc_capacity()
+    assert B.lib().jd_workspace_bytes(eng.prob.ref, C.byref(inline)) - 256 <= \
+        B.lib().jd_noalloc_capacity()
+    u = torch.tensor(wl.random_control(p, 3, 0.3), dtype=torch.float64, device=dev)
+    for it in (1, 4):
+        J1, g1 = eng.cost_grad(u, it=it)
+        J2, g2 = _noalloc(eng, u, it=it)
+        torch.cuda.synchronize()
+        assert float(J1) == float(J2)
+        assert torch.equal(g1, g2)
+
+
 def test_noalloc_refuses_beyond_capacity():
     dev = gpu_device()
     assert B.lib().jd_noalloc_capacity() == 64 << 20
