@@ -194,9 +194,10 @@ bool aligned(const void* ptr, size_t a) { return ((uintptr_t)ptr % a) == 0; }
 int enqueue_forward(const HostProblem& p, const HostRun& r, const double* u, void* traj, double* J,
                     const Ws& w, hipStream_t st) {
     const int fm = traj == nullptr ? FWD_COST : (r.mode == JD_RECOMPUTE ? FWD_CKPT : FWD_STORE);
-    JD_TRY(launch_setup(p, r, u, w.tab, w.hdr, 1, st));
     if (w.noise)
-        JD_TRY(launch_noise(p, r, w.noise, w.hdr, st));
+        JD_TRY(launch_setup_noise(p, r, u, w.tab, w.noise, w.hdr, 1, st));
+    else
+        JD_TRY(launch_setup(p, r, u, w.tab, w.hdr, 1, st));
     JD_TRY(launch_forward(p, r, w.tab, traj, fm, w.cpart, w.hdr, st, kNoGate, w.noise));
     JD_TRY(launch_finalize_cost(p, r, w.cpart, u, nullptr, J, w.hdr, 0, st));
     return JD_OK;
@@ -205,9 +206,10 @@ int enqueue_forward(const HostProblem& p, const HostRun& r, const double* u, voi
 int enqueue_cost_grad(const HostProblem& p, const HostRun& r, const double* u, double* J,
                       double* g, void* traj, const Ws& w, hipStream_t st, Gate gate,
                       const LsTail* tail) {
-    JD_TRY(launch_setup(p, r, u, w.tab, w.hdr, 1, st, gate));
     if (w.noise)
-        JD_TRY(launch_noise(p, r, w.noise, w.hdr, st, gate));
+        JD_TRY(launch_setup_noise(p, r, u, w.tab, w.noise, w.hdr, 1, st, gate));
+    else
+        JD_TRY(launch_setup(p, r, u, w.tab, w.hdr, 1, st, gate));
     // One kernel (each block's forward, then its backward sweep) up to d = 4;
     // at d = 8 the separate kernels are faster (FP32 c3: 9.4 against 10.2 ms,
     // c4: 9.8 against 11.6 ms); the results are bitwise the same.

@@ -98,8 +98,8 @@ __device__ __forceinline__ void buffer_store_row(Real* row, int d, const Real* X
         (void*)row, (short)0, (int)(d * kThreads * (int)sizeof(Real)), kBufferConfig);
     const uint32_t voff = threadIdx.x * (uint32_t)sizeof(Real);
     auto put = [&](int c) {
-        // the byte offset split into a multiple of 4 KB (scalar operand) and
-        // the rest (folded into the instruction's 12-bit immediate)
+        // the byte offset split into a multiple of 4 KB (the scalar operand)
+        // and the rest, added to the lane's offset (loop-invariant values)
         const uint32_t off = (uint32_t)(c * kThreads * (int)sizeof(Real));
         const uint32_t soff = off & ~4095u;
         const uint32_t vo = voff + (off & 4095u);
@@ -177,18 +177,19 @@ struct BMat {
     double b[64];
 };
 
-// g != nullptr: a line-search trial.  The table is built for ut = u - zeta g,
-// which the lanes of components i < d also write out (each lane evaluates the
-// trial entries of its row with k_trial's expression, so the table and ut
-// are bitwise those of k_trial followed by the plain table).
+// Entry idx = k D + i of the per-step table (B u_k and x_d(t_k), row k), and
+// at idx < 32 the header's thresholds and flags.  g != nullptr: a line-search
+// trial.  The table is built for ut = u - zeta g, which the lanes of
+// components i < d also write out (each lane evaluates the trial entries of
+// its row with k_trial's expression, so the table and ut are bitwise those of
+// k_trial followed by the plain table).
 template <typename Real, int D>
-__global__ void __launch_bounds__(kThreads)
-k_table(const double* __restrict__ u, const double* __restrict__ xd, Real* __restrict__ tab, int N,
-        int d, BMat B, WsHeader* hdr, int clear_flag, PoissonTable pt, Gate gate,
-        const double* __restrict__ g, double zeta, double* __restrict__ ut) {
-    if (gate_closed(gate))
-        return;
-    const int idx = blockIdx.x * kThreads + threadIdx.x;
+__device__ __forceinline__ void table_entry(int idx, const double* __restrict__ u,
+                                            const double* __restrict__ xd, Real* __restrict__ tab,
+                                            int N, int d, const BMat& B, WsHeader* hdr,
+                                            int clear_flag, const PoissonTable& pt,
+                                            const double* __restrict__ g, double zeta,
+                                            double* __restrict__ ut) {
     if (idx == 0 && clear_flag)
         hdr->nonfinite = 0;  // every entry point starts here: the flag describes this call
     if (idx < 32)
@@ -212,6 +213,24 @@ k_table(const double* __restrict__ u, const double* __restrict__ xd, Real* __res
     }
     tab[(size_t)k * 2 * D + i] = (Real)bu;
     tab[(size_t)k * 2 * D + D + i] = (Real)x;
+}
+
+template <typename Real, int D>
+__global__ void __launch_bounds__(kThreads)
+k_table(const double* __restrict__ u, const double* __restrict__ xd, Real* __restrict__ tab, int N,
+        int d, BMat B, WsHeader* hdr, int clear_flag, PoissonTable pt, Gate gate,
+        const double* __restrict__ g, double zeta, double* __restrict__ ut) {
+    if (gate_closed(gate))
+        return;
+    table_entry<Real, D>(blockIdx.x * kThreads + threadIdx.x, u, xd, tab, N, d, B, hdr,
+                         clear_flag, pt, g, zeta, ut);
+}
+
+// Blocks of the per-step table for N steps (at least one: the header's
+// thresholds and flags).
+inline int64_t table_blocks(int N, int D) {
+    const int64_t n = (int64_t)N * D > 32 ? (int64_t)N * D : 32;
+    return (n + kThreads - 1) / kThreads;
 }
 
 // ---------------------------------------------------------------------------
@@ -301,16 +320,33 @@ struct ForwardSweep {
 // holds Z^W_c of step k and row (k*2d + d + c) the jump increment of component
 // c (-0.0 where the count is zero).  Lanes past the last path get their
 // draws like in a sweep.
+//
+// The same launch builds the evaluation's per-step table (k_table's work, in
+// its first tb blocks): the thresholds come from the argument, since the
+// table's blocks are only now writing them into the header.
 template <typename Real, int D>
 __global__ void __launch_bounds__(kThreads)
-k_noise(SweepArgs<Real, D> a, Real* __restrict__ noise) {
+k_noise(SweepArgs<Real, D> a, Real* __restrict__ noise, PoissonTable pt, int tb,
+        const double* __restrict__ u, const double* __restrict__ xd, Real* __restrict__ tab,
+        BMat B, WsHeader* hdr, int clear_flag) {
     if (gate_closed(a.gate))
         return;
+    if ((int)blockIdx.x < tb) {
+        table_entry<Real, D>(blockIdx.x * kThreads + threadIdx.x, u, xd, tab, a.N, a.d, B, hdr,
+                             clear_flag, pt, nullptr, 0.0, nullptr);
+        return;
+    }
     __shared__ PoissonTable thr;
-    stage_thresholds(a, &thr);
+    if (threadIdx.x < 32)
+        thr.tm1[threadIdx.x] = pt.tm1[threadIdx.x];
+    if (threadIdx.x == 0)
+        thr.jmax = pt.jmax;
+    __syncthreads();
+    a.thr = &thr;
+    a.thr0 = thr.tm1[0];
     const int64_t nb = (int64_t)a.nblk * a.N;
     const int64_t rows = 2 * (int64_t)a.d * kThreads;
-    for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
+    for (int64_t b = blockIdx.x - tb; b < nb; b += gridDim.x - tb) {
         const int64_t g = b / a.N;
         const int k = (int)(b - g * a.N);
         const int64_t m = g * kThreads + threadIdx.x;
@@ -927,17 +963,14 @@ k_adjoint_segments(SweepArgs<Real, D> a, const Real* __restrict__ tab, Real* __r
 }
 
 // ---------------------------------------------------------------------------
-// One block per step k: sums the d rows (k, c) of block partials in a fixed
-// order, then g_k = nu u_k + B^T (sum / M).
-__global__ void __launch_bounds__(kThreads)
-k_finalize_grad(const double* __restrict__ part, int nblk, int D, int d, int64_t M, double nu,
-                const double* __restrict__ u, BMat B, double* __restrict__ g, WsHeader* hdr,
-                Gate gate) {
-    if (gate_closed(gate))
-        return;
-    __shared__ double sh[kThreads];
-    __shared__ double G[8];
-    const int k = blockIdx.x;
+// Step k's gradient (one block): sums the d rows (k, c) of block partials in
+// a fixed order, then g_k = nu u_k + B^T (sum / M); a non-finite entry raises
+// the flag.  sh: kThreads doubles of LDS, G: 8.
+__device__ __forceinline__ void finalize_grad_step(const double* __restrict__ part, int nblk,
+                                                   int D, int d, int64_t M, double nu,
+                                                   const double* __restrict__ u, const BMat& B,
+                                                   double* g, WsHeader* hdr, int k, double* sh,
+                                                   double* G) {
     for (int c = 0; c < d; ++c) {
         const double* row = part + (size_t)(k * D + c) * nblk;
         double s = 0.0;
@@ -958,6 +991,18 @@ k_finalize_grad(const double* __restrict__ part, int nblk, int D, int d, int64_t
         if (!isfinite(gi))
             hdr->nonfinite = 1;
     }
+}
+
+// One block per step k.
+__global__ void __launch_bounds__(kThreads)
+k_finalize_grad(const double* __restrict__ part, int nblk, int D, int d, int64_t M, double nu,
+                const double* __restrict__ u, BMat B, double* __restrict__ g, WsHeader* hdr,
+                Gate gate) {
+    if (gate_closed(gate))
+        return;
+    __shared__ double sh[kThreads];
+    __shared__ double G[8];
+    finalize_grad_step(part, nblk, D, d, M, nu, u, B, g, hdr, blockIdx.x, sh, G);
 }
 
 // Sufficient decrease J(u - zeta g) <= J(u) - c zeta ||g||^2_L2 on the same
@@ -1039,15 +1084,13 @@ __device__ __forceinline__ void ls_after_grad_step(WsHeader* hdr, int n) {
     }
 }
 
-// One block: J = (1/M) sum C + nu dt/2 sum |u|^2, and if g is given also
-// dt sum |g|^2; flags non-finite results.
-__global__ void __launch_bounds__(kThreads)
-k_finalize_cost(const double* __restrict__ cpart, int nblk, int64_t M, double nu, double dt,
-                const double* __restrict__ u, const double* __restrict__ g, int nd,
-                double* __restrict__ J_out, WsHeader* hdr, int slot, Gate gate, LsTail tail) {
-    if (gate_closed(gate))
-        return;
-    __shared__ double sh[kThreads];
+// J = (1/M) sum C + nu dt/2 sum |u|^2, and if g is given also dt sum |g|^2
+// (one block); flags non-finite results, then runs the line-search tail.
+__device__ __forceinline__ void finalize_cost_block(const double* __restrict__ cpart, int nblk,
+                                                    int64_t M, double nu, double dt,
+                                                    const double* __restrict__ u, const double* g,
+                                                    int nd, double* J_out, WsHeader* hdr, int slot,
+                                                    const LsTail& tail, double* sh) {
     double s = 0.0;
     for (int b = threadIdx.x; b < nblk; b += kThreads)
         s += cpart[b];
@@ -1087,6 +1130,16 @@ k_finalize_cost(const double* __restrict__ cpart, int nblk, int64_t M, double nu
         __syncthreads();
         armijo_step(hdr, tail.ring, tail.u, tail.ut, tail.nd, tail.ls, sh);
     }
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_finalize_cost(const double* __restrict__ cpart, int nblk, int64_t M, double nu, double dt,
+                const double* __restrict__ u, const double* __restrict__ g, int nd,
+                double* __restrict__ J_out, WsHeader* hdr, int slot, Gate gate, LsTail tail) {
+    if (gate_closed(gate))
+        return;
+    __shared__ double sh[kThreads];
+    finalize_cost_block(cpart, nblk, M, nu, dt, u, g, nd, J_out, hdr, slot, tail, sh);
 }
 
 __global__ void __launch_bounds__(kThreads)
@@ -1250,7 +1303,7 @@ static inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kThreads -
 hipError_t launch_setup(const HostProblem& p, const HostRun& r, const double* u, void* tab,
                         WsHeader* hdr, int clear_flag, hipStream_t st, Gate gate) {
     const BMat B = make_B(p);
-    const unsigned nb = blocks_for((int64_t)p.N * p.D > 32 ? (int64_t)p.N * p.D : 32);
+    const unsigned nb = (unsigned)table_blocks(p.N, p.D);
 #define JD_SETUP(T, DD)                                                                           \
     hipLaunchKernelGGL((k_table<T, DD>), dim3(nb), dim3(kThreads), 0, st, u, p.xd, (T*)tab, p.N,    \
                        p.d, B, hdr, clear_flag, p.poisson, gate, nullptr, 0.0, nullptr)
@@ -1263,7 +1316,7 @@ hipError_t launch_setup_trial(const HostProblem& p, const HostRun& r, const doub
                               const double* g, double zeta, double* ut, void* tab, WsHeader* hdr,
                               hipStream_t st, Gate gate) {
     const BMat B = make_B(p);
-    const unsigned nb = blocks_for((int64_t)p.N * p.D > 32 ? (int64_t)p.N * p.D : 32);
+    const unsigned nb = (unsigned)table_blocks(p.N, p.D);
 #define JD_SETUP(T, DD)                                                                           \
     hipLaunchKernelGGL((k_table<T, DD>), dim3(nb), dim3(kThreads), 0, st, u, p.xd, (T*)tab, p.N,    \
                        p.d, B, hdr, 0, p.poisson, gate, g, zeta, ut)
@@ -1313,16 +1366,19 @@ hipError_t launch_forward(const HostProblem& p, const HostRun& r, const void* ta
     return hipGetLastError();
 }
 
-hipError_t launch_noise(const HostProblem& p, const HostRun& r, void* noise, const WsHeader* hdr,
-                        hipStream_t st, Gate gate) {
+hipError_t launch_setup_noise(const HostProblem& p, const HostRun& r, const double* u, void* tab,
+                              void* noise, WsHeader* hdr, int clear_flag, hipStream_t st,
+                              Gate gate) {
+    const int64_t tb = table_blocks(p.N, p.D);
     const int64_t nb = (int64_t)r.nblk * p.N;
-    const unsigned grid = (unsigned)(nb < kNoiseGrid ? nb : kNoiseGrid);
+    const unsigned grid = (unsigned)(tb + (nb < kNoiseGrid ? nb : kNoiseGrid));
+    const BMat B = make_B(p);
 #define JD_NOISE(T, DD)                                                                           \
     do {                                                                                          \
         SweepArgs<T, DD> a = make_args<T, DD>(p, r);                                              \
         a.gate = gate;                                                                            \
-        a.thr = &hdr->poisson;                                                                    \
-        hipLaunchKernelGGL((k_noise<T, DD>), dim3(grid), dim3(kThreads), 0, st, a, (T*)noise);    \
+        hipLaunchKernelGGL((k_noise<T, DD>), dim3(grid), dim3(kThreads), 0, st, a, (T*)noise,     \
+                           p.poisson, (int)tb, u, p.xd, (T*)tab, B, hdr, clear_flag);             \
     } while (0)
     JD_DISPATCH(r.prec, p.D, JD_NOISE);
 #undef JD_NOISE

@@ -139,17 +139,18 @@ bool recompute_supported(const HostProblem& p, const HostRun& r);
 // an optional gate (kNoGate: always runs).
 hipError_t launch_setup(const HostProblem& p, const HostRun& r, const double* u, void* tab,
                         WsHeader* hdr, int clear_flag, hipStream_t st, Gate gate = kNoGate);
-// noise: the iteration's noise table (launch_noise) or nullptr (draws in the
+// noise: the iteration's noise table (launch_setup_noise) or nullptr (draws in the
 // sweep); the results are bitwise the same.
 hipError_t launch_forward(const HostProblem& p, const HostRun& r, const void* tab, void* traj,
                           int fwd_mode, double* cpart, const WsHeader* hdr, hipStream_t st,
                           Gate gate = kNoGate, const void* noise = nullptr);
-// The noise table of iteration r.iter (noise_bytes()): the Brownian normals
-// and jump increments of every path-step.  Reads the Poisson thresholds that
-// launch_setup stages.  Grid: min(nblk N, kNoiseGrid) blocks.
+// launch_setup and the noise table of iteration r.iter (noise_bytes(): the
+// Brownian normals and jump increments of every path-step) in one launch: the
+// table's blocks, then min(nblk N, kNoiseGrid) blocks of draws.
 constexpr int64_t kNoiseGrid = 65536;
-hipError_t launch_noise(const HostProblem& p, const HostRun& r, void* noise, const WsHeader* hdr,
-                        hipStream_t st, Gate gate = kNoGate);
+hipError_t launch_setup_noise(const HostProblem& p, const HostRun& r, const double* u, void* tab,
+                              void* noise, WsHeader* hdr, int clear_flag, hipStream_t st,
+                              Gate gate = kNoGate);
 // seg: the workspace's segment scratch (seg_scratch_bytes(); unused otherwise)
 hipError_t launch_adjoint(const HostProblem& p, const HostRun& r, const void* tab, const void* traj,
                           double* apart, void* seg, const WsHeader* hdr, hipStream_t st,

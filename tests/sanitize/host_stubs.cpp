@@ -59,8 +59,8 @@ hipError_t launch_setup(const HostProblem&, const HostRun&, const double*, void*
                         hipStream_t, Gate) { return launched(); }
 hipError_t launch_forward(const HostProblem&, const HostRun&, const void*, void*, int, double*,
                           const WsHeader*, hipStream_t, Gate, const void*) { return launched(); }
-hipError_t launch_noise(const HostProblem&, const HostRun&, void*, const WsHeader*, hipStream_t,
-                        Gate) { return launched(); }
+hipError_t launch_setup_noise(const HostProblem&, const HostRun&, const double*, void*, void*,
+                              WsHeader*, int, hipStream_t, Gate) { return launched(); }
 hipError_t launch_adjoint(const HostProblem&, const HostRun&, const void*, const void*, double*,
                           void*, const WsHeader*, hipStream_t, Gate) { return launched(); }
 hipError_t launch_cost_grad_stored(const HostProblem&, const HostRun&, const void*, void*, double*,
