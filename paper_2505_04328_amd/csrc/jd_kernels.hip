@@ -920,43 +920,56 @@ k_adjoint_segments(SweepArgs<Real, D> a, const Real* __restrict__ tab, Real* __r
                 }
             }
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-            // backwards over the segment, a reducer tile at a time
-            Real cur[S][D], nxt[S][D];
-            int k = s1 - 1;
-            seg_load<Real, D>(region, cl.stride, k - s0, voff, a.d, cur);
-            for (;;) {
+            // backwards over the segment, a reducer tile at a time: two tile
+            // buffers in turn (the loop is unrolled by two, so no tile is
+            // copied), the next tile's loads issued before the current tile
+            // is swept; a group with every path active skips the masking
+            Real ta[S][D], tb[S][D];
+            const bool full = (g + 1) * kThreads <= a.M;
+            auto sweep = [&](Real (*X)[D], int k) {
                 const int cnt = k - s0 + 1 < S ? k - s0 + 1 : S;
-                const int kn = k - S;
-                if (kn >= s0)
-                    seg_load<Real, D>(region, cl.stride, kn - s0, voff, a.d, nxt);
 #pragma unroll
                 for (int s = 0; s < S; ++s) {
                     const int kk = k - s;
                     if (s < cnt) {
-                        Real v[D];
+                        if (full) {
+                            red.put(s, lam);
+                        } else {
+                            Real v[D];
 #pragma unroll
-                        for (int c = 0; c < D; ++c)
-                            v[c] = act ? lam[c] : (Real)0;
-                        red.put(s, v);
+                            for (int c = 0; c < D; ++c)
+                                v[c] = act ? lam[c] : (Real)0;
+                            red.put(s, v);
+                        }
                         if (kk >= 1) {
                             adjoint_step<Real, D, CoefInLds<Real, D>::any, CB>(
-                                a.c, a.lc, tab + (size_t)kk * 2 * D + D, cur[s], lam);
+                                a.c, a.lc, tab + (size_t)kk * 2 * D + D, X[s], lam);
                             if (DUMP) {
-                                dump_state(a, a.dX, kk, m, cur[s]);
+                                dump_state(a, a.dX, kk, m, X[s]);
                                 dump_state(a, a.dlam, kk, m, lam);
                             }
                         }
                     }
                 }
                 red.flush_tile(k, cnt, a.part, a.nblk);
+            };
+            int k = s1 - 1;
+            seg_load<Real, D>(region, cl.stride, k - s0, voff, a.d, ta);
+            for (;;) {
+                int kn = k - S;
+                if (kn >= s0)
+                    seg_load<Real, D>(region, cl.stride, kn - s0, voff, a.d, tb);
+                sweep(ta, k);
                 if (kn < s0)
                     break;
                 k = kn;
-#pragma unroll
-                for (int s = 0; s < S; ++s)
-#pragma unroll
-                    for (int c = 0; c < D; ++c)
-                        cur[s][c] = nxt[s][c];
+                kn = k - S;
+                if (kn >= s0)
+                    seg_load<Real, D>(region, cl.stride, kn - s0, voff, a.d, ta);
+                sweep(tb, k);
+                if (kn < s0)
+                    break;
+                k = kn;
             }
         }
     }
