@@ -132,13 +132,14 @@ def parse():
                     help="skip the jump-adapted grid section (Section 3)")
     ap.add_argument("--cpu-sample-paths", type=int, default=1 << 20)
     ap.add_argument("--only", choices=["all", "fp32_store", "kernels", "d8-kernels", "fb-kernels",
-                                       "ja-kernels", "fp64-kernels"],
+                                       "ja-kernels", "fp64-kernels", "c1"],
                     default="all",
                     help="kernels: c2's jd_cost_grad, jd_forward and jd_adjoint only; d8-kernels: "
                          "c3's FP32 stored and K = 64 recompute forward and adjoint only; "
                          "fb-kernels: the f4 FP32 gradient only; ja-kernels: the ja2 and ja3 "
                          "FP32 gradients only; fp64-kernels: the FP64 gradients of c2, c3 (stored), "
-                         "f4 and ja2 only (for profiler runs)")
+                         "f4 and ja2 only; c1: c1's 20 FP64 gradient iterations, noise table "
+                         "then inline draws, one run each (for profiler runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")
     ap.add_argument("--serving", action="store_true",
@@ -779,6 +780,24 @@ def main():
             torch.cuda.empty_cache()
         log("fp64 kernel loop done")
         print(json.dumps({"fp64_kernels_only": True, "calls": args.warmup + args.steps}))
+        return
+    if args.only == "c1":
+        # c1's 20 FP64 gradient iterations from u = 0, once with the noise
+        # table and once with the draws in the sweeps, after one warm call each
+        w1 = wl.config("c1")
+        logs = {}
+        for noise in ("table", "inline"):
+            e = B.Engine(w1.problem, M=w1.M, seed=w1.seed, precision="fp64", device=dev,
+                         noise=noise)
+            e.optimize(torch.zeros((w1.problem.N, 1), dtype=torch.float64, device=dev), n_max=2)
+            u = torch.zeros((w1.problem.N, 1), dtype=torch.float64, device=dev)
+            _, logs[noise] = e.optimize(u, n_max=w1.iters)
+            torch.cuda.synchronize()
+            del e
+            log(f"c1 {noise} done")
+        print(json.dumps({"c1_only": True, "iterations": len(logs["table"]),
+                          "trials": sum(1 + l["backtracks"] for l in logs["table"]),
+                          "inline_same_log": logs["table"] == logs["inline"]}))
         return
     if args.only == "ja-kernels":
         # the jump-adapted forward and adjoint at ja2 and ja3, FP32, for counter runs
