@@ -110,7 +110,7 @@ __device__ __forceinline__ void buffer_store_row(Real* row, int d, const Real* X
             __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U32x2, (double)X[c]), r,
                                                   vo, soff, AUX);
     };
-    if (d == D) {
+    if (D == 1 || d == D) {  // a one-component sweep always has d = 1
 #pragma unroll
         for (int c = 0; c < D; ++c)
             put(c);
@@ -267,11 +267,10 @@ struct ForwardSweep {
         put(a, k);
     }
 
-    // Step k with its noise from the iteration's noise table.
-    __device__ __forceinline__ void step_noise(const SweepArgs<Real, D>& a,
-                                               const Real* __restrict__ tab, int k, const Real* zw,
-                                               const Real* jinc) {
-        const Real* trow = tab + (size_t)k * 2 * D;
+    // Step k with its noise from the iteration's noise table; trow: the
+    // step's row of the per-step table.
+    __device__ __forceinline__ void step_noise(const SweepArgs<Real, D>& a, const Real* trow, int k,
+                                               const Real* zw, const Real* jinc) {
         acc += (double)sq_dist<Real, D>(X, trow + D);
         euler_step_noise<Real, D, CB>(a.c, a.lc, trow, X, zw, jinc);
         put(a, k);
@@ -374,7 +373,9 @@ struct NoiseTile {
     Real zw[P][D];
     Real ji[P][D];
 
-    // Steps k0 .. k0+P-1 (clamped to N-1) of the block's region.
+    // Steps k0 .. k0+P-1 (clamped to N-1) of the block's region.  Components
+    // past d hold component d-1's values: they are masked where a step uses
+    // them, so that no select waits for a load here.
     __device__ __forceinline__ void load(const Real* __restrict__ region, int d, int N, int k0) {
         const int64_t rows = 2 * (int64_t)d * kThreads;
 #pragma unroll
@@ -384,34 +385,80 @@ struct NoiseTile {
 #pragma unroll
             for (int c = 0; c < D; ++c) {
                 const int ce = c < d ? c : d - 1;
-                const Real z = r[ce * kThreads];
-                const Real j = r[(d + ce) * kThreads];
-                zw[s][c] = c < d ? z : (Real)0;
-                ji[s][c] = c < d ? j : (Real)-0.0;
+                zw[s][c] = r[ce * kThreads];
+                ji[s][c] = r[(d + ce) * kThreads];
             }
+        }
+    }
+    // The noise of step s: none past component d (Z^W 0, jump increment -0.0);
+    // d >= 1, so component 0 is never masked.
+    __device__ __forceinline__ void get(int s, int d, Real (&z)[D], Real (&j)[D]) const {
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            z[c] = c == 0 || c < d ? zw[s][c] : (Real)0;
+            j[c] = c == 0 || c < d ? ji[s][c] : (Real)-0.0;
         }
     }
 };
 
+// Steps of the per-step table a block copies into LDS at a time (16 KB).
+// Without the copy every step waits for a scalar load of its row: with the
+// draws precomputed nothing else covers that latency.
+constexpr int kTabChunkBytes = 16384;
+template <typename Real, int D>
+constexpr int tab_chunk_steps() { return kTabChunkBytes / (int)(2 * D * sizeof(Real)); }
+
 // All N steps of a forward sweep from the noise table: the next tile's loads
-// are issued before the current tile is swept.
+// are issued before the current tile is swept, and the per-step table is read
+// from the block's LDS copy, a chunk of steps at a time.  Every thread of the
+// block calls it (the chunk copy has barriers).
 template <typename Real, int D, int MODE, bool CB>
 __device__ __forceinline__ void sweep_noise(ForwardSweep<Real, D, MODE, CB>& f,
                                             const SweepArgs<Real, D>& a,
                                             const Real* __restrict__ tab,
                                             const Real* __restrict__ noise) {
     constexpr int P = NoiseTile<Real, D>::P;
+    constexpr int CS = tab_chunk_steps<Real, D>();
+    static_assert(CS % P == 0, "a table chunk holds whole noise tiles");
+    __shared__ Real ltab[CS * 2 * D];
     const Real* region = noise + (int64_t)blockIdx.x * a.N * 2 * a.d * kThreads;
     NoiseTile<Real, D> cur, nxt;
     cur.load(region, a.d, a.N, 0);
+    // The first tile waits here, once: the compiler's wait counts at a step
+    // merge the loop's entry with its back edge, and a first tile still in
+    // flight at the entry would make every tile's first step wait for the
+    // next tile's loads just issued.
+    __builtin_amdgcn_s_waitcnt(0);
     for (int k0 = 0;; k0 += P) {
+        if (k0 % CS == 0) {
+            const int n = (a.N - k0 < CS ? a.N - k0 : CS) * 2 * D;
+            if (k0 != 0)
+                lds_barrier();  // the previous chunk's readers are done
+            for (int e = threadIdx.x; e < n; e += kThreads)
+                ltab[e] = tab[(size_t)k0 * 2 * D + e];
+            lds_barrier();
+        }
         const bool more = k0 + P < a.N;
         if (more)
             nxt.load(region, a.d, a.N, k0 + P);
+        const Real* lrow = ltab + (k0 % CS) * 2 * D;
+        if (more) {
+            // a full tile: no per-step condition, so its table reads issue together
 #pragma unroll
-        for (int s = 0; s < P; ++s)
-            if (k0 + s < a.N)
-                f.step_noise(a, tab, k0 + s, cur.zw[s], cur.ji[s]);
+            for (int s = 0; s < P; ++s) {
+                Real z[D], j[D];
+                cur.get(s, a.d, z, j);
+                f.step_noise(a, lrow + s * 2 * D, k0 + s, z, j);
+            }
+        } else {
+#pragma unroll
+            for (int s = 0; s < P; ++s)
+                if (k0 + s < a.N) {
+                    Real z[D], j[D];
+                    cur.get(s, a.d, z, j);
+                    f.step_noise(a, lrow + s * 2 * D, k0 + s, z, j);
+                }
+        }
         if (!more)
             break;
         cur = nxt;
@@ -475,9 +522,12 @@ __device__ __forceinline__ Real buffer_load(__amdgpu_buffer_rsrc_t r, uint32_t v
 }
 
 // Full tile with top step k: slots k-1 (s = 0) down to k-S (s = S-1).
+// Components past d hold component d-1's values (voff points there); the
+// sweep masks them where a step uses them, so that no select waits for the
+// prefetched loads as they are issued.
 template <typename Real, int D>
 __device__ __forceinline__ void load_tile_buffer(const Real* region, int64_t stride, int k,
-                                                 const uint32_t* voff, int d, Real (*X)[D]) {
+                                                 const uint32_t* voff, Real (*X)[D]) {
     constexpr int S = StepReducer<D, Real>::kSteps;
     const Real* base = region + (int64_t)(k - S) * stride;
     const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
@@ -486,9 +536,8 @@ __device__ __forceinline__ void load_tile_buffer(const Real* region, int64_t str
     for (int s = 0; s < S; ++s)
 #pragma unroll
         for (int c = 0; c < D; ++c) {
-            const Real v = buffer_load<Real>(
+            X[s][c] = buffer_load<Real>(
                 r, voff[c], (uint32_t)((S - 1 - s) * stride * (int64_t)sizeof(Real)));
-            X[s][c] = c < d ? v : (Real)0;
         }
 }
 
@@ -514,7 +563,11 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<Real, D>& a, const Re
         red.put(s, v);
         if (FULL || kk >= 1) {
             const Real* xd = FULL ? trow + (S - 1 - s) * 2 * D + D : tab + (size_t)kk * 2 * D + D;
-            adjoint_step<Real, D, CoefInLds<Real, D>::adjoint, CB>(a.c, a.lc, xd, X[s], lam);
+            Real xs[D];  // components past d are zero (d >= 1: component 0 never is)
+#pragma unroll
+            for (int c = 0; c < D; ++c)
+                xs[c] = c == 0 || c < a.d ? X[s][c] : (Real)0;
+            adjoint_step<Real, D, CoefInLds<Real, D>::adjoint, CB>(a.c, a.lc, xd, xs, lam);
             if (DUMP) {
                 dump_state(a, a.dX, kk, m, X[s]);
                 dump_state(a, a.dlam, kk, m, lam);
@@ -568,7 +621,7 @@ struct StoredAdjoint {
     // Loads the tile with top step k into cur.
     __device__ __forceinline__ void load(const SweepArgs<Real, D>& a) {
         if (full())
-            load_tile_buffer<Real, D>(region, cl.stride, k, voff, a.d, cur);
+            load_tile_buffer<Real, D>(region, cl.stride, k, voff, cur);
         else
             load_tile<Real, D>(a, region, cl, k, cur);
     }
@@ -587,7 +640,7 @@ struct StoredAdjoint {
     __device__ __forceinline__ void prefetch(const SweepArgs<Real, D>& a) {
         const int kn = k - S;
         if (kn - S + 1 >= 1)
-            load_tile_buffer<Real, D>(region, cl.stride, kn, voff, a.d, nxt);
+            load_tile_buffer<Real, D>(region, cl.stride, kn, voff, nxt);
         else if (kn >= 1)
             load_tile<Real, D>(a, region, cl, kn, nxt);
     }
