@@ -329,6 +329,11 @@ NOISE_SHAPES = [
     ("d6 padded", 6, 45, 700, 9, 0.05),
     ("d8 N = 2 tiles + 1", 8, 5, 300, 5, 0.07),
     ("d8 c4-like", 8, 64, 600, 16, 0.0),
+    # the sweeps copy the per-step table into LDS 16 KB at a time: 128 steps
+    # at d = 8 in FP64 (256 in FP32), 256 at d = 3 (FP64), 1024 at d = 1 (FP64)
+    ("d8 three table chunks", 8, 300, 257, 32, 0.05),
+    ("d3 two table chunks", 3, 300, 200, 50, 0.1),
+    ("d1 two table chunks", 1, 1100, 300, 64, 0.0),
 ]
 
 
